@@ -1,0 +1,271 @@
+"""Plain FP64 CPU oracle (ctypes wrapper around ``oracle.c``).
+
+TEST INFRASTRUCTURE ONLY.  This package is the slow, obviously correct
+definition that the GPU library is checked against.  Only the tests, the
+smoke check and the CPU-baseline leg of the benchmark may import it; the
+product path never does, and it shares no code with the GPU library.
+
+Every function follows the paper's equations (Ventre et al., "Modal
+Decomposition in Numerical Computation of Eddy Current Transients"):
+
+* ``assemble_L``        -- the dense SPD inductance stand-in (Sec. 3.1, L_jk).
+* ``cholesky``          -- Z = C C^T (Sec. 3.3.1).
+* ``jacobi_eig``        -- cyclic Jacobi (Golub & Van Loan 8.5) for C = Q Lam Q^T.
+* ``standard_form``     -- C = G^{-1} Ri G^{-T} for the pencil of Sec. 3.2.
+* ``null_basis``        -- K, an orthonormal basis of ker E (Sec. 3.1).
+* ``theta_direct``      -- the Cholesky theta-method (Sec. 3.3.1, eq. time_integration).
+* ``theta_modal``       -- the modal theta-method (Sec. 3.3.2).
+* ``modal_eigen``       -- eigenvalues and Li-normalised eigenvectors (Sec. 3.2).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_i64 = ctypes.c_int64
+
+
+def build(force: bool = True) -> str:
+    """Compile ``oracle.c`` with gcc into ``liboracle.so`` (plain -O2, FP64)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fno-fast-math",
+             "-ffp-contract=off", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        lib.orc_assemble_L.argtypes = [_i64, _dp, ctypes.c_double, _dp]
+        lib.orc_cholesky.argtypes = [_i64, _dp]
+        lib.orc_cholesky.restype = _i64
+        lib.orc_forward.argtypes = [_i64, _dp, _dp]
+        lib.orc_backward_T.argtypes = [_i64, _dp, _dp]
+        lib.orc_jacobi.argtypes = [_i64, _dp, _dp, _dp, ctypes.c_int]
+        lib.orc_jacobi.restype = ctypes.c_int
+        lib.orc_null_basis.argtypes = [_i64, _i64, _dp, _dp]
+        lib.orc_null_basis.restype = ctypes.c_int
+        lib.orc_standard_form.argtypes = [_i64, _dp, _dp, _dp]
+        lib.orc_csr_to_dense.argtypes = [
+            _i64, _i64, ctypes.POINTER(ctypes.c_int64),
+            ctypes.POINTER(ctypes.c_int32), _dp, _dp]
+        lib.orc_theta_direct.argtypes = [
+            ctypes.POINTER(_Problem), ctypes.c_double, ctypes.c_double, _i64,
+            _dp, _dp, _dp, _dp]
+        lib.orc_theta_direct.restype = ctypes.c_int
+        lib.orc_theta_modal.argtypes = [
+            ctypes.POINTER(_Problem), ctypes.c_double, ctypes.c_double, _i64,
+            _dp, _dp, _dp, _dp, _dp]
+        lib.orc_theta_modal.restype = ctypes.c_int
+        lib.orc_modal_eigen.argtypes = [
+            ctypes.POINTER(_Problem), _dp, _dp, ctypes.POINTER(ctypes.c_int)]
+        lib.orc_modal_eigen.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("n", _i64), ("m", _i64), ("n_src", _i64), ("n_probe", _i64),
+                ("L", _dp), ("R", _dp), ("E", _dp), ("M", _dp), ("P", _dp)]
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _ptr(a: np.ndarray | None):
+    if a is None:
+        return None
+    return a.ctypes.data_as(_dp)
+
+
+# ---------------------------------------------------------------------------
+# elementary pieces
+# ---------------------------------------------------------------------------
+def assemble_L(xyz, h: float) -> np.ndarray:
+    """L_ij = h / sqrt(|x_i - x_j|^2 + h^2) (dense SPD inductance stand-in)."""
+    xyz = _f64(xyz)
+    n = xyz.shape[0]
+    out = np.empty((n, n))
+    _load().orc_assemble_L(n, _ptr(xyz), float(h), _ptr(out))
+    return out
+
+
+def csr_to_dense(shape, rowptr, col, val) -> np.ndarray:
+    rows, cols = shape
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    val = _f64(val)
+    out = np.empty((rows, cols))
+    _load().orc_csr_to_dense(
+        rows, cols, rowptr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+        col.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _ptr(val), _ptr(out))
+    return out
+
+
+def cholesky(A) -> np.ndarray:
+    """Lower Cholesky factor; raises ValueError with the failing pivot."""
+    G = _f64(A).copy()
+    piv = _load().orc_cholesky(G.shape[0], _ptr(G))
+    if piv >= 0:
+        raise ValueError(f"not positive definite at pivot {piv}")
+    return G
+
+
+def forward(G, b) -> np.ndarray:
+    G = _f64(G)
+    x = _f64(b).copy()
+    _load().orc_forward(G.shape[0], _ptr(G), _ptr(x))
+    return x
+
+
+def backward_T(G, b) -> np.ndarray:
+    G = _f64(G)
+    x = _f64(b).copy()
+    _load().orc_backward_T(G.shape[0], _ptr(G), _ptr(x))
+    return x
+
+
+def jacobi_eig(A, max_sweeps: int = 100):
+    """Cyclic Jacobi: returns (lam ascending, Q, sweeps)."""
+    A = _f64(A).copy()
+    n = A.shape[0]
+    Q = np.empty((n, n))
+    lam = np.empty(n)
+    sw = _load().orc_jacobi(n, _ptr(A), _ptr(Q), _ptr(lam), int(max_sweeps))
+    if sw < 0:
+        raise RuntimeError("Jacobi did not converge")
+    return lam, Q, sw
+
+
+def null_basis(E) -> np.ndarray:
+    E = _f64(np.atleast_2d(E))
+    m, n = E.shape
+    K = np.empty((n, n - m))
+    if _load().orc_null_basis(m, n, _ptr(E), _ptr(K)):
+        raise ValueError("E is rank deficient")
+    return K
+
+
+def standard_form(G, Ri) -> np.ndarray:
+    G = _f64(G)
+    Ri = _f64(Ri)
+    C = np.empty_like(G)
+    _load().orc_standard_form(G.shape[0], _ptr(G), _ptr(Ri), _ptr(C))
+    return C
+
+
+# ---------------------------------------------------------------------------
+# problems and the two theta-methods
+# ---------------------------------------------------------------------------
+class Problem:
+    """Dense problem statement  R I + L I' + E^T phi = -M0 i0',  E I = iD.
+
+    L, R: n x n; E: m x n (m = Ne - 1, may be 0); M: n x n_src;
+    P: n_probe x n probe rows.
+    """
+
+    def __init__(self, L, R, M, P, E=None):
+        self.L = _f64(L)
+        self.R = _f64(R)
+        n = self.L.shape[0]
+        self.M = _f64(np.asarray(M).reshape(n, -1))
+        self.P = _f64(np.atleast_2d(P))
+        if E is None or np.size(E) == 0:
+            self.E = np.zeros((0, n))
+        else:
+            self.E = _f64(np.atleast_2d(E))
+        self.n = n
+        self.m = self.E.shape[0]
+        self.n_src = self.M.shape[1]
+        self.n_probe = self.P.shape[0]
+
+    def _struct(self) -> _Problem:
+        dummy = np.zeros(1)
+        self._keep = dummy
+        return _Problem(self.n, self.m, self.n_src, self.n_probe,
+                        _ptr(self.L), _ptr(self.R),
+                        _ptr(self.E) if self.m else _ptr(dummy),
+                        _ptr(self.M) if self.n_src else _ptr(dummy),
+                        _ptr(self.P) if self.n_probe else _ptr(dummy))
+
+    def _waves(self, T, i_src, i_D):
+        i_src = _f64(np.zeros((T + 1, 0)) if i_src is None else
+                     np.asarray(i_src).reshape(T + 1, -1))
+        i_D = _f64(np.zeros((T + 1, 0)) if i_D is None else
+                   np.asarray(i_D).reshape(T + 1, -1))
+        assert i_src.shape[1] == self.n_src and i_D.shape[1] == self.m
+        if i_src.size == 0:
+            i_src = np.zeros(1)
+        if i_D.size == 0:
+            i_D = np.zeros(1)
+        return i_src, i_D
+
+
+_ERR = {1: "electrode matrix E is rank deficient",
+        2: "matrix not positive definite",
+        3: "Jacobi did not converge"}
+
+
+def theta_direct(pb: Problem, theta: float, dt: float, T: int, i_src=None,
+                 i_D=None, want_I: bool = False):
+    """Cholesky theta-method; returns signal (T x n_probe) [, I_hist]."""
+    i_src, i_D = pb._waves(T, i_src, i_D)
+    sig = np.zeros((T, max(pb.n_probe, 1)))
+    I_hist = np.zeros((T + 1, pb.n)) if want_I else None
+    st = pb._struct()
+    rc = _load().orc_theta_direct(ctypes.byref(st), float(theta), float(dt),
+                                  int(T), _ptr(i_src), _ptr(i_D), _ptr(sig),
+                                  _ptr(I_hist))
+    if rc:
+        raise RuntimeError(_ERR.get(rc, str(rc)))
+    sig = sig[:, :pb.n_probe]
+    return (sig, I_hist) if want_I else sig
+
+
+def theta_modal(pb: Problem, theta: float, dt: float, T: int, i_src=None,
+                i_D=None, want_I: bool = False):
+    """Modal theta-method; returns (signal, lam) [+ I_hist]."""
+    i_src, i_D = pb._waves(T, i_src, i_D)
+    sig = np.zeros((T, max(pb.n_probe, 1)))
+    lam = np.zeros(pb.n - pb.m)
+    I_hist = np.zeros((T + 1, pb.n)) if want_I else None
+    st = pb._struct()
+    rc = _load().orc_theta_modal(ctypes.byref(st), float(theta), float(dt),
+                                 int(T), _ptr(i_src), _ptr(i_D), _ptr(sig),
+                                 _ptr(lam), _ptr(I_hist))
+    if rc:
+        raise RuntimeError(_ERR.get(rc, str(rc)))
+    sig = sig[:, :pb.n_probe]
+    return (sig, lam, I_hist) if want_I else (sig, lam)
+
+
+def modal_eigen(pb: Problem, want_V: bool = True):
+    """Eigenvalues (ascending) and Li-normalised eigenvectors of (Ri, Li)."""
+    n0 = pb.n - pb.m
+    lam = np.zeros(n0)
+    V = np.zeros((n0, n0)) if want_V else None
+    sw = ctypes.c_int(0)
+    st = pb._struct()
+    rc = _load().orc_modal_eigen(ctypes.byref(st), _ptr(lam), _ptr(V),
+                                 ctypes.byref(sw))
+    if rc:
+        raise RuntimeError(_ERR.get(rc, str(rc)))
+    return (lam, V) if want_V else lam

@@ -1,0 +1,729 @@
+/*
+ * Plain FP64 CPU oracle for the eddy-current theta-methods of
+ * Ventre, Chiariello, Isernia, Mottola, Tamburrino,
+ * "Modal Decomposition in Numerical Computation of Eddy Current Transients"
+ * (arXiv 2407.11993).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously correct
+ * definition the GPU library is checked against.  Only the test-suite, the
+ * smoke check and the CPU-baseline leg of the benchmark load it; the product
+ * path never does.  It shares no code, header or helper with the GPU library.
+ *
+ * Storage: every dense matrix here is ROW-MAJOR, A[i*n + j].
+ * Precision: IEEE double throughout (the paper fixes none; FP64 is the
+ * paper's own setting, ScaLAPACK double routines, Sec. 4.5).
+ *
+ * What is computed (citations are to the paper's sections and equations):
+ *   - the Galerkin circuit system  R I + L dI/dt + E^T phi = V0 + VD,
+ *     E I = iD                                  (Sec. 3.1, eqs. discrete_version_1a/b)
+ *   - the null-space split  I = K Ii + E^T (E E^T)^{-1} iD
+ *                                               (Sec. 3.1, eq. current_electrodes)
+ *   - the projected system with Ri = K^T R K, Li = K^T L K,
+ *     R_D = K^T R E^T (E E^T)^{-1}, L_D = K^T L E^T (E E^T)^{-1}
+ *                                               (Sec. 3.1, eqs. discrete_version_2,
+ *                                                circuit_equations_v2)
+ *   - the classical theta-method with a Cholesky factor of Li + theta dt Ri
+ *                                               (Sec. 3.3.1, eq. time_integration)
+ *   - the modal theta-method on the generalized eigenpairs of (Li, Ri)
+ *                                               (Sec. 3.2 and Sec. 3.3.2)
+ *
+ * Readings of the paper taken where it is silent or inconsistent:
+ *   (r1) the modal right-hand side is the Cholesky right-hand side expressed in
+ *        the modal basis (increment form of the forcing for both methods);
+ *   (r2) Ln, Rn use the reduced Li, Ri; eigenvectors are Li-normalised, so
+ *        Ln = 1 and Rn = lambda_n = 1/tau_n;
+ *   (r3) the factored matrix is the reduced Z = Li + theta dt Ri;
+ *   (r4) the source mutual inductances enter projected by K^T; M^D = 0;
+ *   (r5) K is the orthonormal Householder complement of im(E^T);
+ *   (r10) the probe signal after step k is P (I^{k+1} - I^k) / dt.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define IDX(i, j, ld) ((int64_t)(i) * (int64_t)(ld) + (int64_t)(j))
+
+/* ------------------------------------------------------------------------ */
+/* Step a0: inductance kernel of the synthetic plates.                       */
+/* L_ij = h / sqrt(|x_i - x_j|^2 + h^2): a smooth SPD stand-in for the       */
+/* Coulomb-gauge operator of Sec. 2.2 (eq. operat), whose Galerkin matrix    */
+/* is the dense SPD L of Sec. 3.1.                                           */
+/* ------------------------------------------------------------------------ */
+void orc_assemble_L(int64_t n, const double *xyz, double h, double *L)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t j = 0; j < n; ++j) {
+            double dx = xyz[3 * i + 0] - xyz[3 * j + 0];
+            double dy = xyz[3 * i + 1] - xyz[3 * j + 1];
+            double dz = xyz[3 * i + 2] - xyz[3 * j + 2];
+            L[IDX(i, j, n)] = h / sqrt(dx * dx + dy * dy + dz * dz + h * h);
+        }
+    }
+}
+
+/* CSR (int64 row pointers, int32 columns) to a dense row-major matrix. */
+void orc_csr_to_dense(int64_t rows, int64_t cols, const int64_t *rowptr,
+                      const int32_t *col, const double *val, double *out)
+{
+    memset(out, 0, sizeof(double) * (size_t)(rows * cols));
+    for (int64_t i = 0; i < rows; ++i)
+        for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p)
+            out[IDX(i, col[p], cols)] += val[p];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Dense Cholesky A = G G^T (lower), in place; the upper triangle is zeroed. */
+/* Returns -1 on success, else the index of the first non-positive pivot.    */
+/* (Sec. 3.3.1: the factorisation Z = C C^T; also Li = G G^T for the modal   */
+/*  standard form.)                                                          */
+/* ------------------------------------------------------------------------ */
+int64_t orc_cholesky(int64_t n, double *A)
+{
+    for (int64_t j = 0; j < n; ++j) {
+        double s = A[IDX(j, j, n)];
+        for (int64_t k = 0; k < j; ++k)
+            s -= A[IDX(j, k, n)] * A[IDX(j, k, n)];
+        if (!(s > 0.0))
+            return j;
+        double gjj = sqrt(s);
+        A[IDX(j, j, n)] = gjj;
+        for (int64_t i = j + 1; i < n; ++i) {
+            double t = A[IDX(i, j, n)];
+            for (int64_t k = 0; k < j; ++k)
+                t -= A[IDX(i, k, n)] * A[IDX(j, k, n)];
+            A[IDX(i, j, n)] = t / gjj;
+        }
+    }
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = i + 1; j < n; ++j)
+            A[IDX(i, j, n)] = 0.0;
+    return -1;
+}
+
+/* Forward substitution G y = b (G lower), b overwritten by y. */
+void orc_forward(int64_t n, const double *G, double *b)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double t = b[i];
+        for (int64_t k = 0; k < i; ++k)
+            t -= G[IDX(i, k, n)] * b[k];
+        b[i] = t / G[IDX(i, i, n)];
+    }
+}
+
+/* Backward substitution G^T x = y (G lower), y overwritten by x. */
+void orc_backward_T(int64_t n, const double *G, double *y)
+{
+    for (int64_t i = n - 1; i >= 0; --i) {
+        double t = y[i];
+        for (int64_t k = i + 1; k < n; ++k)
+            t -= G[IDX(k, i, n)] * y[k];
+        y[i] = t / G[IDX(i, i, n)];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Cyclic-by-row Jacobi for a symmetric matrix (Golub & Van Loan, "Matrix   */
+/* Computations", sec. 8.5): A = Q diag(lam) Q^T.  A is destroyed.  A       */
+/* rotation is skipped when |a_pq| <= eps sqrt(|a_pp a_qq|) (the relative   */
+/* threshold of Demmel & Veselic); the sweep loop stops after a sweep that  */
+/* rotates nothing.  lam is returned ascending with Q's columns permuted to  */
+/* match (the paper's tau_n = 1/lam_n in decreasing order, Sec. 2.3).        */
+/* Q is row-major n x n, Q[i*n + j] = component i of eigenvector j.          */
+/* Returns the number of sweeps, or -1 if max_sweeps were not enough.        */
+/* ------------------------------------------------------------------------ */
+int orc_jacobi(int64_t n, double *A, double *Q, double *lam, int max_sweeps)
+{
+    const double eps = 2.220446049250313e-16;
+    /* Qt holds the eigenvectors as rows while rotating (contiguous updates) */
+    double *Qt = (double *)malloc(sizeof(double) * (size_t)(n * n + 1));
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < n; ++j)
+            Qt[IDX(i, j, n)] = (i == j) ? 1.0 : 0.0;
+    int sweep = 0, done = (n < 2);
+    while (!done && sweep < max_sweeps) {
+        int64_t rotated = 0;
+        for (int64_t p = 0; p < n - 1; ++p) {
+            for (int64_t q = p + 1; q < n; ++q) {
+                double apq = A[IDX(p, q, n)];
+                double app = A[IDX(p, p, n)];
+                double aqq = A[IDX(q, q, n)];
+                if (apq == 0.0 || fabs(apq) <= eps * sqrt(fabs(app * aqq)))
+                    continue;
+                /* symmetric 2x2 Schur decomposition: J = [c s; -s c] in the
+                 * (p,q) plane makes (J^T A J)_pq vanish */
+                double tau = (aqq - app) / (2.0 * apq);
+                double t = (tau >= 0.0 ? 1.0 : -1.0) /
+                           (fabs(tau) + sqrt(1.0 + tau * tau));
+                double c = 1.0 / sqrt(1.0 + t * t);
+                double s = t * c;
+                /* A <- J^T A J.  Rows p and q equal columns p and q (A is
+                 * symmetric): update them along the rows, mirror into the
+                 * columns. */
+                double *rp = A + p * n, *rq = A + q * n;
+                for (int64_t k = 0; k < n; ++k) {
+                    if (k == p || k == q)
+                        continue;
+                    double akp = rp[k], akq = rq[k];
+                    double np_ = c * akp - s * akq;
+                    double nq_ = s * akp + c * akq;
+                    rp[k] = np_;
+                    rq[k] = nq_;
+                    A[IDX(k, p, n)] = np_;
+                    A[IDX(k, q, n)] = nq_;
+                }
+                rp[p] = app - t * apq;
+                rq[q] = aqq + t * apq;
+                rp[q] = 0.0;
+                rq[p] = 0.0;
+                /* Q <- Q J, i.e. rows p, q of Qt */
+                double *up = Qt + p * n, *uq = Qt + q * n;
+                for (int64_t k = 0; k < n; ++k) {
+                    double a = up[k], b = uq[k];
+                    up[k] = c * a - s * b;
+                    uq[k] = s * a + c * b;
+                }
+                ++rotated;
+            }
+        }
+        ++sweep;
+        if (rotated == 0)
+            done = 1;
+    }
+    for (int64_t i = 0; i < n; ++i)
+        lam[i] = A[IDX(i, i, n)];
+    /* selection sort of the eigenpairs, ascending */
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t m = i;
+        for (int64_t j = i + 1; j < n; ++j)
+            if (lam[j] < lam[m])
+                m = j;
+        if (m != i) {
+            double t = lam[i];
+            lam[i] = lam[m];
+            lam[m] = t;
+            for (int64_t k = 0; k < n; ++k) {
+                double u = Qt[IDX(i, k, n)];
+                Qt[IDX(i, k, n)] = Qt[IDX(m, k, n)];
+                Qt[IDX(m, k, n)] = u;
+            }
+        }
+    }
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < n; ++j)
+            Q[IDX(i, j, n)] = Qt[IDX(j, i, n)];
+    free(Qt);
+    return done ? sweep : -1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Orthonormal basis K (n x (n-m)) of ker E for E (m x n) of full row rank:  */
+/* Householder QR of E^T = H_1 ... H_m [T; 0]; the last n-m columns of       */
+/* H = H_1 ... H_m are orthonormal and orthogonal to im E^T = X_D, so they   */
+/* span X_0 = ker E (Sec. 3.1, eq. direct_sum_discrete).  Returns 0, or 1 if */
+/* E is rank deficient.                                                      */
+/* ------------------------------------------------------------------------ */
+int orc_null_basis(int64_t m, int64_t n, const double *E, double *K)
+{
+    double *A = (double *)malloc(sizeof(double) * (size_t)(n * (m > 0 ? m : 1)));
+    double *V = (double *)malloc(sizeof(double) * (size_t)(n * (m > 0 ? m : 1)));
+    double *H = (double *)malloc(sizeof(double) * (size_t)(n * n));
+    double *beta = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
+    int bad = 0;
+    /* A = E^T, n x m row-major */
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < m; ++j)
+            A[IDX(i, j, m)] = E[IDX(j, i, n)];
+    memset(V, 0, sizeof(double) * (size_t)(n * (m > 0 ? m : 1)));
+    for (int64_t j = 0; j < m; ++j) {
+        double nrm = 0.0, full = 0.0;
+        for (int64_t i = 0; i < n; ++i)
+            full += E[IDX(j, i, n)] * E[IDX(j, i, n)];
+        for (int64_t i = j; i < n; ++i)
+            nrm += A[IDX(i, j, m)] * A[IDX(i, j, m)];
+        nrm = sqrt(nrm);
+        /* rank test: what is left of column j after the previous reflectors */
+        if (!(nrm > 1e-12 * sqrt(full))) {
+            bad = 1;
+            break;
+        }
+        double alpha = A[IDX(j, j, m)] >= 0.0 ? -nrm : nrm;
+        /* v = a - alpha e_j, H_j = I - beta v v^T, beta = 2 / v^T v */
+        double vv = 0.0;
+        for (int64_t i = j; i < n; ++i) {
+            double vi = A[IDX(i, j, m)] - (i == j ? alpha : 0.0);
+            V[IDX(i, j, m)] = vi;
+            vv += vi * vi;
+        }
+        beta[j] = 2.0 / vv;
+        for (int64_t c = j; c < m; ++c) {
+            double d = 0.0;
+            for (int64_t i = j; i < n; ++i)
+                d += V[IDX(i, j, m)] * A[IDX(i, c, m)];
+            for (int64_t i = j; i < n; ++i)
+                A[IDX(i, c, m)] -= beta[j] * d * V[IDX(i, j, m)];
+        }
+    }
+    if (!bad) {
+        /* H = H_1 H_2 ... H_m I : apply in reverse order to the identity */
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = 0; j < n; ++j)
+                H[IDX(i, j, n)] = (i == j) ? 1.0 : 0.0;
+        for (int64_t j = m - 1; j >= 0; --j) {
+            for (int64_t c = 0; c < n; ++c) {
+                double d = 0.0;
+                for (int64_t i = j; i < n; ++i)
+                    d += V[IDX(i, j, m)] * H[IDX(i, c, n)];
+                for (int64_t i = j; i < n; ++i)
+                    H[IDX(i, c, n)] -= beta[j] * d * V[IDX(i, j, m)];
+            }
+        }
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = m; j < n; ++j)
+                K[IDX(i, j - m, n - m)] = H[IDX(i, j, n)];
+    }
+    free(A);
+    free(V);
+    free(H);
+    free(beta);
+    return bad;
+}
+
+/* C = A^T B for A (r x p), B (r x q), all row-major; C is p x q. */
+static void matTmul(int64_t r, int64_t p, int64_t q, const double *A,
+                    const double *B, double *C)
+{
+    memset(C, 0, sizeof(double) * (size_t)(p * q));
+    for (int64_t k = 0; k < r; ++k)
+        for (int64_t i = 0; i < p; ++i) {
+            double a = A[IDX(k, i, p)];
+            if (a == 0.0)
+                continue;
+            for (int64_t j = 0; j < q; ++j)
+                C[IDX(i, j, q)] += a * B[IDX(k, j, q)];
+        }
+}
+
+/* C = A B for A (p x r), B (r x q), row-major. */
+static void matmul(int64_t p, int64_t r, int64_t q, const double *A,
+                   const double *B, double *C)
+{
+    memset(C, 0, sizeof(double) * (size_t)(p * q));
+    for (int64_t i = 0; i < p; ++i)
+        for (int64_t k = 0; k < r; ++k) {
+            double a = A[IDX(i, k, r)];
+            if (a == 0.0)
+                continue;
+            for (int64_t j = 0; j < q; ++j)
+                C[IDX(i, j, q)] += a * B[IDX(k, j, q)];
+        }
+}
+
+/* ------------------------------------------------------------------------ */
+/* The problem statement (Sec. 3.1, eqs. discrete_version_1a/b and           */
+/* induced_voltages_0): R I + L I' + E^T phi = -M0 i0',  E I = iD,           */
+/* observed through probe rows P.                                            */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t n;       /* unknowns N */
+    int64_t m;       /* electrode rows Ne-1 (0: no electrodes) */
+    int64_t n_src;   /* solenoidal sources (columns of M0) */
+    int64_t n_probe; /* probe rows */
+    const double *L; /* n x n, SPD */
+    const double *R; /* n x n, SPD */
+    const double *E; /* m x n */
+    const double *M; /* n x n_src */
+    const double *P; /* n_probe x n */
+} orc_problem;
+
+/* The reduced quantities of Sec. 3.1 (eqs. discrete_version_2 and
+ * circuit_equations_v2). */
+typedef struct {
+    int64_t n0;
+    double *K;  /* n x n0 */
+    double *Li; /* n0 x n0 */
+    double *Ri; /* n0 x n0 */
+    double *AD; /* n x m   : E^T (E E^T)^{-1} */
+    double *RD; /* n0 x m  : K^T R AD */
+    double *LD; /* n0 x m  : K^T L AD  (+ K^T M^D, taken as 0) */
+    double *Mi; /* n0 x n_src : K^T M0 */
+    double *PK; /* n_probe x n0 : P K */
+    double *PD; /* n_probe x m  : P AD */
+} orc_reduced;
+
+static void free_reduced(orc_reduced *r)
+{
+    free(r->K);
+    free(r->Li);
+    free(r->Ri);
+    free(r->AD);
+    free(r->RD);
+    free(r->LD);
+    free(r->Mi);
+    free(r->PK);
+    free(r->PD);
+}
+
+static int reduce(const orc_problem *pb, orc_reduced *r)
+{
+    const int64_t n = pb->n, m = pb->m, n0 = n - m;
+    const int64_t mm = m > 0 ? m : 1;
+    memset(r, 0, sizeof(*r));
+    r->n0 = n0;
+    r->K = (double *)malloc(sizeof(double) * (size_t)(n * n0));
+    r->Li = (double *)malloc(sizeof(double) * (size_t)(n0 * n0));
+    r->Ri = (double *)malloc(sizeof(double) * (size_t)(n0 * n0));
+    r->AD = (double *)calloc((size_t)(n * mm), sizeof(double));
+    r->RD = (double *)calloc((size_t)(n0 * mm), sizeof(double));
+    r->LD = (double *)calloc((size_t)(n0 * mm), sizeof(double));
+    r->Mi = (double *)calloc((size_t)(n0 * (pb->n_src > 0 ? pb->n_src : 1)), sizeof(double));
+    r->PK = (double *)calloc((size_t)((pb->n_probe > 0 ? pb->n_probe : 1) * n0), sizeof(double));
+    r->PD = (double *)calloc((size_t)((pb->n_probe > 0 ? pb->n_probe : 1) * mm), sizeof(double));
+    double *tmp = (double *)malloc(sizeof(double) * (size_t)(n * (n > mm ? n : mm)));
+    if (m == 0) {
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = 0; j < n; ++j)
+                r->K[IDX(i, j, n)] = (i == j) ? 1.0 : 0.0;
+        memcpy(r->Li, pb->L, sizeof(double) * (size_t)(n * n));
+        memcpy(r->Ri, pb->R, sizeof(double) * (size_t)(n * n));
+        if (pb->n_src > 0)
+            memcpy(r->Mi, pb->M, sizeof(double) * (size_t)(n * pb->n_src));
+        if (pb->n_probe > 0)
+            memcpy(r->PK, pb->P, sizeof(double) * (size_t)(pb->n_probe * n));
+        free(tmp);
+        return 0;
+    }
+    if (orc_null_basis(m, n, pb->E, r->K)) {
+        free(tmp);
+        return 1;
+    }
+    /* Li = K^T L K, Ri = K^T R K (eq. discrete_version_2) */
+    double *LK = (double *)malloc(sizeof(double) * (size_t)(n * n0));
+    matmul(n, n, n0, pb->L, r->K, LK);
+    matTmul(n, n0, n0, r->K, LK, r->Li);
+    matmul(n, n, n0, pb->R, r->K, LK);
+    matTmul(n, n0, n0, r->K, LK, r->Ri);
+    free(LK);
+    /* AD = E^T (E E^T)^{-1}  (eq. current_electrodes) */
+    double *EEt = (double *)malloc(sizeof(double) * (size_t)(m * m));
+    for (int64_t a = 0; a < m; ++a)
+        for (int64_t b = 0; b < m; ++b) {
+            double s = 0.0;
+            for (int64_t k = 0; k < n; ++k)
+                s += pb->E[IDX(a, k, n)] * pb->E[IDX(b, k, n)];
+            EEt[IDX(a, b, m)] = s;
+        }
+    if (orc_cholesky(m, EEt) >= 0) {
+        free(EEt);
+        free(tmp);
+        return 1;
+    }
+    /* row i of AD solves (E E^T) x = E[:, i] */
+    for (int64_t i = 0; i < n; ++i) {
+        double *x = r->AD + i * m;
+        for (int64_t a = 0; a < m; ++a)
+            x[a] = pb->E[IDX(a, i, n)];
+        orc_forward(m, EEt, x);
+        orc_backward_T(m, EEt, x);
+    }
+    free(EEt);
+    /* R_D = K^T R AD, L_D = K^T L AD (eq. circuit_equations_v2, M^D = 0) */
+    matmul(n, n, m, pb->R, r->AD, tmp);
+    matTmul(n, n0, m, r->K, tmp, r->RD);
+    matmul(n, n, m, pb->L, r->AD, tmp);
+    matTmul(n, n0, m, r->K, tmp, r->LD);
+    if (pb->n_src > 0)
+        matTmul(n, n0, pb->n_src, r->K, pb->M, r->Mi);
+    if (pb->n_probe > 0) {
+        matmul(pb->n_probe, n, n0, pb->P, r->K, r->PK);
+        matmul(pb->n_probe, n, m, pb->P, r->AD, r->PD);
+    }
+    free(tmp);
+    return 0;
+}
+
+/* Forcing of one theta step (Sec. 3.3.1, eq. time_integration, reading r1):
+ *   f = -dt R_D (iD^k + theta d iD) - L_D d iD - K^T M0 d i0,
+ * with d x = x^{k+1} - x^k.  Written into f (n0). */
+static void forcing(const orc_problem *pb, const orc_reduced *r, double theta,
+                    double dt, int64_t k, const double *i_src,
+                    const double *i_D, double *f)
+{
+    const int64_t n0 = r->n0, m = pb->m, ns = pb->n_src;
+    for (int64_t i = 0; i < n0; ++i) {
+        double s = 0.0;
+        for (int64_t a = 0; a < m; ++a) {
+            double iDk = i_D[IDX(k, a, m)];
+            double diD = i_D[IDX(k + 1, a, m)] - iDk;
+            s += -dt * r->RD[IDX(i, a, m)] * (iDk + theta * diD) -
+                 r->LD[IDX(i, a, m)] * diD;
+        }
+        for (int64_t c = 0; c < ns; ++c) {
+            double di0 = i_src[IDX(k + 1, c, ns)] - i_src[IDX(k, c, ns)];
+            s += -r->Mi[IDX(i, c, ns)] * di0;
+        }
+        f[i] = s;
+    }
+}
+
+/* Probe signal after step k (reading r10):
+ *   s^{k+1} = P (K dIi + AD d iD) / dt. */
+static void probe(const orc_problem *pb, const orc_reduced *r, double dt,
+                  int64_t k, const double *dIi, const double *i_D, double *out)
+{
+    const int64_t n0 = r->n0, m = pb->m;
+    for (int64_t p = 0; p < pb->n_probe; ++p) {
+        double s = 0.0;
+        for (int64_t i = 0; i < n0; ++i)
+            s += r->PK[IDX(p, i, n0)] * dIi[i];
+        for (int64_t a = 0; a < m; ++a)
+            s += r->PD[IDX(p, a, m)] *
+                 (i_D[IDX(k + 1, a, m)] - i_D[IDX(k, a, m)]);
+        out[p] = s / dt;
+    }
+}
+
+/* Full current I = K Ii + AD iD (eq. current_electrodes). */
+static void full_current(const orc_problem *pb, const orc_reduced *r,
+                         const double *Ii, const double *iD_k, double *I)
+{
+    const int64_t n = pb->n, n0 = r->n0, m = pb->m;
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int64_t j = 0; j < n0; ++j)
+            s += r->K[IDX(i, j, n0)] * Ii[j];
+        for (int64_t a = 0; a < m; ++a)
+            s += r->AD[IDX(i, a, m)] * iD_k[a];
+        I[i] = s;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* The classical theta-method (Sec. 3.3.1, eq. time_integration): factor     */
+/* Z = Li + theta dt Ri = C C^T once, then per step                          */
+/*   Z dI = -dt Ri Ii^k + f^k,  Ii^{k+1} = Ii^k + dI,                        */
+/* solved by forward then backward substitution.  Ii^0 = 0.                  */
+/* signal: T x n_probe; I_hist: (T+1) x n full currents, or NULL.            */
+/* Returns 0, 1 (bad electrodes), 2 (Z not SPD).                             */
+/* ------------------------------------------------------------------------ */
+int orc_theta_direct(const orc_problem *pb, double theta, double dt, int64_t T,
+                     const double *i_src, const double *i_D, double *signal,
+                     double *I_hist)
+{
+    orc_reduced r;
+    if (reduce(pb, &r)) {
+        free_reduced(&r);
+        return 1;
+    }
+    const int64_t n0 = r.n0;
+    double *Z = (double *)malloc(sizeof(double) * (size_t)(n0 * n0));
+    for (int64_t i = 0; i < n0 * n0; ++i)
+        Z[i] = r.Li[i] + theta * dt * r.Ri[i];
+    if (orc_cholesky(n0, Z) >= 0) {
+        free(Z);
+        free_reduced(&r);
+        return 2;
+    }
+    double *Ii = (double *)calloc((size_t)n0, sizeof(double));
+    double *b = (double *)malloc(sizeof(double) * (size_t)n0);
+    if (I_hist)
+        full_current(pb, &r, Ii, i_D, I_hist);
+    for (int64_t k = 0; k < T; ++k) {
+        forcing(pb, &r, theta, dt, k, i_src, i_D, b);
+        for (int64_t i = 0; i < n0; ++i) {
+            double s = 0.0;
+            for (int64_t j = 0; j < n0; ++j)
+                s += r.Ri[IDX(i, j, n0)] * Ii[j];
+            b[i] -= dt * s;
+        }
+        orc_forward(n0, Z, b);
+        orc_backward_T(n0, Z, b);
+        for (int64_t i = 0; i < n0; ++i)
+            Ii[i] += b[i];
+        if (signal)
+            probe(pb, &r, dt, k, b, i_D, signal + k * pb->n_probe);
+        if (I_hist)
+            full_current(pb, &r, Ii, i_D + (k + 1) * pb->m,
+                         I_hist + (k + 1) * pb->n);
+    }
+    free(Ii);
+    free(b);
+    free(Z);
+    free_reduced(&r);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Standard form of the pencil (Sec. 3.2, eq. generalized_eigenvalues_      */
+/* discrete, written with lambda = 1/tau):  Ri v = lambda Li v.  With        */
+/* Li = G G^T, C = G^{-1} Ri G^{-T} has the same eigenvalues, and            */
+/* v = G^{-T} q for each eigenvector q of C.  G is the lower Cholesky        */
+/* factor (row-major n x n); C (n x n) is returned symmetrised.              */
+/* ------------------------------------------------------------------------ */
+void orc_standard_form(int64_t n, const double *G, const double *Ri, double *C)
+{
+    double *X = (double *)malloc(sizeof(double) * (size_t)(n * n));
+    double *col = (double *)malloc(sizeof(double) * (size_t)n);
+    /* X = G^{-1} Ri, column by column */
+    for (int64_t j = 0; j < n; ++j) {
+        for (int64_t i = 0; i < n; ++i)
+            col[i] = Ri[IDX(i, j, n)];
+        orc_forward(n, G, col);
+        for (int64_t i = 0; i < n; ++i)
+            X[IDX(i, j, n)] = col[i];
+    }
+    /* C = G^{-1} X^T  (X^T = Ri G^{-T}) */
+    for (int64_t j = 0; j < n; ++j) {
+        for (int64_t i = 0; i < n; ++i)
+            col[i] = X[IDX(j, i, n)];
+        orc_forward(n, G, col);
+        for (int64_t i = 0; i < n; ++i)
+            C[IDX(i, j, n)] = col[i];
+    }
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = i + 1; j < n; ++j) {
+            double s = 0.5 * (C[IDX(i, j, n)] + C[IDX(j, i, n)]);
+            C[IDX(i, j, n)] = s;
+            C[IDX(j, i, n)] = s;
+        }
+    free(X);
+    free(col);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Modal decomposition of the reduced pencil (Sec. 3.2): eigenvalues        */
+/* lam (ascending, lam_n = R_n / L_n = 1/tau_n) and the Li-normalised        */
+/* eigenvectors V = G^{-T} Q (n0 x n0, column j = mode j), or NULL.          */
+/* Returns 0, 1 (bad electrodes), 2 (Li not SPD), 3 (Jacobi did not         */
+/* converge).                                                                */
+/* ------------------------------------------------------------------------ */
+static int modal_parts(const orc_problem *pb, orc_reduced *r, double *lam,
+                       double *V, int *sweeps)
+{
+    if (reduce(pb, r))
+        return 1;
+    const int64_t n0 = r->n0;
+    double *G = (double *)malloc(sizeof(double) * (size_t)(n0 * n0));
+    memcpy(G, r->Li, sizeof(double) * (size_t)(n0 * n0));
+    if (orc_cholesky(n0, G) >= 0) {
+        free(G);
+        return 2;
+    }
+    double *C = (double *)malloc(sizeof(double) * (size_t)(n0 * n0));
+    double *Q = (double *)malloc(sizeof(double) * (size_t)(n0 * n0));
+    orc_standard_form(n0, G, r->Ri, C);
+    int sw = orc_jacobi(n0, C, Q, lam, 100);
+    if (sweeps)
+        *sweeps = sw;
+    if (sw < 0) {
+        free(G);
+        free(C);
+        free(Q);
+        return 3;
+    }
+    /* V = G^{-T} Q, column by column */
+    double *col = (double *)malloc(sizeof(double) * (size_t)n0);
+    for (int64_t j = 0; j < n0; ++j) {
+        for (int64_t i = 0; i < n0; ++i)
+            col[i] = Q[IDX(i, j, n0)];
+        orc_backward_T(n0, G, col);
+        for (int64_t i = 0; i < n0; ++i)
+            V[IDX(i, j, n0)] = col[i];
+    }
+    free(col);
+    free(G);
+    free(C);
+    free(Q);
+    return 0;
+}
+
+int orc_modal_eigen(const orc_problem *pb, double *lam, double *V, int *sweeps)
+{
+    orc_reduced r;
+    double *Vtmp = V;
+    int64_t n0 = pb->n - pb->m;
+    if (!Vtmp)
+        Vtmp = (double *)malloc(sizeof(double) * (size_t)(n0 * n0));
+    int rc = modal_parts(pb, &r, lam, Vtmp, sweeps);
+    if (!V)
+        free(Vtmp);
+    free_reduced(&r);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The modal theta-method (Sec. 3.3.2).  In the basis of Li-normalised       */
+/* generalized eigenvectors V the system decouples into                      */
+/*   I_n' + lam_n I_n = (V^T g)_n    (eq. modal_decomposition_discrete)      */
+/* and each mode is stepped by the theta-method:                             */
+/*   (1 + theta dt lam_n) dy_n = -dt lam_n y_n + (V^T f^k)_n,                */
+/* where f^k is the same forcing as in the Cholesky method (reading r1).     */
+/* Ii = V y, so the probe signal is P (K V dy + AD d iD) / dt.               */
+/* lam_out (n0) and I_hist ((T+1) x n) may be NULL.                          */
+/* ------------------------------------------------------------------------ */
+int orc_theta_modal(const orc_problem *pb, double theta, double dt, int64_t T,
+                    const double *i_src, const double *i_D, double *signal,
+                    double *lam_out, double *I_hist)
+{
+    orc_reduced r;
+    const int64_t n0 = pb->n - pb->m;
+    double *lam = (double *)malloc(sizeof(double) * (size_t)n0);
+    double *V = (double *)malloc(sizeof(double) * (size_t)(n0 * n0));
+    int rc = modal_parts(pb, &r, lam, V, NULL);
+    if (rc) {
+        free(lam);
+        free(V);
+        free_reduced(&r);
+        return rc;
+    }
+    double *y = (double *)calloc((size_t)n0, sizeof(double));
+    double *dy = (double *)malloc(sizeof(double) * (size_t)n0);
+    double *f = (double *)malloc(sizeof(double) * (size_t)n0);
+    double *dIi = (double *)malloc(sizeof(double) * (size_t)n0);
+    double *Ii = (double *)malloc(sizeof(double) * (size_t)n0);
+    if (I_hist) {
+        memset(Ii, 0, sizeof(double) * (size_t)n0);
+        full_current(pb, &r, Ii, i_D, I_hist);
+    }
+    for (int64_t k = 0; k < T; ++k) {
+        forcing(pb, &r, theta, dt, k, i_src, i_D, f);
+        for (int64_t nn = 0; nn < n0; ++nn) {
+            double e = 0.0; /* modal forcing (V^T f)_n */
+            for (int64_t i = 0; i < n0; ++i)
+                e += V[IDX(i, nn, n0)] * f[i];
+            dy[nn] = (-dt * lam[nn] * y[nn] + e) / (1.0 + theta * dt * lam[nn]);
+        }
+        for (int64_t nn = 0; nn < n0; ++nn)
+            y[nn] += dy[nn];
+        for (int64_t i = 0; i < n0; ++i) {
+            double s = 0.0;
+            for (int64_t nn = 0; nn < n0; ++nn)
+                s += V[IDX(i, nn, n0)] * dy[nn];
+            dIi[i] = s;
+        }
+        if (signal)
+            probe(pb, &r, dt, k, dIi, i_D, signal + k * pb->n_probe);
+        if (I_hist) {
+            for (int64_t i = 0; i < n0; ++i) {
+                double s = 0.0;
+                for (int64_t nn = 0; nn < n0; ++nn)
+                    s += V[IDX(i, nn, n0)] * y[nn];
+                Ii[i] = s;
+            }
+            full_current(pb, &r, Ii, i_D + (k + 1) * pb->m,
+                         I_hist + (k + 1) * pb->n);
+        }
+    }
+    if (lam_out)
+        memcpy(lam_out, lam, sizeof(double) * (size_t)n0);
+    free(y);
+    free(dy);
+    free(f);
+    free(dIi);
+    free(Ii);
+    free(lam);
+    free(V);
+    free_reduced(&r);
+    return 0;
+}

@@ -1,0 +1,341 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: a closed
+form, a library routine on a special case, a brute-force solve of the
+unreduced saddle-point system, or an invariant the paper states.  None of
+these tests needs a GPU.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from paper_2407_11993_amd import inputs
+
+
+def _spd(n, seed):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((n, n))
+    return A @ A.T + n * np.eye(n)
+
+
+def _small_problem(orc, dims=(4, 4, 2), seed=1, coil=(1.5, 1.5, -2.0)):
+    xyz = inputs.grid(*dims)
+    n = xyz.shape[0]
+    rho = inputs.rho_loguniform(n, seed)
+    R = inputs.resistance_csr(dims, rho).to_dense()
+    L = orc.assemble_L(xyz, inputs.H_KERNEL)
+    M = inputs.coil_coupling(xyz, coil)[:, None]
+    return xyz, L, R, M
+
+
+# ---------------------------------------------------------------------------
+# elementary kernels
+# ---------------------------------------------------------------------------
+def test_assemble_L_closed_form(orc):
+    xyz = inputs.grid(3, 2, 2)
+    L = orc.assemble_L(xyz, 0.7)
+    assert np.allclose(np.diag(L), 1.0, rtol=0, atol=1e-15)       # h/sqrt(h^2)
+    i, j = 0, 1                                                    # unit distance
+    assert abs(L[i, j] - 0.7 / math.sqrt(1.0 + 0.49)) < 1e-15
+    i, j = 0, inputs.cell((3, 2, 2), 2, 1, 1)                      # |d|^2 = 6
+    assert abs(L[i, j] - 0.7 / math.sqrt(6.0 + 0.49)) < 1e-15
+    assert np.array_equal(L, L.T)
+    assert np.linalg.eigvalsh(L).min() > 0
+
+
+def test_cholesky_matches_library(orc):
+    A = _spd(37, 3)
+    G = orc.cholesky(A)
+    assert np.allclose(G, np.linalg.cholesky(A), rtol=1e-13, atol=1e-13)
+    assert np.abs(G @ G.T - A).max() / np.abs(A).max() < 1e-14
+    assert np.all(np.triu(G, 1) == 0)
+
+
+def test_cholesky_reports_pivot(orc):
+    A = np.diag([2.0, 1.0, -1.0, 3.0])
+    with pytest.raises(ValueError, match="pivot 2"):
+        orc.cholesky(A)
+
+
+def test_triangular_solves_match_library(orc):
+    G = np.linalg.cholesky(_spd(29, 4))
+    b = np.random.default_rng(5).standard_normal(29)
+    assert np.allclose(orc.forward(G, b), sla.solve_triangular(G, b, lower=True),
+                       rtol=1e-13, atol=1e-13)
+    assert np.allclose(orc.backward_T(G, b),
+                       sla.solve_triangular(G.T, b, lower=False),
+                       rtol=1e-13, atol=1e-13)
+
+
+def test_jacobi_matches_library_and_is_orthogonal(orc):
+    rng = np.random.default_rng(7)
+    A = rng.standard_normal((40, 40))
+    A = A + A.T
+    lam, Q, sweeps = orc.jacobi_eig(A)
+    ref = np.linalg.eigvalsh(A)
+    assert np.all(np.diff(lam) >= 0)
+    assert np.abs(lam - ref).max() <= 1e-13 * np.abs(ref).max()
+    assert np.abs(Q.T @ Q - np.eye(40)).max() < 1e-13
+    assert np.abs(A @ Q - Q * lam).max() < 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("a,b,c", [(2.0, 1.0, 3.0), (1.0, -4.0, 1.0),
+                                   (5.0, 1e-9, 5.0)])
+def test_jacobi_2x2_closed_form(orc, a, b, c):
+    lam, Q, _ = orc.jacobi_eig(np.array([[a, b], [b, c]]))
+    mid, rad = (a + c) / 2, math.hypot((a - c) / 2, b)
+    assert abs(lam[0] - (mid - rad)) < 1e-14 * (abs(mid) + rad)
+    assert abs(lam[1] - (mid + rad)) < 1e-14 * (abs(mid) + rad)
+
+
+def test_standard_form_matches_definition(orc):
+    _, L, R, _ = _small_problem(orc)
+    G = orc.cholesky(L)
+    C = orc.standard_form(G, R)
+    Gi = np.linalg.inv(G)
+    ref = Gi @ R @ Gi.T
+    assert np.abs(C - ref).max() < 1e-12 * np.abs(ref).max()
+    assert np.array_equal(C, C.T)
+
+
+def test_null_basis_properties(orc):
+    n = 20
+    E = np.zeros((2, n))
+    E[0, [0, 1, 2]] = 1.0
+    E[0, [7, 8]] = -1.0
+    E[1, [10, 11]] = 1.0
+    E[1, [18]] = -1.0
+    K = orc.null_basis(E)
+    assert K.shape == (n, n - 2)
+    assert np.abs(E @ K).max() < 1e-14
+    assert np.abs(K.T @ K - np.eye(n - 2)).max() < 1e-14
+    with pytest.raises(ValueError):
+        orc.null_basis(np.vstack([E[0], 2 * E[0]]))
+
+
+# ---------------------------------------------------------------------------
+# the generalized eigenproblem (Sec. 3.2)
+# ---------------------------------------------------------------------------
+def test_pencil_diagonal_special_case(orc):
+    Ld = np.array([1.0, 2.0, 0.5, 4.0])
+    Rd = np.array([3.0, 1.0, 2.0, 2.0])
+    pb = orc.Problem(np.diag(Ld), np.diag(Rd), np.zeros((4, 1)), np.zeros((1, 4)))
+    lam = orc.modal_eigen(pb, want_V=False)
+    assert np.allclose(lam, np.sort(Rd / Ld), rtol=1e-15, atol=0)
+
+
+def test_pencil_2x2_quadratic_formula(orc):
+    L = np.array([[2.0, 0.6], [0.6, 1.0]])
+    R = np.array([[1.0, -0.3], [-0.3, 3.0]])
+    pb = orc.Problem(L, R, np.zeros((2, 1)), np.zeros((1, 2)))
+    lam = orc.modal_eigen(pb, want_V=False)
+    # det(R - lam L) = a lam^2 + b lam + c
+    a = L[0, 0] * L[1, 1] - L[0, 1] ** 2
+    b = -(R[0, 0] * L[1, 1] + R[1, 1] * L[0, 0] - 2 * R[0, 1] * L[0, 1])
+    c = R[0, 0] * R[1, 1] - R[0, 1] ** 2
+    disc = math.sqrt(b * b - 4 * a * c)
+    ref = sorted([(-b - disc) / (2 * a), (-b + disc) / (2 * a)])
+    assert np.allclose(lam, ref, rtol=1e-14, atol=0)
+
+
+def test_modal_eigenvectors_diagonalise_pencil(orc):
+    _, L, R, M = _small_problem(orc)
+    pb = orc.Problem(L, R, M, M.T)
+    lam, V = orc.modal_eigen(pb)
+    n = L.shape[0]
+    assert np.all(lam > 0)                                   # Sec. 3.2: tau > 0
+    assert np.abs(V.T @ L @ V - np.eye(n)).max() < 1e-12     # L_n = 1
+    assert np.abs(V.T @ R @ V - np.diag(lam)).max() < 1e-12 * lam.max()
+    ref = np.sort(np.real(sla.eigvals(R, L)))
+    assert np.abs(lam - ref).max() < 1e-12 * lam.max()
+    # tau_n = L_n / R_n  (eq. modal_decomposition_discrete)
+    tau = np.diag(V.T @ L @ V) / np.diag(V.T @ R @ V)
+    assert np.allclose(1.0 / tau, lam, rtol=1e-11)
+    # trace invariant: sum lam = tr(L^{-1} R)
+    assert abs(lam.sum() - np.trace(np.linalg.solve(L, R))) < 1e-12 * lam.sum()
+
+
+def test_scaling_and_monotonicity(orc):
+    dims = (4, 4, 2)
+    xyz = inputs.grid(*dims)
+    n = xyz.shape[0]
+    L = orc.assemble_L(xyz, inputs.H_KERNEL)
+    rho1 = inputs.rho_loguniform(n, 11)
+    rho2 = rho1 * (1.0 + np.random.default_rng(12).uniform(0, 1, n))
+    R1 = inputs.resistance_csr(dims, rho1).to_dense()
+    R2 = inputs.resistance_csr(dims, rho2).to_dense()
+    z = np.zeros((n, 1))
+    lam1 = orc.modal_eigen(orc.Problem(L, R1, z, z.T), want_V=False)
+    lam2 = orc.modal_eigen(orc.Problem(L, R2, z, z.T), want_V=False)
+    lam3 = orc.modal_eigen(orc.Problem(L, 3.0 * R1, z, z.T), want_V=False)
+    # R -> kR  =>  tau -> tau / k  (Sec. 3.2)
+    assert np.allclose(lam3, 3.0 * lam1, rtol=1e-12)
+    # monotonicity: larger resistivity, shorter time constants (Sec. 2.3, 3.2)
+    assert np.all(lam2 >= lam1 * (1 - 1e-12))
+
+
+# ---------------------------------------------------------------------------
+# time stepping (Sec. 3.3)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("theta", [0.0, 0.5, 0.75, 1.0])
+@pytest.mark.parametrize("lam_dt", [0.01, 0.7, 3.0, 80.0])
+def test_single_mode_amplification(orc, theta, lam_dt):
+    # One unknown, l I' + r I = -m i': after a unit step in i at k = 0 the
+    # forcing vanishes and I^{k+1} = g I^k, g = (1-(1-theta) lam dt)/(1+theta lam dt).
+    l, m, dt = 2.0, 0.5, 0.25
+    r = lam_dt * l / dt
+    T = 12
+    i_src = np.ones((T + 1, 1))
+    i_src[0] = 0.0
+    pb = orc.Problem(np.array([[l]]), np.array([[r]]), np.array([[m]]),
+                     np.array([[1.0]]))
+    g = (1 - (1 - theta) * lam_dt) / (1 + theta * lam_dt)
+    _, I_d = orc.theta_direct(pb, theta, dt, T, i_src, want_I=True)
+    _, _, I_m = orc.theta_modal(pb, theta, dt, T, i_src, want_I=True)
+    for I in (I_d[:, 0], I_m[:, 0]):
+        assert abs(I[1] - (-m / (l + theta * dt * r))) < 1e-15
+        for k in range(1, T):
+            assert abs(I[k + 1] - g * I[k]) <= 1e-14 * abs(g * I[k]) + 1e-300
+
+
+@pytest.mark.parametrize("theta,order", [(0.5, 2.0), (1.0, 1.0)])
+def test_convergence_order(orc, theta, order):
+    # l I' + r I = -m i'(t), i = sin(w t), I(0) = 0, exact solution known.
+    l, r, m, w, tend = 1.0, 3.0, 0.7, 2.0, 2.0
+    lam = r / l
+
+    def exact(t):
+        return -(m * w / l) * (lam * math.cos(w * t) + w * math.sin(w * t)
+                               - lam * math.exp(-lam * t)) / (lam ** 2 + w ** 2)
+
+    errs = []
+    for T in (50, 100, 200, 400):
+        dt = tend / T
+        t = np.arange(T + 1) * dt
+        pb = orc.Problem(np.array([[l]]), np.array([[r]]), np.array([[m]]),
+                         np.array([[1.0]]))
+        _, I = orc.theta_direct(pb, theta, dt, T, np.sin(w * t)[:, None],
+                                want_I=True)
+        errs.append(abs(I[-1, 0] - exact(tend)))
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(3)]
+    assert all(abs(q - order) < 0.1 for q in rates), rates
+
+
+def test_energy_decays_without_forcing(orc):
+    _, L, R, M = _small_problem(orc)
+    T = 60
+    i_src = np.minimum(np.arange(T + 1), 10)[:, None] / 10.0   # ramp then hold
+    for theta in (0.5, 1.0):
+        _, I = orc.theta_direct(orc.Problem(L, R, M, M.T), theta, 0.5, T,
+                                i_src, want_I=True)
+        W = 0.5 * np.einsum("ki,ij,kj->k", I, L, I)
+        assert np.all(np.diff(W[10:]) <= 1e-15 * W[10])
+        assert W[-1] < W[10]
+
+
+def test_crank_nicolson_energy_identity(orc):
+    _, L, R, M = _small_problem(orc)
+    T, dt = 40, 0.5
+    t = np.arange(T + 1) * dt
+    i_src = np.sin(t)[:, None]
+    _, I = orc.theta_direct(orc.Problem(L, R, M, M.T), 0.5, dt, T, i_src,
+                            want_I=True)
+    W = 0.5 * np.einsum("ki,ij,kj->k", I, L, I)
+    for k in range(T):
+        It = 0.5 * (I[k] + I[k + 1])
+        f = -M[:, 0] * (i_src[k + 1, 0] - i_src[k, 0])
+        rhs = -dt * It @ R @ It + It @ f
+        assert abs((W[k + 1] - W[k]) - rhs) < 1e-12 * max(W.max(), 1e-30)
+
+
+def _saddle_point_stepper(L, R, E, M, P, theta, dt, T, i_src, i_D):
+    """Brute force on the unreduced system (Sec. 3.1, eqs. discrete_version_
+    1a/b): each step solves [[L + theta dt R, E^T], [E, 0]] [dI; Phi]
+    = [-dt R I - M0 d i0; d iD] with a dense LU.  No null-space basis."""
+    n, m = L.shape[0], E.shape[0]
+    A = np.zeros((n + m, n + m))
+    A[:n, :n] = L + theta * dt * R
+    A[:n, n:] = E.T
+    A[n:, :n] = E
+    lu = sla.lu_factor(A)
+    # I^0: the injected part only, E I^0 = iD^0 with I^0 in im E^T
+    I = E.T @ np.linalg.solve(E @ E.T, i_D[0]) if m else np.zeros(n)
+    sig = np.zeros((T, P.shape[0]))
+    hist = [I.copy()]
+    for k in range(T):
+        rhs = np.concatenate([-dt * R @ I - M @ (i_src[k + 1] - i_src[k]),
+                              i_D[k + 1] - i_D[k]])
+        dI = sla.lu_solve(lu, rhs)[:n]
+        I = I + dI
+        sig[k] = P @ dI / dt
+        hist.append(I.copy())
+    return sig, np.array(hist)
+
+
+def _electrode_problem(orc, nx=5, ny=6, T=40):
+    w = inputs.electrode_plate(nx, ny, 2, T=T, tau_D=15.0, coil_period=17.0,
+                               seed=21)
+    L = orc.assemble_L(w.xyz, w.h)
+    R = w.R.to_dense()
+    E = w.E.to_dense()
+    return w, L, R, E
+
+
+@pytest.mark.parametrize("theta", [0.5, 1.0])
+def test_direct_matches_unreduced_saddle_point(orc, theta):
+    w, L, R, E = _electrode_problem(orc)
+    pb = orc.Problem(L, R, w.M, w.P, E)
+    sig, I = orc.theta_direct(pb, theta, w.dt, w.T, w.i_src, w.i_D, want_I=True)
+    ref_sig, ref_I = _saddle_point_stepper(L, R, E, w.M, w.P, theta, w.dt, w.T,
+                                           w.i_src, w.i_D)
+    assert np.abs(sig - ref_sig).max() < 1e-11 * np.abs(ref_sig).max()
+    assert np.abs(I - ref_I).max() < 1e-11 * np.abs(ref_I).max()
+    # the constraint E I = iD holds at every step (eq. discrete_version_1b)
+    assert np.abs(I @ E.T - w.i_D).max() < 1e-13
+
+
+@pytest.mark.parametrize("theta", [0.5, 1.0])
+def test_modal_matches_direct_with_electrodes(orc, theta):
+    w, L, R, E = _electrode_problem(orc)
+    pb = orc.Problem(L, R, w.M, w.P, E)
+    s_d, I_d = orc.theta_direct(pb, theta, w.dt, w.T, w.i_src, w.i_D, want_I=True)
+    s_m, lam, I_m = orc.theta_modal(pb, theta, w.dt, w.T, w.i_src, w.i_D,
+                                    want_I=True)
+    assert np.abs(s_m - s_d).max() < 1e-11 * np.abs(s_d).max()
+    assert np.abs(I_m - I_d).max() < 1e-11 * np.abs(I_d).max()
+    # eigenvalues of the reduced pencil do not depend on the choice of K
+    K2 = sla.null_space(E)                       # SVD basis, not Householder
+    ref = np.sort(np.real(sla.eigvals(K2.T @ R @ K2, K2.T @ L @ K2)))
+    assert np.abs(lam - ref).max() < 1e-11 * lam.max()
+
+
+def test_dc_fixed_point(orc):
+    # Constant injected current, no coil: I -> argmin I^T R I s.t. E I = iD.
+    w, L, R, E = _electrode_problem(orc, T=400)
+    iD = np.ones_like(w.i_D)
+    iD[0] = 0.0
+    pb = orc.Problem(L, R, np.zeros_like(w.M), w.P, E)
+    _, I = orc.theta_direct(pb, 1.0, 50.0, 400, np.zeros_like(w.i_src), iD,
+                            want_I=True)
+    n, m = L.shape[0], E.shape[0]
+    A = np.block([[R, E.T], [E, np.zeros((m, m))]])
+    ref = np.linalg.solve(A, np.concatenate([np.zeros(n), iD[-1]]))[:n]
+    assert np.abs(I[-1] - ref).max() < 1e-10 * np.abs(ref).max()
+
+
+def test_modal_equals_direct_on_block(orc):
+    xyz, L, R, M = _small_problem(orc, dims=(3, 4, 3), seed=2)
+    T = 150
+    t = np.arange(T + 1.0)
+    i_src = np.exp(-((t - 40.0) / 12.0) ** 2)[:, None]
+    pb = orc.Problem(L, R, M, M.T)
+    for theta in (0.5, 1.0):
+        s_d = orc.theta_direct(pb, theta, 1.0, T, i_src)
+        s_m, _ = orc.theta_modal(pb, theta, 1.0, T, i_src)
+        ref, _ = _saddle_point_stepper(L, R, np.zeros((0, L.shape[0])), M,
+                                       M.T, theta, 1.0, T, i_src,
+                                       np.zeros((T + 1, 0)))
+        assert np.abs(s_d - ref).max() < 1e-12 * np.abs(ref).max()
+        assert np.abs(s_m - ref).max() < 1e-11 * np.abs(ref).max()
