@@ -1,0 +1,178 @@
+/*
+ * libmm -- modal and Cholesky theta-methods for eddy-current transients on
+ * one MI355X (gfx950), FP64 throughout.
+ *
+ * The problem follows the Galerkin circuit system of Ventre, Chiariello,
+ * Isernia, Mottola, Tamburrino, "Modal Decomposition in Numerical
+ * Computation of Eddy Current Transients" (arXiv 2407.11993), Sec. 3.1,
+ * eqs. discrete_version_1a/b:
+ *
+ *     R I + L dI/dt + E^T phi = V0 + VD,        E I = iD,
+ *
+ * with L the dense SPD inductance matrix, R the sparse SPD resistance matrix,
+ * E the reduced electrode incidence ((Ne-1) x N, Sec. 3.1 eq. definition_E),
+ * and V0 = -M0 di0/dt for solenoidal sources with mutual inductances M0
+ * (Sec. 3.1, eq. induced_voltages_0).  Currents injected at electrodes are
+ * handled by the paper's split I = K Ii + E^T (E E^T)^{-1} iD
+ * (eq. current_electrodes), K an orthonormal basis of ker E.
+ *
+ * Conventions
+ *   - Every array argument is a DEVICE pointer unless stated otherwise.
+ *     Dense matrices are column-major.  The caller owns its inputs and
+ *     outputs; the library copies what it keeps.
+ *   - Calls are ordered on the context's HIP stream and may return before
+ *     the work completes, like any stream-ordered call.  Calls that must
+ *     inspect a device-side result (the factorisation pivots, the
+ *     eigensolver's convergence) synchronise that stream.
+ *   - Status codes are returned synchronously; mm_last_error() gives the text.
+ *   - One context per host thread.
+ *   - Waveforms are sampled at t_k = k dt, k = 0..n_steps, row-major by step:
+ *     i_src[k * n_src + c], i_D[k * (Ne-1) + a].  Each step call continues
+ *     from the state left by the previous one (I(0) = 0 after setup or reset).
+ */
+#ifndef MM_H
+#define MM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MM_OK = 0,
+  MM_E_INVALID = 1,     /* bad argument or unsupported size */
+  MM_E_NOMEM = 2,       /* device allocation failed */
+  MM_E_NOT_SPD = 3,     /* a Cholesky pivot was not positive (index in message) */
+  MM_E_NO_CONVERGE = 4, /* a secular equation did not converge */
+  MM_E_STATE = 5,       /* call out of order (e.g. step_modal before decompose) */
+  MM_E_DEVICE = 6       /* a HIP runtime call failed */
+} mm_status;
+
+typedef struct mm_ctx mm_ctx;
+
+/* The problem statement (Sec. 3.1).  All pointers are device pointers. */
+typedef struct {
+  int64_t n;                /* unknowns N */
+  const double* xyz;        /* n x 3, row i = centre of cell i (row-major);
+                               L_ij = h / sqrt(|x_i - x_j|^2 + h^2) is
+                               assembled on the device (the SPD stand-in of
+                               the inductance matrix, Sec. 3.1 L_jk) */
+  double h;                 /* kernel width, > 0 */
+  int64_t r_nnz;            /* R: symmetric positive definite, CSR, n x n */
+  const int64_t* r_rowptr;  /* n + 1 */
+  const int32_t* r_col;     /* r_nnz, sorted per row */
+  const double* r_val;      /* r_nnz */
+  int32_t n_e;              /* electrodes Ne: 0, or >= 2 */
+  int64_t e_nnz;            /* E: (Ne-1) x n CSR, full row rank */
+  const int64_t* e_rowptr;
+  const int32_t* e_col;
+  const double* e_val;
+  int32_t n_src;            /* solenoidal sources (columns of M0), >= 0 */
+  const double* M0;         /* n x n_src, column-major */
+  int32_t n_probe;          /* probe rows, 1..8 */
+  const double* P;          /* n x n_probe, column-major: column p is probe
+                               row p; signal_p = P(:,p)^T dI/dt */
+} mm_problem;
+
+/* Copy the problem to the device and prepare the context.  `stream` is a
+ * hipStream_t (NULL = the default stream).  On success *out owns all device
+ * memory the library allocates for this problem. */
+mm_status mm_setup(const mm_problem* problem, void* stream, mm_ctx** out);
+
+/* The one-off modal decomposition (Sec. 3.2): Li = G G^T, C = G^{-1} Ri G^{-T},
+ * C = Q Lam Q^T (two-stage tridiagonalisation + divide and conquer), and the
+ * projections of the sources and probes onto the modes.  Independent of theta
+ * and dt.  Synchronises the stream.  Errors: MM_E_NOT_SPD (Li not positive
+ * definite), MM_E_NO_CONVERGE. */
+mm_status mm_decompose(mm_ctx* ctx);
+
+/* The modal theta-method (Sec. 3.3.2) for n_steps steps:
+ *   (1 + theta dt lam_n) dy_n = -dt lam_n y_n + (modal forcing)_n.
+ * The forcing is the Cholesky method's right-hand side (Sec. 3.3.1,
+ * eq. time_integration) written in the modal basis.  signal (n_steps x
+ * n_probe, row-major by step) receives P^T (I^{k+1} - I^k) / dt for
+ * k = 0..n_steps-1.  i_src: (n_steps+1) x n_src; i_D: (n_steps+1) x (Ne-1)
+ * or NULL when Ne = 0.  Requires mm_decompose.  theta in [0, 1], dt > 0. */
+mm_status mm_step_modal(mm_ctx* ctx, double theta, double dt, int64_t n_steps,
+                        const double* i_src, const double* i_D, double* signal);
+
+/* The classical theta-method (Sec. 3.3.1, eq. time_integration): the
+ * factor Z = Li + theta dt Ri = C C^T is computed on the first call and
+ * whenever theta or dt change; each step does one forward and one backward
+ * substitution.  Same arguments and outputs as mm_step_modal.  Synchronises
+ * the stream when it (re)factors.  Errors: MM_E_NOT_SPD. */
+mm_status mm_step_cholesky(mm_ctx* ctx, double theta, double dt, int64_t n_steps,
+                           const double* i_src, const double* i_D,
+                           double* signal);
+
+#define MM_MODAL 0
+#define MM_CHOLESKY 1
+
+/* Reconstruction of the current (Sec. 3.1, eq. current_electrodes):
+ * I = K Ii + E^T (E E^T)^{-1} iD, with Ii = G^{-T} Q y for the modal state.
+ * rows == NULL: out (n) receives I.  Otherwise rows is n x n_rows
+ * (column-major) and out (n_rows) receives rows^T I. */
+mm_status mm_probe(mm_ctx* ctx, int32_t which, int32_t n_rows,
+                   const double* rows, double* out);
+
+/* Set both states back to I = 0. */
+mm_status mm_reset_state(mm_ctx* ctx);
+
+/* Eigenvalues lam_n = 1/tau_n of the reduced pencil, ascending (n0 doubles,
+ * device).  Requires mm_decompose. */
+mm_status mm_eigenvalues(mm_ctx* ctx, double* out);
+
+/* Sizes: out[0] = n, out[1] = n0 = n - (Ne-1), out[2] = decomposed (0/1). */
+mm_status mm_info(const mm_ctx* ctx, int64_t* out /* host, 3 */);
+
+void mm_destroy(mm_ctx* ctx);
+
+/* Text of the last error on this context (or of the last mmk_ call on this
+ * thread when ctx is NULL). */
+const char* mm_last_error(const mm_ctx* ctx);
+
+/* ------------------------------------------------------------------------
+ * Dense building blocks, exposed for the stage-by-stage tests.  Device
+ * pointers, column-major, ordered on `stream`; workspaces are allocated and
+ * freed inside each call (which therefore synchronises the stream).
+ * ------------------------------------------------------------------------ */
+
+/* C = alpha op(A) op(B) + beta C on the FP64 matrix cores. */
+mm_status mmk_dgemm(int32_t trans_a, int32_t trans_b, int64_t m, int64_t n,
+                    int64_t k, double alpha, const double* A, int64_t lda,
+                    const double* B, int64_t ldb, double beta, double* C,
+                    int64_t ldc, void* stream);
+
+/* A = G G^T (lower, in place, strict upper triangle zeroed); *info (host)
+ * = -1 or the first non-positive pivot.  (The factorisation of Sec. 3.3.1
+ * and of Li in Sec. 3.2.) */
+mm_status mmk_dpotrf(int64_t n, double* A, int64_t lda, int64_t* info,
+                     void* stream);
+
+/* A <- A^{-1} for lower-triangular A. */
+mm_status mmk_dtrtri(int64_t n, double* A, int64_t lda, void* stream);
+
+/* Band reduction C = Q1 B Q1^T: A (full symmetric) is overwritten; AB
+ * (ldab x n, ldab >= 2 nb + 1) receives the lower band, AB(d, j) = B(j+d, j). */
+mm_status mmk_dsy2sb(int64_t n, double* A, int64_t lda, int32_t nb, double* AB,
+                     int64_t ldab, void* stream);
+
+/* Band to tridiagonal by bulge chasing: d (n), e (n-1). */
+mm_status mmk_dsb2st(int64_t n, int32_t nb, double* AB, int64_t ldab, double* d,
+                     double* e, void* stream);
+
+/* Tridiagonal divide and conquer: w (n, ascending), Z (n x n, ld n). */
+mm_status mmk_dstedc(int64_t n, const double* d, const double* e, double* w,
+                     double* Z, void* stream);
+
+/* Full symmetric eigensolver: A (full symmetric, destroyed) = Z diag(w) Z^T,
+ * w ascending, Z (n x n, ld n). */
+mm_status mmk_dsyevd(int64_t n, double* A, int64_t lda, int32_t nb, double* w,
+                     double* Z, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MM_H */

@@ -1,0 +1,68 @@
+// Internal launchers of the symmetric eigensolver C = Q Lam Q^T:
+// band reduction (sy2sb.hip), bulge chase and back-transforms (sb2st.hip),
+// tridiagonal divide and conquer (stedc.hip), driver (eig.hip).
+#pragma once
+#include "kernels.h"
+
+#include <vector>
+
+namespace mm {
+
+// ---- stage 1: C = Q1 B Q1^T (full symmetric storage, band nb) -------------
+int64_t sy2sb_ws_elems(int64_t n, int nb);
+int64_t sy2sb_npanels(int64_t n, int nb);
+// tau_all: npanels x nb, T_all: npanels x nb x nb.
+void sy2sb(double* A, int64_t lda, int64_t n, int nb, double* tau_all, double* T_all,
+           double* ws, int64_t ws_elems, hipStream_t s);
+// AB(d, j) = B(j + d, j) for d <= nb; rows nb+1..ldab-1 zeroed.
+void extract_band(const double* A, int64_t lda, int64_t n, int nb, double* AB,
+                  int64_t ldab, hipStream_t s);
+// Z <- Q1 Z for the panel reflectors left in A's lower part by sy2sb.
+void apply_q1(const double* A, int64_t lda, int64_t n, int nb, const double* T_all,
+              double* Z, int64_t ldz, int64_t ncols, double* ws, int64_t ws_elems,
+              hipStream_t s);
+int64_t apply_q1_ws_elems(int64_t n, int nb, int64_t ncols);
+
+// ---- stage 2: B = Q2 T Q2^T by bulge chasing -------------------------------
+struct Sb2stPlan {
+  int64_t n = 0;
+  int nb = 0;
+  std::vector<int64_t> offset;  // first task of sweep s (n entries + total)
+  int64_t tasks = 0;
+};
+Sb2stPlan sb2st_plan(int64_t n, int nb);
+// AB has ldab = 2 nb + 1 rows.  Writes d (n), e (n-1), and the reflectors
+// V2 (tasks x nb) and tau2 (tasks); d_offset is plan.offset on the device.
+void sb2st(double* AB, int64_t ldab, const Sb2stPlan& plan, const int64_t* d_offset,
+           double* V2, double* tau2, double* d, double* e, hipStream_t s);
+// Z <- Q2 Z (rows 0..n-1, ncols columns).
+void apply_q2(const Sb2stPlan& plan, const int64_t* d_offset, const double* V2,
+              const double* tau2, double* Z, int64_t ldz, int64_t ncols, hipStream_t s);
+
+// ---- tridiagonal divide and conquer ---------------------------------------
+int64_t stedc_ws_elems(int64_t n);
+// Eigenvalues (ascending) and eigenvectors (n x n, ld ldz) of the symmetric
+// tridiagonal (d, e).  d and e are not modified.  *d_status receives a
+// non-zero code if a secular equation did not converge.
+void stedc(const double* d, const double* e, int64_t n, double* lam, double* Z,
+           int64_t ldz, double* ws, int64_t ws_elems, int64_t* d_status, hipStream_t s);
+
+// ---- driver -----------------------------------------------------------------
+struct EigWork {
+  int nb = 64;
+  double* tau1 = nullptr;
+  double* T1 = nullptr;
+  double* AB = nullptr;
+  double* V2 = nullptr;
+  double* tau2 = nullptr;
+  int64_t* d_offset = nullptr;
+  double* d = nullptr;
+  double* e = nullptr;
+  double* ws = nullptr;
+  int64_t ws_elems = 0;
+};
+// C (full symmetric, destroyed: it keeps the stage-1 reflectors) -> lam, Q.
+void syevd(double* C, int64_t ldc, int64_t n, double* lam, double* Q, int64_t ldq,
+           const EigWork& w, const Sb2stPlan& plan, int64_t* d_status, hipStream_t s);
+
+}  // namespace mm

@@ -1,0 +1,83 @@
+// Symmetric eigensolver driver C = Q Lam Q^T (the modal decomposition's
+// standard form, Sec. 3.2):
+//   sy2sb (band nb)  ->  sb2st (tridiagonal)  ->  stedc  ->  Q = Q1 (Q2 Z).
+// Q1 is applied panel by panel, last panel first, as the compact WY product
+//   Z(r0:, :) -= V (T (V^T Z(r0:, :)))   on the matrix cores.
+#include "eig.h"
+
+namespace mm {
+namespace {
+
+__global__ void extract_v_k(const double* P, int64_t ldp, int64_t m, int nb, double* V) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m * nb) return;
+  const int64_t i = e % m;
+  const int c = (int)(e / m);
+  double v = 0.0;
+  if (i == c) v = 1.0;
+  else if (i > c) v = P[i + (int64_t)c * ldp];
+  V[e] = v;
+}
+
+}  // namespace
+
+int64_t apply_q1_ws_elems(int64_t n, int nb, int64_t ncols) {
+  return n * nb + 2 * nb * ncols + 8 * nb * ncols;
+}
+
+void apply_q1(const double* A, int64_t lda, int64_t n, int nb, const double* T_all, double* Z,
+              int64_t ldz, int64_t ncols, double* ws, int64_t ws_elems, hipStream_t s) {
+  MM_REQUIRE(ws_elems >= apply_q1_ws_elems(n, nb, ncols), kInvalid,
+             "apply_q1: workspace too small");
+  const int64_t np = sy2sb_npanels(n, nb);
+  double* V = ws;                       // m x nb
+  double* W = V + n * nb;               // nb x ncols
+  double* W2 = W + nb * ncols;          // nb x ncols
+  double* split = W2 + nb * ncols;
+  const int64_t split_elems = 8 * nb * ncols;
+  for (int64_t p = np - 1; p >= 0; --p) {
+    const int64_t j = p * nb, r0 = j + nb, m = n - r0;
+    const double* P = A + r0 + j * lda;
+    hipLaunchKernelGGL(extract_v_k, dim3((unsigned)ceil_div(m * nb, 256)), dim3(256), 0, s, P,
+                       lda, m, nb, V);
+    MM_HIP_TRY(hipGetLastError());
+    const double* T = T_all + p * (int64_t)nb * nb;
+    // W = V^T Z(r0:, :)
+    Gemm g1;
+    g1.m = nb; g1.n = ncols; g1.k = m;
+    g1.A = V; g1.lda = m; g1.ta = true;
+    g1.B = Z + r0; g1.ldb = ldz;
+    g1.C = W; g1.ldc = nb;
+    gemm(g1, s, split, split_elems);
+    // W2 = T W   (T upper: op(A)(i,k) = 0 for k < i)
+    Gemm g2;
+    g2.m = nb; g2.n = ncols; g2.k = nb;
+    g2.A = T; g2.lda = nb; g2.a_upper = true;
+    g2.B = W; g2.ldb = nb;
+    g2.C = W2; g2.ldc = nb;
+    gemm(g2, s);
+    // Z(r0:, :) -= V W2
+    Gemm g3;
+    g3.m = m; g3.n = ncols; g3.k = nb;
+    g3.alpha = -1.0; g3.beta = 1.0;
+    g3.A = V; g3.lda = m;
+    g3.B = W2; g3.ldb = nb;
+    g3.C = Z + r0; g3.ldc = ldz;
+    gemm(g3, s);
+  }
+}
+
+void syevd(double* C, int64_t ldc, int64_t n, double* lam, double* Q, int64_t ldq,
+           const EigWork& w, const Sb2stPlan& plan, int64_t* d_status, hipStream_t s) {
+  MM_REQUIRE(ldq == n, kInvalid, "syevd: ldq must equal n");
+  const int nb = w.nb;
+  sy2sb(C, ldc, n, nb, w.tau1, w.T1, w.ws, w.ws_elems, s);
+  const int64_t ldab = 2 * nb + 1;
+  extract_band(C, ldc, n, nb, w.AB, ldab, s);
+  sb2st(w.AB, ldab, plan, w.d_offset, w.V2, w.tau2, w.d, w.e, s);
+  stedc(w.d, w.e, n, lam, Q, ldq, w.ws, w.ws_elems, d_status, s);
+  apply_q2(plan, w.d_offset, w.V2, w.tau2, Q, ldq, n, s);
+  apply_q1(C, ldc, n, nb, w.T1, Q, ldq, n, w.ws, w.ws_elems, s);
+}
+
+}  // namespace mm

@@ -1,0 +1,304 @@
+// FP64 GEMM on the gfx950 matrix cores (v_mfma_f64_16x16x4_f64).
+//
+// C = alpha op(A) op(B) + beta C, column-major.  One workgroup of four
+// 64-wide waves computes a BM x BN tile; each wave owns a (BM/2) x (BN/2)
+// quarter made of 16x16 MFMA blocks.  op(A) and op(B) are staged through LDS
+// in k-slices of 16 (double buffered, one barrier per slice).  The operands
+// are fed to the MFMA with B first so that each lane's four results lie in
+// one column of C on consecutive rows, which makes the column-major stores
+// contiguous per 16 lanes.
+//
+// Workgroups are renumbered so that consecutive tiles land on the same XCD
+// (the dispatcher deals workgroups round-robin over the 8 XCDs, each with its
+// own L2), and tiles are walked in groups of 8 tile-rows for L2 reuse.
+#include "common.h"
+
+namespace mm {
+namespace {
+
+constexpr int BK = 16;    // k-slice per LDS stage
+constexpr int PAD = 2;    // LDS row padding (doubles): conflict-free k-major stores
+constexpr int NT = 256;   // threads per workgroup (4 waves)
+constexpr int GROUP_M = 8;
+
+struct KArgs {
+  int64_t m, n, k;
+  double alpha, beta;
+  const double* A;
+  int64_t lda;
+  const double* B;
+  int64_t ldb;
+  double* C;
+  int64_t ldc;
+  int lower, a_lower, a_upper, b_lower;
+  int64_t b_band;
+  int64_t sA, sB, sC;
+  int splits;
+  double* ws;
+  const GemmGroup* groups;
+  int tiles_m, tiles_n;  // tile grid the launch covers
+};
+
+__device__ __forceinline__ void tile_of(int bid, int tiles_m, int tiles_n,
+                                        int& ti, int& tj) {
+  const int T = tiles_m * tiles_n;
+  // XCD-aware renumbering: bid = local * 8 + xcd  ->  t = off(xcd) + local
+  const int xcd = bid & 7, local = bid >> 3;
+  const int base = T >> 3, rem = T & 7;
+  const int t = xcd * base + (xcd < rem ? xcd : rem) + local;
+  // grouped ordering along M
+  const int per_group = GROUP_M * tiles_n;
+  const int g = t / per_group;
+  const int first_m = g * GROUP_M;
+  const int gsz = min(tiles_m - first_m, GROUP_M);
+  const int w = t - g * per_group;
+  ti = first_m + w % gsz;
+  tj = w / gsz;
+}
+
+template <int BM, int BN, bool TA, bool TB, bool GROUPED>
+__global__ void __launch_bounds__(NT) gemm_kernel(KArgs a) {
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int FM = WM / 16, FN = WN / 16;
+  constexpr int LA = BM * BK / NT;  // A elements loaded per thread per slice
+  constexpr int LB = BN * BK / NT;
+  __shared__ double As[2][BK][BM + PAD];
+  __shared__ double Bs[2][BK][BN + PAD];
+
+  int64_t M, N, K, lda, ldb, ldc;
+  const double* A;
+  const double* B;
+  double* C;
+  if constexpr (GROUPED) {
+    const GemmGroup g = a.groups[blockIdx.y];
+    M = g.m; N = g.n; K = g.k; lda = g.lda; ldb = g.ldb; ldc = g.ldc;
+    A = g.A; B = g.B; C = g.C;
+  } else {
+    M = a.m; N = a.n; K = a.k; lda = a.lda; ldb = a.ldb; ldc = a.ldc;
+    A = a.A + (int64_t)blockIdx.y * a.sA;
+    B = a.B + (int64_t)blockIdx.y * a.sB;
+    C = a.C + (int64_t)blockIdx.y * a.sC;
+  }
+  int ti, tj;
+  tile_of(blockIdx.x, a.tiles_m, a.tiles_n, ti, tj);
+  const int64_t i0 = (int64_t)ti * BM, j0 = (int64_t)tj * BN;
+  if (i0 >= M || j0 >= N) return;
+  if (a.lower && i0 + BM <= j0) return;  // tile strictly above the diagonal
+
+  int64_t kb = 0, ke = K;
+  if (a.a_lower) ke = min(ke, i0 + BM);
+  if (a.b_band >= 0) ke = min(ke, j0 + BN + a.b_band);
+  if (a.a_upper) kb = max(kb, i0);
+  if (a.b_lower) kb = max(kb, j0);
+  kb = (kb / BK) * BK;
+  if (a.splits > 1) {
+    const int64_t span = ke > kb ? ke - kb : 0;
+    const int64_t chunk = ceil_div(ceil_div(span, a.splits), BK) * BK;
+    const int64_t s0 = kb + (int64_t)blockIdx.z * chunk;
+    kb = s0;
+    ke = min(ke, s0 + chunk);
+  }
+
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int wm0 = (wave & 1) * WM, wn0 = (wave >> 1) * WN;
+  const int lr = lane & 15, lk = lane >> 4;
+
+  v4d acc[FM][FN];
+#pragma unroll
+  for (int x = 0; x < FM; ++x)
+#pragma unroll
+    for (int y = 0; y < FN; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
+
+  double ra[LA], rb[LB];
+
+  auto load = [&](int64_t kt) {
+#pragma unroll
+    for (int r = 0; r < LA; ++r) {
+      const int e = t + r * NT;
+      int ii, kk;
+      if constexpr (!TA) { ii = e % BM; kk = e / BM; }
+      else { kk = e % BK; ii = e / BK; }
+      const int64_t gi = i0 + ii, gk = kt + kk;
+      double v = 0.0;
+      if (gi < M && gk < ke)
+        v = TA ? A[gk + gi * lda] : A[gi + gk * lda];
+      ra[r] = v;
+    }
+#pragma unroll
+    for (int r = 0; r < LB; ++r) {
+      const int e = t + r * NT;
+      int jj, kk;
+      if constexpr (!TB) { kk = e % BK; jj = e / BK; }
+      else { jj = e % BN; kk = e / BN; }
+      const int64_t gj = j0 + jj, gk = kt + kk;
+      double v = 0.0;
+      if (gj < N && gk < ke)
+        v = TB ? B[gj + gk * ldb] : B[gk + gj * ldb];
+      rb[r] = v;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < LA; ++r) {
+      const int e = t + r * NT;
+      int ii, kk;
+      if constexpr (!TA) { ii = e % BM; kk = e / BM; }
+      else { kk = e % BK; ii = e / BK; }
+      As[buf][kk][ii] = ra[r];
+    }
+#pragma unroll
+    for (int r = 0; r < LB; ++r) {
+      const int e = t + r * NT;
+      int jj, kk;
+      if constexpr (!TB) { kk = e % BK; jj = e / BK; }
+      else { jj = e % BN; kk = e / BN; }
+      Bs[buf][kk][jj] = rb[r];
+    }
+  };
+
+  if (ke > kb) {
+    load(kb);
+    store(0);
+    __syncthreads();
+    int cur = 0;
+    for (int64_t kt = kb; kt < ke; kt += BK) {
+      const bool more = kt + BK < ke;
+      if (more) load(kt + BK);
+#pragma unroll
+      for (int kk = 0; kk < BK / 4; ++kk) {
+        double av[FM], bv[FN];
+#pragma unroll
+        for (int x = 0; x < FM; ++x) av[x] = As[cur][kk * 4 + lk][wm0 + x * 16 + lr];
+#pragma unroll
+        for (int y = 0; y < FN; ++y) bv[y] = Bs[cur][kk * 4 + lk][wn0 + y * 16 + lr];
+#pragma unroll
+        for (int x = 0; x < FM; ++x)
+#pragma unroll
+          for (int y = 0; y < FN; ++y)
+            acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[y], av[x], acc[x][y], 0, 0, 0);
+      }
+      if (more) store(cur ^ 1);
+      __syncthreads();
+      cur ^= 1;
+    }
+  }
+
+  // Epilogue.  v_mfma_f64_16x16x4 leaves D(l/16 + 4q, l%16) in result q of
+  // lane l; with B fed first, D is the transposed tile, so lane l holds
+  // C(i0 + wm0 + 16x + lr, j0 + wn0 + 16y + lk + 4q), q < 4.
+  if (a.splits > 1) {
+    double* W = a.ws + (int64_t)blockIdx.z * M * N;
+#pragma unroll
+    for (int x = 0; x < FM; ++x)
+#pragma unroll
+      for (int y = 0; y < FN; ++y)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t gi = i0 + wm0 + x * 16 + lr;
+          const int64_t gj = j0 + wn0 + y * 16 + lk + 4 * q;
+          if (gi < M && gj < N) W[gi + gj * M] = a.alpha * acc[x][y][q];
+        }
+    return;
+  }
+#pragma unroll
+  for (int x = 0; x < FM; ++x)
+#pragma unroll
+    for (int y = 0; y < FN; ++y)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t gi = i0 + wm0 + x * 16 + lr;
+        const int64_t gj = j0 + wn0 + y * 16 + lk + 4 * q;
+        if (gi < M && gj < N && (!a.lower || gi >= gj)) {
+          double v = a.alpha * acc[x][y][q];
+          if (a.beta != 0.0) v += a.beta * C[gi + gj * ldc];
+          C[gi + gj * ldc] = v;
+        }
+      }
+}
+
+// C = beta C + sum_z W_z, in a fixed order (deterministic split-K).
+__global__ void splitk_reduce(int64_t M, int64_t N, int splits, const double* W,
+                              double beta, double* C, int64_t ldc, int lower) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= M * N) return;
+  const int64_t i = idx % M, j = idx / M;
+  if (lower && i < j) return;
+  double s = 0.0;
+  for (int z = 0; z < splits; ++z) s += W[(int64_t)z * M * N + idx];
+  if (beta != 0.0) s += beta * C[i + j * ldc];
+  C[i + j * ldc] = s;
+}
+
+template <int BM, int BN, bool GROUPED>
+void launch(const KArgs& ka, bool ta, bool tb, dim3 grid, hipStream_t s) {
+  if (!ta && !tb) hipLaunchKernelGGL((gemm_kernel<BM, BN, false, false, GROUPED>), grid, dim3(NT), 0, s, ka);
+  else if (!ta && tb) hipLaunchKernelGGL((gemm_kernel<BM, BN, false, true, GROUPED>), grid, dim3(NT), 0, s, ka);
+  else if (ta && !tb) hipLaunchKernelGGL((gemm_kernel<BM, BN, true, false, GROUPED>), grid, dim3(NT), 0, s, ka);
+  else hipLaunchKernelGGL((gemm_kernel<BM, BN, true, true, GROUPED>), grid, dim3(NT), 0, s, ka);
+}
+
+}  // namespace
+
+void gemm(const Gemm& g, hipStream_t stream, double* ws, int64_t ws_elems) {
+  if (g.m <= 0 || g.n <= 0 || g.batch <= 0) return;
+  MM_REQUIRE(g.A != nullptr || g.k == 0, kInvalid, "gemm: null A");
+  MM_REQUIRE(g.C != nullptr, kInvalid, "gemm: null C");
+  KArgs ka{};
+  ka.m = g.m; ka.n = g.n; ka.k = g.k;
+  ka.alpha = g.alpha; ka.beta = g.beta;
+  ka.A = g.A; ka.lda = g.lda; ka.B = g.B; ka.ldb = g.ldb;
+  ka.C = g.C; ka.ldc = g.ldc;
+  ka.lower = g.lower; ka.a_lower = g.a_lower; ka.a_upper = g.a_upper;
+  ka.b_lower = g.b_lower; ka.b_band = g.b_band;
+  ka.sA = g.sA; ka.sB = g.sB; ka.sC = g.sC;
+  ka.splits = 1; ka.ws = nullptr; ka.groups = nullptr;
+  if (g.k <= 0) {
+    ka.k = 0;  // C = beta C through the epilogue
+  }
+  const bool big = g.m * g.n >= (int64_t)256 * 128 * 128;
+  const int bm = big ? 128 : 64, bn = bm;
+  ka.tiles_m = (int)ceil_div(g.m, bm);
+  ka.tiles_n = (int)ceil_div(g.n, bn);
+  const int64_t tiles = (int64_t)ka.tiles_m * ka.tiles_n;
+  MM_REQUIRE(tiles < (int64_t)1 << 31, kInvalid, "gemm: too many tiles");
+  // split-K for few output tiles over a long k (never together with batching)
+  int splits = 1;
+  if (ws && g.batch == 1 && tiles * 4 < 1024 && g.k >= 2048) {
+    splits = (int)std::min<int64_t>(ceil_div(1024, tiles), g.k / 512);
+    const int64_t cap = ws_elems / (g.m * g.n);
+    splits = (int)std::min<int64_t>(splits, cap);
+    if (splits < 2) splits = 1;
+  }
+  ka.splits = splits;
+  ka.ws = splits > 1 ? ws : nullptr;
+  dim3 grid((unsigned)tiles, (unsigned)g.batch, (unsigned)splits);
+  if (big) launch<128, 128, false>(ka, g.ta, g.tb, grid, stream);
+  else launch<64, 64, false>(ka, g.ta, g.tb, grid, stream);
+  MM_HIP_TRY(hipGetLastError());
+  if (splits > 1) {
+    const int64_t total = g.m * g.n;
+    hipLaunchKernelGGL(splitk_reduce, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, stream,
+                       g.m, g.n, splits, ws, g.beta, g.C, g.ldc, (int)g.lower);
+    MM_HIP_TRY(hipGetLastError());
+  }
+}
+
+void gemm_grouped(const GemmGroup* d_groups, int64_t n_groups, int64_t max_m,
+                  int64_t max_n, bool ta, bool tb, double alpha, double beta,
+                  hipStream_t stream) {
+  if (n_groups <= 0 || max_m <= 0 || max_n <= 0) return;
+  KArgs ka{};
+  ka.alpha = alpha; ka.beta = beta; ka.splits = 1; ka.b_band = -1;
+  ka.groups = d_groups;
+  const bool big = max_m * max_n >= (int64_t)64 * 128 * 128;
+  const int bm = big ? 128 : 64;
+  ka.tiles_m = (int)ceil_div(max_m, bm);
+  ka.tiles_n = (int)ceil_div(max_n, bm);
+  dim3 grid((unsigned)((int64_t)ka.tiles_m * ka.tiles_n), (unsigned)n_groups, 1);
+  if (big) launch<128, 128, true>(ka, ta, tb, grid, stream);
+  else launch<64, 64, true>(ka, ta, tb, grid, stream);
+  MM_HIP_TRY(hipGetLastError());
+}
+
+}  // namespace mm

@@ -1,0 +1,103 @@
+// Launchers of the libmm kernels (internal; the public interface is mm.h).
+#pragma once
+#include "common.h"
+
+namespace mm {
+
+// ---- dense factorisations (potrf.hip) ------------------------------------
+int64_t potrf_ws_elems(int64_t n);
+// A = G G^T in place (lower; the strict upper triangle is zeroed).  The first
+// failing pivot (global index) is atomically min-ed into *d_status, which the
+// caller initialises to INT64_MAX.
+void potrf_lower(double* A, int64_t lda, int64_t n, double* ws, int64_t ws_elems,
+                 int64_t* d_status, hipStream_t s);
+int64_t trtri_ws_elems(int64_t n);
+// A <- A^{-1} for lower-triangular A (strict upper triangle zero on entry).
+void trtri_lower(double* A, int64_t lda, int64_t n, double* ws, int64_t ws_elems,
+                 hipStream_t s);
+// Inverses of the nb x nb diagonal blocks of lower-triangular A, packed as
+// ceil(n/nb) blocks of nb*nb (column-major, zero padded).  nb <= 128.
+void diag_block_inverses(const double* A, int64_t lda, int64_t n, int nb,
+                         double* Dinv, hipStream_t s);
+void copy_matrix(const double* S, int64_t lds, double* D, int64_t ldd,
+                 int64_t m, int64_t n, hipStream_t s);
+
+// ---- setup (setup.hip) -----------------------------------------------------
+struct Csr {
+  int64_t rows = 0, cols = 0, nnz = 0;
+  const int64_t* rowptr = nullptr;
+  const int32_t* col = nullptr;
+  const double* val = nullptr;
+};
+// L_ij = h / sqrt(|x_i - x_j|^2 + h^2) for i >= j (lower triangle + diagonal),
+// or the full matrix if `full`.
+void assemble_L(const double* xyz, double h, int64_t n, double* L, int64_t ld,
+                bool full, hipStream_t s);
+// Z(i,j) += alpha R(i,j) for the lower-triangle entries of R.
+void add_csr_lower(double* Z, int64_t ld, double alpha, const Csr& R, hipStream_t s);
+// max_j (j - min{c : R(c,j) != 0}) for symmetric R (written to *d_out).
+void csr_lower_band(const Csr& R, int64_t* d_out, hipStream_t s);
+// W = A R for dense A (n x n, column-major) and symmetric sparse R.
+void dense_times_csr(const double* A, int64_t lda, const Csr& R, double* W,
+                     int64_t ldw, hipStream_t s);
+// A(i,j) = A(j,i) for i < j (copy the lower triangle to the upper).
+void symmetrize_from_lower(double* A, int64_t lda, int64_t n, hipStream_t s);
+void fill(double* p, int64_t count, double v, hipStream_t s);
+void fill_i64(int64_t* p, int64_t count, int64_t v, hipStream_t s);
+
+// ---- Cholesky theta-method (step_chol.hip) --------------------------------
+constexpr int TRSV_NB = 128;
+int64_t trsv_partial_elems(int64_t n);
+int64_t trsv_sync_words(int64_t n);
+
+struct Forcing {
+  // f^k = F u^k with F (n0 x nf, column-major) and u^k from the waveforms:
+  //   u_a         = -dt (iD_a^k + theta (iD_a^{k+1} - iD_a^k))   a < m
+  //   u_{m+a}     = -(iD_a^{k+1} - iD_a^k)                       a < m
+  //   u_{2m+c}    = -(i0_c^{k+1} - i0_c^k)                       c < n_src
+  const double* F = nullptr;
+  int nf = 0, m = 0, n_src = 0;
+  const double* i_src = nullptr;  // (T+1) x n_src, row-major by step
+  const double* i_D = nullptr;    // (T+1) x m
+};
+
+struct CholStep {
+  int64_t n0 = 0;
+  const double* Cf = nullptr;  // factor of Z, lower, column-major
+  int64_t ld = 0;
+  const double* Dinv = nullptr;
+  Csr Ri;                      // reduced resistance
+  Forcing f;
+  double theta = 0.5, dt = 1.0;
+  double* I = nullptr;         // state Ii (n0)
+  double* b = nullptr;         // work vector (n0)
+  double* partial = nullptr;
+  unsigned* sync = nullptr;
+  const double* Pt = nullptr;  // probe weights (n0 x n_probe, column-major)
+  int n_probe = 0;
+  double* probe_partial = nullptr;  // n_steps x NB x n_probe
+};
+void chol_steps(const CholStep& c, int64_t k0, int64_t n_steps, hipStream_t s);
+// signal(k, p) = (sum_J probe_partial(k, J, p) + sum_a Pd(p, a) diD_a^k) / dt
+void probe_finish(const double* probe_partial, int64_t n_steps, int64_t nparts,
+                  int n_probe, const double* Pd, int m, const double* i_D,
+                  int64_t k0, double dt, double* signal, hipStream_t s);
+// Host-visible error word of the TRSV dataflow waits (0 = fine).
+int64_t trsv_error_offset(int64_t n);
+
+// ---- modal theta-method (step_modal.hip) ----------------------------------
+struct ModalStep {
+  int64_t n0 = 0;
+  const double* lam = nullptr;   // n0
+  const double* W = nullptr;     // modal forcing weights (n0 x nf)
+  Forcing f;                     // F unused; nf, m, n_src and waveforms used
+  const double* Pt = nullptr;    // modal probe weights (n0 x n_probe)
+  int n_probe = 0;
+  double theta = 0.5, dt = 1.0;
+  double* y = nullptr;           // modal amplitudes (state)
+  double* probe_partial = nullptr;  // n_steps x n_groups x n_probe
+};
+int modal_groups(int64_t n0);
+void modal_steps(const ModalStep& m, int64_t k0, int64_t n_steps, hipStream_t s);
+
+}  // namespace mm

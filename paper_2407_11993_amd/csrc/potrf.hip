@@ -1,0 +1,281 @@
+// Dense FP64 Cholesky (lower) and triangular inverse, column-major.
+//
+// potrf: blocked right-looking factorisation A = G G^T with NB = 128 column
+// panels.  The 128 x 128 diagonal block is factored inside LDS by one
+// workgroup, which also writes the inverse of its factor; the panel below is
+// then G21 = A21 G11^{-T} (a GEMM against that inverse) and the trailing
+// matrix takes the symmetric rank-128 update A22 -= G21 G21^T on the matrix
+// cores (lower triangle only).  Used for Li = G G^T (modal method) and for
+// Z = Li + theta dt Ri = C C^T (Cholesky method).
+//
+// trtri: G^{-1} by recursive halving,
+//   inv([A 0; B C]) = [A^{-1} 0; -C^{-1} B A^{-1}  C^{-1}],
+// with the leaves (<= 128) inverted in LDS and the two products done by the
+// GEMM with the triangular structure of the operands exploited per tile.
+#include "common.h"
+#include "kernels.h"
+
+namespace mm {
+namespace {
+
+constexpr int DB = 128;        // diagonal block size
+constexpr int LDL = DB + 1;    // LDS leading dimension
+
+// Factor (if `factor`) and invert the jb x jb lower triangle held in LDS.
+// L[i + j*LDL].  On a non-positive pivot, *bad receives its local index.
+__device__ void lds_chol_inv(double* L, int jb, bool factor, bool want_inv,
+                             double* Linv, int* bad) {
+  const int t = threadIdx.x, nt = blockDim.x;
+  __shared__ double tmp[DB];
+  __shared__ double diag;
+  if (factor) {
+    for (int k = 0; k < jb; ++k) {
+      if (t == 0) {
+        double d = L[k + k * LDL];
+        if (!(d > 0.0)) {
+          if (*bad < 0) *bad = k;
+          d = 1.0;  // keep going with a harmless pivot; the caller reports
+        }
+        d = sqrt(d);
+        L[k + k * LDL] = d;
+        diag = d;
+      }
+      __syncthreads();
+      const double inv = 1.0 / diag;
+      for (int i = k + 1 + t; i < jb; i += nt) L[i + k * LDL] *= inv;
+      __syncthreads();
+      // trailing update of the lower triangle, columns k+1..jb-1
+      const int m = jb - k - 1;
+      for (int e = t; e < m * m; e += nt) {
+        const int i = k + 1 + e % m, j = k + 1 + e / m;
+        if (i >= j) L[i + j * LDL] -= L[i + k * LDL] * L[j + k * LDL];
+      }
+      __syncthreads();
+    }
+  }
+  if (!want_inv) return;
+  // Inverse of the lower triangle, column by column from the right:
+  // X(j,j) = 1/L(j,j);  X(j+1:, j) = -X(j+1:, j+1:) L(j+1:, j) / L(j,j),
+  // where X(j+1:, j+1:) is already inverted in place (LAPACK trti2 order).
+  for (int j = jb - 1; j >= 0; --j) {
+    const double ljj = L[j + j * LDL];
+    // tmp(i) = sum_{k=j+1..i} X(i,k) L(k,j)
+    for (int i = j + 1 + t; i < jb; i += nt) {
+      double s = 0.0;
+      for (int k = j + 1; k <= i; ++k) s += L[i + k * LDL] * L[k + j * LDL];
+      tmp[i] = s;
+    }
+    __syncthreads();
+    const double xjj = 1.0 / ljj;
+    for (int i = j + 1 + t; i < jb; i += nt) L[i + j * LDL] = -tmp[i] * xjj;
+    __syncthreads();
+    if (t == 0) L[j + j * LDL] = xjj;
+    __syncthreads();
+  }
+  if (Linv) {
+    for (int e = t; e < jb * jb; e += nt) {
+      const int i = e % jb, j = e / jb;
+      Linv[i + (int64_t)j * jb] = (i >= j) ? L[i + j * LDL] : 0.0;
+    }
+  }
+}
+
+// Factor the diagonal block A[j0.., j0..] in place and write its inverse to
+// Linv (jb x jb, ld jb).  status[0] keeps the first failing global pivot.
+__global__ void __launch_bounds__(256) potrf_diag(double* A, int64_t lda,
+                                                  int64_t j0, int jb,
+                                                  double* Linv, int64_t* status) {
+  __shared__ double L[DB * LDL];
+  __shared__ int bad;
+  const int t = threadIdx.x;
+  if (t == 0) bad = -1;
+  double* Ab = A + j0 + j0 * lda;
+  for (int e = t; e < jb * jb; e += blockDim.x) {
+    const int i = e % jb, j = e / jb;
+    L[i + j * LDL] = Ab[i + (int64_t)j * lda];
+  }
+  __syncthreads();
+  // factor in LDS (the inverse overwrites L, so factor into L, copy it out,
+  // then invert)
+  lds_chol_inv(L, jb, true, false, nullptr, &bad);
+  __syncthreads();
+  for (int e = t; e < jb * jb; e += blockDim.x) {
+    const int i = e % jb, j = e / jb;
+    Ab[i + (int64_t)j * lda] = (i >= j) ? L[i + j * LDL] : 0.0;
+  }
+  __syncthreads();
+  lds_chol_inv(L, jb, false, true, Linv, &bad);
+  if (t == 0 && bad >= 0) {
+    const unsigned long long g = (unsigned long long)(j0 + bad);
+    atomicMin((unsigned long long*)status, g);
+  }
+}
+
+// Invert the lower-triangular diagonal blocks of size <= DB in place.
+// Block b covers [b*bs, min((b+1)*bs, n)).
+__global__ void __launch_bounds__(256) trtri_diag(double* A, int64_t lda,
+                                                  int64_t n, int bs) {
+  __shared__ double L[DB * LDL];
+  __shared__ int bad;
+  const int t = threadIdx.x;
+  const int64_t j0 = (int64_t)blockIdx.x * bs;
+  const int jb = (int)min((int64_t)bs, n - j0);
+  if (t == 0) bad = -1;
+  double* Ab = A + j0 + j0 * lda;
+  for (int e = t; e < jb * jb; e += blockDim.x) {
+    const int i = e % jb, j = e / jb;
+    L[i + j * LDL] = (i >= j) ? Ab[i + (int64_t)j * lda] : 0.0;
+  }
+  __syncthreads();
+  lds_chol_inv(L, jb, false, true, nullptr, &bad);
+  __syncthreads();
+  for (int e = t; e < jb * jb; e += blockDim.x) {
+    const int i = e % jb, j = e / jb;
+    Ab[i + (int64_t)j * lda] = (i >= j) ? L[i + j * LDL] : 0.0;
+  }
+}
+
+// Inverse of diagonal block b (size <= nb) of lower-triangular A, written
+// zero padded as Dinv[b] (nb x nb) and transposed as Dinv[NB + b].
+__global__ void __launch_bounds__(256) diag_inv_k(const double* A, int64_t lda, int64_t n,
+                                                  int nb, double* Dinv) {
+  __shared__ double L[DB * LDL];
+  __shared__ int bad;
+  const int t = threadIdx.x;
+  const int64_t NB = ceil_div(n, nb);
+  const int64_t j0 = (int64_t)blockIdx.x * nb;
+  const int jb = (int)min((int64_t)nb, n - j0);
+  if (t == 0) bad = -1;
+  const double* Ab = A + j0 + j0 * lda;
+  for (int e = t; e < jb * jb; e += blockDim.x) {
+    const int i = e % jb, j = e / jb;
+    L[i + j * LDL] = (i >= j) ? Ab[i + (int64_t)j * lda] : 0.0;
+  }
+  __syncthreads();
+  lds_chol_inv(L, jb, false, true, nullptr, &bad);
+  __syncthreads();
+  double* D = Dinv + (int64_t)blockIdx.x * nb * nb;
+  double* DT = Dinv + (NB + (int64_t)blockIdx.x) * nb * nb;
+  for (int e = t; e < nb * nb; e += blockDim.x) {
+    const int i = e % nb, j = e / nb;
+    const double v = (i < jb && j < jb && i >= j) ? L[i + j * LDL] : 0.0;
+    D[i + (int64_t)j * nb] = v;
+    DT[j + (int64_t)i * nb] = v;
+  }
+}
+
+__global__ void zero_upper(double* A, int64_t lda, int64_t n) {
+  const int64_t j = blockIdx.x;
+  for (int64_t i = threadIdx.x; i < j; i += blockDim.x) A[i + j * lda] = 0.0;
+}
+
+__global__ void copy_block(const double* S, int64_t lds, double* D, int64_t ldd,
+                           int64_t m, int64_t n) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m * n) return;
+  const int64_t i = idx % m, j = idx / m;
+  D[i + j * ldd] = S[i + j * lds];
+}
+
+void trtri_rec(double* A, int64_t lda, int64_t n, double* ws, hipStream_t s) {
+  // leaves are inverted beforehand by trtri_diag with block size DB; here only
+  // the off-diagonal blocks of the recursion are formed.
+  if (n <= DB) return;
+  // split on a multiple of DB so that leaves line up with trtri_diag blocks
+  int64_t n1 = ceil_div(ceil_div(n, 2), DB) * DB;
+  if (n1 >= n) n1 = ((n - 1) / DB) * DB;
+  const int64_t n2 = n - n1;
+  trtri_rec(A, lda, n1, ws, s);
+  trtri_rec(A + n1 + n1 * lda, lda, n2, ws, s);
+  // T = B A11^{-1}   (n2 x n1); A11^{-1} lower: op(B)(k,j) = 0 for k < j
+  Gemm g1;
+  g1.m = n2; g1.n = n1; g1.k = n1;
+  g1.A = A + n1; g1.lda = lda;
+  g1.B = A; g1.ldb = lda;
+  g1.C = ws; g1.ldc = n2;
+  g1.b_lower = true;
+  gemm(g1, s);
+  // B <- -C^{-1} T  (C^{-1} = A22^{-1} lower: op(A)(i,k) = 0 for k > i)
+  Gemm g2;
+  g2.m = n2; g2.n = n1; g2.k = n2;
+  g2.alpha = -1.0;
+  g2.A = A + n1 + n1 * lda; g2.lda = lda;
+  g2.a_lower = true;
+  g2.B = ws; g2.ldb = n2;
+  g2.C = A + n1; g2.ldc = lda;
+  gemm(g2, s);
+}
+
+}  // namespace
+
+void potrf_lower(double* A, int64_t lda, int64_t n, double* ws,
+                 int64_t ws_elems, int64_t* d_status, hipStream_t s) {
+  MM_REQUIRE(ws_elems >= potrf_ws_elems(n), kInvalid, "potrf: workspace too small");
+  double* Linv = ws;                 // DB x DB
+  double* T = ws + (int64_t)DB * DB; // (n) x DB
+  for (int64_t j0 = 0; j0 < n; j0 += DB) {
+    const int jb = (int)std::min<int64_t>(DB, n - j0);
+    hipLaunchKernelGGL(potrf_diag, dim3(1), dim3(256), 0, s, A, lda, j0, jb, Linv, d_status);
+    MM_HIP_TRY(hipGetLastError());
+    const int64_t m = n - j0 - jb;
+    if (m <= 0) break;
+    // T = A21 G11^{-T}: op(B) = Linv^T, op(B)(k,j) = Linv(j,k) = 0 for k > j
+    Gemm g;
+    g.m = m; g.n = jb; g.k = jb;
+    g.A = A + (j0 + jb) + j0 * lda; g.lda = lda;
+    g.B = Linv; g.ldb = jb; g.tb = true; g.b_band = 0;
+    g.C = T; g.ldc = m;
+    gemm(g, s);
+    const int64_t tot = m * jb;
+    hipLaunchKernelGGL(copy_block, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, s,
+                       T, m, A + (j0 + jb) + j0 * lda, lda, m, (int64_t)jb);
+    MM_HIP_TRY(hipGetLastError());
+    // A22 -= T T^T (lower)
+    Gemm u;
+    u.m = m; u.n = m; u.k = jb;
+    u.alpha = -1.0; u.beta = 1.0;
+    u.A = T; u.lda = m;
+    u.B = T; u.ldb = m; u.tb = true;
+    u.C = A + (j0 + jb) + (j0 + jb) * lda; u.ldc = lda;
+    u.lower = true;
+    gemm(u, s);
+  }
+  hipLaunchKernelGGL(zero_upper, dim3((unsigned)n), dim3(256), 0, s, A, lda, n);
+  MM_HIP_TRY(hipGetLastError());
+}
+
+int64_t potrf_ws_elems(int64_t n) { return (int64_t)DB * DB + n * DB; }
+
+void trtri_lower(double* A, int64_t lda, int64_t n, double* ws, int64_t ws_elems,
+                 hipStream_t s) {
+  MM_REQUIRE(ws_elems >= trtri_ws_elems(n), kInvalid, "trtri: workspace too small");
+  const int64_t nblk = ceil_div(n, DB);
+  hipLaunchKernelGGL(trtri_diag, dim3((unsigned)nblk), dim3(256), 0, s, A, lda, n, DB);
+  MM_HIP_TRY(hipGetLastError());
+  trtri_rec(A, lda, n, ws, s);
+}
+
+int64_t trtri_ws_elems(int64_t n) {
+  const int64_t h = ceil_div(n, 2) + DB;
+  return h * h;
+}
+
+void diag_block_inverses(const double* A, int64_t lda, int64_t n, int nb, double* Dinv,
+                         hipStream_t s) {
+  MM_REQUIRE(nb >= 1 && nb <= DB, kInvalid, "diag_block_inverses: block too large");
+  if (n <= 0) return;
+  hipLaunchKernelGGL(diag_inv_k, dim3((unsigned)ceil_div(n, nb)), dim3(256), 0, s, A, lda, n, nb,
+                     Dinv);
+  MM_HIP_TRY(hipGetLastError());
+}
+
+void copy_matrix(const double* S, int64_t lds, double* D, int64_t ldd,
+                 int64_t m, int64_t n, hipStream_t s) {
+  if (m <= 0 || n <= 0) return;
+  const int64_t tot = m * n;
+  hipLaunchKernelGGL(copy_block, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, s,
+                     S, lds, D, ldd, m, n);
+  MM_HIP_TRY(hipGetLastError());
+}
+
+}  // namespace mm

@@ -1,0 +1,145 @@
+// Setup kernels: assembly of the inductance stand-in (HBM-write bound),
+// sparse R operations of the standard form, small fills.
+#include "kernels.h"
+
+namespace mm {
+namespace {
+
+// One thread per element of a column segment; consecutive threads walk
+// consecutive rows, so the column-major stores are contiguous.
+__global__ void assemble_L_k(const double* __restrict__ xyz, double h, int64_t n,
+                             double* __restrict__ L, int64_t ld, int full) {
+  const int64_t j = blockIdx.x;
+  const double xj = xyz[3 * j], yj = xyz[3 * j + 1], zj = xyz[3 * j + 2];
+  const double h2 = h * h;
+  const int64_t i_begin = full ? 0 : j;
+  for (int64_t i = i_begin + threadIdx.x; i < n; i += blockDim.x) {
+    const double dx = xyz[3 * i] - xj, dy = xyz[3 * i + 1] - yj, dz = xyz[3 * i + 2] - zj;
+    L[i + j * ld] = h / sqrt(dx * dx + dy * dy + dz * dz + h2);
+  }
+}
+
+__global__ void add_csr_lower_k(double* Z, int64_t ld, double alpha, int64_t rows,
+                                const int64_t* rowptr, const int32_t* col,
+                                const double* val) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows) return;
+  for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+    const int64_t j = col[p];
+    if (j <= i) Z[i + j * ld] += alpha * val[p];
+  }
+}
+
+__global__ void csr_band_k(int64_t rows, const int64_t* rowptr, const int32_t* col,
+                           unsigned long long* out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= rows) return;
+  int64_t mn = j;
+  for (int64_t p = rowptr[j]; p < rowptr[j + 1]; ++p) mn = min(mn, (int64_t)col[p]);
+  atomicMax(out, (unsigned long long)(j - mn));
+}
+
+// W(:, j) = sum_{p in row j of R} R(j, c_p) A(:, c_p)   (R symmetric)
+__global__ void dense_times_csr_k(const double* __restrict__ A, int64_t lda,
+                                  const int64_t* __restrict__ rowptr,
+                                  const int32_t* __restrict__ col,
+                                  const double* __restrict__ val, int64_t n,
+                                  double* __restrict__ W, int64_t ldw) {
+  const int64_t j = blockIdx.x;
+  const int64_t p0 = rowptr[j], p1 = rowptr[j + 1];
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    double s = 0.0;
+    for (int64_t p = p0; p < p1; ++p) s += val[p] * A[i + (int64_t)col[p] * lda];
+    W[i + j * ldw] = s;
+  }
+}
+
+// Tiled transpose-copy of the lower triangle into the upper one.
+__global__ void symmetrize_k(double* A, int64_t lda, int64_t n) {
+  __shared__ double tile[32][33];
+  const int64_t bi = blockIdx.x, bj = blockIdx.y;  // tile (bi, bj), bi > bj or ==
+  if (bi < bj) return;
+  const int tx = threadIdx.x, ty = threadIdx.y;  // 32 x 8
+  // read lower tile (rows bi*32.., cols bj*32..)
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t i = bi * 32 + tx, j = bj * 32 + r;
+    if (i < n && j < n) tile[r][tx] = A[i + j * lda];
+  }
+  __syncthreads();
+  // write to upper tile (rows bj*32.., cols bi*32..): A(j, i) = A(i, j)
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t j = bj * 32 + tx, i = bi * 32 + r;  // element (row j, col i)
+    if (i < n && j < n && j < i) A[j + i * lda] = tile[tx][r];
+  }
+}
+
+__global__ void fill_k(double* p, int64_t count, double v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void fill_i64_k(int64_t* p, int64_t count, int64_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+unsigned grid1(int64_t count, int per = 256) {
+  int64_t g = ceil_div(count, per);
+  if (g > 65535 * 16) g = 65535 * 16;
+  return (unsigned)std::max<int64_t>(g, 1);
+}
+
+}  // namespace
+
+void assemble_L(const double* xyz, double h, int64_t n, double* L, int64_t ld,
+                bool full, hipStream_t s) {
+  if (n <= 0) return;
+  MM_REQUIRE(n < (int64_t)1 << 31, kInvalid, "assemble_L: n too large");
+  hipLaunchKernelGGL(assemble_L_k, dim3((unsigned)n), dim3(256), 0, s, xyz, h, n, L, ld, (int)full);
+  MM_HIP_TRY(hipGetLastError());
+}
+
+void add_csr_lower(double* Z, int64_t ld, double alpha, const Csr& R, hipStream_t s) {
+  if (R.rows <= 0) return;
+  hipLaunchKernelGGL(add_csr_lower_k, dim3(grid1(R.rows)), dim3(256), 0, s, Z, ld, alpha,
+                     R.rows, R.rowptr, R.col, R.val);
+  MM_HIP_TRY(hipGetLastError());
+}
+
+void csr_lower_band(const Csr& R, int64_t* d_out, hipStream_t s) {
+  fill_i64(d_out, 1, 0, s);
+  hipLaunchKernelGGL(csr_band_k, dim3(grid1(R.rows)), dim3(256), 0, s, R.rows, R.rowptr,
+                     R.col, (unsigned long long*)d_out);
+  MM_HIP_TRY(hipGetLastError());
+}
+
+void dense_times_csr(const double* A, int64_t lda, const Csr& R, double* W,
+                     int64_t ldw, hipStream_t s) {
+  const int64_t n = R.rows;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(dense_times_csr_k, dim3((unsigned)n), dim3(256), 0, s, A, lda, R.rowptr, R.col,
+                     R.val, n, W, ldw);
+  MM_HIP_TRY(hipGetLastError());
+}
+
+void symmetrize_from_lower(double* A, int64_t lda, int64_t n, hipStream_t s) {
+  if (n <= 1) return;
+  const int64_t nt = ceil_div(n, 32);
+  hipLaunchKernelGGL(symmetrize_k, dim3((unsigned)nt, (unsigned)nt), dim3(32, 8), 0, s, A, lda, n);
+  MM_HIP_TRY(hipGetLastError());
+}
+
+void fill(double* p, int64_t count, double v, hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(fill_k, dim3(grid1(count)), dim3(256), 0, s, p, count, v);
+  MM_HIP_TRY(hipGetLastError());
+}
+
+void fill_i64(int64_t* p, int64_t count, int64_t v, hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(fill_i64_k, dim3(grid1(count)), dim3(256), 0, s, p, count, v);
+  MM_HIP_TRY(hipGetLastError());
+}
+
+}  // namespace mm

@@ -1,0 +1,220 @@
+"""Thin Python front end of libmm: device buffers (torch) in, device buffers out.
+
+Every step of the method runs in libmm's HIP kernels; this module only moves
+the problem data to the GPU, calls the C ABI and wraps the results.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+
+
+def _dev(a, dtype=torch.float64, device="cuda"):
+    if isinstance(a, torch.Tensor):
+        return a.to(device=device, dtype=dtype).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=device)
+
+
+def _colmajor(a: np.ndarray, rows: int) -> np.ndarray:
+    """(rows x c) numpy array -> column-major flat buffer."""
+    a = np.asarray(a, dtype=np.float64).reshape(rows, -1)
+    return np.ascontiguousarray(a.T).ravel()
+
+
+class Solver:
+    """One problem (Sec. 3.1) on one GPU: the modal and the Cholesky method.
+
+    ``workload`` is a :class:`paper_2407_11993_amd.inputs.Workload` (or any
+    object with the same fields: xyz, h, R (CSR), M, P, E).
+    """
+
+    def __init__(self, workload, device: str = "cuda"):
+        self.lib = _lib.lib()
+        w = workload
+        self.device = device
+        self.n = int(w.xyz.shape[0])
+        self.m = 0 if w.E is None else int(w.E.shape[0])
+        self.n_src = int(w.M.shape[1])
+        self.n_probe = int(w.P.shape[0])
+        # device copies of the problem statement (kept alive by self)
+        self._xyz = _dev(w.xyz.reshape(-1))
+        self._rp = _dev(w.R.rowptr, torch.int64)
+        self._rc = _dev(w.R.col, torch.int32)
+        self._rv = _dev(w.R.val)
+        self._M = _dev(_colmajor(w.M, self.n)) if self.n_src else None
+        self._P = _dev(_colmajor(w.P.T, self.n))
+        if self.m:
+            self._ep = _dev(w.E.rowptr, torch.int64)
+            self._ec = _dev(w.E.col, torch.int32)
+            self._ev = _dev(w.E.val)
+        pb = _lib.Problem()
+        pb.n = self.n
+        pb.xyz = _lib.ptr(self._xyz)
+        pb.h = float(w.h)
+        pb.r_nnz = int(w.R.val.size)
+        pb.r_rowptr, pb.r_col, pb.r_val = (_lib.ptr(self._rp), _lib.ptr(self._rc),
+                                           _lib.ptr(self._rv))
+        pb.n_e = self.m + 1 if self.m else 0
+        if self.m:
+            pb.e_nnz = int(w.E.val.size)
+            pb.e_rowptr, pb.e_col, pb.e_val = (_lib.ptr(self._ep), _lib.ptr(self._ec),
+                                               _lib.ptr(self._ev))
+        pb.n_src = self.n_src
+        pb.M0 = _lib.ptr(self._M)
+        pb.n_probe = self.n_probe
+        pb.P = _lib.ptr(self._P)
+        ctx = ctypes.c_void_p()
+        _lib.check(self.lib.mm_setup(ctypes.byref(pb), _lib.stream_handle(), ctypes.byref(ctx)))
+        self.ctx = ctx
+        info = (ctypes.c_int64 * 3)()
+        _lib.check(self.lib.mm_info(self.ctx, info), self.ctx)
+        self.n0 = int(info[1])
+
+    # -- lifetime -----------------------------------------------------------
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.mm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- the method -----------------------------------------------------------
+    def decompose(self):
+        _lib.check(self.lib.mm_decompose(self.ctx), self.ctx)
+
+    def _waves(self, n_steps, i_src, i_D):
+        s = None if self.n_src == 0 else _dev(np.asarray(i_src).reshape(n_steps + 1, self.n_src)
+                                              if not isinstance(i_src, torch.Tensor) else i_src)
+        d = None if self.m == 0 else _dev(np.asarray(i_D).reshape(n_steps + 1, self.m)
+                                          if not isinstance(i_D, torch.Tensor) else i_D)
+        return s, d
+
+    def step_modal(self, theta, dt, n_steps, i_src, i_D=None, out=None):
+        s, d = self._waves(n_steps, i_src, i_D)
+        sig = out if out is not None else torch.empty(
+            (n_steps, self.n_probe), dtype=torch.float64, device=self.device)
+        _lib.check(self.lib.mm_step_modal(self.ctx, float(theta), float(dt), int(n_steps),
+                                          _lib.ptr(s), _lib.ptr(d), _lib.ptr(sig)), self.ctx)
+        self._keep = (s, d)
+        return sig
+
+    def step_cholesky(self, theta, dt, n_steps, i_src, i_D=None, out=None):
+        s, d = self._waves(n_steps, i_src, i_D)
+        sig = out if out is not None else torch.empty(
+            (n_steps, self.n_probe), dtype=torch.float64, device=self.device)
+        _lib.check(self.lib.mm_step_cholesky(self.ctx, float(theta), float(dt), int(n_steps),
+                                             _lib.ptr(s), _lib.ptr(d), _lib.ptr(sig)), self.ctx)
+        self._keep = (s, d)
+        return sig
+
+    def current(self, which=_lib.MM_MODAL, rows=None):
+        if rows is None:
+            out = torch.empty(self.n, dtype=torch.float64, device=self.device)
+            _lib.check(self.lib.mm_probe(self.ctx, which, 0, None, _lib.ptr(out)), self.ctx)
+            return out
+        r = _dev(_colmajor(rows, self.n))
+        k = r.numel() // self.n
+        out = torch.empty(k, dtype=torch.float64, device=self.device)
+        _lib.check(self.lib.mm_probe(self.ctx, which, k, _lib.ptr(r), _lib.ptr(out)), self.ctx)
+        return out
+
+    def reset(self):
+        _lib.check(self.lib.mm_reset_state(self.ctx), self.ctx)
+
+    def eigenvalues(self):
+        out = torch.empty(self.n0, dtype=torch.float64, device=self.device)
+        _lib.check(self.lib.mm_eigenvalues(self.ctx, _lib.ptr(out)), self.ctx)
+        return out
+
+
+class _Kernels:
+    """The dense building blocks (mmk_* entry points) on torch tensors.
+
+    Matrices are passed as torch tensors holding the column-major layout, i.e.
+    the transpose view of a row-major (C-order) tensor is used: a tensor ``A``
+    of shape (cols, rows) in C order is the column-major (rows x cols) matrix.
+    The helpers below take and return ordinary row-major torch matrices and
+    do the transposition.
+    """
+
+    @staticmethod
+    def _cm(A: torch.Tensor) -> torch.Tensor:
+        return A.t().contiguous()  # column-major storage of A
+
+    def gemm(self, A, B, trans_a=False, trans_b=False, alpha=1.0, beta=0.0, C=None):
+        A = _dev(A)
+        B = _dev(B)
+        opA = A.t() if trans_a else A
+        opB = B.t() if trans_b else B
+        m, k = opA.shape
+        n = opB.shape[1]
+        Ac, Bc = self._cm(A), self._cm(B)
+        Cc = self._cm(_dev(C)) if C is not None else torch.zeros(n, m, dtype=torch.float64,
+                                                                 device=A.device)
+        _lib.check(_lib.lib().mmk_dgemm(int(trans_a), int(trans_b), m, n, k, float(alpha),
+                                        _lib.ptr(Ac), A.shape[0], _lib.ptr(Bc), B.shape[0],
+                                        float(beta), _lib.ptr(Cc), max(1, m),
+                                        _lib.stream_handle()))
+        return Cc.t()
+
+    def potrf(self, A):
+        Ac = self._cm(_dev(A))
+        n = Ac.shape[0]
+        info = ctypes.c_int64(0)
+        _lib.check(_lib.lib().mmk_dpotrf(n, _lib.ptr(Ac), max(1, n), ctypes.byref(info),
+                                         _lib.stream_handle()))
+        return Ac.t(), int(info.value)
+
+    def trtri(self, G):
+        Gc = self._cm(_dev(G))
+        n = Gc.shape[0]
+        _lib.check(_lib.lib().mmk_dtrtri(n, _lib.ptr(Gc), max(1, n), _lib.stream_handle()))
+        return Gc.t()
+
+    def sy2sb(self, A, nb):
+        Ac = self._cm(_dev(A))
+        n = Ac.shape[0]
+        ldab = 2 * nb + 1
+        AB = torch.zeros(n, ldab, dtype=torch.float64, device=Ac.device)
+        _lib.check(_lib.lib().mmk_dsy2sb(n, _lib.ptr(Ac), n, nb, _lib.ptr(AB), ldab,
+                                         _lib.stream_handle()))
+        return AB  # AB[j, d] = B(j + d, j)
+
+    def sb2st(self, AB, nb):
+        AB = _dev(AB).clone()
+        n, ldab = AB.shape
+        d = torch.empty(n, dtype=torch.float64, device=AB.device)
+        e = torch.empty(max(1, n - 1), dtype=torch.float64, device=AB.device)
+        _lib.check(_lib.lib().mmk_dsb2st(n, nb, _lib.ptr(AB), ldab, _lib.ptr(d), _lib.ptr(e),
+                                         _lib.stream_handle()))
+        return d, e[:n - 1]
+
+    def stedc(self, d, e):
+        d = _dev(d)
+        n = d.numel()
+        e = _dev(e) if n > 1 else torch.zeros(1, dtype=torch.float64, device=d.device)
+        w = torch.empty(n, dtype=torch.float64, device=d.device)
+        Z = torch.empty(n, n, dtype=torch.float64, device=d.device)
+        _lib.check(_lib.lib().mmk_dstedc(n, _lib.ptr(d), _lib.ptr(e), _lib.ptr(w),
+                                         _lib.ptr(Z), _lib.stream_handle()))
+        return w, Z.t()
+
+    def syevd(self, A, nb=64):
+        Ac = self._cm(_dev(A))
+        n = Ac.shape[0]
+        w = torch.empty(n, dtype=torch.float64, device=Ac.device)
+        Z = torch.empty(n, n, dtype=torch.float64, device=Ac.device)
+        _lib.check(_lib.lib().mmk_dsyevd(n, _lib.ptr(Ac), n, int(nb), _lib.ptr(w), _lib.ptr(Z),
+                                         _lib.stream_handle()))
+        return w, Z.t()
+
+
+kernels = _Kernels()

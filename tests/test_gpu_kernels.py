@@ -1,0 +1,173 @@
+"""Stage-by-stage parity of the HIP building blocks (FP64) against plain
+numpy/scipy definitions: GEMM, Cholesky, triangular inverse, band reduction,
+bulge chase, divide and conquer, and the full symmetric eigensolver.
+
+Sizes span several tiles and a ragged tail (128-wide tiles and panels, 64
+band, 32-row D&C leaves)."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def K():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2407_11993_amd import kernels
+    return kernels
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _sym(n, seed, spread=1.0):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((n, n)) * spread
+    return (A + A.T) / 2
+
+
+def _spd(n, seed):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((n, n))
+    return A @ A.T / n + np.eye(n)
+
+
+@pytest.mark.parametrize("m,n,k", [(1, 1, 1), (17, 33, 5), (130, 70, 200),
+                                   (257, 129, 64), (64, 64, 4096), (2100, 2100, 300)])
+@pytest.mark.parametrize("ta,tb", [(False, False), (True, False), (False, True), (True, True)])
+def test_gemm(K, m, n, k, ta, tb):
+    rng = np.random.default_rng(m * 7 + n * 3 + k)
+    A = rng.standard_normal((k, m) if ta else (m, k))
+    B = rng.standard_normal((n, k) if tb else (k, n))
+    C0 = rng.standard_normal((m, n))
+    ref = 0.5 * ((A.T if ta else A) @ (B.T if tb else B)) - 2.0 * C0
+    out = _np(K.gemm(A, B, ta, tb, alpha=0.5, beta=-2.0, C=C0))
+    scale = np.abs(A).max() * np.abs(B).max() * k + 2 * np.abs(C0).max()
+    assert np.abs(out - ref).max() <= 1e-15 * scale * 4
+
+
+@pytest.mark.parametrize("n", [1, 5, 128, 129, 300, 513])
+def test_potrf(K, n):
+    A = _spd(n, n)
+    G, info = K.potrf(A)
+    G = _np(G)
+    assert info == -1
+    assert np.all(np.triu(G, 1) == 0)
+    assert np.abs(G - np.linalg.cholesky(A)).max() < 1e-12
+    assert np.abs(G @ G.T - A).max() < 1e-13 * np.abs(A).max() * max(1, np.sqrt(n))
+
+
+def test_potrf_reports_pivot(K):
+    A = _spd(200, 1)
+    A[150, 150] = -5.0
+    _, info = K.potrf(A)
+    assert info == 150
+
+
+@pytest.mark.parametrize("n", [1, 100, 128, 129, 300, 700])
+def test_trtri(K, n):
+    G = np.linalg.cholesky(_spd(n, n + 11))
+    Gi = _np(K.trtri(G))
+    assert np.all(np.triu(Gi, 1) == 0)
+    ref = sla.solve_triangular(G, np.eye(n), lower=True)
+    assert np.abs(Gi - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+def _band_dense(AB, n, nb):
+    B = np.zeros((n, n))
+    for d in range(nb + 1):
+        for j in range(n - d):
+            B[j + d, j] = AB[j, d]
+            B[j, j + d] = AB[j, d]
+    return B
+
+
+@pytest.mark.parametrize("n,nb", [(3, 1), (70, 16), (200, 64), (333, 64), (129, 32)])
+def test_sy2sb_preserves_spectrum(K, n, nb):
+    A = _sym(n, n + nb)
+    AB = _np(K.sy2sb(A, nb))
+    assert np.all(AB[:, nb + 1:] == 0)
+    B = _band_dense(AB, n, nb)
+    ev = np.linalg.eigvalsh(A)
+    eb = np.linalg.eigvalsh(B)
+    assert np.abs(ev - eb).max() < 1e-13 * np.abs(ev).max() * np.sqrt(n)
+
+
+@pytest.mark.parametrize("n,nb", [(3, 1), (5, 2), (150, 8), (200, 64), (301, 64)])
+def test_sb2st_preserves_spectrum(K, n, nb):
+    rng = np.random.default_rng(n)
+    B = np.zeros((n, n))
+    for d in range(nb + 1):
+        v = rng.standard_normal(n - d)
+        B += np.diag(v, -d) + (np.diag(v, d) if d else 0)
+    AB = np.zeros((n, 2 * nb + 1))
+    for d in range(nb + 1):
+        AB[:n - d, d] = np.diag(B, -d)
+    d_, e_ = K.sb2st(AB, nb)
+    T = np.diag(_np(d_)) + np.diag(_np(e_), 1) + np.diag(_np(e_), -1)
+    ev = np.linalg.eigvalsh(B)
+    assert np.abs(np.linalg.eigvalsh(T) - ev).max() < 1e-13 * np.abs(ev).max() * np.sqrt(n)
+
+
+def _check_eig(A, w, Z, tol=1e-13):
+    n = A.shape[0]
+    scale = max(np.abs(np.linalg.eigvalsh(A)).max(), 1e-300)
+    assert np.all(np.diff(w) >= 0)
+    assert np.abs(w - np.linalg.eigvalsh(A)).max() < tol * scale * max(1, np.sqrt(n))
+    assert np.abs(Z.T @ Z - np.eye(n)).max() < tol * 10 * max(1, np.sqrt(n))
+    assert np.abs(A @ Z - Z * w).max() < tol * 10 * scale * max(1, np.sqrt(n))
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 31, 32, 33, 64, 100, 257, 600])
+def test_stedc_random(K, n):
+    rng = np.random.default_rng(n + 100)
+    d = rng.standard_normal(n)
+    e = rng.standard_normal(max(n - 1, 0))
+    w, Z = K.stedc(d, e)
+    T = np.diag(d) + np.diag(e, 1) + np.diag(e, -1)
+    _check_eig(T, _np(w), _np(Z))
+
+
+@pytest.mark.parametrize("kind", ["zero_couplings", "repeated", "graded", "wilkinson"])
+def test_stedc_structured(K, kind):
+    n = 200
+    rng = np.random.default_rng(7)
+    if kind == "zero_couplings":
+        d = rng.standard_normal(n)
+        e = rng.standard_normal(n - 1)
+        e[::7] = 0.0
+    elif kind == "repeated":
+        d = np.repeat(rng.standard_normal(n // 10), 10)
+        e = 1e-3 * rng.standard_normal(n - 1)
+        e[9::10] = 0.0
+    elif kind == "graded":
+        d = 10.0 ** np.linspace(-8, 4, n)
+        e = np.sqrt(d[:-1] * d[1:]) * 0.1
+    else:
+        m = (n - 1) / 2
+        d = np.abs(np.arange(n) - m)
+        e = np.ones(n - 1)
+    w, Z = K.stedc(d, e)
+    T = np.diag(d) + np.diag(e, 1) + np.diag(e, -1)
+    _check_eig(T, _np(w), _np(Z))
+
+
+@pytest.mark.parametrize("n", [1, 3, 50, 200, 301])
+def test_syevd(K, n):
+    A = _sym(n, 3 * n + 1)
+    w, Z = K.syevd(A)
+    _check_eig(A, _np(w), _np(Z))
+
+
+def test_syevd_clustered(K):
+    n = 256
+    rng = np.random.default_rng(3)
+    Qr, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = np.concatenate([np.full(60, 1.0), np.full(60, 2.0), rng.uniform(3, 4, n - 120)])
+    A = (Qr * lam) @ Qr.T
+    A = (A + A.T) / 2
+    w, Z = K.syevd(A)
+    _check_eig(A, _np(w), _np(Z), tol=5e-13)
