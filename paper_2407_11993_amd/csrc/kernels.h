@@ -15,10 +15,11 @@ int64_t trtri_ws_elems(int64_t n);
 // A <- A^{-1} for lower-triangular A (strict upper triangle zero on entry).
 void trtri_lower(double* A, int64_t lda, int64_t n, double* ws, int64_t ws_elems,
                  hipStream_t s);
-// Inverses of the nb x nb diagonal blocks of lower-triangular A, packed as
-// ceil(n/nb) blocks of nb*nb (column-major, zero padded).  nb <= 128.
+// Inverses of the nb x nb diagonal blocks of lower-triangular A (strict
+// upper triangle zero), packed as ceil(n/nb) blocks of nb*nb (column-major,
+// zero padded).  ws: trtri_ws_elems(nb) doubles.
 void diag_block_inverses(const double* A, int64_t lda, int64_t n, int nb,
-                         double* Dinv, hipStream_t s);
+                         double* Dinv, double* ws, int64_t ws_elems, hipStream_t s);
 void copy_matrix(const double* S, int64_t lds, double* D, int64_t ldd,
                  int64_t m, int64_t n, hipStream_t s);
 
@@ -46,9 +47,10 @@ void fill(double* p, int64_t count, double v, hipStream_t s);
 void fill_i64(int64_t* p, int64_t count, int64_t v, hipStream_t s);
 
 // ---- Cholesky theta-method (step_chol.hip) --------------------------------
-constexpr int TRSV_NB = 128;
-int64_t trsv_partial_elems(int64_t n);
-int64_t trsv_sync_words(int64_t n);
+// Block size of the triangular solves for order n (128, 256 or 512), and
+// the number of probe partial sums they produce per step.
+int trsv_block(int64_t n);
+int64_t trsv_parts(int64_t n);
 
 struct Forcing {
   // f^k = F u^k with F (n0 x nf, column-major) and u^k from the waveforms:
@@ -65,25 +67,23 @@ struct CholStep {
   int64_t n0 = 0;
   const double* Cf = nullptr;  // factor of Z, lower, column-major
   int64_t ld = 0;
-  const double* Dinv = nullptr;
+  int B = 128;                 // block size (trsv_block(n0))
+  const double* Dinv = nullptr;  // inverses of the B x B diagonal blocks of Cf
   Csr Ri;                      // reduced resistance
   Forcing f;
   double theta = 0.5, dt = 1.0;
   double* I = nullptr;         // state Ii (n0)
   double* b = nullptr;         // work vector (n0)
-  double* partial = nullptr;
-  unsigned* sync = nullptr;
+  double* y = nullptr;         // work vector (n0)
   const double* Pt = nullptr;  // probe weights (n0 x n_probe, column-major)
   int n_probe = 0;
-  double* probe_partial = nullptr;  // n_steps x NB x n_probe
+  double* probe_partial = nullptr;  // n_steps x trsv_parts(n0) x n_probe
 };
 void chol_steps(const CholStep& c, int64_t k0, int64_t n_steps, hipStream_t s);
-// signal(k, p) = (sum_J probe_partial(k, J, p) + sum_a Pd(p, a) diD_a^k) / dt
+// signal(k, p) = (sum_j probe_partial(k, j, p) + sum_a Pd(p, a) diD_a^k) / dt
 void probe_finish(const double* probe_partial, int64_t n_steps, int64_t nparts,
                   int n_probe, const double* Pd, int m, const double* i_D,
                   int64_t k0, double dt, double* signal, hipStream_t s);
-// Host-visible error word of the TRSV dataflow waits (0 = fine).
-int64_t trsv_error_offset(int64_t n);
 
 // ---- modal theta-method (step_modal.hip) ----------------------------------
 struct ModalStep {

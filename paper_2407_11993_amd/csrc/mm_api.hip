@@ -72,7 +72,7 @@ struct mm_ctx {
   // Cholesky method
   bool factored = false;
   double f_theta = 0.0, f_dt = 0.0;
-  Dev Z, Dinv, I, b, partial, sync;
+  Dev Z, Dinv, I, b, yv;
   // probe partial sums of one step call
   Dev pp;
   Dev tmp;
@@ -335,7 +335,8 @@ mm_status mm_step_cholesky(mm_ctx* c, double theta, double dt, int64_t n_steps,
     MM_REQUIRE(signal || n_steps == 0, kInvalid, "signal is required");
     hipStream_t s = c->stream;
     const int64_t n0 = c->n0;
-    const int64_t NB = ceil_div(n0, TRSV_NB);
+    const int B = trsv_block(n0);
+    const int64_t NB = ceil_div(n0, B);
     if (!c->I.p) {
       c->I.alloc(sizeof(double) * n0);
       fill(c->I.d(), n0, 0.0, s);
@@ -343,45 +344,39 @@ mm_status mm_step_cholesky(mm_ctx* c, double theta, double dt, int64_t n_steps,
     if (!c->factored || c->f_theta != theta || c->f_dt != dt) {
       c->factored = false;
       c->Z.alloc(sizeof(double) * n0 * n0);
-      c->Dinv.alloc(sizeof(double) * 2 * NB * TRSV_NB * TRSV_NB);
+      c->Dinv.alloc(sizeof(double) * NB * B * B);
       c->b.alloc(sizeof(double) * n0);
-      c->partial.alloc(sizeof(double) * trsv_partial_elems(n0));
-      const int64_t words = (trsv_sync_words(n0) + 1) / 2 * 2;  // whole int64 words
-      c->sync.alloc(sizeof(unsigned) * words);
-      fill_i64(c->sync.as<int64_t>(), words / 2, 0, s);
+      c->yv.alloc(sizeof(double) * n0);
       // b0: Z = Li + theta dt Ri = C C^T   (Ne = 0: Li = L, Ri = R)
       double* Z = c->Z.d();
       assemble_L(c->xyz.d(), c->h, c->n, Z, n0, false, s);
       add_csr_lower(Z, n0, theta * dt, c->R(), s);
       factor_checked(Z, n0, c->status.as<int64_t>(), c->tmp, s, "Li + theta dt Ri");
+      c->tmp.alloc(sizeof(double) * trtri_ws_elems(B));
+      diag_block_inverses(Z, n0, n0, B, c->Dinv.d(), c->tmp.d(), trtri_ws_elems(B), s);
+      MM_HIP_TRY(hipStreamSynchronize(s));
       c->tmp.release();
-      diag_block_inverses(Z, n0, n0, TRSV_NB, c->Dinv.d(), s);
       c->factored = true;
       c->f_theta = theta;
       c->f_dt = dt;
     }
     if (n_steps == 0) return;
-    c->pp.alloc(sizeof(double) * n_steps * NB * c->n_probe);
+    const int64_t parts = trsv_parts(n0);
+    c->pp.alloc(sizeof(double) * n_steps * parts * c->n_probe);
     CholStep cs;
     cs.n0 = n0;
     cs.Cf = c->Z.d(); cs.ld = n0;
+    cs.B = B;
     cs.Dinv = c->Dinv.d();
     cs.Ri = c->R();
     cs.f.F = c->M0.d(); cs.f.nf = c->nf; cs.f.m = (int)c->m; cs.f.n_src = c->n_src;
     cs.f.i_src = i_src; cs.f.i_D = i_D;
     cs.theta = theta; cs.dt = dt;
-    cs.I = c->I.d(); cs.b = c->b.d();
-    cs.partial = c->partial.d();
-    cs.sync = c->sync.as<unsigned>();
+    cs.I = c->I.d(); cs.b = c->b.d(); cs.y = c->yv.d();
     cs.Pt = c->P.d(); cs.n_probe = c->n_probe;
     cs.probe_partial = c->pp.d();
     chol_steps(cs, 0, n_steps, s);
-    probe_finish(c->pp.d(), n_steps, NB, c->n_probe, nullptr, 0, i_D, 0, dt, signal, s);
-    // the dataflow waits of the solves are bounded; report if one gave up
-    unsigned err = 0;
-    MM_HIP_TRY(hipMemcpyAsync(&err, c->sync.p, sizeof(unsigned), hipMemcpyDeviceToHost, s));
-    MM_HIP_TRY(hipStreamSynchronize(s));
-    if (err != 0) throw Error{kDevice, "triangular solve dataflow wait timed out"};
+    probe_finish(c->pp.d(), n_steps, parts, c->n_probe, nullptr, 0, i_D, 0, dt, signal, s);
   });
 }
 

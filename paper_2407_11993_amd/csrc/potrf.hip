@@ -135,35 +135,6 @@ __global__ void __launch_bounds__(256) trtri_diag(double* A, int64_t lda,
   }
 }
 
-// Inverse of diagonal block b (size <= nb) of lower-triangular A, written
-// zero padded as Dinv[b] (nb x nb) and transposed as Dinv[NB + b].
-__global__ void __launch_bounds__(256) diag_inv_k(const double* A, int64_t lda, int64_t n,
-                                                  int nb, double* Dinv) {
-  __shared__ double L[DB * LDL];
-  __shared__ int bad;
-  const int t = threadIdx.x;
-  const int64_t NB = ceil_div(n, nb);
-  const int64_t j0 = (int64_t)blockIdx.x * nb;
-  const int jb = (int)min((int64_t)nb, n - j0);
-  if (t == 0) bad = -1;
-  const double* Ab = A + j0 + j0 * lda;
-  for (int e = t; e < jb * jb; e += blockDim.x) {
-    const int i = e % jb, j = e / jb;
-    L[i + j * LDL] = (i >= j) ? Ab[i + (int64_t)j * lda] : 0.0;
-  }
-  __syncthreads();
-  lds_chol_inv(L, jb, false, true, nullptr, &bad);
-  __syncthreads();
-  double* D = Dinv + (int64_t)blockIdx.x * nb * nb;
-  double* DT = Dinv + (NB + (int64_t)blockIdx.x) * nb * nb;
-  for (int e = t; e < nb * nb; e += blockDim.x) {
-    const int i = e % nb, j = e / nb;
-    const double v = (i < jb && j < jb && i >= j) ? L[i + j * LDL] : 0.0;
-    D[i + (int64_t)j * nb] = v;
-    DT[j + (int64_t)i * nb] = v;
-  }
-}
-
 __global__ void zero_upper(double* A, int64_t lda, int64_t n) {
   const int64_t j = blockIdx.x;
   for (int64_t i = threadIdx.x; i < j; i += blockDim.x) A[i + j * lda] = 0.0;
@@ -261,12 +232,17 @@ int64_t trtri_ws_elems(int64_t n) {
 }
 
 void diag_block_inverses(const double* A, int64_t lda, int64_t n, int nb, double* Dinv,
-                         hipStream_t s) {
-  MM_REQUIRE(nb >= 1 && nb <= DB, kInvalid, "diag_block_inverses: block too large");
+                         double* ws, int64_t ws_elems, hipStream_t s) {
+  MM_REQUIRE(nb >= 1, kInvalid, "diag_block_inverses: block size");
   if (n <= 0) return;
-  hipLaunchKernelGGL(diag_inv_k, dim3((unsigned)ceil_div(n, nb)), dim3(256), 0, s, A, lda, n, nb,
-                     Dinv);
-  MM_HIP_TRY(hipGetLastError());
+  const int64_t NB = ceil_div(n, nb);
+  fill(Dinv, NB * nb * nb, 0.0, s);
+  for (int64_t J = 0; J < NB; ++J) {
+    const int64_t j0 = J * nb, jb = std::min<int64_t>(nb, n - j0);
+    double* D = Dinv + J * nb * nb;
+    copy_matrix(A + j0 + j0 * lda, lda, D, nb, jb, jb, s);
+    trtri_lower(D, nb, jb, ws, ws_elems, s);
+  }
 }
 
 void copy_matrix(const double* S, int64_t lds, double* D, int64_t ldd,
