@@ -1,0 +1,198 @@
+"""Benchmark: end-to-end seconds of the modal vs the Cholesky theta-method.
+
+One step = the whole hot path on one synthetic problem, every phase on the
+GPU: problem setup and L assembly, the modal decomposition, modal stepping
+for each theta, and the Cholesky method (one factorisation per theta and
+two triangular solves per time step).  Default workload: the 128x128 plate
+(N = 16,384) with a 10x3 crack, T = 10,000 steps, theta in {0.5, 1.0}.
+
+Prints one JSON line.  `value` is the modal method's end-to-end seconds for
+the workload (lower is better); the Cholesky method's seconds, the speed-up,
+the decomposition's FP64 TFLOP/s and the roofline of the dominant kernel are
+reported beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
+FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 matrix (= vector), published
+
+
+def _workload(name: str, T: int | None):
+    from paper_2407_11993_amd import inputs
+    if name == "plate-128x128-crack":
+        return inputs.config2(T=T or 10000)
+    if name == "block-8x8x8":
+        return inputs.config1(T=T or 2000)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def _decomp_flops(n: int) -> float:
+    # algorithmic FP64 flops of the modal decomposition:
+    # potrf n^3/3, trtri n^3/3, C = G^{-1} W^T (lower) n^3/3,
+    # band reduction 4n^3/3, back-transform Q2 2n^3 + Q1 2n^3,
+    # D&C merges <= 4n^3/3 (not counted: deflation dependent)
+    return (1 / 3 + 1 / 3 + 1 / 3 + 4 / 3 + 2 + 2) * float(n) ** 3
+
+
+def run_gpu(args):
+    import numpy as np
+    import torch
+    from paper_2407_11993_amd import Solver
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    w = _workload(args.workload, args.T)
+    stream = torch.cuda.current_stream()
+    # waveforms resident in HBM before the timed region
+    i_src = torch.as_tensor(w.i_src, dtype=torch.float64, device="cuda")
+
+    def one_step():
+        ev = {k: torch.cuda.Event(enable_timing=True) for k in
+              ("start", "setup", "decomp", "modal", "chol_start", "chol")}
+        ev["start"].record(stream)
+        s = Solver(w)
+        ev["setup"].record(stream)
+        s.decompose()
+        ev["decomp"].record(stream)
+        sig_m = []
+        for th in w.thetas:
+            s.reset()
+            sig_m.append(s.step_modal(th, w.dt, w.T, i_src))
+        ev["modal"].record(stream)
+        s.reset()
+        ev["chol_start"].record(stream)
+        sig_c = []
+        for th in w.thetas:
+            s.reset()
+            sig_c.append(s.step_cholesky(th, w.dt, w.T, i_src))
+        ev["chol"].record(stream)
+        torch.cuda.synchronize()
+        t = {
+            "setup": ev["start"].elapsed_time(ev["setup"]) / 1e3,
+            "decompose": ev["setup"].elapsed_time(ev["decomp"]) / 1e3,
+            "modal_steps": ev["decomp"].elapsed_time(ev["modal"]) / 1e3,
+            "cholesky": ev["chol_start"].elapsed_time(ev["chol"]) / 1e3,
+        }
+        s.close()
+        print("bench: step done " + " ".join(f"{k}={v:.3f}s" for k, v in t.items()),
+              file=sys.stderr, flush=True)
+        return t, sig_m, sig_c
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    times = []
+    for _ in range(args.steps):
+        t, sig_m, sig_c = one_step()
+        times.append(t)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    agree = max(float((a - b).abs().max() / b.abs().max()) for a, b in zip(sig_m, sig_c))
+    avg = {k: sum(x[k] for x in times) / len(times) for k in times[0]}
+    modal_s = avg["setup"] + avg["decompose"] + avg["modal_steps"]
+    # the Cholesky method needs the same problem setup (L assembly is inside
+    # its factorisation)
+    chol_s = avg["setup"] + avg["cholesky"]
+    n = w.n
+    nsteps_total = w.T * len(w.thetas)
+    # dominant kernel group: the two triangular solves of every Cholesky step.
+    # Algorithmic bytes per step: the lower triangle of the factor read once
+    # per solve, 2 * 8 * n(n+1)/2.
+    trsv_bytes = 2 * 8.0 * n * (n + 1) / 2
+    per_step = avg["cholesky"] / nsteps_total
+    achieved = trsv_bytes / per_step / 1e9
+    res = {
+        "metric": "end-to-end s, modal theta-method (Cholesky theta-method beside it)",
+        "value": round(modal_s, 4),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * wall / args.steps, 2),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "N": n, "T": w.T, "thetas": list(w.thetas),
+                   "dt": w.dt, "probes": w.n_probe},
+        "cholesky_s": round(chol_s, 4),
+        "speedup_modal_vs_cholesky": round(chol_s / modal_s, 3),
+        "signal_agreement_modal_vs_cholesky": agree,
+        "phases_s": {k: round(v, 4) for k, v in avg.items()},
+        "decomposition_tflops": round(_decomp_flops(n) / avg["decompose"] / 1e12, 3),
+        "roofline": {"bound": "hbm", "kernel": "triangular solve pair (fwd+bwd per step)",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+    }
+    return res
+
+
+def cpu_baseline(args):
+    """The oracle (plain C, one thread) on a bounded sample, scaled to the
+    workload: decomposition by (N/n)^3, stepping by (N/n)^2 (T/t)."""
+    import numpy as np
+
+    import oracle
+    from paper_2407_11993_amd import inputs
+    oracle.build(force=False)
+    full = _workload(args.workload, args.T)
+    side = 20
+    t_sample = 4000
+    w = inputs.plate(side, side, seed=0, crack=((8, 12), (9, 10), 1e3), T=t_sample,
+                     wave="gauss", coil=((side - 1) / 2, (side - 1) / 2, 2.0))
+    L = oracle.assemble_L(w.xyz, w.h)
+    pb = oracle.Problem(L, w.R.to_dense(), w.M, w.P)
+    t0 = time.perf_counter()
+    oracle.modal_eigen(pb, want_V=True)
+    t_dec = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.theta_modal(pb, 0.5, 1.0, t_sample, w.i_src)
+    t_modal = time.perf_counter() - t0 - t_dec
+    t0 = time.perf_counter()
+    oracle.theta_direct(pb, 0.5, 1.0, t_sample, w.i_src)
+    t_direct = time.perf_counter() - t0
+    r = full.n / w.n
+    nth = len(full.thetas)
+    modal_est = t_dec * r ** 3 + max(t_modal, 0.0) * r ** 2 * (full.T / t_sample) * nth
+    return {"value": round(modal_est, 1), "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": (f"oracle modal path (Jacobi decomposition + modal theta-steps) and "
+                       f"direct Cholesky stepper on a {side}x{side} plate (N={w.n}, "
+                       f"T={t_sample}, theta=0.5): decomposition {t_dec:.2f} s, modal "
+                       f"steps {max(t_modal, 0):.2f} s, direct {t_direct:.2f} s; value "
+                       f"extrapolated to N={full.n}, T={full.T} x {nth} thetas by N^3 "
+                       f"(decomposition) and N^2 T (steps)"),
+            "cholesky_estimate_s": round(t_direct * r ** 2 * (full.T / t_sample) * nth, 1)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="plate-128x128-crack")
+    ap.add_argument("--T", type=int, default=None, help="override the step count")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU; --gpus above 1 is not supported "
+              "(the multi-GPU sharding is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    res = run_gpu(args)
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(args)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()
