@@ -35,9 +35,11 @@ Sb2stPlan sb2st_plan(int64_t n, int nb);
 // V2 (tasks x nb) and tau2 (tasks); d_offset is plan.offset on the device.
 void sb2st(double* AB, int64_t ldab, const Sb2stPlan& plan, const int64_t* d_offset,
            double* V2, double* tau2, double* d, double* e, hipStream_t s);
-// Z <- Q2 Z (rows 0..n-1, ncols columns).
+// Z <- Q2 Z (rows 0..n-1, ncols columns); ws: any size above 2^15 doubles
+// (more is faster: the compact-WY blocks are processed in batches).
 void apply_q2(const Sb2stPlan& plan, const int64_t* d_offset, const double* V2,
-              const double* tau2, double* Z, int64_t ldz, int64_t ncols, hipStream_t s);
+              const double* tau2, double* Z, int64_t ldz, int64_t ncols, double* ws,
+              int64_t ws_elems, hipStream_t s);
 
 // ---- tridiagonal divide and conquer ---------------------------------------
 int64_t stedc_ws_elems(int64_t n);

@@ -76,7 +76,7 @@ void syevd(double* C, int64_t ldc, int64_t n, double* lam, double* Q, int64_t ld
   extract_band(C, ldc, n, nb, w.AB, ldab, s);
   sb2st(w.AB, ldab, plan, w.d_offset, w.V2, w.tau2, w.d, w.e, s);
   stedc(w.d, w.e, n, lam, Q, ldq, w.ws, w.ws_elems, d_status, s);
-  apply_q2(plan, w.d_offset, w.V2, w.tau2, Q, ldq, n, s);
+  apply_q2(plan, w.d_offset, w.V2, w.tau2, Q, ldq, n, w.ws, w.ws_elems, s);
   apply_q1(C, ldc, n, nb, w.T1, Q, ldq, n, w.ws, w.ws_elems, s);
 }
 

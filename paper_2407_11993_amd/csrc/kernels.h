@@ -69,6 +69,9 @@ struct CholStep {
   int64_t ld = 0;
   int B = 128;                 // block size (trsv_block(n0))
   const double* Dinv = nullptr;  // inverses of the B x B diagonal blocks of Cf
+  const double* DinvT = nullptr; // the same blocks transposed
+  int64_t* kstep = nullptr;    // device step counter (one int64)
+  bool use_graph = true;       // replay one captured step per time step
   Csr Ri;                      // reduced resistance
   Forcing f;
   double theta = 0.5, dt = 1.0;
@@ -80,6 +83,9 @@ struct CholStep {
   double* probe_partial = nullptr;  // n_steps x trsv_parts(n0) x n_probe
 };
 void chol_steps(const CholStep& c, int64_t k0, int64_t n_steps, hipStream_t s);
+// DinvT(block b) = Dinv(block b)^T for nblocks blocks of B x B.
+void transpose_blocks(const double* Dinv, int64_t nblocks, int B, double* DinvT,
+                      hipStream_t s);
 // signal(k, p) = (sum_j probe_partial(k, j, p) + sum_a Pd(p, a) diD_a^k) / dt
 void probe_finish(const double* probe_partial, int64_t n_steps, int64_t nparts,
                   int n_probe, const double* Pd, int m, const double* i_D,

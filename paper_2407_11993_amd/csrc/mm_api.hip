@@ -4,6 +4,7 @@
 #include "mm.h"
 
 #include <climits>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -72,7 +73,8 @@ struct mm_ctx {
   // Cholesky method
   bool factored = false;
   double f_theta = 0.0, f_dt = 0.0;
-  Dev Z, Dinv, I, b, yv;
+  Dev Z, Dinv, DinvT, I, b, yv, kstep;
+  bool use_graph = true;  // MM_NO_GRAPH=1 in the environment turns graphs off
   // probe partial sums of one step call
   Dev pp;
   Dev tmp;
@@ -163,6 +165,8 @@ mm_status mm_setup(const mm_problem* pb, void* stream, mm_ctx** out) {
     MM_REQUIRE(pb->n_e == 0, kInvalid, "electrodes are not supported by this build yet");
     c->stream = (hipStream_t)stream;
     hipStream_t s = c->stream;
+    const char* ng = std::getenv("MM_NO_GRAPH");
+    c->use_graph = !(ng && ng[0] == '1');
     c->n = pb->n;
     c->m = pb->n_e > 0 ? pb->n_e - 1 : 0;
     c->n0 = c->n - c->m;
@@ -345,8 +349,10 @@ mm_status mm_step_cholesky(mm_ctx* c, double theta, double dt, int64_t n_steps,
       c->factored = false;
       c->Z.alloc(sizeof(double) * n0 * n0);
       c->Dinv.alloc(sizeof(double) * NB * B * B);
+      c->DinvT.alloc(sizeof(double) * NB * B * B);
       c->b.alloc(sizeof(double) * n0);
       c->yv.alloc(sizeof(double) * n0);
+      c->kstep.alloc(sizeof(int64_t));
       // b0: Z = Li + theta dt Ri = C C^T   (Ne = 0: Li = L, Ri = R)
       double* Z = c->Z.d();
       assemble_L(c->xyz.d(), c->h, c->n, Z, n0, false, s);
@@ -354,6 +360,7 @@ mm_status mm_step_cholesky(mm_ctx* c, double theta, double dt, int64_t n_steps,
       factor_checked(Z, n0, c->status.as<int64_t>(), c->tmp, s, "Li + theta dt Ri");
       c->tmp.alloc(sizeof(double) * trtri_ws_elems(B));
       diag_block_inverses(Z, n0, n0, B, c->Dinv.d(), c->tmp.d(), trtri_ws_elems(B), s);
+      transpose_blocks(c->Dinv.d(), NB, B, c->DinvT.d(), s);
       MM_HIP_TRY(hipStreamSynchronize(s));
       c->tmp.release();
       c->factored = true;
@@ -368,6 +375,9 @@ mm_status mm_step_cholesky(mm_ctx* c, double theta, double dt, int64_t n_steps,
     cs.Cf = c->Z.d(); cs.ld = n0;
     cs.B = B;
     cs.Dinv = c->Dinv.d();
+    cs.DinvT = c->DinvT.d();
+    cs.kstep = c->kstep.as<int64_t>();
+    cs.use_graph = c->use_graph;
     cs.Ri = c->R();
     cs.f.F = c->M0.d(); cs.f.nf = c->nf; cs.f.m = (int)c->m; cs.f.n_src = c->n_src;
     cs.f.i_src = i_src; cs.f.i_D = i_D;

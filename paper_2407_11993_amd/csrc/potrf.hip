@@ -2,7 +2,8 @@
 //
 // potrf: blocked right-looking factorisation A = G G^T with NB = 128 column
 // panels.  The 128 x 128 diagonal block is factored inside LDS by one
-// workgroup, which also writes the inverse of its factor; the panel below is
+// workgroup (itself blocked by 16), which also writes the inverse of its
+// factor; the panel below is
 // then G21 = A21 G11^{-T} (a GEMM against that inverse) and the trailing
 // matrix takes the symmetric rank-128 update A22 -= G21 G21^T on the matrix
 // cores (lower triangle only).  Used for Li = G G^T (modal method) and for
@@ -21,62 +22,93 @@ namespace {
 constexpr int DB = 128;        // diagonal block size
 constexpr int LDL = DB + 1;    // LDS leading dimension
 
-// Factor (if `factor`) and invert the jb x jb lower triangle held in LDS.
-// L[i + j*LDL].  On a non-positive pivot, *bad receives its local index.
-__device__ void lds_chol_inv(double* L, int jb, bool factor, bool want_inv,
-                             double* Linv, int* bad) {
-  const int t = threadIdx.x, nt = blockDim.x;
-  __shared__ double tmp[DB];
-  __shared__ double diag;
-  if (factor) {
-    for (int k = 0; k < jb; ++k) {
-      if (t == 0) {
+// In-LDS factorisation of the jb x jb (jb <= 128) lower triangle L[i + j*LDL],
+// blocked by 16 columns: the 16 x 16 diagonal piece is factored by one
+// thread (left-looking inside the piece), the rows below it by one thread
+// per row (forward substitution), and the trailing lower triangle takes the
+// rank-16 update in parallel.  Needs blockDim.x == 256.  A non-positive pivot
+// is recorded in *bad (local index) and replaced by 1 so the work finishes.
+__device__ void lds_potrf16(double* L, int jb, int* bad) {
+  const int t = threadIdx.x;
+  for (int k0 = 0; k0 < jb; k0 += 16) {
+    const int ke = min(k0 + 16, jb);
+    if (t == 0) {
+      for (int k = k0; k < ke; ++k) {
         double d = L[k + k * LDL];
+        for (int c = k0; c < k; ++c) d -= L[k + c * LDL] * L[k + c * LDL];
         if (!(d > 0.0)) {
           if (*bad < 0) *bad = k;
-          d = 1.0;  // keep going with a harmless pivot; the caller reports
+          d = 1.0;
         }
         d = sqrt(d);
         L[k + k * LDL] = d;
-        diag = d;
+        for (int i = k + 1; i < ke; ++i) {
+          double x = L[i + k * LDL];
+          for (int c = k0; c < k; ++c) x -= L[i + c * LDL] * L[k + c * LDL];
+          L[i + k * LDL] = x / d;
+        }
       }
-      __syncthreads();
-      const double inv = 1.0 / diag;
-      for (int i = k + 1 + t; i < jb; i += nt) L[i + k * LDL] *= inv;
-      __syncthreads();
-      // trailing update of the lower triangle, columns k+1..jb-1
-      const int m = jb - k - 1;
-      for (int e = t; e < m * m; e += nt) {
-        const int i = k + 1 + e % m, j = k + 1 + e / m;
-        if (i >= j) L[i + j * LDL] -= L[i + k * LDL] * L[j + k * LDL];
-      }
-      __syncthreads();
-    }
-  }
-  if (!want_inv) return;
-  // Inverse of the lower triangle, column by column from the right:
-  // X(j,j) = 1/L(j,j);  X(j+1:, j) = -X(j+1:, j+1:) L(j+1:, j) / L(j,j),
-  // where X(j+1:, j+1:) is already inverted in place (LAPACK trti2 order).
-  for (int j = jb - 1; j >= 0; --j) {
-    const double ljj = L[j + j * LDL];
-    // tmp(i) = sum_{k=j+1..i} X(i,k) L(k,j)
-    for (int i = j + 1 + t; i < jb; i += nt) {
-      double s = 0.0;
-      for (int k = j + 1; k <= i; ++k) s += L[i + k * LDL] * L[k + j * LDL];
-      tmp[i] = s;
     }
     __syncthreads();
-    const double xjj = 1.0 / ljj;
-    for (int i = j + 1 + t; i < jb; i += nt) L[i + j * LDL] = -tmp[i] * xjj;
+    for (int i = ke + t; i < jb; i += 256) {
+      for (int k = k0; k < ke; ++k) {
+        double x = L[i + k * LDL];
+        for (int c = k0; c < k; ++c) x -= L[i + c * LDL] * L[k + c * LDL];
+        L[i + k * LDL] = x / L[k + k * LDL];
+      }
+    }
     __syncthreads();
-    if (t == 0) L[j + j * LDL] = xjj;
+    const int a = t & 15, bq = t >> 4;
+    for (int j = ke + bq; j < jb; j += 16)
+      for (int i = ke + a; i < jb; i += 16)
+        if (i >= j) {
+          double x = L[i + j * LDL];
+#pragma unroll 4
+          for (int c = k0; c < ke; ++c) x -= L[i + c * LDL] * L[j + c * LDL];
+          L[i + j * LDL] = x;
+        }
     __syncthreads();
   }
-  if (Linv) {
-    for (int e = t; e < jb * jb; e += nt) {
-      const int i = e % jb, j = e / jb;
-      Linv[i + (int64_t)j * jb] = (i >= j) ? L[i + j * LDL] : 0.0;
+}
+
+// In-LDS inverse of the jb x jb lower triangle, in place, by 16-wide block
+// columns from the right:  X_jj = L_jj^{-1} (one thread, unblocked, rows
+// processed bottom-up so every original entry is read before it is
+// overwritten), then X(je:, j0:je) = -X(je:, je:) L(je:, j0:je) X_jj with the
+// already inverted trailing part.  Needs blockDim.x == 256.
+__device__ void lds_trtri16(double* L, int jb) {
+  __shared__ double Yb[128 * 16];
+  const int t = threadIdx.x;
+  const int nblk = (jb + 15) / 16;
+  for (int bj = nblk - 1; bj >= 0; --bj) {
+    const int j0 = bj * 16, je = min(j0 + 16, jb), w = je - j0;
+    if (t == 0) {
+      for (int j = je - 1; j >= j0; --j) {
+        const double xjj = 1.0 / L[j + j * LDL];
+        for (int i = je - 1; i > j; --i) {
+          double sacc = 0.0;
+          for (int k = j + 1; k <= i; ++k) sacc += L[i + k * LDL] * L[k + j * LDL];
+          L[i + j * LDL] = -sacc * xjj;
+        }
+        L[j + j * LDL] = xjj;
+      }
     }
+    __syncthreads();
+    const int R = jb - je;
+    for (int e = t; e < R * w; e += 256) {
+      const int i = e % R, c = e / R;
+      double sacc = 0.0;
+      for (int k = je; k <= je + i; ++k) sacc += L[(je + i) + k * LDL] * L[k + (j0 + c) * LDL];
+      Yb[i + c * 128] = sacc;
+    }
+    __syncthreads();
+    for (int e = t; e < R * w; e += 256) {
+      const int i = e % R, c = e / R;
+      double sacc = 0.0;
+      for (int k = c; k < w; ++k) sacc += Yb[i + k * 128] * L[(j0 + k) + (j0 + c) * LDL];
+      L[(je + i) + (j0 + c) * LDL] = -sacc;
+    }
+    __syncthreads();
   }
 }
 
@@ -95,16 +127,17 @@ __global__ void __launch_bounds__(256) potrf_diag(double* A, int64_t lda,
     L[i + j * LDL] = Ab[i + (int64_t)j * lda];
   }
   __syncthreads();
-  // factor in LDS (the inverse overwrites L, so factor into L, copy it out,
-  // then invert)
-  lds_chol_inv(L, jb, true, false, nullptr, &bad);
-  __syncthreads();
+  lds_potrf16(L, jb, &bad);
   for (int e = t; e < jb * jb; e += blockDim.x) {
     const int i = e % jb, j = e / jb;
     Ab[i + (int64_t)j * lda] = (i >= j) ? L[i + j * LDL] : 0.0;
   }
   __syncthreads();
-  lds_chol_inv(L, jb, false, true, Linv, &bad);
+  lds_trtri16(L, jb);
+  for (int e = t; e < jb * jb; e += blockDim.x) {
+    const int i = e % jb, j = e / jb;
+    Linv[i + (int64_t)j * jb] = (i >= j) ? L[i + j * LDL] : 0.0;
+  }
   if (t == 0 && bad >= 0) {
     const unsigned long long g = (unsigned long long)(j0 + bad);
     atomicMin((unsigned long long*)status, g);
@@ -116,19 +149,16 @@ __global__ void __launch_bounds__(256) potrf_diag(double* A, int64_t lda,
 __global__ void __launch_bounds__(256) trtri_diag(double* A, int64_t lda,
                                                   int64_t n, int bs) {
   __shared__ double L[DB * LDL];
-  __shared__ int bad;
   const int t = threadIdx.x;
   const int64_t j0 = (int64_t)blockIdx.x * bs;
   const int jb = (int)min((int64_t)bs, n - j0);
-  if (t == 0) bad = -1;
   double* Ab = A + j0 + j0 * lda;
   for (int e = t; e < jb * jb; e += blockDim.x) {
     const int i = e % jb, j = e / jb;
     L[i + j * LDL] = (i >= j) ? Ab[i + (int64_t)j * lda] : 0.0;
   }
   __syncthreads();
-  lds_chol_inv(L, jb, false, true, nullptr, &bad);
-  __syncthreads();
+  lds_trtri16(L, jb);
   for (int e = t; e < jb * jb; e += blockDim.x) {
     const int i = e % jb, j = e / jb;
     Ab[i + (int64_t)j * lda] = (i >= j) ? L[i + j * LDL] : 0.0;

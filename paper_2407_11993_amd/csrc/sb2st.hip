@@ -1,5 +1,4 @@
-// Stage 2 of the two-stage tridiagonalisation: bulge chasing B = Q2 T Q2^T,
-// and the two back-transforms Q = Q1 (Q2 Z).
+// Stage 2 of the two-stage tridiagonalisation: bulge chasing B = Q2 T Q2^T.
 //
 // Band storage: AB(d, j) = B(j + d, j), 0 <= d <= 2 nb (the rows beyond nb
 // hold the bulge).  Sweep s annihilates column s below the subdiagonal; its
@@ -13,22 +12,13 @@
 // Tasks (s, k) with the same 3s + k touch disjoint windows of the band, and
 // every task a task depends on has a smaller 3s + k, so one launch per value
 // of 3s + k runs all of its tasks concurrently.
-//
-// Q2 = H_{0,0} H_{0,1} ... H_{1,0} ... in generation order, so Q2 Z applies
-// them last-first.  Groups of 64 consecutive sweeps are applied together
-// (group g descending, then k ascending, then s descending inside the
-// group): every pair of reflectors whose order this changes acts on disjoint
-// rows and therefore commutes.  A workgroup owns 64 columns of Z and keeps
-// the group's row window in LDS while applying its reflectors.
+// The back-transform by these reflectors is in q2.hip.
 #include "eig.h"
 
 namespace mm {
 namespace {
 
 constexpr int NT = 256;
-constexpr int GS = 64;       // sweeps per back-transform group
-constexpr int ZC = 64;       // Z columns per workgroup in apply_q2
-constexpr int WIN = 128;     // max window rows (nb + GS - 1)
 
 __device__ __forceinline__ double wsum(double v) {
 #pragma unroll
@@ -55,6 +45,10 @@ struct Band {
   }
 };
 
+// One task (s, k).  The three blocks it touches -- the block left of the
+// diagonal block (its first column is the one eliminated), the diagonal block
+// and the block below -- are staged in LDS with independent loads, updated
+// there, and written back.  nb <= 64.
 __global__ void __launch_bounds__(NT) sb2st_stage(Band B, int64_t n, int nb, int64_t stage,
                                                   int64_t s_lo, const int64_t* off,
                                                   double* V2, double* tau2) {
@@ -64,92 +58,129 @@ __global__ void __launch_bounds__(NT) sb2st_stage(Band B, int64_t n, int nb, int
   if (k < 0) return;
   const int64_t Ks = ceil_div(n - 1 - s, nb);
   if (k >= Ks) return;
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int64_t r0 = s + 1 + k * nb;
   const int len = (int)min((int64_t)nb, n - r0);
   const int64_t c0 = (k == 0) ? s : s + 1 + (k - 1) * nb;  // column to eliminate
-  const int64_t cend = (k == 0) ? s + 1 : r0;              // left block columns [c0, cend)
+  const int ncl = (int)(((k == 0) ? s + 1 : r0) - c0);       // left block columns
   const int64_t rn0 = r0 + len;
   const int lenn = (int)max((int64_t)0, min((int64_t)nb, n - rn0));
-  __shared__ double v[128], p[128], q[128], sh[8];
-  __shared__ double s_tau, s_beta;
+  __shared__ double Lb[64][65], Db[64][65], Bb[64][65];
+  __shared__ double v[64], p[64], w[64], sh[8];
+  __shared__ double s_tau, s_beta, s_scale;
 
-  if (t < len) v[t] = B.at(r0 + t, c0);
+  // ---- stage (column-major walks: consecutive threads, consecutive rows)
+  for (int e = t; e < len * ncl; e += NT) {
+    const int i = e % len, j = e / len;
+    Lb[i][j] = B.at(r0 + i, c0 + j);
+  }
+  for (int e = t; e < len * len; e += NT) {
+    const int i = e % len, j = e / len;
+    if (i >= j) {
+      const double a = B.at(r0 + i, r0 + j);
+      Db[i][j] = a;
+      Db[j][i] = a;
+    }
+  }
+  for (int e = t; e < lenn * len; e += NT) {
+    const int i = e % lenn, j = e / lenn;
+    Bb[i][j] = B.at(rn0 + i, r0 + j);
+  }
   __syncthreads();
-  const double a0 = v[0];
-  const double sig2 = block_sum((t >= 1 && t < len) ? v[t] * v[t] : 0.0, sh);
+  // ---- Householder reflector of the eliminated column Lb(:, 0)
+  {
+    double x = (t >= 1 && t < len) ? Lb[t][0] : 0.0;
+    x = wsum(x * x);
+    if (lane == 0) sh[wave] = x;
+  }
+  __syncthreads();
   if (t == 0) {
-    double tv = 0.0, beta = a0;
+    const double a0 = Lb[0][0];
+    const double sig2 = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    double tv = 0.0, beta = a0, scale = 0.0;
     if (sig2 > 0.0) {
       beta = -copysign(sqrt(a0 * a0 + sig2), a0);
       tv = (beta - a0) / beta;
+      scale = 1.0 / (a0 - beta);
     }
     s_tau = tv;
     s_beta = beta;
+    s_scale = scale;
   }
   __syncthreads();
   const double tau = s_tau;
-  if (tau != 0.0 && t < len) v[t] = (t == 0) ? 1.0 : v[t] / (a0 - s_beta);
-  if (tau == 0.0 && t < len) v[t] = (t == 0) ? 1.0 : 0.0;
+  if (t < 64) v[t] = (t == 0) ? 1.0 : ((t < len) ? Lb[t][0] * s_scale : 0.0);
   __syncthreads();
-  // store the reflector
   const int64_t task = off[s] + k;
   if (t < nb) V2[task * nb + t] = (t < len) ? v[t] : 0.0;
   if (t == 0) tau2[task] = tau;
-  if (tau == 0.0) return;
+  if (tau == 0.0) return;  // H = I: nothing changes (uniform branch)
 
-  // eliminated column: (beta, 0, ..., 0)
-  if (t < len) B.at(r0 + t, c0) = (t == 0) ? s_beta : 0.0;
-  // left application to the columns c0+1 .. cend-1 (k >= 1):
-  //   A(R, c) -= tau v (v^T A(R, c))
+  // ---- left application: Lb(:, j) -= tau v (v^T Lb(:, j)), j >= 1;
+  //      the eliminated column becomes (beta, 0, ..., 0)
   {
-    const int lane = t & 63, wave = t >> 6;
-    for (int64_t c = c0 + 1 + wave; c < cend; c += NT / 64) {
+    const int j = t >> 2, part = t & 3;  // 4 threads per column, 16 rows each
+    if (j >= 1 && j < ncl) {
       double d = 0.0;
-      for (int i = lane; i < len; i += 64) d += v[i] * B.at(r0 + i, c);
-      d = wsum(d);
-      for (int i = lane; i < len; i += 64) B.at(r0 + i, c) -= tau * v[i] * d;
+      for (int i = part; i < len; i += 4) d += v[i] * Lb[i][j];
+      d += __shfl_xor(d, 1, 64);
+      d += __shfl_xor(d, 2, 64);
+      const double f = tau * d;
+      for (int i = part; i < len; i += 4) Lb[i][j] -= f * v[i];
     }
+    if (t < len) Lb[t][0] = (t == 0) ? s_beta : 0.0;
   }
-  __syncthreads();
-  // two-sided on D = A(R, R): p = tau D v, w = p - tau/2 (p^T v) v,
-  // D -= v w^T + w v^T (lower triangle)
+  // ---- two-sided on D: p = tau D v, w = p - tau/2 (p^T v) v, D -= v w^T + w v^T
   {
-    const int i = t & 127, h = t >> 7;
+    const int i = t >> 2, part = t & 3;
     double acc = 0.0;
     if (i < len)
-      for (int j = h; j < len; j += 2) acc += B.sym(r0 + i, r0 + j) * v[j];
-    q[t & 127] = 0.0;
-    __syncthreads();
-    if (h == 0 && i < len) p[i] = acc;
-    __syncthreads();
-    if (h == 1 && i < len) p[i] += acc;
-    __syncthreads();
-    if (t < len) p[t] *= tau;
-    __syncthreads();
-    const double pv = block_sum(t < len ? p[t] * v[t] : 0.0, sh);
-    if (t < len) q[t] = p[t] - 0.5 * tau * pv * v[t];  // q = w
-    __syncthreads();
-    for (int e = t; e < len * len; e += NT) {
-      const int ii = e % len, jj = e / len;
-      if (ii >= jj) B.at(r0 + ii, r0 + jj) -= v[ii] * q[jj] + q[ii] * v[jj];
-    }
+      for (int j = part; j < len; j += 4) acc += Db[i][j] * v[j];
+    acc += __shfl_xor(acc, 1, 64);
+    acc += __shfl_xor(acc, 2, 64);
+    if (part == 0 && i < 64) p[i] = (i < len) ? tau * acc : 0.0;
   }
   __syncthreads();
-  // right application to the block below: A(Rn, R) -= tau (A(Rn, R) v) v^T
+  {
+    double x = (t < len) ? p[t] * v[t] : 0.0;
+    x = wsum(x);
+    if (lane == 0) sh[4 + wave] = x;
+  }
+  __syncthreads();
+  {
+    const double pv = (sh[4] + sh[5]) + (sh[6] + sh[7]);
+    if (t < 64) w[t] = (t < len) ? p[t] - 0.5 * tau * pv * v[t] : 0.0;
+  }
+  __syncthreads();
+  for (int e = t; e < len * len; e += NT) {
+    const int i = e % len, j = e / len;
+    if (i >= j) Db[i][j] -= v[i] * w[j] + w[i] * v[j];
+  }
+  // ---- right application to the block below: Bb -= tau (Bb v) v^T
   if (lenn > 0) {
-    const int i = t & 127, h = t >> 7;
+    const int i = t >> 2, part = t & 3;
     double acc = 0.0;
     if (i < lenn)
-      for (int j = h; j < len; j += 2) acc += B.at(rn0 + i, r0 + j) * v[j];
-    if (h == 0 && i < lenn) p[i] = acc;
-    __syncthreads();
-    if (h == 1 && i < lenn) p[i] += acc;
-    __syncthreads();
-    for (int e = t; e < lenn * len; e += NT) {
-      const int ii = e % lenn, jj = e / lenn;
-      B.at(rn0 + ii, r0 + jj) -= tau * p[ii] * v[jj];
-    }
+      for (int j = part; j < len; j += 4) acc += Bb[i][j] * v[j];
+    acc += __shfl_xor(acc, 1, 64);
+    acc += __shfl_xor(acc, 2, 64);
+    const double f = tau * acc;
+    if (i < lenn)
+      for (int j = part; j < len; j += 4) Bb[i][j] -= f * v[j];
+  }
+  __syncthreads();
+  // ---- write back
+  for (int e = t; e < len * ncl; e += NT) {
+    const int i = e % len, j = e / len;
+    B.at(r0 + i, c0 + j) = Lb[i][j];
+  }
+  for (int e = t; e < len * len; e += NT) {
+    const int i = e % len, j = e / len;
+    if (i >= j) B.at(r0 + i, r0 + j) = Db[i][j];
+  }
+  for (int e = t; e < lenn * len; e += NT) {
+    const int i = e % lenn, j = e / lenn;
+    B.at(rn0 + i, r0 + j) = Bb[i][j];
   }
 }
 
@@ -158,68 +189,6 @@ __global__ void band_to_tridiag(const double* AB, int64_t ld, int64_t n, double*
   if (j >= n) return;
   d[j] = AB[j * ld];
   if (j + 1 < n) e[j] = AB[1 + j * ld];
-}
-
-// Z <- (group of sweeps [sa, sb)) applied to Z rows, all k, for 64 columns.
-// Lane layout: column cz = wave*16 + lane/4, rows i == (lane & 3) mod 4.
-__global__ void __launch_bounds__(NT) apply_q2_group(int64_t n, int nb, int64_t sa, int64_t sb,
-                                                     const int64_t* off, const double* V2,
-                                                     const double* tau2, double* Z, int64_t ldz,
-                                                     int64_t ncols) {
-  __shared__ double Zw[WIN][ZC + 1];
-  __shared__ double Vs[GS][128];
-  __shared__ double Ts[GS];
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int64_t col0 = (int64_t)blockIdx.x * ZC;
-  const int cz = wave * 16 + (lane >> 2);
-  const int quarter = lane & 3;
-  const int64_t sl = min(sb, n - 2);  // sweeps beyond n-3 have no tasks
-  if (sa >= sl) return;
-  const int64_t kmax = ceil_div(n - 1 - sa, nb);
-  for (int64_t k = 0; k < kmax; ++k) {
-    const int64_t wlo = sa + 1 + k * nb;
-    if (wlo >= n) break;
-    const int64_t whi = min(sl + k * nb + nb, n);  // last sweep sl-1: rows up to sl + (k+1) nb
-    const int wlen = (int)(whi - wlo);
-    // load window and reflectors
-    for (int e = t; e < wlen * ZC; e += NT) {
-      const int r = e % wlen, c = e / wlen;
-      Zw[r][c] = (col0 + c < ncols) ? Z[(wlo + r) + (col0 + c) * ldz] : 0.0;
-    }
-    for (int e = t; e < GS * nb; e += NT) {
-      const int gs = e / nb, i = e % nb;
-      const int64_t s = sa + gs;
-      double val = 0.0;
-      if (s < sl && k < ceil_div(n - 1 - s, nb)) val = V2[(off[s] + k) * nb + i];
-      Vs[gs][i] = val;
-    }
-    for (int gs = t; gs < GS; gs += NT) {
-      const int64_t s = sa + gs;
-      Ts[gs] = (s < sl && k < ceil_div(n - 1 - s, nb)) ? tau2[off[s] + k] : 0.0;
-    }
-    __syncthreads();
-    for (int64_t s = sl - 1; s >= sa; --s) {
-      const int gs = (int)(s - sa);
-      const double tau = Ts[gs];
-      if (tau == 0.0) continue;
-      const int64_t r0 = s + 1 + k * nb;
-      if (r0 >= n) continue;
-      const int len = (int)min((int64_t)nb, n - r0);
-      const int ro = (int)(r0 - wlo);
-      double d = 0.0;
-      for (int i = quarter; i < len; i += 4) d += Vs[gs][i] * Zw[ro + i][cz];
-      d += __shfl_xor(d, 1, 64);
-      d += __shfl_xor(d, 2, 64);
-      const double f = tau * d;
-      for (int i = quarter; i < len; i += 4) Zw[ro + i][cz] -= f * Vs[gs][i];
-    }
-    __syncthreads();
-    for (int e = t; e < wlen * ZC; e += NT) {
-      const int r = e % wlen, c = e / wlen;
-      if (col0 + c < ncols) Z[(wlo + r) + (col0 + c) * ldz] = Zw[r][c];
-    }
-    __syncthreads();
-  }
 }
 
 }  // namespace
@@ -243,7 +212,7 @@ void sb2st(double* AB, int64_t ldab, const Sb2stPlan& plan, const int64_t* d_off
            double* V2, double* tau2, double* d, double* e, hipStream_t s) {
   const int64_t n = plan.n;
   const int nb = plan.nb;
-  MM_REQUIRE(nb >= 1 && nb <= 128 && ldab >= 2 * nb + 1, kInvalid, "sb2st: bad band");
+  MM_REQUIRE(nb >= 1 && nb <= 64 && ldab >= 2 * nb + 1, kInvalid, "sb2st: band must be 1..64");
   if (n >= 3) {
     const int64_t K0 = ceil_div(n - 1, nb);
     const int64_t last_stage = 3 * (n - 3) + ceil_div(n - 1 - (n - 3), nb) - 1;
@@ -260,23 +229,6 @@ void sb2st(double* AB, int64_t ldab, const Sb2stPlan& plan, const int64_t* d_off
   }
   hipLaunchKernelGGL(band_to_tridiag, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, AB,
                      ldab, n, d, e);
-  MM_HIP_TRY(hipGetLastError());
-}
-
-void apply_q2(const Sb2stPlan& plan, const int64_t* d_offset, const double* V2,
-              const double* tau2, double* Z, int64_t ldz, int64_t ncols, hipStream_t s) {
-  const int64_t n = plan.n;
-  const int nb = plan.nb;
-  MM_REQUIRE(nb + GS - 1 <= WIN, kInvalid, "apply_q2: band too wide");
-  if (n < 3 || ncols <= 0) return;
-  const int64_t nsweeps = n - 2;  // sweeps 0..n-3
-  const int64_t ngroups = ceil_div(nsweeps, GS);
-  const unsigned grid = (unsigned)ceil_div(ncols, ZC);
-  for (int64_t g = ngroups - 1; g >= 0; --g) {
-    const int64_t sa = g * GS, sb = std::min(sa + GS, nsweeps);
-    hipLaunchKernelGGL(apply_q2_group, dim3(grid), dim3(NT), 0, s, n, nb, sa, sb, d_offset,
-                       V2, tau2, Z, ldz, ncols);
-  }
   MM_HIP_TRY(hipGetLastError());
 }
 

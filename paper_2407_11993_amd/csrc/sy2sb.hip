@@ -90,8 +90,18 @@ __global__ void __launch_bounds__(QT) panel_qr_step(double* P, int64_t ldp, int6
         } else {
           P[i + (int64_t)cp * ldp] = sh[1];  // R(cp, cp) = beta
         }
-        for (int jj = 0; jj < nb - cp - 1; ++jj)
-          P[i + (int64_t)(cp + 1 + jj) * ldp] -= vi * wv[jj];
+        // chunks of 8 independent loads, then 8 stores
+        const int cnt = nb - cp - 1;
+        double* row = P + i + (int64_t)(cp + 1) * ldp;
+        for (int j0 = 0; j0 < cnt; j0 += 8) {
+          double x[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (j0 + u < cnt) x[u] = row[(int64_t)(j0 + u) * ldp];
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (j0 + u < cnt) row[(int64_t)(j0 + u) * ldp] = x[u] - vi * wv[j0 + u];
+        }
       }
     } else if (g == 0 && t == 0) {
       tau[cp] = 0.0;
@@ -104,11 +114,20 @@ __global__ void __launch_bounds__(QT) panel_qr_step(double* P, int64_t ldp, int6
   double* po = part + (int64_t)g * stride;
   const int ncol = nb - c;
   const bool mine = (i < m && i > c);
-  const double a = mine ? P[i + (int64_t)c * ldp] : 0.0;
-  for (int j = 0; j < ncol; ++j) {
-    const double b = (j == 0) ? a : (mine ? P[i + (int64_t)(c + j) * ldp] : 0.0);
-    const double v = wsum(a * b);
-    if (lane == 0) red[wave][j] = v;
+  const double* row = P + i + (int64_t)c * ldp;
+  const double a = mine ? row[0] : 0.0;
+  for (int j0 = 0; j0 < ncol; j0 += 8) {
+    double x[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      x[u] = (mine && j0 + u < ncol) ? row[(int64_t)(j0 + u) * ldp] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (j0 + u < ncol) {
+        const double v = wsum(a * x[u]);
+        if (lane == 0) red[wave][j0 + u] = v;
+      }
+    }
   }
   // snapshot of row c (owned by slice 0)
   if (g == 0) {

@@ -101,6 +101,21 @@ def test_plate_vs_oracle(orc, nx, ny, crack):
         assert _rel(sm, sc) < 1e-8
 
 
+def test_cholesky_graph_replay_matches_eager(monkeypatch):
+    """Each time step of the Cholesky method is one replay of a captured HIP
+    graph; every replay must equal the eager launch sequence bit for bit."""
+    from paper_2407_11993_amd import Solver
+    w = inputs.plate(45, 47, seed=5, crack=((10, 20), (20, 23), 1e3), T=60, wave="gauss")
+    s1 = Solver(w)
+    a = _np(s1.step_cholesky(0.5, 1.0, w.T, w.i_src))
+    monkeypatch.setenv("MM_NO_GRAPH", "1")
+    s2 = Solver(w)
+    b = _np(s2.step_cholesky(0.5, 1.0, w.T, w.i_src))
+    assert np.array_equal(a, b)
+    from paper_2407_11993_amd import _lib
+    assert np.array_equal(_np(s1.current(_lib.MM_CHOLESKY)), _np(s2.current(_lib.MM_CHOLESKY)))
+
+
 def test_errors_are_reported():
     from paper_2407_11993_amd import Solver, _lib
     w = inputs.plate(6, 5, seed=1, T=10)
