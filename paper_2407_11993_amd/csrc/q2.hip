@@ -90,15 +90,25 @@ __global__ void __launch_bounds__(NT) q2_build_k(const Pair* pairs, int64_t p0, 
     if (t == 0) T[c][c] = tc;
     __syncthreads();
   }
-  // VT = V T, written with V (column-major, ld WR)
-  double* Vo = Vout + (int64_t)blockIdx.x * WR * GS;
-  double* VTo = VTout + (int64_t)blockIdx.x * WR * GS;
+  // VT = V T.  Both are written in the MFMA operand order of pass 2:
+  //   F1[(h*2 + x)*32 + kk][lane] = V(4kk + lane/16, 32h + 16x + lane%16)
+  //   F2[(wv*2 + x)*16 + kk][lane] = VT(32wv + 16x + lane%16, 4kk + lane/16)
+  // so that every operand load there is one contiguous 512-byte wave load.
+  __syncthreads();
+  double* F1 = Vout + (int64_t)blockIdx.x * WR * GS;
+  double* F2 = VTout + (int64_t)blockIdx.x * WR * GS;
   for (int e = t; e < WR * GS; e += NT) {
-    const int i = e % WR, j = e / WR;
+    const int ln = e & 63, f = e >> 6;          // f = (h*2 + x)*32 + kk
+    const int kk = f & 31, x = (f >> 5) & 1, h = f >> 6;
+    F1[e] = V[4 * kk + (ln >> 4)][32 * h + 16 * x + (ln & 15)];
+  }
+  for (int e = t; e < WR * GS; e += NT) {
+    const int ln = e & 63, f = e >> 6;          // f = (wv*2 + x)*16 + kk
+    const int kk = f & 15, x = (f >> 4) & 1, wv = f >> 5;
+    const int i = 32 * wv + 16 * x + (ln & 15), j = 4 * kk + (ln >> 4);
     double acc = 0.0;
     for (int q = 0; q <= j; ++q) acc += V[i][q] * T[q][j];
-    Vo[e] = V[i][j];
-    VTo[e] = acc;
+    F2[e] = acc;
   }
 }
 
@@ -117,8 +127,8 @@ __global__ void __launch_bounds__(NT) q2_apply_k(const Pair* pairs, int64_t p0, 
   for (int64_t p = p0; p < p1; ++p) {
     const Pair pr = pairs[p];
     const int wlen = (int)pr.wlen;
-    const double* V = Vall + (p - p0) * WR * GS;
-    const double* VT = VTall + (p - p0) * WR * GS;
+    const double* F1 = Vall + (p - p0) * WR * GS;
+    const double* F2 = VTall + (p - p0) * WR * GS;
     // stage the window (zero rows beyond wlen, zero columns beyond ncols)
     for (int e = t; e < WR * ZC; e += NT) {
       const int i = e % WR, j = e / WR;
@@ -127,16 +137,23 @@ __global__ void __launch_bounds__(NT) q2_apply_k(const Pair* pairs, int64_t p0, 
     __syncthreads();
     // W = V^T Zw  (64 x 64, K = 128): wave quadrant (wm, wn) of 32 x 32
     {
-      const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+      const int h = wave & 1, wm = h * 32, wn = (wave >> 1) * 32;
       v4d acc[2][2];
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int y = 0; y < 2; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
-      for (int k0 = 0; k0 < WR; k0 += 4) {
+      double fa[2][WR / 4];
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int kk = 0; kk < WR / 4; ++kk) fa[x][kk] = F1[((h * 2 + x) * 32 + kk) * 64 + lane];
+#pragma unroll
+      for (int kk = 0; kk < WR / 4; ++kk) {
+        const int k0 = 4 * kk;
         double av[2], bv[2];
 #pragma unroll
-        for (int x = 0; x < 2; ++x) av[x] = V[(k0 + lk) + (int64_t)(wm + 16 * x + lr) * WR];
+        for (int x = 0; x < 2; ++x) av[x] = fa[x][kk];
 #pragma unroll
         for (int y = 0; y < 2; ++y) bv[y] = Zw[k0 + lk][wn + 16 * y + lr];
 #pragma unroll
@@ -161,10 +178,17 @@ __global__ void __launch_bounds__(NT) q2_apply_k(const Pair* pairs, int64_t p0, 
       for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int y = 0; y < 4; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
-      for (int k0 = 0; k0 < GS; k0 += 4) {
+      double fb[2][GS / 4];
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int kk = 0; kk < GS / 4; ++kk) fb[x][kk] = F2[((wave * 2 + x) * 16 + kk) * 64 + lane];
+#pragma unroll
+      for (int kk = 0; kk < GS / 4; ++kk) {
+        const int k0 = 4 * kk;
         double av[2], bv[4];
 #pragma unroll
-        for (int x = 0; x < 2; ++x) av[x] = VT[(rm + 16 * x + lr) + (int64_t)(k0 + lk) * WR];
+        for (int x = 0; x < 2; ++x) av[x] = fb[x][kk];
 #pragma unroll
         for (int y = 0; y < 4; ++y) bv[y] = W[k0 + lk][16 * y + lr];
 #pragma unroll

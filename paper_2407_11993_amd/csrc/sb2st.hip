@@ -48,7 +48,8 @@ struct Band {
 // One task (s, k).  The three blocks it touches -- the block left of the
 // diagonal block (its first column is the one eliminated), the diagonal block
 // and the block below -- are staged in LDS with independent loads, updated
-// there, and written back.  nb <= 64.
+// there, and written back.  nb <= 64, so a block row or column fits one
+// wave: the four waves split the other dimension.
 __global__ void __launch_bounds__(NT) sb2st_stage(Band B, int64_t n, int nb, int64_t stage,
                                                   int64_t s_lo, const int64_t* off,
                                                   double* V2, double* tau2) {
@@ -65,123 +66,112 @@ __global__ void __launch_bounds__(NT) sb2st_stage(Band B, int64_t n, int nb, int
   const int ncl = (int)(((k == 0) ? s + 1 : r0) - c0);       // left block columns
   const int64_t rn0 = r0 + len;
   const int lenn = (int)max((int64_t)0, min((int64_t)nb, n - rn0));
+  const int64_t task = off[s] + k;
   __shared__ double Lb[64][65], Db[64][65], Bb[64][65];
-  __shared__ double v[64], p[64], w[64], sh[8];
-  __shared__ double s_tau, s_beta, s_scale;
+  __shared__ double v[64], p4[4][64], w_s[64];
+  __shared__ double s_tau, s_beta;
 
-  // ---- stage (column-major walks: consecutive threads, consecutive rows)
-  for (int e = t; e < len * ncl; e += NT) {
-    const int i = e % len, j = e / len;
-    Lb[i][j] = B.at(r0 + i, c0 + j);
-  }
-  for (int e = t; e < len * len; e += NT) {
-    const int i = e % len, j = e / len;
-    if (i >= j) {
-      const double a = B.at(r0 + i, r0 + j);
-      Db[i][j] = a;
-      Db[j][i] = a;
+  // ---- stage: every thread issues all of its loads before the first LDS
+  // store (addresses are clamped into the block, the value is selected), so
+  // the three blocks arrive in one memory latency
+  {
+    const int li = min(lane, len - 1), lb = min(lane, max(lenn, 1) - 1);
+    double rl[16], rd[16], rb[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int j = wave + 4 * q;
+      rl[q] = B.at(r0 + li, c0 + min(j, ncl - 1));
+      const int jd = min(j, len - 1);
+      rd[q] = B.sym(r0 + li, r0 + jd);
+      rb[q] = (lenn > 0) ? B.at(rn0 + lb, r0 + jd) : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int j = wave + 4 * q;
+      if (lane < len && j < ncl) Lb[lane][j] = rl[q];
+      if (lane < len && j < len) Db[lane][j] = rd[q];
+      if (lane < lenn && j < len) Bb[lane][j] = rb[q];
     }
   }
-  for (int e = t; e < lenn * len; e += NT) {
-    const int i = e % lenn, j = e / lenn;
-    Bb[i][j] = B.at(rn0 + i, r0 + j);
-  }
   __syncthreads();
-  // ---- Householder reflector of the eliminated column Lb(:, 0)
-  {
-    double x = (t >= 1 && t < len) ? Lb[t][0] : 0.0;
-    x = wsum(x * x);
-    if (lane == 0) sh[wave] = x;
-  }
-  __syncthreads();
-  if (t == 0) {
-    const double a0 = Lb[0][0];
-    const double sig2 = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  // ---- Householder reflector of the eliminated column Lb(:, 0) (wave 0)
+  if (wave == 0) {
+    const double x = (lane < len) ? Lb[lane][0] : 0.0;
+    const double sig2 = wsum((lane >= 1) ? x * x : 0.0);
+    const double a0 = __shfl(x, 0, 64);
     double tv = 0.0, beta = a0, scale = 0.0;
     if (sig2 > 0.0) {
       beta = -copysign(sqrt(a0 * a0 + sig2), a0);
       tv = (beta - a0) / beta;
       scale = 1.0 / (a0 - beta);
     }
-    s_tau = tv;
-    s_beta = beta;
-    s_scale = scale;
+    v[lane] = (lane == 0) ? 1.0 : ((lane < len) ? x * scale : 0.0);
+    if (lane == 0) {
+      s_tau = tv;
+      s_beta = beta;
+    }
+    if (lane < nb) V2[task * nb + lane] = (lane < len) ? v[lane] : 0.0;
+    if (lane == 0) tau2[task] = tv;
   }
   __syncthreads();
   const double tau = s_tau;
-  if (t < 64) v[t] = (t == 0) ? 1.0 : ((t < len) ? Lb[t][0] * s_scale : 0.0);
-  __syncthreads();
-  const int64_t task = off[s] + k;
-  if (t < nb) V2[task * nb + t] = (t < len) ? v[t] : 0.0;
-  if (t == 0) tau2[task] = tau;
   if (tau == 0.0) return;  // H = I: nothing changes (uniform branch)
+  const double vl = v[lane];
 
-  // ---- left application: Lb(:, j) -= tau v (v^T Lb(:, j)), j >= 1;
-  //      the eliminated column becomes (beta, 0, ..., 0)
-  {
-    const int j = t >> 2, part = t & 3;  // 4 threads per column, 16 rows each
-    if (j >= 1 && j < ncl) {
-      double d = 0.0;
-      for (int i = part; i < len; i += 4) d += v[i] * Lb[i][j];
-      d += __shfl_xor(d, 1, 64);
-      d += __shfl_xor(d, 2, 64);
-      const double f = tau * d;
-      for (int i = part; i < len; i += 4) Lb[i][j] -= f * v[i];
-    }
-    if (t < len) Lb[t][0] = (t == 0) ? s_beta : 0.0;
+  // ---- left application: Lb(:, j) -= tau v (v^T Lb(:, j)), j >= 1; lane =
+  //      column, each wave sums a quarter of the rows; the eliminated column
+  //      becomes (beta, 0, ..., 0)
+  if (ncl > 1) {
+    const int i0 = 16 * wave, i1 = min(i0 + 16, len);
+    double acc = 0.0;
+    if (lane < ncl)
+      for (int i = i0; i < i1; ++i) acc += v[i] * Lb[i][lane];
+    p4[wave][lane] = acc;
+    __syncthreads();
+    const double d = (p4[0][lane] + p4[1][lane]) + (p4[2][lane] + p4[3][lane]);
+    if (lane >= 1 && lane < ncl)
+      for (int i = i0; i < i1; ++i) Lb[i][lane] -= tau * v[i] * d;
+    __syncthreads();  // p4 is reused below
   }
+  if (wave == 0 && lane < len) Lb[lane][0] = (lane == 0) ? s_beta : 0.0;
   // ---- two-sided on D: p = tau D v, w = p - tau/2 (p^T v) v, D -= v w^T + w v^T
   {
-    const int i = t >> 2, part = t & 3;
     double acc = 0.0;
-    if (i < len)
-      for (int j = part; j < len; j += 4) acc += Db[i][j] * v[j];
-    acc += __shfl_xor(acc, 1, 64);
-    acc += __shfl_xor(acc, 2, 64);
-    if (part == 0 && i < 64) p[i] = (i < len) ? tau * acc : 0.0;
+    if (lane < len)
+      for (int j = wave; j < len; j += 4) acc += Db[lane][j] * v[j];
+    p4[wave][lane] = acc;
   }
   __syncthreads();
-  {
-    double x = (t < len) ? p[t] * v[t] : 0.0;
-    x = wsum(x);
-    if (lane == 0) sh[4 + wave] = x;
-  }
+  const double pl = (lane < len) ? tau * ((p4[0][lane] + p4[1][lane]) + (p4[2][lane] + p4[3][lane]))
+                                 : 0.0;
+  const double pv = wsum(pl * vl);
+  const double wl = pl - 0.5 * tau * pv * vl;  // w for row `lane`
+  // every wave needs w_j for its columns j: publish w in LDS
+  __syncthreads();  // all reads of p4 above are done
+  if (wave == 0) w_s[lane] = wl;
   __syncthreads();
-  {
-    const double pv = (sh[4] + sh[5]) + (sh[6] + sh[7]);
-    if (t < 64) w[t] = (t < len) ? p[t] - 0.5 * tau * pv * v[t] : 0.0;
-  }
-  __syncthreads();
-  for (int e = t; e < len * len; e += NT) {
-    const int i = e % len, j = e / len;
-    if (i >= j) Db[i][j] -= v[i] * w[j] + w[i] * v[j];
-  }
+  for (int j = wave; j < len; j += 4)
+    if (lane < len && lane >= j) Db[lane][j] -= vl * w_s[j] + wl * v[j];
   // ---- right application to the block below: Bb -= tau (Bb v) v^T
   if (lenn > 0) {
-    const int i = t >> 2, part = t & 3;
     double acc = 0.0;
-    if (i < lenn)
-      for (int j = part; j < len; j += 4) acc += Bb[i][j] * v[j];
-    acc += __shfl_xor(acc, 1, 64);
-    acc += __shfl_xor(acc, 2, 64);
-    const double f = tau * acc;
-    if (i < lenn)
-      for (int j = part; j < len; j += 4) Bb[i][j] -= f * v[j];
+    if (lane < lenn)
+      for (int j = wave; j < len; j += 4) acc += Bb[lane][j] * v[j];
+    p4[wave][lane] = acc;  // p4 was last read before the barrier above
+    __syncthreads();
+    const double q = (lane < lenn) ? (p4[0][lane] + p4[1][lane]) + (p4[2][lane] + p4[3][lane])
+                                   : 0.0;
+    for (int j = wave; j < len; j += 4)
+      if (lane < lenn) Bb[lane][j] -= tau * q * v[j];
   }
   __syncthreads();
   // ---- write back
-  for (int e = t; e < len * ncl; e += NT) {
-    const int i = e % len, j = e / len;
-    B.at(r0 + i, c0 + j) = Lb[i][j];
-  }
-  for (int e = t; e < len * len; e += NT) {
-    const int i = e % len, j = e / len;
-    if (i >= j) B.at(r0 + i, r0 + j) = Db[i][j];
-  }
-  for (int e = t; e < lenn * len; e += NT) {
-    const int i = e % lenn, j = e / lenn;
-    B.at(rn0 + i, r0 + j) = Bb[i][j];
-  }
+  for (int j = wave; j < ncl; j += 4)
+    if (lane < len) B.at(r0 + lane, c0 + j) = Lb[lane][j];
+  for (int j = wave; j < len; j += 4)
+    if (lane < len && lane >= j) B.at(r0 + lane, r0 + j) = Db[lane][j];
+  for (int j = wave; j < len; j += 4)
+    if (lane < lenn) B.at(rn0 + lane, r0 + j) = Bb[lane][j];
 }
 
 __global__ void band_to_tridiag(const double* AB, int64_t ld, int64_t n, double* d, double* e) {
