@@ -115,99 +115,143 @@ __global__ void __launch_bounds__(NT) q2_build_k(const Pair* pairs, int64_t p0, 
 // ---------------------------------------------------------------------------
 // pass 2: apply the blocks of pairs [p0, p1) to 64 columns of Z per workgroup
 // ---------------------------------------------------------------------------
+// Zero structure used (valid for any nb <= 64): column gs of V is non-zero
+// only on window rows [gs, gs + 64), so W = V^T Zw for V columns
+// [16x, 16x + 16) needs window rows [16x, 16x + 80) only; VT = V T has row i
+// non-zero only in columns j >= i - 63, so row block r of VT (rows
+// [16r, 16r + 16)) needs k-steps kk >= ks(r) = max(0, 4r - 16).
+// Consecutive blocks k, k + 1 of one group (nb = 64) have windows offset by
+// 64 rows: the lower half of block k's window stays in LDS as the upper half
+// of block k + 1's, and only 64 new rows are loaded, prefetched into
+// registers while the matrix cores work on block k.
+__device__ constexpr int ks_of(int r) { return r < 4 ? 0 : 4 * r - 16; }
+__device__ constexpr int koff_of(int r) {  // compact fragment offset of row block r
+  return r <= 5 ? 16 * r : (r == 6 ? 92 : 100);
+}
+constexpr int NVT = 104;  // non-zero VT fragments (16 x 4 each)
+
 __global__ void __launch_bounds__(NT) q2_apply_k(const Pair* pairs, int64_t p0, int64_t p1,
                                                  const double* Vall, const double* VTall,
-                                                 double* Z, int64_t ldz, int64_t ncols) {
-  __shared__ double Zw[WR][ZC + LP];
+                                                 double* Z, int64_t ldz, int64_t n,
+                                                 int64_t ncols) {
+  __shared__ double Zh[2][64][ZC + LP];  // window halves; Zh[a] holds rows [0, 64)
   __shared__ double W[GS][ZC + LP];
+  __shared__ double VTs[NVT * 64];       // compact VT fragments of the current block
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   const int64_t col0 = (int64_t)blockIdx.x * ZC;
   const int ncl = (int)min((int64_t)ZC, ncols - col0);
+  int a = 0;
+  bool resident = false;  // the window's upper half is already in LDS
   for (int64_t p = p0; p < p1; ++p) {
     const Pair pr = pairs[p];
-    const int wlen = (int)pr.wlen;
+    bool cont = false;
+    if (p + 1 < p1) {
+      const Pair nx = pairs[p + 1];
+      cont = nx.sa == pr.sa && nx.k == pr.k + 1 && nx.wlo == pr.wlo + 64;
+    }
     const double* F1 = Vall + (p - p0) * WR * GS;
     const double* F2 = VTall + (p - p0) * WR * GS;
-    // stage the window (zero rows beyond wlen, zero columns beyond ncols)
-    for (int e = t; e < WR * ZC; e += NT) {
-      const int i = e % WR, j = e / WR;
-      Zw[i][j] = (i < wlen && j < ncl) ? Z[(pr.wlo + i) + (col0 + j) * ldz] : 0.0;
+    // issue this block's VT fragments (26 per thread) and the next block's
+    // new rows (16 per thread)
+    double vt[NVT / 4];
+#pragma unroll
+    for (int u = 0; u < NVT / 4; ++u) {
+      const int e = t + NT * u, fc = e >> 6;
+      const int g = fc < 80 ? fc : fc < 92 ? fc + 4 : fc < 100 ? fc + 12 : fc + 24;
+      vt[u] = F2[g * 64 + (e & 63)];
     }
-    __syncthreads();
-    // W = V^T Zw  (64 x 64, K = 128): wave quadrant (wm, wn) of 32 x 32
-    {
-      const int h = wave & 1, wm = h * 32, wn = (wave >> 1) * 32;
-      v4d acc[2][2];
+    double zn[16];
+    if (cont) {
 #pragma unroll
-      for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < 2; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
-      double fa[2][WR / 4];
-#pragma unroll
-      for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int kk = 0; kk < WR / 4; ++kk) fa[x][kk] = F1[((h * 2 + x) * 32 + kk) * 64 + lane];
-#pragma unroll
-      for (int kk = 0; kk < WR / 4; ++kk) {
-        const int k0 = 4 * kk;
-        double av[2], bv[2];
-#pragma unroll
-        for (int x = 0; x < 2; ++x) av[x] = fa[x][kk];
-#pragma unroll
-        for (int y = 0; y < 2; ++y) bv[y] = Zw[k0 + lk][wn + 16 * y + lr];
-#pragma unroll
-        for (int x = 0; x < 2; ++x)
-#pragma unroll
-          for (int y = 0; y < 2; ++y)
-            acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[y], av[x], acc[x][y], 0, 0, 0);
+      for (int u = 0; u < 16; ++u) {
+        const int e = t + NT * u, i = e & 63, j = e >> 6;
+        const int64_t row = pr.wlo + 128 + i;
+        zn[u] = (row < n && j < ncl) ? Z[row + (col0 + j) * ldz] : 0.0;
       }
-#pragma unroll
-      for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < 2; ++y)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) W[wm + 16 * x + lr][wn + 16 * y + lk + 4 * q] = acc[x][y][q];
     }
-    __syncthreads();
-    // Zw -= VT W  (128 x 64, K = 64): wave owns rows [32 wave, 32 wave + 32)
-    {
-      const int rm = wave * 32;
-      v4d acc[2][4];
-#pragma unroll
-      for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
-      double fb[2][GS / 4];
-#pragma unroll
-      for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int kk = 0; kk < GS / 4; ++kk) fb[x][kk] = F2[((wave * 2 + x) * 16 + kk) * 64 + lane];
-#pragma unroll
-      for (int kk = 0; kk < GS / 4; ++kk) {
-        const int k0 = 4 * kk;
-        double av[2], bv[4];
-#pragma unroll
-        for (int x = 0; x < 2; ++x) av[x] = fb[x][kk];
-#pragma unroll
-        for (int y = 0; y < 4; ++y) bv[y] = W[k0 + lk][16 * y + lr];
-#pragma unroll
-        for (int x = 0; x < 2; ++x)
-#pragma unroll
-          for (int y = 0; y < 4; ++y)
-            acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[y], av[x], acc[x][y], 0, 0, 0);
+    if (!resident) {
+      // the whole window (rows beyond n and columns beyond ncols are zero)
+#pragma unroll 4
+      for (int u = 0; u < 32; ++u) {
+        const int e = t + NT * u, i = e & 127, j = e >> 7;
+        const int64_t row = pr.wlo + i;
+        Zh[a ^ (i >> 6)][i & 63][j] = (row < n && j < ncl) ? Z[row + (col0 + j) * ldz] : 0.0;
       }
+      __syncthreads();
+    }
+    // ---- W = V^T Zw: wave owns W rows [16 wave, 16 wave + 16), k-steps
+    //      kk = 4 wave + s (window rows 16 wave + 4 s + lk), s < 20
+    {
+      double fa[20];
 #pragma unroll
-      for (int x = 0; x < 2; ++x)
+      for (int s2 = 0; s2 < 20; ++s2) fa[s2] = F1[(wave * 32 + 4 * wave + s2) * 64 + lane];
+      v4d acc[4];
+#pragma unroll
+      for (int y = 0; y < 4; ++y) acc[y] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s2 = 0; s2 < 20; ++s2) {
+        const int i = 16 * wave + 4 * s2 + lk;
+        const double* zr = &Zh[a ^ (i >> 6)][i & 63][0];
+        double bv[4];
+#pragma unroll
+        for (int y = 0; y < 4; ++y) bv[y] = zr[16 * y + lr];
 #pragma unroll
         for (int y = 0; y < 4; ++y)
+          acc[y] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[y], fa[s2], acc[y], 0, 0, 0);
+      }
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int i = rm + 16 * x + lr, j = 16 * y + lk + 4 * q;
-            if (i < wlen && j < ncl) Z[(pr.wlo + i) + (col0 + j) * ldz] = Zw[i][j] - acc[x][y][q];
+      for (int y = 0; y < 4; ++y)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) W[16 * wave + lr][16 * y + lk + 4 * q] = acc[y][q];
+    }
+#pragma unroll
+    for (int u = 0; u < NVT / 4; ++u) VTs[t + NT * u] = vt[u];
+    __syncthreads();
+    // ---- Zw -= VT W: wave owns columns [16 wave, 16 wave + 16), all rows
+    {
+      double wb[16];
+#pragma unroll
+      for (int kk = 0; kk < 16; ++kk) wb[kk] = W[4 * kk + lk][16 * wave + lr];
+      v4d acc[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) acc[r] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kk = 0; kk < 16; ++kk)
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+          if (kk >= ks_of(r))
+            acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                wb[kk], VTs[(koff_of(r) + kk - ks_of(r)) * 64 + lane], acc[r], 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int i = 16 * r + lr;
+        double* zr = &Zh[a ^ (r >> 2)][i & 63][0];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int j = 16 * wave + lk + 4 * q;
+          const double zv = zr[j] - acc[r][q];
+          if (cont && r >= 4) {
+            zr[j] = zv;
+          } else {
+            const int64_t row = pr.wlo + i;
+            if (row < n && j < ncl) Z[row + (col0 + j) * ldz] = zv;
           }
+        }
+      }
     }
     __syncthreads();
+    if (cont) {
+      // the lower half becomes the upper half; the new rows fill the other
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int e = t + NT * u;
+        Zh[a][e & 63][e >> 6] = zn[u];
+      }
+      a ^= 1;
+      __syncthreads();
+    }
+    resident = cont;
   }
 }
 
@@ -229,7 +273,7 @@ void apply_q2(const Sb2stPlan& plan, const int64_t* d_offset, const double* V2,
     for (int64_t k = 0; k < kmax; ++k) {
       const int64_t wlo = sa + 1 + k * nb;
       if (wlo >= n) break;
-      const int64_t whi = std::min(sl + (k + 1) * nb, n);
+      const int64_t whi = std::min(wlo + WR, n);
       pairs.push_back(Pair{sa, sl, k, wlo, whi - wlo});
     }
   }
@@ -250,7 +294,7 @@ void apply_q2(const Sb2stPlan& plan, const int64_t* d_offset, const double* V2,
     hipLaunchKernelGGL(q2_build_k, dim3((unsigned)(p1 - p0)), dim3(NT), 0, s, d_pairs, p0, n, nb,
                        d_offset, V2, tau2, Vb, VTb);
     hipLaunchKernelGGL(q2_apply_k, dim3(grid), dim3(NT), 0, s, d_pairs, p0, p1, Vb, VTb, Z, ldz,
-                       ncols);
+                       n, ncols);
     MM_HIP_TRY(hipGetLastError());
   }
   // the host vector must outlive the copy

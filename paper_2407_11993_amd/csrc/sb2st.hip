@@ -20,20 +20,30 @@ namespace {
 
 constexpr int NT = 256;
 
-__device__ __forceinline__ double wsum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+// Wave-wide sum, every lane gets the result: sums over quads and rows of 16
+// lanes by DPP moves (xor 1, xor 2, half-row mirror, row mirror), then the
+// four row sums are read with readlane.
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+  const int2 b = __builtin_bit_cast(int2, v);
+  int2 r;
+  r.x = __builtin_amdgcn_update_dpp(0, b.x, CTRL, 0xF, 0xF, false);
+  r.y = __builtin_amdgcn_update_dpp(0, b.y, CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, r);
 }
-
-// Block-wide sum (NT threads); every thread gets the result.
-__device__ double block_sum(double v, double* sh) {
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  v = wsum(v);
-  __syncthreads();
-  if (lane == 0) sh[wave] = v;
-  __syncthreads();
-  return (sh[0] + sh[1]) + (sh[2] + sh[3]);
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const int2 b = __builtin_bit_cast(int2, v);
+  int2 r;
+  r.x = __builtin_amdgcn_readlane(b.x, l);
+  r.y = __builtin_amdgcn_readlane(b.y, l);
+  return __builtin_bit_cast(double, r);
+}
+__device__ __forceinline__ double wsum(double v) {
+  v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp<0x141>(v);  // row_half_mirror
+  v += dpp<0x140>(v);  // row_mirror
+  return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
 }
 
 struct Band {
@@ -47,23 +57,24 @@ struct Band {
 
 // One task (s, k).  The three blocks it touches -- the block left of the
 // diagonal block (its first column is the one eliminated), the diagonal block
-// and the block below -- are staged in LDS with independent loads, updated
-// there, and written back.  nb <= 64, so a block row or column fits one
-// wave: the four waves split the other dimension.
-__global__ void __launch_bounds__(NT) sb2st_stage(Band B, int64_t n, int nb, int64_t stage,
-                                                  int64_t s_lo, const int64_t* off,
-                                                  double* V2, double* tau2) {
-  const int64_t s = s_lo + blockIdx.x;
+// and the block below -- are staged in LDS as zero-padded 64 x 64 tiles with
+// independent loads, updated there, and written back.  nb <= 64, so a block
+// row or column fits one wave and the four waves split the other dimension;
+// the zero padding lets every loop run a fixed 16 iterations, unrolled.
+__global__ void __launch_bounds__(NT) sb2st_stage(Band B, int n, int nb, int stage, int s_lo,
+                                                  const int64_t* off, double* V2,
+                                                  double* tau2) {
+  const int s = s_lo + (int)blockIdx.x;
   if (s > n - 3) return;
-  const int64_t k = stage - 3 * s;
+  const int k = stage - 3 * s;
   if (k < 0) return;
-  const int64_t Ks = ceil_div(n - 1 - s, nb);
+  const int Ks = (n - 2 - s + nb) / nb;  // ceil((n - 1 - s) / nb)
   if (k >= Ks) return;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int64_t r0 = s + 1 + k * nb;
+  const int64_t r0 = s + 1 + (int64_t)k * nb;
   const int len = (int)min((int64_t)nb, n - r0);
-  const int64_t c0 = (k == 0) ? s : s + 1 + (k - 1) * nb;  // column to eliminate
-  const int ncl = (int)(((k == 0) ? s + 1 : r0) - c0);       // left block columns
+  const int64_t c0 = (k == 0) ? s : s + 1 + (int64_t)(k - 1) * nb;  // column to eliminate
+  const int ncl = (int)(((k == 0) ? s + 1 : r0) - c0);                // left block columns
   const int64_t rn0 = r0 + len;
   const int lenn = (int)max((int64_t)0, min((int64_t)nb, n - rn0));
   const int64_t task = off[s] + k;
@@ -71,9 +82,8 @@ __global__ void __launch_bounds__(NT) sb2st_stage(Band B, int64_t n, int nb, int
   __shared__ double v[64], p4[4][64], w_s[64];
   __shared__ double s_tau, s_beta;
 
-  // ---- stage: every thread issues all of its loads before the first LDS
-  // store (addresses are clamped into the block, the value is selected), so
-  // the three blocks arrive in one memory latency
+  // ---- stage: all loads are issued before the first LDS store (addresses
+  // clamped into the block, values selected)
   {
     const int li = min(lane, len - 1), lb = min(lane, max(lenn, 1) - 1);
     double rl[16], rd[16], rb[16];
@@ -88,29 +98,30 @@ __global__ void __launch_bounds__(NT) sb2st_stage(Band B, int64_t n, int nb, int
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int j = wave + 4 * q;
-      if (lane < len && j < ncl) Lb[lane][j] = rl[q];
-      if (lane < len && j < len) Db[lane][j] = rd[q];
-      if (lane < lenn && j < len) Bb[lane][j] = rb[q];
+      Lb[lane][j] = (lane < len && j < ncl) ? rl[q] : 0.0;
+      Db[lane][j] = (lane < len && j < len) ? rd[q] : 0.0;
+      Bb[lane][j] = (lane < lenn && j < len) ? rb[q] : 0.0;
     }
   }
   __syncthreads();
   // ---- Householder reflector of the eliminated column Lb(:, 0) (wave 0)
   if (wave == 0) {
-    const double x = (lane < len) ? Lb[lane][0] : 0.0;
+    const double x = Lb[lane][0];
     const double sig2 = wsum((lane >= 1) ? x * x : 0.0);
-    const double a0 = __shfl(x, 0, 64);
+    const double a0 = lane_value(x, 0);
     double tv = 0.0, beta = a0, scale = 0.0;
     if (sig2 > 0.0) {
       beta = -copysign(sqrt(a0 * a0 + sig2), a0);
       tv = (beta - a0) / beta;
       scale = 1.0 / (a0 - beta);
     }
-    v[lane] = (lane == 0) ? 1.0 : ((lane < len) ? x * scale : 0.0);
+    const double vv = (lane == 0) ? 1.0 : x * scale;  // zero beyond len
+    v[lane] = vv;
     if (lane == 0) {
       s_tau = tv;
       s_beta = beta;
     }
-    if (lane < nb) V2[task * nb + lane] = (lane < len) ? v[lane] : 0.0;
+    if (lane < nb) V2[task * nb + lane] = vv;
     if (lane == 0) tau2[task] = tv;
   }
   __syncthreads();
@@ -122,56 +133,68 @@ __global__ void __launch_bounds__(NT) sb2st_stage(Band B, int64_t n, int nb, int
   //      column, each wave sums a quarter of the rows; the eliminated column
   //      becomes (beta, 0, ..., 0)
   if (ncl > 1) {
-    const int i0 = 16 * wave, i1 = min(i0 + 16, len);
+    const int i0 = 16 * wave;
     double acc = 0.0;
-    if (lane < ncl)
-      for (int i = i0; i < i1; ++i) acc += v[i] * Lb[i][lane];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc += v[i0 + q] * Lb[i0 + q][lane];
     p4[wave][lane] = acc;
     __syncthreads();
-    const double d = (p4[0][lane] + p4[1][lane]) + (p4[2][lane] + p4[3][lane]);
-    if (lane >= 1 && lane < ncl)
-      for (int i = i0; i < i1; ++i) Lb[i][lane] -= tau * v[i] * d;
+    const double d = (lane >= 1) ? tau * ((p4[0][lane] + p4[1][lane]) + (p4[2][lane] + p4[3][lane]))
+                                 : 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) Lb[i0 + q][lane] -= v[i0 + q] * d;
     __syncthreads();  // p4 is reused below
   }
-  if (wave == 0 && lane < len) Lb[lane][0] = (lane == 0) ? s_beta : 0.0;
+  if (wave == 0) Lb[lane][0] = (lane == 0) ? s_beta : 0.0;
   // ---- two-sided on D: p = tau D v, w = p - tau/2 (p^T v) v, D -= v w^T + w v^T
   {
     double acc = 0.0;
-    if (lane < len)
-      for (int j = wave; j < len; j += 4) acc += Db[lane][j] * v[j];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc += Db[lane][wave + 4 * q] * v[wave + 4 * q];
     p4[wave][lane] = acc;
   }
   __syncthreads();
-  const double pl = (lane < len) ? tau * ((p4[0][lane] + p4[1][lane]) + (p4[2][lane] + p4[3][lane]))
-                                 : 0.0;
+  const double pl = tau * ((p4[0][lane] + p4[1][lane]) + (p4[2][lane] + p4[3][lane]));
   const double pv = wsum(pl * vl);
   const double wl = pl - 0.5 * tau * pv * vl;  // w for row `lane`
-  // every wave needs w_j for its columns j: publish w in LDS
   __syncthreads();  // all reads of p4 above are done
   if (wave == 0) w_s[lane] = wl;
   __syncthreads();
-  for (int j = wave; j < len; j += 4)
-    if (lane < len && lane >= j) Db[lane][j] -= vl * w_s[j] + wl * v[j];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int j = wave + 4 * q;
+    Db[lane][j] -= vl * w_s[j] + wl * v[j];
+  }
   // ---- right application to the block below: Bb -= tau (Bb v) v^T
   if (lenn > 0) {
     double acc = 0.0;
-    if (lane < lenn)
-      for (int j = wave; j < len; j += 4) acc += Bb[lane][j] * v[j];
-    p4[wave][lane] = acc;  // p4 was last read before the barrier above
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc += Bb[lane][wave + 4 * q] * v[wave + 4 * q];
+    p4[wave][lane] = acc;  // p4 was last read before the barriers above
     __syncthreads();
-    const double q = (lane < lenn) ? (p4[0][lane] + p4[1][lane]) + (p4[2][lane] + p4[3][lane])
-                                   : 0.0;
-    for (int j = wave; j < len; j += 4)
-      if (lane < lenn) Bb[lane][j] -= tau * q * v[j];
+    const double tq = tau * ((p4[0][lane] + p4[1][lane]) + (p4[2][lane] + p4[3][lane]));
+#pragma unroll
+    for (int q = 0; q < 16; ++q) Bb[lane][wave + 4 * q] -= tq * v[wave + 4 * q];
   }
   __syncthreads();
-  // ---- write back
-  for (int j = wave; j < ncl; j += 4)
-    if (lane < len) B.at(r0 + lane, c0 + j) = Lb[lane][j];
-  for (int j = wave; j < len; j += 4)
-    if (lane < len && lane >= j) B.at(r0 + lane, r0 + j) = Db[lane][j];
-  for (int j = wave; j < len; j += 4)
-    if (lane < lenn) B.at(rn0 + lane, r0 + j) = Bb[lane][j];
+  // ---- write back: read every value first, then store
+  {
+    double rl[16], rd[16], rb[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int j = wave + 4 * q;
+      rl[q] = Lb[lane][j];
+      rd[q] = Db[lane][j];
+      rb[q] = Bb[lane][j];
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int j = wave + 4 * q;
+      if (lane < len && j < ncl) B.at(r0 + lane, c0 + j) = rl[q];
+      if (lane < len && j <= lane) B.at(r0 + lane, r0 + j) = rd[q];
+      if (lane < lenn && j < len) B.at(rn0 + lane, r0 + j) = rb[q];
+    }
+  }
 }
 
 __global__ void band_to_tridiag(const double* AB, int64_t ld, int64_t n, double* d, double* e) {
@@ -203,6 +226,7 @@ void sb2st(double* AB, int64_t ldab, const Sb2stPlan& plan, const int64_t* d_off
   const int64_t n = plan.n;
   const int nb = plan.nb;
   MM_REQUIRE(nb >= 1 && nb <= 64 && ldab >= 2 * nb + 1, kInvalid, "sb2st: band must be 1..64");
+  MM_REQUIRE(n < (int64_t)1 << 29, kInvalid, "sb2st: order too large");
   if (n >= 3) {
     const int64_t K0 = ceil_div(n - 1, nb);
     const int64_t last_stage = 3 * (n - 3) + ceil_div(n - 1 - (n - 3), nb) - 1;
@@ -212,8 +236,8 @@ void sb2st(double* AB, int64_t ldab, const Sb2stPlan& plan, const int64_t* d_off
       int64_t s_lo = st - (K0 - 1) <= 0 ? 0 : ceil_div(st - (K0 - 1), 3);
       int64_t s_hi = std::min(st / 3, n - 3);
       if (s_hi < s_lo) continue;
-      hipLaunchKernelGGL(sb2st_stage, dim3((unsigned)(s_hi - s_lo + 1)), dim3(NT), 0, s, B, n,
-                         nb, st, s_lo, d_offset, V2, tau2);
+      hipLaunchKernelGGL(sb2st_stage, dim3((unsigned)(s_hi - s_lo + 1)), dim3(NT), 0, s, B,
+                         (int)n, nb, (int)st, (int)s_lo, d_offset, V2, tau2);
     }
     MM_HIP_TRY(hipGetLastError());
   }

@@ -162,6 +162,15 @@ def test_syevd(K, n):
     _check_eig(A, _np(w), _np(Z))
 
 
+@pytest.mark.parametrize("n,nb", [(200, 16), (230, 40), (700, 64)])
+def test_syevd_band_widths(K, n, nb):
+    # nb < 64 takes the back-transform path without window reuse; n = 700
+    # chains many consecutive blocks per group of 64 sweeps
+    A = _sym(n, 5 * n + nb)
+    w, Z = K.syevd(A, nb=nb)
+    _check_eig(A, _np(w), _np(Z))
+
+
 def test_syevd_clustered(K):
     n = 256
     rng = np.random.default_rng(3)
