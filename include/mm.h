@@ -153,12 +153,13 @@ mm_status mmk_dpotrf(int64_t n, double* A, int64_t lda, int64_t* info,
 /* A <- A^{-1} for lower-triangular A. */
 mm_status mmk_dtrtri(int64_t n, double* A, int64_t lda, void* stream);
 
-/* Band reduction C = Q1 B Q1^T: A (full symmetric) is overwritten; AB
- * (ldab x n, ldab >= 2 nb + 1) receives the lower band, AB(d, j) = B(j+d, j). */
+/* Band reduction C = Q1 B Q1^T (1 <= nb <= 64): A (full symmetric) is
+ * overwritten; AB (ldab x n, ldab >= 2 nb + 1) receives the lower band,
+ * AB(d, j) = B(j+d, j). */
 mm_status mmk_dsy2sb(int64_t n, double* A, int64_t lda, int32_t nb, double* AB,
                      int64_t ldab, void* stream);
 
-/* Band to tridiagonal by bulge chasing: d (n), e (n-1). */
+/* Band to tridiagonal by bulge chasing (1 <= nb <= 64): d (n), e (n-1). */
 mm_status mmk_dsb2st(int64_t n, int32_t nb, double* AB, int64_t ldab, double* d,
                      double* e, void* stream);
 

@@ -521,7 +521,7 @@ mm_status mmk_dtrtri(int64_t n, double* A, int64_t lda, void* stream) {
 mm_status mmk_dsy2sb(int64_t n, double* A, int64_t lda, int32_t nb, double* AB, int64_t ldab,
                      void* stream) {
   return guarded(nullptr, [&] {
-    MM_REQUIRE(n >= 1 && nb >= 1 && nb <= 128 && ldab >= 2 * nb + 1, kInvalid, "sizes");
+    MM_REQUIRE(n >= 1 && nb >= 1 && nb <= 64 && ldab >= 2 * nb + 1, kInvalid, "sizes");
     hipStream_t s = (hipStream_t)stream;
     Dev ws, tau, T;
     const int64_t np = std::max<int64_t>(1, sy2sb_npanels(n, nb));
@@ -537,7 +537,7 @@ mm_status mmk_dsy2sb(int64_t n, double* A, int64_t lda, int32_t nb, double* AB, 
 mm_status mmk_dsb2st(int64_t n, int32_t nb, double* AB, int64_t ldab, double* d, double* e,
                      void* stream) {
   return guarded(nullptr, [&] {
-    MM_REQUIRE(n >= 1 && nb >= 1 && nb <= 128 && ldab >= 2 * nb + 1, kInvalid, "sizes");
+    MM_REQUIRE(n >= 1 && nb >= 1 && nb <= 64 && ldab >= 2 * nb + 1, kInvalid, "sizes");
     hipStream_t s = (hipStream_t)stream;
     Sb2stPlan plan = sb2st_plan(n, nb);
     Dev off, V2, tau2;

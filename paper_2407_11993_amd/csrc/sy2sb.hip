@@ -29,114 +29,125 @@ constexpr int QROWS = 256;  // panel rows per workgroup
 // launch c-1 wrote while writing its own):
 //   part[buf][g][0]      : squared norm of column c over slice g, rows > c
 //   part[buf][g][1 + jj] : dot(column c, column c+1+jj) over slice g, rows > c
-//   rowv[buf][jj]        : A(c, c+jj) as it was when the partials were taken
-//                          (a snapshot, because slice 0 updates row c while the
-//                          other slices still need its old value)
-// Each thread owns exactly one panel row (QROWS == QT).
-__device__ __forceinline__ double wsum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
+//   rowv[buf][jj]        : A(c, c+jj) after the launch's update (a snapshot,
+//                          because slice 0 updates row c while the other
+//                          slices still need the value of the previous one)
+// Each thread owns exactly one panel row (QROWS == QT) and holds the columns
+// of that row it works on in registers: every global load of a launch is
+// issued at its start, so a launch costs about one memory latency.
+constexpr int MAXNB = 64;
 
 __global__ void __launch_bounds__(QT) panel_qr_step(double* P, int64_t ldp, int64_t m,
                                                     int nb, int c, double* scratch,
                                                     int G, double* tau) {
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int t = threadIdx.x;
   const int g = blockIdx.x;
   const int64_t i = (int64_t)g * QROWS + t;  // this thread's panel row
   const int stride = nb + 1;
   const int64_t per_buf = (int64_t)G * stride + nb;
-  __shared__ double red[4][129];
-  __shared__ double tot[129];
-  __shared__ double wv[129];
+  __shared__ double red2[MAXNB][QT + 1];  // products, column-major by row
+  __shared__ double red[4][MAXNB + 1];
+  __shared__ double tot[MAXNB + 1];
+  __shared__ double wv[MAXNB + 1];
   __shared__ double sh[3];
-  // ---- finish column cp = c-1 ------------------------------------------------
-  if (c >= 1) {
-    const int cp = c - 1;
+  const int b0 = c >= 1 ? c - 1 : 0;  // first column held in registers
+  const int nx = nb - b0;             // columns held
+  // ---- issue every load: the row, the previous column's partials, its row
+  double x[MAXNB];
+  const bool row_ok = i < m;
+  const double* prow = P + (row_ok ? i : 0) + (int64_t)b0 * ldp;
+#pragma unroll
+  for (int u = 0; u < MAXNB; ++u) x[u] = (row_ok && u < nx) ? prow[(int64_t)u * ldp] : 0.0;
+  const int cp = c - 1;
+  const bool finish = c >= 1 && cp < m;
+  if (finish) {
     const double* part = scratch + (cp & 1) * per_buf;
     const double* rowv = part + (int64_t)G * stride;
-    if (cp < m) {
-      const int ncol = nb - cp;
-      for (int j = t; j < ncol; j += QT) {
-        double s = 0.0;
-        for (int q = 0; q < G; ++q) s += part[(int64_t)q * stride + j];
-        tot[j] = s;
-      }
-      __syncthreads();
-      if (t == 0) {
-        const double a0 = rowv[0];
-        const double sig2 = tot[0];
-        double tv = 0.0, beta = a0, scale = 0.0;
-        if (sig2 > 0.0) {
-          beta = -copysign(sqrt(a0 * a0 + sig2), a0);
-          tv = (beta - a0) / beta;
-          scale = 1.0 / (a0 - beta);
-        }
-        sh[0] = tv; sh[1] = beta; sh[2] = scale;
-        if (g == 0) tau[cp] = tv;
-      }
-      __syncthreads();
-      const double tv = sh[0], scale = sh[2];
-      // w_j = tau v^T A(:, j) = tau (A(cp, j) + scale * dot_j),  j > cp
-      for (int jj = t; jj < nb - cp - 1; jj += QT)
-        wv[jj] = tv * (rowv[1 + jj] + scale * tot[1 + jj]);
-      __syncthreads();
-      if (tv != 0.0 && i < m && i >= cp) {
-        double vi = 1.0;
-        if (i > cp) {
-          vi = P[i + (int64_t)cp * ldp] * scale;
-          P[i + (int64_t)cp * ldp] = vi;  // v is stored below the diagonal
-        } else {
-          P[i + (int64_t)cp * ldp] = sh[1];  // R(cp, cp) = beta
-        }
-        // chunks of 8 independent loads, then 8 stores
-        const int cnt = nb - cp - 1;
-        double* row = P + i + (int64_t)(cp + 1) * ldp;
-        for (int j0 = 0; j0 < cnt; j0 += 8) {
-          double x[8];
+    const int ncol = nb - cp;
+    // four threads per column, each summing a contiguous quarter of slices
+    const int j = t & 63, h = t >> 6, G4 = (G + 3) / 4;
+    double ps = 0.0;
+    for (int u0 = 0; u0 < G4; u0 += 16) {
+      double xs[16];  // clamped addresses: all sixteen loads in flight at once
 #pragma unroll
-          for (int u = 0; u < 8; ++u)
-            if (j0 + u < cnt) x[u] = row[(int64_t)(j0 + u) * ldp];
+      for (int u = 0; u < 16; ++u)
+        xs[u] = part[(int64_t)min(h * G4 + u0 + u, G - 1) * stride + min(j, ncol - 1)];
 #pragma unroll
-          for (int u = 0; u < 8; ++u)
-            if (j0 + u < cnt) row[(int64_t)(j0 + u) * ldp] = x[u] - vi * wv[j0 + u];
-        }
+      for (int u = 0; u < 16; ++u) {
+        const int q = h * G4 + u0 + u;
+        ps += (u0 + u < G4 && q < G && j < ncol) ? xs[u] : 0.0;
       }
-    } else if (g == 0 && t == 0) {
-      tau[cp] = 0.0;
     }
-    __syncthreads();  // row c (updated above by its owner) is read below
+    red[h][j] = ps;
+    const double rv = (t < ncol) ? rowv[t] : 0.0;
+    __syncthreads();
+    if (t < ncol) tot[t] = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
+    __syncthreads();
+    if (t == 0) {
+      const double a0 = rv;
+      const double sig2 = tot[0];
+      double tv = 0.0, beta = a0, scale = 0.0;
+      if (sig2 > 0.0) {
+        beta = -copysign(sqrt(a0 * a0 + sig2), a0);
+        tv = (beta - a0) / beta;
+        scale = 1.0 / (a0 - beta);
+      }
+      sh[0] = tv; sh[1] = beta; sh[2] = scale;
+      if (g == 0) tau[cp] = tv;
+    }
+    __syncthreads();
+    const double tv = sh[0], scale = sh[2];
+    // w_j = tau v^T A(:, j) = tau (A(cp, j) + scale * dot_j),  j > cp
+    if (t >= 1 && t < ncol) wv[t] = tv * (rv + scale * tot[t]);
+    __syncthreads();
+    if (tv != 0.0 && row_ok && i >= cp) {
+      const double vi = (i > cp) ? x[0] * scale : 1.0;
+      x[0] = (i > cp) ? vi : sh[1];  // v below the diagonal, R(cp, cp) = beta
+#pragma unroll
+      for (int u = 1; u < MAXNB; ++u)
+        if (u < nx) x[u] -= vi * wv[u];
+      double* wrow = P + i + (int64_t)b0 * ldp;
+#pragma unroll
+      for (int u = 0; u < MAXNB; ++u)
+        if (u < nx) wrow[(int64_t)u * ldp] = x[u];
+    }
+  } else if (c >= 1 && g == 0 && t == 0) {
+    tau[cp] = 0.0;
   }
   if (c >= nb || c >= m) return;
-  // ---- partials of column c over rows > c ------------------------------------
+  // ---- partials of column c over rows > c, from the registers -----------------
   double* part = scratch + (c & 1) * per_buf;
   double* po = part + (int64_t)g * stride;
+  const int uc = c - b0;  // register index of column c (0 or 1)
   const int ncol = nb - c;
-  const bool mine = (i < m && i > c);
-  const double* row = P + i + (int64_t)c * ldp;
-  const double a = mine ? row[0] : 0.0;
-  for (int j0 = 0; j0 < ncol; j0 += 8) {
-    double x[8];
+  const bool mine = row_ok && i > c;
+  const double a = mine ? (uc ? x[1] : x[0]) : 0.0;
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
-      x[u] = (mine && j0 + u < ncol) ? row[(int64_t)(j0 + u) * ldp] : 0.0;
+  for (int u = 0; u < MAXNB; ++u) {
+    const int jj = u - uc;
+    if (jj >= 0 && jj < ncol) red2[jj][t] = a * x[u];
+  }
+  // snapshot of row c (owned by slice 0, thread c)
+  if (g == 0 && t == c) {
+    double* rowv = part + (int64_t)G * stride;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      if (j0 + u < ncol) {
-        const double v = wsum(a * x[u]);
-        if (lane == 0) red[wave][j0 + u] = v;
-      }
+    for (int u = 0; u < MAXNB; ++u) {
+      const int jj = u - uc;
+      if (jj >= 0 && jj < ncol) rowv[jj] = x[u];
     }
   }
-  // snapshot of row c (owned by slice 0)
-  if (g == 0) {
-    double* rowv = part + (int64_t)G * stride;
-    for (int j = t; j < ncol; j += QT) rowv[j] = P[c + (int64_t)(c + j) * ldp];
+  __syncthreads();
+  {
+    const int j = t & 63, h = t >> 6;
+    double s2 = 0.0;
+    if (j < ncol) {
+#pragma unroll 16
+      for (int r = 0; r < 64; ++r) s2 += red2[j][64 * h + r];
+    }
+    red[h][j] = s2;
   }
   __syncthreads();
-  for (int j = t; j < ncol; j += QT)
-    po[j] = (red[0][j] + red[1][j]) + (red[2][j] + red[3][j]);
+  if (t < ncol) po[t] = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
 }
 
 // Explicit V (m x nb, column-major, ld m) from the stored reflectors.
@@ -191,7 +202,7 @@ int64_t sy2sb_npanels(int64_t n, int nb) {
 
 void sy2sb(double* A, int64_t lda, int64_t n, int nb, double* tau_all, double* T_all,
            double* ws, int64_t ws_elems, hipStream_t s) {
-  MM_REQUIRE(nb >= 1 && nb <= 128, kInvalid, "sy2sb: band must be 1..128");
+  MM_REQUIRE(nb >= 1 && nb <= MAXNB, kInvalid, "sy2sb: band must be 1..64");
   MM_REQUIRE(ws_elems >= sy2sb_ws_elems(n, nb), kInvalid, "sy2sb: workspace too small");
   const int64_t Gmax = ceil_div(n, QROWS);
   const int stride = nb + 1;
