@@ -18,7 +18,6 @@ namespace {
 
 constexpr int BK = 16;    // k-slice per LDS stage
 constexpr int PAD = 2;    // LDS row padding (doubles): conflict-free k-major stores
-constexpr int NT = 256;   // threads per workgroup (4 waves)
 constexpr int GROUP_M = 8;
 
 struct KArgs {
@@ -56,9 +55,14 @@ __device__ __forceinline__ void tile_of(int bid, int tiles_m, int tiles_n,
   tj = w / gsz;
 }
 
-template <int BM, int BN, bool TA, bool TB, bool GROUPED>
-__global__ void __launch_bounds__(NT) gemm_kernel(KArgs a) {
-  constexpr int WM = BM / 2, WN = BN / 2;
+#ifndef MM_GEMM_WPE
+#define MM_GEMM_WPE 2
+#endif
+template <int BM, int BN, int WGM, int WGN, bool TA, bool TB, bool GROUPED>
+__global__ void __launch_bounds__(64 * WGM * WGN)
+    __attribute__((amdgpu_waves_per_eu(MM_GEMM_WPE))) gemm_kernel(KArgs a) {
+  constexpr int NT = 64 * WGM * WGN;
+  constexpr int WM = BM / WGM, WN = BN / WGN;
   constexpr int FM = WM / 16, FN = WN / 16;
   constexpr int LA = BM * BK / NT;  // A elements loaded per thread per slice
   constexpr int LB = BN * BK / NT;
@@ -101,7 +105,7 @@ __global__ void __launch_bounds__(NT) gemm_kernel(KArgs a) {
 
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
-  const int wm0 = (wave & 1) * WM, wn0 = (wave >> 1) * WN;
+  const int wm0 = (wave % WGM) * WM, wn0 = (wave / WGM) * WN;
   const int lr = lane & 15, lk = lane >> 4;
 
   v4d acc[FM][FN];
@@ -112,30 +116,50 @@ __global__ void __launch_bounds__(NT) gemm_kernel(KArgs a) {
 
   double ra[LA], rb[LB];
 
+  // Operand loads.  With e = t + r NT the element of load r is a per-lane
+  // base plus r times a wave-uniform stride in every layout, so interior
+  // slices load unguarded from one base pointer; edge slices are guarded.
+  constexpr int64_t RA = TA ? (NT / BK) : (NT / BM);  // op(A) rows/cols per r
+  constexpr int64_t RB = TB ? (NT / BN) : (NT / BK);
+  constexpr bool FAST = BM >= 128;  // the small tile keeps the guarded loads
   auto load = [&](int64_t kt) {
+    if (FAST && i0 + BM <= M && kt + BK <= ke) {
+      const double* Ap = TA ? A + (kt + t % BK) + (i0 + t / BK) * lda
+                            : A + (i0 + t % BM) + (kt + t / BM) * lda;
 #pragma unroll
-    for (int r = 0; r < LA; ++r) {
-      const int e = t + r * NT;
-      int ii, kk;
-      if constexpr (!TA) { ii = e % BM; kk = e / BM; }
-      else { kk = e % BK; ii = e / BK; }
-      const int64_t gi = i0 + ii, gk = kt + kk;
-      double v = 0.0;
-      if (gi < M && gk < ke)
-        v = TA ? A[gk + gi * lda] : A[gi + gk * lda];
-      ra[r] = v;
+      for (int r = 0; r < LA; ++r) ra[r] = Ap[r * RA * lda];
+    } else {
+#pragma unroll
+      for (int r = 0; r < LA; ++r) {
+        const int e = t + r * NT;
+        int ii, kk;
+        if constexpr (!TA) { ii = e % BM; kk = e / BM; }
+        else { kk = e % BK; ii = e / BK; }
+        const int64_t gi = i0 + ii, gk = kt + kk;
+        double v = 0.0;
+        if (gi < M && gk < ke)
+          v = TA ? A[gk + gi * lda] : A[gi + gk * lda];
+        ra[r] = v;
+      }
     }
+    if (FAST && j0 + BN <= N && kt + BK <= ke) {
+      const double* Bp = TB ? B + (j0 + t % BN) + (kt + t / BN) * ldb
+                            : B + (kt + t % BK) + (j0 + t / BK) * ldb;
 #pragma unroll
-    for (int r = 0; r < LB; ++r) {
-      const int e = t + r * NT;
-      int jj, kk;
-      if constexpr (!TB) { kk = e % BK; jj = e / BK; }
-      else { jj = e % BN; kk = e / BN; }
-      const int64_t gj = j0 + jj, gk = kt + kk;
-      double v = 0.0;
-      if (gj < N && gk < ke)
-        v = TB ? B[gj + gk * ldb] : B[gk + gj * ldb];
-      rb[r] = v;
+      for (int r = 0; r < LB; ++r) rb[r] = Bp[r * RB * ldb];
+    } else {
+#pragma unroll
+      for (int r = 0; r < LB; ++r) {
+        const int e = t + r * NT;
+        int jj, kk;
+        if constexpr (!TB) { kk = e % BK; jj = e / BK; }
+        else { jj = e % BN; kk = e / BN; }
+        const int64_t gj = j0 + jj, gk = kt + kk;
+        double v = 0.0;
+        if (gj < N && gk < ke)
+          v = TB ? B[gj + gk * ldb] : B[gk + gj * ldb];
+        rb[r] = v;
+      }
     }
   };
   auto store = [&](int buf) {
@@ -201,6 +225,40 @@ __global__ void __launch_bounds__(NT) gemm_kernel(KArgs a) {
         }
     return;
   }
+  // C = alpha acc + beta C.  Interior tiles: the C values of half the wave's
+  // tile are loaded together before any is used (two memory latencies per
+  // tile, not one per element), addressed from one per-lane base pointer and
+  // wave-uniform offsets.  Edge tiles take the guarded element-wise path.
+  const bool full = i0 + BM <= M && j0 + BN <= N && (!a.lower || i0 >= j0 + BN - 1);
+  const double alpha = a.alpha, beta = a.beta;
+  if (full) {
+    double* Cb = C + (i0 + wm0 + lr) + (j0 + wn0 + lk) * ldc;
+#pragma unroll
+    for (int xh = 0; xh < FM; xh += FM / 2) {
+      __builtin_amdgcn_sched_barrier(0);
+      double cv[FM / 2][FN][4];
+      if (beta != 0.0) {
+#pragma unroll
+        for (int x = 0; x < FM / 2; ++x)
+#pragma unroll
+          for (int y = 0; y < FN; ++y)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              cv[x][y][q] = Cb[(xh + x) * 16 + (int64_t)(y * 16 + 4 * q) * ldc];
+      }
+#pragma unroll
+      for (int x = 0; x < FM / 2; ++x)
+#pragma unroll
+        for (int y = 0; y < FN; ++y)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            double v = alpha * acc[xh + x][y][q];
+            if (beta != 0.0) v += beta * cv[x][y][q];
+            Cb[(xh + x) * 16 + (int64_t)(y * 16 + 4 * q) * ldc] = v;
+          }
+    }
+    return;
+  }
 #pragma unroll
   for (int x = 0; x < FM; ++x)
 #pragma unroll
@@ -210,8 +268,8 @@ __global__ void __launch_bounds__(NT) gemm_kernel(KArgs a) {
         const int64_t gi = i0 + wm0 + x * 16 + lr;
         const int64_t gj = j0 + wn0 + y * 16 + lk + 4 * q;
         if (gi < M && gj < N && (!a.lower || gi >= gj)) {
-          double v = a.alpha * acc[x][y][q];
-          if (a.beta != 0.0) v += a.beta * C[gi + gj * ldc];
+          double v = alpha * acc[x][y][q];
+          if (beta != 0.0) v += beta * C[gi + gj * ldc];
           C[gi + gj * ldc] = v;
         }
       }
@@ -230,13 +288,24 @@ __global__ void splitk_reduce(int64_t M, int64_t N, int splits, const double* W,
   C[i + j * ldc] = s;
 }
 
-template <int BM, int BN, bool GROUPED>
+template <int BM, int BN, int WGM, int WGN, bool GROUPED>
 void launch(const KArgs& ka, bool ta, bool tb, dim3 grid, hipStream_t s) {
-  if (!ta && !tb) hipLaunchKernelGGL((gemm_kernel<BM, BN, false, false, GROUPED>), grid, dim3(NT), 0, s, ka);
-  else if (!ta && tb) hipLaunchKernelGGL((gemm_kernel<BM, BN, false, true, GROUPED>), grid, dim3(NT), 0, s, ka);
-  else if (ta && !tb) hipLaunchKernelGGL((gemm_kernel<BM, BN, true, false, GROUPED>), grid, dim3(NT), 0, s, ka);
-  else hipLaunchKernelGGL((gemm_kernel<BM, BN, true, true, GROUPED>), grid, dim3(NT), 0, s, ka);
+  const dim3 block(64 * WGM * WGN);
+  if (!ta && !tb) hipLaunchKernelGGL((gemm_kernel<BM, BN, WGM, WGN, false, false, GROUPED>), grid, block, 0, s, ka);
+  else if (!ta && tb) hipLaunchKernelGGL((gemm_kernel<BM, BN, WGM, WGN, false, true, GROUPED>), grid, block, 0, s, ka);
+  else if (ta && !tb) hipLaunchKernelGGL((gemm_kernel<BM, BN, WGM, WGN, true, false, GROUPED>), grid, block, 0, s, ka);
+  else hipLaunchKernelGGL((gemm_kernel<BM, BN, WGM, WGN, true, true, GROUPED>), grid, block, 0, s, ka);
 }
+
+// Tile of the large configuration.
+#ifndef MM_GEMM_BIG
+#define MM_GEMM_BIG 128, 64, 4, 2
+#endif
+template <int BM_, int BN_, int WGM_, int WGN_>
+struct Cfg {
+  static constexpr int BM = BM_, BN = BN_, WGM = WGM_, WGN = WGN_;
+};
+using Big = Cfg<MM_GEMM_BIG>;
 
 }  // namespace
 
@@ -257,7 +326,7 @@ void gemm(const Gemm& g, hipStream_t stream, double* ws, int64_t ws_elems) {
     ka.k = 0;  // C = beta C through the epilogue
   }
   const bool big = g.m * g.n >= (int64_t)256 * 128 * 128;
-  const int bm = big ? 128 : 64, bn = bm;
+  const int bm = big ? Big::BM : 64, bn = big ? Big::BN : 64;
   ka.tiles_m = (int)ceil_div(g.m, bm);
   ka.tiles_n = (int)ceil_div(g.n, bn);
   const int64_t tiles = (int64_t)ka.tiles_m * ka.tiles_n;
@@ -273,8 +342,8 @@ void gemm(const Gemm& g, hipStream_t stream, double* ws, int64_t ws_elems) {
   ka.splits = splits;
   ka.ws = splits > 1 ? ws : nullptr;
   dim3 grid((unsigned)tiles, (unsigned)g.batch, (unsigned)splits);
-  if (big) launch<128, 128, false>(ka, g.ta, g.tb, grid, stream);
-  else launch<64, 64, false>(ka, g.ta, g.tb, grid, stream);
+  if (big) launch<Big::BM, Big::BN, Big::WGM, Big::WGN, false>(ka, g.ta, g.tb, grid, stream);
+  else launch<64, 64, 2, 2, false>(ka, g.ta, g.tb, grid, stream);
   MM_HIP_TRY(hipGetLastError());
   if (splits > 1) {
     const int64_t total = g.m * g.n;
@@ -292,12 +361,12 @@ void gemm_grouped(const GemmGroup* d_groups, int64_t n_groups, int64_t max_m,
   ka.alpha = alpha; ka.beta = beta; ka.splits = 1; ka.b_band = -1;
   ka.groups = d_groups;
   const bool big = max_m * max_n >= (int64_t)64 * 128 * 128;
-  const int bm = big ? 128 : 64;
+  const int bm = big ? Big::BM : 64, bn = big ? Big::BN : 64;
   ka.tiles_m = (int)ceil_div(max_m, bm);
-  ka.tiles_n = (int)ceil_div(max_n, bm);
+  ka.tiles_n = (int)ceil_div(max_n, bn);
   dim3 grid((unsigned)((int64_t)ka.tiles_m * ka.tiles_n), (unsigned)n_groups, 1);
-  if (big) launch<128, 128, true>(ka, ta, tb, grid, stream);
-  else launch<64, 64, true>(ka, ta, tb, grid, stream);
+  if (big) launch<Big::BM, Big::BN, Big::WGM, Big::WGN, true>(ka, ta, tb, grid, stream);
+  else launch<64, 64, 2, 2, true>(ka, ta, tb, grid, stream);
   MM_HIP_TRY(hipGetLastError());
 }
 
