@@ -77,7 +77,12 @@ typedef struct {
 
 /* Copy the problem to the device and prepare the context.  `stream` is a
  * hipStream_t (NULL = the default stream).  On success *out owns all device
- * memory the library allocates for this problem. */
+ * memory the library allocates for this problem.  With electrodes (Ne >= 2)
+ * this also builds the reduced problem of Sec. 3.1 (eqs. discrete_version_2,
+ * circuit_equations_v2): K is the Householder complement of im E^T, and
+ * K^T L K, K^T R K, R_D, L_D, K^T M0 and the probe weights are formed on the
+ * device.  MM_E_INVALID if E is not of full row rank, or if
+ * 2 (Ne - 1) + n_src > 8. */
 mm_status mm_setup(const mm_problem* problem, void* stream, mm_ctx** out);
 
 /* The one-off modal decomposition (Sec. 3.2): Li = G G^T, C = G^{-1} Ri G^{-T},

@@ -24,19 +24,34 @@ void copy_matrix(const double* S, int64_t lds, double* D, int64_t ldd,
                  int64_t m, int64_t n, hipStream_t s);
 
 // ---- setup (setup.hip) -----------------------------------------------------
+// Sparse matrix in CSR form.  The logical matrix is the stored one with its
+// first `off` rows and columns dropped: logical entry (i, j) is stored entry
+// (i + off, j + off); `rows` counts logical rows.
 struct Csr {
   int64_t rows = 0, cols = 0, nnz = 0;
+  int64_t off = 0;
   const int64_t* rowptr = nullptr;
   const int32_t* col = nullptr;
   const double* val = nullptr;
 };
-// L_ij = h / sqrt(|x_i - x_j|^2 + h^2) for i >= j (lower triangle + diagonal),
-// or the full matrix if `full`.
+// Symmetric low-rank term  U Yc^T + Yc U^T  with Yc = Y1 + w2 Y2 (Y2 may be
+// null); U, Y1, Y2 are n x m column-major with leading dimension ld.
+struct LowRank {
+  const double* U = nullptr;
+  const double* Y1 = nullptr;
+  const double* Y2 = nullptr;
+  double w2 = 0.0;
+  int64_t ld = 0;
+  int m = 0;
+};
+// L_ij = h / sqrt(|x_i - x_j|^2 + h^2) - (U Yc^T + Yc U^T)_ij for i >= j
+// (lower triangle + diagonal), or the full matrix if `full`.
 void assemble_L(const double* xyz, double h, int64_t n, double* L, int64_t ld,
-                bool full, hipStream_t s);
+                bool full, hipStream_t s, const LowRank& lr = LowRank{});
 // Z(i,j) += alpha R(i,j) for the lower-triangle entries of R.
 void add_csr_lower(double* Z, int64_t ld, double alpha, const Csr& R, hipStream_t s);
-// max_j (j - min{c : R(c,j) != 0}) for symmetric R (written to *d_out).
+// max_j (j - min{c : R(c,j) != 0}) over the stored rows of symmetric R (an
+// upper bound for the logical matrix of any offset), written to *d_out.
 void csr_lower_band(const Csr& R, int64_t* d_out, hipStream_t s);
 // W = A R for dense A (n x n, column-major) and symmetric sparse R.
 void dense_times_csr(const double* A, int64_t lda, const Csr& R, double* W,
@@ -45,6 +60,46 @@ void dense_times_csr(const double* A, int64_t lda, const Csr& R, double* W,
 void symmetrize_from_lower(double* A, int64_t lda, int64_t n, hipStream_t s);
 void fill(double* p, int64_t count, double v, hipStream_t s);
 void fill_i64(int64_t* p, int64_t count, int64_t v, hipStream_t s);
+
+// ---- electrode reduction (electrode.hip) ----------------------------------
+// Householder QR of E^T for the m x n electrode matrix E (CSR, m <= 8):
+// E^T = H [Re; 0] with H = H_0 ... H_{m-1} = I - V T V^T.  Writes V (n x m,
+// unit diagonal, zero above it), small = [T | Re^{-T}] (two m x m blocks,
+// column-major) and *d_status = 1 if E is rank deficient.  work: n m doubles.
+void electrode_qr(const Csr& E, int64_t n, int m, double* V, double* small, double* work,
+                  int64_t* d_status, hipStream_t s);
+// X <- H X (trans false) or H^T X for X (n x k, ld ldx).  ws: apply_h_ws_elems.
+int64_t apply_h_ws_elems(int m, int64_t k);
+void apply_h(const double* V, const double* T, int64_t n, int m, double* X, int64_t ldx,
+             int64_t k, bool trans, double* ws, int64_t ws_elems, hipStream_t s);
+// Y = X T - 1/2 V (T^T V^T X T) for X = A V: then H^T A H = A - V Y^T - Y V^T.
+void two_sided_y(const double* V, const double* T, int64_t n, int m, const double* X,
+                 double* Y, double* ws, int64_t ws_elems, hipStream_t s);
+// out (n x k) = L U for the inductance stand-in, U non-zero only on rows idx.
+void l_times_rows(const double* xyz, double h, int64_t n, const int32_t* idx, int ns,
+                  const double* U, int64_t ldu, int k, double* out, int64_t ldo,
+                  hipStream_t s);
+// out (R.rows x k) = R U (logical R, offset honoured), k <= 8.
+void csr_times_dense(const Csr& R, const double* U, int64_t ldu, int k, double* out,
+                     int64_t ldo, hipStream_t s);
+// z = [Rinv^T iD ; Ii]  (m + n0 entries)
+void electrode_lift(const double* RinvT, const double* iD, int m, const double* Ii,
+                    int64_t n0, double* z, hipStream_t s);
+// mark[i] = 1 if row i of A (rows x k) or of B has a non-zero entry.
+void mark_rows(const double* A, const double* B, int64_t ld, int64_t rows, int k,
+               unsigned char* mark, hipStream_t s);
+// D (ns x k) = rows idx of S (ld lds)
+void gather_rows(const double* S, int64_t lds, const int32_t* idx, int ns, int k, double* D,
+                 hipStream_t s);
+
+// Sparse low-rank part of the reduced resistance, R_i = R'' - V Y^T - Y V^T
+// with V, Y non-zero only on the rows idx (ns of them): Vs, Ys are ns x m.
+struct RLowRank {
+  int ns = 0, m = 0;
+  const int32_t* idx = nullptr;
+  const double* Vs = nullptr;
+  const double* Ys = nullptr;
+};
 
 // ---- Cholesky theta-method (step_chol.hip) --------------------------------
 // Block size of the triangular solves for order n (128, 256 or 512), and
@@ -72,7 +127,8 @@ struct CholStep {
   const double* DinvT = nullptr; // the same blocks transposed
   int64_t* kstep = nullptr;    // device step counter (one int64)
   bool use_graph = true;       // replay one captured step per time step
-  Csr Ri;                      // reduced resistance
+  Csr Ri;                      // reduced resistance, sparse part
+  RLowRank Rlr;                // reduced resistance, low-rank part (electrodes)
   Forcing f;
   double theta = 0.5, dt = 1.0;
   double* I = nullptr;         // state Ii (n0)

@@ -66,7 +66,16 @@ struct mm_ctx {
   double h = 0.0;
   int64_t r_nnz = 0, band = 0;
   Dev xyz, r_rowptr, r_col, r_val, M0, P;
-  Dev status;  // [0] potrf pivot (INT64_MAX = fine), [1] eigensolver status
+  Dev status;  // [0] potrf pivot (INT64_MAX = fine), [1] eigensolver status,
+               // [2] band of R, [3] electrode rank test
+  // reduced problem: forcing columns F = [R_D | L_D | K^T M0] (n0 x nf), probe
+  // weights Pt = K^T P (n0 x n_probe), direct probe term PD = P A_D (n_probe x m)
+  Dev F, Pt, PD;
+  // electrode reduction (m > 0): H = I - Vh T Vh^T (small = [T | Re^{-T} | tau]),
+  // two-sided factors YL, YR of L and R (n x m), the sparse low-rank part of R_i
+  Dev e_rowptr, e_col, e_val, Vh, small, YL, YR, idxV, lr_idx, lr_V, lr_Y;
+  int nsV = 0, ns_lr = 0;
+  Dev iD_modal, iD_chol;  // injected currents at each method's current step
   // modal method
   bool decomposed = false;
   Dev G, Q, lam, Wm, Pm, y;
@@ -80,7 +89,8 @@ struct mm_ctx {
   Dev tmp;
   std::string err;
 
-  Csr R() const {
+  // R as given (n x n) and its trailing block R[m:, m:] (the sparse part of R_i)
+  Csr Rfull() const {
     Csr c;
     c.rows = n; c.cols = n; c.nnz = r_nnz;
     c.rowptr = r_rowptr.as<int64_t>();
@@ -88,6 +98,29 @@ struct mm_ctx {
     c.val = r_val.d();
     return c;
   }
+  Csr R() const {
+    Csr c = Rfull();
+    c.rows = n0; c.cols = n0; c.off = m;
+    return c;
+  }
+  // low-rank part of L_i (+ w R_i): rows m.. of Vh and YL (+ w YR)
+  LowRank lr(double w) const {
+    LowRank l;
+    if (m == 0) return l;
+    l.U = Vh.d() + m; l.Y1 = YL.d() + m;
+    l.Y2 = w != 0.0 ? YR.d() + m : nullptr; l.w2 = w;
+    l.ld = n; l.m = (int)m;
+    return l;
+  }
+  RLowRank Rlr() const {
+    RLowRank r;
+    if (m == 0 || ns_lr == 0) return r;
+    r.ns = ns_lr; r.m = (int)m;
+    r.idx = lr_idx.as<int32_t>(); r.Vs = lr_V.d(); r.Ys = lr_Y.d();
+    return r;
+  }
+  const double* T() const { return small.d(); }
+  const double* RinvT() const { return small.d() + m * m; }
 };
 
 namespace {
@@ -137,6 +170,144 @@ void factor_checked(double* A, int64_t n, int64_t* d_status, Dev& ws, hipStream_
                              std::to_string(piv) + ")"};
 }
 
+// The reduced problem of the injected-current decomposition (Sec. 3.1):
+// K = H[:, m:], L_i = (H^T L H)[m:, m:], R_i = (H^T R H)[m:, m:],
+// R_D = K^T R A_D, L_D = K^T L A_D, K^T M0, K^T P, P A_D with A_D = H [Re^{-T}; 0].
+// Without electrodes F = M0 and Pt = P.
+void reduce_problem(mm_ctx* c, const mm_problem* pb) {
+  hipStream_t s = c->stream;
+  const int64_t n = c->n, n0 = c->n0;
+  const int m = (int)c->m;
+  c->F.alloc(sizeof(double) * n0 * std::max(1, c->nf));
+  c->Pt.alloc(sizeof(double) * n0 * c->n_probe);
+  if (m == 0) {
+    if (c->n_src > 0)
+      MM_HIP_TRY(hipMemcpyAsync(c->F.p, c->M0.p, sizeof(double) * n * c->n_src,
+                                hipMemcpyDeviceToDevice, s));
+    MM_HIP_TRY(hipMemcpyAsync(c->Pt.p, c->P.p, sizeof(double) * n * c->n_probe,
+                              hipMemcpyDeviceToDevice, s));
+    return;
+  }
+  // E (m x n CSR); the support of V is inside E's columns and rows 0..m-1
+  MM_REQUIRE(pb->e_rowptr && pb->e_col && pb->e_val && pb->e_nnz >= 1, kInvalid,
+             "electrodes need E (CSR)");
+  copy_in(c->e_rowptr, pb->e_rowptr, sizeof(int64_t) * (m + 1), s);
+  copy_in(c->e_col, pb->e_col, sizeof(int32_t) * pb->e_nnz, s);
+  copy_in(c->e_val, pb->e_val, sizeof(double) * pb->e_nnz, s);
+  std::vector<int64_t> rp(m + 1);
+  std::vector<int32_t> ecol(pb->e_nnz);
+  MM_HIP_TRY(hipMemcpyAsync(rp.data(), c->e_rowptr.p, sizeof(int64_t) * (m + 1),
+                            hipMemcpyDeviceToHost, s));
+  MM_HIP_TRY(hipMemcpyAsync(ecol.data(), c->e_col.p, sizeof(int32_t) * pb->e_nnz,
+                            hipMemcpyDeviceToHost, s));
+  MM_HIP_TRY(hipStreamSynchronize(s));
+  MM_REQUIRE(rp[0] == 0 && rp[m] == pb->e_nnz, kInvalid, "E: bad row pointers");
+  std::vector<unsigned char> inV(n, 0);
+  for (int a = 0; a < m; ++a) inV[a] = 1;
+  for (int32_t j : ecol) {
+    MM_REQUIRE(j >= 0 && j < n, kInvalid, "E: column index out of range");
+    inV[j] = 1;
+  }
+  std::vector<int32_t> idx;
+  for (int64_t i = 0; i < n; ++i)
+    if (inV[i]) idx.push_back((int32_t)i);
+  c->nsV = (int)idx.size();
+  c->idxV.alloc(sizeof(int32_t) * idx.size());
+  MM_HIP_TRY(hipMemcpyAsync(c->idxV.p, idx.data(), sizeof(int32_t) * idx.size(),
+                            hipMemcpyHostToDevice, s));
+  Csr E;
+  E.rows = m; E.cols = n; E.nnz = pb->e_nnz;
+  E.rowptr = c->e_rowptr.as<int64_t>(); E.col = c->e_col.as<int32_t>(); E.val = c->e_val.d();
+  // H = I - V T V^T from the QR of E^T
+  c->Vh.alloc(sizeof(double) * n * m);
+  c->small.alloc(sizeof(double) * (2 * m * m + m));
+  const int kmax = std::max(std::max(m, c->n_src), c->n_probe);
+  const int64_t wse = apply_h_ws_elems(m, kmax);
+  Dev work, ws, X, U;
+  work.alloc(sizeof(double) * n * kmax);
+  ws.alloc(sizeof(double) * wse);
+  X.alloc(sizeof(double) * n * kmax);
+  U.alloc(sizeof(double) * n * m);
+  int64_t* st = c->status.as<int64_t>() + 3;
+  fill_i64(st, 1, 0, s);
+  electrode_qr(E, n, m, c->Vh.d(), c->small.d(), work.d(), st, s);
+  int64_t bad = 0;
+  MM_HIP_TRY(hipMemcpyAsync(&bad, st, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  MM_HIP_TRY(hipStreamSynchronize(s));
+  MM_REQUIRE(bad == 0, kInvalid, "the electrode rows of E are linearly dependent");
+  const double* V = c->Vh.d();
+  const double* T = c->T();
+  // two-sided factors: H^T L H = L - V YL^T - YL V^T (likewise R)
+  c->YL.alloc(sizeof(double) * n * m);
+  c->YR.alloc(sizeof(double) * n * m);
+  l_times_rows(c->xyz.d(), c->h, n, c->idxV.as<int32_t>(), c->nsV, V, n, m, X.d(), n, s);
+  two_sided_y(V, T, n, m, X.d(), c->YL.d(), ws.d(), wse, s);
+  csr_times_dense(c->Rfull(), V, n, m, X.d(), n, s);
+  two_sided_y(V, T, n, m, X.d(), c->YR.d(), ws.d(), wse, s);
+  // U = H [I_m; 0] spans im E^T;  R_D = (H^T R U)[m:] Re^{-T},  L_D likewise
+  fill(U.d(), n * m, 0.0, s);
+  for (int a = 0; a < m; ++a) fill(U.d() + a * (n + 1), 1, 1.0, s);
+  apply_h(V, T, n, m, U.d(), n, m, false, ws.d(), wse, s);
+  auto project = [&](double* Y, int col0) {  // F(:, col0:col0+m) = (H^T Y)[m:] Re^{-T}
+    apply_h(V, T, n, m, Y, n, m, true, ws.d(), wse, s);
+    Gemm g;
+    g.m = n0; g.n = m; g.k = m;
+    g.A = Y + m; g.lda = n;
+    g.B = c->RinvT(); g.ldb = m;
+    g.C = c->F.d() + (int64_t)col0 * n0; g.ldc = n0;
+    gemm(g, s);
+  };
+  csr_times_dense(c->Rfull(), U.d(), n, m, X.d(), n, s);
+  project(X.d(), 0);
+  l_times_rows(c->xyz.d(), c->h, n, c->idxV.as<int32_t>(), c->nsV, U.d(), n, m, X.d(), n, s);
+  project(X.d(), m);
+  if (c->n_src > 0) {  // K^T M0
+    MM_HIP_TRY(hipMemcpyAsync(X.p, c->M0.p, sizeof(double) * n * c->n_src,
+                              hipMemcpyDeviceToDevice, s));
+    apply_h(V, T, n, m, X.d(), n, c->n_src, true, ws.d(), wse, s);
+    copy_matrix(X.d() + m, n, c->F.d() + (int64_t)2 * m * n0, n0, n0, c->n_src, s);
+  }
+  // probes: Pt = (H^T P)[m:],  PD = P A_D = (H^T P)[:m]^T Re^{-T}
+  MM_HIP_TRY(hipMemcpyAsync(X.p, c->P.p, sizeof(double) * n * c->n_probe,
+                            hipMemcpyDeviceToDevice, s));
+  apply_h(V, T, n, m, X.d(), n, c->n_probe, true, ws.d(), wse, s);
+  copy_matrix(X.d() + m, n, c->Pt.d(), n0, n0, c->n_probe, s);
+  c->PD.alloc(sizeof(double) * c->n_probe * m);
+  {
+    Gemm g;
+    g.m = c->n_probe; g.n = m; g.k = m;
+    g.A = X.d(); g.lda = n; g.ta = true;
+    g.B = c->RinvT(); g.ldb = m;
+    g.C = c->PD.d(); g.ldc = c->n_probe;
+    gemm(g, s);
+  }
+  // the low-rank part of R_i lives on the rows where V or YR is non-zero
+  Dev mark;
+  mark.alloc(n0);
+  mark_rows(V + m, c->YR.d() + m, n, n0, m, mark.as<unsigned char>(), s);
+  std::vector<unsigned char> mk(n0);
+  MM_HIP_TRY(hipMemcpyAsync(mk.data(), mark.p, n0, hipMemcpyDeviceToHost, s));
+  MM_HIP_TRY(hipStreamSynchronize(s));
+  std::vector<int32_t> li;
+  for (int64_t i = 0; i < n0; ++i)
+    if (mk[i]) li.push_back((int32_t)i);
+  c->ns_lr = (int)li.size();
+  if (c->ns_lr > 0) {
+    c->lr_idx.alloc(sizeof(int32_t) * li.size());
+    MM_HIP_TRY(hipMemcpyAsync(c->lr_idx.p, li.data(), sizeof(int32_t) * li.size(),
+                              hipMemcpyHostToDevice, s));
+    c->lr_V.alloc(sizeof(double) * li.size() * m);
+    c->lr_Y.alloc(sizeof(double) * li.size() * m);
+    gather_rows(V + m, n, c->lr_idx.as<int32_t>(), c->ns_lr, m, c->lr_V.d(), s);
+    gather_rows(c->YR.d() + m, n, c->lr_idx.as<int32_t>(), c->ns_lr, m, c->lr_Y.d(), s);
+  }
+  c->iD_modal.alloc(sizeof(double) * m);
+  c->iD_chol.alloc(sizeof(double) * m);
+  fill(c->iD_modal.d(), m, 0.0, s);
+  fill(c->iD_chol.d(), m, 0.0, s);
+  MM_HIP_TRY(hipStreamSynchronize(s));  // the host vectors above must outlive the copies
+}
+
 }  // namespace
 
 extern "C" {
@@ -161,8 +332,8 @@ mm_status mm_setup(const mm_problem* pb, void* stream, mm_ctx** out) {
                "1..8 probe rows are required");
     MM_REQUIRE(pb->n_src >= 0 && pb->n_src <= 8 && (pb->n_src == 0 || pb->M0), kInvalid,
                "0..8 sources");
-    MM_REQUIRE(pb->n_e == 0 || pb->n_e >= 2, kInvalid, "Ne must be 0 or >= 2");
-    MM_REQUIRE(pb->n_e == 0, kInvalid, "electrodes are not supported by this build yet");
+    MM_REQUIRE(pb->n_e == 0 || (pb->n_e >= 2 && pb->n_e - 1 < pb->n), kInvalid,
+               "Ne must be 0 or 2..n");
     c->stream = (hipStream_t)stream;
     hipStream_t s = c->stream;
     const char* ng = std::getenv("MM_NO_GRAPH");
@@ -183,10 +354,12 @@ mm_status mm_setup(const mm_problem* pb, void* stream, mm_ctx** out) {
     copy_in(c->M0, pb->M0, sizeof(double) * c->n * c->n_src, s);
     copy_in(c->P, pb->P, sizeof(double) * c->n * c->n_probe, s);
     c->status.alloc(4 * sizeof(int64_t));
-    csr_lower_band(c->R(), c->status.as<int64_t>() + 2, s);
+    csr_lower_band(c->Rfull(), c->status.as<int64_t>() + 2, s);
     MM_HIP_TRY(hipMemcpyAsync(&c->band, c->status.as<int64_t>() + 2, sizeof(int64_t),
                               hipMemcpyDeviceToHost, s));
     MM_HIP_TRY(hipStreamSynchronize(s));
+    // a1: the reduced problem (electrodes), forcing columns and probe weights
+    reduce_problem(c, pb);
   });
   if (st != MM_OK) {
     delete c;
@@ -215,8 +388,9 @@ mm_status mm_decompose(mm_ctx* c) {
     double* Q = c->Q.d();
     double* C = Cb.d();
     int64_t* st = c->status.as<int64_t>();
-    // a0: L (lower triangle);  a2: Li = G G^T  (Ne = 0: Li = L)
-    assemble_L(c->xyz.d(), c->h, c->n, G, n0, false, s);
+    // a0, a1: L_i (lower triangle);  a2: L_i = G G^T  (Ne = 0: L_i = L)
+    const int m = (int)c->m;
+    assemble_L(c->xyz.d() + 3 * m, c->h, n0, G, n0, false, s, c->lr(0.0));
     factor_checked(G, n0, st, ws, s, "L");
     // a3: C = G^{-1} R G^{-T}:  G <- G^{-1};  W = G^{-1} R (in Q);  C = G^{-1} W^T
     const int64_t wse = eig_ws_elems(n0, nb);
@@ -232,15 +406,40 @@ mm_status mm_decompose(mm_ctx* c) {
       g.lower = true;
       gemm(g, s);
     }
+    if (m > 0) {
+      // low-rank part of R_i = R[m:, m:] - V Y^T - Y V^T:
+      // C -= A B^T + B A^T with A = G^{-1} V, B = G^{-1} Y, as one rank-2m product
+      Dev ABA;
+      ABA.alloc(sizeof(double) * n0 * 3 * m);
+      const double* src[2] = {c->Vh.d() + m, c->YR.d() + m};
+      for (int q = 0; q < 2; ++q) {
+        Gemm g;
+        g.m = n0; g.n = m; g.k = n0;
+        g.A = G; g.lda = n0; g.a_lower = true;
+        g.B = src[q]; g.ldb = c->n;
+        g.C = ABA.d() + (int64_t)q * m * n0; g.ldc = n0;
+        gemm(g, s);
+      }
+      copy_matrix(ABA.d(), n0, ABA.d() + (int64_t)2 * m * n0, n0, n0, m, s);
+      Gemm g;
+      g.m = n0; g.n = n0; g.k = 2 * m;
+      g.alpha = -1.0; g.beta = 1.0;
+      g.A = ABA.d(); g.lda = n0;
+      g.B = ABA.d() + (int64_t)m * n0; g.ldb = n0; g.tb = true;
+      g.C = C; g.ldc = n0;
+      g.lower = true;
+      gemm(g, s);
+      MM_HIP_TRY(hipStreamSynchronize(s));  // ABA is released here
+    }
     symmetrize_from_lower(C, n0, n0, s);
-    // G^{-1} applied to the forcing vectors and the probe rows (Ne = 0: F = M0)
+    // G^{-1} applied to the forcing columns and the probe weights
     GF.alloc(sizeof(double) * n0 * std::max(1, c->nf));
     GP.alloc(sizeof(double) * n0 * c->n_probe);
     if (c->nf > 0) {
       Gemm g;
       g.m = n0; g.n = c->nf; g.k = n0;
       g.A = G; g.lda = n0; g.a_lower = true;
-      g.B = c->M0.d(); g.ldb = n0;
+      g.B = c->F.d(); g.ldb = n0;
       g.C = GF.d(); g.ldc = n0;
       gemm(g, s);
     }
@@ -248,7 +447,7 @@ mm_status mm_decompose(mm_ctx* c) {
       Gemm g;
       g.m = n0; g.n = c->n_probe; g.k = n0;
       g.A = G; g.lda = n0; g.a_lower = true;
-      g.B = c->P.d(); g.ldb = n0;
+      g.B = c->Pt.d(); g.ldb = n0;
       g.C = GP.d(); g.ldc = n0;
       gemm(g, s);
     }
@@ -325,7 +524,11 @@ mm_status mm_step_modal(mm_ctx* c, double theta, double dt, int64_t n_steps,
     ms.y = c->y.d();
     ms.probe_partial = c->pp.d();
     modal_steps(ms, 0, n_steps, s);
-    probe_finish(c->pp.d(), n_steps, G, c->n_probe, nullptr, 0, i_D, 0, dt, signal, s);
+    probe_finish(c->pp.d(), n_steps, G, c->n_probe, c->m ? c->PD.d() : nullptr, (int)c->m,
+                 i_D, 0, dt, signal, s);
+    if (c->m)
+      MM_HIP_TRY(hipMemcpyAsync(c->iD_modal.p, i_D + n_steps * c->m, sizeof(double) * c->m,
+                                hipMemcpyDeviceToDevice, s));
   });
 }
 
@@ -355,7 +558,8 @@ mm_status mm_step_cholesky(mm_ctx* c, double theta, double dt, int64_t n_steps,
       c->kstep.alloc(sizeof(int64_t));
       // b0: Z = Li + theta dt Ri = C C^T   (Ne = 0: Li = L, Ri = R)
       double* Z = c->Z.d();
-      assemble_L(c->xyz.d(), c->h, c->n, Z, n0, false, s);
+      const int m = (int)c->m;
+      assemble_L(c->xyz.d() + 3 * m, c->h, n0, Z, n0, false, s, c->lr(theta * dt));
       add_csr_lower(Z, n0, theta * dt, c->R(), s);
       factor_checked(Z, n0, c->status.as<int64_t>(), c->tmp, s, "Li + theta dt Ri");
       c->tmp.alloc(sizeof(double) * trtri_ws_elems(B));
@@ -379,14 +583,19 @@ mm_status mm_step_cholesky(mm_ctx* c, double theta, double dt, int64_t n_steps,
     cs.kstep = c->kstep.as<int64_t>();
     cs.use_graph = c->use_graph;
     cs.Ri = c->R();
-    cs.f.F = c->M0.d(); cs.f.nf = c->nf; cs.f.m = (int)c->m; cs.f.n_src = c->n_src;
+    cs.Rlr = c->Rlr();
+    cs.f.F = c->F.d(); cs.f.nf = c->nf; cs.f.m = (int)c->m; cs.f.n_src = c->n_src;
     cs.f.i_src = i_src; cs.f.i_D = i_D;
     cs.theta = theta; cs.dt = dt;
     cs.I = c->I.d(); cs.b = c->b.d(); cs.y = c->yv.d();
-    cs.Pt = c->P.d(); cs.n_probe = c->n_probe;
+    cs.Pt = c->Pt.d(); cs.n_probe = c->n_probe;
     cs.probe_partial = c->pp.d();
     chol_steps(cs, 0, n_steps, s);
-    probe_finish(c->pp.d(), n_steps, parts, c->n_probe, nullptr, 0, i_D, 0, dt, signal, s);
+    probe_finish(c->pp.d(), n_steps, parts, c->n_probe, c->m ? c->PD.d() : nullptr, (int)c->m,
+                 i_D, 0, dt, signal, s);
+    if (c->m)
+      MM_HIP_TRY(hipMemcpyAsync(c->iD_chol.p, i_D + n_steps * c->m, sizeof(double) * c->m,
+                                hipMemcpyDeviceToDevice, s));
   });
 }
 
@@ -397,13 +606,15 @@ mm_status mm_probe(mm_ctx* c, int32_t which, int32_t n_rows, const double* rows,
     MM_REQUIRE(which == MM_MODAL || which == MM_CHOLESKY, kInvalid, "which");
     MM_REQUIRE(rows == nullptr || n_rows >= 1, kInvalid, "n_rows");
     hipStream_t s = c->stream;
-    const int64_t n0 = c->n0;
+    const int64_t n = c->n, n0 = c->n0;
+    const int m = (int)c->m;
     Dev buf;
-    buf.alloc(sizeof(double) * 2 * n0);
-    double* Ifull = buf.d();
+    buf.alloc(sizeof(double) * (2 * n0 + n));
+    double* Ii = buf.d();           // reduced current (n0)
+    double* Ifull = buf.d() + n0;   // full current (n)
     if (which == MM_MODAL) {
       MM_REQUIRE(c->decomposed, kState, "mm_probe(MM_MODAL) before mm_decompose");
-      double* t = buf.d() + n0;
+      double* t = buf.d() + n0 + n;
       // a11: Ii = G^{-T} (Q y)
       Gemm g1;
       g1.m = n0; g1.n = 1; g1.k = n0;
@@ -415,19 +626,31 @@ mm_status mm_probe(mm_ctx* c, int32_t which, int32_t n_rows, const double* rows,
       g2.m = n0; g2.n = 1; g2.k = n0;
       g2.A = c->G.d(); g2.lda = n0; g2.ta = true; g2.a_upper = true;
       g2.B = t; g2.ldb = n0;
-      g2.C = Ifull; g2.ldc = n0;
+      g2.C = Ii; g2.ldc = n0;
       gemm(g2, s);
     } else {
       MM_REQUIRE(c->I.p != nullptr, kState, "mm_probe(MM_CHOLESKY) before any Cholesky step");
-      MM_HIP_TRY(hipMemcpyAsync(Ifull, c->I.p, sizeof(double) * n0, hipMemcpyDeviceToDevice, s));
+      MM_HIP_TRY(hipMemcpyAsync(Ii, c->I.p, sizeof(double) * n0, hipMemcpyDeviceToDevice, s));
+    }
+    if (m == 0) {
+      MM_HIP_TRY(hipMemcpyAsync(Ifull, Ii, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    } else {
+      // I = K Ii + A_D iD = H [Re^{-T} iD ; Ii]
+      const double* iD = (which == MM_MODAL ? c->iD_modal : c->iD_chol).d();
+      electrode_lift(c->RinvT(), iD, m, Ii, n0, Ifull, s);
+      const int64_t wse = apply_h_ws_elems(m, 1);
+      Dev ws;
+      ws.alloc(sizeof(double) * wse);
+      apply_h(c->Vh.d(), c->T(), n, m, Ifull, n, 1, false, ws.d(), wse, s);
+      MM_HIP_TRY(hipStreamSynchronize(s));  // ws is released here
     }
     if (!rows) {
-      MM_HIP_TRY(hipMemcpyAsync(out, Ifull, sizeof(double) * c->n, hipMemcpyDeviceToDevice, s));
+      MM_HIP_TRY(hipMemcpyAsync(out, Ifull, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     } else {
       Gemm g;
-      g.m = n_rows; g.n = 1; g.k = c->n;
-      g.A = rows; g.lda = c->n; g.ta = true;
-      g.B = Ifull; g.ldb = c->n;
+      g.m = n_rows; g.n = 1; g.k = n;
+      g.A = rows; g.lda = n; g.ta = true;
+      g.B = Ifull; g.ldb = n;
       g.C = out; g.ldc = n_rows;
       gemm(g, s);
     }
@@ -440,6 +663,10 @@ mm_status mm_reset_state(mm_ctx* c) {
   return guarded(c, [&] {
     if (c->y.p) fill(c->y.d(), c->n0, 0.0, c->stream);
     if (c->I.p) fill(c->I.d(), c->n0, 0.0, c->stream);
+    if (c->m) {
+      fill(c->iD_modal.d(), c->m, 0.0, c->stream);
+      fill(c->iD_chol.d(), c->m, 0.0, c->stream);
+    }
   });
 }
 

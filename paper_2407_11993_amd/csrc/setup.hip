@@ -6,27 +6,38 @@ namespace mm {
 namespace {
 
 // One thread per element of a column segment; consecutive threads walk
-// consecutive rows, so the column-major stores are contiguous.
+// consecutive rows, so the column-major stores are contiguous.  The optional
+// symmetric low-rank term (the electrode reduction's two-sided Householder
+// update) is subtracted on the fly.
 __global__ void assemble_L_k(const double* __restrict__ xyz, double h, int64_t n,
-                             double* __restrict__ L, int64_t ld, int full) {
+                             double* __restrict__ L, int64_t ld, int full, LowRank lr) {
   const int64_t j = blockIdx.x;
   const double xj = xyz[3 * j], yj = xyz[3 * j + 1], zj = xyz[3 * j + 2];
   const double h2 = h * h;
+  double uj[8], yj_[8];
+  for (int a = 0; a < lr.m; ++a) {
+    uj[a] = lr.U[j + a * lr.ld];
+    yj_[a] = lr.Y1[j + a * lr.ld] + (lr.Y2 ? lr.w2 * lr.Y2[j + a * lr.ld] : 0.0);
+  }
   const int64_t i_begin = full ? 0 : j;
   for (int64_t i = i_begin + threadIdx.x; i < n; i += blockDim.x) {
     const double dx = xyz[3 * i] - xj, dy = xyz[3 * i + 1] - yj, dz = xyz[3 * i + 2] - zj;
-    L[i + j * ld] = h / sqrt(dx * dx + dy * dy + dz * dz + h2);
+    double v = h / sqrt(dx * dx + dy * dy + dz * dz + h2);
+    for (int a = 0; a < lr.m; ++a) {
+      const double ui = lr.U[i + a * lr.ld];
+      const double yi = lr.Y1[i + a * lr.ld] + (lr.Y2 ? lr.w2 * lr.Y2[i + a * lr.ld] : 0.0);
+      v -= ui * yj_[a] + yi * uj[a];
+    }
+    L[i + j * ld] = v;
   }
 }
 
-__global__ void add_csr_lower_k(double* Z, int64_t ld, double alpha, int64_t rows,
-                                const int64_t* rowptr, const int32_t* col,
-                                const double* val) {
+__global__ void add_csr_lower_k(double* Z, int64_t ld, double alpha, Csr R) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= rows) return;
-  for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
-    const int64_t j = col[p];
-    if (j <= i) Z[i + j * ld] += alpha * val[p];
+  if (i >= R.rows) return;
+  for (int64_t p = R.rowptr[i + R.off]; p < R.rowptr[i + R.off + 1]; ++p) {
+    const int64_t j = (int64_t)R.col[p] - R.off;
+    if (j >= 0 && j <= i) Z[i + j * ld] += alpha * R.val[p];
   }
 }
 
@@ -39,17 +50,18 @@ __global__ void csr_band_k(int64_t rows, const int64_t* rowptr, const int32_t* c
   atomicMax(out, (unsigned long long)(j - mn));
 }
 
-// W(:, j) = sum_{p in row j of R} R(j, c_p) A(:, c_p)   (R symmetric)
-__global__ void dense_times_csr_k(const double* __restrict__ A, int64_t lda,
-                                  const int64_t* __restrict__ rowptr,
-                                  const int32_t* __restrict__ col,
-                                  const double* __restrict__ val, int64_t n,
+// W(:, j) = sum_{p in row j of R} R(j, c_p) A(:, c_p)   (R symmetric, logical
+// indices: stored row j + off, columns c >= off shifted by off)
+__global__ void dense_times_csr_k(const double* __restrict__ A, int64_t lda, Csr R, int64_t n,
                                   double* __restrict__ W, int64_t ldw) {
   const int64_t j = blockIdx.x;
-  const int64_t p0 = rowptr[j], p1 = rowptr[j + 1];
+  const int64_t p0 = R.rowptr[j + R.off], p1 = R.rowptr[j + R.off + 1];
   for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
     double s = 0.0;
-    for (int64_t p = p0; p < p1; ++p) s += val[p] * A[i + (int64_t)col[p] * lda];
+    for (int64_t p = p0; p < p1; ++p) {
+      const int64_t c = (int64_t)R.col[p] - R.off;
+      if (c >= 0) s += R.val[p] * A[i + c * lda];
+    }
     W[i + j * ldw] = s;
   }
 }
@@ -93,17 +105,19 @@ unsigned grid1(int64_t count, int per = 256) {
 }  // namespace
 
 void assemble_L(const double* xyz, double h, int64_t n, double* L, int64_t ld,
-                bool full, hipStream_t s) {
+                bool full, hipStream_t s, const LowRank& lr) {
   if (n <= 0) return;
   MM_REQUIRE(n < (int64_t)1 << 31, kInvalid, "assemble_L: n too large");
-  hipLaunchKernelGGL(assemble_L_k, dim3((unsigned)n), dim3(256), 0, s, xyz, h, n, L, ld, (int)full);
+  MM_REQUIRE(lr.m >= 0 && lr.m <= 8 && (lr.m == 0 || (lr.U && lr.Y1)), kInvalid,
+             "assemble_L: bad low-rank term");
+  hipLaunchKernelGGL(assemble_L_k, dim3((unsigned)n), dim3(256), 0, s, xyz, h, n, L, ld,
+                     (int)full, lr);
   MM_HIP_TRY(hipGetLastError());
 }
 
 void add_csr_lower(double* Z, int64_t ld, double alpha, const Csr& R, hipStream_t s) {
   if (R.rows <= 0) return;
-  hipLaunchKernelGGL(add_csr_lower_k, dim3(grid1(R.rows)), dim3(256), 0, s, Z, ld, alpha,
-                     R.rows, R.rowptr, R.col, R.val);
+  hipLaunchKernelGGL(add_csr_lower_k, dim3(grid1(R.rows)), dim3(256), 0, s, Z, ld, alpha, R);
   MM_HIP_TRY(hipGetLastError());
 }
 
@@ -118,8 +132,8 @@ void dense_times_csr(const double* A, int64_t lda, const Csr& R, double* W,
                      int64_t ldw, hipStream_t s) {
   const int64_t n = R.rows;
   if (n <= 0) return;
-  hipLaunchKernelGGL(dense_times_csr_k, dim3((unsigned)n), dim3(256), 0, s, A, lda, R.rowptr, R.col,
-                     R.val, n, W, ldw);
+  hipLaunchKernelGGL(dense_times_csr_k, dim3((unsigned)n), dim3(256), 0, s, A, lda, R, n, W,
+                     ldw);
   MM_HIP_TRY(hipGetLastError());
 }
 

@@ -57,10 +57,55 @@ __global__ void chol_rhs_k(int64_t n0, Csr Ri, Forcing f, double theta, double d
   if (i >= n0) return;
   const int64_t k = *kstep;
   double s = 0.0;
-  for (int64_t p = Ri.rowptr[i]; p < Ri.rowptr[i + 1]; ++p) s += Ri.val[p] * I[Ri.col[p]];
+  for (int64_t p = Ri.rowptr[i + Ri.off]; p < Ri.rowptr[i + Ri.off + 1]; ++p) {
+    const int64_t c = (int64_t)Ri.col[p] - Ri.off;
+    if (c >= 0) s += Ri.val[p] * I[c];
+  }
   double r = -dt * s;
   for (int j = 0; j < f.nf; ++j) r += f.F[i + (int64_t)j * n0] * forcing_u(f, j, k, theta, dt);
   b[i] = r;
+}
+
+// b += dt (V (Y^T I) + Y (V^T I)) on the rows idx: the low-rank part of
+// -dt R_i I when R_i = R'' - V Y^T - Y V^T (one workgroup).
+__global__ void __launch_bounds__(256) lowrank_rhs_k(RLowRank lr, double dt,
+                                                     const double* __restrict__ I,
+                                                     double* __restrict__ b) {
+  constexpr int MAXM = 8;
+  __shared__ double red[2 * MAXM][4];
+  __shared__ double dv[2 * MAXM];  // [0, m): V^T I, [m, 2m): Y^T I
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int m = lr.m;
+  double av[MAXM], ay[MAXM];
+#pragma unroll
+  for (int a = 0; a < MAXM; ++a) av[a] = ay[a] = 0.0;
+  for (int j = t; j < lr.ns; j += 256) {
+    const double x = I[lr.idx[j]];
+#pragma unroll
+    for (int a = 0; a < MAXM; ++a)
+      if (a < m) {
+        av[a] += lr.Vs[j + (int64_t)a * lr.ns] * x;
+        ay[a] += lr.Ys[j + (int64_t)a * lr.ns] * x;
+      }
+  }
+#pragma unroll
+  for (int a = 0; a < MAXM; ++a)
+    if (a < m) {
+      const double v1 = wave_sum(av[a]), v2 = wave_sum(ay[a]);
+      if (lane == 0) {
+        red[a][wave] = v1;
+        red[m + a][wave] = v2;
+      }
+    }
+  __syncthreads();
+  if (t < 2 * m) dv[t] = (red[t][0] + red[t][1]) + (red[t][2] + red[t][3]);
+  __syncthreads();
+  for (int j = t; j < lr.ns; j += 256) {
+    double s = 0.0;
+    for (int a = 0; a < m; ++a)
+      s += lr.Vs[j + (int64_t)a * lr.ns] * dv[m + a] + lr.Ys[j + (int64_t)a * lr.ns] * dv[a];
+    b[lr.idx[j]] += dt * s;
+  }
 }
 
 __global__ void step_inc_k(int64_t* kstep) {
@@ -227,6 +272,8 @@ void enqueue_step(const CholStep& c, hipStream_t s) {
   const unsigned dgrid = (unsigned)ceil_div(B, NT / 64);
   hipLaunchKernelGGL(chol_rhs_k, dim3(rgrid), dim3(256), 0, s, n, c.Ri, c.f, c.theta, c.dt,
                      c.kstep, c.I, c.b);
+  if (c.Rlr.ns > 0)
+    hipLaunchKernelGGL(lowrank_rhs_k, dim3(1), dim3(256), 0, s, c.Rlr, c.dt, c.I, c.b);
   for (int64_t J = 0; J < NB; ++J) {
     hipLaunchKernelGGL(fwd_diag_k, dim3(dgrid), dim3(NT), 0, s, n, B, J, c.DinvT, c.b, c.y);
     const int64_t below = n - (J + 1) * B;
@@ -259,6 +306,8 @@ int64_t trsv_parts(int64_t n) {
 void chol_steps(const CholStep& c, int64_t k0, int64_t n_steps, hipStream_t s) {
   MM_REQUIRE(c.B >= 64 && c.B <= MAXB && c.B % 64 == 0, kInvalid, "chol_steps: block size");
   MM_REQUIRE(c.n_probe <= 8, kInvalid, "chol_steps: at most 8 probes");
+  MM_REQUIRE(c.Rlr.ns == 0 || (c.Rlr.m >= 1 && c.Rlr.m <= 8), kInvalid,
+             "chol_steps: low-rank resistance term of rank 1..8");
   if (n_steps <= 0) return;
   fill_i64(c.kstep, 1, k0, s);
   if (!c.use_graph || n_steps < 4) {
