@@ -102,10 +102,11 @@ struct RLowRank {
 };
 
 // ---- Cholesky theta-method (step_chol.hip) --------------------------------
-// Block size of the triangular solves for order n (128, 256 or 512), and
+// Block size of the triangular solves for order n (256 .. 2048), and
 // the number of probe partial sums they produce per step.
 int trsv_block(int64_t n);
 int64_t trsv_parts(int64_t n);
+
 
 struct Forcing {
   // f^k = F u^k with F (n0 x nf, column-major) and u^k from the waveforms:

@@ -26,8 +26,11 @@ namespace mm {
 namespace {
 
 constexpr int NT = 256;
-constexpr int MAXB = 2048;
+constexpr int MAXB = 4096;
 constexpr int BCOLS = 4;        // backward update: columns per wave
+
+// Workgroups of a diagonal-block kernel: four waves, two rows or columns each.
+__host__ __device__ inline int diag_groups(int B) { return (B / 2 + NT / 64 - 1) / (NT / 64); }
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -112,68 +115,104 @@ __global__ void step_inc_k(int64_t* kstep) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *kstep += 1;
 }
 
-// Forward diagonal block: y_J(r) = sum_{c <= r} Dinv_J(r, c) b_J(c), one wave
-// per output row, reading row r of Dinv_J contiguously from DinvT.
+// Diagonal blocks.  Rows (forward) or columns (backward) p and jb-1-p of the
+// triangular block inverse are folded onto one wave: together they hold
+// jb + 1 entries, so every wave does the same work and issues all of its
+// loads at once (clamped addresses, masked values).  KC load slots per lane:
+// the two rows of a forward pair span at most B / 64 + 1 chunks of 64, the
+// two columns of a backward pair at most B / 64 + 2 (their first chunks need
+// not be aligned).  The right-hand side of the block is staged in LDS once
+// per workgroup.
+// Forward: y_J(r) = sum_{c <= r} Dinv_J(r, c) b_J(c), row r of Dinv_J read
+// contiguously from DinvT.
+template <int KC>
 __global__ void __launch_bounds__(NT) fwd_diag_k(int64_t n, int B, int64_t J,
                                                  const double* __restrict__ DinvT,
                                                  const double* __restrict__ b,
                                                  double* __restrict__ y) {
-  __shared__ double r[MAXB];
+  __shared__ double bs[MAXB];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int64_t J0 = J * B;
   const int jb = (int)min((int64_t)B, n - J0);
-  for (int c = t; c < jb; c += NT) r[c] = b[J0 + c];
+  // a wave past the last pair computes pair 0 again and discards it, so the
+  // barrier below is reached by every thread
+  const int pw = blockIdx.x * (NT / 64) + wave;
+  const bool live = pw < (jb + 1) / 2;
+  const int p = live ? pw : 0;
+  const int r1 = p, r2 = jb - 1 - p;
+  const int n1 = r1 / 64 + 1, n2 = (r2 > r1) ? r2 / 64 + 1 : 0;
+  const double* D1 = DinvT + J * (int64_t)B * B + (int64_t)r1 * B;
+  const double* D2 = DinvT + J * (int64_t)B * B + (int64_t)r2 * B;
+  double dv[KC];
+#pragma unroll
+  for (int v = 0; v < KC; ++v) {
+    const bool sec = v >= n1;
+    dv[v] = (sec ? D2 : D1)[min(64 * (sec ? v - n1 : v) + lane, sec ? r2 : r1)];
+  }
+  // the block's right-hand side, staged while the loads above are in flight
+  for (int c = t; c < jb; c += NT) bs[c] = b[J0 + c];
   __syncthreads();
-  const int row = blockIdx.x * (NT / 64) + wave;
-  if (row >= jb) return;
-  const double* Dr = DinvT + J * (int64_t)B * B + (int64_t)row * B;
-  double s = 0.0;
-#pragma unroll 8
-  for (int c = lane; c <= row; c += 64) s += Dr[c] * r[c];
-  s = wave_sum(s);
-  if (lane == 0) y[J0 + row] = s;
+  double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+  for (int v = 0; v < KC; ++v) {
+    const bool sec = v >= n1;
+    const int rr = sec ? r2 : r1;
+    const int c = 64 * (sec ? v - n1 : v) + lane;
+    const bool ok = v < n1 + n2 && c <= rr;
+    const double val = ok ? dv[v] * bs[min(c, rr)] : 0.0;
+    if (sec) s2 += val;
+    else s1 += val;
+  }
+  s1 = wave_sum(s1);
+  s2 = wave_sum(s2);
+  if (live && lane == 0) {
+    y[J0 + r1] = s1;
+    if (r2 > r1) y[J0 + r2] = s2;
+  }
 }
 
-// Forward update: b_i -= sum_c C(i, J0 + c) y_J(c) for rows i >= J0 + B.
-// Workgroup: 16 rows x B columns (four 128-byte row segments per wave load).
-// Wave w owns columns [w B/4, (w+1) B/4); lane (r, g) = (lane % 16, lane / 16)
-// reads row r of columns g, g+4, g+8, ... of that range.
-__global__ void __launch_bounds__(NT) fwd_update_k(int64_t n, int B, int64_t J,
-                                                   const double* __restrict__ C, int64_t ld,
-                                                   const double* __restrict__ y,
-                                                   double* __restrict__ b) {
-  __shared__ double yj[MAXB];
-  __shared__ double part[NT / 64][16];
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int r = lane & 15, g = lane >> 4;
+// Forward panel update  b_i -= sum_c C(i, J0 + c) y_J(c)  for the rows
+// i >= J0 + B.  Workgroup: a tile of 64 rows (one per lane, so every wave
+// load is one contiguous 512-byte column segment) times all B columns of the
+// panel, which its UW waves take in turn, UL columns at a time: each wave
+// keeps UL loads in flight.  The waves' row sums are combined in LDS in wave
+// order (deterministic, no atomics).
+constexpr int UW = 16;  // waves per forward-update workgroup
+constexpr int UL = 16;  // column loads in flight per wave
+__global__ void __launch_bounds__(64 * UW) fwd_update_k(int64_t n, int B, int64_t J,
+                                                        const double* __restrict__ C, int64_t ld,
+                                                        const double* __restrict__ y,
+                                                        double* __restrict__ b) {
+  __shared__ double red[UW][64];
+  const int t = threadIdx.x, lane = t & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);  // wave-uniform: y via scalar loads
   const int64_t J0 = J * B;
-  for (int c = t; c < B; c += NT) yj[c] = y[J0 + c];  // J is not the last block
-  __syncthreads();
-  const int64_t row = J0 + B + (int64_t)blockIdx.x * 16 + r;
-  const int cq = B / 4;
-  double s = 0.0;
-  if (row < n) {
-    const double* Cp = C + row + (J0 + (int64_t)wave * cq + g) * ld;
-    const double* yp = yj + wave * cq + g;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 16
-    for (int c = 0; c < cq / 4; ++c) acc[c & 3] += Cp[(int64_t)(4 * c) * ld] * yp[4 * c];
-    s = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  const int64_t row = J0 + B + (int64_t)blockIdx.x * 64 + lane;
+  const double* Cp = C + min(row, n - 1) + J0 * ld;  // clamped: rows past n are not stored
+  const double* yp = y + J0;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  // B is a multiple of UW * UL = 256 columns
+  for (int q0 = wave * UL; q0 < B; q0 += UW * UL) {
+    double cv[UL];
+#pragma unroll
+    for (int u = 0; u < UL; ++u) cv[u] = Cp[(int64_t)(q0 + u) * ld];
+    __builtin_amdgcn_sched_barrier(0);  // all UL loads issue before the first use
+#pragma unroll
+    for (int u = 0; u < UL; ++u) acc[u & 3] += cv[u] * yp[q0 + u];
   }
-  // lanes r, r+16, r+32, r+48 hold the same row
-  s += __shfl_xor(s, 16, 64);
-  s += __shfl_xor(s, 32, 64);
-  if (lane < 16) part[wave][lane] = s;
+  red[wave][lane] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
   __syncthreads();
-  if (t < 16) {
-    const int64_t rr = J0 + B + (int64_t)blockIdx.x * 16 + t;
-    if (rr < n) b[rr] -= (part[0][t] + part[1][t]) + (part[2][t] + part[3][t]);
-  }
+  if (wave != 0) return;
+  double v = 0.0;
+#pragma unroll
+  for (int w = 0; w < UW; ++w) v += red[w][lane];
+  if (row < n) b[row] -= v;
 }
 
-// Backward diagonal block: x_J(c) = sum_{r >= c} Dinv_J(r, c) y_J(r), one wave
-// per output (column c of Dinv_J, contiguous).  Fused: Ii += x_J and the probe
-// partial sums of this workgroup's outputs.
+// Backward: x_J(c) = sum_{r >= c} Dinv_J(r, c) y_J(r), column c of Dinv_J
+// read contiguously.  Fused: Ii += x_J and the probe partial sums of this
+// workgroup's outputs (one per workgroup and probe, fixed order).
+template <int KC>
 __global__ void __launch_bounds__(NT) bwd_diag_k(int64_t n, int B, int64_t J,
                                                  const double* __restrict__ Dinv,
                                                  const double* __restrict__ y,
@@ -181,61 +220,112 @@ __global__ void __launch_bounds__(NT) bwd_diag_k(int64_t n, int B, int64_t J,
                                                  const double* __restrict__ Pt, int n_probe,
                                                  double* __restrict__ pp_base,
                                                  const int64_t* kstep, int64_t parts) {
-  __shared__ double r[MAXB];
+  __shared__ double ys[MAXB];
   __shared__ double red[8][NT / 64];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int64_t J0 = J * B;
   const int jb = (int)min((int64_t)B, n - J0);
-  for (int c = t; c < jb; c += NT) r[c] = y[J0 + c];
-  __syncthreads();
-  const int c = blockIdx.x * (NT / 64) + wave;
-  double out = 0.0;
-  if (c < jb) {
-    const double* Dc = Dinv + J * (int64_t)B * B + (int64_t)c * B;
-    double s = 0.0;
-#pragma unroll 8
-    for (int rr = c + lane; rr < jb; rr += 64) s += Dc[rr] * r[rr];
-    out = wave_sum(s);
-    if (lane == 0) {
-      x[J0 + c] = out;
-      state[J0 + c] += out;
+  // a wave past the last pair computes pair 0 again and discards it, so the
+  // barrier below is reached by every thread
+  const int pw = blockIdx.x * (NT / 64) + wave;
+  const bool live = pw < (jb + 1) / 2;
+  const int p = live ? pw : 0;
+  const int c1 = p, c2 = jb - 1 - p;
+  double o1 = 0.0, o2 = 0.0;
+  {
+    const int last = (jb - 1) / 64;  // chunk of the block's last row
+    const int f1 = c1 / 64, f2 = c2 / 64;
+    const int n1 = last - f1 + 1, n2 = (c2 > c1) ? last - f2 + 1 : 0;
+    const double* D1 = Dinv + J * (int64_t)B * B + (int64_t)c1 * B;
+    const double* D2 = Dinv + J * (int64_t)B * B + (int64_t)c2 * B;
+    double dv[KC];
+#pragma unroll
+    for (int v = 0; v < KC; ++v) {
+      const bool sec = v >= n1;
+      const int r = 64 * (sec ? f2 + (v - n1) : f1 + v) + lane;
+      dv[v] = (sec ? D2 : D1)[min(max(r, sec ? c2 : c1), jb - 1)];
+    }
+    // the block's right-hand side, staged while the loads above are in flight
+    for (int c = t; c < jb; c += NT) ys[c] = y[J0 + c];
+    __syncthreads();
+    double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+    for (int v = 0; v < KC; ++v) {
+      const bool sec = v >= n1;
+      const int cc0 = sec ? c2 : c1;
+      const int r = 64 * (sec ? f2 + (v - n1) : f1 + v) + lane;
+      const bool ok = v < n1 + n2 && r >= cc0 && r < jb;
+      const double val = ok ? dv[v] * ys[min(max(r, cc0), jb - 1)] : 0.0;
+      if (sec) s2 += val;
+      else s1 += val;
+    }
+    o1 = live ? wave_sum(s1) : 0.0;
+    o2 = live ? wave_sum(s2) : 0.0;
+    if (live && lane == 0) {
+      x[J0 + c1] = o1;
+      state[J0 + c1] += o1;
+      if (c2 > c1) {
+        x[J0 + c2] = o2;
+        state[J0 + c2] += o2;
+      }
     }
   }
-  // probe partials: one per (block J, workgroup), fixed order over the waves
   const int64_t k = *kstep;
-  for (int p = 0; p < n_probe; ++p)
-    if (lane == 0) red[p][wave] = (c < jb) ? Pt[(J0 + c) + (int64_t)p * n] * out : 0.0;
+  for (int q = 0; q < n_probe; ++q)
+    if (lane == 0) {
+      double v = 0.0;
+      if (live) {
+        v = Pt[(J0 + c1) + (int64_t)q * n] * o1;
+        if (c2 > c1) v += Pt[(J0 + c2) + (int64_t)q * n] * o2;
+      }
+      red[q][wave] = v;
+    }
   __syncthreads();
   if (t < n_probe) {
-    const int64_t part_idx = J * ((B + NT / 64 - 1) / (NT / 64)) + blockIdx.x;
+    const int64_t part_idx = J * diag_groups(B) + blockIdx.x;
     pp_base[(k * parts + part_idx) * n_probe + t] =
         (red[t][0] + red[t][1]) + (red[t][2] + red[t][3]);
   }
 }
 
-// Backward update: y_c -= sum_r C(J0 + r, c) x_J(r) for columns c < J0.
-// Each wave handles BCOLS columns at once (contiguous segments of B rows).
+// Backward update  y_c -= sum_r C(J0 + r, c) x_J(r)  for the columns c < J0.
+// Each wave owns BCOLS columns over all of block J's rows; lanes walk the
+// rows, so every load is a contiguous 512-byte column segment, and RB row
+// chunks of all BCOLS columns are loaded before any is used (BCOLS * RB
+// loads in flight per wave).
+constexpr int RB = 4;
 __global__ void __launch_bounds__(NT) bwd_update_k(int64_t n, int B, int64_t J,
                                                    const double* __restrict__ C, int64_t ld,
                                                    const double* __restrict__ x,
                                                    double* __restrict__ y) {
-  __shared__ double xj[MAXB];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int64_t J0 = J * B;
   const int jb = (int)min((int64_t)B, n - J0);
-  for (int c = t; c < jb; c += NT) xj[c] = x[J0 + c];
-  __syncthreads();
   const int64_t col0 = ((int64_t)blockIdx.x * (NT / 64) + wave) * BCOLS;
   double s[BCOLS];
 #pragma unroll
   for (int q = 0; q < BCOLS; ++q) s[q] = 0.0;
   // J > 0 here, so block J starts at J0 >= B and col0 + q < J0 <= n - jb:
-  // every column pointer below stays inside the matrix.
+  // every (clamped) column pointer below stays inside the matrix.
   const double* Cc[BCOLS];
 #pragma unroll
   for (int q = 0; q < BCOLS; ++q) Cc[q] = C + J0 + min(col0 + q, J0 - 1) * ld;
-#pragma unroll 4
-  for (int rr = lane; rr < jb; rr += 64) {
+  const double* xj = x + J0;
+  int rr = lane;
+  for (; rr + 64 * (RB - 1) < jb; rr += 64 * RB) {
+    double cv[RB][BCOLS], xv[RB];
+#pragma unroll
+    for (int u = 0; u < RB; ++u) {
+      xv[u] = xj[rr + 64 * u];
+#pragma unroll
+      for (int q = 0; q < BCOLS; ++q) cv[u][q] = Cc[q][rr + 64 * u];
+    }
+#pragma unroll
+    for (int u = 0; u < RB; ++u)
+#pragma unroll
+      for (int q = 0; q < BCOLS; ++q) s[q] += cv[u][q] * xv[u];
+  }
+  for (; rr < jb; rr += 64) {
     const double xv = xj[rr];
 #pragma unroll
     for (int q = 0; q < BCOLS; ++q) s[q] += Cc[q][rr] * xv;
@@ -262,6 +352,28 @@ __global__ void probe_finish_k(const double* pp, int64_t n_steps, int64_t nparts
   signal[e] = s / dt;
 }
 
+template <int C64>  // C64 = B / 64
+void launch_diag_b(bool fwd, unsigned grid, hipStream_t s, int64_t n, int64_t J,
+                   const CholStep& c) {
+  if (fwd)
+    hipLaunchKernelGGL((fwd_diag_k<C64 + 1>), dim3(grid), dim3(NT), 0, s, n, c.B, J, c.DinvT,
+                       c.b, c.y);
+  else
+    hipLaunchKernelGGL((bwd_diag_k<C64 + 2>), dim3(grid), dim3(NT), 0, s, n, c.B, J, c.Dinv,
+                       c.y, c.b, c.I, c.Pt, c.n_probe, c.probe_partial, c.kstep, trsv_parts(n));
+}
+void launch_diag(bool fwd, int B, unsigned grid, hipStream_t s, int64_t n, int64_t J,
+                 const CholStep& c) {
+  switch (B) {
+    case 256: launch_diag_b<4>(fwd, grid, s, n, J, c); break;
+    case 512: launch_diag_b<8>(fwd, grid, s, n, J, c); break;
+    case 1024: launch_diag_b<16>(fwd, grid, s, n, J, c); break;
+    case 2048: launch_diag_b<32>(fwd, grid, s, n, J, c); break;
+    case 4096: launch_diag_b<64>(fwd, grid, s, n, J, c); break;
+    default: throw Error{kInvalid, "triangular solve: unsupported block size"};
+  }
+}
+
 // One step's launch sequence (the step index is read from *kstep).
 void enqueue_step(const CholStep& c, hipStream_t s) {
   const int64_t n = c.n0;
@@ -269,21 +381,20 @@ void enqueue_step(const CholStep& c, hipStream_t s) {
   const int64_t NB = ceil_div(n, B);
   const int64_t parts = trsv_parts(n);
   const unsigned rgrid = (unsigned)ceil_div(n, 256);
-  const unsigned dgrid = (unsigned)ceil_div(B, NT / 64);
+  const unsigned dgrid = (unsigned)diag_groups(B);
   hipLaunchKernelGGL(chol_rhs_k, dim3(rgrid), dim3(256), 0, s, n, c.Ri, c.f, c.theta, c.dt,
                      c.kstep, c.I, c.b);
   if (c.Rlr.ns > 0)
     hipLaunchKernelGGL(lowrank_rhs_k, dim3(1), dim3(256), 0, s, c.Rlr, c.dt, c.I, c.b);
   for (int64_t J = 0; J < NB; ++J) {
-    hipLaunchKernelGGL(fwd_diag_k, dim3(dgrid), dim3(NT), 0, s, n, B, J, c.DinvT, c.b, c.y);
+    launch_diag(true, B, dgrid, s, n, J, c);
     const int64_t below = n - (J + 1) * B;
     if (below > 0)
-      hipLaunchKernelGGL(fwd_update_k, dim3((unsigned)ceil_div(below, 16)), dim3(NT), 0, s, n, B,
-                         J, c.Cf, c.ld, c.y, c.b);
+      hipLaunchKernelGGL(fwd_update_k, dim3((unsigned)ceil_div(below, 64)), dim3(64 * UW), 0, s,
+                         n, B, J, c.Cf, c.ld, c.y, c.b);
   }
   for (int64_t J = NB - 1; J >= 0; --J) {
-    hipLaunchKernelGGL(bwd_diag_k, dim3(dgrid), dim3(NT), 0, s, n, B, J, c.Dinv, c.y, c.b, c.I,
-                       c.Pt, c.n_probe, c.probe_partial, c.kstep, parts);
+    launch_diag(false, B, dgrid, s, n, J, c);
     const int64_t J0 = J * B;
     if (J0 > 0)
       hipLaunchKernelGGL(bwd_update_k, dim3((unsigned)ceil_div(J0, (NT / 64) * BCOLS)), dim3(NT),
@@ -295,16 +406,21 @@ void enqueue_step(const CholStep& c, hipStream_t s) {
 }  // namespace
 
 int trsv_block(int64_t n) {
-  return n >= 16384 ? 2048 : (n >= 8192 ? 1024 : (n >= 2048 ? 512 : 128));
+  // about eight diagonal blocks, at most 2048: fewer, larger launches (4096
+  // measured no faster at N = 16384 and doubles the inverse blocks' memory)
+  int B = 256;
+  while (B < 2048 && 8 * (int64_t)(2 * B) <= n) B *= 2;
+  return B;
 }
 
 int64_t trsv_parts(int64_t n) {
   const int B = trsv_block(n);
-  return ceil_div(n, B) * ceil_div(B, NT / 64);
+  return ceil_div(n, B) * diag_groups(B);
 }
 
 void chol_steps(const CholStep& c, int64_t k0, int64_t n_steps, hipStream_t s) {
-  MM_REQUIRE(c.B >= 64 && c.B <= MAXB && c.B % 64 == 0, kInvalid, "chol_steps: block size");
+  MM_REQUIRE(c.B == 256 || c.B == 512 || c.B == 1024 || c.B == 2048 || c.B == 4096, kInvalid,
+             "chol_steps: block size must be a power of two in [256, 4096]");
   MM_REQUIRE(c.n_probe <= 8, kInvalid, "chol_steps: at most 8 probes");
   MM_REQUIRE(c.Rlr.ns == 0 || (c.Rlr.m >= 1 && c.Rlr.m <= 8), kInvalid,
              "chol_steps: low-rank resistance term of rank 1..8");
