@@ -68,9 +68,9 @@ typedef struct {
   const int64_t* e_rowptr;
   const int32_t* e_col;
   const double* e_val;
-  int32_t n_src;            /* solenoidal sources (columns of M0), >= 0 */
+  int32_t n_src;            /* solenoidal sources (columns of M0), 0..4096 */
   const double* M0;         /* n x n_src, column-major */
-  int32_t n_probe;          /* probe rows, 1..8 */
+  int32_t n_probe;          /* probe rows, 1..4096 */
   const double* P;          /* n x n_probe, column-major: column p is probe
                                row p; signal_p = P(:,p)^T dI/dt */
 } mm_problem;
@@ -127,6 +127,37 @@ mm_status mm_reset_state(mm_ctx* ctx);
 /* Eigenvalues lam_n = 1/tau_n of the reduced pencil, ascending (n0 doubles,
  * device).  Requires mm_decompose. */
 mm_status mm_eigenvalues(mm_ctx* ctx, double* out);
+
+/* ---- Batched modal runs ----------------------------------------------------
+ * Many independent runs of the modal theta-method (Sec. 3.3.2) in one launch:
+ * run r drives source src[r] (a column of M0) with its own waveform and
+ * observes probe probe[r] (a column of P), from a zero state, for lens[r]
+ * steps; injected currents are zero.  One mode group of one run per
+ * workgroup; every thread keeps its modes in registers for the whole run.
+ *   lens, src, probe: HOST arrays of n_runs entries.
+ *   waves:   device, packed waveforms: run r's samples at t_k = k dt,
+ *            k = 0..lens[r], start at sum_{q<r} (lens[q] + 1).
+ *   signals: device, packed outputs: run r's lens[r] samples start at
+ *            sum_{q<r} lens[q]; s^{k+1} = P(:, probe)^T dI^k / dt as for
+ *            mm_step_modal.
+ *   tile:    -1 = autotune (each workgroup shape is timed on the batch cut
+ *            to 256 steps per run, the fastest kept), or an index 0..5 into
+ *            the library's tile list (threads x modes per thread:
+ *            256x1, 256x2, 256x4, 128x4, 256x8, 128x8).
+ * The plan keeps the waves and signals pointers: mm_batch_run replays one
+ * captured HIP graph (stepping launch + signal pass) on the context's
+ * stream; refill `waves` in place between runs.  Requires mm_decompose;
+ * the plan must be destroyed before its context. */
+typedef struct mm_batch mm_batch;
+mm_status mm_batch_create(mm_ctx* ctx, double theta, double dt, int32_t n_runs,
+                          const int64_t* lens, const int32_t* src, const int32_t* probe,
+                          const double* waves, double* signals, int32_t tile,
+                          mm_batch** out);
+mm_status mm_batch_run(mm_batch* batch);
+/* out[0] = threads per workgroup, out[1] = modes per thread, out[2] = mode
+ * groups per run, out[3] = total steps (sum of lens). */
+mm_status mm_batch_info(const mm_batch* batch, int64_t* out);
+void mm_batch_destroy(mm_batch* batch);
 
 /* Sizes: out[0] = n, out[1] = n0 = n - (Ne-1), out[2] = decomposed (0/1). */
 mm_status mm_info(const mm_ctx* ctx, int64_t* out /* host, 3 */);

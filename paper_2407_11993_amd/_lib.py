@@ -23,7 +23,8 @@ MM_CHOLESKY = 1
 # Every exported entry point of include/mm.h.
 SYMBOLS = ["mm_setup", "mm_decompose", "mm_step_modal", "mm_step_cholesky",
            "mm_probe", "mm_reset_state", "mm_eigenvalues", "mm_info",
-           "mm_destroy", "mm_last_error", "mmk_dgemm", "mmk_dpotrf",
+           "mm_destroy", "mm_last_error", "mm_batch_create", "mm_batch_run",
+           "mm_batch_info", "mm_batch_destroy", "mmk_dgemm", "mmk_dpotrf",
            "mmk_dtrtri", "mmk_dsy2sb", "mmk_dsb2st", "mmk_dstedc", "mmk_dsyevd"]
 
 
@@ -62,6 +63,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "mm_info": [vp, ctypes.POINTER(ctypes.c_int64)],
         "mm_destroy": [vp],
         "mm_last_error": [vp],
+        "mm_batch_create": [vp, dbl, dbl, i32, ctypes.POINTER(ctypes.c_int64),
+                            ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                            vp, vp, i32, ctypes.POINTER(vp)],
+        "mm_batch_run": [vp],
+        "mm_batch_info": [vp, ctypes.POINTER(ctypes.c_int64)],
+        "mm_batch_destroy": [vp],
         "mmk_dgemm": [i32, i32, i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64, vp],
         "mmk_dpotrf": [i64, vp, i64, ctypes.POINTER(ctypes.c_int64), vp],
         "mmk_dtrtri": [i64, vp, i64, vp],
@@ -73,7 +80,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     for name, args in sigs.items():
         fn = getattr(lib, name)
         fn.argtypes = args
-        fn.restype = None if name == "mm_destroy" else (
+        fn.restype = None if name in ("mm_destroy", "mm_batch_destroy") else (
             ctypes.c_char_p if name == "mm_last_error" else ctypes.c_int)
     return lib
 

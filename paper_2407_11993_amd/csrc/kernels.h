@@ -163,4 +163,36 @@ struct ModalStep {
 int modal_groups(int64_t n0);
 void modal_steps(const ModalStep& m, int64_t k0, int64_t n_steps, hipStream_t s);
 
+// Batched runs of the modal theta-method: run r drives one forcing column
+// wcol[r] of W with its own waveform (samples waves[woff[r] + k], k = 0..lens[r])
+// and observes one probe column pcol[r] of Pm, from a zero state.  Run
+// order[j] is placed on grid row j (longest first balances the tail).
+struct BatchStep {
+  int64_t n0 = 0;
+  const double* lam = nullptr;
+  const double* W = nullptr;   // n0 x (columns), leading dimension ldw
+  int64_t ldw = 0;
+  const double* Pm = nullptr;  // n0 x (columns), leading dimension n0
+  double theta = 0.5, dt = 1.0;
+  int n_runs = 0;
+  const int32_t* order = nullptr;
+  const int64_t* lens = nullptr;
+  const int64_t* woff = nullptr;
+  const int64_t* soff = nullptr;  // first signal index of each run
+  const int32_t* wcol = nullptr;
+  const int32_t* pcol = nullptr;
+  const double* waves = nullptr;
+  double* partial = nullptr;      // (sum of lens) x G
+  int G = 0;                      // mode groups per run (batch_groups)
+};
+struct BatchTile {
+  int threads, modes;  // threads per workgroup, modes per thread
+};
+extern const BatchTile kBatchTiles[];
+extern const int kNumBatchTiles;
+int batch_groups(int64_t n0, int tile);
+// The stepping launch, then (if signal) signal[e] = sum_g partial[e G + g] / dt.
+void batch_steps(const BatchStep& b, int tile, int64_t total_steps, double* signal,
+                 hipStream_t s);
+
 }  // namespace mm

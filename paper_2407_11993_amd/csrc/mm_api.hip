@@ -3,6 +3,7 @@
 // directory.
 #include "mm.h"
 
+#include <algorithm>
 #include <climits>
 #include <cstdlib>
 #include <cstring>
@@ -47,7 +48,9 @@ struct Dev {
   double* d() const { return static_cast<double*>(p); }
 };
 
-constexpr int kBand = 64;  // bandwidth of the first tridiagonalisation stage
+constexpr int kBand = 64;         // bandwidth of the first tridiagonalisation stage
+constexpr int kMaxColumns = 4096;  // sources, probes
+constexpr int kMaxRunColumns = 8;  // forcing columns and probes of one stepping call
 
 int64_t eig_ws_elems(int64_t n, int nb) {
   int64_t w = std::max(sy2sb_ws_elems(n, nb), stedc_ws_elems(n));
@@ -154,6 +157,12 @@ void check_steps(double theta, double dt, int64_t n_steps) {
   MM_REQUIRE(theta >= 0.0 && theta <= 1.0, kInvalid, "theta must lie in [0, 1]");
   MM_REQUIRE(dt > 0.0, kInvalid, "dt must be positive");
   MM_REQUIRE(n_steps >= 0, kInvalid, "n_steps must be >= 0");
+}
+
+void check_run_columns(const mm_ctx* c) {
+  MM_REQUIRE(c->nf <= kMaxRunColumns && c->n_probe <= kMaxRunColumns, kInvalid,
+             "a stepping call drives at most 8 forcing columns (2(Ne-1) + n_src) and 8 probes; "
+             "use mm_batch for many sources or probes");
 }
 
 // Factor `A` (n x n) in place and report the first bad pivot.
@@ -328,10 +337,10 @@ mm_status mm_setup(const mm_problem* pb, void* stream, mm_ctx** out) {
     MM_REQUIRE(pb->h > 0.0, kInvalid, "h must be positive");
     MM_REQUIRE(pb->xyz && pb->r_rowptr && pb->r_col && pb->r_val, kInvalid,
                "xyz and R are required");
-    MM_REQUIRE(pb->n_probe >= 1 && pb->n_probe <= 8 && pb->P, kInvalid,
-               "1..8 probe rows are required");
-    MM_REQUIRE(pb->n_src >= 0 && pb->n_src <= 8 && (pb->n_src == 0 || pb->M0), kInvalid,
-               "0..8 sources");
+    MM_REQUIRE(pb->n_probe >= 1 && pb->n_probe <= kMaxColumns && pb->P, kInvalid,
+               "1..4096 probe rows are required");
+    MM_REQUIRE(pb->n_src >= 0 && pb->n_src <= kMaxColumns && (pb->n_src == 0 || pb->M0),
+               kInvalid, "0..4096 sources");
     MM_REQUIRE(pb->n_e == 0 || (pb->n_e >= 2 && pb->n_e - 1 < pb->n), kInvalid,
                "Ne must be 0 or 2..n");
     c->stream = (hipStream_t)stream;
@@ -344,7 +353,7 @@ mm_status mm_setup(const mm_problem* pb, void* stream, mm_ctx** out) {
     c->n_src = pb->n_src;
     c->n_probe = pb->n_probe;
     c->nf = 2 * (int)c->m + c->n_src;
-    MM_REQUIRE(c->nf <= 8, kInvalid, "too many forcing terms (2(Ne-1) + n_src <= 8)");
+    MM_REQUIRE(2 * c->m <= 8, kInvalid, "at most 5 electrodes");
     c->h = pb->h;
     c->r_nnz = pb->r_nnz;
     copy_in(c->xyz, pb->xyz, sizeof(double) * 3 * c->n, s);
@@ -505,6 +514,7 @@ mm_status mm_step_modal(mm_ctx* c, double theta, double dt, int64_t n_steps,
   return guarded(c, [&] {
     MM_REQUIRE(c->decomposed, kState, "mm_step_modal before mm_decompose");
     check_steps(theta, dt, n_steps);
+    check_run_columns(c);
     MM_REQUIRE(c->n_src == 0 || i_src, kInvalid, "i_src is required");
     MM_REQUIRE(c->m == 0 || i_D, kInvalid, "i_D is required");
     MM_REQUIRE(signal || n_steps == 0, kInvalid, "signal is required");
@@ -537,6 +547,7 @@ mm_status mm_step_cholesky(mm_ctx* c, double theta, double dt, int64_t n_steps,
   if (!c) return MM_E_INVALID;
   return guarded(c, [&] {
     check_steps(theta, dt, n_steps);
+    check_run_columns(c);
     MM_REQUIRE(c->n_src == 0 || i_src, kInvalid, "i_src is required");
     MM_REQUIRE(c->m == 0 || i_D, kInvalid, "i_D is required");
     MM_REQUIRE(signal || n_steps == 0, kInvalid, "signal is required");
@@ -678,6 +689,189 @@ mm_status mm_eigenvalues(mm_ctx* c, double* out) {
     MM_HIP_TRY(hipMemcpyAsync(out, c->lam.p, sizeof(double) * c->n0, hipMemcpyDeviceToDevice,
                               c->stream));
   });
+}
+
+}  // extern "C"
+
+struct mm_batch {
+  mm_ctx* ctx = nullptr;
+  int n_runs = 0;
+  int64_t total_steps = 0;
+  int tile = 0;
+  BatchStep bs;
+  Dev order, lens, woff, soff, wcol, pcol, partial;
+  double* signals = nullptr;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~mm_batch() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+};
+
+namespace {
+
+template <class T>
+void upload(Dev& d, const std::vector<T>& v, hipStream_t s) {
+  d.alloc(sizeof(T) * std::max<size_t>(1, v.size()));
+  if (!v.empty())
+    MM_HIP_TRY(hipMemcpyAsync(d.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s));
+}
+
+// Time one launch of tile `tile` on the batch truncated to `tcap` steps per
+// run (the autotuner's sample).
+float time_tile(mm_batch* b, int tile, int64_t tcap, hipStream_t s) {
+  const int n = b->n_runs;
+  std::vector<int64_t> lens(n), soff(n);
+  std::vector<int64_t> hl(n);
+  MM_HIP_TRY(hipMemcpyAsync(hl.data(), b->lens.p, sizeof(int64_t) * n, hipMemcpyDeviceToHost, s));
+  MM_HIP_TRY(hipStreamSynchronize(s));
+  int64_t acc = 0;
+  for (int r = 0; r < n; ++r) {
+    lens[r] = std::min(hl[r], tcap);
+    soff[r] = acc;
+    acc += lens[r];
+  }
+  Dev dl, ds, part;
+  upload(dl, lens, s);
+  upload(ds, soff, s);
+  BatchStep t = b->bs;
+  t.lens = dl.as<int64_t>();
+  t.soff = ds.as<int64_t>();
+  t.G = batch_groups(t.n0, tile);
+  part.alloc(sizeof(double) * std::max<int64_t>(1, acc) * t.G);
+  t.partial = part.d();
+  hipEvent_t e0, e1;
+  MM_HIP_TRY(hipEventCreate(&e0));
+  MM_HIP_TRY(hipEventCreate(&e1));
+  batch_steps(t, tile, 0, nullptr, s);  // warm-up
+  MM_HIP_TRY(hipEventRecord(e0, s));
+  batch_steps(t, tile, 0, nullptr, s);
+  batch_steps(t, tile, 0, nullptr, s);
+  MM_HIP_TRY(hipEventRecord(e1, s));
+  MM_HIP_TRY(hipEventSynchronize(e1));
+  float ms = 0.f;
+  MM_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ms;
+}
+
+}  // namespace
+
+extern "C" {
+
+mm_status mm_batch_create(mm_ctx* c, double theta, double dt, int32_t n_runs,
+                          const int64_t* lens, const int32_t* src, const int32_t* probe,
+                          const double* waves, double* signals, int32_t tile, mm_batch** out) {
+  if (!c || !out) return MM_E_INVALID;
+  *out = nullptr;
+  mm_batch* b = nullptr;
+  mm_status st = guarded(c, [&] {
+    MM_REQUIRE(c->decomposed, kState, "mm_batch_create before mm_decompose");
+    check_steps(theta, dt, 0);
+    MM_REQUIRE(n_runs >= 1 && lens && src && probe, kInvalid, "n_runs >= 1, lens, src, probe");
+    MM_REQUIRE(tile >= -1 && tile < kNumBatchTiles, kInvalid, "tile must be -1 or a tile index");
+    b = new mm_batch();
+    b->ctx = c;
+    b->n_runs = n_runs;
+    hipStream_t s = c->stream;
+    std::vector<int64_t> hl(n_runs), woff(n_runs), soff(n_runs);
+    std::vector<int32_t> wcol(n_runs), pcol(n_runs), order(n_runs);
+    int64_t ws = 0, ss = 0;
+    for (int r = 0; r < n_runs; ++r) {
+      MM_REQUIRE(lens[r] >= 0, kInvalid, "run lengths must be >= 0");
+      MM_REQUIRE(src[r] >= 0 && src[r] < c->n_src, kInvalid, "source index out of range");
+      MM_REQUIRE(probe[r] >= 0 && probe[r] < c->n_probe, kInvalid, "probe index out of range");
+      hl[r] = lens[r];
+      woff[r] = ws;
+      soff[r] = ss;
+      ws += lens[r] + 1;
+      ss += lens[r];
+      wcol[r] = 2 * (int32_t)c->m + src[r];  // forcing column of source src[r]
+      pcol[r] = probe[r];
+      order[r] = r;
+    }
+    MM_REQUIRE(ss == 0 || (waves && signals), kInvalid, "waves and signals are required");
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int q) { return hl[a] > hl[q]; });  // longest first
+    b->total_steps = ss;
+    b->signals = signals;
+    upload(b->order, order, s);
+    upload(b->lens, hl, s);
+    upload(b->woff, woff, s);
+    upload(b->soff, soff, s);
+    upload(b->wcol, wcol, s);
+    upload(b->pcol, pcol, s);
+    BatchStep& t = b->bs;
+    t.n0 = c->n0;
+    t.lam = c->lam.d();
+    t.W = c->Wm.d();
+    t.ldw = c->n0;
+    t.Pm = c->Pm.d();
+    t.theta = theta;
+    t.dt = dt;
+    t.n_runs = n_runs;
+    t.order = b->order.as<int32_t>();
+    t.lens = b->lens.as<int64_t>();
+    t.woff = b->woff.as<int64_t>();
+    t.soff = b->soff.as<int64_t>();
+    t.wcol = b->wcol.as<int32_t>();
+    t.pcol = b->pcol.as<int32_t>();
+    t.waves = waves;
+    // autotuner: time every tile on the batch cut to 256 steps per run
+    if (tile < 0) {
+      float best = 0.f;
+      for (int q = 0; q < kNumBatchTiles; ++q) {
+        const float ms = time_tile(b, q, 256, s);
+        if (q == 0 || ms < best) {
+          best = ms;
+          tile = q;
+        }
+      }
+    }
+    b->tile = tile;
+    t.G = batch_groups(c->n0, tile);
+    b->partial.alloc(sizeof(double) * std::max<int64_t>(1, ss) * t.G);
+    t.partial = b->partial.d();
+    // one graph: the stepping launch and the signal pass
+    MM_HIP_TRY(hipStreamSynchronize(s));
+    MM_HIP_TRY(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+    MM_HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    batch_steps(t, tile, ss, signals, b->cap);
+    MM_HIP_TRY(hipStreamEndCapture(b->cap, &b->graph));
+    MM_HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  });
+  if (st != MM_OK) {
+    delete b;
+    return st;
+  }
+  *out = b;
+  return MM_OK;
+}
+
+mm_status mm_batch_run(mm_batch* b) {
+  if (!b) return MM_E_INVALID;
+  return guarded(b->ctx, [&] {
+    MM_HIP_TRY(hipGraphLaunch(b->exec, b->ctx->stream));
+  });
+}
+
+mm_status mm_batch_info(const mm_batch* b, int64_t* out) {
+  if (!b || !out) return MM_E_INVALID;
+  out[0] = kBatchTiles[b->tile].threads;
+  out[1] = kBatchTiles[b->tile].modes;
+  out[2] = b->bs.G;
+  out[3] = b->total_steps;
+  return MM_OK;
+}
+
+void mm_batch_destroy(mm_batch* b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->ctx->stream);
+  delete b;
 }
 
 mm_status mm_info(const mm_ctx* c, int64_t* out) {

@@ -94,7 +94,148 @@ void launch_np(const ModalStep& m, int64_t n_steps, hipStream_t s, dim3 grid) {
   else hipLaunchKernelGGL((modal_step_k<NF, 8>), grid, dim3(NT), 0, s, m, n_steps);
 }
 
+// ---------------------------------------------------------------------------
+// Batched runs: workgroup (mode group g, run r).  Each thread holds MPT modes
+// (amplitude, factors, the run's forcing and probe weights) in registers for
+// the whole run.  Probe contributions are accumulated per thread over S steps
+// and reduced (wave by DPP moves, workgroup through LDS) once per S steps.
+// ---------------------------------------------------------------------------
+constexpr int S = 8;  // steps per reduction
+
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+  const int2 b = __builtin_bit_cast(int2, v);
+  int2 r;
+  r.x = __builtin_amdgcn_update_dpp(0, b.x, CTRL, 0xF, 0xF, false);
+  r.y = __builtin_amdgcn_update_dpp(0, b.y, CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, r);
+}
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const int2 b = __builtin_bit_cast(int2, v);
+  int2 r;
+  r.x = __builtin_amdgcn_readlane(b.x, l);
+  r.y = __builtin_amdgcn_readlane(b.y, l);
+  return __builtin_bit_cast(double, r);
+}
+// quads and rows of 16 by DPP (xor 1, xor 2, half-row and row mirrors), then
+// the four rows' sums by readlane, added in a fixed order
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v += dpp<0xB1>(v);
+  v += dpp<0x4E>(v);
+  v += dpp<0x141>(v);
+  v += dpp<0x140>(v);
+  return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
+}
+
+template <int NTB, int MPT>
+__global__ void __launch_bounds__(NTB) batch_step_k(BatchStep b) {
+  constexpr int NW = NTB / 64;
+  __shared__ double red[2][S][NW];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int g = blockIdx.x;
+  const int r = b.order[blockIdx.y];
+  const int64_t T = b.lens[r];
+  if (T == 0) return;
+  const int64_t n0 = b.n0;
+  const double* Wc = b.W + (int64_t)b.wcol[r] * b.ldw;
+  const double* Pc = b.Pm + (int64_t)b.pcol[r] * n0;
+  double y[MPT], c[MPT], a[MPT], w[MPT], p[MPT];
+#pragma unroll
+  for (int i = 0; i < MPT; ++i) {
+    const int64_t n = (int64_t)g * NTB * MPT + (int64_t)i * NTB + t;
+    y[i] = 0.0;
+    c[i] = a[i] = w[i] = p[i] = 0.0;
+    if (n < n0) {
+      const double lam = b.lam[n];
+      a[i] = b.dt * lam;
+      c[i] = 1.0 / (1.0 + b.theta * b.dt * lam);
+      w[i] = Wc[n];
+      p[i] = Pc[n];
+    }
+  }
+  const double* wv = b.waves + b.woff[r];
+  double* part = b.partial + b.soff[r] * b.G + g;
+  for (int64_t k0 = 0, it = 0; k0 < T; k0 += S, ++it) {
+    double smp[S + 1];
+#pragma unroll
+    for (int q = 0; q <= S; ++q) smp[q] = wv[min(k0 + q, T)];
+    double acc[S];
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+      acc[q] = 0.0;
+      if (k0 + q < T) {
+        const double u = -(smp[q + 1] - smp[q]);
+#pragma unroll
+        for (int i = 0; i < MPT; ++i) {
+          const double dy = c[i] * (w[i] * u - a[i] * y[i]);
+          y[i] += dy;
+          acc[q] += p[i] * dy;
+        }
+      }
+    }
+    const int buf = (int)(it & 1);
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+      const double v = wave_sum_dpp(acc[q]);
+      if (lane == 0) red[buf][q][wave] = v;
+    }
+    __syncthreads();
+    if (t < S && k0 + t < T) {
+      double v = 0.0;
+#pragma unroll
+      for (int ww = 0; ww < NW; ++ww) v += red[buf][t][ww];
+      part[(k0 + t) * b.G] = v;
+    }
+  }
+}
+
+// signal[e] = sum_g partial[e G + g] / dt, in group order
+__global__ void batch_finish_k(const double* partial, int64_t total, int G, double dt,
+                               double* signal) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const double* q = partial + e * G;
+  double s = 0.0;
+  for (int g = 0; g < G; ++g) s += q[g];
+  signal[e] = s / dt;
+}
+
+template <int NTB, int MPT>
+void launch_batch(const BatchStep& b, hipStream_t s) {
+  hipLaunchKernelGGL((batch_step_k<NTB, MPT>), dim3((unsigned)b.G, (unsigned)b.n_runs),
+                     dim3(NTB), 0, s, b);
+}
+
 }  // namespace
+
+const BatchTile kBatchTiles[] = {{256, 1}, {256, 2}, {256, 4}, {128, 4}, {256, 8}, {128, 8}};
+const int kNumBatchTiles = (int)(sizeof(kBatchTiles) / sizeof(kBatchTiles[0]));
+
+int batch_groups(int64_t n0, int tile) {
+  const BatchTile& bt = kBatchTiles[tile];
+  return (int)std::max<int64_t>(1, ceil_div(n0, (int64_t)bt.threads * bt.modes));
+}
+
+void batch_steps(const BatchStep& b, int tile, int64_t total_steps, double* signal,
+                 hipStream_t s) {
+  MM_REQUIRE(tile >= 0 && tile < kNumBatchTiles, kInvalid, "batch_steps: tile");
+  MM_REQUIRE(b.G == batch_groups(b.n0, tile), kInvalid, "batch_steps: group count");
+  if (b.n_runs <= 0) return;
+  switch (tile) {
+    case 0: launch_batch<256, 1>(b, s); break;
+    case 1: launch_batch<256, 2>(b, s); break;
+    case 2: launch_batch<256, 4>(b, s); break;
+    case 3: launch_batch<128, 4>(b, s); break;
+    case 4: launch_batch<256, 8>(b, s); break;
+    default: launch_batch<128, 8>(b, s); break;
+  }
+  MM_HIP_TRY(hipGetLastError());
+  if (total_steps > 0 && signal) {
+    hipLaunchKernelGGL(batch_finish_k, dim3((unsigned)ceil_div(total_steps, 256)), dim3(256), 0,
+                       s, b.partial, total_steps, b.G, b.dt, signal);
+    MM_HIP_TRY(hipGetLastError());
+  }
+}
 
 int modal_groups(int64_t n0) { return (int)std::max<int64_t>(1, ceil_div(n0, NT)); }
 

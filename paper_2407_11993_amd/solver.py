@@ -126,6 +126,15 @@ class Solver:
         _lib.check(self.lib.mm_probe(self.ctx, which, k, _lib.ptr(r), _lib.ptr(out)), self.ctx)
         return out
 
+    def batch(self, theta, dt, lens, src, probe, waves, tile=-1):
+        """Plan of many independent modal runs (one launch, one HIP graph).
+
+        ``lens``, ``src``, ``probe``: per-run steps, source column and probe
+        column; ``waves``: the runs' waveforms packed one after the other
+        (lens[r] + 1 samples each).  Returns a :class:`Batch`; its
+        ``run()`` fills and returns the packed signals (sum(lens) values)."""
+        return Batch(self, theta, dt, lens, src, probe, waves, tile)
+
     def reset(self):
         _lib.check(self.lib.mm_reset_state(self.ctx), self.ctx)
 
@@ -218,3 +227,52 @@ class _Kernels:
 
 
 kernels = _Kernels()
+
+
+class Batch:
+    """Batched modal runs over one decomposed :class:`Solver` (mm_batch_*)."""
+
+    def __init__(self, solver, theta, dt, lens, src, probe, waves, tile=-1):
+        self.solver = solver
+        lib = solver.lib
+        self.lens = np.ascontiguousarray(lens, dtype=np.int64)
+        src = np.ascontiguousarray(src, dtype=np.int32)
+        probe = np.ascontiguousarray(probe, dtype=np.int32)
+        n = self.lens.size
+        assert src.size == n and probe.size == n
+        total = int(self.lens.sum())
+        self.waves = _dev(waves) if not isinstance(waves, torch.Tensor) else waves
+        assert self.waves.numel() == total + n
+        self.signals = torch.empty(max(total, 1), dtype=torch.float64, device=solver.device)
+        self.offsets = np.concatenate([[0], np.cumsum(self.lens)])
+        h = ctypes.c_void_p()
+        _lib.check(lib.mm_batch_create(
+            solver.ctx, float(theta), float(dt), n,
+            self.lens.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+            src.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+            probe.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+            _lib.ptr(self.waves), _lib.ptr(self.signals), int(tile), ctypes.byref(h)),
+            solver.ctx)
+        self.h = h
+        info = (ctypes.c_int64 * 4)()
+        _lib.check(lib.mm_batch_info(self.h, info), solver.ctx)
+        self.threads, self.modes, self.groups, self.total = (int(v) for v in info)
+
+    def run(self):
+        _lib.check(self.solver.lib.mm_batch_run(self.h), self.solver.ctx)
+        return self.signals[:self.total]
+
+    def signal(self, r):
+        """Signal of run r (a view into the packed output)."""
+        return self.signals[self.offsets[r]:self.offsets[r + 1]]
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.solver.lib.mm_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
