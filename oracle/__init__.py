@@ -16,6 +16,8 @@ Decomposition in Numerical Computation of Eddy Current Transients"):
 * ``theta_direct``      -- the Cholesky theta-method (Sec. 3.3.1, eq. time_integration).
 * ``theta_modal``       -- the modal theta-method (Sec. 3.3.2).
 * ``modal_eigen``       -- eigenvalues and Li-normalised eigenvectors (Sec. 3.2).
+* ``adjoint_direct``    -- gradient of a probe-signal misfit through the
+                           theta-method (adjoint recursion, every state kept).
 """
 from __future__ import annotations
 
@@ -77,6 +79,10 @@ def _load():
         lib.orc_modal_eigen.argtypes = [
             ctypes.POINTER(_Problem), _dp, _dp, ctypes.POINTER(ctypes.c_int)]
         lib.orc_modal_eigen.restype = ctypes.c_int
+        lib.orc_adjoint_direct.argtypes = [
+            _i64, _dp, _dp, _i64, _dp, _dp, ctypes.c_double, ctypes.c_double, _i64,
+            _dp, _dp, _dp, _dp, _dp]
+        lib.orc_adjoint_direct.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -269,3 +275,27 @@ def modal_eigen(pb: Problem, want_V: bool = True):
     if rc:
         raise RuntimeError(_ERR.get(rc, str(rc)))
     return (lam, V) if want_V else lam
+
+
+def adjoint_direct(L, R, M, P, theta: float, dt: float, T: int, i_src, obs):
+    """Misfit J = sum_c sum_k (s_c^{k+1} - obs[c, k])^2 over runs c (source
+    column c of M, probe row c of P, shared waveform i_src of T+1 samples) and
+    its gradients: dJ/dR (n x n, every entry independent) and dJ/di (T+1)."""
+    L = _f64(L)
+    R = _f64(R)
+    n = L.shape[0]
+    M = _f64(np.asarray(M).reshape(n, -1))
+    C = M.shape[1]
+    P = _f64(np.atleast_2d(P))
+    assert P.shape == (C, n)
+    i_src = _f64(np.asarray(i_src).reshape(T + 1))
+    obs = _f64(np.asarray(obs).reshape(C, T))
+    J = np.zeros(1)
+    dJdR = np.zeros((n, n))
+    dJdi = np.zeros(T + 1)
+    rc = _load().orc_adjoint_direct(n, _ptr(L), _ptr(R), C, _ptr(M), _ptr(P), float(theta),
+                                    float(dt), int(T), _ptr(i_src), _ptr(obs), _ptr(J),
+                                    _ptr(dJdR), _ptr(dJdi))
+    if rc:
+        raise RuntimeError(_ERR.get(rc, str(rc)))
+    return float(J[0]), dJdR, dJdi

@@ -727,3 +727,109 @@ int orc_theta_modal(const orc_problem *pb, double theta, double dt, int64_t T,
     free_reduced(&r);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Adjoint of the probe-signal misfit over runs that share one waveform     */
+/* (gradient of the theta-method of Sec. 3.3.1, eq. time_integration).      */
+/* Run c drives source column c of M (n x C) with the waveform i (T+1       */
+/* samples) and observes probe row c of P (C x n); no electrodes.  With     */
+/* Z = L + theta dt R and the residual of step k                            */
+/*     F_k = Z dI_k + dt R I_k - M_c u_k,   u_k = -(i_{k+1} - i_k),          */
+/* the misfit J = sum_c sum_k (P_c dI_k / dt - obs_c[k])^2 has the adjoint   */
+/*     Z lambda_k = g_k P_c^T - dt R mu_k,   mu_k = sum_{j > k} lambda_j,    */
+/*     g_k = 2 (P_c dI_k / dt - obs_c[k]) / dt,                             */
+/* and the gradients                                                        */
+/*     dJ/dR(a,b) = - sum_{c,k} lambda_k(a) (theta dt dI_k(b) + dt I_k(b)),  */
+/*     dJ/du_k    =   sum_c lambda_k^T M_c,                                  */
+/*     dJ/di_j    =   dJ/du_j - dJ/du_{j-1}.                                 */
+/* Every entry of R is treated as independent (dJdR is n x n, row-major).   */
+/* Every state is kept (no checkpoints).  Returns 0, or 2 if Z is not SPD.   */
+/* ------------------------------------------------------------------------ */
+int orc_adjoint_direct(int64_t n, const double *L, const double *R, int64_t C,
+                       const double *M, const double *P, double theta,
+                       double dt, int64_t T, const double *i_src,
+                       const double *obs, double *J, double *dJdR,
+                       double *dJdi)
+{
+    double *Z = (double *)malloc(sizeof(double) * (size_t)(n * n));
+    for (int64_t a = 0; a < n * n; ++a)
+        Z[a] = L[a] + theta * dt * R[a];
+    if (orc_cholesky(n, Z) >= 0) {
+        free(Z);
+        return 2;
+    }
+    double *I = (double *)malloc(sizeof(double) * (size_t)((T + 1) * n));
+    double *dI = (double *)malloc(sizeof(double) * (size_t)((T > 0 ? T : 1) * n));
+    double *g = (double *)malloc(sizeof(double) * (size_t)(T > 0 ? T : 1));
+    double *lam = (double *)malloc(sizeof(double) * (size_t)n);
+    double *mu = (double *)malloc(sizeof(double) * (size_t)n);
+    double *b = (double *)malloc(sizeof(double) * (size_t)n);
+    double *dJdu = (double *)calloc((size_t)(T > 0 ? T : 1), sizeof(double));
+    *J = 0.0;
+    for (int64_t a = 0; a < n * n; ++a)
+        dJdR[a] = 0.0;
+    for (int64_t c = 0; c < C; ++c) {
+        /* forward: every I_k and dI_k of run c */
+        for (int64_t a = 0; a < n; ++a)
+            I[a] = 0.0;
+        for (int64_t k = 0; k < T; ++k) {
+            const double u = -(i_src[k + 1] - i_src[k]);
+            const double *Ik = I + k * n;
+            for (int64_t a = 0; a < n; ++a) {
+                double s = 0.0;
+                for (int64_t q = 0; q < n; ++q)
+                    s += R[IDX(a, q, n)] * Ik[q];
+                b[a] = -dt * s + M[IDX(a, c, C)] * u;
+            }
+            orc_forward(n, Z, b);
+            orc_backward_T(n, Z, b);
+            double s = 0.0;
+            for (int64_t a = 0; a < n; ++a) {
+                dI[k * n + a] = b[a];
+                I[(k + 1) * n + a] = Ik[a] + b[a];
+                s += P[IDX(c, a, n)] * b[a];
+            }
+            const double res = s / dt - obs[c * T + k];
+            *J += res * res;
+            g[k] = 2.0 * res / dt;
+        }
+        /* backward */
+        for (int64_t a = 0; a < n; ++a)
+            mu[a] = 0.0;
+        for (int64_t k = T - 1; k >= 0; --k) {
+            for (int64_t a = 0; a < n; ++a) {
+                double s = 0.0;
+                for (int64_t q = 0; q < n; ++q)
+                    s += R[IDX(a, q, n)] * mu[q];
+                lam[a] = g[k] * P[IDX(c, a, n)] - dt * s;
+            }
+            orc_forward(n, Z, lam);
+            orc_backward_T(n, Z, lam);
+            double du = 0.0;
+            for (int64_t a = 0; a < n; ++a)
+                du += lam[a] * M[IDX(a, c, C)];
+            dJdu[k] += du;
+            for (int64_t a = 0; a < n; ++a) {
+                const double la = lam[a];
+                if (la == 0.0)
+                    continue;
+                for (int64_t q = 0; q < n; ++q)
+                    dJdR[IDX(a, q, n)] -=
+                        la * (theta * dt * dI[k * n + q] + dt * I[k * n + q]);
+            }
+            for (int64_t a = 0; a < n; ++a)
+                mu[a] += lam[a];
+        }
+    }
+    for (int64_t j = 0; j <= T; ++j)
+        dJdi[j] = (j < T ? dJdu[j] : 0.0) - (j > 0 ? dJdu[j - 1] : 0.0);
+    free(Z);
+    free(I);
+    free(dI);
+    free(g);
+    free(lam);
+    free(mu);
+    free(b);
+    free(dJdu);
+    return 0;
+}

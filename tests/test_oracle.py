@@ -339,3 +339,74 @@ def test_modal_equals_direct_on_block(orc):
                                        np.zeros((T + 1, 0)))
         assert np.abs(s_d - ref).max() < 1e-12 * np.abs(ref).max()
         assert np.abs(s_m - ref).max() < 1e-11 * np.abs(ref).max()
+
+
+# ---------------------------------------------------------------------------
+# Adjoint of the probe-signal misfit (gradient of the theta-method)
+# ---------------------------------------------------------------------------
+def _adj_problem(seed=3, nx=4, ny=3, C=2, T=30):
+    from paper_2407_11993_amd import inputs
+    dims = (nx, ny, 1)
+    xyz = inputs.grid(*dims)
+    n = xyz.shape[0]
+    rho = inputs.rho_loguniform(n, seed)
+    R = inputs.resistance_csr(dims, rho).to_dense()
+    rng = np.random.default_rng(seed)
+    M = np.stack([inputs.coil_coupling(xyz, (rng.uniform(0, nx - 1), rng.uniform(0, ny - 1), 1.5))
+                  for _ in range(C)], axis=1)
+    t = np.arange(T + 1, dtype=np.float64)
+    i_src = np.sin(2 * np.pi * t / 17.0) + 0.3 * np.exp(-((t - 8) / 4.0) ** 2)
+    obs = 0.01 * rng.standard_normal((C, T))
+    return xyz, R, M, i_src, obs
+
+
+def _misfit(orc, L, R, M, theta, T, i_src, obs):
+    J = 0.0
+    for c in range(M.shape[1]):
+        pb = orc.Problem(L, R, M[:, c:c + 1], M[:, c][None, :])
+        s = orc.theta_direct(pb, theta, 1.0, T, i_src[:, None])[:, 0]
+        J += float(((s - obs[c]) ** 2).sum())
+    return J
+
+
+@pytest.mark.parametrize("theta", [0.5, 1.0])
+def test_adjoint_misfit_matches_direct_stepper(orc, theta):
+    xyz, R, M, i_src, obs = _adj_problem()
+    L = orc.assemble_L(xyz, 0.7)
+    T = obs.shape[1]
+    J, _, _ = orc.adjoint_direct(L, R, M, M.T, theta, 1.0, T, i_src, obs)
+    assert abs(J - _misfit(orc, L, R, M, theta, T, i_src, obs)) < 1e-13 * J
+
+
+@pytest.mark.parametrize("theta", [0.5, 1.0])
+def test_adjoint_resistance_gradient_by_central_differences(orc, theta):
+    """Symmetric perturbations R(a,b) = R(b,a) += eps: the derivative is
+    dJdR[a,b] + dJdR[b,a] (one term on the diagonal)."""
+    xyz, R, M, i_src, obs = _adj_problem()
+    L = orc.assemble_L(xyz, 0.7)
+    T = obs.shape[1]
+    _, G, _ = orc.adjoint_direct(L, R, M, M.T, theta, 1.0, T, i_src, obs)
+    n = R.shape[0]
+    pairs = [(0, 0), (5, 5), (1, 0), (4, 5), (7, 3), (11, 10), (2, 9)]
+    for a, b in pairs:
+        eps = 1e-5
+        E = np.zeros((n, n))
+        E[a, b] = E[b, a] = 1.0
+        fd = (_misfit(orc, L, R + eps * E, M, theta, T, i_src, obs)
+              - _misfit(orc, L, R - eps * E, M, theta, T, i_src, obs)) / (2 * eps)
+        ad = G[a, b] + (G[b, a] if a != b else 0.0)
+        assert abs(fd - ad) <= 1e-6 * max(abs(ad), np.abs(G).max()), (a, b, fd, ad)
+
+
+def test_adjoint_waveform_gradient_by_central_differences(orc):
+    xyz, R, M, i_src, obs = _adj_problem(seed=5, C=3, T=25)
+    L = orc.assemble_L(xyz, 0.7)
+    T = obs.shape[1]
+    _, _, gi = orc.adjoint_direct(L, R, M, M.T, 0.5, 1.0, T, i_src, obs)
+    for j in (0, 1, 7, 13, T - 1, T):
+        eps = 1e-6
+        e = np.zeros(T + 1)
+        e[j] = eps
+        fd = (_misfit(orc, L, R, M, 0.5, T, i_src + e, obs)
+              - _misfit(orc, L, R, M, 0.5, T, i_src - e, obs)) / (2 * eps)
+        assert abs(fd - gi[j]) <= 1e-6 * np.abs(gi).max(), (j, fd, gi[j])
