@@ -159,6 +159,24 @@ mm_status mm_batch_run(mm_batch* batch);
 mm_status mm_batch_info(const mm_batch* batch, int64_t* out);
 void mm_batch_destroy(mm_batch* batch);
 
+/* ---- Adjoint -----------------------------------------------------------------
+ * Gradient of the probe-signal misfit
+ *     J = sum_r sum_{k=0}^{n_steps-1} (s_r^{k+1} - s_obs[r * n_steps + k])^2
+ * over n_runs modal runs (Sec. 3.3.2) that share one source waveform i_src
+ * (device, n_steps + 1 samples): run r drives source src[r] and observes
+ * probe probe[r] (HOST arrays), from a zero state.  The modal recursion is
+ * run backward (the exact adjoint of the theta-method of Sec. 3.3.1 in the
+ * modal basis); amplitudes are checkpointed every ckpt_every steps and
+ * recomputed per segment, so memory grows with n_steps / ckpt_every, not
+ * n_steps.  Outputs (device): *J; dJ_dR (r_nnz): dJ/dR at every stored entry
+ * of R, each entry treated as independent (for a symmetric model R(rho) the
+ * chain rule adds both triangles); dJ_di (n_steps + 1): dJ/d i_src(t_k).
+ * Requires mm_decompose and Ne = 0.  Synchronises the stream. */
+mm_status mm_adjoint_modal(mm_ctx* ctx, double theta, double dt, int64_t n_steps,
+                           int32_t n_runs, const int32_t* src, const int32_t* probe,
+                           const double* i_src, const double* s_obs, int64_t ckpt_every,
+                           double* J, double* dJ_dR, double* dJ_di);
+
 /* Sizes: out[0] = n, out[1] = n0 = n - (Ne-1), out[2] = decomposed (0/1). */
 mm_status mm_info(const mm_ctx* ctx, int64_t* out /* host, 3 */);
 

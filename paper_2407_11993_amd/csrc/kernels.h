@@ -195,4 +195,37 @@ int batch_groups(int64_t n0, int tile);
 void batch_steps(const BatchStep& b, int tile, int64_t total_steps, double* signal,
                  hipStream_t s);
 
+// ---- adjoint of the probe-signal misfit (adjoint.hip) ----------------------
+// Runs r = 0..n_runs-1 share one waveform (T+1 samples) and drive forcing
+// column wcol[r] of W, observed through probe column pcol[r] of Pm.
+struct AdjointStep {
+  int64_t n0 = 0, T = 0, K = 1, n_ckpt = 0;
+  int G = 0, n_runs = 0;
+  const double* lam = nullptr;
+  const double* W = nullptr;
+  int64_t ldw = 0;
+  const double* Pm = nullptr;
+  const int32_t* wcol = nullptr;
+  const int32_t* pcol = nullptr;
+  double theta = 0.5, dt = 1.0;
+  const double* wave = nullptr;  // T + 1
+  const double* obs = nullptr;   // n_runs x T
+  double* ckpt = nullptr;        // n_runs x n_ckpt x n0
+  double* part_sig = nullptr;    // n_runs x T x G
+  double* resid = nullptr;       // n_runs x T
+  double* nu = nullptr;          // n_runs x n0, zero before the backward pass
+  double* part_u = nullptr;      // n_runs x T x G
+};
+int adjoint_groups(int64_t n0);
+// Forward pass with checkpoints, residuals and J (sq: n_runs x T scratch).
+void adjoint_forward(const AdjointStep& s, double* J, double* sq, hipStream_t st);
+// Segment [k0, k1) (k0 a checkpoint): zeta into Zb and the backward
+// recursion into Lb, both n0 x (n_runs * K), column r * K + (k - k0).
+void adjoint_segment(const AdjointStep& s, int64_t k0, int64_t k1, double* Zb, double* Lb,
+                     hipStream_t st);
+// du (T) = dJ/du_k, di (T + 1) = dJ/di_j.
+void adjoint_waveform_grad(const AdjointStep& s, double* du, double* di, hipStream_t st);
+// out[p] = -Phi(i_p, j_p) at the stored entries of R (offset 0).
+void adjoint_gather(const Csr& R, const double* Phi, int64_t ld, double* out, hipStream_t st);
+
 }  // namespace mm

@@ -874,6 +874,107 @@ void mm_batch_destroy(mm_batch* b) {
   delete b;
 }
 
+mm_status mm_adjoint_modal(mm_ctx* c, double theta, double dt, int64_t n_steps,
+                           int32_t n_runs, const int32_t* src, const int32_t* probe,
+                           const double* i_src, const double* s_obs, int64_t ckpt_every,
+                           double* J, double* dJ_dR, double* dJ_di) {
+  if (!c) return MM_E_INVALID;
+  return guarded(c, [&] {
+    MM_REQUIRE(c->decomposed, kState, "mm_adjoint_modal before mm_decompose");
+    check_steps(theta, dt, n_steps);
+    MM_REQUIRE(c->m == 0, kInvalid, "mm_adjoint_modal: problems without electrodes only");
+    MM_REQUIRE(n_steps >= 1 && n_runs >= 1 && src && probe, kInvalid,
+               "n_steps >= 1, n_runs >= 1, src and probe are required");
+    MM_REQUIRE(ckpt_every >= 1, kInvalid, "ckpt_every >= 1");
+    MM_REQUIRE(i_src && s_obs && J && dJ_dR && dJ_di, kInvalid, "missing array argument");
+    hipStream_t s = c->stream;
+    const int64_t n0 = c->n0, T = n_steps;
+    std::vector<int32_t> wcol(n_runs), pcol(n_runs);
+    for (int r = 0; r < n_runs; ++r) {
+      MM_REQUIRE(src[r] >= 0 && src[r] < c->n_src, kInvalid, "source index out of range");
+      MM_REQUIRE(probe[r] >= 0 && probe[r] < c->n_probe, kInvalid, "probe index out of range");
+      wcol[r] = src[r];
+      pcol[r] = probe[r];
+    }
+    Dev dw, dp, ckpt, psig, resid, sq, nu, pu, du;
+    upload(dw, wcol, s);
+    upload(dp, pcol, s);
+    AdjointStep a;
+    a.n0 = n0; a.T = T; a.K = std::min(ckpt_every, T); a.n_ckpt = ceil_div(T, a.K);
+    a.G = adjoint_groups(n0); a.n_runs = n_runs;
+    a.lam = c->lam.d(); a.W = c->Wm.d(); a.ldw = n0; a.Pm = c->Pm.d();
+    a.wcol = dw.as<int32_t>(); a.pcol = dp.as<int32_t>();
+    a.theta = theta; a.dt = dt;
+    a.wave = i_src; a.obs = s_obs;
+    ckpt.alloc(sizeof(double) * n_runs * a.n_ckpt * n0);
+    psig.alloc(sizeof(double) * n_runs * T * a.G);
+    resid.alloc(sizeof(double) * n_runs * T);
+    sq.alloc(sizeof(double) * n_runs * T);
+    nu.alloc(sizeof(double) * n_runs * n0);
+    pu.alloc(sizeof(double) * n_runs * T * a.G);
+    du.alloc(sizeof(double) * T);
+    a.ckpt = ckpt.d(); a.part_sig = psig.d(); a.resid = resid.d(); a.nu = nu.d();
+    a.part_u = pu.d();
+    fill(nu.d(), n_runs * n0, 0.0, s);
+    adjoint_forward(a, J, sq.d(), s);
+    // backward over the segments, last first; S += L Z^T per segment
+    Dev S, Zb, Lb;
+    S.alloc(sizeof(double) * n0 * n0);
+    const int64_t cols = (int64_t)n_runs * a.K;
+    Zb.alloc(sizeof(double) * n0 * cols);
+    Lb.alloc(sizeof(double) * n0 * cols);
+    for (int64_t j = a.n_ckpt - 1; j >= 0; --j) {
+      const int64_t k0 = j * a.K, k1 = std::min(T, k0 + a.K);
+      if (k1 - k0 < a.K) {  // short last segment: its unused columns must be zero
+        fill(Zb.d(), n0 * cols, 0.0, s);
+        fill(Lb.d(), n0 * cols, 0.0, s);
+      }
+      adjoint_segment(a, k0, k1, Zb.d(), Lb.d(), s);
+      Gemm g;
+      g.m = n0; g.n = n0; g.k = cols;
+      g.beta = (j == a.n_ckpt - 1) ? 0.0 : 1.0;
+      g.A = Lb.d(); g.lda = n0;
+      g.B = Zb.d(); g.ldb = n0; g.tb = true;
+      g.C = S.d(); g.ldc = n0;
+      gemm(g, s);
+    }
+    adjoint_waveform_grad(a, du.d(), dJ_di, s);
+    MM_HIP_TRY(hipStreamSynchronize(s));  // Zb, Lb released below
+    Zb.release();
+    Lb.release();
+    // dJ/dR = -V S V^T at the stored entries, V = G^{-T} Q
+    Dev V, T1;
+    V.alloc(sizeof(double) * n0 * n0);
+    T1.alloc(sizeof(double) * n0 * n0);
+    {
+      Gemm g;
+      g.m = n0; g.n = n0; g.k = n0;
+      g.A = c->G.d(); g.lda = n0; g.ta = true; g.a_upper = true;
+      g.B = c->Q.d(); g.ldb = n0;
+      g.C = V.d(); g.ldc = n0;
+      gemm(g, s);
+    }
+    {
+      Gemm g;
+      g.m = n0; g.n = n0; g.k = n0;
+      g.A = V.d(); g.lda = n0;
+      g.B = S.d(); g.ldb = n0;
+      g.C = T1.d(); g.ldc = n0;
+      gemm(g, s);
+    }
+    {
+      Gemm g;  // Phi = T1 V^T, into S's storage
+      g.m = n0; g.n = n0; g.k = n0;
+      g.A = T1.d(); g.lda = n0;
+      g.B = V.d(); g.ldb = n0; g.tb = true;
+      g.C = S.d(); g.ldc = n0;
+      gemm(g, s);
+    }
+    adjoint_gather(c->Rfull(), S.d(), n0, dJ_dR, s);
+    MM_HIP_TRY(hipStreamSynchronize(s));
+  });
+}
+
 mm_status mm_info(const mm_ctx* c, int64_t* out) {
   if (!c || !out) return MM_E_INVALID;
   out[0] = c->n;

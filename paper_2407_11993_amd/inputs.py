@@ -173,6 +173,42 @@ def resistance_csr_fast(dims, rho, shift: float = R_SHIFT) -> CSR:
     return CSR((n, n), rowptr, c.astype(np.int32), v.astype(np.float64))
 
 
+def resistance_model(dims, shift: float = R_SHIFT):
+    """The resistance values as a linear function of the cell resistivities,
+    R.val = A rho + c, on the pattern (and entry order) of
+    :func:`resistance_csr_fast`.  Returns (rowptr, col, A as COO triples
+    (entry, cell, coefficient), c)."""
+    nx, ny, nz = dims
+    n = nx * ny * nz
+    idx = np.arange(n).reshape(nz, ny, nx)
+    src, dst = [], []
+    for axis in range(3):
+        a = np.take(idx, np.arange(idx.shape[axis] - 1), axis=axis).ravel()
+        b = np.take(idx, np.arange(1, idx.shape[axis]), axis=axis).ravel()
+        src += [a, b]
+        dst += [b, a]
+    src = np.concatenate(src)
+    dst = np.concatenate(dst)
+    E = src.size
+    r = np.concatenate([src, np.arange(n)])
+    c = np.concatenate([dst, np.arange(n)])
+    order = np.lexsort((c, r))
+    pos = np.empty(order.size, dtype=np.int64)
+    pos[order] = np.arange(order.size)
+    # off-diagonal entry of edge e: -(rho_src + rho_dst) / 2
+    # diagonal entry of cell i: shift + sum over its edges (rho_i + rho_j) / 2
+    ent = np.concatenate([pos[:E], pos[:E], pos[E + src], pos[E + src]])
+    cel = np.concatenate([src, dst, src, dst])
+    coef = np.concatenate([np.full(E, -0.5), np.full(E, -0.5), np.full(E, 0.5), np.full(E, 0.5)])
+    const = np.zeros(order.size)
+    const[pos[E:]] = shift
+    rs, cs = r[order], c[order]
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(rowptr, rs + 1, 1)
+    rowptr = np.cumsum(rowptr)
+    return rowptr, cs.astype(np.int32), (ent, cel, coef), const
+
+
 def coil_coupling(xyz, p, h: float = H_KERNEL) -> np.ndarray:
     d2 = ((xyz - np.asarray(p, dtype=np.float64)) ** 2).sum(axis=1)
     return h / np.sqrt(d2 + h * h)

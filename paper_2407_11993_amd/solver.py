@@ -44,7 +44,10 @@ class Solver:
         self._xyz = _dev(w.xyz.reshape(-1))
         self._rp = _dev(w.R.rowptr, torch.int64)
         self._rc = _dev(w.R.col, torch.int32)
-        self._rv = _dev(w.R.val)
+        # the resistance values may be given as a device tensor (R_val), e.g.
+        # built from a resistivity field by torch
+        rv = getattr(w, "R_val", None)
+        self._rv = rv if isinstance(rv, torch.Tensor) else _dev(w.R.val)
         self._M = _dev(_colmajor(w.M, self.n)) if self.n_src else None
         self._P = _dev(_colmajor(w.P.T, self.n))
         if self.m:
@@ -134,6 +137,25 @@ class Solver:
         (lens[r] + 1 samples each).  Returns a :class:`Batch`; its
         ``run()`` fills and returns the packed signals (sum(lens) values)."""
         return Batch(self, theta, dt, lens, src, probe, waves, tile)
+
+    def adjoint(self, theta, dt, n_steps, src, probe, i_src, s_obs, ckpt_every=500):
+        """J, dJ/dR (at R's stored entries) and dJ/di_src for the misfit of
+        runs that share the waveform i_src (mm_adjoint_modal)."""
+        src = np.ascontiguousarray(src, dtype=np.int32)
+        probe = np.ascontiguousarray(probe, dtype=np.int32)
+        wave = _dev(i_src) if not isinstance(i_src, torch.Tensor) else i_src
+        obs = _dev(s_obs) if not isinstance(s_obs, torch.Tensor) else s_obs
+        assert wave.numel() == n_steps + 1 and obs.numel() == src.size * n_steps
+        J = torch.empty(1, dtype=torch.float64, device=self.device)
+        gR = torch.empty(self._rv.numel(), dtype=torch.float64, device=self.device)
+        gi = torch.empty(n_steps + 1, dtype=torch.float64, device=self.device)
+        _lib.check(self.lib.mm_adjoint_modal(
+            self.ctx, float(theta), float(dt), int(n_steps), int(src.size),
+            src.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+            probe.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+            _lib.ptr(wave.contiguous()), _lib.ptr(obs.contiguous()), int(ckpt_every),
+            _lib.ptr(J), _lib.ptr(gR), _lib.ptr(gi)), self.ctx)
+        return J[0], gR, gi
 
     def reset(self):
         _lib.check(self.lib.mm_reset_state(self.ctx), self.ctx)

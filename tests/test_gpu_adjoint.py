@@ -1,0 +1,126 @@
+"""The modal adjoint (gradient of the probe-signal misfit) on the GPU against
+the oracle's physical-space adjoint, and against central differences of the
+GPU's own misfit through the torch.autograd.Function."""
+import numpy as np
+import pytest
+
+from paper_2407_11993_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _problem(nx=12, ny=8, C=3, T=120, seed=2):
+    dims = (nx, ny, 1)
+    xyz = inputs.grid(*dims)
+    n = xyz.shape[0]
+    rho = inputs.rho_loguniform(n, seed)
+    rng = np.random.default_rng(seed)
+    coils = [(rng.uniform(0, nx - 1), rng.uniform(0, ny - 1), 2.0) for _ in range(C)]
+    M = np.stack([inputs.coil_coupling(xyz, p) for p in coils], axis=1)
+    t = np.arange(T + 1, dtype=np.float64)
+    i_src = np.exp(-((t - 30) / 12.0) ** 2) + 0.2 * np.sin(2 * np.pi * t / 41.0)
+    obs = 0.02 * rng.standard_normal((C, T))
+    return dims, xyz, rho, M, i_src, obs
+
+
+def _solver(dims, xyz, rho, M):
+    from paper_2407_11993_amd import Solver
+    n = xyz.shape[0]
+    R = inputs.resistance_csr(dims, rho)
+    w = inputs.Workload("adjoint-test", dims, xyz, inputs.H_KERNEL, rho, R, M, M.T.copy(), None,
+                        (0.5,), 1.0, 1, np.zeros((2, M.shape[1])), np.zeros((2, 0)))
+    s = Solver(w)
+    s.decompose()
+    return s, R
+
+
+@pytest.mark.parametrize("theta,K", [(0.5, 25), (1.0, 120), (0.5, 1)])
+def test_adjoint_matches_oracle(orc, theta, K):
+    dims, xyz, rho, M, i_src, obs = _problem()
+    T = obs.shape[1]
+    s, R = _solver(dims, xyz, rho, M)
+    runs = np.arange(M.shape[1])
+    J, gR, gi = s.adjoint(theta, 1.0, T, runs, runs, i_src, obs, ckpt_every=K)
+    L = orc.assemble_L(xyz, inputs.H_KERNEL)
+    Jr, Gr, gir = orc.adjoint_direct(L, R.to_dense(), M, M.T, theta, 1.0, T, i_src, obs)
+    assert abs(float(J) - Jr) < 1e-10 * Jr
+    rows = np.repeat(np.arange(R.shape[0]), np.diff(R.rowptr))
+    ref = Gr[rows, R.col]
+    got = _np(gR)
+    assert np.abs(got - ref).max() < 1e-9 * np.abs(ref).max()
+    assert np.abs(_np(gi) - gir).max() < 1e-9 * np.abs(gir).max()
+
+
+def test_checkpoint_interval_does_not_change_the_result():
+    dims, xyz, rho, M, i_src, obs = _problem(T=90)
+    T = obs.shape[1]
+    s, _ = _solver(dims, xyz, rho, M)
+    runs = np.arange(M.shape[1])
+    outs = [s.adjoint(0.5, 1.0, T, runs, runs, i_src, obs, ckpt_every=K) for K in (1, 8, 33, 90)]
+    J0, g0, i0 = (_np(x) for x in outs[0])
+    for J, g, i in outs[1:]:
+        assert abs(float(J) - float(J0)) <= 1e-13 * abs(float(J0))
+        assert np.abs(_np(g) - g0).max() <= 1e-12 * np.abs(g0).max()
+        assert np.abs(_np(i) - i0).max() <= 1e-12 * np.abs(i0).max()
+
+
+def test_autograd_resistivity_and_waveform_gradients():
+    """dJ/drho from the autograd Function against the oracle's dJ/dR pushed
+    through the resistance model, and against central differences of the
+    GPU misfit."""
+    import torch
+    import oracle as orc
+    from paper_2407_11993_amd.autograd import MisfitProblem, ModalMisfit
+    dims, xyz, rho, M, i_src, obs = _problem(nx=10, ny=7, C=2, T=80, seed=4)
+    dev = "cuda"
+    pb = MisfitProblem(dims, M, torch.as_tensor(obs, device=dev), theta=0.5, ckpt_every=16)
+    r = torch.as_tensor(rho, device=dev).requires_grad_(True)
+    i = torch.as_tensor(i_src, device=dev).requires_grad_(True)
+    J = ModalMisfit.apply(r, i, pb)
+    J.backward()
+    g_rho, g_i = _np(r.grad), _np(i.grad)
+    # oracle chain: dJ/drho = A^T dJ/dR
+    R = inputs.resistance_csr(dims, rho)
+    L = orc.assemble_L(xyz, inputs.H_KERNEL)
+    Jr, Gr, gir = orc.adjoint_direct(L, R.to_dense(), M, M.T, 0.5, 1.0, obs.shape[1], i_src, obs)
+    _, _, (ent, cel, coef), _ = inputs.resistance_model(dims)
+    rows = np.repeat(np.arange(R.shape[0]), np.diff(R.rowptr))
+    gR = Gr[rows, R.col]
+    ref = np.zeros(rho.size)
+    np.add.at(ref, cel, coef * gR[ent])
+    assert np.abs(g_rho - ref).max() < 1e-9 * np.abs(ref).max()
+    assert np.abs(g_i - gir).max() < 1e-9 * np.abs(gir).max()
+    # central differences of the GPU misfit in a few cells and samples
+    rng = np.random.default_rng(0)
+    for cell in rng.choice(rho.size, 4, replace=False):
+        e = torch.zeros_like(r)
+        h = 1e-6 * rho[cell]
+        e[cell] = h
+        with torch.no_grad():
+            fd = (float(ModalMisfit.apply(r + e, i, pb)) - float(ModalMisfit.apply(r - e, i, pb))) / (2 * h)
+        assert abs(fd - g_rho[cell]) <= 1e-5 * np.abs(g_rho).max(), (cell, fd, g_rho[cell])
+    for j in (3, 40, 79):
+        e = torch.zeros_like(i)
+        e[j] = 1e-6
+        with torch.no_grad():
+            fd = (float(ModalMisfit.apply(r, i + e, pb)) - float(ModalMisfit.apply(r, i - e, pb))) / 2e-6
+        assert abs(fd - g_i[j]) <= 1e-5 * np.abs(g_i).max(), (j, fd, g_i[j])
+
+
+def test_adjoint_rejects_electrodes_and_bad_arguments():
+    from paper_2407_11993_amd import Solver, _lib
+    w = inputs.electrode_plate(8, 10, 3, T=10)
+    s = Solver(w)
+    s.decompose()
+    with pytest.raises(_lib.MMError) as e:
+        s.adjoint(0.5, 1.0, 10, [0], [0], np.zeros(11), np.zeros(10))
+    assert e.value.code == 1
+    dims, xyz, rho, M, i_src, obs = _problem(nx=6, ny=5, C=2, T=10)
+    s2, _ = _solver(dims, xyz, rho, M)
+    with pytest.raises(_lib.MMError) as e:
+        s2.adjoint(0.5, 1.0, 10, [0, 2], [0, 1], i_src, obs)  # source 2 does not exist
+    assert e.value.code == 1
