@@ -113,6 +113,113 @@ def run_batched(args):
     return res
 
 
+def run_adjoint(args):
+    """Config 5: gradient of the 64-coil probe-signal misfit with respect to
+    every cell's resistivity and the shared waveform (modal adjoint with
+    checkpoints every 500 steps), evaluated at the background field, with
+    observations from the reference field (two defects).  Timed: problem
+    setup, decomposition and the adjoint (forward, backward, S GEMMs,
+    V S V^T).  A few cells are checked by central differences."""
+    import numpy as np
+    import torch
+    from paper_2407_11993_amd import Solver, inputs
+    from paper_2407_11993_amd.autograd import MisfitProblem
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    cfg = inputs.config5(T=args.T or 10000)
+    T, M, dims = cfg["T"], cfg["M"], cfg["dims"]
+    C = M.shape[1]
+    dev = "cuda"
+    stream = torch.cuda.current_stream()
+    wave = torch.as_tensor(cfg["i_src"], device=dev)
+    # observations: the reference field, all coils in one batched launch
+    pb0 = MisfitProblem(dims, M, torch.zeros((C, T), device=dev, dtype=torch.float64))
+    rho_ref = torch.as_tensor(cfg["rho_ref"], device=dev)
+    R_ref = (torch.sparse.mm(pb0.A, rho_ref.reshape(-1, 1)).reshape(-1) + pb0.c).contiguous()
+    s = Solver(pb0.workload(R_ref))
+    s.decompose()
+    runs = np.arange(C)
+    b = s.batch(0.5, 1.0, [T] * C, runs, runs, wave.repeat(C))
+    obs = b.run().reshape(C, T).clone()
+    b.close()
+    s.close()
+    print(f"bench: observations from the reference field (N={cfg['xyz'].shape[0]})",
+          file=sys.stderr, flush=True)
+    pb = MisfitProblem(dims, M, obs, theta=0.5, ckpt_every=500)
+    rho = torch.as_tensor(cfg["rho_bg"], device=dev)
+
+    def solver_at(r):
+        R_val = (torch.sparse.mm(pb.A, r.reshape(-1, 1)).reshape(-1) + pb.c).contiguous()
+        return Solver(pb.workload(R_val))
+
+    def misfit(r):  # forward only: one batched launch of all coils
+        sv = solver_at(r)
+        sv.decompose()
+        bb = sv.batch(0.5, 1.0, [T] * C, runs, runs, wave.repeat(C))
+        J = float(((bb.run().reshape(C, T) - obs) ** 2).sum())
+        bb.close()
+        sv.close()
+        return J
+
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    sv = solver_at(rho)
+    ev[1].record(stream)
+    sv.decompose()
+    ev[2].record(stream)
+    J, gR, g_i = sv.adjoint(0.5, 1.0, T, runs, runs, wave, obs, 500)
+    ev[3].record(stream)
+    torch.cuda.synchronize()
+    t_setup, t_dec, t_adj = (ev[i].elapsed_time(ev[i + 1]) / 1e3 for i in range(3))
+    sv.close()
+    g_rho = torch.sparse.mm(pb.At, gR.reshape(-1, 1)).reshape(-1)
+    J = float(J)
+    print(f"bench: decomposition {t_dec:.2f} s, adjoint {t_adj:.2f} s, J = {J:.6e}",
+          file=sys.stderr, flush=True)
+    J_fwd = misfit(rho)
+    gmax = float(g_rho.abs().max())
+    # cells with the largest |dJ/drho| (where the check is informative) and
+    # random ones; relative step 1e-4 keeps the difference far above the
+    # misfit's rounding while the central difference error stays O(h^2)
+    rng = np.random.default_rng(55)
+    top = torch.topk(g_rho.abs(), (args.fd_cells + 1) // 2).indices.cpu().numpy()
+    rest = rng.choice(rho.numel(), args.fd_cells - top.size, replace=False)
+    fd = []
+    for cell in np.concatenate([top, rest]):
+        h = 1e-4 * float(rho[cell])
+        e = torch.zeros_like(rho)
+        e[cell] = h
+        d = (misfit(rho + e) - misfit(rho - e)) / (2 * h)
+        fd.append({"cell": int(cell), "fd": d, "adjoint": float(g_rho[cell]),
+                   "err_rel_max_g": abs(d - float(g_rho[cell])) / gmax,
+                   "err_rel_cell": abs(d - float(g_rho[cell])) / max(abs(d), 1e-300)})
+        print(f"bench: fd cell {cell}: {fd[-1]}", file=sys.stderr, flush=True)
+    n = rho.numel()
+    s_flops = 2.0 * n * n * C * T
+    t_all = t_setup + t_dec + t_adj
+    res = {
+        "metric": "adjoint gradient of the 64-coil misfit, end-to-end s",
+        "value": round(t_all, 3), "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": round(1e3 * t_all, 1), "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": cfg["name"], "N": n, "coils": C, "T": T, "theta": 0.5,
+                   "ckpt_every": 500},
+        "phases_s": {"setup": round(t_setup, 3), "decompose": round(t_dec, 3),
+                     "adjoint": round(t_adj, 3)},
+        "J": J, "J_forward_batched": J_fwd, "max_abs_dJ_drho": gmax,
+        "max_abs_dJ_di": float(g_i.abs().max()),
+        "fd_check": fd,
+        "roofline": {"bound": "mfma", "kernel": "adjoint (S = sum l zeta^T GEMMs dominate)",
+                     "achieved": round(s_flops / t_adj / 1e12, 3),
+                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(s_flops / t_adj / 1e12 / FP64_PEAK_TFLOPS, 4),
+                     "traffic": None},
+    }
+    return res
+
+
 def _decomp_flops(n: int) -> float:
     # algorithmic FP64 flops of the modal decomposition (see DESIGN.md):
     # potrf n^3/3, trtri n^3/3, C = G^{-1} W^T (lower) n^3/3,
@@ -267,6 +374,8 @@ def main():
     ap.add_argument("--workload", default="plate-128x128-crack")
     ap.add_argument("--T", type=int, default=None, help="override the step count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fd-cells", type=int, default=2,
+                    help="adjoint workload: cells checked by central differences")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; --gpus above 1 is not supported "
@@ -274,6 +383,8 @@ def main():
         sys.exit(2)
     if args.workload.startswith("batched"):
         res = run_batched(args)
+    elif args.workload.startswith("adjoint"):
+        res = run_adjoint(args)
     else:
         res = run_gpu(args)
         if not args.no_cpu_baseline:

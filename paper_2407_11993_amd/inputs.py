@@ -299,6 +299,28 @@ def electrode_plate(nx: int, ny: int, ew: int, *, T: int, tau_D: float = 2000.0,
                     rho, R, M, M.T.copy(), E, (0.5,), 1.0, T, i_src, i_D)
 
 
+def config5(nx: int = 128, ny: int = 256, n_i: int = 8, n_j: int = 8, T: int = 10000,
+            seed: int = 5):
+    """Adjoint workload: background resistivity log-uniform (seed 5), the
+    reference field adds defect A (x in [40,52), y in [60,63), rho = 1e3) and
+    defect B (x in [80,86), y in [180,186), rho = 5); n_i x n_j coils at
+    (16 i + 7.5, 32 j + 15.5, 2) sharing the Gaussian pulse of the 128x128
+    plate.  Returns a dict (dims, xyz, rho_bg, rho_ref, M, i_src, T)."""
+    dims = (nx, ny, 1)
+    xyz = grid(*dims)
+    n = xyz.shape[0]
+    rho_bg = rho_loguniform(n, seed)
+    rho_ref = rho_bg.copy()
+    paint_box(rho_ref, dims, (40, 52), (60, 63), 1e3)
+    paint_box(rho_ref, dims, (80, 86), (180, 186), 5.0)
+    coils = [(16 * i + 7.5, 32 * j + 15.5, 2.0) for j in range(n_j) for i in range(n_i)]
+    M = np.stack([coil_coupling(xyz, p) for p in coils], axis=1)
+    t = tk(T, 1.0)
+    i_src = np.exp(-((t - 500.0) / 100.0) ** 2)
+    return dict(name=f"adjoint-{nx}x{ny}-{len(coils)}coils", dims=dims, xyz=xyz,
+                rho_bg=rho_bg, rho_ref=rho_ref, M=M, i_src=i_src, T=T)
+
+
 def config3(T: int = 100000) -> Workload:
     """256x384 plate, rho = 1, electrodes of 16 cells on the two short edges,
     iD = 1 - exp(-t/2000), coil at the centre with period 500."""
