@@ -85,7 +85,7 @@ struct mm_ctx {
   // Cholesky method
   bool factored = false;
   double f_theta = 0.0, f_dt = 0.0;
-  Dev Z, Dinv, DinvT, I, b, yv, kstep;
+  Dev Z, Dinv, DinvT, I, b, yv, acc, kstep;
   bool use_graph = true;  // MM_NO_GRAPH=1 in the environment turns graphs off
   // probe partial sums of one step call
   Dev pp;
@@ -566,16 +566,18 @@ mm_status mm_step_cholesky(mm_ctx* c, double theta, double dt, int64_t n_steps,
       c->DinvT.alloc(sizeof(double) * NB * B * B);
       c->b.alloc(sizeof(double) * n0);
       c->yv.alloc(sizeof(double) * n0);
-      c->kstep.alloc(sizeof(int64_t));
+      c->acc.alloc(sizeof(double) * 2 * (B / 256) * n0);
+      c->kstep.alloc(2 * sizeof(int64_t));
       // b0: Z = Li + theta dt Ri = C C^T   (Ne = 0: Li = L, Ri = R)
       double* Z = c->Z.d();
       const int m = (int)c->m;
       assemble_L(c->xyz.d() + 3 * m, c->h, n0, Z, n0, false, s, c->lr(theta * dt));
       add_csr_lower(Z, n0, theta * dt, c->R(), s);
       factor_checked(Z, n0, c->status.as<int64_t>(), c->tmp, s, "Li + theta dt Ri");
-      c->tmp.alloc(sizeof(double) * trtri_ws_elems(B));
+      c->tmp.alloc(sizeof(double) * std::max<int64_t>(trtri_ws_elems(B), (int64_t)B * n0));
       diag_block_inverses(Z, n0, n0, B, c->Dinv.d(), c->tmp.d(), trtri_ws_elems(B), s);
       transpose_blocks(c->Dinv.d(), NB, B, c->DinvT.d(), s);
+      trsv_prescale(Z, n0, B, c->Dinv.d(), c->tmp.d(), s);
       MM_HIP_TRY(hipStreamSynchronize(s));
       c->tmp.release();
       c->factored = true;
@@ -599,6 +601,7 @@ mm_status mm_step_cholesky(mm_ctx* c, double theta, double dt, int64_t n_steps,
     cs.f.i_src = i_src; cs.f.i_D = i_D;
     cs.theta = theta; cs.dt = dt;
     cs.I = c->I.d(); cs.b = c->b.d(); cs.y = c->yv.d();
+    cs.accf = c->acc.d(); cs.accb = c->acc.d() + (B / 256) * n0;
     cs.Pt = c->Pt.d(); cs.n_probe = c->n_probe;
     cs.probe_partial = c->pp.d();
     chol_steps(cs, 0, n_steps, s);

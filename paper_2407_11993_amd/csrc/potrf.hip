@@ -22,31 +22,68 @@ namespace {
 constexpr int DB = 128;        // diagonal block size
 constexpr int LDL = DB + 1;    // LDS leading dimension
 
+// Stage the jb x jb (jb <= 128) block Ab (leading dimension lda) into LDS,
+// keeping the lower triangle when `lower` (zero above): thread t reads rows
+// t % 128 of the columns t / 128 + 2m, 32 loads in flight per batch.
+__device__ void stage_block(const double* Ab, int64_t lda, int jb, bool lower, double* L) {
+  const int t = threadIdx.x, i = t & 127, jh = t >> 7;
+  const int ic = min(i, jb - 1);
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    double r[32];
+#pragma unroll
+    for (int m = 0; m < 32; ++m) {
+      const int j = min(jh + 2 * (32 * b + m), jb - 1);
+      r[m] = Ab[ic + (int64_t)j * lda];
+    }
+#pragma unroll
+    for (int m = 0; m < 32; ++m) {
+      const int j = jh + 2 * (32 * b + m);
+      if (i < jb && j < jb) L[i + j * LDL] = (!lower || i >= j) ? r[m] : 0.0;
+    }
+  }
+}
+
 // In-LDS factorisation of the jb x jb (jb <= 128) lower triangle L[i + j*LDL],
-// blocked by 16 columns: the 16 x 16 diagonal piece is factored by one
-// thread (left-looking inside the piece), the rows below it by one thread
-// per row (forward substitution), and the trailing lower triangle takes the
-// rank-16 update in parallel.  Needs blockDim.x == 256.  A non-positive pivot
-// is recorded in *bad (local index) and replaced by 1 so the work finishes.
+// blocked by 16 columns: the 16 x 16 diagonal piece is factored by the first
+// wave (right-looking, lane = one row and four columns of the piece), the
+// rows below it by one thread per row (forward substitution), and the
+// trailing lower triangle takes the rank-16 update in parallel.  Needs
+// blockDim.x == 256.  A non-positive pivot is recorded in *bad (local index)
+// and replaced by 1 so the work finishes.
+//
+// The single-wave loops rely on one wave's LDS operations completing in
+// program order: every lane's reads of a column are issued before any lane
+// writes it, so no workgroup barrier is needed inside them.
 __device__ void lds_potrf16(double* L, int jb, int* bad) {
   const int t = threadIdx.x;
   for (int k0 = 0; k0 < jb; k0 += 16) {
     const int ke = min(k0 + 16, jb);
-    if (t == 0) {
+    if (t < 64) {
+      const int i = k0 + (t & 15), jq = k0 + (t >> 4);
       for (int k = k0; k < ke; ++k) {
         double d = L[k + k * LDL];
-        for (int c = k0; c < k; ++c) d -= L[k + c * LDL] * L[k + c * LDL];
         if (!(d > 0.0)) {
-          if (*bad < 0) *bad = k;
+          if (t == 0 && *bad < 0) *bad = k;
           d = 1.0;
         }
         d = sqrt(d);
-        L[k + k * LDL] = d;
-        for (int i = k + 1; i < ke; ++i) {
-          double x = L[i + k * LDL];
-          for (int c = k0; c < k; ++c) x -= L[i + c * LDL] * L[k + c * LDL];
-          L[i + k * LDL] = x / d;
+        const double li = (i > k && i < ke) ? L[i + k * LDL] / d : 0.0;
+        double lj[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int j = jq + 4 * q;
+          lj[q] = (j > k && j < ke) ? L[j + k * LDL] / d : 0.0;
         }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int j = jq + 4 * q;
+          if (j > k && i >= j && i < ke) L[i + j * LDL] -= li * lj[q];
+        }
+        if (t < 16 && i > k && i < ke) L[i + k * LDL] = li;
+        if (t == 0) L[k + k * LDL] = d;
+        __builtin_amdgcn_wave_barrier();
       }
     }
     __syncthreads();
@@ -82,15 +119,19 @@ __device__ void lds_trtri16(double* L, int jb) {
   const int nblk = (jb + 15) / 16;
   for (int bj = nblk - 1; bj >= 0; --bj) {
     const int j0 = bj * 16, je = min(j0 + 16, jb), w = je - j0;
-    if (t == 0) {
-      for (int j = je - 1; j >= j0; --j) {
-        const double xjj = 1.0 / L[j + j * LDL];
-        for (int i = je - 1; i > j; --i) {
-          double sacc = 0.0;
-          for (int k = j + 1; k <= i; ++k) sacc += L[i + k * LDL] * L[k + j * LDL];
-          L[i + j * LDL] = -sacc * xjj;
-        }
-        L[j + j * LDL] = xjj;
+    // X_jj = L_jj^{-1} row by row (L X = I): lane c owns column c; row r
+    // reads the original row r of L and the finished rows above it
+    if (t < 64) {
+      const int c = t;
+      for (int r = 0; r < w; ++r) {
+        const double xrr = 1.0 / L[(j0 + r) + (j0 + r) * LDL];
+        double sacc = 0.0;
+        if (c < r)
+          for (int k = c; k < r; ++k) sacc += L[(j0 + r) + (j0 + k) * LDL] * L[(j0 + k) + (j0 + c) * LDL];
+        __builtin_amdgcn_wave_barrier();
+        if (c < r) L[(j0 + r) + (j0 + c) * LDL] = -sacc * xrr;
+        if (c == r) L[(j0 + r) + (j0 + r) * LDL] = xrr;
+        __builtin_amdgcn_wave_barrier();
       }
     }
     __syncthreads();
@@ -122,10 +163,7 @@ __global__ void __launch_bounds__(256) potrf_diag(double* A, int64_t lda,
   const int t = threadIdx.x;
   if (t == 0) bad = -1;
   double* Ab = A + j0 + j0 * lda;
-  for (int e = t; e < jb * jb; e += blockDim.x) {
-    const int i = e % jb, j = e / jb;
-    L[i + j * LDL] = Ab[i + (int64_t)j * lda];
-  }
+  stage_block(Ab, lda, jb, false, L);
   __syncthreads();
   lds_potrf16(L, jb, &bad);
   for (int e = t; e < jb * jb; e += blockDim.x) {
@@ -153,10 +191,7 @@ __global__ void __launch_bounds__(256) trtri_diag(double* A, int64_t lda,
   const int64_t j0 = (int64_t)blockIdx.x * bs;
   const int jb = (int)min((int64_t)bs, n - j0);
   double* Ab = A + j0 + j0 * lda;
-  for (int e = t; e < jb * jb; e += blockDim.x) {
-    const int i = e % jb, j = e / jb;
-    L[i + j * LDL] = (i >= j) ? Ab[i + (int64_t)j * lda] : 0.0;
-  }
+  stage_block(Ab, lda, jb, true, L);
   __syncthreads();
   lds_trtri16(L, jb);
   for (int e = t; e < jb * jb; e += blockDim.x) {
