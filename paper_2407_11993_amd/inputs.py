@@ -321,6 +321,28 @@ def config5(nx: int = 128, ny: int = 256, n_i: int = 8, n_j: int = 8, T: int = 1
                 rho_bg=rho_bg, rho_ref=rho_ref, M=M, i_src=i_src, T=T)
 
 
+def config5_mini(T: int = 2000, seed: int = 5):
+    """The adjoint workload at a quarter of the size in x and y: 32x64 plate
+    (N = 2048), background log-uniform (seed 5), defect A at x in [10,13),
+    y in [15,16) (rho = 1e3) and defect B at x in [20,22), y in [45,47)
+    (rho = 5) in the reference field, 8 coils at (8 i + 3.5, 32 j + 15.5, 2),
+    i < 4, j < 2, sharing the same Gaussian pulse."""
+    nx, ny = 32, 64
+    dims = (nx, ny, 1)
+    xyz = grid(*dims)
+    n = xyz.shape[0]
+    rho_bg = rho_loguniform(n, seed)
+    rho_ref = rho_bg.copy()
+    paint_box(rho_ref, dims, (10, 13), (15, 16), 1e3)
+    paint_box(rho_ref, dims, (20, 22), (45, 47), 5.0)
+    coils = [(8 * i + 3.5, 32 * j + 15.5, 2.0) for j in range(2) for i in range(4)]
+    M = np.stack([coil_coupling(xyz, p) for p in coils], axis=1)
+    t = tk(T, 1.0)
+    i_src = np.exp(-((t - 500.0) / 100.0) ** 2)
+    return dict(name=f"adjoint-{nx}x{ny}-{len(coils)}coils", dims=dims, xyz=xyz,
+                rho_bg=rho_bg, rho_ref=rho_ref, M=M, i_src=i_src, T=T)
+
+
 def config3(T: int = 100000) -> Workload:
     """256x384 plate, rho = 1, electrodes of 16 cells on the two short edges,
     iD = 1 - exp(-t/2000), coil at the centre with period 500."""

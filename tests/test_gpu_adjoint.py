@@ -55,6 +55,38 @@ def test_adjoint_matches_oracle(orc, theta, K):
     assert np.abs(_np(gi) - gir).max() < 1e-9 * np.abs(gir).max()
 
 
+def test_quarter_size_workload_matches_stored_oracle_adjoint():
+    """The 32x64 adjoint workload (8 coils, T = 2000, checkpoints every 500)
+    against the oracle's adjoint stored in tests/golden by
+    make_adjoint_golden.py (which calls only the oracle; about half an hour
+    on one core): J, 512 sampled dJ/dR entries (the 64 largest and 448 at
+    random) and every dJ/di sample, to 1e-9 of their maxima."""
+    import os
+    import re
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    cfg = inputs.config5_mini()
+    T, M = cfg["T"], cfg["M"]
+    C = M.shape[1]
+    obs = np.loadtxt(os.path.join(here, "adjoint_mini_obs.txt")).reshape(C, T)
+    with open(os.path.join(here, "adjoint_mini_dJdR.txt")) as f:
+        hdr = f.readline()
+    J_ref = float(re.search(r"J=(\S+)", hdr).group(1))
+    g_max = float(re.search(r"max_abs_dJdR=(\S+)", hdr).group(1))
+    nnz = int(re.search(r"nnz=(\d+)", hdr).group(1))
+    tab = np.loadtxt(os.path.join(here, "adjoint_mini_dJdR.txt"))
+    idx, g_ref = tab[:, 0].astype(np.int64), tab[:, 1]
+    gi_ref = np.loadtxt(os.path.join(here, "adjoint_mini_dJdi.txt"))
+    s, R = _solver(cfg["dims"], cfg["xyz"], cfg["rho_bg"], M)
+    runs = np.arange(C)
+    J, gR, gi = s.adjoint(0.5, 1.0, T, runs, runs, cfg["i_src"], obs, ckpt_every=500)
+    got = _np(gR)
+    assert got.size == nnz == R.col.size
+    assert abs(float(J) - J_ref) < 1e-10 * J_ref
+    assert np.abs(got[idx] - g_ref).max() < 1e-9 * g_max
+    assert abs(np.abs(got).max() - g_max) < 1e-9 * g_max
+    assert np.abs(_np(gi) - gi_ref).max() < 1e-9 * np.abs(gi_ref).max()
+
+
 def test_checkpoint_interval_does_not_change_the_result():
     dims, xyz, rho, M, i_src, obs = _problem(T=90)
     T = obs.shape[1]

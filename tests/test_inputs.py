@@ -14,3 +14,16 @@ def test_resistance_model_reproduces_the_assembly():
         np.add.at(vals, ent, coef * rho[cel])
         assert np.array_equal(rowptr, R.rowptr) and np.array_equal(col, R.col)
         assert np.abs(vals - R.val).max() < 1e-14 * np.abs(R.val).max()
+
+
+def test_adjoint_workloads_have_the_stated_shapes():
+    """The full and quarter-size adjoint workloads: plate sizes, coil counts,
+    the two defects only in the reference field, the shared pulse."""
+    for cfg, n, C, T, (a, b) in ((inputs.config5(T=50), 128 * 256, 64, 50, (1e3, 5.0)),
+                                 (inputs.config5_mini(T=40), 32 * 64, 8, 40, (1e3, 5.0))):
+        assert cfg["xyz"].shape == (n, 3)
+        assert cfg["M"].shape == (n, C)
+        assert cfg["i_src"].shape == (T + 1,)
+        diff = cfg["rho_ref"] != cfg["rho_bg"]
+        assert set(np.unique(cfg["rho_ref"][diff])) == {a, b}
+        assert np.all((cfg["rho_bg"] >= 0.5) & (cfg["rho_bg"] <= 2.0))
