@@ -121,13 +121,11 @@ struct Forcing {
 
 struct CholStep {
   int64_t n0 = 0;
-  const double* Cf = nullptr;  // factor of Z after trsv_prescale (W below, V^T above)
-  int64_t ld = 0;
+  const double* pf = nullptr;  // forward panels (trsv_prescale)
+  const double* pb = nullptr;  // backward panels (trsv_prescale)
   int B = 128;                 // block size (trsv_block(n0))
   const double* Dinv = nullptr;  // inverses of the B x B diagonal blocks of the factor
   const double* DinvT = nullptr; // the same blocks transposed
-  double* accf = nullptr;      // forward partial sums, (B / 256) x n0
-  double* accb = nullptr;      // backward partial sums, (B / 256) x n0
   int64_t* kstep = nullptr;    // device step counter and its per-step copy (two int64)
   bool use_graph = true;       // replay one captured step per time step
   Csr Ri;                      // reduced resistance, sparse part
@@ -142,11 +140,13 @@ struct CholStep {
   double* probe_partial = nullptr;  // n_steps x trsv_parts(n0) x n_probe
 };
 void chol_steps(const CholStep& c, int64_t k0, int64_t n_steps, hipStream_t s);
-// Once per factorisation: with D_J^{-1} = Dinv (block J), overwrite the
-// factor's blocks below the diagonal blocks with W_JK = D_J^{-1} C_JK and fill
-// the blocks above them with V_KJ^T = D_J^{-T} C_KJ^T.  T: B x n workspace.
-void trsv_prescale(double* Cf, int64_t n, int B, const double* Dinv, double* T,
-                   hipStream_t s);
+// Once per factorisation: with C the factor (lower, leading dimension n) and
+// D_J^{-1} = Dinv (block J), form the forward panels W_IK = D_I^{-1} C_IK and
+// the backward panels V_KJ = C_KJ D_J^{-1} in row-contiguous layout (pf, pb;
+// trsv_panel_elems doubles in all).
+int64_t trsv_panel_elems(int64_t n, int B);
+void trsv_prescale(const double* Cf, int64_t n, int B, const double* Dinv, double* pf,
+                   double* pb, hipStream_t s);
 // DinvT(block b) = Dinv(block b)^T for nblocks blocks of B x B.
 void transpose_blocks(const double* Dinv, int64_t nblocks, int B, double* DinvT,
                       hipStream_t s);

@@ -85,7 +85,7 @@ struct mm_ctx {
   // Cholesky method
   bool factored = false;
   double f_theta = 0.0, f_dt = 0.0;
-  Dev Z, Dinv, DinvT, I, b, yv, acc, kstep;
+  Dev Z, Dinv, DinvT, panels, I, b, yv, kstep;
   bool use_graph = true;  // MM_NO_GRAPH=1 in the environment turns graphs off
   // probe partial sums of one step call
   Dev pp;
@@ -566,7 +566,6 @@ mm_status mm_step_cholesky(mm_ctx* c, double theta, double dt, int64_t n_steps,
       c->DinvT.alloc(sizeof(double) * NB * B * B);
       c->b.alloc(sizeof(double) * n0);
       c->yv.alloc(sizeof(double) * n0);
-      c->acc.alloc(sizeof(double) * 2 * (B / 256) * n0);
       c->kstep.alloc(2 * sizeof(int64_t));
       // b0: Z = Li + theta dt Ri = C C^T   (Ne = 0: Li = L, Ri = R)
       double* Z = c->Z.d();
@@ -574,12 +573,16 @@ mm_status mm_step_cholesky(mm_ctx* c, double theta, double dt, int64_t n_steps,
       assemble_L(c->xyz.d() + 3 * m, c->h, n0, Z, n0, false, s, c->lr(theta * dt));
       add_csr_lower(Z, n0, theta * dt, c->R(), s);
       factor_checked(Z, n0, c->status.as<int64_t>(), c->tmp, s, "Li + theta dt Ri");
-      c->tmp.alloc(sizeof(double) * std::max<int64_t>(trtri_ws_elems(B), (int64_t)B * n0));
+      c->tmp.alloc(sizeof(double) * trtri_ws_elems(B));
       diag_block_inverses(Z, n0, n0, B, c->Dinv.d(), c->tmp.d(), trtri_ws_elems(B), s);
       transpose_blocks(c->Dinv.d(), NB, B, c->DinvT.d(), s);
-      trsv_prescale(Z, n0, B, c->Dinv.d(), c->tmp.d(), s);
+      const int64_t pe = trsv_panel_elems(n0, B);
+      c->panels.alloc(sizeof(double) * std::max<int64_t>(pe, 1));
+      const int64_t nfwd = pe - (int64_t)B * B * (NB * (NB - 1) / 2);
+      trsv_prescale(Z, n0, B, c->Dinv.d(), c->panels.d(), c->panels.d() + nfwd, s);
       MM_HIP_TRY(hipStreamSynchronize(s));
       c->tmp.release();
+      c->Z.release();  // the steps read only the panels and the block inverses
       c->factored = true;
       c->f_theta = theta;
       c->f_dt = dt;
@@ -589,7 +592,11 @@ mm_status mm_step_cholesky(mm_ctx* c, double theta, double dt, int64_t n_steps,
     c->pp.alloc(sizeof(double) * n_steps * parts * c->n_probe);
     CholStep cs;
     cs.n0 = n0;
-    cs.Cf = c->Z.d(); cs.ld = n0;
+    {
+      const int64_t nfwd = trsv_panel_elems(n0, B) - (int64_t)B * B * (NB * (NB - 1) / 2);
+      cs.pf = c->panels.d();
+      cs.pb = c->panels.d() + nfwd;
+    }
     cs.B = B;
     cs.Dinv = c->Dinv.d();
     cs.DinvT = c->DinvT.d();
@@ -601,7 +608,6 @@ mm_status mm_step_cholesky(mm_ctx* c, double theta, double dt, int64_t n_steps,
     cs.f.i_src = i_src; cs.f.i_D = i_D;
     cs.theta = theta; cs.dt = dt;
     cs.I = c->I.d(); cs.b = c->b.d(); cs.y = c->yv.d();
-    cs.accf = c->acc.d(); cs.accb = c->acc.d() + (B / 256) * n0;
     cs.Pt = c->Pt.d(); cs.n_probe = c->n_probe;
     cs.probe_partial = c->pp.d();
     chol_steps(cs, 0, n_steps, s);

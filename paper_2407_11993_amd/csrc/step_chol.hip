@@ -5,18 +5,18 @@
 // Block substitution with pre-scaled panels.  With D = blockdiag(C_JJ) (B x B
 // blocks, B = 2048 at large N) the two solves are
 //   forward:  y_J = D_J^{-1} b_J - sum_{K<J} W_JK y_K,      W_JK = D_J^{-1} C_JK,
-//   backward: x_J = D_J^{-T} y_J - sum_{K>J} V_KJ^T x_K,    V_KJ = C_KJ D_J^{-1},
-// so once per factorisation W replaces C's blocks below the diagonal blocks
-// and V^T fills the (otherwise unused) blocks above them.  A solve is then
-// one block-diagonal product over all blocks at once, followed by a chain of
-// panel updates with no diagonal work between them, and both solves read
-// column panels.  The bytes read per solve are those of C's lower triangle
-// (D^{-1}'s lower triangles plus the panels), and the solves stay HBM-bound.
-// A panel update is split into 256-column chunks, each accumulating into its
-// own copy of the partial sums, so that short panels still fill the chip and
-// no two workgroups write the same word.  Synchronisation is by kernel
-// boundaries only (no workgroup waits on another); every sum has a fixed
-// order, so reruns are bit-identical.
+//   backward: x_J = D_J^{-T} y_J - sum_{K>J} V_KJ^T x_K,    V_KJ = C_KJ D_J^{-1}.
+// W and V are formed once per factorisation and stored as panels whose rows
+// are contiguous: panel K of the forward solve holds, for every row i below
+// block K, the B entries W(i, block K); panel K of the backward solve holds,
+// for every row i above block K, the entries V^T(i, block K).  A solve is one
+// block-diagonal product over all blocks at once (the block inverses' lower
+// triangles, two rows folded per wave), then a chain of panel updates with no
+// diagonal work between them, each a set of row dot products streaming its
+// panel front to back, one wave per row.  The words read per solve equal
+// those of C's lower triangle, and the solves are HBM-bound.
+// Synchronisation is by kernel boundaries only (no workgroup waits on
+// another); every sum has a fixed order, so reruns are bit-identical.
 //
 // One step's launches read the step index from device memory, so the whole
 // step is captured once into a HIP graph and replayed n_steps times.
@@ -26,18 +26,31 @@ namespace mm {
 namespace {
 
 constexpr int NT = 256;
-constexpr int MAXB = 4096;
-constexpr int UW = 16;  // waves per panel-update workgroup
-constexpr int UL = 16;  // column loads in flight per wave (UW * UL = 256 columns per chunk)
 
-// Workgroups of a diagonal-block kernel: four waves, two rows or columns each.
-constexpr int DT = 512;  // block-diagonal kernels: 8 waves, 16 rows or columns per workgroup
-__host__ __device__ inline int diag_groups(int B) { return (B / 2 + DT / 64 - 1) / (DT / 64); }
-
-// base[byte_off / 8] with a 32-bit byte offset, so the load can take the
-// scalar base + 32-bit vector offset form (one address register per load)
-__device__ __forceinline__ double ld_off(const double* base, unsigned byte_off) {
-  return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + byte_off);
+// Wave-wide sum, every lane gets the result: sums over quads and rows of 16
+// lanes by DPP moves (xor 1, xor 2, half-row mirror, row mirror), then the
+// four row sums read with readlane and added in a fixed order.
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+  const int2 b = __builtin_bit_cast(int2, v);
+  int2 r;
+  r.x = __builtin_amdgcn_update_dpp(0, b.x, CTRL, 0xF, 0xF, false);
+  r.y = __builtin_amdgcn_update_dpp(0, b.y, CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, r);
+}
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const int2 b = __builtin_bit_cast(int2, v);
+  int2 r;
+  r.x = __builtin_amdgcn_readlane(b.x, l);
+  r.y = __builtin_amdgcn_readlane(b.y, l);
+  return __builtin_bit_cast(double, r);
+}
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v += dpp<0xB1>(v);
+  v += dpp<0x4E>(v);
+  v += dpp<0x141>(v);
+  v += dpp<0x140>(v);
+  return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -121,202 +134,98 @@ __global__ void __launch_bounds__(256) lowrank_rhs_k(RLowRank lr, double dt,
   }
 }
 
-// Block-diagonal products.  Rows (forward) or columns (backward) p and
-// jb-1-p of a triangular block inverse are folded onto one wave: together
-// they hold jb + 1 entries, so every wave does the same work and issues all
-// of its loads at once (clamped addresses, masked values).  KC load slots per
-// lane: the two rows of a forward pair span at most B / 64 + 1 chunks of 64,
-// the two columns of a backward pair at most B / 64 + 2 (their first chunks
-// need not be aligned).  blockIdx.y is the block; its right-hand side is
-// staged in LDS once per workgroup.  The workgroups of block J also clear
-// the accumulators (S x n) on the block's rows for the panel updates that
-// follow.
-// Forward: z_J(r) = sum_{c <= r} Dinv_J(r, c) b_J(c), row r of Dinv_J read
-// contiguously from DinvT.
-template <int KC>
-__global__ void __launch_bounds__(DT) fwd_bd_k(int64_t n, int B, const double* __restrict__ DinvT,
-                                               const double* __restrict__ b,
-                                               double* __restrict__ z, double* __restrict__ acc,
-                                               int S) {
-  __shared__ double bs[MAXB];
-  const int t = threadIdx.x, lane = t & 63;
-  const int wave = t >> 6;
+// Block-diagonal products, all blocks in one launch (blockIdx.y = block J),
+// one wave per row of the triangle:
+//   forward  (LOWER): out_J(r) = sum_{c <= r} Dinv_J(r, c) in_J(c), row r of
+//                     Dinv_J read contiguously from DinvT;
+//   backward:         out_J(c) = sum_{r >= c} Dinv_J(r, c) in_J(r), column c
+//                     of Dinv_J read contiguously.
+// A wave takes R pairs of rows (p, jb - 1 - p), whose lengths add up to
+// jb + 1, so every wave does the same work; a row's 64-entry chunks are
+// loaded at once (chunks outside the triangle skipped, wave-uniformly) and
+// reduced over the wave by DPP moves.  The block's input is staged in LDS
+// once per workgroup.
+template <int NL, bool LOWER>
+__global__ void __launch_bounds__(NT) trid_k(int64_t n, const double* __restrict__ D,
+                                             const double* __restrict__ in,
+                                             double* __restrict__ out, int R) {
+  constexpr int B = NL * 64;
+  __shared__ double xs[B];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int64_t J = blockIdx.y;
   const int64_t J0 = J * B;
   const int jb = (int)min((int64_t)B, n - J0);
-  // a wave past the last pair computes pair 0 again and discards it, so the
-  // barrier below is reached by every thread
-  const int pw = blockIdx.x * (DT / 64) + wave;
-  const bool live = pw < (jb + 1) / 2;
-  const int p = live ? pw : 0;
-  const int r1 = p, r2 = jb - 1 - p;
-  const int n1 = r1 / 64 + 1, n2 = (r2 > r1) ? r2 / 64 + 1 : 0;
-  // one base per block and 32-bit byte offsets (8 B * B < 2^32)
-  const double* Db = DinvT + J * (int64_t)B * B;
-  double dv[KC];
-#pragma unroll
-  for (int v = 0; v < KC; ++v) {
-    const bool sec = v >= n1;
-    const int rr = sec ? r2 : r1;
-    dv[v] = ld_off(Db, 8u * (unsigned)(rr * B + min(64 * (sec ? v - n1 : v) + lane, rr)));
-  }
-  // the block's right-hand side, staged while the loads above are in flight
-  for (int c = t; c < jb; c += DT) bs[c] = b[J0 + c];
-  for (int64_t e = (int64_t)blockIdx.x * DT + t; e < (int64_t)jb * S; e += (int64_t)gridDim.x * DT)
-    acc[(e / jb) * n + J0 + e % jb] = 0.0;
+  const int np = (jb + 1) / 2;  // pairs
+  for (int c = t; c < B; c += NT) xs[c] = (c < jb) ? in[J0 + c] : 0.0;
   __syncthreads();
-  double s1 = 0.0, s2 = 0.0;
+  const double* Db = D + J * (int64_t)B * B;
+  for (int rr = 0; rr < 2 * R; ++rr) {
+    const int p = (blockIdx.x * R + rr / 2) * (NT / 64) + wave;
+    if (p >= np) break;  // wave-uniform
+    const int a = (rr & 1) ? jb - 1 - p : p;
+    if ((rr & 1) && a == p) break;  // the middle row of an odd block, done already
+    // chunks [m0, m1] of this row hold its entries
+    const int m0 = LOWER ? 0 : a / 64, m1 = LOWER ? a / 64 : (jb - 1) / 64;
+    const double* row = Db + (int64_t)a * B;
+    double pv[NL];
 #pragma unroll
-  for (int v = 0; v < KC; ++v) {
-    const bool sec = v >= n1;
-    const int rr = sec ? r2 : r1;
-    const int c = 64 * (sec ? v - n1 : v) + lane;
-    const bool ok = v < n1 + n2 && c <= rr;
-    const double val = ok ? dv[v] * bs[min(c, rr)] : 0.0;
-    if (sec) s2 += val;
-    else s1 += val;
-  }
-  s1 = wave_sum(s1);
-  s2 = wave_sum(s2);
-  if (live && lane == 0) {
-    z[J0 + r1] = s1;
-    if (r2 > r1) z[J0 + r2] = s2;
-  }
-}
-
-// Backward: x_J(c) = sum_{r >= c} Dinv_J(r, c) y_J(r), column c of Dinv_J
-// read contiguously, y the forward solve's result.
-template <int KC>
-__global__ void __launch_bounds__(DT) bwd_bd_k(int64_t n, int B, const double* __restrict__ Dinv,
-                                               const double* __restrict__ y, int S,
-                                               double* __restrict__ x, double* __restrict__ accb) {
-  __shared__ double ys[MAXB];
-  const int t = threadIdx.x, lane = t & 63;
-  const int wave = t >> 6;
-  const int64_t J = blockIdx.y;
-  const int64_t J0 = J * B;
-  const int jb = (int)min((int64_t)B, n - J0);
-  const int pw = blockIdx.x * (DT / 64) + wave;
-  const bool live = pw < (jb + 1) / 2;
-  const int p = live ? pw : 0;
-  const int c1 = p, c2 = jb - 1 - p;
-  const int last = (jb - 1) / 64;  // chunk of the block's last row
-  const int f1 = c1 / 64, f2 = c2 / 64;
-  const int n1 = last - f1 + 1, n2 = (c2 > c1) ? last - f2 + 1 : 0;
-  // one base per block and 32-bit byte offsets (8 B * B < 2^32)
-  const double* Db = Dinv + J * (int64_t)B * B;
-  double dv[KC];
+    for (int m = 0; m < NL; ++m) pv[m] = (m >= m0 && m <= m1) ? row[64 * m + lane] : 0.0;
+    double a4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int v = 0; v < KC; ++v) {
-    const bool sec = v >= n1;
-    const int cc = sec ? c2 : c1;
-    const int r = 64 * (sec ? f2 + (v - n1) : f1 + v) + lane;
-    dv[v] = ld_off(Db, 8u * (unsigned)(cc * B + min(max(r, cc), jb - 1)));
-  }
-  for (int c = t; c < jb; c += DT) ys[c] = y[J0 + c];
-  for (int64_t e = (int64_t)blockIdx.x * DT + t; e < (int64_t)jb * S; e += (int64_t)gridDim.x * DT)
-    accb[(e / jb) * n + J0 + e % jb] = 0.0;
-  __syncthreads();
-  double s1 = 0.0, s2 = 0.0;
-#pragma unroll
-  for (int v = 0; v < KC; ++v) {
-    const bool sec = v >= n1;
-    const int cc0 = sec ? c2 : c1;
-    const int r = 64 * (sec ? f2 + (v - n1) : f1 + v) + lane;
-    const bool ok = v < n1 + n2 && r >= cc0 && r < jb;
-    const double val = ok ? dv[v] * ys[min(max(r, cc0), jb - 1)] : 0.0;
-    if (sec) s2 += val;
-    else s1 += val;
-  }
-  s1 = wave_sum(s1);
-  s2 = wave_sum(s2);
-  if (live && lane == 0) {
-    x[J0 + c1] = s1;
-    if (c2 > c1) x[J0 + c2] = s2;
-  }
-}
-
-// Panel update with the pre-scaled panel M (W below the diagonal blocks for
-// the forward solve, V^T above them for the backward one):
-//   acc_g(i) += sum_{c in chunks g, g+G, ...} M(i, col0 + c) v(c),   row0 <= i < row0 + nrows,
-// where a chunk is UW * UL = 256 columns of the panel, g = blockIdx.y < G,
-// and v(c) = z(col0 + c) - sum_q acc_q(col0 + c) are the block's final values
-// (every earlier panel's contribution is in the accumulators), staged in LDS
-// once per workgroup for all of its chunks.  Workgroup: a tile of 64 rows
-// (one per lane, so every wave load is one contiguous 512-byte column
-// segment) walking its chunks, UL columns per wave and chunk, the loads of a
-// chunk issued before the first use; the waves' row sums are combined in LDS
-// in wave order.  Column group g owns accumulator copy g, so no two
-// workgroups write the same word and every sum has a fixed order (no
-// atomics).
-template <int S>
-__global__ void __launch_bounds__(64 * UW) upd_k(int64_t n, int64_t row0, int64_t nrows,
-                                                 int64_t col0, int jb,
-                                                 const double* __restrict__ M, int64_t ld,
-                                                 const double* __restrict__ z,
-                                                 double* __restrict__ acc, int G) {
-  constexpr int CH = UW * UL;  // columns per chunk
-  __shared__ double red[UW][64];
-  __shared__ double vs[S * CH];
-  const int t = threadIdx.x, lane = t & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
-  const int g = blockIdx.y;
-  const int64_t row = row0 + (int64_t)blockIdx.x * 64 + lane;
-  const bool rok = row < row0 + nrows;
-  const double* Mp = M + min(row, row0 + nrows - 1);  // clamped row
-  int ch = g;
-  double cv[UL];
-#pragma unroll
-  for (int u = 0; u < UL; ++u) cv[u] = Mp[(col0 + min(ch * CH + wave * UL + u, jb - 1)) * ld];
-  __builtin_amdgcn_sched_barrier(0);  // the first chunk's loads issue first
-  double old = 0.0;
-  if (wave == 0 && rok) old = acc[(int64_t)g * n + row];
-  const int P = (S - g + G - 1) / G;  // chunks of this workgroup
-  for (int e = t; e < P * CH; e += 64 * UW) {
-    const int c = (g + (e / CH) * G) * CH + e % CH;
-    double v = 0.0;  // zero past the panel's last column
-    if (c < jb) {
-      v = z[col0 + c];
-#pragma unroll
-      for (int q = 0; q < S; ++q) v -= acc[(int64_t)q * n + col0 + c];
+    for (int m = 0; m < NL; ++m) {
+      const int e = 64 * m + lane;
+      const bool ok = LOWER ? e <= a : e >= a;  // the triangle (xs is zero past jb)
+      a4[m & 3] += ok ? pv[m] * xs[e] : 0.0;
     }
-    vs[e] = v;
+    const double d = wave_sum_dpp((a4[0] + a4[1]) + (a4[2] + a4[3]));
+    if (lane == 0) out[J0 + a] = d;
   }
-  __syncthreads();
-  double a4[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int p = 0;; ++p) {
-#pragma unroll
-    for (int u = 0; u < UL; ++u) a4[u & 3] += cv[u] * vs[p * CH + wave * UL + u];
-    ch += G;
-    if (ch >= S) break;
-#pragma unroll
-    for (int u = 0; u < UL; ++u) cv[u] = Mp[(col0 + min(ch * CH + wave * UL + u, jb - 1)) * ld];
-  }
-  red[wave][lane] = (a4[0] + a4[1]) + (a4[2] + a4[3]);
-  __syncthreads();
-  if (wave != 0) return;
-  double sum = 0.0;
-#pragma unroll
-  for (int w = 0; w < UW; ++w) sum += red[w][lane];
-  if (rok) acc[(int64_t)g * n + row] = old + sum;
 }
 
-// y = z - sum_q acc_q (the forward solve's result, in place of z).
-__global__ void combine_k(int64_t n, double* __restrict__ z, const double* __restrict__ acc,
-                          int S) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double v = z[i];
-  for (int q = 0; q < S; ++q) v -= acc[(int64_t)q * n + i];
-  z[i] = v;
+// Panel update, one wave per row:
+//   vec(row0 + i) -= sum_{c < jb} P(c, i) vec(col0 + c),   0 <= i < nrows,
+// with P (B x nrows, column-major, leading dimension B) the panel, so row i's
+// B entries are contiguous.  Lane l reads entries l + 64 m (every wave load
+// one contiguous 512-byte segment, all B / 64 of a row in flight at once),
+// the block's values vec(col0 + c) (zero past jb) are staged in LDS once per
+// workgroup, and a row's sum is reduced over the wave by DPP moves.  A
+// workgroup's rows are consecutive (wave w takes rows w, w + 4, ...), so it
+// streams one contiguous piece of the panel; latency is hidden by the other
+// waves of the CU.
+template <int NL>
+__global__ void __launch_bounds__(NT) rowupd_k(int64_t row0, int64_t nrows, int64_t col0, int jb,
+                                               const double* __restrict__ P,
+                                               double* __restrict__ vec, int R) {
+  constexpr int B = NL * 64;
+  __shared__ double xs[B];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  int64_t i = (int64_t)blockIdx.x * R * (NT / 64) + wave;
+  double pv[NL];
+  if (i < nrows) {
+#pragma unroll
+    for (int m = 0; m < NL; ++m) pv[m] = P[i * B + 64 * m + lane];
+  }
+  for (int c = t; c < B; c += NT) xs[c] = (c < jb) ? vec[col0 + c] : 0.0;
+  __syncthreads();
+  for (int r = 0; r < R && i < nrows; ++r) {
+    if (r > 0) {
+#pragma unroll
+      for (int m = 0; m < NL; ++m) pv[m] = P[i * B + 64 * m + lane];
+    }
+    double a4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int m = 0; m < NL; ++m) a4[m & 3] += pv[m] * xs[64 * m + lane];
+    const double d = wave_sum_dpp((a4[0] + a4[1]) + (a4[2] + a4[3]));
+    if (lane == 0) vec[row0 + i] -= d;
+    i += NT / 64;
+  }
 }
 
-// End of a step: dI = x - sum_q accb_q, Ii += dI, and the probe partial sums
-// of this workgroup's 256 rows (one per workgroup and probe, fixed order).
-// The step index is kstep[1]; the first thread advances kstep[0] (read by
-// no other kernel of the step after chol_rhs_k).
+// End of a step: Ii += dI (dI = x, the backward solve's result) and the probe
+// partial sums of this workgroup's 256 rows (one per workgroup and probe,
+// fixed order).  The step index is kstep[1]; the first thread advances
+// kstep[0] (read by no other kernel of the step after chol_rhs_k).
 __global__ void __launch_bounds__(NT) finish_k(int64_t n, const double* __restrict__ x,
-                                               const double* __restrict__ accb, int S,
                                                double* __restrict__ state,
                                                const double* __restrict__ Pt, int n_probe,
                                                double* __restrict__ pp_base,
@@ -327,13 +236,12 @@ __global__ void __launch_bounds__(NT) finish_k(int64_t n, const double* __restri
   double d = 0.0;
   if (i < n) {
     d = x[i];
-    for (int q = 0; q < S; ++q) d -= accb[(int64_t)q * n + i];
     state[i] += d;
   }
   const int64_t k = kstep[1];
   if (i == 0) kstep[0] = k + 1;
   for (int p = 0; p < n_probe; ++p) {
-    const double v = wave_sum(i < n ? Pt[i + (int64_t)p * n] * d : 0.0);
+    const double v = wave_sum_dpp(i < n ? Pt[i + (int64_t)p * n] * d : 0.0);
     if (lane == 0) red[p][wave] = v;
   }
   __syncthreads();
@@ -357,96 +265,88 @@ __global__ void probe_finish_k(const double* pp, int64_t n_steps, int64_t nparts
   signal[e] = s / dt;
 }
 
-template <int C64>  // C64 = B / 64
-void launch_bd_b(bool fwd, unsigned grid, unsigned nb, hipStream_t s, int64_t n,
-                 const CholStep& c) {
-  if (fwd)
-    hipLaunchKernelGGL((fwd_bd_k<C64 + 1>), dim3(grid, nb), dim3(DT), 0, s, n, c.B, c.DinvT, c.b,
-                       c.y, c.accf, c.B / (UW * UL));
+// Panel offsets (in doubles): forward panel K (K < NB - 1) is B x (n - (K+1) B),
+// backward panel K (K >= 1) is B x K B, each stored after the previous ones.
+int64_t fwd_panel_offset(int64_t n, int B, int64_t K) {
+  // sum_{K' < K} B (n - (K' + 1) B)
+  return (int64_t)B * (K * n - (int64_t)B * K * (K + 1) / 2);
+}
+int64_t bwd_panel_offset(int B, int64_t K) {
+  // sum_{1 <= K' < K} B K' B
+  return (int64_t)B * B * (K * (K - 1) / 2);
+}
+
+// Rows (pairs) per wave: about five workgroups per CU in all.
+int rows_per_wave(int64_t rows) {
+  constexpr int64_t kSlots = 256 * 5 * (NT / 64);
+  return (int)std::max<int64_t>(1, ceil_div(rows, kSlots));
+}
+
+template <int NL>
+void launch_trid(bool lower, const CholStep& c, const double* in, double* out, hipStream_t s) {
+  const int64_t n = c.n0;
+  const int64_t NB = ceil_div(n, (int64_t)c.B);
+  const int64_t pairs = (c.B + 1) / 2;
+  const int R = rows_per_wave(pairs * NB);
+  const dim3 grid((unsigned)ceil_div(pairs, (int64_t)R * (NT / 64)), (unsigned)NB);
+  if (lower)
+    hipLaunchKernelGGL((trid_k<NL, true>), grid, dim3(NT), 0, s, n, c.DinvT, in, out, R);
   else
-    hipLaunchKernelGGL((bwd_bd_k<C64 + 2>), dim3(grid, nb), dim3(DT), 0, s, n, c.B, c.Dinv, c.y,
-                       c.B / (UW * UL), c.b, c.accb);
-}
-void launch_bd(bool fwd, int B, unsigned grid, unsigned nb, hipStream_t s, int64_t n,
-               const CholStep& c) {
-  switch (B) {
-    case 256: launch_bd_b<4>(fwd, grid, nb, s, n, c); break;
-    case 512: launch_bd_b<8>(fwd, grid, nb, s, n, c); break;
-    case 1024: launch_bd_b<16>(fwd, grid, nb, s, n, c); break;
-    case 2048: launch_bd_b<32>(fwd, grid, nb, s, n, c); break;
-    case 4096: launch_bd_b<64>(fwd, grid, nb, s, n, c); break;
-    default: throw Error{kInvalid, "triangular solve: unsupported block size"};
-  }
+    hipLaunchKernelGGL((trid_k<NL, false>), grid, dim3(NT), 0, s, n, c.Dinv, in, out, R);
 }
 
-// Column groups G of a panel update of `tiles` row tiles and S chunks.  With
-// one workgroup per CU at a time (the kernel's register use), a workgroup of
-// P = S / G chunks costs about P + 1/2 chunk-times (the 1/2: staging the
-// block values and combining the waves), so the estimate is
-// ceil(tiles G / CUs) (S / G + 1/2); the smallest G of least estimate wins.
-int upd_groups(int64_t tiles, int S) {
-  constexpr int64_t kCUs = 256;
-  int best = 1;
-  double best_cost = 1e300;
-  for (int G = 1; G <= S; G *= 2) {
-    const double cost = (double)ceil_div(tiles * G, kCUs) * ((double)S / G + 0.5);
-    if (cost < best_cost) {
-      best_cost = cost;
-      best = G;
-    }
-  }
-  return best;
-}
-
-void launch_upd(int64_t n, int64_t row0, int64_t nrows, int64_t col0, int jb, const CholStep& c,
-                const double* z, double* acc, hipStream_t s) {
+template <int NL>
+void launch_rowupd(int64_t row0, int64_t nrows, int64_t col0, int jb, const double* P,
+                   double* vec, hipStream_t s) {
   if (nrows <= 0) return;
-  const int S = c.B / (UW * UL);
-  const int64_t tiles = ceil_div(nrows, 64);
-  const int G = upd_groups(tiles, S);
-  const dim3 grid((unsigned)tiles, (unsigned)G);
-  switch (S) {
-    case 1: hipLaunchKernelGGL((upd_k<1>), grid, dim3(64 * UW), 0, s, n, row0, nrows, col0, jb, c.Cf, c.ld, z, acc, G); break;
-    case 2: hipLaunchKernelGGL((upd_k<2>), grid, dim3(64 * UW), 0, s, n, row0, nrows, col0, jb, c.Cf, c.ld, z, acc, G); break;
-    case 4: hipLaunchKernelGGL((upd_k<4>), grid, dim3(64 * UW), 0, s, n, row0, nrows, col0, jb, c.Cf, c.ld, z, acc, G); break;
-    case 8: hipLaunchKernelGGL((upd_k<8>), grid, dim3(64 * UW), 0, s, n, row0, nrows, col0, jb, c.Cf, c.ld, z, acc, G); break;
-    case 16: hipLaunchKernelGGL((upd_k<16>), grid, dim3(64 * UW), 0, s, n, row0, nrows, col0, jb, c.Cf, c.ld, z, acc, G); break;
-    default: throw Error{kInvalid, "triangular solve: unsupported block size"};
-  }
+  const int R = rows_per_wave(nrows);
+  hipLaunchKernelGGL((rowupd_k<NL>), dim3((unsigned)ceil_div(nrows, (int64_t)R * (NT / 64))),
+                     dim3(NT), 0, s, row0, nrows, col0, jb, P, vec, R);
 }
 
-// One step's launch sequence (the step index is kstep[0], advanced by the last kernel):
-//   b = rhs;  z = D^{-1} b;  for J = 0..NB-2: accf += W(:, J) (z - accf)_J, rows below J;
-//   y = z - accf;  x = D^{-T} y;  for J = NB-1..1: accb += V^T(:, J) (x - accb)_J, rows above J;
-//   dI = x - accb;  Ii += dI;  probe partial sums.
-void enqueue_step(const CholStep& c, hipStream_t s) {
+// One step's launch sequence (the step index is kstep[0], advanced by the
+// last kernel):
+//   b = rhs;  y = D^{-1} b;  for K = 0..NB-2: y(rows below K) -= W(:, K) y_K;
+//   x = D^{-T} y (into b);   for K = NB-1..1: x(rows above K) -= V^T(:, K) x_K;
+//   Ii += x;  probe partial sums.
+template <int NL>
+void enqueue_step_b(const CholStep& c, hipStream_t s) {
   const int64_t n = c.n0;
   const int B = c.B;
-  const int64_t NB = ceil_div(n, B);
+  const int64_t NB = ceil_div(n, (int64_t)B);
   const int64_t parts = trsv_parts(n);
   const unsigned rgrid = (unsigned)ceil_div(n, 256);
-  const unsigned dgrid = (unsigned)diag_groups(B);
   hipLaunchKernelGGL(chol_rhs_k, dim3(rgrid), dim3(256), 0, s, n, c.Ri, c.f, c.theta, c.dt,
                      c.kstep, c.I, c.b);
   if (c.Rlr.ns > 0)
     hipLaunchKernelGGL(lowrank_rhs_k, dim3(1), dim3(256), 0, s, c.Rlr, c.dt, c.I, c.b);
-  launch_bd(true, B, dgrid, (unsigned)NB, s, n, c);
-  for (int64_t J = 0; J + 1 < NB; ++J)
-    launch_upd(n, (J + 1) * B, n - (J + 1) * B, J * B, B, c, c.y, c.accf, s);
-  if (NB > 1)
-    hipLaunchKernelGGL(combine_k, dim3(rgrid), dim3(256), 0, s, n, c.y, c.accf, B / (UW * UL));
-  launch_bd(false, B, dgrid, (unsigned)NB, s, n, c);
-  for (int64_t J = NB - 1; J >= 1; --J)
-    launch_upd(n, 0, J * B, J * B, (int)std::min<int64_t>(B, n - J * B), c, c.b, c.accb, s);
-  hipLaunchKernelGGL(finish_k, dim3((unsigned)parts), dim3(NT), 0, s, n, c.b, c.accb,
-                     B / (UW * UL), c.I, c.Pt, c.n_probe, c.probe_partial, c.kstep, parts);
+  launch_trid<NL>(true, c, c.b, c.y, s);
+  for (int64_t K = 0; K + 1 < NB; ++K)
+    launch_rowupd<NL>((K + 1) * B, n - (K + 1) * B, K * B, B, c.pf + fwd_panel_offset(n, B, K),
+                      c.y, s);
+  launch_trid<NL>(false, c, c.y, c.b, s);
+  for (int64_t K = NB - 1; K >= 1; --K)
+    launch_rowupd<NL>(0, K * B, K * B, (int)std::min<int64_t>(B, n - K * B),
+                      c.pb + bwd_panel_offset(B, K), c.b, s);
+  hipLaunchKernelGGL(finish_k, dim3((unsigned)parts), dim3(NT), 0, s, n, c.b, c.I, c.Pt,
+                     c.n_probe, c.probe_partial, c.kstep, parts);
+}
+
+void enqueue_step(const CholStep& c, hipStream_t s) {
+  switch (c.B) {
+    case 256: enqueue_step_b<4>(c, s); break;
+    case 512: enqueue_step_b<8>(c, s); break;
+    case 1024: enqueue_step_b<16>(c, s); break;
+    case 2048: enqueue_step_b<32>(c, s); break;
+    default: throw Error{kInvalid, "triangular solve: unsupported block size"};
+  }
 }
 
 }  // namespace
 
 int trsv_block(int64_t n) {
-  // about eight diagonal blocks, at most 2048: fewer, larger launches (4096
-  // measured no faster at N = 16384 and doubles the inverse blocks' memory)
+  // about eight diagonal blocks, at most 2048 (4096 measured slower at
+  // N = 16384: the 64-chunk rows lower the occupancy of both kernels)
   int B = 256;
   while (B < 2048 && 8 * (int64_t)(2 * B) <= n) B *= 2;
   return B;
@@ -455,8 +355,8 @@ int trsv_block(int64_t n) {
 int64_t trsv_parts(int64_t n) { return ceil_div(n, NT); }
 
 void chol_steps(const CholStep& c, int64_t k0, int64_t n_steps, hipStream_t s) {
-  MM_REQUIRE(c.B == 256 || c.B == 512 || c.B == 1024 || c.B == 2048 || c.B == 4096, kInvalid,
-             "chol_steps: block size must be a power of two in [256, 4096]");
+  MM_REQUIRE(c.B == 256 || c.B == 512 || c.B == 1024 || c.B == 2048, kInvalid,
+             "chol_steps: block size must be a power of two in [256, 2048]");
   MM_REQUIRE(c.n_probe <= 8, kInvalid, "chol_steps: at most 8 probes");
   MM_REQUIRE(c.Rlr.ns == 0 || (c.Rlr.m >= 1 && c.Rlr.m <= 8), kInvalid,
              "chol_steps: low-rank resistance term of rank 1..8");
@@ -498,29 +398,41 @@ void chol_steps(const CholStep& c, int64_t k0, int64_t n_steps, hipStream_t s) {
     throw Error{kDevice, std::string("Cholesky step graph: ") + hipGetErrorString(e)};
 }
 
-void trsv_prescale(double* Cf, int64_t n, int B, const double* Dinv, double* T,
-                   hipStream_t s) {
-  const int64_t NB = ceil_div(n, B);
-  // V^T first: it reads C's blocks below the diagonal before W overwrites them
-  for (int64_t J = 0; J < NB; ++J) {
-    const int64_t J0 = J * B, jb = std::min<int64_t>(B, n - J0), m = n - J0 - jb;
-    if (m <= 0) continue;
-    Gemm g;  // (V_{below,J})^T = D_J^{-T} C_{below,J}^T, into the blocks right of D_J
-    g.m = jb; g.n = m; g.k = jb;
-    g.A = Dinv + J * (int64_t)B * B; g.lda = B; g.ta = true; g.a_upper = true;
-    g.B = Cf + (J0 + jb) + J0 * n; g.ldb = n; g.tb = true;
-    g.C = Cf + J0 + (J0 + jb) * n; g.ldc = n;
-    gemm(g, s);
+int64_t trsv_panel_elems(int64_t n, int B) {
+  const int64_t NB = ceil_div(n, (int64_t)B);
+  return fwd_panel_offset(n, B, NB - 1) + bwd_panel_offset(B, NB);
+}
+
+void trsv_prescale(const double* Cf, int64_t n, int B, const double* Dinv, double* pf,
+                   double* pb, hipStream_t s) {
+  const int64_t NB = ceil_div(n, (int64_t)B);
+  const int64_t nf = fwd_panel_offset(n, B, NB - 1);
+  // the short last block leaves rows of the backward panels' columns unset
+  fill(pb, bwd_panel_offset(B, NB), 0.0, s);
+  for (int64_t K = 0; K + 1 < NB; ++K) {
+    double* base = pf + fwd_panel_offset(n, B, K);
+    for (int64_t I = K + 1; I < NB; ++I) {
+      const int64_t jbI = std::min<int64_t>(B, n - I * B);
+      Gemm g;  // W_IK^T = C_IK^T D_I^{-T}: row i of panel K is column i here
+      g.m = B; g.n = jbI; g.k = jbI;
+      g.A = Cf + I * B + K * B * n; g.lda = n; g.ta = true;
+      g.B = Dinv + I * (int64_t)B * B; g.ldb = B; g.tb = true; g.b_band = 0;
+      g.C = base + (I - K - 1) * (int64_t)B * B; g.ldc = B;
+      gemm(g, s);
+    }
   }
-  for (int64_t J = 1; J < NB; ++J) {
-    const int64_t J0 = J * B, jb = std::min<int64_t>(B, n - J0);
-    Gemm g;  // W_{J,left} = D_J^{-1} C_{J,left}, through T (B x n)
-    g.m = jb; g.n = J0; g.k = jb;
-    g.A = Dinv + J * (int64_t)B * B; g.lda = B; g.a_lower = true;
-    g.B = Cf + J0; g.ldb = n;
-    g.C = T; g.ldc = jb;
-    gemm(g, s);
-    copy_matrix(T, jb, Cf + J0, n, jb, J0, s);
+  (void)nf;
+  for (int64_t K = 1; K < NB; ++K) {
+    const int64_t jbK = std::min<int64_t>(B, n - K * B);
+    double* base = pb + bwd_panel_offset(B, K);
+    for (int64_t J = 0; J < K; ++J) {
+      Gemm g;  // V_KJ = C_KJ D_J^{-1}: row i of panel K (in block J) is column i here
+      g.m = jbK; g.n = B; g.k = B;
+      g.A = Cf + K * B + J * B * n; g.lda = n;
+      g.B = Dinv + J * (int64_t)B * B; g.ldb = B; g.b_lower = true;
+      g.C = base + J * (int64_t)B * B; g.ldc = B;
+      gemm(g, s);
+    }
   }
 }
 
