@@ -92,6 +92,18 @@ mm_status mm_setup(const mm_problem* problem, void* stream, mm_ctx** out);
  * definite), MM_E_NO_CONVERGE. */
 mm_status mm_decompose(mm_ctx* ctx);
 
+/* The decomposition as the modal signals need it (Sec. 3.2 feeding Sec. 3.3.2):
+ * the eigenvalues and the projected source and probe weights Q^T G^{-1} [F, P],
+ * without forming the eigenvector matrix Q.  Q = Q1 Q2 Z is applied to the
+ * few columns only: Q1^T panel by panel after the band reduction, Q2^T by
+ * every bulge-chase task as it generates its reflector, Z^T by one product
+ * after divide and conquer.  Afterwards mm_step_modal, mm_eigenvalues and
+ * mm_batch_* work as after mm_decompose; mm_probe(MM_MODAL) and
+ * mm_adjoint_modal return MM_E_STATE (they need Q).  Synchronises the
+ * stream.  Errors: those of mm_decompose; MM_E_INVALID when the forcing
+ * columns (2 (Ne-1) + n_src) and the probes exceed 32 in all. */
+mm_status mm_decompose_projected(mm_ctx* ctx);
+
 /* The modal theta-method (Sec. 3.3.2) for n_steps steps:
  *   (1 + theta dt lam_n) dy_n = -dt lam_n y_n + (modal forcing)_n.
  * The forcing is the Cholesky method's right-hand side (Sec. 3.3.1,

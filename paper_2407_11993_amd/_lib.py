@@ -21,7 +21,7 @@ MM_MODAL = 0
 MM_CHOLESKY = 1
 
 # Every exported entry point of include/mm.h.
-SYMBOLS = ["mm_setup", "mm_decompose", "mm_step_modal", "mm_step_cholesky",
+SYMBOLS = ["mm_setup", "mm_decompose", "mm_decompose_projected", "mm_step_modal", "mm_step_cholesky",
            "mm_probe", "mm_reset_state", "mm_eigenvalues", "mm_info",
            "mm_destroy", "mm_last_error", "mm_batch_create", "mm_batch_run",
            "mm_batch_info", "mm_batch_destroy", "mm_adjoint_modal", "mmk_dgemm", "mmk_dpotrf",
@@ -55,6 +55,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     sigs = {
         "mm_setup": [ctypes.POINTER(Problem), vp, ctypes.POINTER(vp)],
         "mm_decompose": [vp],
+        "mm_decompose_projected": [vp],
         "mm_step_modal": [vp, dbl, dbl, i64, vp, vp, vp],
         "mm_step_cholesky": [vp, dbl, dbl, i64, vp, vp, vp],
         "mm_probe": [vp, i32, i32, vp, vp],

@@ -22,6 +22,10 @@ void apply_q1(const double* A, int64_t lda, int64_t n, int nb, const double* T_a
               double* Z, int64_t ldz, int64_t ncols, double* ws, int64_t ws_elems,
               hipStream_t s);
 int64_t apply_q1_ws_elems(int64_t n, int nb, int64_t ncols);
+// Y <- Q1^T Y (the panels' block reflectors transposed, first panel first).
+void apply_q1t(const double* A, int64_t lda, int64_t n, int nb, const double* T_all,
+               double* Y, int64_t ldy, int64_t ncols, double* ws, int64_t ws_elems,
+               hipStream_t s);
 
 // ---- stage 2: B = Q2 T Q2^T by bulge chasing -------------------------------
 struct Sb2stPlan {
@@ -33,8 +37,11 @@ struct Sb2stPlan {
 Sb2stPlan sb2st_plan(int64_t n, int nb);
 // AB has ldab = 2 nb + 1 rows.  Writes d (n), e (n-1), and the reflectors
 // V2 (tasks x nb) and tau2 (tasks); d_offset is plan.offset on the device.
+// With ny > 0 (at most sb2st_max_cols()), Y (n x ny, ld ldy) becomes Q2^T Y.
+int sb2st_max_cols();
 void sb2st(double* AB, int64_t ldab, const Sb2stPlan& plan, const int64_t* d_offset,
-           double* V2, double* tau2, double* d, double* e, hipStream_t s);
+           double* V2, double* tau2, double* d, double* e, hipStream_t s,
+           double* Y = nullptr, int64_t ldy = 0, int ny = 0);
 // Z <- Q2 Z (rows 0..n-1, ncols columns); ws: any size above 2^15 doubles
 // (more is faster: the compact-WY blocks are processed in batches).
 void apply_q2(const Sb2stPlan& plan, const int64_t* d_offset, const double* V2,
@@ -66,5 +73,12 @@ struct EigWork {
 // C (full symmetric, destroyed: it keeps the stage-1 reflectors) -> lam, Q.
 void syevd(double* C, int64_t ldc, int64_t n, double* lam, double* Q, int64_t ldq,
            const EigWork& w, const Sb2stPlan& plan, int64_t* d_status, hipStream_t s);
+// Eigenvalues and Q^T Y for a few columns Y (n x ny, ny <= sb2st_max_cols()),
+// without forming Q: Y <- Q2^T Q1^T Y on the way through the band reduction
+// and the bulge chase, then ZY = Z^T Y with Z the tridiagonal eigenvectors
+// (computed in Zw, n x n, ld n, which is left holding Z).
+void syevd_project(double* C, int64_t ldc, int64_t n, double* lam, double* Zw, double* Y,
+                   int64_t ldy, int ny, double* ZY, int64_t ldzy, const EigWork& w,
+                   const Sb2stPlan& plan, int64_t* d_status, hipStream_t s);
 
 }  // namespace mm

@@ -67,6 +67,68 @@ void apply_q1(const double* A, int64_t lda, int64_t n, int nb, const double* T_a
   }
 }
 
+void apply_q1t(const double* A, int64_t lda, int64_t n, int nb, const double* T_all, double* Y,
+               int64_t ldy, int64_t ncols, double* ws, int64_t ws_elems, hipStream_t s) {
+  MM_REQUIRE(ws_elems >= apply_q1_ws_elems(n, nb, ncols), kInvalid,
+             "apply_q1t: workspace too small");
+  const int64_t np = sy2sb_npanels(n, nb);
+  double* V = ws;                       // m x nb
+  double* W = V + n * nb;               // nb x ncols
+  double* W2 = W + nb * ncols;          // nb x ncols
+  double* split = W2 + nb * ncols;
+  const int64_t split_elems = 8 * nb * ncols;
+  for (int64_t p = 0; p < np; ++p) {
+    const int64_t j = p * nb, r0 = j + nb, m = n - r0;
+    const double* P = A + r0 + j * lda;
+    hipLaunchKernelGGL(extract_v_k, dim3((unsigned)ceil_div(m * nb, 256)), dim3(256), 0, s, P,
+                       lda, m, nb, V);
+    MM_HIP_TRY(hipGetLastError());
+    const double* T = T_all + p * (int64_t)nb * nb;
+    // W = V^T Y(r0:, :)
+    Gemm g1;
+    g1.m = nb; g1.n = ncols; g1.k = m;
+    g1.A = V; g1.lda = m; g1.ta = true;
+    g1.B = Y + r0; g1.ldb = ldy;
+    g1.C = W; g1.ldc = nb;
+    gemm(g1, s, split, split_elems);
+    // W2 = T^T W   (T^T lower: op(A)(i,k) = 0 for k > i)
+    Gemm g2;
+    g2.m = nb; g2.n = ncols; g2.k = nb;
+    g2.A = T; g2.lda = nb; g2.ta = true; g2.a_lower = true;
+    g2.B = W; g2.ldb = nb;
+    g2.C = W2; g2.ldc = nb;
+    gemm(g2, s);
+    // Y(r0:, :) -= V W2
+    Gemm g3;
+    g3.m = m; g3.n = ncols; g3.k = nb;
+    g3.alpha = -1.0; g3.beta = 1.0;
+    g3.A = V; g3.lda = m;
+    g3.B = W2; g3.ldb = nb;
+    g3.C = Y + r0; g3.ldc = ldy;
+    gemm(g3, s);
+  }
+}
+
+void syevd_project(double* C, int64_t ldc, int64_t n, double* lam, double* Zw, double* Y,
+                   int64_t ldy, int ny, double* ZY, int64_t ldzy, const EigWork& w,
+                   const Sb2stPlan& plan, int64_t* d_status, hipStream_t s) {
+  MM_REQUIRE(ny >= 1 && ny <= sb2st_max_cols(), kInvalid,
+             "syevd_project: 1..32 projected columns");
+  const int nb = w.nb;
+  sy2sb(C, ldc, n, nb, w.tau1, w.T1, w.ws, w.ws_elems, s);
+  apply_q1t(C, ldc, n, nb, w.T1, Y, ldy, ny, w.ws, w.ws_elems, s);
+  const int64_t ldab = 2 * nb + 1;
+  extract_band(C, ldc, n, nb, w.AB, ldab, s);
+  sb2st(w.AB, ldab, plan, w.d_offset, w.V2, w.tau2, w.d, w.e, s, Y, ldy, ny);
+  stedc(w.d, w.e, n, lam, Zw, n, w.ws, w.ws_elems, d_status, s);
+  Gemm g;  // ZY = Z^T Y
+  g.m = n; g.n = ny; g.k = n;
+  g.A = Zw; g.lda = n; g.ta = true;
+  g.B = Y; g.ldb = ldy;
+  g.C = ZY; g.ldc = ldzy;
+  gemm(g, s);
+}
+
 void syevd(double* C, int64_t ldc, int64_t n, double* lam, double* Q, int64_t ldq,
            const EigWork& w, const Sb2stPlan& plan, int64_t* d_status, hipStream_t s) {
   MM_REQUIRE(ldq == n, kInvalid, "syevd: ldq must equal n");

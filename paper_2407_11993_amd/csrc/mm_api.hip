@@ -81,6 +81,7 @@ struct mm_ctx {
   Dev iD_modal, iD_chol;  // injected currents at each method's current step
   // modal method
   bool decomposed = false;
+  bool has_Q = false;  // the eigenvector matrix is formed (mm_decompose, not _projected)
   Dev G, Q, lam, Wm, Pm, y;
   // Cholesky method
   bool factored = false;
@@ -378,20 +379,29 @@ mm_status mm_setup(const mm_problem* pb, void* stream, mm_ctx** out) {
   return MM_OK;
 }
 
-mm_status mm_decompose(mm_ctx* c) {
-  if (!c) return MM_E_INVALID;
-  return guarded(c, [&] {
+namespace {
+
+// a0-a8.  project: eigenvalues and the projected forcing and probe weights
+// only, the eigenvector matrix Q = Q1 Q2 Z never formed (Q^T Y = Z^T Q2^T Q1^T Y
+// applied to the few columns Y = G^{-1} [F, P] on the way through the band
+// reduction and the bulge chase).
+void decompose_impl(mm_ctx* c, bool project) {
     hipStream_t s = c->stream;
     const int64_t n0 = c->n0;
     const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(kBand, n0 - 1));
+    const int ny = c->nf + c->n_probe;
+    MM_REQUIRE(!project || ny <= sb2st_max_cols(), kInvalid,
+               "mm_decompose_projected: at most 32 forcing and probe columns in all "
+               "(use mm_decompose)");
     c->decomposed = false;
+    c->has_Q = false;
     c->G.alloc(sizeof(double) * n0 * n0);
     c->Q.alloc(sizeof(double) * n0 * n0);
     c->lam.alloc(sizeof(double) * n0);
     c->Wm.alloc(sizeof(double) * n0 * std::max(1, c->nf));
     c->Pm.alloc(sizeof(double) * n0 * c->n_probe);
     c->y.alloc(sizeof(double) * n0);
-    Dev Cb, ws, GF, GP;
+    Dev Cb, ws, GFP;
     Cb.alloc(sizeof(double) * n0 * n0);
     double* G = c->G.d();
     double* Q = c->Q.d();
@@ -441,15 +451,16 @@ mm_status mm_decompose(mm_ctx* c) {
       MM_HIP_TRY(hipStreamSynchronize(s));  // ABA is released here
     }
     symmetrize_from_lower(C, n0, n0, s);
-    // G^{-1} applied to the forcing columns and the probe weights
-    GF.alloc(sizeof(double) * n0 * std::max(1, c->nf));
-    GP.alloc(sizeof(double) * n0 * c->n_probe);
+    // G^{-1} applied to the forcing columns and the probe weights, side by side
+    GFP.alloc(sizeof(double) * n0 * ny);
+    double* GF = GFP.d();
+    double* GP = GFP.d() + (int64_t)c->nf * n0;
     if (c->nf > 0) {
       Gemm g;
       g.m = n0; g.n = c->nf; g.k = n0;
       g.A = G; g.lda = n0; g.a_lower = true;
       g.B = c->F.d(); g.ldb = n0;
-      g.C = GF.d(); g.ldc = n0;
+      g.C = GF; g.ldc = n0;
       gemm(g, s);
     }
     {
@@ -457,7 +468,7 @@ mm_status mm_decompose(mm_ctx* c) {
       g.m = n0; g.n = c->n_probe; g.k = n0;
       g.A = G; g.lda = n0; g.a_lower = true;
       g.B = c->Pt.d(); g.ldb = n0;
-      g.C = GP.d(); g.ldc = n0;
+      g.C = GP; g.ldc = n0;
       gemm(g, s);
     }
     // a4-a7: C = Q Lam Q^T
@@ -480,23 +491,33 @@ mm_status mm_decompose(mm_ctx* c) {
     w.d_offset = off.as<int64_t>(); w.d = dv.d(); w.e = ev.d();
     w.ws = ws.d(); w.ws_elems = wse;
     fill_i64(st + 1, 1, 0, s);
-    syevd(C, n0, n0, c->lam.d(), Q, n0, w, plan, st + 1, s);
-    // a8: modal weights  W = Q^T G^{-1} F,  Pt = Q^T G^{-1} P
-    if (c->nf > 0) {
-      Gemm g;
-      g.m = n0; g.n = c->nf; g.k = n0;
-      g.A = Q; g.lda = n0; g.ta = true;
-      g.B = GF.d(); g.ldb = n0;
-      g.C = c->Wm.d(); g.ldc = n0;
-      gemm(g, s);
-    }
-    {
-      Gemm g;
-      g.m = n0; g.n = c->n_probe; g.k = n0;
-      g.A = Q; g.lda = n0; g.ta = true;
-      g.B = GP.d(); g.ldb = n0;
-      g.C = c->Pm.d(); g.ldc = n0;
-      gemm(g, s);
+    if (project) {
+      // a4-a8 without Q: [W, Pt] = Z^T Q2^T Q1^T G^{-1} [F, P]  (Q holds Z meanwhile)
+      Dev ZY;
+      ZY.alloc(sizeof(double) * n0 * ny);
+      syevd_project(C, n0, n0, c->lam.d(), Q, GFP.d(), n0, ny, ZY.d(), n0, w, plan, st + 1, s);
+      if (c->nf > 0) copy_matrix(ZY.d(), n0, c->Wm.d(), n0, n0, c->nf, s);
+      copy_matrix(ZY.d() + (int64_t)c->nf * n0, n0, c->Pm.d(), n0, n0, c->n_probe, s);
+      MM_HIP_TRY(hipStreamSynchronize(s));  // ZY is released here
+    } else {
+      syevd(C, n0, n0, c->lam.d(), Q, n0, w, plan, st + 1, s);
+      // a8: modal weights  W = Q^T G^{-1} F,  Pt = Q^T G^{-1} P
+      if (c->nf > 0) {
+        Gemm g;
+        g.m = n0; g.n = c->nf; g.k = n0;
+        g.A = Q; g.lda = n0; g.ta = true;
+        g.B = GF; g.ldb = n0;
+        g.C = c->Wm.d(); g.ldc = n0;
+        gemm(g, s);
+      }
+      {
+        Gemm g;
+        g.m = n0; g.n = c->n_probe; g.k = n0;
+        g.A = Q; g.lda = n0; g.ta = true;
+        g.B = GP; g.ldb = n0;
+        g.C = c->Pm.d(); g.ldc = n0;
+        gemm(g, s);
+      }
     }
     fill(c->y.d(), n0, 0.0, s);
     int64_t est = 0;
@@ -504,8 +525,21 @@ mm_status mm_decompose(mm_ctx* c) {
     MM_HIP_TRY(hipStreamSynchronize(s));
     MM_HIP_TRY(hipGetLastError());
     if (est != 0) throw Error{kNoConverge, "a secular equation did not converge"};
+    if (project) c->Q.release();  // it held the tridiagonal eigenvectors only
     c->decomposed = true;
-  });
+    c->has_Q = !project;
+}
+
+}  // namespace
+
+mm_status mm_decompose(mm_ctx* c) {
+  if (!c) return MM_E_INVALID;
+  return guarded(c, [&] { decompose_impl(c, false); });
+}
+
+mm_status mm_decompose_projected(mm_ctx* c) {
+  if (!c) return MM_E_INVALID;
+  return guarded(c, [&] { decompose_impl(c, true); });
 }
 
 mm_status mm_step_modal(mm_ctx* c, double theta, double dt, int64_t n_steps,
@@ -634,6 +668,9 @@ mm_status mm_probe(mm_ctx* c, int32_t which, int32_t n_rows, const double* rows,
     double* Ifull = buf.d() + n0;   // full current (n)
     if (which == MM_MODAL) {
       MM_REQUIRE(c->decomposed, kState, "mm_probe(MM_MODAL) before mm_decompose");
+      MM_REQUIRE(c->has_Q, kState,
+                 "mm_probe(MM_MODAL) needs the eigenvectors: use mm_decompose, not "
+                 "mm_decompose_projected");
       double* t = buf.d() + n0 + n;
       // a11: Ii = G^{-T} (Q y)
       Gemm g1;
@@ -890,6 +927,9 @@ mm_status mm_adjoint_modal(mm_ctx* c, double theta, double dt, int64_t n_steps,
   if (!c) return MM_E_INVALID;
   return guarded(c, [&] {
     MM_REQUIRE(c->decomposed, kState, "mm_adjoint_modal before mm_decompose");
+    MM_REQUIRE(c->has_Q, kState,
+               "mm_adjoint_modal needs the eigenvectors: use mm_decompose, not "
+               "mm_decompose_projected");
     check_steps(theta, dt, n_steps);
     MM_REQUIRE(c->m == 0, kInvalid, "mm_adjoint_modal: problems without electrodes only");
     MM_REQUIRE(n_steps >= 1 && n_runs >= 1 && src && probe, kInvalid,

@@ -12,13 +12,18 @@
 // Tasks (s, k) with the same 3s + k touch disjoint windows of the band, and
 // every task a task depends on has a smaller 3s + k, so one launch per value
 // of 3s + k runs all of its tasks concurrently.
-// The back-transform by these reflectors is in q2.hip.
+// The back-transform by these reflectors is in q2.hip.  Optionally a few
+// columns Y (n x ny, ny <= 4 YQ) are taken along: every task applies its
+// reflector to the rows R_k of Y, so Y leaves as Q2^T Y (two reflectors
+// whose rows overlap are applied in the order they were generated, by the
+// same argument as for the band).
 #include "eig.h"
 
 namespace mm {
 namespace {
 
 constexpr int NT = 256;
+constexpr int YQ = 8;  // columns of Y per wave
 
 // Wave-wide sum, every lane gets the result: sums over quads and rows of 16
 // lanes by DPP moves (xor 1, xor 2, half-row mirror, row mirror), then the
@@ -63,7 +68,8 @@ struct Band {
 // the zero padding lets every loop run a fixed 16 iterations, unrolled.
 __global__ void __launch_bounds__(NT) sb2st_stage(Band B, int n, int nb, int stage, int s_lo,
                                                   const int64_t* off, double* V2,
-                                                  double* tau2) {
+                                                  double* tau2, double* Y, int64_t ldy,
+                                                  int ny) {
   const int s = s_lo + (int)blockIdx.x;
   if (s > n - 3) return;
   const int k = stage - 3 * s;
@@ -81,11 +87,17 @@ __global__ void __launch_bounds__(NT) sb2st_stage(Band B, int n, int nb, int sta
   __shared__ double Lb[64][65], Db[64][65], Bb[64][65];
   __shared__ double v[64], p4[4][64], w_s[64];
   __shared__ double s_tau, s_beta;
+  double yv[YQ];  // rows R_k of Y (lane = row), columns wave + 4 q
 
   // ---- stage: all loads are issued before the first LDS store (addresses
   // clamped into the block, values selected)
   {
     const int li = min(lane, len - 1), lb = min(lane, max(lenn, 1) - 1);
+#pragma unroll
+    for (int q = 0; q < YQ; ++q) {
+      const int c = wave + 4 * q;
+      yv[q] = (c < ny) ? Y[(r0 + li) + c * ldy] : 0.0;
+    }
     double rl[16], rd[16], rb[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
@@ -128,6 +140,10 @@ __global__ void __launch_bounds__(NT) sb2st_stage(Band B, int n, int nb, int sta
   const double tau = s_tau;
   if (tau == 0.0) return;  // H = I: nothing changes (uniform branch)
   const double vl = v[lane];
+  // ---- Y(R_k, c) -= tau v (v^T Y(R_k, c)); v is zero past len
+#pragma unroll
+  for (int q = 0; q < YQ; ++q)
+    if (wave + 4 * q < ny) yv[q] -= tau * vl * wsum(vl * yv[q]);
 
   // ---- left application: Lb(:, j) -= tau v (v^T Lb(:, j)), j >= 1; lane =
   //      column, each wave sums a quarter of the rows; the eliminated column
@@ -194,6 +210,11 @@ __global__ void __launch_bounds__(NT) sb2st_stage(Band B, int n, int nb, int sta
       if (lane < len && j <= lane) B.at(r0 + lane, r0 + j) = rd[q];
       if (lane < lenn && j < len) B.at(rn0 + lane, r0 + j) = rb[q];
     }
+#pragma unroll
+    for (int q = 0; q < YQ; ++q) {
+      const int c = wave + 4 * q;
+      if (c < ny && lane < len) Y[(r0 + lane) + c * ldy] = yv[q];
+    }
   }
 }
 
@@ -205,6 +226,8 @@ __global__ void band_to_tridiag(const double* AB, int64_t ld, int64_t n, double*
 }
 
 }  // namespace
+
+int sb2st_max_cols() { return 4 * YQ; }
 
 Sb2stPlan sb2st_plan(int64_t n, int nb) {
   Sb2stPlan p;
@@ -222,10 +245,13 @@ Sb2stPlan sb2st_plan(int64_t n, int nb) {
 }
 
 void sb2st(double* AB, int64_t ldab, const Sb2stPlan& plan, const int64_t* d_offset,
-           double* V2, double* tau2, double* d, double* e, hipStream_t s) {
+           double* V2, double* tau2, double* d, double* e, hipStream_t s, double* Y,
+           int64_t ldy, int ny) {
   const int64_t n = plan.n;
   const int nb = plan.nb;
   MM_REQUIRE(nb >= 1 && nb <= 64 && ldab >= 2 * nb + 1, kInvalid, "sb2st: band must be 1..64");
+  MM_REQUIRE(ny >= 0 && ny <= sb2st_max_cols() && (ny == 0 || (Y && ldy >= n)), kInvalid,
+             "sb2st: at most 32 columns carried along");
   MM_REQUIRE(n < (int64_t)1 << 29, kInvalid, "sb2st: order too large");
   if (n >= 3) {
     const int64_t K0 = ceil_div(n - 1, nb);
@@ -237,7 +263,7 @@ void sb2st(double* AB, int64_t ldab, const Sb2stPlan& plan, const int64_t* d_off
       int64_t s_hi = std::min(st / 3, n - 3);
       if (s_hi < s_lo) continue;
       hipLaunchKernelGGL(sb2st_stage, dim3((unsigned)(s_hi - s_lo + 1)), dim3(NT), 0, s, B,
-                         (int)n, nb, (int)st, (int)s_lo, d_offset, V2, tau2);
+                         (int)n, nb, (int)st, (int)s_lo, d_offset, V2, tau2, Y, ldy, ny);
     }
     MM_HIP_TRY(hipGetLastError());
   }

@@ -90,8 +90,11 @@ class Solver:
             pass
 
     # -- the method -----------------------------------------------------------
-    def decompose(self):
-        _lib.check(self.lib.mm_decompose(self.ctx), self.ctx)
+    def decompose(self, projected=False):
+        """mm_decompose, or with projected=True mm_decompose_projected (the
+        eigenvalues and projected weights only, no eigenvector matrix)."""
+        fn = self.lib.mm_decompose_projected if projected else self.lib.mm_decompose
+        _lib.check(fn(self.ctx), self.ctx)
 
     def _waves(self, n_steps, i_src, i_D):
         s = None if self.n_src == 0 else _dev(np.asarray(i_src).reshape(n_steps + 1, self.n_src)

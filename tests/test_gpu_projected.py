@@ -1,0 +1,110 @@
+"""The projected decomposition (eigenvalues and Q^T G^{-1} [F, P] without the
+eigenvector matrix) through the C ABI: against the CPU oracle (signals 1e-9
+of max|s|), against the full decomposition (eigenvalues bit for bit, since
+the same band reduction, bulge chase and divide and conquer run; projected
+weights and signals to 1e-12), on the electrode reduction, for batched runs,
+and its error paths."""
+import numpy as np
+import pytest
+
+from paper_2407_11993_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+def _pair(w):
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2407_11993_amd import Solver
+    full, proj = Solver(w), Solver(w)
+    full.decompose()
+    proj.decompose(projected=True)
+    return full, proj
+
+
+@pytest.mark.parametrize("case", ["block8", "plate-crack", "plate-576"])
+def test_projected_matches_oracle_and_full(orc, case):
+    if case == "block8":
+        w = inputs.config1()
+        w.T = 600
+        w.i_src = w.i_src[:w.T + 1]
+    elif case == "plate-crack":
+        w = inputs.plate(23, 19, seed=23, crack=((5, 12), (8, 10), 1e3), T=300, wave="gauss")
+    else:
+        w = inputs.plate(24, 24, seed=3, crack=None, T=250, wave="gauss")
+    full, proj = _pair(w)
+    assert np.array_equal(_np(full.eigenvalues()), _np(proj.eigenvalues()))
+    L = orc.assemble_L(w.xyz, w.h)
+    pb = orc.Problem(L, w.R.to_dense(), w.M, w.P)
+    for theta in (0.5, 1.0):
+        full.reset()
+        proj.reset()
+        ref = orc.theta_direct(pb, theta, 1.0, w.T, w.i_src)
+        sf = _np(full.step_modal(theta, 1.0, w.T, w.i_src))
+        sp = _np(proj.step_modal(theta, 1.0, w.T, w.i_src))
+        assert _rel(sp, ref) < 1e-9
+        assert _rel(sp, sf) < 1e-12
+
+
+def test_projected_electrodes_match_oracle(orc):
+    w = inputs.electrode_plate(12, 9, 3, T=250, tau_D=40.0, coil_period=70.0, seed=3)
+    full, proj = _pair(w)
+    assert np.array_equal(_np(full.eigenvalues()), _np(proj.eigenvalues()))
+    L = orc.assemble_L(w.xyz, w.h)
+    pb = orc.Problem(L, w.R.to_dense(), w.M, w.P, E=w.E.to_dense())
+    ref = orc.theta_direct(pb, 0.5, w.dt, w.T, w.i_src, w.i_D)
+    sp = _np(proj.step_modal(0.5, w.dt, w.T, w.i_src, w.i_D))
+    sf = _np(full.step_modal(0.5, w.dt, w.T, w.i_src, w.i_D))
+    assert _rel(sp, ref) < 1e-9
+    assert _rel(sp, sf) < 1e-12
+
+
+def test_projected_batched_runs_match_full():
+    base = inputs.plate(14, 11, seed=11, crack=((3, 7), (4, 6), 1e3), T=1)
+    rng = np.random.default_rng(11)
+    coils = [(rng.uniform(0, 13), rng.uniform(0, 10), 2.0) for _ in range(6)]
+    M = np.stack([inputs.coil_coupling(base.xyz, p) for p in coils], axis=1)
+    base.M = M
+    base.P = M.T.copy()
+    full, proj = _pair(base)
+    lens = [120, 7, 64, 0, 90]
+    waves = np.concatenate([np.sin(2 * np.pi * np.arange(T + 1) / 37.0) for T in lens])
+    out = []
+    for s in (full, proj):
+        b = s.batch(0.5, 1.0, lens, [0, 1, 2, 3, 5], [0, 1, 2, 3, 4], waves)
+        out.append(_np(b.run()).copy())
+        b.close()
+    assert _rel(out[1], out[0]) < 1e-12
+
+
+def test_projected_error_paths():
+    from paper_2407_11993_amd import Solver, _lib
+    w = inputs.config1()
+    s = Solver(w)
+    s.decompose(projected=True)
+    with pytest.raises(_lib.MMError) as e:
+        s.current(_lib.MM_MODAL)
+    assert e.value.code == 5 and "mm_decompose" in str(e.value)
+    T = 10
+    with pytest.raises(_lib.MMError) as e:
+        s.adjoint(0.5, 1.0, T, [0], [0], np.zeros(T + 1), np.zeros(T))
+    assert e.value.code == 5
+    # more than 32 forcing and probe columns in all
+    base = inputs.plate(9, 8, seed=2, T=1)
+    pts = [(x + 0.5, y + 0.5, 2.0) for x in range(6) for y in range(6)]
+    M = np.stack([inputs.coil_coupling(base.xyz, p) for p in pts[:3]], axis=1)
+    base.M = M
+    base.P = np.stack([inputs.coil_coupling(base.xyz, p) for p in pts[:30]], axis=0)
+    big = Solver(base)
+    with pytest.raises(_lib.MMError) as e:
+        big.decompose(projected=True)
+    assert e.value.code == 1
+    big.decompose()  # the full decomposition has no such limit
