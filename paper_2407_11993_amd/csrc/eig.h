@@ -55,6 +55,12 @@ int64_t stedc_ws_elems(int64_t n);
 // non-zero code if a secular equation did not converge.
 void stedc(const double* d, const double* e, int64_t n, double* lam, double* Z,
            int64_t ldz, double* ws, int64_t ws_elems, int64_t* d_status, hipStream_t s);
+// Eigenvalues and ZY = Z^T Y (n x ny) without forming Z: every node of the
+// tree keeps its eigenvectors' projections and boundary entries only.
+int64_t stedc_project_ws_elems(int64_t n, int ny);
+void stedc_project(const double* d, const double* e, int64_t n, double* lam, const double* Y,
+                   int64_t ldy, int ny, double* ZY, int64_t ldzy, double* ws, int64_t ws_elems,
+                   int64_t* d_status, hipStream_t s);
 
 // ---- driver -----------------------------------------------------------------
 struct EigWork {
@@ -75,10 +81,10 @@ void syevd(double* C, int64_t ldc, int64_t n, double* lam, double* Q, int64_t ld
            const EigWork& w, const Sb2stPlan& plan, int64_t* d_status, hipStream_t s);
 // Eigenvalues and Q^T Y for a few columns Y (n x ny, ny <= sb2st_max_cols()),
 // without forming Q: Y <- Q2^T Q1^T Y on the way through the band reduction
-// and the bulge chase, then ZY = Z^T Y with Z the tridiagonal eigenvectors
-// (computed in Zw, n x n, ld n, which is left holding Z).
-void syevd_project(double* C, int64_t ldc, int64_t n, double* lam, double* Zw, double* Y,
-                   int64_t ldy, int ny, double* ZY, int64_t ldzy, const EigWork& w,
-                   const Sb2stPlan& plan, int64_t* d_status, hipStream_t s);
+// and the bulge chase, then ZY = Z^T Y from the projected divide and conquer
+// (w.ws must hold stedc_project_ws_elems and sy2sb's and apply_q1t's needs).
+void syevd_project(double* C, int64_t ldc, int64_t n, double* lam, double* Y, int64_t ldy,
+                   int ny, double* ZY, int64_t ldzy, const EigWork& w, const Sb2stPlan& plan,
+                   int64_t* d_status, hipStream_t s);
 
 }  // namespace mm

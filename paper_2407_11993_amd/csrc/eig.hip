@@ -109,9 +109,9 @@ void apply_q1t(const double* A, int64_t lda, int64_t n, int nb, const double* T_
   }
 }
 
-void syevd_project(double* C, int64_t ldc, int64_t n, double* lam, double* Zw, double* Y,
-                   int64_t ldy, int ny, double* ZY, int64_t ldzy, const EigWork& w,
-                   const Sb2stPlan& plan, int64_t* d_status, hipStream_t s) {
+void syevd_project(double* C, int64_t ldc, int64_t n, double* lam, double* Y, int64_t ldy,
+                   int ny, double* ZY, int64_t ldzy, const EigWork& w, const Sb2stPlan& plan,
+                   int64_t* d_status, hipStream_t s) {
   MM_REQUIRE(ny >= 1 && ny <= sb2st_max_cols(), kInvalid,
              "syevd_project: 1..32 projected columns");
   const int nb = w.nb;
@@ -120,13 +120,7 @@ void syevd_project(double* C, int64_t ldc, int64_t n, double* lam, double* Zw, d
   const int64_t ldab = 2 * nb + 1;
   extract_band(C, ldc, n, nb, w.AB, ldab, s);
   sb2st(w.AB, ldab, plan, w.d_offset, w.V2, w.tau2, w.d, w.e, s, Y, ldy, ny);
-  stedc(w.d, w.e, n, lam, Zw, n, w.ws, w.ws_elems, d_status, s);
-  Gemm g;  // ZY = Z^T Y
-  g.m = n; g.n = ny; g.k = n;
-  g.A = Zw; g.lda = n; g.ta = true;
-  g.B = Y; g.ldb = ldy;
-  g.C = ZY; g.ldc = ldzy;
-  gemm(g, s);
+  stedc_project(w.d, w.e, n, lam, Y, ldy, ny, ZY, ldzy, w.ws, w.ws_elems, d_status, s);
 }
 
 void syevd(double* C, int64_t ldc, int64_t n, double* lam, double* Q, int64_t ldq,

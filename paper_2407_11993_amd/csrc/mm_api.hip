@@ -52,9 +52,17 @@ constexpr int kBand = 64;         // bandwidth of the first tridiagonalisation s
 constexpr int kMaxColumns = 4096;  // sources, probes
 constexpr int kMaxRunColumns = 8;  // forcing columns and probes of one stepping call
 
-int64_t eig_ws_elems(int64_t n, int nb) {
-  int64_t w = std::max(sy2sb_ws_elems(n, nb), stedc_ws_elems(n));
-  w = std::max(w, apply_q1_ws_elems(n, nb, n));
+// workspace of the decomposition; the projected one never needs the full
+// divide-and-conquer buffers (4 n^2) or Q1 applied to n columns
+int64_t eig_ws_elems(int64_t n, int nb, bool project = false) {
+  int64_t w = sy2sb_ws_elems(n, nb);
+  if (project) {
+    w = std::max(w, stedc_project_ws_elems(n, sb2st_max_cols()));
+    w = std::max(w, apply_q1_ws_elems(n, nb, sb2st_max_cols()));
+  } else {
+    w = std::max(w, stedc_ws_elems(n));
+    w = std::max(w, apply_q1_ws_elems(n, nb, n));
+  }
   w = std::max(w, potrf_ws_elems(n));
   w = std::max(w, trtri_ws_elems(n));
   return w;
@@ -412,7 +420,7 @@ void decompose_impl(mm_ctx* c, bool project) {
     assemble_L(c->xyz.d() + 3 * m, c->h, n0, G, n0, false, s, c->lr(0.0));
     factor_checked(G, n0, st, ws, s, "L");
     // a3: C = G^{-1} R G^{-T}:  G <- G^{-1};  W = G^{-1} R (in Q);  C = G^{-1} W^T
-    const int64_t wse = eig_ws_elems(n0, nb);
+    const int64_t wse = eig_ws_elems(n0, nb, project);
     ws.alloc(sizeof(double) * wse);
     trtri_lower(G, n0, n0, ws.d(), wse, s);
     dense_times_csr(G, n0, c->R(), Q, n0, s);
@@ -495,7 +503,7 @@ void decompose_impl(mm_ctx* c, bool project) {
       // a4-a8 without Q: [W, Pt] = Z^T Q2^T Q1^T G^{-1} [F, P]  (Q holds Z meanwhile)
       Dev ZY;
       ZY.alloc(sizeof(double) * n0 * ny);
-      syevd_project(C, n0, n0, c->lam.d(), Q, GFP.d(), n0, ny, ZY.d(), n0, w, plan, st + 1, s);
+      syevd_project(C, n0, n0, c->lam.d(), GFP.d(), n0, ny, ZY.d(), n0, w, plan, st + 1, s);
       if (c->nf > 0) copy_matrix(ZY.d(), n0, c->Wm.d(), n0, n0, c->nf, s);
       copy_matrix(ZY.d() + (int64_t)c->nf * n0, n0, c->Pm.d(), n0, n0, c->n_probe, s);
       MM_HIP_TRY(hipStreamSynchronize(s));  // ZY is released here

@@ -16,6 +16,13 @@
 //   roots are exact for a nearby z, which keeps the vectors orthogonal);
 //   U(i,j) = zhat_i / (d_i - lam_j) normalised;  Z_new = Z_kept U (matrix
 //   cores);  and the merged spectrum is sorted into place.
+//
+// Projected mode (stedc_project): only Z^T Y for a few columns Y is wanted.
+// Every node keeps, row q for its q-th eigenvector, the projections
+// Z_node^T Y_node and two boundary columns Z_node^T e_first, Z_node^T e_last
+// (its eigenvectors' first and last entries, which the parent's z needs).
+// A merge applies its rotations to rows, U^T to the kept rows, copies the
+// deflated ones and sorts rows into place; nothing of size n^2 but U is kept.
 #include "eig.h"
 
 #include <vector>
@@ -53,7 +60,9 @@ __global__ void tear_k(const double* d, const double* e, int64_t n, const int64_
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(64) leaf_jacobi(const double* dw, const double* e,
                                                   const int64_t* leaf_lo, const int64_t* leaf_hi,
-                                                  double* lam, double* Z, int64_t ldz) {
+                                                  double* lam, double* Z, int64_t ldz,
+                                                  const double* Y, int64_t ldy, int ny,
+                                                  double* PY, int64_t ldpy) {
   __shared__ double A[LEAF][LEAF + 1];
   __shared__ double V[LEAF][LEAF + 1];
   __shared__ double cs[2];
@@ -130,6 +139,20 @@ __global__ void __launch_bounds__(64) leaf_jacobi(const double* dw, const double
   }
   __syncthreads();
   if (t < m) lam[lo + rank[t]] = A[t][t];
+  if (PY) {
+    // projected mode: row rank[j] gets V(:, j)^T [Y, e_first, e_last]
+    for (int q = t; q < m * (ny + 2); q += 64) {
+      const int j = q % m, c = q / m;
+      double acc = 0.0;
+      if (c < ny) {
+        for (int i = 0; i < m; ++i) acc += V[i][j] * Y[(lo + i) + (int64_t)c * ldy];
+      } else {
+        acc = V[c == ny ? 0 : m - 1][j];
+      }
+      PY[(lo + rank[j]) + (int64_t)c * ldpy] = acc;
+    }
+    return;
+  }
   for (int q = t; q < m * m; q += 64) {
     const int i = q % m, j = q / m;
     Z[(lo + i) + (lo + rank[j]) * ldz] = V[i][j];
@@ -158,7 +181,8 @@ struct MergeBufs {
 
 __global__ void __launch_bounds__(NT) merge_prepare(const Merge* merges, const double* e,
                                                     const double* lam, const double* Z,
-                                                    int64_t ldz, MergeBufs b) {
+                                                    int64_t ldz, MergeBufs b, double* PY,
+                                                    int64_t ldpy, int ny) {
   const Merge mg = merges[blockIdx.x];
   const int64_t lo = mg.lo, mid = mg.mid, hi = mg.hi;
   const int64_t n1 = mid - lo, n2 = hi - mid, nm = hi - lo;
@@ -174,7 +198,8 @@ __global__ void __launch_bounds__(NT) merge_prepare(const Merge* merges, const d
     if (i < n1) {
       col = lo + i;
       v = lam[col];
-      zz = Z[(mid - 1) + col * ldz] * r2;
+      // child 1's eigenvector `col` at its last row
+      zz = (PY ? PY[col + (int64_t)(ny + 1) * ldpy] : Z[(mid - 1) + col * ldz]) * r2;
       // count entries of half 2 strictly below v
       int64_t a = 0, c = n2;
       while (a < c) { const int64_t h = (a + c) / 2; if (lam[mid + h] < v) a = h + 1; else c = h; }
@@ -183,7 +208,8 @@ __global__ void __launch_bounds__(NT) merge_prepare(const Merge* merges, const d
       const int64_t j = i - n1;
       col = mid + j;
       v = lam[col];
-      zz = sgn * Z[mid + col * ldz] * r2;
+      // child 2's eigenvector `col` at its first row
+      zz = sgn * (PY ? PY[col + (int64_t)ny * ldpy] : Z[mid + col * ldz]) * r2;
       // count entries of half 1 below or equal to v
       int64_t a = 0, c = n1;
       while (a < c) { const int64_t h = (a + c) / 2; if (lam[lo + h] <= v) a = h + 1; else c = h; }
@@ -195,6 +221,13 @@ __global__ void __launch_bounds__(NT) merge_prepare(const Merge* merges, const d
   }
   __syncthreads();
   __threadfence_block();
+  if (PY) {
+    // the parent's boundary rows: its first row is child 1's first row (zero
+    // on child 2's eigenvectors), its last row child 2's last row (zero on
+    // child 1's); z above has read the entries cleared here
+    for (int64_t i = t; i < nm; i += NT)
+      PY[(lo + i) + (int64_t)(i < n1 ? ny + 1 : ny) * ldpy] = 0.0;
+  }
   if (t != 0) return;
   // ---- deflation scan --------------------------------------------------------
   double dmax = 0.0, zmax = 0.0;
@@ -494,6 +527,79 @@ __global__ void merge_place(const Merge* merges, MergeBufs b, const double* Zold
   }
 }
 
+// ---- projected mode: the merge steps on the rows of PY (n x W, W = ny + 2).
+// Rotations of eigenvector columns ca, cb act on rows ca, cb.
+__global__ void merge_rotate_rows(const Merge* merges, MergeBufs b, double* PY, int64_t ldpy,
+                                  int W) {
+  const int64_t nrot = b.meta[2 * blockIdx.y + 1];
+  const int c = (int)((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+  if (nrot == 0 || c >= W) return;
+  const Merge mg = merges[blockIdx.y];
+  for (int64_t q = 0; q < nrot; ++q) {
+    const int64_t ca = b.rot_a[mg.lo + q], cb = b.rot_b[mg.lo + q];
+    const double cc = b.rot_c[mg.lo + q], ss = b.rot_s[mg.lo + q];
+    const double za = PY[ca + c * ldpy], zb = PY[cb + c * ldpy];
+    PY[ca + c * ldpy] = cc * za - ss * zb;
+    PY[cb + c * ldpy] = ss * za + cc * zb;
+  }
+}
+
+// kept rows into G (k x W, ld k) at G + lo W
+__global__ void merge_gather_rows(const Merge* merges, MergeBufs b, const double* PY, int64_t ldpy,
+                                  int W, double* Gbuf) {
+  const Merge mg = merges[blockIdx.y];
+  const int64_t lo = mg.lo;
+  const int64_t k = b.meta[2 * blockIdx.y];
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= k * W) return;
+  const int64_t j = e % k, c = e / k;
+  Gbuf[lo * W + e] = PY[b.cols[lo + b.kept[lo + j]] + c * ldpy];
+}
+
+// grouped GEMM descriptors: Pt = U^T G (k x W, ld k) at Pt + lo W
+__global__ void merge_gemm_desc_rows(const Merge* merges, const MergeBufs b, double* Gbuf,
+                                     double* U, double* Ptb, int64_t n, int W, GemmGroup* desc,
+                                     int64_t nmerge) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nmerge) return;
+  const int64_t lo = merges[g].lo;
+  const int64_t k = b.meta[2 * g];
+  GemmGroup d;
+  d.A = U + lo * n; d.lda = k > 0 ? k : 1;
+  d.B = Gbuf + lo * W; d.ldb = k > 0 ? k : 1;
+  d.C = Ptb + lo * W; d.ldc = k > 0 ? k : 1;
+  d.m = k; d.n = W; d.k = k;
+  desc[g] = d;
+}
+
+// sort rows into place: destination rank as in merge_place
+__global__ void merge_place_rows(const Merge* merges, MergeBufs b, const double* PYold,
+                                 const double* Ptb, double* PYnew, int64_t ldpy, int W,
+                                 double* lam) {
+  const Merge mg = merges[blockIdx.y];
+  const int64_t lo = mg.lo, nm = mg.hi - mg.lo;
+  const int64_t q = blockIdx.x;
+  if (q >= nm) return;
+  const int64_t k = b.meta[2 * blockIdx.y];
+  const double v = b.vals[lo + q];
+  const int64_t sq = b.src[lo + q];
+  __shared__ int64_t s_rank;
+  if (threadIdx.x == 0) s_rank = 0;
+  __syncthreads();
+  int64_t r = 0;
+  for (int64_t p = threadIdx.x; p < nm; p += blockDim.x) {
+    const double w = b.vals[lo + p];
+    if (w < v || (w == v && p < q)) ++r;
+  }
+  atomicAdd((unsigned long long*)&s_rank, (unsigned long long)r);
+  __syncthreads();
+  const int64_t dst = lo + s_rank;
+  if (threadIdx.x == 0) lam[dst] = v;
+  for (int c = threadIdx.x; c < W; c += blockDim.x)
+    PYnew[dst + (int64_t)c * ldpy] =
+        sq >= 0 ? Ptb[lo * W + sq + (int64_t)c * k] : PYold[(-sq - 1) + (int64_t)c * ldpy];
+}
+
 __global__ void copy_vec(const double* s, double* d, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) d[i] = s[i];
@@ -545,6 +651,76 @@ int depth_for(int64_t n) {
   return D;
 }
 
+// projected mode: U (n^2), and n x W blocks for the rows (current, next),
+// the gathered kept rows and their product with U^T
+struct LayoutP {
+  double *dw, *lamA, *lamB, *U, *G, *Pt, *PYa, *PYb;
+  int64_t *cuts, *leaf_lo, *leaf_hi;
+  Merge* merges;
+  GemmGroup* desc;
+  MergeBufs mb;
+  double* end;
+};
+
+LayoutP carve_proj(double* ws, int64_t n, int64_t max_merges, int W) {
+  LayoutP L;
+  double* p = ws;
+  auto take = [&](int64_t count) { double* r = p; p += count; return r; };
+  L.dw = take(n);
+  L.lamA = take(n);
+  L.lamB = take(n);
+  L.U = take(n * n);
+  L.G = take(n * W);
+  L.Pt = take(n * W);
+  L.PYa = take(n * W);
+  L.PYb = take(n * W);
+  L.cuts = (int64_t*)take(n + 1);
+  L.leaf_lo = (int64_t*)take(n + 1);
+  L.leaf_hi = (int64_t*)take(n + 1);
+  L.merges = (Merge*)take(3 * (max_merges + 1));
+  L.desc = (GemmGroup*)take((int64_t)(sizeof(GemmGroup) / 8 + 1) * (max_merges + 1));
+  MergeBufs& b = L.mb;
+  b.ds = take(n); b.zs = take(n); b.cols = (int64_t*)take(n); b.kind = (int*)take(n);
+  b.kept = (int64_t*)take(n);
+  b.rot_a = (int64_t*)take(n); b.rot_b = (int64_t*)take(n); b.rot_c = take(n); b.rot_s = take(n);
+  b.meta = (int64_t*)take(2 * (max_merges + 1)); b.rho = take(max_merges + 1);
+  b.origin = (int64_t*)take(n); b.tau = take(n); b.lamk = take(n); b.zhat = take(n);
+  b.vals = take(n); b.src = (int64_t*)take(n);
+  b.dfl = (int64_t*)take(n); b.dk = take(n); b.zk = take(n);
+  L.end = p;
+  return L;
+}
+
+// The balanced tree over [0, n): levels[d] are the nodes at depth d (every
+// node above the leaves is cut at its midpoint), then the cut positions and
+// the leaves' ranges.
+struct Tree {
+  int D = 0;
+  std::vector<std::vector<Merge>> levels;
+  std::vector<int64_t> cuts, llo, lhi;
+};
+Tree build_tree(int64_t n) {
+  Tree tr;
+  tr.D = depth_for(n);
+  const int D = tr.D;
+  tr.levels.resize(D + 1);
+  tr.levels[0].push_back({0, 0, n});
+  for (int dd = 0; dd < D; ++dd) {
+    for (size_t q = 0; q < tr.levels[dd].size(); ++q) {
+      const int64_t lo = tr.levels[dd][q].lo, hi = tr.levels[dd][q].hi;
+      const int64_t mid = lo + (hi - lo) / 2;
+      tr.levels[dd][q].mid = mid;
+      tr.levels[dd + 1].push_back({lo, lo, mid});
+      tr.levels[dd + 1].push_back({mid, mid, hi});
+    }
+  }
+  for (int dd = 0; dd < D; ++dd)
+    for (const Merge& nd : tr.levels[dd]) tr.cuts.push_back(nd.mid);
+  for (const Merge& nd : tr.levels[D]) { tr.llo.push_back(nd.lo); tr.lhi.push_back(nd.hi); }
+  if (D == 0) { tr.llo.assign(1, 0); tr.lhi.assign(1, n); }
+  return tr;
+}
+
 }  // namespace
 
 int64_t stedc_ws_elems(int64_t n) {
@@ -590,7 +766,7 @@ void stedc(const double* d, const double* e, int64_t n, double* lam, double* Z, 
   fill(Z, n * n, 0.0, s);
   fill(L.Zb, n * n, 0.0, s);
   hipLaunchKernelGGL(leaf_jacobi, dim3((unsigned)llo.size()), dim3(64), 0, s, L.dw, e, L.leaf_lo,
-                     L.leaf_hi, L.lamA, Z, ldz);
+                     L.leaf_hi, L.lamA, Z, ldz, nullptr, 0, 0, nullptr, 0);
   MM_HIP_TRY(hipGetLastError());
   double* Zc = Z;      // current eigenvectors
   double* Zn = L.Zb;   // next
@@ -603,7 +779,7 @@ void stedc(const double* d, const double* e, int64_t n, double* lam, double* Z, 
     for (const Merge& mg : lv) maxm = std::max(maxm, mg.hi - mg.lo);
     MM_HIP_TRY(hipMemcpyAsync(L.merges, lv.data(), nmg * sizeof(Merge), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(merge_prepare, dim3((unsigned)nmg), dim3(NT), 0, s, L.merges, e, lc, Zc,
-                       ldz, L.mb);
+                       ldz, L.mb, nullptr, 0, 0);
     hipLaunchKernelGGL(merge_rotate, dim3((unsigned)ceil_div(maxm, 256), (unsigned)nmg), dim3(256),
                        0, s, L.merges, L.mb, Zc, ldz);
     hipLaunchKernelGGL(merge_compact, dim3((unsigned)ceil_div(maxm, 256), (unsigned)nmg), dim3(256),
@@ -630,6 +806,76 @@ void stedc(const double* d, const double* e, int64_t n, double* lam, double* Z, 
   }
   hipLaunchKernelGGL(copy_vec, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, lc, lam, n);
   if (Zc != Z) copy_matrix(Zc, n, Z, ldz, n, n, s);
+  MM_HIP_TRY(hipGetLastError());
+}
+
+int64_t stedc_project_ws_elems(int64_t n, int ny) {
+  const int64_t mm = (int64_t)1 << depth_for(n);
+  double* base = reinterpret_cast<double*>(64);
+  LayoutP L = carve_proj(base, n, mm, ny + 2);
+  return (int64_t)(L.end - base);
+}
+
+void stedc_project(const double* d, const double* e, int64_t n, double* lam, const double* Y,
+                   int64_t ldy, int ny, double* ZY, int64_t ldzy, double* ws, int64_t ws_elems,
+                   int64_t* d_status, hipStream_t s) {
+  MM_REQUIRE(ny >= 1, kInvalid, "stedc_project: at least one column");
+  MM_REQUIRE(ws_elems >= stedc_project_ws_elems(n, ny), kInvalid,
+             "stedc_project: workspace too small");
+  if (n <= 0) return;
+  const int W = ny + 2;
+  const Tree tr = build_tree(n);
+  const int D = tr.D;
+  const int64_t max_merges = (int64_t)1 << D;
+  LayoutP L = carve_proj(ws, n, max_merges, W);
+  const int64_t ncuts = (int64_t)tr.cuts.size();
+  if (ncuts)
+    MM_HIP_TRY(hipMemcpyAsync(L.cuts, tr.cuts.data(), ncuts * 8, hipMemcpyHostToDevice, s));
+  MM_HIP_TRY(hipMemcpyAsync(L.leaf_lo, tr.llo.data(), tr.llo.size() * 8, hipMemcpyHostToDevice, s));
+  MM_HIP_TRY(hipMemcpyAsync(L.leaf_hi, tr.lhi.data(), tr.lhi.size() * 8, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(tear_k, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, d, e, n, L.cuts,
+                     ncuts, L.dw);
+  hipLaunchKernelGGL(leaf_jacobi, dim3((unsigned)tr.llo.size()), dim3(64), 0, s, L.dw, e,
+                     L.leaf_lo, L.leaf_hi, L.lamA, nullptr, 0, Y, ldy, ny, L.PYa, n);
+  MM_HIP_TRY(hipGetLastError());
+  double* PYc = L.PYa;
+  double* PYn = L.PYb;
+  double* lc = L.lamA;
+  double* ln = L.lamB;
+  for (int dd = D - 1; dd >= 0; --dd) {
+    const std::vector<Merge>& lv = tr.levels[dd];
+    const int64_t nmg = (int64_t)lv.size();
+    int64_t maxm = 0;
+    for (const Merge& mg : lv) maxm = std::max(maxm, mg.hi - mg.lo);
+    MM_HIP_TRY(hipMemcpyAsync(L.merges, lv.data(), nmg * sizeof(Merge), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(merge_prepare, dim3((unsigned)nmg), dim3(NT), 0, s, L.merges, e, lc,
+                       nullptr, 0, L.mb, PYc, n, ny);
+    hipLaunchKernelGGL(merge_rotate_rows, dim3((unsigned)ceil_div(W, 64), (unsigned)nmg), dim3(64),
+                       0, s, L.merges, L.mb, PYc, n, W);
+    hipLaunchKernelGGL(merge_compact, dim3((unsigned)ceil_div(maxm, 256), (unsigned)nmg), dim3(256),
+                       0, s, L.merges, L.mb);
+    hipLaunchKernelGGL(merge_secular, dim3((unsigned)ceil_div(maxm, 64), (unsigned)nmg), dim3(64),
+                       0, s, L.merges, L.mb, d_status);
+    hipLaunchKernelGGL(merge_lowner, dim3((unsigned)ceil_div(maxm, 64), (unsigned)nmg), dim3(64),
+                       0, s, L.merges, L.mb);
+    hipLaunchKernelGGL(merge_form_u, dim3((unsigned)maxm, (unsigned)nmg), dim3(NT), 0, s, L.merges,
+                       L.mb, L.U, n);
+    hipLaunchKernelGGL(merge_gather_rows, dim3((unsigned)ceil_div(maxm * W, 256), (unsigned)nmg),
+                       dim3(256), 0, s, L.merges, L.mb, PYc, n, W, L.G);
+    hipLaunchKernelGGL(merge_gemm_desc_rows, dim3((unsigned)ceil_div(nmg, 64)), dim3(64), 0, s,
+                       L.merges, L.mb, L.G, L.U, L.Pt, n, W, L.desc, nmg);
+    MM_HIP_TRY(hipGetLastError());
+    gemm_grouped(L.desc, nmg, maxm, W, true, false, 1.0, 0.0, s);
+    hipLaunchKernelGGL(merge_collect, dim3((unsigned)ceil_div(maxm, 256), (unsigned)nmg),
+                       dim3(256), 0, s, L.merges, L.mb);
+    hipLaunchKernelGGL(merge_place_rows, dim3((unsigned)maxm, (unsigned)nmg), dim3(64), 0, s,
+                       L.merges, L.mb, PYc, L.Pt, PYn, n, W, ln);
+    MM_HIP_TRY(hipGetLastError());
+    std::swap(PYc, PYn);
+    std::swap(lc, ln);
+  }
+  hipLaunchKernelGGL(copy_vec, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, lc, lam, n);
+  copy_matrix(PYc, n, ZY, ldzy, n, ny, s);
   MM_HIP_TRY(hipGetLastError());
 }
 

@@ -1,9 +1,10 @@
 """The projected decomposition (eigenvalues and Q^T G^{-1} [F, P] without the
 eigenvector matrix) through the C ABI: against the CPU oracle (signals 1e-9
-of max|s|), against the full decomposition (eigenvalues bit for bit, since
-the same band reduction, bulge chase and divide and conquer run; projected
-weights and signals to 1e-12), on the electrode reduction, for batched runs,
-and its error paths."""
+of max|s|), against the full decomposition (eigenvalues to 1e-13 of the
+largest: the same band reduction and bulge chase run, and the divide and
+conquer takes each merge's z from projected boundary rows instead of the
+formed eigenvectors, so only rounding differs; signals to 1e-12), on the
+electrode reduction, for batched runs, and its error paths."""
 import numpy as np
 import pytest
 
@@ -41,7 +42,8 @@ def test_projected_matches_oracle_and_full(orc, case):
     else:
         w = inputs.plate(24, 24, seed=3, crack=None, T=250, wave="gauss")
     full, proj = _pair(w)
-    assert np.array_equal(_np(full.eigenvalues()), _np(proj.eigenvalues()))
+    lf, lp = _np(full.eigenvalues()), _np(proj.eigenvalues())
+    assert np.abs(lf - lp).max() <= 1e-13 * np.abs(lf).max()
     L = orc.assemble_L(w.xyz, w.h)
     pb = orc.Problem(L, w.R.to_dense(), w.M, w.P)
     for theta in (0.5, 1.0):
@@ -57,7 +59,8 @@ def test_projected_matches_oracle_and_full(orc, case):
 def test_projected_electrodes_match_oracle(orc):
     w = inputs.electrode_plate(12, 9, 3, T=250, tau_D=40.0, coil_period=70.0, seed=3)
     full, proj = _pair(w)
-    assert np.array_equal(_np(full.eigenvalues()), _np(proj.eigenvalues()))
+    lf, lp = _np(full.eigenvalues()), _np(proj.eigenvalues())
+    assert np.abs(lf - lp).max() <= 1e-13 * np.abs(lf).max()
     L = orc.assemble_L(w.xyz, w.h)
     pb = orc.Problem(L, w.R.to_dense(), w.M, w.P, E=w.E.to_dense())
     ref = orc.theta_direct(pb, 0.5, w.dt, w.T, w.i_src, w.i_D)
