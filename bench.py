@@ -42,6 +42,106 @@ def _workload(name: str, T: int | None):
 FLOPS_PER_MODE_STEP = 7.0
 
 
+def run_electrodes(args):
+    """The paper-scale plate with injected currents (256 x 384 cells,
+    N = 98,304, two electrodes, 1e5 steps, theta = 1/2) or a smaller plate of
+    the same kind: the modal method end to end (setup, projected
+    decomposition, all steps), and the Cholesky method's factorisation plus a
+    measured block of steps whose per-step time is extrapolated to all steps
+    (reported as such).  The signals of the two methods are compared over the
+    measured steps."""
+    import torch
+    from paper_2407_11993_amd import Solver
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    w = _electrode_workload(args.workload, args.T)
+    T = w.T
+    print(f"bench: inputs of {w.name} ready (N={w.n}, T={T})", file=sys.stderr, flush=True)
+    theta, dt = w.thetas[0], w.dt
+    K = min(args.chol_steps, T)
+    stream = torch.cuda.current_stream()
+    i_src = torch.as_tensor(w.i_src, dtype=torch.float64, device="cuda")
+    i_D = torch.as_tensor(w.i_D, dtype=torch.float64, device="cuda")
+
+    def one_step():
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(7)]
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        s = Solver(w)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        print("bench: setup done", file=sys.stderr, flush=True)
+        s.decompose(projected=True)
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+        print(f"bench: N={w.n}, projected decomposition "
+              f"{ev[1].elapsed_time(ev[2]) / 1e3:.2f} s", file=sys.stderr, flush=True)
+        sm = s.step_modal(theta, dt, T, i_src, i_D)
+        ev[3].record(stream)
+        torch.cuda.synchronize()
+        print(f"bench: {T} modal steps {ev[2].elapsed_time(ev[3]) / 1e3:.2f} s",
+              file=sys.stderr, flush=True)
+        s.reset()
+        ev[4].record(stream)
+        s.step_cholesky(theta, dt, 0, i_src[:1], i_D[:1])  # the factorisation
+        ev[5].record(stream)
+        sc = s.step_cholesky(theta, dt, K, i_src[:K + 1], i_D[:K + 1])
+        ev[6].record(stream)
+        torch.cuda.synchronize()
+        t = [ev[i].elapsed_time(ev[i + 1]) / 1e3 for i in range(6)]
+        print(f"bench: Cholesky factorisation {t[4]:.2f} s, {K} steps {t[5]:.2f} s",
+              file=sys.stderr, flush=True)
+        agree = float((sm[:K] - sc).abs().max() / sc.abs().max())
+        s.close()
+        return {"setup": t[0], "decompose": t[1], "modal_steps": t[2], "cholesky_factor": t[4],
+                "cholesky_steps_measured": t[5]}, agree
+
+    for _ in range(args.warmup):
+        one_step()
+    t0 = time.perf_counter()
+    runs = [one_step() for _ in range(args.steps)]
+    wall = time.perf_counter() - t0
+    avg = {k: sum(r[0][k] for r in runs) / len(runs) for k in runs[0][0]}
+    agree = max(r[1] for r in runs)
+    n0 = w.n - w.m
+    per_step = avg["cholesky_steps_measured"] / K
+    modal_s = avg["setup"] + avg["decompose"] + avg["modal_steps"]
+    chol_s = avg["setup"] + avg["cholesky_factor"] + per_step * T
+    trsv_bytes = 2 * 8.0 * n0 * (n0 + 1) / 2
+    achieved = trsv_bytes / per_step / 1e9
+    dec_flops = (1 / 3 + 1 / 3 + 1 / 3 + 4 / 3) * float(n0) ** 3  # potrf, trtri, C, band
+    return {
+        "metric": "end-to-end s, modal theta-method (Cholesky theta-method beside it)",
+        "value": round(modal_s, 3), "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * wall / args.steps, 1),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "N": w.n, "N0": n0, "T": T, "theta": theta, "dt": dt,
+                   "electrodes": w.m + 1, "probes": w.n_probe,
+                   "decomposition": "eigenvalues and projected weights Q^T G^-1 [F, P] "
+                                    "(the eigenvector matrix is not formed)"},
+        "cholesky_s_extrapolated": round(chol_s, 1),
+        "cholesky_steps_measured": K,
+        "speedup_modal_vs_cholesky": round(chol_s / modal_s, 2),
+        "signal_agreement_modal_vs_cholesky": agree,
+        "phases_s": {k: round(v, 3) for k, v in avg.items()},
+        "decomposition_tflops": round(dec_flops / avg["decompose"] / 1e12, 3),
+        "roofline": {"bound": "hbm", "kernel": "triangular solve pair (fwd+bwd per step)",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+    }
+
+
+def _electrode_workload(name, T):
+    from paper_2407_11993_amd import inputs
+    nx, ny = (int(v) for v in name.split("-")[1].split("x"))
+    T = T or 100000
+    if (nx, ny) == (256, 384):
+        return inputs.config3(T=T)
+    return inputs.electrode_plate(nx, ny, 16, T=T, name=f"plate-{nx}x{ny}-electrodes")
+
+
 def run_batched(args):
     """Config 4: 256 coil positions with their own waveform lengths, stepped
     in one graph-captured batched launch, against 256 sequential solves of
@@ -339,38 +439,45 @@ def run_gpu(args):
 
 
 def cpu_baseline(args):
-    """The oracle (plain C, one thread) on a bounded sample, scaled to the
-    workload: decomposition by (N/n)^3, stepping by (N/n)^2 (T/t)."""
-    import numpy as np
-
+    """The oracle (plain C, one thread) on a bounded sample of the same kind
+    of workload, scaled to it: decomposition by (N/n)^3, stepping by
+    (N/n)^2 (T/t)."""
     import oracle
     from paper_2407_11993_amd import inputs
     oracle.build(force=False)
-    full = _workload(args.workload, args.T)
-    side = 20
     t_sample = 4000
-    w = inputs.plate(side, side, seed=0, crack=((8, 12), (9, 10), 1e3), T=t_sample,
-                     wave="gauss", coil=((side - 1) / 2, (side - 1) / 2, 2.0))
+    if args.workload.endswith("-electrodes"):
+        full = _electrode_workload(args.workload, args.T)
+        w = inputs.electrode_plate(24, 36, 6, T=t_sample)
+        what = "a 24x36 plate with two 6-cell electrodes"
+    else:
+        full = _workload(args.workload, args.T)
+        side = 20
+        w = inputs.plate(side, side, seed=0, crack=((8, 12), (9, 10), 1e3), T=t_sample,
+                         wave="gauss", coil=((side - 1) / 2, (side - 1) / 2, 2.0))
+        what = f"a {side}x{side} plate with a crack"
     L = oracle.assemble_L(w.xyz, w.h)
-    pb = oracle.Problem(L, w.R.to_dense(), w.M, w.P)
+    pb = oracle.Problem(L, w.R.to_dense(), w.M, w.P,
+                        E=None if w.E is None else w.E.to_dense())
+    i_D = w.i_D if w.m else None
     t0 = time.perf_counter()
     oracle.modal_eigen(pb, want_V=True)
     t_dec = time.perf_counter() - t0
     t0 = time.perf_counter()
-    oracle.theta_modal(pb, 0.5, 1.0, t_sample, w.i_src)
+    oracle.theta_modal(pb, 0.5, 1.0, t_sample, w.i_src, i_D)
     t_modal = time.perf_counter() - t0 - t_dec
     t0 = time.perf_counter()
-    oracle.theta_direct(pb, 0.5, 1.0, t_sample, w.i_src)
+    oracle.theta_direct(pb, 0.5, 1.0, t_sample, w.i_src, i_D)
     t_direct = time.perf_counter() - t0
     r = full.n / w.n
     nth = len(full.thetas)
     modal_est = t_dec * r ** 3 + max(t_modal, 0.0) * r ** 2 * (full.T / t_sample) * nth
     return {"value": round(modal_est, 1), "unit": "s", "cores": 1, "kind": "oracle",
             "sample": (f"oracle modal path (Jacobi decomposition + modal theta-steps) and "
-                       f"direct Cholesky stepper on a {side}x{side} plate (N={w.n}, "
-                       f"T={t_sample}, theta=0.5): decomposition {t_dec:.2f} s, modal "
-                       f"steps {max(t_modal, 0):.2f} s, direct {t_direct:.2f} s; value "
-                       f"extrapolated to N={full.n}, T={full.T} x {nth} thetas by N^3 "
+                       f"direct Cholesky stepper on {what} (N={w.n}, T={t_sample}, "
+                       f"theta=0.5): decomposition {t_dec:.2f} s, modal steps "
+                       f"{max(t_modal, 0):.2f} s, direct {t_direct:.2f} s; value "
+                       f"extrapolated to N={full.n}, T={full.T} x {nth} theta(s) by N^3 "
                        f"(decomposition) and N^2 T (steps)"),
             "cholesky_estimate_s": round(t_direct * r ** 2 * (full.T / t_sample) * nth, 1)}
 
@@ -379,13 +486,22 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="plate-128x128-crack")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed runs first (default 1; 0 for the electrode plates, whose "
+                         "one run is minutes of GPU time at full size)")
+    ap.add_argument("--workload", default="plate-256x384-electrodes",
+                    help="plate-256x384-electrodes (N = 98,304, 1e5 steps: the headline), "
+                         "plate-WxH-electrodes, plate-128x128-crack, block-8x8x8, "
+                         "batched-coils-128x128, adjoint-128x256")
     ap.add_argument("--T", type=int, default=None, help="override the step count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fd-cells", type=int, default=2,
                     help="adjoint workload: cells checked by central differences")
+    ap.add_argument("--chol-steps", type=int, default=300,
+                    help="electrode plates: Cholesky steps measured (the rest extrapolated)")
     args = ap.parse_args()
+    if args.warmup is None:
+        args.warmup = 0 if args.workload.endswith("-electrodes") else 1
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; --gpus above 1 is not supported "
               "(the multi-GPU sharding is described in DESIGN.md)", file=sys.stderr)
@@ -394,6 +510,10 @@ def main():
         res = run_batched(args)
     elif args.workload.startswith("adjoint"):
         res = run_adjoint(args)
+    elif args.workload.endswith("-electrodes"):
+        res = run_electrodes(args)
+        if not args.no_cpu_baseline:
+            res["cpu_baseline"] = cpu_baseline(args)
     else:
         res = run_gpu(args)
         if not args.no_cpu_baseline:

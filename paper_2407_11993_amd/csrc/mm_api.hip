@@ -52,7 +52,7 @@ constexpr int kBand = 64;         // bandwidth of the first tridiagonalisation s
 constexpr int kMaxColumns = 4096;  // sources, probes
 constexpr int kMaxRunColumns = 8;  // forcing columns and probes of one stepping call
 
-// workspace of the decomposition; the projected one never needs the full
+// workspace of the eigensolver; the projected one never needs the full
 // divide-and-conquer buffers (4 n^2) or Q1 applied to n columns
 int64_t eig_ws_elems(int64_t n, int nb, bool project = false) {
   int64_t w = sy2sb_ws_elems(n, nb);
@@ -63,8 +63,6 @@ int64_t eig_ws_elems(int64_t n, int nb, bool project = false) {
     w = std::max(w, stedc_ws_elems(n));
     w = std::max(w, apply_q1_ws_elems(n, nb, n));
   }
-  w = std::max(w, potrf_ws_elems(n));
-  w = std::max(w, trtri_ws_elems(n));
   return w;
 }
 
@@ -403,27 +401,31 @@ void decompose_impl(mm_ctx* c, bool project) {
                "(use mm_decompose)");
     c->decomposed = false;
     c->has_Q = false;
+    // Buffers in the order they are needed, released as soon as they are not
+    // (at N = 98,304 one n0^2 buffer is 77 GB: at most three live at once).
+    c->Q.release();
     c->G.alloc(sizeof(double) * n0 * n0);
-    c->Q.alloc(sizeof(double) * n0 * n0);
     c->lam.alloc(sizeof(double) * n0);
     c->Wm.alloc(sizeof(double) * n0 * std::max(1, c->nf));
     c->Pm.alloc(sizeof(double) * n0 * c->n_probe);
     c->y.alloc(sizeof(double) * n0);
     Dev Cb, ws, GFP;
-    Cb.alloc(sizeof(double) * n0 * n0);
     double* G = c->G.d();
-    double* Q = c->Q.d();
-    double* C = Cb.d();
     int64_t* st = c->status.as<int64_t>();
     // a0, a1: L_i (lower triangle);  a2: L_i = G G^T  (Ne = 0: L_i = L)
     const int m = (int)c->m;
     assemble_L(c->xyz.d() + 3 * m, c->h, n0, G, n0, false, s, c->lr(0.0));
     factor_checked(G, n0, st, ws, s, "L");
     // a3: C = G^{-1} R G^{-T}:  G <- G^{-1};  W = G^{-1} R (in Q);  C = G^{-1} W^T
-    const int64_t wse = eig_ws_elems(n0, nb, project);
-    ws.alloc(sizeof(double) * wse);
-    trtri_lower(G, n0, n0, ws.d(), wse, s);
+    ws.alloc(sizeof(double) * trtri_ws_elems(n0));
+    trtri_lower(G, n0, n0, ws.d(), trtri_ws_elems(n0), s);
+    MM_HIP_TRY(hipStreamSynchronize(s));
+    ws.release();
+    c->Q.alloc(sizeof(double) * n0 * n0);  // W = G^{-1} R here, later the eigenvectors
+    double* Q = c->Q.d();
     dense_times_csr(G, n0, c->R(), Q, n0, s);
+    Cb.alloc(sizeof(double) * n0 * n0);
+    double* C = Cb.d();
     {
       Gemm g;
       g.m = n0; g.n = n0; g.k = n0;
@@ -479,6 +481,15 @@ void decompose_impl(mm_ctx* c, bool project) {
       g.C = GP; g.ldc = n0;
       gemm(g, s);
     }
+    if (project) {
+      // neither G^{-1} nor W is needed again without the eigenvector matrix
+      MM_HIP_TRY(hipStreamSynchronize(s));
+      c->Q.release();
+      c->G.release();
+      Q = nullptr;
+    }
+    const int64_t wse = eig_ws_elems(n0, nb, project);
+    ws.alloc(sizeof(double) * wse);
     // a4-a7: C = Q Lam Q^T
     Sb2stPlan plan = sb2st_plan(n0, nb);
     Dev tau1, T1, AB, V2, tau2, off, dv, ev;
@@ -486,8 +497,10 @@ void decompose_impl(mm_ctx* c, bool project) {
     tau1.alloc(sizeof(double) * np * nb);
     T1.alloc(sizeof(double) * np * nb * nb);
     AB.alloc(sizeof(double) * (2 * nb + 1) * n0);
-    V2.alloc(sizeof(double) * std::max<int64_t>(1, plan.tasks) * nb);
-    tau2.alloc(sizeof(double) * std::max<int64_t>(1, plan.tasks));
+    if (!project) {  // the bulge-chase reflectors, kept for the back-transform
+      V2.alloc(sizeof(double) * std::max<int64_t>(1, plan.tasks) * nb);
+      tau2.alloc(sizeof(double) * std::max<int64_t>(1, plan.tasks));
+    }
     off.alloc(sizeof(int64_t) * (n0 + 1));
     dv.alloc(sizeof(double) * n0);
     ev.alloc(sizeof(double) * std::max<int64_t>(1, n0));
@@ -495,7 +508,9 @@ void decompose_impl(mm_ctx* c, bool project) {
                               hipMemcpyHostToDevice, s));
     EigWork w;
     w.nb = nb;
-    w.tau1 = tau1.d(); w.T1 = T1.d(); w.AB = AB.d(); w.V2 = V2.d(); w.tau2 = tau2.d();
+    w.tau1 = tau1.d(); w.T1 = T1.d(); w.AB = AB.d();
+    w.V2 = project ? nullptr : V2.d();
+    w.tau2 = project ? nullptr : tau2.d();
     w.d_offset = off.as<int64_t>(); w.d = dv.d(); w.e = ev.d();
     w.ws = ws.d(); w.ws_elems = wse;
     fill_i64(st + 1, 1, 0, s);

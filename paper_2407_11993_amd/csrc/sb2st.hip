@@ -133,8 +133,10 @@ __global__ void __launch_bounds__(NT) sb2st_stage(Band B, int n, int nb, int sta
       s_tau = tv;
       s_beta = beta;
     }
-    if (lane < nb) V2[task * nb + lane] = vv;
-    if (lane == 0) tau2[task] = tv;
+    if (V2) {  // kept for the back-transform (not when only Q2^T Y is wanted)
+      if (lane < nb) V2[task * nb + lane] = vv;
+      if (lane == 0) tau2[task] = tv;
+    }
   }
   __syncthreads();
   const double tau = s_tau;
