@@ -42,8 +42,10 @@ int sb2st_max_cols();
 void sb2st(double* AB, int64_t ldab, const Sb2stPlan& plan, const int64_t* d_offset,
            double* V2, double* tau2, double* d, double* e, hipStream_t s,
            double* Y = nullptr, int64_t ldy = 0, int ny = 0);
-// Z <- Q2 Z (rows 0..n-1, ncols columns); ws: any size above 2^15 doubles
-// (more is faster: the compact-WY blocks are processed in batches).
+// Z <- Q2 Z (rows 0..n-1, ncols columns); ws: at least the block list plus
+// one block's V and VT (2^15 doubles); apply_q2_ws_elems(n, nb) holds every
+// block at once (a smaller ws processes the compact-WY blocks in batches).
+int64_t apply_q2_ws_elems(int64_t n, int nb);
 void apply_q2(const Sb2stPlan& plan, const int64_t* d_offset, const double* V2,
               const double* tau2, double* Z, int64_t ldz, int64_t ncols, double* ws,
               int64_t ws_elems, hipStream_t s);

@@ -8,9 +8,15 @@
 // one column of C on consecutive rows, which makes the column-major stores
 // contiguous per 16 lanes.
 //
-// Workgroups are renumbered so that consecutive tiles land on the same XCD
-// (the dispatcher deals workgroups round-robin over the 8 XCDs, each with its
-// own L2), and tiles are walked in groups of 8 tile-rows for L2 reuse.
+// Tiles are walked in groups of 8 tile-rows for L2 reuse, and dealt to the
+// XCDs in chunks of consecutive tiles (the dispatcher deals workgroups
+// round-robin over the 8 XCDs, each with its own L2): workgroup b runs tile
+// t = ((b/8) / CH * 8 + b%8) * CH + (b/8) % CH, so each XCD walks its own
+// chunks in order and shares operands within a chunk, while every XCD gets
+// chunks from all over the tile grid.  The last matters for triangular
+// launches (lower C, triangular operands), whose work per tile row grows
+// down the grid: contiguous eighths of the grid per XCD leave the last XCD
+// with most of the work.
 #include "common.h"
 
 namespace mm {
@@ -36,15 +42,18 @@ struct KArgs {
   double* ws;
   const GemmGroup* groups;
   int tiles_m, tiles_n;  // tile grid the launch covers
+  int ch_log2;           // log2 of the tiles per chunk dealt to one XCD
 };
 
-__device__ __forceinline__ void tile_of(int bid, int tiles_m, int tiles_n,
+// The tile of workgroup bid; false for the padding of the grid (a multiple of
+// 8 chunks).
+__device__ __forceinline__ bool tile_of(int bid, int tiles_m, int tiles_n, int ch_log2,
                                         int& ti, int& tj) {
   const int T = tiles_m * tiles_n;
-  // XCD-aware renumbering: bid = local * 8 + xcd  ->  t = off(xcd) + local
   const int xcd = bid & 7, local = bid >> 3;
-  const int base = T >> 3, rem = T & 7;
-  const int t = xcd * base + (xcd < rem ? xcd : rem) + local;
+  const int chunk = ((local >> ch_log2) << 3) + xcd;
+  const int t = (chunk << ch_log2) + (local & ((1 << ch_log2) - 1));
+  if (t >= T) return false;
   // grouped ordering along M
   const int per_group = GROUP_M * tiles_n;
   const int g = t / per_group;
@@ -53,6 +62,22 @@ __device__ __forceinline__ void tile_of(int bid, int tiles_m, int tiles_n,
   const int w = t - g * per_group;
   ti = first_m + w % gsz;
   tj = w / gsz;
+  return true;
+}
+
+// Chunk size for T tiles: the largest power of two up to 64 that still gives
+// every XCD at least 16 chunks (a partial last round of chunks then costs an
+// XCD at most 1/16 of its share).
+int chunk_log2(int64_t T) {
+  int c = 6;
+  while (c > 0 && ((int64_t)8 * 16) << c > T) --c;
+  return c;
+}
+
+// Workgroups of a launch over T tiles: T rounded up to 8 chunks.
+int64_t padded_tiles(int64_t T, int ch_log2) {
+  const int64_t q = (int64_t)8 << ch_log2;
+  return ceil_div(T, q) * q;
 }
 
 #ifndef MM_GEMM_WPE
@@ -84,7 +109,7 @@ __global__ void __launch_bounds__(64 * WGM * WGN)
     C = a.C + (int64_t)blockIdx.y * a.sC;
   }
   int ti, tj;
-  tile_of(blockIdx.x, a.tiles_m, a.tiles_n, ti, tj);
+  if (!tile_of(blockIdx.x, a.tiles_m, a.tiles_n, a.ch_log2, ti, tj)) return;
   const int64_t i0 = (int64_t)ti * BM, j0 = (int64_t)tj * BN;
   if (i0 >= M || j0 >= N) return;
   if (a.lower && i0 + BM <= j0) return;  // tile strictly above the diagonal
@@ -330,7 +355,9 @@ void gemm(const Gemm& g, hipStream_t stream, double* ws, int64_t ws_elems) {
   ka.tiles_m = (int)ceil_div(g.m, bm);
   ka.tiles_n = (int)ceil_div(g.n, bn);
   const int64_t tiles = (int64_t)ka.tiles_m * ka.tiles_n;
-  MM_REQUIRE(tiles < (int64_t)1 << 31, kInvalid, "gemm: too many tiles");
+  ka.ch_log2 = chunk_log2(tiles);
+  const int64_t wgs = padded_tiles(tiles, ka.ch_log2);
+  MM_REQUIRE(wgs < (int64_t)1 << 31, kInvalid, "gemm: too many tiles");
   // split-K for few output tiles over a long k (never together with batching)
   int splits = 1;
   if (ws && g.batch == 1 && tiles * 4 < 1024 && g.k >= 2048) {
@@ -341,7 +368,7 @@ void gemm(const Gemm& g, hipStream_t stream, double* ws, int64_t ws_elems) {
   }
   ka.splits = splits;
   ka.ws = splits > 1 ? ws : nullptr;
-  dim3 grid((unsigned)tiles, (unsigned)g.batch, (unsigned)splits);
+  dim3 grid((unsigned)wgs, (unsigned)g.batch, (unsigned)splits);
   if (big) launch<Big::BM, Big::BN, Big::WGM, Big::WGN, false>(ka, g.ta, g.tb, grid, stream);
   else launch<64, 64, 2, 2, false>(ka, g.ta, g.tb, grid, stream);
   MM_HIP_TRY(hipGetLastError());
@@ -364,7 +391,11 @@ void gemm_grouped(const GemmGroup* d_groups, int64_t n_groups, int64_t max_m,
   const int bm = big ? Big::BM : 64, bn = big ? Big::BN : 64;
   ka.tiles_m = (int)ceil_div(max_m, bm);
   ka.tiles_n = (int)ceil_div(max_n, bn);
-  dim3 grid((unsigned)((int64_t)ka.tiles_m * ka.tiles_n), (unsigned)n_groups, 1);
+  const int64_t tiles = (int64_t)ka.tiles_m * ka.tiles_n;
+  ka.ch_log2 = chunk_log2(tiles);
+  const int64_t wgs = padded_tiles(tiles, ka.ch_log2);
+  MM_REQUIRE(wgs < (int64_t)1 << 31, kInvalid, "gemm_grouped: too many tiles");
+  dim3 grid((unsigned)wgs, (unsigned)n_groups, 1);
   if (big) launch<Big::BM, Big::BN, Big::WGM, Big::WGN, true>(ka, ta, tb, grid, stream);
   else launch<64, 64, 2, 2, true>(ka, ta, tb, grid, stream);
   MM_HIP_TRY(hipGetLastError());

@@ -62,6 +62,7 @@ int64_t eig_ws_elems(int64_t n, int nb, bool project = false) {
   } else {
     w = std::max(w, stedc_ws_elems(n));
     w = std::max(w, apply_q1_ws_elems(n, nb, n));
+    w = std::max(w, apply_q2_ws_elems(n, nb));
   }
   return w;
 }

@@ -255,18 +255,12 @@ __global__ void __launch_bounds__(NT) q2_apply_k(const Pair* pairs, int64_t p0, 
   }
 }
 
-}  // namespace
-
-void apply_q2(const Sb2stPlan& plan, const int64_t* d_offset, const double* V2,
-              const double* tau2, double* Z, int64_t ldz, int64_t ncols, double* ws,
-              int64_t ws_elems, hipStream_t s) {
-  const int64_t n = plan.n;
-  const int nb = plan.nb;
-  MM_REQUIRE(nb + GS - 1 <= WR, kInvalid, "apply_q2: band too wide");
-  if (n < 3 || ncols <= 0) return;
+// the (g, k) blocks in application order: g descending, k ascending
+std::vector<Pair> q2_pairs(int64_t n, int nb) {
+  std::vector<Pair> pairs;
+  if (n < 3) return pairs;
   const int64_t nsweeps = n - 2;  // sweeps 0..n-3 carry reflectors
   const int64_t ngroups = ceil_div(nsweeps, GS);
-  std::vector<Pair> pairs;
   for (int64_t g = ngroups - 1; g >= 0; --g) {
     const int64_t sa = g * GS, sl = std::min(sa + GS, nsweeps);
     const int64_t kmax = ceil_div(n - 1 - sa, nb);
@@ -277,9 +271,31 @@ void apply_q2(const Sb2stPlan& plan, const int64_t* d_offset, const double* V2,
       pairs.push_back(Pair{sa, sl, k, wlo, whi - wlo});
     }
   }
+  return pairs;
+}
+
+constexpr int64_t kPerPair = 2 * (int64_t)WR * GS;  // V and VT of one block
+
+int64_t pair_list_words(int64_t npairs) { return (int64_t)((sizeof(Pair) * npairs + 7) / 8); }
+
+}  // namespace
+
+int64_t apply_q2_ws_elems(int64_t n, int nb) {
+  const int64_t npairs = (int64_t)q2_pairs(n, nb).size();
+  return pair_list_words(npairs) + kPerPair * std::max<int64_t>(1, npairs) + 1;
+}
+
+void apply_q2(const Sb2stPlan& plan, const int64_t* d_offset, const double* V2,
+              const double* tau2, double* Z, int64_t ldz, int64_t ncols, double* ws,
+              int64_t ws_elems, hipStream_t s) {
+  const int64_t n = plan.n;
+  const int nb = plan.nb;
+  MM_REQUIRE(nb + GS - 1 <= WR, kInvalid, "apply_q2: band too wide");
+  if (n < 3 || ncols <= 0) return;
+  const std::vector<Pair> pairs = q2_pairs(n, nb);
   const int64_t npairs = (int64_t)pairs.size();
-  const int64_t per_pair = 2 * (int64_t)WR * GS;
-  const int64_t pair_words = (int64_t)((sizeof(Pair) * npairs + 7) / 8);
+  const int64_t per_pair = kPerPair;
+  const int64_t pair_words = pair_list_words(npairs);
   MM_REQUIRE(ws_elems > pair_words + per_pair, kInvalid, "apply_q2: workspace too small");
   Pair* d_pairs = reinterpret_cast<Pair*>(ws);
   double* buf = ws + pair_words;
