@@ -210,6 +210,12 @@ mm_status mmk_dgemm(int32_t trans_a, int32_t trans_b, int64_t m, int64_t n,
                     const double* B, int64_t ldb, double beta, double* C,
                     int64_t ldc, void* stream);
 
+/* C = alpha A B + beta C with A (m x m) symmetric, only its lower triangle
+ * read; B and C are m x n. */
+mm_status mmk_dsymm_lower(int64_t m, int64_t n, double alpha, const double* A,
+                          int64_t lda, const double* B, int64_t ldb, double beta,
+                          double* C, int64_t ldc, void* stream);
+
 /* A = G G^T (lower, in place, strict upper triangle zeroed); *info (host)
  * = -1 or the first non-positive pivot.  (The factorisation of Sec. 3.3.1
  * and of Li in Sec. 3.2.) */
@@ -219,8 +225,9 @@ mm_status mmk_dpotrf(int64_t n, double* A, int64_t lda, int64_t* info,
 /* A <- A^{-1} for lower-triangular A. */
 mm_status mmk_dtrtri(int64_t n, double* A, int64_t lda, void* stream);
 
-/* Band reduction C = Q1 B Q1^T (1 <= nb <= 64): A (full symmetric) is
- * overwritten; AB (ldab x n, ldab >= 2 nb + 1) receives the lower band,
+/* Band reduction C = Q1 B Q1^T (1 <= nb <= 64): A is symmetric and only its
+ * lower triangle is read; that triangle is overwritten (the upper one is left
+ * as it was); AB (ldab x n, ldab >= 2 nb + 1) receives the lower band,
  * AB(d, j) = B(j+d, j). */
 mm_status mmk_dsy2sb(int64_t n, double* A, int64_t lda, int32_t nb, double* AB,
                      int64_t ldab, void* stream);

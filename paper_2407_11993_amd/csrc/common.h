@@ -67,6 +67,9 @@ struct Gemm {
   bool a_upper = false;
   bool b_lower = false;
   int64_t b_band = -1;
+  // op(A) symmetric with only its lower triangle stored: element (i, k) is
+  // read from A(max(i, k), min(i, k)).  Not with ta or the other A flags.
+  bool a_sym = false;
   int64_t batch = 1;
   int64_t sA = 0, sB = 0, sC = 0;  // batch strides (elements)
 };

@@ -35,7 +35,7 @@ struct KArgs {
   int64_t ldb;
   double* C;
   int64_t ldc;
-  int lower, a_lower, a_upper, b_lower;
+  int lower, a_lower, a_upper, b_lower, a_sym;
   int64_t b_band;
   int64_t sA, sB, sC;
   int splits;
@@ -147,13 +147,43 @@ __global__ void __launch_bounds__(64 * WGM * WGN)
   constexpr int64_t RA = TA ? (NT / BK) : (NT / BM);  // op(A) rows/cols per r
   constexpr int64_t RB = TB ? (NT / BN) : (NT / BK);
   constexpr bool FAST = BM >= 128;  // the small tile keeps the guarded loads
+  // A symmetric in its lower triangle (not TA): a slice that reaches above the
+  // diagonal is read from the transposed position.  Slices wholly above it
+  // load k-contiguous (the TA pattern, recorded in ltr for the LDS store);
+  // slices that cross the diagonal pick per element.
+  bool ltr = false;
   auto load = [&](int64_t kt) {
-    if (FAST && i0 + BM <= M && kt + BK <= ke) {
+    bool sym_done = false;
+    if constexpr (!TA) {
+      if (a.a_sym && kt + BK - 1 > i0) {
+        sym_done = true;
+        if (kt >= i0 + BM - 1 && i0 + BM <= M && kt + BK <= ke) {
+          ltr = true;
+          const double* Ap = A + (kt + t % BK) + (i0 + t / BK) * lda;
+#pragma unroll
+          for (int r = 0; r < LA; ++r) ra[r] = Ap[(int64_t)r * (NT / BK) * lda];
+        } else {
+          ltr = false;
+#pragma unroll
+          for (int r = 0; r < LA; ++r) {
+            const int e = t + r * NT;
+            const int64_t gi = i0 + e % BM, gk = kt + e / BM;
+            double v = 0.0;
+            if (gi < M && gk < ke) v = gi >= gk ? A[gi + gk * lda] : A[gk + gi * lda];
+            ra[r] = v;
+          }
+        }
+      }
+    }
+    if (sym_done) {
+    } else if (FAST && i0 + BM <= M && kt + BK <= ke) {
+      ltr = false;
       const double* Ap = TA ? A + (kt + t % BK) + (i0 + t / BK) * lda
                             : A + (i0 + t % BM) + (kt + t / BM) * lda;
 #pragma unroll
       for (int r = 0; r < LA; ++r) ra[r] = Ap[r * RA * lda];
     } else {
+      ltr = false;
 #pragma unroll
       for (int r = 0; r < LA; ++r) {
         const int e = t + r * NT;
@@ -188,13 +218,21 @@ __global__ void __launch_bounds__(64 * WGM * WGN)
     }
   };
   auto store = [&](int buf) {
+    if (!TA && ltr) {
 #pragma unroll
-    for (int r = 0; r < LA; ++r) {
-      const int e = t + r * NT;
-      int ii, kk;
-      if constexpr (!TA) { ii = e % BM; kk = e / BM; }
-      else { kk = e % BK; ii = e / BK; }
-      As[buf][kk][ii] = ra[r];
+      for (int r = 0; r < LA; ++r) {
+        const int e = t + r * NT;
+        As[buf][e % BK][e / BK] = ra[r];
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < LA; ++r) {
+        const int e = t + r * NT;
+        int ii, kk;
+        if constexpr (!TA) { ii = e % BM; kk = e / BM; }
+        else { kk = e % BK; ii = e / BK; }
+        As[buf][kk][ii] = ra[r];
+      }
     }
 #pragma unroll
     for (int r = 0; r < LB; ++r) {
@@ -345,6 +383,9 @@ void gemm(const Gemm& g, hipStream_t stream, double* ws, int64_t ws_elems) {
   ka.C = g.C; ka.ldc = g.ldc;
   ka.lower = g.lower; ka.a_lower = g.a_lower; ka.a_upper = g.a_upper;
   ka.b_lower = g.b_lower; ka.b_band = g.b_band;
+  ka.a_sym = g.a_sym;
+  MM_REQUIRE(!g.a_sym || (!g.ta && !g.a_lower && !g.a_upper && g.m == g.k), kInvalid,
+             "gemm: a_sym takes A untransposed and without triangle flags");
   ka.sA = g.sA; ka.sB = g.sB; ka.sC = g.sC;
   ka.splits = 1; ka.ws = nullptr; ka.groups = nullptr;
   if (g.k <= 0) {

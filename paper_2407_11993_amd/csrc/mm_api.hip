@@ -1086,6 +1086,23 @@ mm_status mmk_dgemm(int32_t ta, int32_t tb, int64_t m, int64_t n, int64_t k, dou
   });
 }
 
+mm_status mmk_dsymm_lower(int64_t m, int64_t n, double alpha, const double* A, int64_t lda,
+                          const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
+                          void* stream) {
+  return guarded(nullptr, [&] {
+    MM_REQUIRE(m >= 0 && n >= 0, kInvalid, "negative size");
+    MM_REQUIRE(lda >= std::max<int64_t>(1, m) && ldb >= std::max<int64_t>(1, m) &&
+                   ldc >= std::max<int64_t>(1, m), kInvalid, "lda, ldb or ldc");
+    Gemm g;
+    g.m = m; g.n = n; g.k = m; g.alpha = alpha; g.beta = beta;
+    g.A = A; g.lda = lda; g.a_sym = true;
+    g.B = B; g.ldb = ldb;
+    g.C = C; g.ldc = ldc;
+    gemm(g, (hipStream_t)stream);
+    MM_HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  });
+}
+
 mm_status mmk_dpotrf(int64_t n, double* A, int64_t lda, int64_t* info, void* stream) {
   return guarded(nullptr, [&] {
     MM_REQUIRE(n >= 0 && lda >= std::max<int64_t>(1, n), kInvalid, "n or lda");

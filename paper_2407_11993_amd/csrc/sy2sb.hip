@@ -14,6 +14,10 @@
 //      matrix cores:  X = A22 V T,  Y = X - 1/2 V (T^T V^T X),
 //      A22 -= V Y^T + Y V^T.
 //
+// Only the lower triangle of A is read or written: A22 V reads A22 as a
+// symmetric matrix stored in its lower triangle, and the rank-2nb update
+// writes the lower triangle only (half the work and traffic of a full one).
+//
 // R overwrites the panel's top nb x nb block; V stays below it (the implicit
 // unit diagonal at row r0 + c of column j + c) for the back-transform.
 #include "kernels.h"
@@ -244,10 +248,10 @@ void sy2sb(double* A, int64_t lda, int64_t n, int nb, double* tau_all, double* T
     hipLaunchKernelGGL(form_t, dim3(1), dim3(128), 0, s, Sm, tau, nb, T);
     MM_HIP_TRY(hipGetLastError());
     double* A22 = A + r0 + r0 * lda;
-    // X0 = A22 V  (m x nb)
+    // X0 = A22 V  (m x nb; A22 symmetric, lower triangle stored)
     Gemm g1;
     g1.m = m; g1.n = nb; g1.k = m;
-    g1.A = A22; g1.lda = lda;
+    g1.A = A22; g1.lda = lda; g1.a_sym = true;
     g1.B = V; g1.ldb = m;
     g1.C = X; g1.ldc = m;
     gemm(g1, s, split, split_elems);
@@ -280,13 +284,14 @@ void sy2sb(double* A, int64_t lda, int64_t n, int nb, double* tau_all, double* T
     g5.B = Zm; g5.ldb = nb;
     g5.C = Y; g5.ldc = m;
     gemm(g5, s);
-    // A22 -= [V Y] [Y V]^T  (both triangles)
+    // A22 -= [V Y] [Y V]^T  (lower triangle)
     Gemm g6;
     g6.m = m; g6.n = m; g6.k = 2 * nb;
     g6.alpha = -1.0; g6.beta = 1.0;
     g6.A = VYV; g6.lda = m;
     g6.B = VYV + m * nb; g6.ldb = m; g6.tb = true;
     g6.C = A22; g6.ldc = lda;
+    g6.lower = true;
     gemm(g6, s);
   }
 }

@@ -199,6 +199,19 @@ class _Kernels:
                                         _lib.stream_handle()))
         return Cc.t()
 
+    def symm_lower(self, A, B, alpha=1.0, beta=0.0, C=None):
+        """alpha A B + beta C with A symmetric; only A's lower triangle is read."""
+        A = _dev(A)
+        B = _dev(B)
+        m, n = B.shape
+        Ac, Bc = self._cm(A), self._cm(B)
+        Cc = self._cm(_dev(C)) if C is not None else torch.zeros(n, m, dtype=torch.float64,
+                                                                 device=A.device)
+        _lib.check(_lib.lib().mmk_dsymm_lower(m, n, float(alpha), _lib.ptr(Ac), max(1, m),
+                                              _lib.ptr(Bc), max(1, m), float(beta),
+                                              _lib.ptr(Cc), max(1, m), _lib.stream_handle()))
+        return Cc.t()
+
     def potrf(self, A):
         Ac = self._cm(_dev(A))
         n = Ac.shape[0]

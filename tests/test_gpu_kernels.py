@@ -49,6 +49,21 @@ def test_gemm(K, m, n, k, ta, tb):
     assert np.abs(out - ref).max() <= 1e-15 * scale * 4
 
 
+@pytest.mark.parametrize("m,n", [(1, 1), (5, 3), (130, 70), (257, 129), (2100, 2100),
+                                 (4096, 1030)])
+def test_symm_lower(K, m, n):
+    """The upper triangle of A holds NaN: a read of it would show in C."""
+    rng = np.random.default_rng(m + 5 * n)
+    S = _sym(m, m + 1)
+    A = np.tril(S) + np.triu(np.full((m, m), np.nan), 1)
+    B = rng.standard_normal((m, n))
+    C0 = rng.standard_normal((m, n))
+    ref = 0.5 * (S @ B) - 2.0 * C0
+    out = _np(K.symm_lower(A, B, alpha=0.5, beta=-2.0, C=C0))
+    scale = np.abs(S).max() * np.abs(B).max() * m + 2 * np.abs(C0).max()
+    assert np.abs(out - ref).max() <= 1e-15 * scale * 4
+
+
 @pytest.mark.parametrize("n", [1, 5, 128, 129, 300, 513])
 def test_potrf(K, n):
     A = _spd(n, n)
@@ -90,6 +105,9 @@ def test_sy2sb_preserves_spectrum(K, n, nb):
     A = _sym(n, n + nb)
     AB = _np(K.sy2sb(A, nb))
     assert np.all(AB[:, nb + 1:] == 0)
+    # only the lower triangle is read: NaN above it changes nothing
+    Au = np.tril(A) + np.triu(np.full((n, n), np.nan), 1)
+    assert np.array_equal(_np(K.sy2sb(Au, nb)), AB)
     B = _band_dense(AB, n, nb)
     ev = np.linalg.eigvalsh(A)
     eb = np.linalg.eigvalsh(B)
