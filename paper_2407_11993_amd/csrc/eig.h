@@ -58,11 +58,13 @@ int64_t stedc_ws_elems(int64_t n);
 void stedc(const double* d, const double* e, int64_t n, double* lam, double* Z,
            int64_t ldz, double* ws, int64_t ws_elems, int64_t* d_status, hipStream_t s);
 // Eigenvalues and ZY = Z^T Y (n x ny) without forming Z: every node of the
-// tree keeps its eigenvectors' projections and boundary entries only.
+// tree keeps its eigenvectors' projections and boundary entries only.  U is
+// n^2 doubles of scratch for the merges' eigenvector blocks (it may not
+// overlap Y, ZY or ws); ws holds stedc_project_ws_elems(n, ny) doubles.
 int64_t stedc_project_ws_elems(int64_t n, int ny);
 void stedc_project(const double* d, const double* e, int64_t n, double* lam, const double* Y,
-                   int64_t ldy, int ny, double* ZY, int64_t ldzy, double* ws, int64_t ws_elems,
-                   int64_t* d_status, hipStream_t s);
+                   int64_t ldy, int ny, double* ZY, int64_t ldzy, double* U, double* ws,
+                   int64_t ws_elems, int64_t* d_status, hipStream_t s);
 
 // ---- driver -----------------------------------------------------------------
 struct EigWork {
@@ -85,6 +87,8 @@ void syevd(double* C, int64_t ldc, int64_t n, double* lam, double* Q, int64_t ld
 // without forming Q: Y <- Q2^T Q1^T Y on the way through the band reduction
 // and the bulge chase, then ZY = Z^T Y from the projected divide and conquer
 // (w.ws must hold stedc_project_ws_elems and sy2sb's and apply_q1t's needs).
+// C is destroyed: once its band is extracted, its storage (ldc n >= n^2
+// doubles) is the divide and conquer's eigenvector scratch.
 void syevd_project(double* C, int64_t ldc, int64_t n, double* lam, double* Y, int64_t ldy,
                    int ny, double* ZY, int64_t ldzy, const EigWork& w, const Sb2stPlan& plan,
                    int64_t* d_status, hipStream_t s);

@@ -120,7 +120,8 @@ void syevd_project(double* C, int64_t ldc, int64_t n, double* lam, double* Y, in
   const int64_t ldab = 2 * nb + 1;
   extract_band(C, ldc, n, nb, w.AB, ldab, s);
   sb2st(w.AB, ldab, plan, w.d_offset, w.V2, w.tau2, w.d, w.e, s, Y, ldy, ny);
-  stedc_project(w.d, w.e, n, lam, Y, ldy, ny, ZY, ldzy, w.ws, w.ws_elems, d_status, s);
+  // C is dead from here on (its reflectors were applied to Y, its band copied)
+  stedc_project(w.d, w.e, n, lam, Y, ldy, ny, ZY, ldzy, C, w.ws, w.ws_elems, d_status, s);
 }
 
 void syevd(double* C, int64_t ldc, int64_t n, double* lam, double* Q, int64_t ldq,

@@ -53,7 +53,8 @@ constexpr int kMaxColumns = 4096;  // sources, probes
 constexpr int kMaxRunColumns = 8;  // forcing columns and probes of one stepping call
 
 // workspace of the eigensolver; the projected one never needs the full
-// divide-and-conquer buffers (4 n^2) or Q1 applied to n columns
+// divide-and-conquer buffers (4 n^2) or Q1 applied to n columns, and its
+// divide and conquer keeps its n^2 eigenvector scratch in C's storage
 int64_t eig_ws_elems(int64_t n, int nb, bool project = false) {
   int64_t w = sy2sb_ws_elems(n, nb);
   if (project) {
@@ -404,13 +405,29 @@ void decompose_impl(mm_ctx* c, bool project) {
     c->has_Q = false;
     // Buffers in the order they are needed, released as soon as they are not
     // (at N = 98,304 one n0^2 buffer is 77 GB: at most three live at once).
+    // The small buffers of the eigensolver are allocated first: an
+    // allocation that has to reuse memory just freed by another one of this
+    // size can take seconds.
     c->Q.release();
+    const int64_t wse = eig_ws_elems(n0, nb, project);
+    Dev Cb, ws, GFP;
+    ws.alloc(sizeof(double) * std::max(wse, potrf_ws_elems(n0)));
+    Sb2stPlan plan = sb2st_plan(n0, nb);
+    Dev tau1, T1, AB, V2, tau2, off, dv, ev, ZY;
+    const int64_t np = std::max<int64_t>(1, sy2sb_npanels(n0, nb));
+    tau1.alloc(sizeof(double) * np * nb);
+    T1.alloc(sizeof(double) * np * nb * nb);
+    AB.alloc(sizeof(double) * (2 * nb + 1) * n0);
+    off.alloc(sizeof(int64_t) * (n0 + 1));
+    dv.alloc(sizeof(double) * n0);
+    ev.alloc(sizeof(double) * std::max<int64_t>(1, n0));
+    if (project) ZY.alloc(sizeof(double) * n0 * ny);
+    GFP.alloc(sizeof(double) * n0 * ny);
     c->G.alloc(sizeof(double) * n0 * n0);
     c->lam.alloc(sizeof(double) * n0);
     c->Wm.alloc(sizeof(double) * n0 * std::max(1, c->nf));
     c->Pm.alloc(sizeof(double) * n0 * c->n_probe);
     c->y.alloc(sizeof(double) * n0);
-    Dev Cb, ws, GFP;
     double* G = c->G.d();
     int64_t* st = c->status.as<int64_t>();
     // a0, a1: L_i (lower triangle);  a2: L_i = G G^T  (Ne = 0: L_i = L)
@@ -418,10 +435,12 @@ void decompose_impl(mm_ctx* c, bool project) {
     assemble_L(c->xyz.d() + 3 * m, c->h, n0, G, n0, false, s, c->lr(0.0));
     factor_checked(G, n0, st, ws, s, "L");
     // a3: C = G^{-1} R G^{-T}:  G <- G^{-1};  W = G^{-1} R (in Q);  C = G^{-1} W^T
-    ws.alloc(sizeof(double) * trtri_ws_elems(n0));
-    trtri_lower(G, n0, n0, ws.d(), trtri_ws_elems(n0), s);
-    MM_HIP_TRY(hipStreamSynchronize(s));
-    ws.release();
+    {
+      Dev tws;
+      tws.alloc(sizeof(double) * trtri_ws_elems(n0));
+      trtri_lower(G, n0, n0, tws.d(), trtri_ws_elems(n0), s);
+      MM_HIP_TRY(hipStreamSynchronize(s));
+    }
     c->Q.alloc(sizeof(double) * n0 * n0);  // W = G^{-1} R here, later the eigenvectors
     double* Q = c->Q.d();
     dense_times_csr(G, n0, c->R(), Q, n0, s);
@@ -463,7 +482,6 @@ void decompose_impl(mm_ctx* c, bool project) {
     }
     symmetrize_from_lower(C, n0, n0, s);
     // G^{-1} applied to the forcing columns and the probe weights, side by side
-    GFP.alloc(sizeof(double) * n0 * ny);
     double* GF = GFP.d();
     double* GP = GFP.d() + (int64_t)c->nf * n0;
     if (c->nf > 0) {
@@ -489,22 +507,11 @@ void decompose_impl(mm_ctx* c, bool project) {
       c->G.release();
       Q = nullptr;
     }
-    const int64_t wse = eig_ws_elems(n0, nb, project);
-    ws.alloc(sizeof(double) * wse);
     // a4-a7: C = Q Lam Q^T
-    Sb2stPlan plan = sb2st_plan(n0, nb);
-    Dev tau1, T1, AB, V2, tau2, off, dv, ev;
-    const int64_t np = std::max<int64_t>(1, sy2sb_npanels(n0, nb));
-    tau1.alloc(sizeof(double) * np * nb);
-    T1.alloc(sizeof(double) * np * nb * nb);
-    AB.alloc(sizeof(double) * (2 * nb + 1) * n0);
     if (!project) {  // the bulge-chase reflectors, kept for the back-transform
       V2.alloc(sizeof(double) * std::max<int64_t>(1, plan.tasks) * nb);
       tau2.alloc(sizeof(double) * std::max<int64_t>(1, plan.tasks));
     }
-    off.alloc(sizeof(int64_t) * (n0 + 1));
-    dv.alloc(sizeof(double) * n0);
-    ev.alloc(sizeof(double) * std::max<int64_t>(1, n0));
     MM_HIP_TRY(hipMemcpyAsync(off.p, plan.offset.data(), sizeof(int64_t) * (n0 + 1),
                               hipMemcpyHostToDevice, s));
     EigWork w;
@@ -516,9 +523,7 @@ void decompose_impl(mm_ctx* c, bool project) {
     w.ws = ws.d(); w.ws_elems = wse;
     fill_i64(st + 1, 1, 0, s);
     if (project) {
-      // a4-a8 without Q: [W, Pt] = Z^T Q2^T Q1^T G^{-1} [F, P]  (Q holds Z meanwhile)
-      Dev ZY;
-      ZY.alloc(sizeof(double) * n0 * ny);
+      // a4-a8 without Q: [W, Pt] = Z^T Q2^T Q1^T G^{-1} [F, P]
       syevd_project(C, n0, n0, c->lam.d(), GFP.d(), n0, ny, ZY.d(), n0, w, plan, st + 1, s);
       if (c->nf > 0) copy_matrix(ZY.d(), n0, c->Wm.d(), n0, n0, c->nf, s);
       copy_matrix(ZY.d() + (int64_t)c->nf * n0, n0, c->Pm.d(), n0, n0, c->n_probe, s);

@@ -662,14 +662,14 @@ struct LayoutP {
   double* end;
 };
 
-LayoutP carve_proj(double* ws, int64_t n, int64_t max_merges, int W) {
+LayoutP carve_proj(double* ws, int64_t n, int64_t max_merges, int W, double* U) {
   LayoutP L;
   double* p = ws;
   auto take = [&](int64_t count) { double* r = p; p += count; return r; };
   L.dw = take(n);
   L.lamA = take(n);
   L.lamB = take(n);
-  L.U = take(n * n);
+  L.U = U;  // n^2 doubles the caller provides
   L.G = take(n * W);
   L.Pt = take(n * W);
   L.PYa = take(n * W);
@@ -812,14 +812,15 @@ void stedc(const double* d, const double* e, int64_t n, double* lam, double* Z, 
 int64_t stedc_project_ws_elems(int64_t n, int ny) {
   const int64_t mm = (int64_t)1 << depth_for(n);
   double* base = reinterpret_cast<double*>(64);
-  LayoutP L = carve_proj(base, n, mm, ny + 2);
+  LayoutP L = carve_proj(base, n, mm, ny + 2, nullptr);
   return (int64_t)(L.end - base);
 }
 
 void stedc_project(const double* d, const double* e, int64_t n, double* lam, const double* Y,
-                   int64_t ldy, int ny, double* ZY, int64_t ldzy, double* ws, int64_t ws_elems,
-                   int64_t* d_status, hipStream_t s) {
+                   int64_t ldy, int ny, double* ZY, int64_t ldzy, double* U, double* ws,
+                   int64_t ws_elems, int64_t* d_status, hipStream_t s) {
   MM_REQUIRE(ny >= 1, kInvalid, "stedc_project: at least one column");
+  MM_REQUIRE(U != nullptr || n <= 0, kInvalid, "stedc_project: no eigenvector scratch");
   MM_REQUIRE(ws_elems >= stedc_project_ws_elems(n, ny), kInvalid,
              "stedc_project: workspace too small");
   if (n <= 0) return;
@@ -827,7 +828,7 @@ void stedc_project(const double* d, const double* e, int64_t n, double* lam, con
   const Tree tr = build_tree(n);
   const int D = tr.D;
   const int64_t max_merges = (int64_t)1 << D;
-  LayoutP L = carve_proj(ws, n, max_merges, W);
+  LayoutP L = carve_proj(ws, n, max_merges, W, U);
   const int64_t ncuts = (int64_t)tr.cuts.size();
   if (ncuts)
     MM_HIP_TRY(hipMemcpyAsync(L.cuts, tr.cuts.data(), ncuts * 8, hipMemcpyHostToDevice, s));
