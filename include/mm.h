@@ -210,6 +210,23 @@ mm_status mmk_dgemm(int32_t trans_a, int32_t trans_b, int64_t m, int64_t n,
                     const double* B, int64_t ldb, double beta, double* C,
                     int64_t ldc, void* stream);
 
+/* mmk_dgemm with structure the product skips work for:
+ *   MMK_LOWER    only C's lower triangle (i >= j) is computed and written;
+ *   MMK_A_LOWER  op(A) is lower triangular, MMK_A_UPPER upper triangular;
+ *   MMK_B_LOWER  op(B) is lower triangular;
+ *   b_band >= 0  op(B)(l, j) = 0 for l > j + b_band (-1: no band).
+ * The zero parts of op(A) and op(B) must be stored as zeros: whole 16-wide
+ * k-slices are skipped where a tile's rows or columns have only zeros, the
+ * rest is read as stored. */
+#define MMK_LOWER 1
+#define MMK_A_LOWER 2
+#define MMK_A_UPPER 4
+#define MMK_B_LOWER 8
+mm_status mmk_dgemm_tri(int32_t trans_a, int32_t trans_b, int64_t m, int64_t n,
+                        int64_t k, double alpha, const double* A, int64_t lda,
+                        const double* B, int64_t ldb, double beta, double* C,
+                        int64_t ldc, int32_t flags, int64_t b_band, void* stream);
+
 /* C = alpha A B + beta C with A (m x m) symmetric, only its lower triangle
  * read; B and C are m x n. */
 mm_status mmk_dsymm_lower(int64_t m, int64_t n, double alpha, const double* A,

@@ -24,7 +24,7 @@ MM_CHOLESKY = 1
 SYMBOLS = ["mm_setup", "mm_decompose", "mm_decompose_projected", "mm_step_modal", "mm_step_cholesky",
            "mm_probe", "mm_reset_state", "mm_eigenvalues", "mm_info",
            "mm_destroy", "mm_last_error", "mm_batch_create", "mm_batch_run",
-           "mm_batch_info", "mm_batch_destroy", "mm_adjoint_modal", "mmk_dgemm", "mmk_dsymm_lower", "mmk_dpotrf",
+           "mm_batch_info", "mm_batch_destroy", "mm_adjoint_modal", "mmk_dgemm", "mmk_dgemm_tri", "mmk_dsymm_lower", "mmk_dpotrf",
            "mmk_dtrtri", "mmk_dsy2sb", "mmk_dsb2st", "mmk_dstedc", "mmk_dsyevd"]
 
 
@@ -73,6 +73,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "mm_adjoint_modal": [vp, dbl, dbl, i64, i32, ctypes.POINTER(ctypes.c_int32),
                              ctypes.POINTER(ctypes.c_int32), vp, vp, i64, vp, vp, vp],
         "mmk_dgemm": [i32, i32, i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64, vp],
+        "mmk_dgemm_tri": [i32, i32, i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64, i32, i64, vp],
         "mmk_dsymm_lower": [i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64, vp],
         "mmk_dpotrf": [i64, vp, i64, ctypes.POINTER(ctypes.c_int64), vp],
         "mmk_dtrtri": [i64, vp, i64, vp],

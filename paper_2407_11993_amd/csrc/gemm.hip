@@ -338,6 +338,229 @@ __global__ void __launch_bounds__(64 * WGM * WGN)
       }
 }
 
+// ---------------------------------------------------------------------------
+// Large tiles: 128 x 128 per workgroup of four waves, 64 x 64 per wave (16
+// MFMA accumulators, so each operand value read from LDS feeds four MFMAs).
+// Every operand and C access is a buffer instruction on a uniform base (the
+// slice's or the tile's corner) with one 32-bit per-lane offset and a uniform
+// per-element offset, so that addresses take no 64-bit vector registers.
+// Interior slices load unguarded; edge slices clamp their addresses to the
+// matrix and zero the entries at k >= ke.
+//
+// Load patterns of one 128 x 16 slice (256 threads, 8 elements each):
+//   column pattern: thread t holds row t%128 of k = t/128 + 2r (r < 8);
+//   row pattern:    thread t holds k = t%16 of row t/16 + 16r.
+// op(A) untransposed and op(B) transposed are read column-wise, the others
+// row-wise; with a_sym, a slice wholly above the diagonal is read row-wise
+// from the transposed position and one that crosses it element by element.
+// ---------------------------------------------------------------------------
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+constexpr int kRsrcFlags = 0x00020000;  // gfx9 buffer resource word 3
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_of(const double* p) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(p), (short)0, 0x7fffffff,
+                                           kRsrcFlags);
+}
+__device__ __forceinline__ double bld(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ __forceinline__ void bst(double v, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+}
+
+template <bool TA, bool TB, bool SYM>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+    gemm128_kernel(KArgs a) {
+  constexpr int BM = 128, BN = 128, L = 8;
+  __shared__ double As[2][BK][BM + PAD];
+  __shared__ double Bs[2][BK][BN + PAD];
+  const int64_t M = a.m, N = a.n, K = a.k, lda = a.lda, ldb = a.ldb, ldc = a.ldc;
+  const double* A = a.A + (int64_t)blockIdx.y * a.sA;
+  const double* B = a.B + (int64_t)blockIdx.y * a.sB;
+  double* C = a.C + (int64_t)blockIdx.y * a.sC;
+  int ti, tj;
+  if (!tile_of(blockIdx.x, a.tiles_m, a.tiles_n, a.ch_log2, ti, tj)) return;
+  const int64_t i0 = (int64_t)ti * BM, j0 = (int64_t)tj * BN;
+  if (i0 >= M || j0 >= N) return;
+  if (a.lower && i0 + BM <= j0) return;  // tile strictly above the diagonal
+  int64_t kb = 0, ke = K;
+  if (a.a_lower) ke = min(ke, i0 + BM);
+  if (a.b_band >= 0) ke = min(ke, j0 + BN + a.b_band);
+  if (a.a_upper) kb = max(kb, i0);
+  if (a.b_lower) kb = max(kb, j0);
+  kb = (kb / BK) * BK;
+
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int wm0 = (wave & 1) * 64, wn0 = (wave >> 1) * 64;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int cp_i = t & 127, cp_k = t >> 7;  // column pattern: (cp_i, cp_k + 2r)
+  const int rp_k = t & 15, rp_i = t >> 4;   // row pattern: (rp_i + 16r, rp_k)
+  const int iM = (int)min<int64_t>(BM, M - i0);  // rows of the tile inside C
+  const int jN = (int)min<int64_t>(BN, N - j0);
+  const int la = (int)lda, lb = (int)ldb;
+
+  v4d acc[4][4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
+
+  double ra[L], rb[L];
+  bool a_row = TA;  // pattern of the A slice in ra
+
+  // (rows, k) slice of a matrix X read column-wise: element (i, k) at
+  // X0 + i + k ld, i < ni valid rows, k < nk valid k.
+  auto load_col = [&](double* r, const double* X0, int ld, int ni, int nk) {
+    const __amdgpu_buffer_rsrc_t rs = rsrc_of(X0);
+    if (ni == 128 && nk == BK) {
+      const int v = (cp_i + cp_k * ld) * 8;
+#pragma unroll
+      for (int q = 0; q < L; ++q) r[q] = bld(rs, v, q * 2 * ld * 8);
+    } else {
+      const int ci = min(cp_i, ni - 1);
+#pragma unroll
+      for (int q = 0; q < L; ++q) {
+        const int k = cp_k + 2 * q;
+        const double x = bld(rs, (ci + min(k, nk - 1) * ld) * 8, 0);
+        r[q] = k < nk ? x : 0.0;
+      }
+    }
+  };
+  // the same slice read row-wise: element (i, k) at X0 + k + i ld
+  auto load_row = [&](double* r, const double* X0, int ld, int ni, int nk) {
+    const __amdgpu_buffer_rsrc_t rs = rsrc_of(X0);
+    if (ni == 128 && nk == BK) {
+      const int v = (rp_k + rp_i * ld) * 8;
+#pragma unroll
+      for (int q = 0; q < L; ++q) r[q] = bld(rs, v, q * 16 * ld * 8);
+    } else {
+      const int ck = min(rp_k, nk - 1);
+#pragma unroll
+      for (int q = 0; q < L; ++q) {
+        const int i = min(rp_i + 16 * q, ni - 1);
+        const double x = bld(rs, (ck + i * ld) * 8, 0);
+        r[q] = rp_k < nk ? x : 0.0;
+      }
+    }
+  };
+  auto load = [&](int64_t kt) {
+    const int nk = (int)min<int64_t>(BK, ke - kt);
+    if constexpr (SYM) {
+      if (kt + BK - 1 <= i0) {  // below the diagonal
+        a_row = false;
+        load_col(ra, A + i0 + kt * lda, la, iM, nk);
+      } else if (kt >= i0 + BM - 1) {  // above it: A(k, i)
+        a_row = true;
+        load_row(ra, A + kt + i0 * lda, la, iM, nk);
+      } else {  // crossing it: per element, from the corner b = min(i0, kt)
+        a_row = false;
+        const int64_t b = min(i0, kt);
+        const __amdgpu_buffer_rsrc_t rs = rsrc_of(A + b + b * lda);
+        const int gi = (int)(i0 - b) + min(cp_i, iM - 1);
+#pragma unroll
+        for (int q = 0; q < L; ++q) {
+          const int k = cp_k + 2 * q;
+          const int gk = (int)(kt - b) + min(k, nk - 1);
+          const int rr = gi >= gk ? gi : gk, cc = gi >= gk ? gk : gi;
+          const double x = bld(rs, (rr + cc * la) * 8, 0);
+          ra[q] = k < nk ? x : 0.0;
+        }
+      }
+    } else if constexpr (TA) {
+      load_row(ra, A + kt + i0 * lda, la, iM, nk);
+    } else {
+      load_col(ra, A + i0 + kt * lda, la, iM, nk);
+    }
+    if constexpr (TB) load_col(rb, B + j0 + kt * ldb, lb, jN, nk);
+    else load_row(rb, B + kt + j0 * ldb, lb, jN, nk);
+  };
+  auto store = [&](int buf) {
+    if (a_row) {
+#pragma unroll
+      for (int q = 0; q < L; ++q) As[buf][rp_k][rp_i + 16 * q] = ra[q];
+    } else {
+#pragma unroll
+      for (int q = 0; q < L; ++q) As[buf][cp_k + 2 * q][cp_i] = ra[q];
+    }
+    if constexpr (TB) {
+#pragma unroll
+      for (int q = 0; q < L; ++q) Bs[buf][cp_k + 2 * q][cp_i] = rb[q];
+    } else {
+#pragma unroll
+      for (int q = 0; q < L; ++q) Bs[buf][rp_k][rp_i + 16 * q] = rb[q];
+    }
+  };
+
+  if (ke > kb) {
+    load(kb);
+    store(0);
+    __syncthreads();
+    int cur = 0;
+    for (int64_t kt = kb; kt < ke; kt += BK) {
+      const bool more = kt + BK < ke;
+      if (more) load(kt + BK);
+#pragma unroll
+      for (int kk = 0; kk < BK / 4; ++kk) {
+        double av[4], bv[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) av[x] = As[cur][kk * 4 + lk][wm0 + x * 16 + lr];
+#pragma unroll
+        for (int y = 0; y < 4; ++y) bv[y] = Bs[cur][kk * 4 + lk][wn0 + y * 16 + lr];
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int y = 0; y < 4; ++y)
+            acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[y], av[x], acc[x][y], 0, 0, 0);
+      }
+      if (more) store(cur ^ 1);
+      __syncthreads();
+      cur ^= 1;
+    }
+  }
+
+  // Epilogue: lane l holds C(i0 + wm0 + 16x + lr, j0 + wn0 + 16y + lk + 4q).
+  const __amdgpu_buffer_rsrc_t rc = rsrc_of(C + i0 + j0 * ldc);
+  const int lc = (int)ldc;
+  const int vc = ((wm0 + lr) + (wn0 + lk) * lc) * 8;
+  const double alpha = a.alpha, beta = a.beta;
+  const bool full = iM == BM && jN == BN && (!a.lower || i0 >= j0 + BN - 1);
+  if (full) {
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      double cv[4][4];
+      if (beta != 0.0) {
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) cv[y][q] = bld(rc, vc, (x * 16 + (y * 16 + 4 * q) * lc) * 8);
+      }
+#pragma unroll
+      for (int y = 0; y < 4; ++y)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          double v = alpha * acc[x][y][q];
+          if (beta != 0.0) v += beta * cv[y][q];
+          bst(v, rc, vc, (x * 16 + (y * 16 + 4 * q) * lc) * 8);
+        }
+    }
+    return;
+  }
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int li = wm0 + x * 16 + lr, lj = wn0 + y * 16 + lk + 4 * q;
+        if (li < iM && lj < jN && (!a.lower || i0 + li >= j0 + lj)) {
+          const int off = (li + lj * lc) * 8;
+          double v = alpha * acc[x][y][q];
+          if (beta != 0.0) v += beta * bld(rc, off, 0);
+          bst(v, rc, off, 0);
+        }
+      }
+}
+
 // C = beta C + sum_z W_z, in a fixed order (deterministic split-K).
 __global__ void splitk_reduce(int64_t M, int64_t N, int splits, const double* W,
                               double beta, double* C, int64_t ldc, int lower) {
@@ -384,8 +607,8 @@ void gemm(const Gemm& g, hipStream_t stream, double* ws, int64_t ws_elems) {
   ka.lower = g.lower; ka.a_lower = g.a_lower; ka.a_upper = g.a_upper;
   ka.b_lower = g.b_lower; ka.b_band = g.b_band;
   ka.a_sym = g.a_sym;
-  MM_REQUIRE(!g.a_sym || (!g.ta && !g.a_lower && !g.a_upper && g.m == g.k), kInvalid,
-             "gemm: a_sym takes A untransposed and without triangle flags");
+  MM_REQUIRE(!g.a_sym || (!g.ta && !g.tb && !g.a_lower && !g.a_upper && g.m == g.k), kInvalid,
+             "gemm: a_sym takes A and B untransposed and no triangle flags for A");
   ka.sA = g.sA; ka.sB = g.sB; ka.sC = g.sC;
   ka.splits = 1; ka.ws = nullptr; ka.groups = nullptr;
   if (g.k <= 0) {
@@ -409,6 +632,24 @@ void gemm(const Gemm& g, hipStream_t stream, double* ws, int64_t ws_elems) {
   }
   ka.splits = splits;
   ka.ws = splits > 1 ? ws : nullptr;
+  // 128 x 128 tiles: both output sides at least a tile, no split-K, and
+  // 32-bit byte offsets across 256 rows or columns of every operand
+  const int64_t ldmax = std::max(std::max(g.lda, g.ldb), g.ldc);
+  if (big && splits == 1 && g.m >= 128 && g.n >= 128 && ldmax * 256 * 8 < ((int64_t)1 << 31)) {
+    ka.tiles_m = (int)ceil_div(g.m, 128);
+    ka.tiles_n = (int)ceil_div(g.n, 128);
+    const int64_t t128 = (int64_t)ka.tiles_m * ka.tiles_n;
+    ka.ch_log2 = chunk_log2(t128);
+    dim3 grid128((unsigned)padded_tiles(t128, ka.ch_log2), (unsigned)g.batch, 1);
+    const dim3 block(256);
+    if (g.a_sym) hipLaunchKernelGGL((gemm128_kernel<false, false, true>), grid128, block, 0, stream, ka);
+    else if (!g.ta && !g.tb) hipLaunchKernelGGL((gemm128_kernel<false, false, false>), grid128, block, 0, stream, ka);
+    else if (!g.ta && g.tb) hipLaunchKernelGGL((gemm128_kernel<false, true, false>), grid128, block, 0, stream, ka);
+    else if (g.ta && !g.tb) hipLaunchKernelGGL((gemm128_kernel<true, false, false>), grid128, block, 0, stream, ka);
+    else hipLaunchKernelGGL((gemm128_kernel<true, true, false>), grid128, block, 0, stream, ka);
+    MM_HIP_TRY(hipGetLastError());
+    return;
+  }
   dim3 grid((unsigned)wgs, (unsigned)g.batch, (unsigned)splits);
   if (big) launch<Big::BM, Big::BN, Big::WGM, Big::WGN, false>(ka, g.ta, g.tb, grid, stream);
   else launch<64, 64, 2, 2, false>(ka, g.ta, g.tb, grid, stream);

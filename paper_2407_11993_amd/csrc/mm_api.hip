@@ -1091,6 +1091,29 @@ mm_status mmk_dgemm(int32_t ta, int32_t tb, int64_t m, int64_t n, int64_t k, dou
   });
 }
 
+mm_status mmk_dgemm_tri(int32_t ta, int32_t tb, int64_t m, int64_t n, int64_t k, double alpha,
+                        const double* A, int64_t lda, const double* B, int64_t ldb,
+                        double beta, double* C, int64_t ldc, int32_t flags, int64_t b_band,
+                        void* stream) {
+  return guarded(nullptr, [&] {
+    MM_REQUIRE(m >= 0 && n >= 0 && k >= 0, kInvalid, "negative size");
+    MM_REQUIRE(ldc >= std::max<int64_t>(1, m), kInvalid, "ldc");
+    MM_REQUIRE((flags & ~15) == 0 && b_band >= -1, kInvalid, "flags or b_band");
+    Gemm g;
+    g.m = m; g.n = n; g.k = k; g.alpha = alpha; g.beta = beta;
+    g.A = A; g.lda = lda; g.ta = ta != 0;
+    g.B = B; g.ldb = ldb; g.tb = tb != 0;
+    g.C = C; g.ldc = ldc;
+    g.lower = (flags & MMK_LOWER) != 0;
+    g.a_lower = (flags & MMK_A_LOWER) != 0;
+    g.a_upper = (flags & MMK_A_UPPER) != 0;
+    g.b_lower = (flags & MMK_B_LOWER) != 0;
+    g.b_band = b_band;
+    gemm(g, (hipStream_t)stream);
+    MM_HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  });
+}
+
 mm_status mmk_dsymm_lower(int64_t m, int64_t n, double alpha, const double* A, int64_t lda,
                           const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
                           void* stream) {

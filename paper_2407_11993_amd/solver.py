@@ -199,6 +199,25 @@ class _Kernels:
                                         _lib.stream_handle()))
         return Cc.t()
 
+    def gemm_tri(self, A, B, trans_a=False, trans_b=False, alpha=1.0, beta=0.0, C=None,
+                 flags=0, b_band=-1):
+        """gemm with structure flags (MMK_LOWER, MMK_A_LOWER, MMK_A_UPPER, MMK_B_LOWER)
+        and a band of op(B); the zero parts must be stored as zeros."""
+        A = _dev(A)
+        B = _dev(B)
+        opA = A.t() if trans_a else A
+        opB = B.t() if trans_b else B
+        m, k = opA.shape
+        n = opB.shape[1]
+        Ac, Bc = self._cm(A), self._cm(B)
+        Cc = self._cm(_dev(C)) if C is not None else torch.zeros(n, m, dtype=torch.float64,
+                                                                 device=A.device)
+        _lib.check(_lib.lib().mmk_dgemm_tri(int(trans_a), int(trans_b), m, n, k, float(alpha),
+                                            _lib.ptr(Ac), A.shape[0], _lib.ptr(Bc), B.shape[0],
+                                            float(beta), _lib.ptr(Cc), max(1, m), int(flags),
+                                            int(b_band), _lib.stream_handle()))
+        return Cc.t()
+
     def symm_lower(self, A, B, alpha=1.0, beta=0.0, C=None):
         """alpha A B + beta C with A symmetric; only A's lower triangle is read."""
         A = _dev(A)

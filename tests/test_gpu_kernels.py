@@ -49,6 +49,37 @@ def test_gemm(K, m, n, k, ta, tb):
     assert np.abs(out - ref).max() <= 1e-15 * scale * 4
 
 
+MMK_LOWER, MMK_A_LOWER, MMK_A_UPPER, MMK_B_LOWER = 1, 2, 4, 8
+
+
+# the structure flags on both tile sizes (2100 x 2200 uses 128 x 128 tiles)
+@pytest.mark.parametrize("m,n,k", [(300, 260, 280), (2100, 2200, 2150)])
+@pytest.mark.parametrize("ta,tb", [(False, False), (False, True), (True, False)])
+@pytest.mark.parametrize("flags,b_band", [(MMK_LOWER, -1), (MMK_A_LOWER, -1), (MMK_A_UPPER, -1),
+                                          (MMK_B_LOWER, -1), (0, 40),
+                                          (MMK_LOWER | MMK_A_LOWER, 70)])
+def test_gemm_tri(K, m, n, k, ta, tb, flags, b_band):
+    rng = np.random.default_rng(m + n + k + flags + b_band)
+    opA = rng.standard_normal((m, k))
+    opB = rng.standard_normal((k, n))
+    if flags & MMK_A_LOWER:
+        opA = np.tril(opA)
+    if flags & MMK_A_UPPER:
+        opA = np.triu(opA)
+    if flags & MMK_B_LOWER:
+        opB = np.tril(opB)
+    if b_band >= 0:
+        opB = np.triu(opB, -b_band)
+    C0 = rng.standard_normal((m, n))
+    ref = 0.5 * (opA @ opB) - 2.0 * C0
+    if flags & MMK_LOWER:
+        ref = np.where(np.tril(np.ones((m, n), dtype=bool)), ref, C0)
+    out = _np(K.gemm_tri(opA.T.copy() if ta else opA, opB.T.copy() if tb else opB, ta, tb,
+                         alpha=0.5, beta=-2.0, C=C0, flags=flags, b_band=b_band))
+    scale = np.abs(opA).max() * np.abs(opB).max() * k + 2 * np.abs(C0).max()
+    assert np.abs(out - ref).max() <= 1e-15 * scale * 4
+
+
 @pytest.mark.parametrize("m,n", [(1, 1), (5, 3), (130, 70), (257, 129), (2100, 2100),
                                  (4096, 1030)])
 def test_symm_lower(K, m, n):
@@ -64,7 +95,8 @@ def test_symm_lower(K, m, n):
     assert np.abs(out - ref).max() <= 1e-15 * scale * 4
 
 
-@pytest.mark.parametrize("n", [1, 5, 128, 129, 300, 513])
+# 2600: the trailing updates run on 128 x 128 tiles (lower output, B transposed)
+@pytest.mark.parametrize("n", [1, 5, 128, 129, 300, 513, 2600])
 def test_potrf(K, n):
     A = _spd(n, n)
     G, info = K.potrf(A)
@@ -82,7 +114,8 @@ def test_potrf_reports_pivot(K):
     assert info == 150
 
 
-@pytest.mark.parametrize("n", [1, 100, 128, 129, 300, 700])
+# 4300: the top-level products run on 128 x 128 tiles (triangular operands)
+@pytest.mark.parametrize("n", [1, 100, 128, 129, 300, 700, 4300])
 def test_trtri(K, n):
     G = np.linalg.cholesky(_spd(n, n + 11))
     Gi = _np(K.trtri(G))
