@@ -340,14 +340,16 @@ __global__ void __launch_bounds__(64 * WGM * WGN)
 
 // ---------------------------------------------------------------------------
 // Large tiles: 128 x 128 per workgroup of four waves, 64 x 64 per wave (16
-// MFMA accumulators, so each operand value read from LDS feeds four MFMAs).
+// MFMA accumulators, so each operand value read from LDS feeds four MFMAs),
+// or 128 x 64 with 64 x 32 per wave for products with at most 64 columns.
 // Every operand and C access is a buffer instruction on a uniform base (the
 // slice's or the tile's corner) with one 32-bit per-lane offset and a uniform
 // per-element offset, so that addresses take no 64-bit vector registers.
 // Interior slices load unguarded; edge slices clamp their addresses to the
 // matrix and zero the entries at k >= ke.
 //
-// Load patterns of one 128 x 16 slice (256 threads, 8 elements each):
+// Load patterns of one 128 x 16 slice (256 threads, 8 elements each; a
+// 64 x 16 slice of B likewise with 4):
 //   column pattern: thread t holds row t%128 of k = t/128 + 2r (r < 8);
 //   row pattern:    thread t holds k = t%16 of row t/16 + 16r.
 // op(A) untransposed and op(B) transposed are read column-wise, the others
@@ -368,10 +370,72 @@ __device__ __forceinline__ void bst(double v, __amdgpu_buffer_rsrc_t r, int voff
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
 }
 
-template <bool TA, bool TB, bool SYM>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
-    gemm128_kernel(KArgs a) {
-  constexpr int BM = 128, BN = 128, L = 8;
+// An R x 16 slice (R = 128 or 64) of a matrix X read column-wise by 256
+// threads: element (i, k) at X0 + i + k ld; thread t holds i = t % R of
+// k = t / R + (256 / R) q.  ni valid rows, nk valid k (the rest clamped and,
+// past nk, zeroed).
+template <int R>
+__device__ __forceinline__ void load_col(double* r, const double* X0, int ld, int ni, int nk,
+                                         int t) {
+  constexpr int S = 256 / R, NL = R / 16;
+  const __amdgpu_buffer_rsrc_t rs = rsrc_of(X0);
+  const int ci0 = t % R, ck0 = t / R;
+  if (ni == R && nk == BK) {
+    const int v = (ci0 + ck0 * ld) * 8;
+#pragma unroll
+    for (int q = 0; q < NL; ++q) r[q] = bld(rs, v, q * S * ld * 8);
+  } else {
+    const int ci = min(ci0, ni - 1);
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int k = ck0 + S * q;
+      const double x = bld(rs, (ci + min(k, nk - 1) * ld) * 8, 0);
+      r[q] = k < nk ? x : 0.0;
+    }
+  }
+}
+// The same slice read row-wise: element (i, k) at X0 + k + i ld; thread t
+// holds k = t % 16 of row t / 16 + 16 q.
+template <int R>
+__device__ __forceinline__ void load_row(double* r, const double* X0, int ld, int ni, int nk,
+                                         int t) {
+  constexpr int NL = R / 16;
+  const __amdgpu_buffer_rsrc_t rs = rsrc_of(X0);
+  const int rk = t & 15, ri = t >> 4;
+  if (ni == R && nk == BK) {
+    const int v = (rk + ri * ld) * 8;
+#pragma unroll
+    for (int q = 0; q < NL; ++q) r[q] = bld(rs, v, q * 16 * ld * 8);
+  } else {
+    const int ck = min(rk, nk - 1);
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int i = min(ri + 16 * q, ni - 1);
+      const double x = bld(rs, (ck + i * ld) * 8, 0);
+      r[q] = rk < nk ? x : 0.0;
+    }
+  }
+}
+// LDS image S[k][i] of a slice held in the column or the row pattern
+template <int R>
+__device__ __forceinline__ void store_col(double (*S)[R + PAD], const double* r, int t) {
+  constexpr int ST = 256 / R, NL = R / 16;
+#pragma unroll
+  for (int q = 0; q < NL; ++q) S[t / R + ST * q][t % R] = r[q];
+}
+template <int R>
+__device__ __forceinline__ void store_row(double (*S)[R + PAD], const double* r, int t) {
+  constexpr int NL = R / 16;
+#pragma unroll
+  for (int q = 0; q < NL; ++q) S[t & 15][(t >> 4) + 16 * q] = r[q];
+}
+
+// BN = 128: four waves of 64 x 64 (two workgroups per CU); BN = 64: four
+// waves of 64 x 32 (three per CU), for products with at most 64 columns.
+template <int BN, bool TA, bool TB, bool SYM>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BN == 64 ? 3 : 2)))
+    gemm_big_kernel(KArgs a) {
+  constexpr int BM = 128, FN = BN / 32, LA = BM / 16, LB = BN / 16;
   __shared__ double As[2][BK][BM + PAD];
   __shared__ double Bs[2][BK][BN + PAD];
   const int64_t M = a.m, N = a.n, K = a.k, lda = a.lda, ldb = a.ldb, ldc = a.ldc;
@@ -391,75 +455,38 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
   kb = (kb / BK) * BK;
 
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int wm0 = (wave & 1) * 64, wn0 = (wave >> 1) * 64;
+  const int wm0 = (wave & 1) * 64, wn0 = (wave >> 1) * (BN / 2);
   const int lr = lane & 15, lk = lane >> 4;
-  const int cp_i = t & 127, cp_k = t >> 7;  // column pattern: (cp_i, cp_k + 2r)
-  const int rp_k = t & 15, rp_i = t >> 4;   // row pattern: (rp_i + 16r, rp_k)
   const int iM = (int)min<int64_t>(BM, M - i0);  // rows of the tile inside C
   const int jN = (int)min<int64_t>(BN, N - j0);
   const int la = (int)lda, lb = (int)ldb;
 
-  v4d acc[4][4];
+  v4d acc[4][FN];
 #pragma unroll
   for (int x = 0; x < 4; ++x)
 #pragma unroll
-    for (int y = 0; y < 4; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int y = 0; y < FN; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
 
-  double ra[L], rb[L];
+  double ra[LA], rb[LB];
   bool a_row = TA;  // pattern of the A slice in ra
 
-  // (rows, k) slice of a matrix X read column-wise: element (i, k) at
-  // X0 + i + k ld, i < ni valid rows, k < nk valid k.
-  auto load_col = [&](double* r, const double* X0, int ld, int ni, int nk) {
-    const __amdgpu_buffer_rsrc_t rs = rsrc_of(X0);
-    if (ni == 128 && nk == BK) {
-      const int v = (cp_i + cp_k * ld) * 8;
-#pragma unroll
-      for (int q = 0; q < L; ++q) r[q] = bld(rs, v, q * 2 * ld * 8);
-    } else {
-      const int ci = min(cp_i, ni - 1);
-#pragma unroll
-      for (int q = 0; q < L; ++q) {
-        const int k = cp_k + 2 * q;
-        const double x = bld(rs, (ci + min(k, nk - 1) * ld) * 8, 0);
-        r[q] = k < nk ? x : 0.0;
-      }
-    }
-  };
-  // the same slice read row-wise: element (i, k) at X0 + k + i ld
-  auto load_row = [&](double* r, const double* X0, int ld, int ni, int nk) {
-    const __amdgpu_buffer_rsrc_t rs = rsrc_of(X0);
-    if (ni == 128 && nk == BK) {
-      const int v = (rp_k + rp_i * ld) * 8;
-#pragma unroll
-      for (int q = 0; q < L; ++q) r[q] = bld(rs, v, q * 16 * ld * 8);
-    } else {
-      const int ck = min(rp_k, nk - 1);
-#pragma unroll
-      for (int q = 0; q < L; ++q) {
-        const int i = min(rp_i + 16 * q, ni - 1);
-        const double x = bld(rs, (ck + i * ld) * 8, 0);
-        r[q] = rp_k < nk ? x : 0.0;
-      }
-    }
-  };
   auto load = [&](int64_t kt) {
     const int nk = (int)min<int64_t>(BK, ke - kt);
     if constexpr (SYM) {
       if (kt + BK - 1 <= i0) {  // below the diagonal
         a_row = false;
-        load_col(ra, A + i0 + kt * lda, la, iM, nk);
+        load_col<BM>(ra, A + i0 + kt * lda, la, iM, nk, t);
       } else if (kt >= i0 + BM - 1) {  // above it: A(k, i)
         a_row = true;
-        load_row(ra, A + kt + i0 * lda, la, iM, nk);
+        load_row<BM>(ra, A + kt + i0 * lda, la, iM, nk, t);
       } else {  // crossing it: per element, from the corner b = min(i0, kt)
         a_row = false;
         const int64_t b = min(i0, kt);
         const __amdgpu_buffer_rsrc_t rs = rsrc_of(A + b + b * lda);
-        const int gi = (int)(i0 - b) + min(cp_i, iM - 1);
+        const int gi = (int)(i0 - b) + min(t & 127, iM - 1);
 #pragma unroll
-        for (int q = 0; q < L; ++q) {
-          const int k = cp_k + 2 * q;
+        for (int q = 0; q < LA; ++q) {
+          const int k = (t >> 7) + 2 * q;
           const int gk = (int)(kt - b) + min(k, nk - 1);
           const int rr = gi >= gk ? gi : gk, cc = gi >= gk ? gk : gi;
           const double x = bld(rs, (rr + cc * la) * 8, 0);
@@ -467,28 +494,18 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
         }
       }
     } else if constexpr (TA) {
-      load_row(ra, A + kt + i0 * lda, la, iM, nk);
+      load_row<BM>(ra, A + kt + i0 * lda, la, iM, nk, t);
     } else {
-      load_col(ra, A + i0 + kt * lda, la, iM, nk);
+      load_col<BM>(ra, A + i0 + kt * lda, la, iM, nk, t);
     }
-    if constexpr (TB) load_col(rb, B + j0 + kt * ldb, lb, jN, nk);
-    else load_row(rb, B + kt + j0 * ldb, lb, jN, nk);
+    if constexpr (TB) load_col<BN>(rb, B + j0 + kt * ldb, lb, jN, nk, t);
+    else load_row<BN>(rb, B + kt + j0 * ldb, lb, jN, nk, t);
   };
   auto store = [&](int buf) {
-    if (a_row) {
-#pragma unroll
-      for (int q = 0; q < L; ++q) As[buf][rp_k][rp_i + 16 * q] = ra[q];
-    } else {
-#pragma unroll
-      for (int q = 0; q < L; ++q) As[buf][cp_k + 2 * q][cp_i] = ra[q];
-    }
-    if constexpr (TB) {
-#pragma unroll
-      for (int q = 0; q < L; ++q) Bs[buf][cp_k + 2 * q][cp_i] = rb[q];
-    } else {
-#pragma unroll
-      for (int q = 0; q < L; ++q) Bs[buf][rp_k][rp_i + 16 * q] = rb[q];
-    }
+    if (a_row) store_row<BM>(As[buf], ra, t);
+    else store_col<BM>(As[buf], ra, t);
+    if constexpr (TB) store_col<BN>(Bs[buf], rb, t);
+    else store_row<BN>(Bs[buf], rb, t);
   };
 
   if (ke > kb) {
@@ -501,15 +518,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
       if (more) load(kt + BK);
 #pragma unroll
       for (int kk = 0; kk < BK / 4; ++kk) {
-        double av[4], bv[4];
+        double av[4], bv[FN];
 #pragma unroll
         for (int x = 0; x < 4; ++x) av[x] = As[cur][kk * 4 + lk][wm0 + x * 16 + lr];
 #pragma unroll
-        for (int y = 0; y < 4; ++y) bv[y] = Bs[cur][kk * 4 + lk][wn0 + y * 16 + lr];
+        for (int y = 0; y < FN; ++y) bv[y] = Bs[cur][kk * 4 + lk][wn0 + y * 16 + lr];
 #pragma unroll
         for (int x = 0; x < 4; ++x)
 #pragma unroll
-          for (int y = 0; y < 4; ++y)
+          for (int y = 0; y < FN; ++y)
             acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[y], av[x], acc[x][y], 0, 0, 0);
       }
       if (more) store(cur ^ 1);
@@ -527,15 +544,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
   if (full) {
 #pragma unroll
     for (int x = 0; x < 4; ++x) {
-      double cv[4][4];
+      double cv[FN][4];
       if (beta != 0.0) {
 #pragma unroll
-        for (int y = 0; y < 4; ++y)
+        for (int y = 0; y < FN; ++y)
 #pragma unroll
           for (int q = 0; q < 4; ++q) cv[y][q] = bld(rc, vc, (x * 16 + (y * 16 + 4 * q) * lc) * 8);
       }
 #pragma unroll
-      for (int y = 0; y < 4; ++y)
+      for (int y = 0; y < FN; ++y)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           double v = alpha * acc[x][y][q];
@@ -548,7 +565,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 #pragma unroll
   for (int x = 0; x < 4; ++x)
 #pragma unroll
-    for (int y = 0; y < 4; ++y)
+    for (int y = 0; y < FN; ++y)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int li = wm0 + x * 16 + lr, lj = wn0 + y * 16 + lk + 4 * q;
@@ -559,6 +576,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
           bst(v, rc, off, 0);
         }
       }
+}
+
+template <int BN>
+void launch_big(const KArgs& ka, bool ta, bool tb, bool sym, dim3 grid, hipStream_t s) {
+  const dim3 block(256);
+  if (sym) hipLaunchKernelGGL((gemm_big_kernel<BN, false, false, true>), grid, block, 0, s, ka);
+  else if (!ta && !tb) hipLaunchKernelGGL((gemm_big_kernel<BN, false, false, false>), grid, block, 0, s, ka);
+  else if (!ta && tb) hipLaunchKernelGGL((gemm_big_kernel<BN, false, true, false>), grid, block, 0, s, ka);
+  else if (ta && !tb) hipLaunchKernelGGL((gemm_big_kernel<BN, true, false, false>), grid, block, 0, s, ka);
+  else hipLaunchKernelGGL((gemm_big_kernel<BN, true, true, false>), grid, block, 0, s, ka);
 }
 
 // C = beta C + sum_z W_z, in a fixed order (deterministic split-K).
@@ -632,21 +659,22 @@ void gemm(const Gemm& g, hipStream_t stream, double* ws, int64_t ws_elems) {
   }
   ka.splits = splits;
   ka.ws = splits > 1 ? ws : nullptr;
-  // 128 x 128 tiles: both output sides at least a tile, no split-K, and
-  // 32-bit byte offsets across 256 rows or columns of every operand
+  // 128-row tiles (128 x 128, or 128 x 64 for at most 64 columns): no
+  // split-K, at least a million outputs, and 32-bit byte offsets across 256
+  // rows or columns of every operand
   const int64_t ldmax = std::max(std::max(g.lda, g.ldb), g.ldc);
-  if (big && splits == 1 && g.m >= 128 && g.n >= 128 && ldmax * 256 * 8 < ((int64_t)1 << 31)) {
+  if (splits == 1 && g.m >= 128 && g.n >= 64 && g.m * g.n >= ((int64_t)1 << 20) &&
+      ldmax * 256 * 8 < ((int64_t)1 << 31)) {
+    // 128 x 64 also for short updates (k <= 256): three workgroups per CU
+    // overlap one another's C traffic better (3 % faster at k = 128)
+    const int bnb = (g.n <= 64 || g.k <= 256) ? 64 : 128;
     ka.tiles_m = (int)ceil_div(g.m, 128);
-    ka.tiles_n = (int)ceil_div(g.n, 128);
-    const int64_t t128 = (int64_t)ka.tiles_m * ka.tiles_n;
-    ka.ch_log2 = chunk_log2(t128);
-    dim3 grid128((unsigned)padded_tiles(t128, ka.ch_log2), (unsigned)g.batch, 1);
-    const dim3 block(256);
-    if (g.a_sym) hipLaunchKernelGGL((gemm128_kernel<false, false, true>), grid128, block, 0, stream, ka);
-    else if (!g.ta && !g.tb) hipLaunchKernelGGL((gemm128_kernel<false, false, false>), grid128, block, 0, stream, ka);
-    else if (!g.ta && g.tb) hipLaunchKernelGGL((gemm128_kernel<false, true, false>), grid128, block, 0, stream, ka);
-    else if (g.ta && !g.tb) hipLaunchKernelGGL((gemm128_kernel<true, false, false>), grid128, block, 0, stream, ka);
-    else hipLaunchKernelGGL((gemm128_kernel<true, true, false>), grid128, block, 0, stream, ka);
+    ka.tiles_n = (int)ceil_div(g.n, bnb);
+    const int64_t tb = (int64_t)ka.tiles_m * ka.tiles_n;
+    ka.ch_log2 = chunk_log2(tb);
+    const dim3 gb((unsigned)padded_tiles(tb, ka.ch_log2), (unsigned)g.batch, 1);
+    if (bnb == 64) launch_big<64>(ka, g.ta, g.tb, g.a_sym, gb, stream);
+    else launch_big<128>(ka, g.ta, g.tb, g.a_sym, gb, stream);
     MM_HIP_TRY(hipGetLastError());
     return;
   }

@@ -193,9 +193,10 @@ __global__ void form_t(const double* S, const double* tau, int nb, double* T) {
 int64_t sy2sb_ws_elems(int64_t n, int nb) {
   const int64_t G = ceil_div(n, QROWS);
   const int64_t stride = nb + 1;
-  // scratch (2 (G stride + nb)) + V|Y|V (n x 3nb) + X (n x nb) + small (4 nb^2)
-  // + split-K partials (8 n nb)
-  return 2 * (G * stride + nb) + n * 3 * nb + n * nb + 4 * (int64_t)nb * nb + 8 * n * nb;
+  // scratch (2 (G stride + nb)) + V|Y|V (n x 3nb) + X (n x nb) + small (6 nb^2)
+  // + the pair buffer W (n x 6nb) + split-K partials (8 n nb)
+  return 2 * (G * stride + nb) + n * 3 * nb + n * nb + 6 * (int64_t)nb * nb + n * 6 * nb +
+         8 * n * nb;
 }
 
 int64_t sy2sb_npanels(int64_t n, int nb) {
@@ -204,95 +205,188 @@ int64_t sy2sb_npanels(int64_t n, int nb) {
   return p;
 }
 
+namespace {
+
+struct Sy2sbWs {
+  double* part;
+  double* X;      // n x nb
+  double* Sm;     // nb x nb
+  double* Pm;     // nb x nb
+  double* Zm;     // nb x nb
+  double* S2;     // 2nb x nb
+  double* split;  // split-K partials
+  int64_t split_elems;
+};
+
+// Householder QR of the m x nb panel P (ld lda): R over its top block, the
+// reflectors below; V (unit diagonal, ld m) written to V1 and V2, T formed.
+void qr_panel(double* P, int64_t lda, int64_t m, int nb, double* tau, double* T, double* V1,
+              double* V2, const Sy2sbWs& w, hipStream_t s) {
+  const int G = (int)ceil_div(m, QROWS);
+  for (int c = 0; c <= nb; ++c)
+    hipLaunchKernelGGL(panel_qr_step, dim3(G), dim3(QT), 0, s, P, lda, m, nb, c, w.part, G, tau);
+  MM_HIP_TRY(hipGetLastError());
+  const dim3 gv((unsigned)ceil_div(m * nb, 256));
+  hipLaunchKernelGGL(extract_v, gv, dim3(256), 0, s, P, lda, m, nb, V1);
+  hipLaunchKernelGGL(extract_v, gv, dim3(256), 0, s, P, lda, m, nb, V2);
+  MM_HIP_TRY(hipGetLastError());
+  Gemm gs;  // S = V^T V
+  gs.m = nb; gs.n = nb; gs.k = m;
+  gs.A = V1; gs.lda = m; gs.ta = true;
+  gs.B = V1; gs.ldb = m;
+  gs.C = w.Sm; gs.ldc = nb;
+  gemm(gs, s, w.split, w.split_elems);
+  hipLaunchKernelGGL(form_t, dim3(1), dim3(128), 0, s, w.Sm, tau, nb, T);
+  MM_HIP_TRY(hipGetLastError());
+}
+
+// X = A22 V (A22 m x m symmetric, lower triangle stored) into w.X
+void sym_times_v(const double* A22, int64_t lda, int64_t m, int nb, const double* V,
+                 const Sy2sbWs& w, hipStream_t s) {
+  Gemm g;
+  g.m = m; g.n = nb; g.k = m;
+  g.A = A22; g.lda = lda; g.a_sym = true;
+  g.B = V; g.ldb = m;
+  g.C = w.X; g.ldc = m;
+  gemm(g, s, w.split, w.split_elems);
+}
+
+// Y = X T - 1/2 V (T^T V^T X T)  (the two-sided update is A22 - V Y^T - Y V^T)
+void form_y(const double* V, const double* T, int64_t m, int nb, double* Y, const Sy2sbWs& w,
+            hipStream_t s) {
+  Gemm g2;  // Y = X T  (T upper: op(B)(k,j) = 0 for k > j)
+  g2.m = m; g2.n = nb; g2.k = nb;
+  g2.A = w.X; g2.lda = m;
+  g2.B = T; g2.ldb = nb; g2.b_band = 0;
+  g2.C = Y; g2.ldc = m;
+  gemm(g2, s);
+  Gemm g3;  // Pm = V^T Y
+  g3.m = nb; g3.n = nb; g3.k = m;
+  g3.A = V; g3.lda = m; g3.ta = true;
+  g3.B = Y; g3.ldb = m;
+  g3.C = w.Pm; g3.ldc = nb;
+  gemm(g3, s, w.split, w.split_elems);
+  Gemm g4;  // Zm = T^T Pm
+  g4.m = nb; g4.n = nb; g4.k = nb;
+  g4.A = T; g4.lda = nb; g4.ta = true;
+  g4.B = w.Pm; g4.ldb = nb;
+  g4.C = w.Zm; g4.ldc = nb;
+  gemm(g4, s);
+  Gemm g5;  // Y -= 1/2 V Zm
+  g5.m = m; g5.n = nb; g5.k = nb;
+  g5.alpha = -0.5; g5.beta = 1.0;
+  g5.A = V; g5.lda = m;
+  g5.B = w.Zm; g5.ldb = nb;
+  g5.C = Y; g5.ldc = m;
+  gemm(g5, s);
+}
+
+// A -= U1 U2^T on the lower triangle (m x m, U1 and U2 m x k, ld m)
+void lower_update(double* A, int64_t lda, int64_t m, int64_t k, const double* U1,
+                  const double* U2, hipStream_t s) {
+  Gemm g;
+  g.m = m; g.n = m; g.k = k;
+  g.alpha = -1.0; g.beta = 1.0;
+  g.A = U1; g.lda = m;
+  g.B = U2; g.ldb = m; g.tb = true;
+  g.C = A; g.ldc = lda;
+  g.lower = true;
+  gemm(g, s);
+}
+
+}  // namespace
+
+// Panels are taken in pairs.  For panels 1 (columns j.., rows r0 = j+nb..) and
+// 2 (the next nb columns, rows r0+nb..): panel 1 is factored and its Y1 formed
+// as for a single panel; only panel 2's columns receive panel 1's update
+// before panel 2 is factored; panel 2's product with the once-updated
+// trailing matrix A33' = A33 - V1b Y1b^T - Y1b V1b^T (V1b, Y1b: V1, Y1 below
+// their first nb rows) is formed from the not-yet-updated A33 as
+//   A33' V2 = A33 V2 - [V1b Y1b] ([Y1b V1b]^T V2);
+// then both updates are applied to A33 at once, as one rank-4nb update
+//   A33 -= [V1b V2 Y1b Y2] [Y1b Y2 V1b V2]^T,
+// with the operands two windows of W = [V1b V2 Y1b Y2 V1b V2] (k = 4nb
+// instead of two passes over A33 with k = 2nb).
 void sy2sb(double* A, int64_t lda, int64_t n, int nb, double* tau_all, double* T_all,
            double* ws, int64_t ws_elems, hipStream_t s) {
   MM_REQUIRE(nb >= 1 && nb <= MAXNB, kInvalid, "sy2sb: band must be 1..64");
   MM_REQUIRE(ws_elems >= sy2sb_ws_elems(n, nb), kInvalid, "sy2sb: workspace too small");
   const int64_t Gmax = ceil_div(n, QROWS);
   const int stride = nb + 1;
-  double* part = ws;
-  double* VYV = part + 2 * (Gmax * stride + nb);  // n x 3nb
-  double* X = VYV + n * 3 * nb;                // n x nb
-  double* Sm = X + n * nb;                     // nb x nb
-  double* Pm = Sm + (int64_t)nb * nb;          // nb x nb
-  double* Zm = Pm + (int64_t)nb * nb;          // nb x nb
-  double* split = Zm + 2 * (int64_t)nb * nb;   // split-K workspace
-  const int64_t split_elems = 8 * n * nb;
+  Sy2sbWs w;
+  w.part = ws;
+  double* VYV = w.part + 2 * (Gmax * stride + nb);  // n x 3nb
+  w.X = VYV + n * 3 * nb;                            // n x nb
+  w.Sm = w.X + n * nb;
+  w.Pm = w.Sm + (int64_t)nb * nb;
+  w.Zm = w.Pm + (int64_t)nb * nb;
+  w.S2 = w.Zm + 2 * (int64_t)nb * nb;                // 2nb x nb
+  double* W = w.S2 + 2 * (int64_t)nb * nb;           // n x 6nb
+  w.split = W + n * 6 * nb;
+  w.split_elems = 8 * n * nb;
   int64_t p = 0;
-  for (int64_t j = 0; j + nb < n - 1; j += nb, ++p) {
+  for (int64_t j = 0; j + nb < n - 1;) {
     const int64_t r0 = j + nb;
     const int64_t m = n - r0;
-    double* P = A + r0 + j * lda;
-    double* tau = tau_all + p * nb;
-    double* T = T_all + p * (int64_t)nb * nb;
-    const int G = (int)ceil_div(m, QROWS);
-    for (int c = 0; c <= nb; ++c)
-      hipLaunchKernelGGL(panel_qr_step, dim3(G), dim3(QT), 0, s, P, lda, m, nb, c, part,
-                         G, tau);
-    MM_HIP_TRY(hipGetLastError());
-    // V, the Gram matrix and T
-    double* V = VYV;                 // columns 0..nb-1
-    double* Y = VYV + m * nb;        // columns nb..2nb-1
-    double* V2 = VYV + 2 * m * nb;   // columns 2nb..3nb-1
-    hipLaunchKernelGGL(extract_v, dim3((unsigned)ceil_div(m * nb, 256)), dim3(256), 0, s,
-                       P, lda, m, nb, V);
-    hipLaunchKernelGGL(extract_v, dim3((unsigned)ceil_div(m * nb, 256)), dim3(256), 0, s,
-                       P, lda, m, nb, V2);
-    MM_HIP_TRY(hipGetLastError());
-    Gemm gs;  // S = V^T V
-    gs.m = nb; gs.n = nb; gs.k = m;
-    gs.A = V; gs.lda = m; gs.ta = true;
-    gs.B = V; gs.ldb = m;
-    gs.C = Sm; gs.ldc = nb;
-    gemm(gs, s, split, split_elems);
-    hipLaunchKernelGGL(form_t, dim3(1), dim3(128), 0, s, Sm, tau, nb, T);
-    MM_HIP_TRY(hipGetLastError());
     double* A22 = A + r0 + r0 * lda;
-    // X0 = A22 V  (m x nb; A22 symmetric, lower triangle stored)
-    Gemm g1;
-    g1.m = m; g1.n = nb; g1.k = m;
-    g1.A = A22; g1.lda = lda; g1.a_sym = true;
-    g1.B = V; g1.ldb = m;
-    g1.C = X; g1.ldc = m;
-    gemm(g1, s, split, split_elems);
-    // Y = X0 T  (T upper: op(B)(k,j) = 0 for k > j)
-    Gemm g2;
-    g2.m = m; g2.n = nb; g2.k = nb;
-    g2.A = X; g2.lda = m;
-    g2.B = T; g2.ldb = nb; g2.b_band = 0;
-    g2.C = Y; g2.ldc = m;
-    gemm(g2, s);
-    // Pm = V^T Y   (nb x nb)
-    Gemm g3;
-    g3.m = nb; g3.n = nb; g3.k = m;
-    g3.A = V; g3.lda = m; g3.ta = true;
-    g3.B = Y; g3.ldb = m;
-    g3.C = Pm; g3.ldc = nb;
-    gemm(g3, s, split, split_elems);
-    // Zm = T^T Pm
-    Gemm g4;
-    g4.m = nb; g4.n = nb; g4.k = nb;
-    g4.A = T; g4.lda = nb; g4.ta = true;
-    g4.B = Pm; g4.ldb = nb;
-    g4.C = Zm; g4.ldc = nb;
-    gemm(g4, s);
-    // Y -= 1/2 V Zm
-    Gemm g5;
-    g5.m = m; g5.n = nb; g5.k = nb;
-    g5.alpha = -0.5; g5.beta = 1.0;
-    g5.A = V; g5.lda = m;
-    g5.B = Zm; g5.ldb = nb;
-    g5.C = Y; g5.ldc = m;
-    gemm(g5, s);
-    // A22 -= [V Y] [Y V]^T  (lower triangle)
-    Gemm g6;
-    g6.m = m; g6.n = m; g6.k = 2 * nb;
-    g6.alpha = -1.0; g6.beta = 1.0;
-    g6.A = VYV; g6.lda = m;
-    g6.B = VYV + m * nb; g6.ldb = m; g6.tb = true;
-    g6.C = A22; g6.ldc = lda;
-    g6.lower = true;
-    gemm(g6, s);
+    double* V = VYV;               // columns 0..nb-1
+    double* Y = VYV + m * nb;      // columns nb..2nb-1 (then V again)
+    qr_panel(A + r0 + j * lda, lda, m, nb, tau_all + p * nb, T_all + p * (int64_t)nb * nb, V,
+             VYV + 2 * m * nb, w, s);
+    sym_times_v(A22, lda, m, nb, V, w, s);
+    form_y(V, T_all + p * (int64_t)nb * nb, m, nb, Y, w, s);
+    // a second panel follows, with more than nb + 1 rows
+    const bool pair = j + 3 * nb < n - 1;
+    if (!pair) {
+      lower_update(A22, lda, m, 2 * nb, VYV, VYV + m * nb, s);  // [V Y] [Y V]^T
+      j += nb;
+      ++p;
+      continue;
+    }
+    // panel 2's columns (the first nb of A22) get panel 1's update
+    {
+      Gemm g;
+      g.m = m; g.n = nb; g.k = 2 * nb;
+      g.alpha = -1.0; g.beta = 1.0;
+      g.A = VYV; g.lda = m;              // [V Y]
+      g.B = VYV + m * nb; g.ldb = m;     // [Y V], rows 0..nb-1
+      g.tb = true;
+      g.C = A22; g.ldc = lda;
+      gemm(g, s);
+    }
+    const int64_t m2 = m - nb;
+    double* A33 = A22 + nb + nb * lda;
+    double* W0 = W;                  // V1b
+    double* W1 = W + m2 * nb;        // V2
+    double* W2 = W + 2 * m2 * nb;    // Y1b
+    double* W3 = W + 3 * m2 * nb;    // Y2
+    double* W4 = W + 4 * m2 * nb;    // V1b
+    double* W5 = W + 5 * m2 * nb;    // V2
+    double* T2 = T_all + (p + 1) * (int64_t)nb * nb;
+    qr_panel(A22 + nb, lda, m2, nb, tau_all + (p + 1) * nb, T2, W1, W5, w, s);
+    sym_times_v(A33, lda, m2, nb, W1, w, s);
+    {
+      Gemm g;  // S2 = [Y1b V1b]^T V2   (2nb x nb)
+      g.m = 2 * nb; g.n = nb; g.k = m2;
+      g.A = VYV + m * nb + nb; g.lda = m; g.ta = true;
+      g.B = W1; g.ldb = m2;
+      g.C = w.S2; g.ldc = 2 * nb;
+      gemm(g, s, w.split, w.split_elems);
+      Gemm h;  // X2 -= [V1b Y1b] S2
+      h.m = m2; h.n = nb; h.k = 2 * nb;
+      h.alpha = -1.0; h.beta = 1.0;
+      h.A = VYV + nb; h.lda = m;
+      h.B = w.S2; h.ldb = 2 * nb;
+      h.C = w.X; h.ldc = m2;
+      gemm(h, s);
+    }
+    form_y(W1, T2, m2, nb, W3, w, s);
+    copy_matrix(VYV + nb, m, W0, m2, m2, nb, s);           // V1b
+    copy_matrix(VYV + nb, m, W4, m2, m2, nb, s);           // V1b
+    copy_matrix(VYV + m * nb + nb, m, W2, m2, m2, nb, s);  // Y1b
+    lower_update(A33, lda, m2, 4 * nb, W0, W2, s);         // [V1b V2 Y1b Y2] [Y1b Y2 V1b V2]^T
+    j += 2 * nb;
+    p += 2;
   }
 }
 

@@ -36,7 +36,8 @@ def _spd(n, seed):
 
 
 @pytest.mark.parametrize("m,n,k", [(1, 1, 1), (17, 33, 5), (130, 70, 200),
-                                   (257, 129, 64), (64, 64, 4096), (2100, 2100, 300)])
+                                   (257, 129, 64), (64, 64, 4096), (2100, 2100, 300),
+                                   (16500, 61, 300)])
 @pytest.mark.parametrize("ta,tb", [(False, False), (True, False), (False, True), (True, True)])
 def test_gemm(K, m, n, k, ta, tb):
     rng = np.random.default_rng(m * 7 + n * 3 + k)
@@ -53,7 +54,7 @@ MMK_LOWER, MMK_A_LOWER, MMK_A_UPPER, MMK_B_LOWER = 1, 2, 4, 8
 
 
 # the structure flags on both tile sizes (2100 x 2200 uses 128 x 128 tiles)
-@pytest.mark.parametrize("m,n,k", [(300, 260, 280), (2100, 2200, 2150)])
+@pytest.mark.parametrize("m,n,k", [(300, 260, 280), (2100, 2200, 2150), (16500, 64, 1100)])
 @pytest.mark.parametrize("ta,tb", [(False, False), (False, True), (True, False)])
 @pytest.mark.parametrize("flags,b_band", [(MMK_LOWER, -1), (MMK_A_LOWER, -1), (MMK_A_UPPER, -1),
                                           (MMK_B_LOWER, -1), (0, 40),
@@ -81,7 +82,7 @@ def test_gemm_tri(K, m, n, k, ta, tb, flags, b_band):
 
 
 @pytest.mark.parametrize("m,n", [(1, 1), (5, 3), (130, 70), (257, 129), (2100, 2100),
-                                 (4096, 1030)])
+                                 (4096, 1030), (16400, 64)])
 def test_symm_lower(K, m, n):
     """The upper triangle of A holds NaN: a read of it would show in C."""
     rng = np.random.default_rng(m + 5 * n)
@@ -133,7 +134,10 @@ def _band_dense(AB, n, nb):
     return B
 
 
-@pytest.mark.parametrize("n,nb", [(3, 1), (70, 16), (200, 64), (333, 64), (129, 32)])
+# panels are reduced in pairs (an odd count ends with a single one); 2600 runs
+# the updates on 128-row tiles
+@pytest.mark.parametrize("n,nb", [(3, 1), (70, 16), (200, 64), (333, 64), (129, 32),
+                                  (140, 16), (2600, 64)])
 def test_sy2sb_preserves_spectrum(K, n, nb):
     A = _sym(n, n + nb)
     AB = _np(K.sy2sb(A, nb))
