@@ -108,11 +108,14 @@ def test_potrf(K, n):
     assert np.abs(G @ G.T - A).max() < 1e-13 * np.abs(A).max() * max(1, np.sqrt(n))
 
 
-def test_potrf_reports_pivot(K):
-    A = _spd(200, 1)
-    A[150, 150] = -5.0
+# diagonal blocks are factored in pairs: the first failing pivot is reported
+# from either block of a pair
+@pytest.mark.parametrize("n,piv", [(200, 150), (400, 100), (400, 150), (400, 300)])
+def test_potrf_reports_pivot(K, n, piv):
+    A = _spd(n, 1)
+    A[piv, piv] = -5.0
     _, info = K.potrf(A)
-    assert info == 150
+    assert info == piv
 
 
 # 4300: the top-level products run on 128 x 128 tiles (triangular operands)
