@@ -80,7 +80,8 @@ struct EigWork {
   double* ws = nullptr;
   int64_t ws_elems = 0;
 };
-// C (full symmetric, destroyed: it keeps the stage-1 reflectors) -> lam, Q.
+// C (symmetric, only its lower triangle read; destroyed: it keeps the stage-1
+// reflectors) -> lam, Q.
 void syevd(double* C, int64_t ldc, int64_t n, double* lam, double* Q, int64_t ldq,
            const EigWork& w, const Sb2stPlan& plan, int64_t* d_status, hipStream_t s);
 // Eigenvalues and Q^T Y for a few columns Y (n x ny, ny <= sb2st_max_cols()),

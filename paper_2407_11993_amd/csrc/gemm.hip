@@ -453,6 +453,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BN == 
   if (a.a_upper) kb = max(kb, i0);
   if (a.b_lower) kb = max(kb, j0);
   kb = (kb / BK) * BK;
+  if (a.splits > 1) {  // this workgroup's share of k (blockIdx.z)
+    const int64_t span = ke > kb ? ke - kb : 0;
+    const int64_t chunk = ceil_div(ceil_div(span, a.splits), BK) * BK;
+    const int64_t s0 = kb + (int64_t)blockIdx.z * chunk;
+    kb = s0;
+    ke = min(ke, s0 + chunk);
+  }
 
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm0 = (wave & 1) * 64, wn0 = (wave >> 1) * (BN / 2);
@@ -536,10 +543,24 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BN == 
   }
 
   // Epilogue: lane l holds C(i0 + wm0 + 16x + lr, j0 + wn0 + 16y + lk + 4q).
+  const double alpha = a.alpha, beta = a.beta;
+  if (a.splits > 1) {  // partial sums W_z (M x N, ld M), reduced afterwards
+    const __amdgpu_buffer_rsrc_t rw = rsrc_of(a.ws + (int64_t)blockIdx.z * M * N + i0 + j0 * M);
+    const int lm = (int)M;
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < FN; ++y)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int li = wm0 + x * 16 + lr, lj = wn0 + y * 16 + lk + 4 * q;
+          if (li < iM && lj < jN) bst(alpha * acc[x][y][q], rw, (li + lj * lm) * 8, 0);
+        }
+    return;
+  }
   const __amdgpu_buffer_rsrc_t rc = rsrc_of(C + i0 + j0 * ldc);
   const int lc = (int)ldc;
   const int vc = ((wm0 + lr) + (wn0 + lk) * lc) * 8;
-  const double alpha = a.alpha, beta = a.beta;
   const bool full = iM == BM && jN == BN && (!a.lower || i0 >= j0 + BN - 1);
   if (full) {
 #pragma unroll
@@ -659,11 +680,11 @@ void gemm(const Gemm& g, hipStream_t stream, double* ws, int64_t ws_elems) {
   }
   ka.splits = splits;
   ka.ws = splits > 1 ? ws : nullptr;
-  // 128-row tiles (128 x 128, or 128 x 64 for at most 64 columns): no
-  // split-K, at least a million outputs, and 32-bit byte offsets across 256
-  // rows or columns of every operand
-  const int64_t ldmax = std::max(std::max(g.lda, g.ldb), g.ldc);
-  if (splits == 1 && g.m >= 128 && g.n >= 64 && g.m * g.n >= ((int64_t)1 << 20) &&
+  // 128-row tiles (128 x 128, or 128 x 64 for at most 64 columns): at least
+  // a million outputs, and 32-bit byte offsets across 256 rows or columns of
+  // every operand (and of the split-K partials)
+  const int64_t ldmax = std::max(std::max(std::max(g.lda, g.ldb), g.ldc), g.m);
+  if (g.m >= 128 && g.n >= 64 && g.m * g.n >= ((int64_t)1 << 20) &&
       ldmax * 256 * 8 < ((int64_t)1 << 31)) {
     // 128 x 64 also for short updates (k <= 256): three workgroups per CU
     // overlap one another's C traffic better (3 % faster at k = 128)
@@ -671,11 +692,29 @@ void gemm(const Gemm& g, hipStream_t stream, double* ws, int64_t ws_elems) {
     ka.tiles_m = (int)ceil_div(g.m, 128);
     ka.tiles_n = (int)ceil_div(g.n, bnb);
     const int64_t tb = (int64_t)ka.tiles_m * ka.tiles_n;
+    // split-K when a long-k product has fewer tiles than two rounds of
+    // resident workgroups (three 128 x 64 or two 128 x 128 per CU): tall,
+    // narrow products with k = m, such as the band reduction's A22 V
+    const int64_t slots = bnb == 64 ? 768 : 512;
+    int sp = 1;
+    if (ws && g.batch == 1 && g.k >= 4096 && tb < 2 * slots) {
+      sp = (int)std::min<int64_t>(std::min<int64_t>(ceil_div(2 * slots, tb), g.k / 2048),
+                                  std::min<int64_t>(ws_elems / (g.m * g.n), 8));
+      if (sp < 2) sp = 1;
+    }
+    ka.splits = sp;
+    ka.ws = sp > 1 ? ws : nullptr;
     ka.ch_log2 = chunk_log2(tb);
-    const dim3 gb((unsigned)padded_tiles(tb, ka.ch_log2), (unsigned)g.batch, 1);
+    const dim3 gb((unsigned)padded_tiles(tb, ka.ch_log2), (unsigned)g.batch, (unsigned)sp);
     if (bnb == 64) launch_big<64>(ka, g.ta, g.tb, g.a_sym, gb, stream);
     else launch_big<128>(ka, g.ta, g.tb, g.a_sym, gb, stream);
     MM_HIP_TRY(hipGetLastError());
+    if (sp > 1) {
+      const int64_t total = g.m * g.n;
+      hipLaunchKernelGGL(splitk_reduce, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, stream,
+                         g.m, g.n, sp, ws, g.beta, g.C, g.ldc, (int)g.lower);
+      MM_HIP_TRY(hipGetLastError());
+    }
     return;
   }
   dim3 grid((unsigned)wgs, (unsigned)g.batch, (unsigned)splits);

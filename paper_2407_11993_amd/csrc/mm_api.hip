@@ -444,14 +444,18 @@ void decompose_impl(mm_ctx* c, bool project) {
     c->Q.alloc(sizeof(double) * n0 * n0);  // W = G^{-1} R here, later the eigenvectors
     double* Q = c->Q.d();
     dense_times_csr(G, n0, c->R(), Q, n0, s);
-    Cb.alloc(sizeof(double) * n0 * n0);
+    // C's columns start on 128-byte boundaries (n0 is odd at the electrode
+    // plates): the band reduction reads C's lower triangle also row-wise, in
+    // 128-byte pieces of many columns, which would otherwise straddle lines
+    const int64_t ldC = ceil_div(n0, 16) * 16;
+    Cb.alloc(sizeof(double) * ldC * n0);
     double* C = Cb.d();
     {
       Gemm g;
       g.m = n0; g.n = n0; g.k = n0;
       g.A = G; g.lda = n0; g.a_lower = true;
       g.B = Q; g.ldb = n0; g.tb = true; g.b_band = c->band;
-      g.C = C; g.ldc = n0;
+      g.C = C; g.ldc = ldC;
       g.lower = true;
       gemm(g, s);
     }
@@ -475,12 +479,11 @@ void decompose_impl(mm_ctx* c, bool project) {
       g.alpha = -1.0; g.beta = 1.0;
       g.A = ABA.d(); g.lda = n0;
       g.B = ABA.d() + (int64_t)m * n0; g.ldb = n0; g.tb = true;
-      g.C = C; g.ldc = n0;
+      g.C = C; g.ldc = ldC;
       g.lower = true;
       gemm(g, s);
       MM_HIP_TRY(hipStreamSynchronize(s));  // ABA is released here
     }
-    symmetrize_from_lower(C, n0, n0, s);
     // G^{-1} applied to the forcing columns and the probe weights, side by side
     double* GF = GFP.d();
     double* GP = GFP.d() + (int64_t)c->nf * n0;
@@ -524,12 +527,12 @@ void decompose_impl(mm_ctx* c, bool project) {
     fill_i64(st + 1, 1, 0, s);
     if (project) {
       // a4-a8 without Q: [W, Pt] = Z^T Q2^T Q1^T G^{-1} [F, P]
-      syevd_project(C, n0, n0, c->lam.d(), GFP.d(), n0, ny, ZY.d(), n0, w, plan, st + 1, s);
+      syevd_project(C, ldC, n0, c->lam.d(), GFP.d(), n0, ny, ZY.d(), n0, w, plan, st + 1, s);
       if (c->nf > 0) copy_matrix(ZY.d(), n0, c->Wm.d(), n0, n0, c->nf, s);
       copy_matrix(ZY.d() + (int64_t)c->nf * n0, n0, c->Pm.d(), n0, n0, c->n_probe, s);
       MM_HIP_TRY(hipStreamSynchronize(s));  // ZY is released here
     } else {
-      syevd(C, n0, n0, c->lam.d(), Q, n0, w, plan, st + 1, s);
+      syevd(C, ldC, n0, c->lam.d(), Q, n0, w, plan, st + 1, s);
       // a8: modal weights  W = Q^T G^{-1} F,  Pt = Q^T G^{-1} P
       if (c->nf > 0) {
         Gemm g;
@@ -1126,7 +1129,10 @@ mm_status mmk_dsymm_lower(int64_t m, int64_t n, double alpha, const double* A, i
     g.A = A; g.lda = lda; g.a_sym = true;
     g.B = B; g.ldb = ldb;
     g.C = C; g.ldc = ldc;
-    gemm(g, (hipStream_t)stream);
+    Dev ws;  // split-K partials for tall, narrow products
+    const int64_t wse = 8 * std::max<int64_t>(1, m * n);
+    if (m >= 4096 && m * n <= ((int64_t)1 << 24)) ws.alloc(sizeof(double) * wse);
+    gemm(g, (hipStream_t)stream, ws.p ? ws.d() : nullptr, ws.p ? wse : 0);
     MM_HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
   });
 }

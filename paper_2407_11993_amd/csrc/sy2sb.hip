@@ -154,8 +154,9 @@ __global__ void __launch_bounds__(QT) panel_qr_step(double* P, int64_t ldp, int6
   if (t < ncol) po[t] = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
 }
 
-// Explicit V (m x nb, column-major, ld m) from the stored reflectors.
-__global__ void extract_v(const double* P, int64_t ldp, int64_t m, int nb, double* V) {
+// Explicit V (m x nb, column-major, ld ldv) from the stored reflectors.
+__global__ void extract_v(const double* P, int64_t ldp, int64_t m, int nb, double* V,
+                          int64_t ldv) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= m * nb) return;
   const int64_t i = e % m;
@@ -163,7 +164,7 @@ __global__ void extract_v(const double* P, int64_t ldp, int64_t m, int nb, doubl
   double v = 0.0;
   if (i == c) v = 1.0;
   else if (i > c) v = P[i + (int64_t)c * ldp];
-  V[e] = v;
+  V[i + c * ldv] = v;
 }
 
 // T (nb x nb, upper) from tau and the Gram matrix S = V^T V:
@@ -190,12 +191,17 @@ __global__ void form_t(const double* S, const double* tau, int nb, double* T) {
 
 }  // namespace
 
+// Leading dimension of the panel buffers: columns start on 128-byte
+// boundaries (the products read them row-wise in 128-byte pieces).
+static inline int64_t ld16(int64_t m) { return ceil_div(m, 16) * 16; }
+
 int64_t sy2sb_ws_elems(int64_t n, int nb) {
   const int64_t G = ceil_div(n, QROWS);
   const int64_t stride = nb + 1;
-  // scratch (2 (G stride + nb)) + V|Y|V (n x 3nb) + X (n x nb) + small (6 nb^2)
-  // + the pair buffer W (n x 6nb) + split-K partials (8 n nb)
-  return 2 * (G * stride + nb) + n * 3 * nb + n * nb + 6 * (int64_t)nb * nb + n * 6 * nb +
+  const int64_t np = ld16(n);
+  // scratch (2 (G stride + nb)) + V|Y|V (np x 3nb) + X (np x nb) + small
+  // (6 nb^2) + the pair buffer W (np x 6nb) + split-K partials (8 n nb)
+  return 2 * (G * stride + nb) + np * 3 * nb + np * nb + 6 * (int64_t)nb * nb + np * 6 * nb +
          8 * n * nb;
 }
 
@@ -219,51 +225,51 @@ struct Sy2sbWs {
 };
 
 // Householder QR of the m x nb panel P (ld lda): R over its top block, the
-// reflectors below; V (unit diagonal, ld m) written to V1 and V2, T formed.
+// reflectors below; V (unit diagonal, ld ldv) written to V1 and V2, T formed.
 void qr_panel(double* P, int64_t lda, int64_t m, int nb, double* tau, double* T, double* V1,
-              double* V2, const Sy2sbWs& w, hipStream_t s) {
+              double* V2, int64_t ldv, const Sy2sbWs& w, hipStream_t s) {
   const int G = (int)ceil_div(m, QROWS);
   for (int c = 0; c <= nb; ++c)
     hipLaunchKernelGGL(panel_qr_step, dim3(G), dim3(QT), 0, s, P, lda, m, nb, c, w.part, G, tau);
   MM_HIP_TRY(hipGetLastError());
   const dim3 gv((unsigned)ceil_div(m * nb, 256));
-  hipLaunchKernelGGL(extract_v, gv, dim3(256), 0, s, P, lda, m, nb, V1);
-  hipLaunchKernelGGL(extract_v, gv, dim3(256), 0, s, P, lda, m, nb, V2);
+  hipLaunchKernelGGL(extract_v, gv, dim3(256), 0, s, P, lda, m, nb, V1, ldv);
+  hipLaunchKernelGGL(extract_v, gv, dim3(256), 0, s, P, lda, m, nb, V2, ldv);
   MM_HIP_TRY(hipGetLastError());
   Gemm gs;  // S = V^T V
   gs.m = nb; gs.n = nb; gs.k = m;
-  gs.A = V1; gs.lda = m; gs.ta = true;
-  gs.B = V1; gs.ldb = m;
+  gs.A = V1; gs.lda = ldv; gs.ta = true;
+  gs.B = V1; gs.ldb = ldv;
   gs.C = w.Sm; gs.ldc = nb;
   gemm(gs, s, w.split, w.split_elems);
   hipLaunchKernelGGL(form_t, dim3(1), dim3(128), 0, s, w.Sm, tau, nb, T);
   MM_HIP_TRY(hipGetLastError());
 }
 
-// X = A22 V (A22 m x m symmetric, lower triangle stored) into w.X
+// X = A22 V (A22 m x m symmetric, lower triangle stored) into w.X (ld ldv)
 void sym_times_v(const double* A22, int64_t lda, int64_t m, int nb, const double* V,
-                 const Sy2sbWs& w, hipStream_t s) {
+                 int64_t ldv, const Sy2sbWs& w, hipStream_t s) {
   Gemm g;
   g.m = m; g.n = nb; g.k = m;
   g.A = A22; g.lda = lda; g.a_sym = true;
-  g.B = V; g.ldb = m;
-  g.C = w.X; g.ldc = m;
+  g.B = V; g.ldb = ldv;
+  g.C = w.X; g.ldc = ldv;
   gemm(g, s, w.split, w.split_elems);
 }
 
 // Y = X T - 1/2 V (T^T V^T X T)  (the two-sided update is A22 - V Y^T - Y V^T)
-void form_y(const double* V, const double* T, int64_t m, int nb, double* Y, const Sy2sbWs& w,
-            hipStream_t s) {
+void form_y(const double* V, const double* T, int64_t m, int nb, double* Y, int64_t ldv,
+            const Sy2sbWs& w, hipStream_t s) {
   Gemm g2;  // Y = X T  (T upper: op(B)(k,j) = 0 for k > j)
   g2.m = m; g2.n = nb; g2.k = nb;
-  g2.A = w.X; g2.lda = m;
+  g2.A = w.X; g2.lda = ldv;
   g2.B = T; g2.ldb = nb; g2.b_band = 0;
-  g2.C = Y; g2.ldc = m;
+  g2.C = Y; g2.ldc = ldv;
   gemm(g2, s);
   Gemm g3;  // Pm = V^T Y
   g3.m = nb; g3.n = nb; g3.k = m;
-  g3.A = V; g3.lda = m; g3.ta = true;
-  g3.B = Y; g3.ldb = m;
+  g3.A = V; g3.lda = ldv; g3.ta = true;
+  g3.B = Y; g3.ldb = ldv;
   g3.C = w.Pm; g3.ldc = nb;
   gemm(g3, s, w.split, w.split_elems);
   Gemm g4;  // Zm = T^T Pm
@@ -275,20 +281,20 @@ void form_y(const double* V, const double* T, int64_t m, int nb, double* Y, cons
   Gemm g5;  // Y -= 1/2 V Zm
   g5.m = m; g5.n = nb; g5.k = nb;
   g5.alpha = -0.5; g5.beta = 1.0;
-  g5.A = V; g5.lda = m;
+  g5.A = V; g5.lda = ldv;
   g5.B = w.Zm; g5.ldb = nb;
-  g5.C = Y; g5.ldc = m;
+  g5.C = Y; g5.ldc = ldv;
   gemm(g5, s);
 }
 
-// A -= U1 U2^T on the lower triangle (m x m, U1 and U2 m x k, ld m)
+// A -= U1 U2^T on the lower triangle (m x m, U1 and U2 m x k, ld ldu)
 void lower_update(double* A, int64_t lda, int64_t m, int64_t k, const double* U1,
-                  const double* U2, hipStream_t s) {
+                  const double* U2, int64_t ldu, hipStream_t s) {
   Gemm g;
   g.m = m; g.n = m; g.k = k;
   g.alpha = -1.0; g.beta = 1.0;
-  g.A = U1; g.lda = m;
-  g.B = U2; g.ldb = m; g.tb = true;
+  g.A = U1; g.lda = ldu;
+  g.B = U2; g.ldb = ldu; g.tb = true;
   g.C = A; g.ldc = lda;
   g.lower = true;
   gemm(g, s);
@@ -315,30 +321,32 @@ void sy2sb(double* A, int64_t lda, int64_t n, int nb, double* tau_all, double* T
   const int stride = nb + 1;
   Sy2sbWs w;
   w.part = ws;
-  double* VYV = w.part + 2 * (Gmax * stride + nb);  // n x 3nb
-  w.X = VYV + n * 3 * nb;                            // n x nb
-  w.Sm = w.X + n * nb;
+  const int64_t np = ld16(n);
+  double* VYV = w.part + 2 * (Gmax * stride + nb);  // np x 3nb
+  w.X = VYV + np * 3 * nb;                           // np x nb
+  w.Sm = w.X + np * nb;
   w.Pm = w.Sm + (int64_t)nb * nb;
   w.Zm = w.Pm + (int64_t)nb * nb;
   w.S2 = w.Zm + 2 * (int64_t)nb * nb;                // 2nb x nb
-  double* W = w.S2 + 2 * (int64_t)nb * nb;           // n x 6nb
-  w.split = W + n * 6 * nb;
+  double* W = w.S2 + 2 * (int64_t)nb * nb;           // np x 6nb
+  w.split = W + np * 6 * nb;
   w.split_elems = 8 * n * nb;
   int64_t p = 0;
   for (int64_t j = 0; j + nb < n - 1;) {
     const int64_t r0 = j + nb;
     const int64_t m = n - r0;
+    const int64_t mp = ld16(m);  // ld of [V Y V] and X
     double* A22 = A + r0 + r0 * lda;
     double* V = VYV;               // columns 0..nb-1
-    double* Y = VYV + m * nb;      // columns nb..2nb-1 (then V again)
+    double* Y = VYV + mp * nb;     // columns nb..2nb-1 (then V again)
     qr_panel(A + r0 + j * lda, lda, m, nb, tau_all + p * nb, T_all + p * (int64_t)nb * nb, V,
-             VYV + 2 * m * nb, w, s);
-    sym_times_v(A22, lda, m, nb, V, w, s);
-    form_y(V, T_all + p * (int64_t)nb * nb, m, nb, Y, w, s);
+             VYV + 2 * mp * nb, mp, w, s);
+    sym_times_v(A22, lda, m, nb, V, mp, w, s);
+    form_y(V, T_all + p * (int64_t)nb * nb, m, nb, Y, mp, w, s);
     // a second panel follows, with more than nb + 1 rows
     const bool pair = j + 3 * nb < n - 1;
     if (!pair) {
-      lower_update(A22, lda, m, 2 * nb, VYV, VYV + m * nb, s);  // [V Y] [Y V]^T
+      lower_update(A22, lda, m, 2 * nb, VYV, VYV + mp * nb, mp, s);  // [V Y] [Y V]^T
       j += nb;
       ++p;
       continue;
@@ -348,43 +356,45 @@ void sy2sb(double* A, int64_t lda, int64_t n, int nb, double* tau_all, double* T
       Gemm g;
       g.m = m; g.n = nb; g.k = 2 * nb;
       g.alpha = -1.0; g.beta = 1.0;
-      g.A = VYV; g.lda = m;              // [V Y]
-      g.B = VYV + m * nb; g.ldb = m;     // [Y V], rows 0..nb-1
+      g.A = VYV; g.lda = mp;              // [V Y]
+      g.B = VYV + mp * nb; g.ldb = mp;    // [Y V], rows 0..nb-1
       g.tb = true;
       g.C = A22; g.ldc = lda;
       gemm(g, s);
     }
     const int64_t m2 = m - nb;
+    const int64_t m2p = ld16(m2);  // ld of W
     double* A33 = A22 + nb + nb * lda;
-    double* W0 = W;                  // V1b
-    double* W1 = W + m2 * nb;        // V2
-    double* W2 = W + 2 * m2 * nb;    // Y1b
-    double* W3 = W + 3 * m2 * nb;    // Y2
-    double* W4 = W + 4 * m2 * nb;    // V1b
-    double* W5 = W + 5 * m2 * nb;    // V2
+    double* W0 = W;                   // V1b
+    double* W1 = W + m2p * nb;        // V2
+    double* W2 = W + 2 * m2p * nb;    // Y1b
+    double* W3 = W + 3 * m2p * nb;    // Y2
+    double* W4 = W + 4 * m2p * nb;    // V1b
+    double* W5 = W + 5 * m2p * nb;    // V2
     double* T2 = T_all + (p + 1) * (int64_t)nb * nb;
-    qr_panel(A22 + nb, lda, m2, nb, tau_all + (p + 1) * nb, T2, W1, W5, w, s);
-    sym_times_v(A33, lda, m2, nb, W1, w, s);
+    qr_panel(A22 + nb, lda, m2, nb, tau_all + (p + 1) * nb, T2, W1, W5, m2p, w, s);
+    sym_times_v(A33, lda, m2, nb, W1, m2p, w, s);
     {
       Gemm g;  // S2 = [Y1b V1b]^T V2   (2nb x nb)
       g.m = 2 * nb; g.n = nb; g.k = m2;
-      g.A = VYV + m * nb + nb; g.lda = m; g.ta = true;
-      g.B = W1; g.ldb = m2;
+      g.A = VYV + mp * nb + nb; g.lda = mp; g.ta = true;
+      g.B = W1; g.ldb = m2p;
       g.C = w.S2; g.ldc = 2 * nb;
       gemm(g, s, w.split, w.split_elems);
       Gemm h;  // X2 -= [V1b Y1b] S2
       h.m = m2; h.n = nb; h.k = 2 * nb;
       h.alpha = -1.0; h.beta = 1.0;
-      h.A = VYV + nb; h.lda = m;
+      h.A = VYV + nb; h.lda = mp;
       h.B = w.S2; h.ldb = 2 * nb;
-      h.C = w.X; h.ldc = m2;
+      h.C = w.X; h.ldc = m2p;
       gemm(h, s);
     }
-    form_y(W1, T2, m2, nb, W3, w, s);
-    copy_matrix(VYV + nb, m, W0, m2, m2, nb, s);           // V1b
-    copy_matrix(VYV + nb, m, W4, m2, m2, nb, s);           // V1b
-    copy_matrix(VYV + m * nb + nb, m, W2, m2, m2, nb, s);  // Y1b
-    lower_update(A33, lda, m2, 4 * nb, W0, W2, s);         // [V1b V2 Y1b Y2] [Y1b Y2 V1b V2]^T
+    form_y(W1, T2, m2, nb, W3, m2p, w, s);
+    copy_matrix(VYV + nb, mp, W0, m2p, m2, nb, s);            // V1b
+    copy_matrix(VYV + nb, mp, W4, m2p, m2, nb, s);            // V1b
+    copy_matrix(VYV + mp * nb + nb, mp, W2, m2p, m2, nb, s);  // Y1b
+    // [V1b V2 Y1b Y2] [Y1b Y2 V1b V2]^T
+    lower_update(A33, lda, m2, 4 * nb, W0, W2, m2p, s);
     j += 2 * nb;
     p += 2;
   }

@@ -37,7 +37,7 @@ def _spd(n, seed):
 
 @pytest.mark.parametrize("m,n,k", [(1, 1, 1), (17, 33, 5), (130, 70, 200),
                                    (257, 129, 64), (64, 64, 4096), (2100, 2100, 300),
-                                   (16500, 61, 300)])
+                                   (16500, 61, 300), (16500, 64, 8192)])
 @pytest.mark.parametrize("ta,tb", [(False, False), (True, False), (False, True), (True, True)])
 def test_gemm(K, m, n, k, ta, tb):
     rng = np.random.default_rng(m * 7 + n * 3 + k)
