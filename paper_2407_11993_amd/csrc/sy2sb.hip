@@ -195,14 +195,16 @@ __global__ void form_t(const double* S, const double* tau, int nb, double* T) {
 // boundaries (the products read them row-wise in 128-byte pieces).
 static inline int64_t ld16(int64_t m) { return ceil_div(m, 16) * 16; }
 
+constexpr int GP = 4;  // panels per group
+
 int64_t sy2sb_ws_elems(int64_t n, int nb) {
   const int64_t G = ceil_div(n, QROWS);
   const int64_t stride = nb + 1;
   const int64_t np = ld16(n);
-  // scratch (2 (G stride + nb)) + V|Y|V (np x 3nb) + X (np x nb) + small
-  // (6 nb^2) + the pair buffer W (np x 6nb) + split-K partials (8 n nb)
-  return 2 * (G * stride + nb) + np * 3 * nb + np * nb + 6 * (int64_t)nb * nb + np * 6 * nb +
-         8 * n * nb;
+  // scratch (2 (G stride + nb)) + X (np x nb) + small (3 nb^2 + 2 GP nb^2)
+  // + U1, U2 (np x 2 GP nb each) + split-K partials (8 n nb)
+  return 2 * (G * stride + nb) + np * nb + (3 + 2 * GP) * (int64_t)nb * nb +
+         2 * np * 2 * GP * nb + 8 * n * nb;
 }
 
 int64_t sy2sb_npanels(int64_t n, int nb) {
@@ -219,7 +221,7 @@ struct Sy2sbWs {
   double* Sm;     // nb x nb
   double* Pm;     // nb x nb
   double* Zm;     // nb x nb
-  double* S2;     // 2nb x nb
+  double* S2;     // 2 (GP - 1) nb x nb
   double* split;  // split-K partials
   int64_t split_elems;
 };
@@ -302,17 +304,19 @@ void lower_update(double* A, int64_t lda, int64_t m, int64_t k, const double* U1
 
 }  // namespace
 
-// Panels are taken in pairs.  For panels 1 (columns j.., rows r0 = j+nb..) and
-// 2 (the next nb columns, rows r0+nb..): panel 1 is factored and its Y1 formed
-// as for a single panel; only panel 2's columns receive panel 1's update
-// before panel 2 is factored; panel 2's product with the once-updated
-// trailing matrix A33' = A33 - V1b Y1b^T - Y1b V1b^T (V1b, Y1b: V1, Y1 below
-// their first nb rows) is formed from the not-yet-updated A33 as
-//   A33' V2 = A33 V2 - [V1b Y1b] ([Y1b V1b]^T V2);
-// then both updates are applied to A33 at once, as one rank-4nb update
-//   A33 -= [V1b V2 Y1b Y2] [Y1b Y2 V1b V2]^T,
-// with the operands two windows of W = [V1b V2 Y1b Y2 V1b V2] (k = 4nb
-// instead of two passes over A33 with k = 2nb).
+// Panels are taken in groups of up to GP.  Panel t of a group (columns
+// j_t = j + (t-1) nb, rows R_t = [j_t + nb, n)) is reduced against the
+// trailing matrix A as it was at the start of the group, corrected for the
+// group's earlier panels s < t (whose updates A -= V_s Y_s^T + Y_s V_s^T are
+// not yet applied):
+//   * its columns (rows from j_t) receive those updates first;
+//   * its product with the updated trailing matrix is
+//       A'[R_t, R_t] V_t = A[R_t, R_t] V_t - U1[R_t] (U2[R_t]^T V_t),
+//     with U1 = [V_1 Y_1 V_2 Y_2 ...] and U2 = [Y_1 V_1 Y_2 V_2 ...];
+// and after the group's last panel q the trailing matrix A[R_q, R_q] receives
+// all the group's updates at once, A -= U1 U2^T with k = 2 q nb.  V_s and Y_s
+// are stored on the group's common rows [j + nb, n) from their own first row
+// (j + s nb) on: every product above reads them at or below that row.
 void sy2sb(double* A, int64_t lda, int64_t n, int nb, double* tau_all, double* T_all,
            double* ws, int64_t ws_elems, hipStream_t s) {
   MM_REQUIRE(nb >= 1 && nb <= MAXNB, kInvalid, "sy2sb: band must be 1..64");
@@ -322,81 +326,70 @@ void sy2sb(double* A, int64_t lda, int64_t n, int nb, double* tau_all, double* T
   Sy2sbWs w;
   w.part = ws;
   const int64_t np = ld16(n);
-  double* VYV = w.part + 2 * (Gmax * stride + nb);  // np x 3nb
-  w.X = VYV + np * 3 * nb;                           // np x nb
+  w.X = w.part + 2 * (Gmax * stride + nb);           // np x nb
   w.Sm = w.X + np * nb;
   w.Pm = w.Sm + (int64_t)nb * nb;
   w.Zm = w.Pm + (int64_t)nb * nb;
-  w.S2 = w.Zm + 2 * (int64_t)nb * nb;                // 2nb x nb
-  double* W = w.S2 + 2 * (int64_t)nb * nb;           // np x 6nb
-  w.split = W + np * 6 * nb;
+  w.S2 = w.Zm + (int64_t)nb * nb;                    // 2 (GP - 1) nb x nb
+  double* U1 = w.S2 + 2 * GP * (int64_t)nb * nb;     // np x 2 GP nb
+  double* U2 = U1 + np * 2 * GP * nb;                // np x 2 GP nb
+  w.split = U2 + np * 2 * GP * nb;
   w.split_elems = 8 * n * nb;
   int64_t p = 0;
   for (int64_t j = 0; j + nb < n - 1;) {
-    const int64_t r0 = j + nb;
-    const int64_t m = n - r0;
-    const int64_t mp = ld16(m);  // ld of [V Y V] and X
-    double* A22 = A + r0 + r0 * lda;
-    double* V = VYV;               // columns 0..nb-1
-    double* Y = VYV + mp * nb;     // columns nb..2nb-1 (then V again)
-    qr_panel(A + r0 + j * lda, lda, m, nb, tau_all + p * nb, T_all + p * (int64_t)nb * nb, V,
-             VYV + 2 * mp * nb, mp, w, s);
-    sym_times_v(A22, lda, m, nb, V, mp, w, s);
-    form_y(V, T_all + p * (int64_t)nb * nb, m, nb, Y, mp, w, s);
-    // a second panel follows, with more than nb + 1 rows
-    const bool pair = j + 3 * nb < n - 1;
-    if (!pair) {
-      lower_update(A22, lda, m, 2 * nb, VYV, VYV + mp * nb, mp, s);  // [V Y] [Y V]^T
-      j += nb;
-      ++p;
-      continue;
+    const int64_t m = n - (j + nb);  // rows of the group's first panel
+    const int64_t mp = ld16(m);      // ld of U1, U2 and X
+    // panels in this group: the next one joins while it has more than nb + 1 rows
+    int q = 1;
+    while (q < GP && j + (q + 2) * nb < n - 1) ++q;
+    for (int t = 1; t <= q; ++t) {
+      const int64_t jt = j + (t - 1) * nb;  // first column of panel t
+      const int64_t rt = jt + nb;           // first row of R_t
+      const int64_t mt = n - rt;
+      const int64_t off = (t - 1) * nb;     // R_t on the common rows
+      double* Tp = T_all + (p + t - 1) * (int64_t)nb * nb;
+      double* V1 = U1 + (2 * t - 2) * nb * mp + off;
+      double* Y1 = U1 + (2 * t - 1) * nb * mp + off;
+      double* Y2 = U2 + (2 * t - 2) * nb * mp + off;
+      double* V2 = U2 + (2 * t - 1) * nb * mp + off;
+      const int64_t kprev = 2 * (int64_t)(t - 1) * nb;
+      if (t > 1) {
+        // panel t's columns, rows [jt, n) (R_{t-1}), get the group's updates so far
+        Gemm g;
+        g.m = n - jt; g.n = nb; g.k = kprev;
+        g.alpha = -1.0; g.beta = 1.0;
+        g.A = U1 + off - nb; g.lda = mp;
+        g.B = U2 + off - nb; g.ldb = mp; g.tb = true;  // its first nb rows
+        g.C = A + jt + jt * lda; g.ldc = lda;
+        gemm(g, s);
+      }
+      qr_panel(A + rt + jt * lda, lda, mt, nb, tau_all + (p + t - 1) * nb, Tp, V1, V2, mp, w, s);
+      sym_times_v(A + rt + rt * lda, lda, mt, nb, V1, mp, w, s);
+      if (t > 1) {
+        Gemm g;  // S2 = U2[R_t]^T V_t   (kprev x nb)
+        g.m = kprev; g.n = nb; g.k = mt;
+        g.A = U2 + off; g.lda = mp; g.ta = true;
+        g.B = V1; g.ldb = mp;
+        g.C = w.S2; g.ldc = kprev;
+        gemm(g, s, w.split, w.split_elems);
+        Gemm h;  // X -= U1[R_t] S2
+        h.m = mt; h.n = nb; h.k = kprev;
+        h.alpha = -1.0; h.beta = 1.0;
+        h.A = U1 + off; h.lda = mp;
+        h.B = w.S2; h.ldb = kprev;
+        h.C = w.X; h.ldc = mp;
+        gemm(h, s);
+      }
+      form_y(V1, Tp, mt, nb, Y1, mp, w, s);
+      copy_matrix(Y1, mp, Y2, mp, mt, nb, s);
     }
-    // panel 2's columns (the first nb of A22) get panel 1's update
-    {
-      Gemm g;
-      g.m = m; g.n = nb; g.k = 2 * nb;
-      g.alpha = -1.0; g.beta = 1.0;
-      g.A = VYV; g.lda = mp;              // [V Y]
-      g.B = VYV + mp * nb; g.ldb = mp;    // [Y V], rows 0..nb-1
-      g.tb = true;
-      g.C = A22; g.ldc = lda;
-      gemm(g, s);
-    }
-    const int64_t m2 = m - nb;
-    const int64_t m2p = ld16(m2);  // ld of W
-    double* A33 = A22 + nb + nb * lda;
-    double* W0 = W;                   // V1b
-    double* W1 = W + m2p * nb;        // V2
-    double* W2 = W + 2 * m2p * nb;    // Y1b
-    double* W3 = W + 3 * m2p * nb;    // Y2
-    double* W4 = W + 4 * m2p * nb;    // V1b
-    double* W5 = W + 5 * m2p * nb;    // V2
-    double* T2 = T_all + (p + 1) * (int64_t)nb * nb;
-    qr_panel(A22 + nb, lda, m2, nb, tau_all + (p + 1) * nb, T2, W1, W5, m2p, w, s);
-    sym_times_v(A33, lda, m2, nb, W1, m2p, w, s);
-    {
-      Gemm g;  // S2 = [Y1b V1b]^T V2   (2nb x nb)
-      g.m = 2 * nb; g.n = nb; g.k = m2;
-      g.A = VYV + mp * nb + nb; g.lda = mp; g.ta = true;
-      g.B = W1; g.ldb = m2p;
-      g.C = w.S2; g.ldc = 2 * nb;
-      gemm(g, s, w.split, w.split_elems);
-      Gemm h;  // X2 -= [V1b Y1b] S2
-      h.m = m2; h.n = nb; h.k = 2 * nb;
-      h.alpha = -1.0; h.beta = 1.0;
-      h.A = VYV + nb; h.lda = mp;
-      h.B = w.S2; h.ldb = 2 * nb;
-      h.C = w.X; h.ldc = m2p;
-      gemm(h, s);
-    }
-    form_y(W1, T2, m2, nb, W3, m2p, w, s);
-    copy_matrix(VYV + nb, mp, W0, m2p, m2, nb, s);            // V1b
-    copy_matrix(VYV + nb, mp, W4, m2p, m2, nb, s);            // V1b
-    copy_matrix(VYV + mp * nb + nb, mp, W2, m2p, m2, nb, s);  // Y1b
-    // [V1b V2 Y1b Y2] [Y1b Y2 V1b V2]^T
-    lower_update(A33, lda, m2, 4 * nb, W0, W2, m2p, s);
-    j += 2 * nb;
-    p += 2;
+    // the group's updates on the trailing matrix A[R_q, R_q]
+    const int64_t rq = j + q * nb;
+    const int64_t offq = (q - 1) * nb;
+    lower_update(A + rq + rq * lda, lda, n - rq, 2 * (int64_t)q * nb, U1 + offq, U2 + offq, mp,
+                 s);
+    j += q * nb;
+    p += q;
   }
 }
 
