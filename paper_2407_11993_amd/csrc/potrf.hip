@@ -246,10 +246,12 @@ void trtri_rec(double* A, int64_t lda, int64_t n, double* ws, hipStream_t s) {
 
 namespace {
 
+constexpr int GB = 4;  // diagonal blocks per group
+
 // Diagonal block [j0, j0 + jb) factored (with its inverse in Linv), then the
-// block column below it, A21 <- A21 G11^{-T}, of m rows (also left in T).
+// block column below it, A21 <- A21 G11^{-T}, of m rows (also left in T, ld ldt).
 void factor_block(double* A, int64_t lda, int64_t j0, int jb, int64_t m, double* Linv,
-                  double* T, int64_t* d_status, hipStream_t s) {
+                  double* T, int64_t ldt, int64_t* d_status, hipStream_t s) {
   hipLaunchKernelGGL(potrf_diag, dim3(1), dim3(256), 0, s, A, lda, j0, jb, Linv, d_status);
   MM_HIP_TRY(hipGetLastError());
   if (m <= 0) return;
@@ -258,76 +260,75 @@ void factor_block(double* A, int64_t lda, int64_t j0, int jb, int64_t m, double*
   g.m = m; g.n = jb; g.k = jb;
   g.A = A + (j0 + jb) + j0 * lda; g.lda = lda;
   g.B = Linv; g.ldb = jb; g.tb = true; g.b_band = 0;
-  g.C = T; g.ldc = m;
+  g.C = T; g.ldc = ldt;
   gemm(g, s);
   const int64_t tot = m * jb;
   hipLaunchKernelGGL(copy_block, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, s,
-                     T, m, A + (j0 + jb) + j0 * lda, lda, m, (int64_t)jb);
+                     T, ldt, A + (j0 + jb) + j0 * lda, lda, m, (int64_t)jb);
   MM_HIP_TRY(hipGetLastError());
 }
 
+int64_t ld16(int64_t m) { return ceil_div(m, 16) * 16; }
+
 }  // namespace
 
-// Right-looking blocked Cholesky, two diagonal blocks at a time: block a is
-// factored and its column applied to block b's columns only; block b is
-// factored; the trailing matrix then receives both block columns as one
-// rank-2DB update (k = 256 instead of two passes with k = 128).
+// Right-looking blocked Cholesky in groups of up to GB diagonal blocks: block
+// t of a group first receives the updates of the group's earlier blocks on
+// its own columns, is factored, and leaves its scaled block column T_t in U;
+// the trailing matrix below the group then receives all of them as one
+// update A -= U U^T (k = 128 t, instead of t passes with k = 128).  U's rows
+// are those below the group's first block; T_t is stored from its own first
+// row on, and every product reads it only there.
 void potrf_lower(double* A, int64_t lda, int64_t n, double* ws,
                  int64_t ws_elems, int64_t* d_status, hipStream_t s) {
   MM_REQUIRE(ws_elems >= potrf_ws_elems(n), kInvalid, "potrf: workspace too small");
   double* Linv = ws;                  // DB x DB
-  double* T = ws + (int64_t)DB * DB;  // n x DB
-  double* U = T + n * DB;             // n x 2DB: [Ta below block b | Tb]
+  double* U = ws + (int64_t)DB * DB;  // ldu x GB DB
   for (int64_t j0 = 0; j0 < n;) {
-    const int ja = (int)std::min<int64_t>(DB, n - j0);
-    const int64_t ma = n - j0 - ja;
-    factor_block(A, lda, j0, ja, ma, Linv, T, d_status, s);
-    if (ma <= 0) break;
-    const int64_t j1 = j0 + ja;
-    const int jbb = (int)std::min<int64_t>(DB, n - j1);
-    const int64_t mb = n - j1 - jbb;
-    if (ja < DB || mb <= 0) {
-      // single block column: A22 -= T T^T (lower)
+    const int64_t r1 = j0 + DB;       // U's first row
+    const int64_t ldu = ld16(std::max<int64_t>(1, n - r1));
+    // full blocks join the group while rows remain below them
+    int q = 1;
+    while (q < GB && j0 + (q + 1) * (int64_t)DB < n) ++q;
+    if (n - j0 <= DB) q = 1;
+    int64_t jnext = j0;
+    for (int t = 1; t <= q; ++t) {
+      const int64_t jt = j0 + (t - 1) * (int64_t)DB;
+      const int jb = (int)std::min<int64_t>(DB, n - jt);
+      const int64_t mt = n - jt - jb;
+      if (t > 1) {
+        // block t's columns, rows [jt, n), get the group's earlier blocks
+        Gemm u;
+        u.m = n - jt; u.n = jb; u.k = (int64_t)(t - 1) * DB;
+        u.alpha = -1.0; u.beta = 1.0;
+        u.A = U + (jt - r1); u.lda = ldu;
+        u.B = U + (jt - r1); u.ldb = ldu; u.tb = true;  // its first jb rows
+        u.C = A + jt + jt * lda; u.ldc = lda;
+        gemm(u, s);
+      }
+      factor_block(A, lda, jt, jb, mt, Linv, U + (t - 1) * (int64_t)DB * ldu + (jt + jb - r1),
+                   ldu, d_status, s);
+      jnext = jt + jb;
+    }
+    const int64_t mq = n - jnext;
+    if (mq > 0) {
+      // A[jnext:, jnext:] -= U U^T (lower), U's rows from jnext
       Gemm u;
-      u.m = ma; u.n = ma; u.k = ja;
+      u.m = mq; u.n = mq; u.k = (int64_t)q * DB;
       u.alpha = -1.0; u.beta = 1.0;
-      u.A = T; u.lda = ma;
-      u.B = T; u.ldb = ma; u.tb = true;
-      u.C = A + j1 + j1 * lda; u.ldc = lda;
+      u.A = U + (jnext - r1); u.lda = ldu;
+      u.B = U + (jnext - r1); u.ldb = ldu; u.tb = true;
+      u.C = A + jnext + jnext * lda; u.ldc = lda;
       u.lower = true;
       gemm(u, s);
-      j0 = j1;
-      continue;
     }
-    // block b's columns (all ma rows from j1) get block a's update
-    {
-      Gemm u;
-      u.m = ma; u.n = jbb; u.k = ja;
-      u.alpha = -1.0; u.beta = 1.0;
-      u.A = T; u.lda = ma;
-      u.B = T; u.ldb = ma; u.tb = true;
-      u.C = A + j1 + j1 * lda; u.ldc = lda;
-      gemm(u, s);
-    }
-    // Ta below block b into U's first DB columns (T is reused by block b)
-    copy_matrix(T + jbb, ma, U, mb, mb, ja, s);
-    factor_block(A, lda, j1, jbb, mb, Linv, U + mb * DB, d_status, s);
-    // A33 -= [Ta_below Tb] [Ta_below Tb]^T (lower, k = 2DB)
-    Gemm u;
-    u.m = mb; u.n = mb; u.k = ja + jbb;
-    u.alpha = -1.0; u.beta = 1.0;
-    u.A = U; u.lda = mb;
-    u.B = U; u.ldb = mb; u.tb = true;
-    u.C = A + (j1 + jbb) + (j1 + jbb) * lda; u.ldc = lda;
-    u.lower = true;
-    gemm(u, s);
-    j0 = j1 + jbb;
+    j0 = jnext;
   }
   hipLaunchKernelGGL(zero_upper, dim3((unsigned)n), dim3(256), 0, s, A, lda, n);
   MM_HIP_TRY(hipGetLastError());
 }
 
-int64_t potrf_ws_elems(int64_t n) { return (int64_t)DB * DB + n * DB + n * 2 * DB; }
+int64_t potrf_ws_elems(int64_t n) { return (int64_t)DB * DB + ld16(n) * GB * DB; }
 
 void trtri_lower(double* A, int64_t lda, int64_t n, double* ws, int64_t ws_elems,
                  hipStream_t s) {
