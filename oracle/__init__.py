@@ -16,6 +16,10 @@ Decomposition in Numerical Computation of Eddy Current Transients"):
 * ``theta_direct``      -- the Cholesky theta-method (Sec. 3.3.1, eq. time_integration).
 * ``theta_modal``       -- the modal theta-method (Sec. 3.3.2).
 * ``modal_eigen``       -- eigenvalues and Li-normalised eigenvectors (Sec. 3.2).
+* ``exact_modal``       -- the decoupled modal equations of Sec. 3.2 integrated in
+                           closed form over each step, waveforms linear between
+                           samples (the analytical route of Sec. 3.3 left to later work).
+* ``exact_phi``         -- the two step integrals that closed form uses.
 * ``adjoint_direct``    -- gradient of a probe-signal misfit through the
                            theta-method (adjoint recursion, every state kept).
 """
@@ -76,6 +80,10 @@ def _load():
             ctypes.POINTER(_Problem), ctypes.c_double, ctypes.c_double, _i64,
             _dp, _dp, _dp, _dp, _dp]
         lib.orc_theta_modal.restype = ctypes.c_int
+        lib.orc_exact_modal.argtypes = [
+            ctypes.POINTER(_Problem), ctypes.c_double, _i64, _dp, _dp, _dp, _dp]
+        lib.orc_exact_modal.restype = ctypes.c_int
+        lib.orc_exact_phi.argtypes = [ctypes.c_double, ctypes.c_double, _dp, _dp]
         lib.orc_modal_eigen.argtypes = [
             ctypes.POINTER(_Problem), _dp, _dp, ctypes.POINTER(ctypes.c_int)]
         lib.orc_modal_eigen.restype = ctypes.c_int
@@ -261,6 +269,31 @@ def theta_modal(pb: Problem, theta: float, dt: float, T: int, i_src=None,
         raise RuntimeError(_ERR.get(rc, str(rc)))
     sig = sig[:, :pb.n_probe]
     return (sig, lam, I_hist) if want_I else (sig, lam)
+
+
+def exact_modal(pb: Problem, dt: float, T: int, i_src=None, i_D=None,
+                want_I: bool = False):
+    """Modal stepping with exact per-mode integration of waveforms that are
+    linear between samples; returns signal (T x n_probe) [, I_hist]."""
+    i_src, i_D = pb._waves(T, i_src, i_D)
+    sig = np.zeros((T, max(pb.n_probe, 1)))
+    I_hist = np.zeros((T + 1, pb.n)) if want_I else None
+    st = pb._struct()
+    rc = _load().orc_exact_modal(ctypes.byref(st), float(dt), int(T), _ptr(i_src),
+                                 _ptr(i_D), _ptr(sig), _ptr(I_hist))
+    if rc:
+        raise RuntimeError(_ERR.get(rc, str(rc)))
+    sig = sig[:, :pb.n_probe]
+    return (sig, I_hist) if want_I else sig
+
+
+def exact_phi(lam: float, dt: float):
+    """(phi1, phi2): the integrals of exp(-lam (dt - s)) and of s exp(-lam (dt - s))
+    over [0, dt] that the exact step uses."""
+    a = np.zeros(1)
+    b = np.zeros(1)
+    _load().orc_exact_phi(float(lam), float(dt), _ptr(a), _ptr(b))
+    return float(a[0]), float(b[0])
 
 
 def modal_eigen(pb: Problem, want_V: bool = True):

@@ -26,6 +26,9 @@
  *                                               (Sec. 3.3.1, eq. time_integration)
  *   - the modal theta-method on the generalized eigenpairs of (Li, Ri)
  *                                               (Sec. 3.2 and Sec. 3.3.2)
+ *   - exact integration of the decoupled modal equations for inputs linear
+ *     between samples (the analytical route Sec. 3.3 leaves to later work;
+ *     reading r11)
  *
  * Readings of the paper taken where it is silent or inconsistent:
  *   (r1) the modal right-hand side is the Cholesky right-hand side expressed in
@@ -35,7 +38,10 @@
  *   (r3) the factored matrix is the reduced Z = Li + theta dt Ri;
  *   (r4) the source mutual inductances enter projected by K^T; M^D = 0;
  *   (r5) K is the orthonormal Householder complement of im(E^T);
- *   (r10) the probe signal after step k is P (I^{k+1} - I^k) / dt.
+ *   (r10) the probe signal after step k is P (I^{k+1} - I^k) / dt;
+ *   (r11) "exact" integration takes every source waveform linear between its
+ *        samples (first-order hold), so on a step the modal forcing is
+ *        g(s) = e0 + e1 s and each mode is integrated in closed form.
  */
 #include <math.h>
 #include <stdint.h>
@@ -720,6 +726,135 @@ int orc_theta_modal(const orc_problem *pb, double theta, double dt, int64_t T,
     free(y);
     free(dy);
     free(f);
+    free(dIi);
+    free(Ii);
+    free(lam);
+    free(V);
+    free_reduced(&r);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exact integration of one mode over a step of length dt (reading r11):     */
+/*   y' + lam y = e0 + e1 s,  s in [0, dt]                                    */
+/* gives y(dt) = exp(-lam dt) y(0) + e0 phi1 + e1 phi2 with                   */
+/*   phi1 = int_0^dt exp(-lam (dt - s)) ds   = dt  sum_k (-x)^k / (k+1)!      */
+/*   phi2 = int_0^dt exp(-lam (dt - s)) s ds = dt^2 sum_k (-x)^k / (k+2)!     */
+/* (x = lam dt).  The series are summed for x < 1/2; above, the closed forms */
+/* phi1 = (1 - exp(-x)) / lam, phi2 = (dt - phi1) / lam have no cancellation. */
+/* ------------------------------------------------------------------------ */
+void orc_exact_phi(double lam, double dt, double *phi1, double *phi2)
+{
+    const double x = lam * dt;
+    if (x < 0.5) {
+        double t1 = 1.0, t2 = 0.5, s1 = 0.0, s2 = 0.0;
+        for (int k = 0; k < 40; ++k) {
+            s1 += t1;
+            s2 += t2;
+            t1 *= -x / (double)(k + 2);
+            t2 *= -x / (double)(k + 3);
+        }
+        *phi1 = dt * s1;
+        *phi2 = dt * dt * s2;
+    } else {
+        *phi1 = -expm1(-x) / lam;
+        *phi2 = (dt - *phi1) / lam;
+    }
+}
+
+/* Modal stepping with exact per-mode integration (reading r11).  With the   */
+/* waveforms linear on step k (d x = x^{k+1} - x^k), the reduced forcing of   */
+/* eq. circuit_equations_v2 is                                               */
+/*   f(s) = f0 + f1 s,  f0 = -R_D iD^k - L_D d iD / dt - K^T M0 d i0 / dt,    */
+/*                      f1 = -R_D d iD / dt,                                 */
+/* its modal components e0 = V^T f0, e1 = V^T f1, and every mode advances as */
+/* in orc_exact_phi.  Probe signal and history as in orc_theta_modal.        */
+/* ------------------------------------------------------------------------ */
+int orc_exact_modal(const orc_problem *pb, double dt, int64_t T,
+                    const double *i_src, const double *i_D, double *signal,
+                    double *I_hist)
+{
+    orc_reduced r;
+    const int64_t n0 = pb->n - pb->m, m = pb->m, ns = pb->n_src;
+    double *lam = (double *)malloc(sizeof(double) * (size_t)n0);
+    double *V = (double *)malloc(sizeof(double) * (size_t)(n0 * n0));
+    int rc = modal_parts(pb, &r, lam, V, NULL);
+    if (rc) {
+        free(lam);
+        free(V);
+        free_reduced(&r);
+        return rc;
+    }
+    double *decay = (double *)malloc(sizeof(double) * (size_t)n0);
+    double *p1 = (double *)malloc(sizeof(double) * (size_t)n0);
+    double *p2 = (double *)malloc(sizeof(double) * (size_t)n0);
+    for (int64_t nn = 0; nn < n0; ++nn) {
+        decay[nn] = exp(-lam[nn] * dt);
+        orc_exact_phi(lam[nn], dt, &p1[nn], &p2[nn]);
+    }
+    double *y = (double *)calloc((size_t)n0, sizeof(double));
+    double *dy = (double *)malloc(sizeof(double) * (size_t)n0);
+    double *f0 = (double *)malloc(sizeof(double) * (size_t)n0);
+    double *f1 = (double *)malloc(sizeof(double) * (size_t)n0);
+    double *dIi = (double *)malloc(sizeof(double) * (size_t)n0);
+    double *Ii = (double *)malloc(sizeof(double) * (size_t)n0);
+    if (I_hist) {
+        memset(Ii, 0, sizeof(double) * (size_t)n0);
+        full_current(pb, &r, Ii, i_D, I_hist);
+    }
+    for (int64_t k = 0; k < T; ++k) {
+        for (int64_t i = 0; i < n0; ++i) {
+            double a = 0.0, b = 0.0;
+            for (int64_t e = 0; e < m; ++e) {
+                const double iDk = i_D[IDX(k, e, m)];
+                const double diD = i_D[IDX(k + 1, e, m)] - iDk;
+                a += -r.RD[IDX(i, e, m)] * iDk - r.LD[IDX(i, e, m)] * diD / dt;
+                b += -r.RD[IDX(i, e, m)] * diD / dt;
+            }
+            for (int64_t c = 0; c < ns; ++c) {
+                const double di0 = i_src[IDX(k + 1, c, ns)] - i_src[IDX(k, c, ns)];
+                a += -r.Mi[IDX(i, c, ns)] * di0 / dt;
+            }
+            f0[i] = a;
+            f1[i] = b;
+        }
+        for (int64_t nn = 0; nn < n0; ++nn) {
+            double e0 = 0.0, e1 = 0.0;
+            for (int64_t i = 0; i < n0; ++i) {
+                e0 += V[IDX(i, nn, n0)] * f0[i];
+                e1 += V[IDX(i, nn, n0)] * f1[i];
+            }
+            const double ynew = decay[nn] * y[nn] + e0 * p1[nn] + e1 * p2[nn];
+            dy[nn] = ynew - y[nn];
+        }
+        for (int64_t nn = 0; nn < n0; ++nn)
+            y[nn] += dy[nn];
+        for (int64_t i = 0; i < n0; ++i) {
+            double s = 0.0;
+            for (int64_t nn = 0; nn < n0; ++nn)
+                s += V[IDX(i, nn, n0)] * dy[nn];
+            dIi[i] = s;
+        }
+        if (signal)
+            probe(pb, &r, dt, k, dIi, i_D, signal + k * pb->n_probe);
+        if (I_hist) {
+            for (int64_t i = 0; i < n0; ++i) {
+                double s = 0.0;
+                for (int64_t nn = 0; nn < n0; ++nn)
+                    s += V[IDX(i, nn, n0)] * y[nn];
+                Ii[i] = s;
+            }
+            full_current(pb, &r, Ii, i_D + (k + 1) * pb->m,
+                         I_hist + (k + 1) * pb->n);
+        }
+    }
+    free(decay);
+    free(p1);
+    free(p2);
+    free(y);
+    free(dy);
+    free(f0);
+    free(f1);
     free(dIi);
     free(Ii);
     free(lam);

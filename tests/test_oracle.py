@@ -410,3 +410,71 @@ def test_adjoint_waveform_gradient_by_central_differences(orc):
         fd = (_misfit(orc, L, R, M, 0.5, T, i_src + e, obs)
               - _misfit(orc, L, R, M, 0.5, T, i_src - e, obs)) / (2 * eps)
         assert abs(fd - gi[j]) <= 1e-6 * np.abs(gi).max(), (j, fd, gi[j])
+
+
+# ---------------------------------------------------------------------------
+# exact per-mode integration (waveforms linear between samples)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("x", [1e-9, 1e-4, 0.3, 0.4999, 0.5001, 2.0, 45.0])
+def test_exact_phi_by_quadrature(orc, x):
+    import scipy.integrate as si
+    dt = 0.8
+    lam = x / dt
+    p1, p2 = orc.exact_phi(lam, dt)
+    q1 = si.quad(lambda s: math.exp(-lam * (dt - s)), 0.0, dt, epsabs=0, epsrel=2e-14)[0]
+    q2 = si.quad(lambda s: s * math.exp(-lam * (dt - s)), 0.0, dt, epsabs=0, epsrel=2e-14)[0]
+    assert abs(p1 - q1) <= 5e-14 * q1
+    assert abs(p2 - q2) <= 5e-14 * q2
+
+
+def test_exact_modal_matches_matrix_exponential(orc):
+    # No electrodes: L I' + R I = -M i'(t) with i linear between samples is
+    # integrated exactly by the block exponential expm([[A, I], [0, 0]] dt)
+    # = [[exp(A dt), Phi], [0, I]], A = -L^{-1} R, Phi = int_0^dt exp(A s) ds.
+    _, L, R, M = _small_problem(orc)
+    n = L.shape[0]
+    T, dt = 40, 0.7
+    rng = np.random.default_rng(7)
+    i_src = np.concatenate([[0.0], np.cumsum(rng.standard_normal(T))])[:, None]
+    P = rng.standard_normal((2, n))
+    A = -np.linalg.solve(L, R)
+    Bk = np.zeros((2 * n, 2 * n))
+    Bk[:n, :n] = A * dt
+    Bk[:n, n:] = np.eye(n) * dt
+    E = sla.expm(Bk)
+    eA, Phi = E[:n, :n], E[:n, n:]
+    LiM = np.linalg.solve(L, M[:, 0])
+    I = np.zeros(n)
+    ref = np.zeros((T, 2))
+    for k in range(T):
+        b = -LiM * (i_src[k + 1, 0] - i_src[k, 0]) / dt
+        In = eA @ I + Phi @ b
+        ref[k] = P @ (In - I) / dt
+        I = In
+    sig = orc.exact_modal(orc.Problem(L, R, M, P), dt, T, i_src)
+    assert np.abs(sig - ref).max() < 1e-11 * np.abs(ref).max()
+
+
+def test_exact_modal_is_the_fine_step_limit_with_electrodes(orc):
+    # With electrodes (R_D i_D varies linearly within a step) the exact step
+    # is the limit of Crank-Nicolson on r substeps of the same piecewise-linear
+    # waveforms: the difference of the step-averaged probe signal falls as r^-2.
+    w, L, R, E = _electrode_problem(orc)
+    pb = orc.Problem(L, R, w.M, w.P, E)
+    T, dt = 30, w.dt * 4
+    i_src = w.i_src[:T + 1]
+    i_D = w.i_D[:T + 1]
+    ref = orc.exact_modal(pb, dt, T, i_src, i_D)
+    errs = []
+    for r in (8, 16, 32):
+        f = np.arange(T * r + 1) / r          # fine sample positions in coarse steps
+        fs = np.stack([np.interp(f, np.arange(T + 1), i_src[:, c])
+                       for c in range(i_src.shape[1])], axis=1)
+        fD = np.stack([np.interp(f, np.arange(T + 1), i_D[:, a])
+                       for a in range(i_D.shape[1])], axis=1)
+        s_fine, _ = orc.theta_modal(pb, 0.5, dt / r, T * r, fs, fD)
+        coarse = s_fine.reshape(T, r, -1).mean(axis=1)
+        errs.append(np.abs(coarse - ref).max() / np.abs(ref).max())
+    assert errs[-1] < 1e-4
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert all(abs(q - 2.0) < 0.15 for q in rates), (errs, rates)
