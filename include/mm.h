@@ -114,6 +114,19 @@ mm_status mm_decompose_projected(mm_ctx* ctx);
 mm_status mm_step_modal(mm_ctx* ctx, double theta, double dt, int64_t n_steps,
                         const double* i_src, const double* i_D, double* signal);
 
+/* Exact integration of the decoupled modal equations (Sec. 3.2, eq.
+ * modal_decomposition_discrete), the analytical route Sec. 3.3 leaves to
+ * later work: every source waveform is taken linear between its samples
+ * (first-order hold), so on step k each mode obeys y' + lam y = e1 + e2 s/dt
+ * and is advanced in closed form,
+ *   y^{k+1} = exp(-lam dt) y^k + beta e1 + gamma e2,
+ *   beta = (1 - exp(-x)) / x, gamma = (1 - beta) / x, x = lam dt.
+ * No time-step error for such waveforms; the cost per step is that of
+ * mm_step_modal.  Arguments, state, signal and errors as mm_step_modal
+ * (dt > 0); the two may be mixed on one state. */
+mm_status mm_step_modal_exact(mm_ctx* ctx, double dt, int64_t n_steps,
+                              const double* i_src, const double* i_D, double* signal);
+
 /* The classical theta-method (Sec. 3.3.1, eq. time_integration): the
  * factor Z = Li + theta dt Ri = C C^T is computed on the first call and
  * whenever theta or dt change; each step does one forward and one backward

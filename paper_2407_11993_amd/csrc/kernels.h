@@ -164,6 +164,7 @@ struct ModalStep {
   const double* Pt = nullptr;    // modal probe weights (n0 x n_probe)
   int n_probe = 0;
   double theta = 0.5, dt = 1.0;
+  bool exact = false;            // exact per-mode integration instead of theta
   double* y = nullptr;           // modal amplitudes (state)
   double* probe_partial = nullptr;  // n_steps x n_groups x n_probe
 };

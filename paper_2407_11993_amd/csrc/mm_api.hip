@@ -574,11 +574,11 @@ mm_status mm_decompose_projected(mm_ctx* c) {
   return guarded(c, [&] { decompose_impl(c, true); });
 }
 
-mm_status mm_step_modal(mm_ctx* c, double theta, double dt, int64_t n_steps,
-                        const double* i_src, const double* i_D, double* signal) {
-  if (!c) return MM_E_INVALID;
-  return guarded(c, [&] {
-    MM_REQUIRE(c->decomposed, kState, "mm_step_modal before mm_decompose");
+namespace {
+
+void step_modal_impl(mm_ctx* c, double theta, double dt, bool exact, int64_t n_steps,
+                     const double* i_src, const double* i_D, double* signal) {
+    MM_REQUIRE(c->decomposed, kState, "modal stepping before mm_decompose");
     check_steps(theta, dt, n_steps);
     check_run_columns(c);
     MM_REQUIRE(c->n_src == 0 || i_src, kInvalid, "i_src is required");
@@ -597,6 +597,7 @@ mm_status mm_step_modal(mm_ctx* c, double theta, double dt, int64_t n_steps,
     ms.Pt = c->Pm.d();
     ms.n_probe = c->n_probe;
     ms.theta = theta; ms.dt = dt;
+    ms.exact = exact;
     ms.y = c->y.d();
     ms.probe_partial = c->pp.d();
     modal_steps(ms, 0, n_steps, s);
@@ -605,7 +606,20 @@ mm_status mm_step_modal(mm_ctx* c, double theta, double dt, int64_t n_steps,
     if (c->m)
       MM_HIP_TRY(hipMemcpyAsync(c->iD_modal.p, i_D + n_steps * c->m, sizeof(double) * c->m,
                                 hipMemcpyDeviceToDevice, s));
-  });
+}
+
+}  // namespace
+
+mm_status mm_step_modal(mm_ctx* c, double theta, double dt, int64_t n_steps,
+                        const double* i_src, const double* i_D, double* signal) {
+  if (!c) return MM_E_INVALID;
+  return guarded(c, [&] { step_modal_impl(c, theta, dt, false, n_steps, i_src, i_D, signal); });
+}
+
+mm_status mm_step_modal_exact(mm_ctx* c, double dt, int64_t n_steps, const double* i_src,
+                              const double* i_D, double* signal) {
+  if (!c) return MM_E_INVALID;
+  return guarded(c, [&] { step_modal_impl(c, 0.5, dt, true, n_steps, i_src, i_D, signal); });
 }
 
 mm_status mm_step_cholesky(mm_ctx* c, double theta, double dt, int64_t n_steps,

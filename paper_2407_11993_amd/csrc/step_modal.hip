@@ -6,6 +6,13 @@
 // Cholesky method, expressed in the modal basis), and the probe signal of
 // the step is  s_p = sum_n Pt(n, p) dy_n / dt  (+ the direct electrode term).
 //
+// With exact = true every mode is integrated in closed form over the step,
+// the waveforms taken linear between their samples: the forcing on the step
+// is e1 + e2 s / dt (s in [0, dt]; e2 from the R_D i_D columns only) and
+//   dy = -alpha y + beta e1 + gamma e2,   x = lam dt,
+//   alpha = 1 - exp(-x), beta = alpha / x, gamma = (1 - beta) / x,
+// in the same increment encoding of the forcing (e1 uses theta = 0).
+//
 // One launch runs all steps: a thread keeps its mode's amplitude, factor and
 // weights in registers for the whole horizon, so HBM traffic is O(N + T).
 // Each step reduces the probe contributions over the wave (xor butterfly)
@@ -49,25 +56,61 @@ __global__ void __launch_bounds__(NT) modal_step_k(ModalStep ms, int64_t n_steps
   const int64_t n0 = ms.n0;
   const int nf = NF > 0 ? NF : ms.f.nf;
   const int np = ms.n_probe;  // <= NP (template capacity)
-  double y = 0.0, c = 0.0, a = 0.0;
+  const bool exact = ms.exact;
+  const double th = exact ? 0.0 : ms.theta;
+  double y = 0.0, c = 0.0, a = 0.0, g = 0.0;
   double w[MAXF], pt[NP > 0 ? NP : 1];
   for (int j = 0; j < MAXF; ++j) w[j] = 0.0;
   for (int p = 0; p < (NP > 0 ? NP : 1); ++p) pt[p] = 0.0;
   if (n < n0) {
     const double lam = ms.lam[n];
     y = ms.y[n];
-    a = ms.dt * lam;
-    c = 1.0 / (1.0 + ms.theta * ms.dt * lam);
+    if (exact) {
+      // a = alpha, c = beta, g = gamma; gamma summed as sum_k (-x)^k / (k+2)!
+      // below x = 1/2, where 1 - beta cancels
+      const double x = ms.dt * lam;
+      a = -expm1(-x);
+      if (x == 0.0) {
+        c = 1.0;
+        g = 0.5;
+      } else {
+        c = a / x;
+        if (x < 0.5) {
+          double term = 0.5;
+          g = 0.0;
+          for (int q = 0; q < 24; ++q) {
+            g += term;
+            term *= -x / (double)(q + 3);
+          }
+        } else {
+          g = (1.0 - c) / x;
+        }
+      }
+    } else {
+      a = ms.dt * lam;
+      c = 1.0 / (1.0 + ms.theta * ms.dt * lam);
+    }
     for (int j = 0; j < nf; ++j) w[j] = ms.W[n + (int64_t)j * n0];
     for (int p = 0; p < np; ++p) pt[p] = ms.Pt[n + (int64_t)p * n0];
   }
   const int64_t G = gridDim.x;
+  const int mD = ms.f.m;
   for (int64_t k = 0; k < n_steps; ++k) {
     double e = 0.0;
 #pragma unroll
     for (int j = 0; j < MAXF; ++j)
-      if (j < nf) e += w[j] * forcing_u(ms.f, j, k, ms.theta, ms.dt);
-    const double dy = c * (e - a * y);
+      if (j < nf) e += w[j] * forcing_u(ms.f, j, k, th, ms.dt);
+    double dy;
+    if (exact) {
+      double e2 = 0.0;  // -dt (iD^{k+1} - iD^k) on the R_D columns
+#pragma unroll
+      for (int j = 0; j < MAXF; ++j)
+        if (j < mD)
+          e2 += w[j] * (-ms.dt * (ms.f.i_D[(k + 1) * mD + j] - ms.f.i_D[k * mD + j]));
+      dy = c * e + g * e2 - a * y;
+    } else {
+      dy = c * (e - a * y);
+    }
     y += dy;
     const int buf = (int)(k & 1);
 #pragma unroll

@@ -112,6 +112,18 @@ class Solver:
         self._keep = (s, d)
         return sig
 
+    def step_modal_exact(self, dt, n_steps, i_src, i_D=None, out=None):
+        """Modal stepping with exact per-mode integration (waveforms linear
+        between samples); same state and signal as step_modal."""
+        s, d = self._waves(n_steps, i_src, i_D)
+        sig = out if out is not None else torch.empty(
+            (n_steps, self.n_probe), dtype=torch.float64, device=self.device)
+        _lib.check(self.lib.mm_step_modal_exact(self.ctx, float(dt), int(n_steps),
+                                                _lib.ptr(s), _lib.ptr(d), _lib.ptr(sig)),
+                   self.ctx)
+        self._keep = (s, d)
+        return sig
+
     def step_cholesky(self, theta, dt, n_steps, i_src, i_D=None, out=None):
         s, d = self._waves(n_steps, i_src, i_D)
         sig = out if out is not None else torch.empty(
