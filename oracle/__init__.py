@@ -20,6 +20,9 @@ Decomposition in Numerical Computation of Eddy Current Transients"):
                            closed form over each step, waveforms linear between
                            samples (the analytical route of Sec. 3.3 left to later work).
 * ``exact_phi``         -- the two step integrals that closed form uses.
+* ``phasors_direct``    -- steady-state probe phasors under sinusoidal sources: one
+                           complex solve of the unreduced system per frequency (the
+                           frequency-domain method of Sec. 4.5).
 * ``adjoint_direct``    -- gradient of a probe-signal misfit through the
                            theta-method (adjoint recursion, every state kept).
 """
@@ -294,6 +297,34 @@ def exact_phi(lam: float, dt: float):
     b = np.zeros(1)
     _load().orc_exact_phi(float(lam), float(dt), _ptr(a), _ptr(b))
     return float(a[0]), float(b[0])
+
+
+def phasors_direct(pb: Problem, omegas, amp_src, amp_D=None):
+    """Steady-state phasors of the probe signals P dI/dt for sources
+    i0_c(t) = Re{amp_src[w, c] exp(j omega_w t)} and electrode currents
+    iD_a(t) = Re{amp_D[w, a] exp(j omega_w t)}: for every frequency the
+    unreduced circuit system of Sec. 3.1 in phasor form,
+        (R + j omega L) I + E^T phi = -j omega M0 I0,   E I = ID,
+    is solved directly (complex LU), and the probe phasor is j omega P I.
+    Returns n_w x n_probe complex."""
+    omegas = np.asarray(omegas, dtype=np.float64).reshape(-1)
+    n, m = pb.n, pb.m
+    amp_src = np.asarray(amp_src, dtype=np.complex128).reshape(len(omegas), pb.n_src)
+    if m:
+        amp_D = np.asarray(amp_D, dtype=np.complex128).reshape(len(omegas), m)
+    out = np.zeros((len(omegas), pb.n_probe), dtype=np.complex128)
+    for w, om in enumerate(omegas):
+        A = np.zeros((n + m, n + m), dtype=np.complex128)
+        A[:n, :n] = pb.R + 1j * om * pb.L
+        rhs = np.zeros(n + m, dtype=np.complex128)
+        rhs[:n] = -1j * om * (pb.M @ amp_src[w])
+        if m:
+            A[:n, n:] = pb.E.T
+            A[n:, :n] = pb.E
+            rhs[n:] = amp_D[w]
+        I = np.linalg.solve(A, rhs)[:n]
+        out[w] = 1j * om * (pb.P @ I)
+    return out
 
 
 def modal_eigen(pb: Problem, want_V: bool = True):

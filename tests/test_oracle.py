@@ -478,3 +478,69 @@ def test_exact_modal_is_the_fine_step_limit_with_electrodes(orc):
     assert errs[-1] < 1e-4
     rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
     assert all(abs(q - 2.0) < 0.15 for q in rates), (errs, rates)
+
+
+# ---------------------------------------------------------------------------
+# frequency domain: steady-state phasors by direct complex solves
+# ---------------------------------------------------------------------------
+def test_phasor_single_unknown_closed_form(orc):
+    # l I' + r I = -m i', i = Re{I0 e^{jwt}}:  I = -j w m I0 / (r + j w l),
+    # probe p dI/dt -> j w p I.
+    l, r, m, p = 2.0, 3.0, 0.5, 1.5
+    om = np.array([0.1, 1.0, 7.0])
+    a = np.array([1.0 + 0.5j, 2.0, -1j])
+    pb = orc.Problem(np.array([[l]]), np.array([[r]]), np.array([[m]]), np.array([[p]]))
+    got = orc.phasors_direct(pb, om, a[:, None])[:, 0]
+    ref = 1j * om * p * (-1j * om * m * a / (r + 1j * om * l))
+    assert np.abs(got - ref).max() < 1e-15 * np.abs(ref).max()
+
+
+def test_phasor_is_the_time_domain_steady_state(orc):
+    # Drive the exact time integrator with a sampled sinusoid until the
+    # transient has decayed and project the step-averaged probe signal over
+    # the last two periods on exp(j w t_k).  The linear interpolation of the
+    # samples of exp(j w t) has components at every alias w_m = w + 2 pi m / dt
+    # with gain sinc^2(w_m dt / 2), each response is averaged over the step
+    # ((exp(j x_m) - 1) / (j x_m), x_m = w_m dt) and sampled at t_k, where all
+    # aliases coincide with w: the projection equals the sum over m of the
+    # direct phasors at w_m times those two factors (truncated at |m| <= K,
+    # tail ~ 1/K).
+    _, L, R, M = _small_problem(orc)
+    n = L.shape[0]
+    P = np.random.default_rng(3).standard_normal((2, n))
+    pb = orc.Problem(L, R, M, P)
+    lam = orc.modal_eigen(pb, want_V=False)
+    dt, per = 0.05, 640                       # samples per period
+    om = 2 * math.pi / (per * dt)
+    T = int(math.ceil(40.0 / lam.min() / dt / per) + 2) * per
+    t = np.arange(T + 1) * dt
+    a = 0.8 - 0.3j
+    sig = orc.exact_modal(pb, dt, T, np.real(a * np.exp(1j * om * t))[:, None])
+    tk = t[T - 2 * per:T]
+    proj = 2.0 / len(tk) * (sig[-2 * per:] * np.exp(-1j * om * tk)[:, None]).sum(axis=0)
+
+    def alias_sum(K):
+        oms = om + 2 * math.pi * np.arange(-K, K + 1) / dt
+        x = oms * dt
+        g = ((2 - 2 * np.cos(x)) / x ** 2) * ((np.exp(1j * x) - 1) / (1j * x))
+        s = orc.phasors_direct(pb, oms, np.full((len(oms), 1), a))
+        return (s * g[:, None]).sum(axis=0)
+
+    e400 = np.abs(proj - alias_sum(400)).max() / np.abs(proj).max()
+    e4000 = np.abs(proj - alias_sum(4000)).max() / np.abs(proj).max()
+    assert e4000 < 1e-8
+    assert 6.0 < e400 / e4000 < 14.0          # the truncated tail, ~ 1/K
+
+
+def test_phasor_conjugate_symmetry_and_linearity(orc):
+    w, L, R, E = _electrode_problem(orc)
+    pb = orc.Problem(L, R, w.M, w.P, E)
+    om = np.array([0.03, 0.4])
+    rng = np.random.default_rng(5)
+    a = rng.standard_normal((2, pb.n_src)) + 1j * rng.standard_normal((2, pb.n_src))
+    d = rng.standard_normal((2, pb.m)) + 1j * rng.standard_normal((2, pb.m))
+    s1 = orc.phasors_direct(pb, om, a, d)
+    s2 = orc.phasors_direct(pb, -om, np.conj(a), np.conj(d))
+    assert np.abs(s2 - np.conj(s1)).max() < 1e-12 * np.abs(s1).max()
+    s3 = orc.phasors_direct(pb, om, 2.0 * a, 2.0 * d)
+    assert np.abs(s3 - 2.0 * s1).max() < 1e-12 * np.abs(s1).max()
