@@ -127,6 +127,25 @@ mm_status mm_step_modal(mm_ctx* ctx, double theta, double dt, int64_t n_steps,
 mm_status mm_step_modal_exact(mm_ctx* ctx, double dt, int64_t n_steps,
                               const double* i_src, const double* i_D, double* signal);
 
+/* Steady-state phasors of the probe signals under sinusoidal sources, from
+ * the decomposition (Sec. 3.2, eq. modal_decomposition_discrete; the
+ * frequency-domain comparison of Sec. 4.5): with i0_c(t) = Re{A_c e^{jwt}}
+ * and iD_a(t) = Re{D_a e^{jwt}} every mode has the phasor
+ *   y_n = (W u(w))_n / (lam_n + j w),
+ * u: -D on the R_D columns, -j w D on the L_D columns, -j w A on the source
+ * columns, and the probe signal P dI/dt has the phasor
+ *   S_p(w) = j w (Pt^T y + P A_D D)_p.
+ * O(N) per frequency instead of a complex factorisation of R + j w L.
+ * All pointers are device memory; complex numbers are (re, im) pairs:
+ * omega (n_w, rad per unit time), amp_src (n_w x n_src pairs, row-major by
+ * frequency; NULL when n_src = 0), amp_D (n_w x (Ne-1) pairs; NULL when
+ * Ne = 0), out (n_w x n_probe pairs).  Requires mm_decompose or
+ * mm_decompose_projected; ordered on the context's stream.  Errors:
+ * MM_E_STATE before the decomposition, MM_E_INVALID for missing arrays, more
+ * than 8 forcing columns or probes, or n_w > 65535. */
+mm_status mm_modal_phasors(mm_ctx* ctx, int64_t n_w, const double* omega,
+                           const double* amp_src, const double* amp_D, double* out);
+
 /* The classical theta-method (Sec. 3.3.1, eq. time_integration): the
  * factor Z = Li + theta dt Ri = C C^T is computed on the first call and
  * whenever theta or dt change; each step does one forward and one backward

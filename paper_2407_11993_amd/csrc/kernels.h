@@ -169,6 +169,27 @@ struct ModalStep {
   double* probe_partial = nullptr;  // n_steps x n_groups x n_probe
 };
 int modal_groups(int64_t n0);
+
+// Steady-state probe phasors for sinusoidal sources (phasor.hip).  Complex
+// numbers are (re, im) pairs; amp_src n_w x n_src, amp_D n_w x m, out
+// n_w x n_probe, all row-major by frequency; partial holds
+// n_w x phasor_groups(n0) x n_probe pairs.
+struct ModalPhasor {
+  int64_t n0 = 0;
+  const double* lam = nullptr;   // n0
+  const double* W = nullptr;     // n0 x (2m + n_src): R_D, L_D, source columns
+  const double* Pt = nullptr;    // n0 x n_probe
+  const double* PD = nullptr;    // n_probe x m (direct electrode term), or nullptr
+  int m = 0, n_src = 0, n_probe = 0;
+  int64_t n_w = 0;
+  const double* omega = nullptr;    // n_w
+  const double* amp_src = nullptr;  // n_w x n_src pairs
+  const double* amp_D = nullptr;    // n_w x m pairs
+  double* partial = nullptr;
+  double* out = nullptr;            // n_w x n_probe pairs
+};
+int64_t phasor_groups(int64_t n0);
+void modal_phasors(const ModalPhasor& mp, hipStream_t s);
 void modal_steps(const ModalStep& m, int64_t k0, int64_t n_steps, hipStream_t s);
 
 // Batched runs of the modal theta-method: run r drives one forcing column

@@ -622,6 +622,34 @@ mm_status mm_step_modal_exact(mm_ctx* c, double dt, int64_t n_steps, const doubl
   return guarded(c, [&] { step_modal_impl(c, 0.5, dt, true, n_steps, i_src, i_D, signal); });
 }
 
+mm_status mm_modal_phasors(mm_ctx* c, int64_t n_w, const double* omega, const double* amp_src,
+                           const double* amp_D, double* out) {
+  if (!c) return MM_E_INVALID;
+  return guarded(c, [&] {
+    MM_REQUIRE(c->decomposed, kState, "mm_modal_phasors before mm_decompose");
+    MM_REQUIRE(n_w >= 0, kInvalid, "n_w must be >= 0");
+    check_run_columns(c);
+    if (n_w == 0) return;
+    MM_REQUIRE(omega && out, kInvalid, "omega and out are required");
+    MM_REQUIRE(c->n_src == 0 || amp_src, kInvalid, "amp_src is required");
+    MM_REQUIRE(c->m == 0 || amp_D, kInvalid, "amp_D is required");
+    hipStream_t s = c->stream;
+    c->pp.alloc(sizeof(double) * n_w * phasor_groups(c->n0) * c->n_probe * 2);
+    ModalPhasor mp;
+    mp.n0 = c->n0;
+    mp.lam = c->lam.d();
+    mp.W = c->Wm.d();
+    mp.Pt = c->Pm.d();
+    mp.PD = c->m ? c->PD.d() : nullptr;
+    mp.m = (int)c->m; mp.n_src = c->n_src; mp.n_probe = c->n_probe;
+    mp.n_w = n_w;
+    mp.omega = omega; mp.amp_src = amp_src; mp.amp_D = amp_D;
+    mp.partial = c->pp.d();
+    mp.out = out;
+    modal_phasors(mp, s);
+  });
+}
+
 mm_status mm_step_cholesky(mm_ctx* c, double theta, double dt, int64_t n_steps,
                            const double* i_src, const double* i_D, double* signal) {
   if (!c) return MM_E_INVALID;

@@ -124,6 +124,27 @@ class Solver:
         self._keep = (s, d)
         return sig
 
+    def phasors(self, omegas, amp_src, amp_D=None):
+        """Steady-state phasors (n_w x n_probe, complex) of the probe signals
+        P dI/dt for sources Re{amp_src[w, c] exp(j omegas[w] t)} and electrode
+        currents Re{amp_D[w, a] exp(j omegas[w] t)}."""
+        om = _dev(torch.as_tensor(omegas, dtype=torch.float64).reshape(-1))
+        nw = om.numel()
+
+        def pairs(a, cols):
+            if cols == 0:
+                return None
+            a = torch.as_tensor(a, dtype=torch.complex128).reshape(nw, cols)
+            return _dev(torch.view_as_real(a.contiguous()).contiguous())
+
+        src = pairs(amp_src, self.n_src)
+        dd = pairs(amp_D, self.m) if self.m else None
+        out = torch.empty((nw, self.n_probe, 2), dtype=torch.float64, device=self.device)
+        _lib.check(self.lib.mm_modal_phasors(self.ctx, int(nw), _lib.ptr(om), _lib.ptr(src),
+                                             _lib.ptr(dd), _lib.ptr(out)), self.ctx)
+        self._keep = (om, src, dd)
+        return torch.view_as_complex(out)
+
     def step_cholesky(self, theta, dt, n_steps, i_src, i_D=None, out=None):
         s, d = self._waves(n_steps, i_src, i_D)
         sig = out if out is not None else torch.empty(
