@@ -127,6 +127,18 @@ mm_status mm_step_modal(mm_ctx* ctx, double theta, double dt, int64_t n_steps,
 mm_status mm_step_modal_exact(mm_ctx* ctx, double dt, int64_t n_steps,
                               const double* i_src, const double* i_D, double* signal);
 
+/* The modal stepping of mm_step_modal (exact = 0, theta in [0, 1]) or of
+ * mm_step_modal_exact (exact != 0, theta ignored), parallel in time, for
+ * few modes and many steps: every mode's step is the affine map
+ * y -> A y + b_k, so the steps are cut into chunks that run from a zero state
+ * in parallel, are chained by A^L per mode, and run again from their start
+ * states (twice the mode-steps, (N/256) x (T/L) workgroups instead of N/256).
+ * Same arguments, state, signal (to rounding) and errors as those calls; at
+ * most 65535 x 2^16 steps.  Allocates 2 T/L N doubles of workspace. */
+mm_status mm_step_modal_scan(mm_ctx* ctx, double theta, int32_t exact, double dt,
+                             int64_t n_steps, const double* i_src, const double* i_D,
+                             double* signal);
+
 /* Steady-state phasors of the probe signals under sinusoidal sources, from
  * the decomposition (Sec. 3.2, eq. modal_decomposition_discrete; the
  * frequency-domain comparison of Sec. 4.5): with i0_c(t) = Re{A_c e^{jwt}}

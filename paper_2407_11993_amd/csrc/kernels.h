@@ -191,6 +191,11 @@ struct ModalPhasor {
 int64_t phasor_groups(int64_t n0);
 void modal_phasors(const ModalPhasor& mp, hipStream_t s);
 void modal_steps(const ModalStep& m, int64_t k0, int64_t n_steps, hipStream_t s);
+// The same steps cut into chunks of L steps run in parallel (few modes, many
+// steps); ws holds 2 ceil(n_steps / L) n0 doubles.  scan_chunk picks L.
+int64_t scan_chunk(int64_t n0, int64_t n_steps);
+void modal_steps_scan(const ModalStep& m, int64_t n_steps, int64_t L, double* ws,
+                      hipStream_t s);
 
 // Batched runs of the modal theta-method: run r drives one forcing column
 // wcol[r] of W with its own waveform (samples waves[woff[r] + k], k = 0..lens[r])

@@ -98,6 +98,7 @@ struct mm_ctx {
   bool use_graph = true;  // MM_NO_GRAPH=1 in the environment turns graphs off
   // probe partial sums of one step call
   Dev pp;
+  Dev scanws;  // chunk end values and start states of the time-parallel stepping
   Dev tmp;
   std::string err;
 
@@ -577,7 +578,8 @@ mm_status mm_decompose_projected(mm_ctx* c) {
 namespace {
 
 void step_modal_impl(mm_ctx* c, double theta, double dt, bool exact, int64_t n_steps,
-                     const double* i_src, const double* i_D, double* signal) {
+                     const double* i_src, const double* i_D, double* signal,
+                     bool scan = false) {
     MM_REQUIRE(c->decomposed, kState, "modal stepping before mm_decompose");
     check_steps(theta, dt, n_steps);
     check_run_columns(c);
@@ -600,7 +602,13 @@ void step_modal_impl(mm_ctx* c, double theta, double dt, bool exact, int64_t n_s
     ms.exact = exact;
     ms.y = c->y.d();
     ms.probe_partial = c->pp.d();
-    modal_steps(ms, 0, n_steps, s);
+    if (scan) {
+      const int64_t L = scan_chunk(c->n0, n_steps);
+      c->scanws.alloc(sizeof(double) * 2 * ceil_div(n_steps, L) * c->n0);
+      modal_steps_scan(ms, n_steps, L, c->scanws.d(), s);
+    } else {
+      modal_steps(ms, 0, n_steps, s);
+    }
     probe_finish(c->pp.d(), n_steps, G, c->n_probe, c->m ? c->PD.d() : nullptr, (int)c->m,
                  i_D, 0, dt, signal, s);
     if (c->m)
@@ -620,6 +628,14 @@ mm_status mm_step_modal_exact(mm_ctx* c, double dt, int64_t n_steps, const doubl
                               const double* i_D, double* signal) {
   if (!c) return MM_E_INVALID;
   return guarded(c, [&] { step_modal_impl(c, 0.5, dt, true, n_steps, i_src, i_D, signal); });
+}
+
+mm_status mm_step_modal_scan(mm_ctx* c, double theta, int32_t exact, double dt, int64_t n_steps,
+                             const double* i_src, const double* i_D, double* signal) {
+  if (!c) return MM_E_INVALID;
+  return guarded(c, [&] {
+    step_modal_impl(c, exact ? 0.5 : theta, dt, exact != 0, n_steps, i_src, i_D, signal, true);
+  });
 }
 
 mm_status mm_modal_phasors(mm_ctx* c, int64_t n_w, const double* omega, const double* amp_src,

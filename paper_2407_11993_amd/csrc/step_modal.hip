@@ -129,6 +129,152 @@ __global__ void __launch_bounds__(NT) modal_step_k(ModalStep ms, int64_t n_steps
   if (n < n0) ms.y[n] = y;
 }
 
+// ---------------------------------------------------------------------------
+// Time-parallel variant for few modes and many steps.  Per mode a step is the
+// affine map y -> A y + b_k (theta: A = 1 - c dt lam, b_k = c e_k; exact:
+// A = exp(-lam dt), b_k = beta e1_k + gamma e2_k).  The horizon is cut into
+// chunks of L steps: (1) every (mode group, chunk) workgroup runs its chunk
+// from a zero state and stores the end value Z; (2) one pass per mode chains
+// the chunks, y_{q+1} = A^len_q y_q + Z_q, giving every chunk's start state;
+// (3) the chunks are rerun from their start states and write the per-step
+// probe partials of the sequential kernel.  2 N T mode-steps instead of N T,
+// spread over (N / 256) x (T / L) workgroups instead of N / 256.
+// ---------------------------------------------------------------------------
+struct Coef {
+  double A, c, g;  // y_{k+1} = A y_k + c e_k (+ g e2_k for exact)
+};
+
+__device__ Coef mode_coef(const ModalStep& ms, double lam) {
+  Coef r;
+  const double x = ms.dt * lam;
+  if (ms.exact) {
+    const double al = -expm1(-x);
+    r.A = exp(-x);
+    if (x == 0.0) {
+      r.c = 1.0;
+      r.g = 0.5;
+    } else {
+      r.c = al / x;
+      if (x < 0.5) {
+        double term = 0.5;
+        r.g = 0.0;
+        for (int q = 0; q < 24; ++q) {
+          r.g += term;
+          term *= -x / (double)(q + 3);
+        }
+      } else {
+        r.g = (1.0 - r.c) / x;
+      }
+    }
+  } else {
+    r.c = 1.0 / (1.0 + ms.theta * x);
+    r.A = 1.0 - r.c * x;
+    r.g = 0.0;
+  }
+  return r;
+}
+
+template <int NF, int NP, bool PROBE>
+__global__ void __launch_bounds__(NT) modal_chunk_k(ModalStep ms, int64_t n_steps, int64_t L,
+                                                    const double* ystart, double* Z) {
+  __shared__ double red[2][NT / 64][NP > 0 ? NP : 1];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int64_t n = (int64_t)blockIdx.x * NT + t;
+  const int64_t n0 = ms.n0;
+  const int64_t q = blockIdx.y;
+  const int64_t k0 = q * L, k1 = min(k0 + L, n_steps);
+  const int nf = NF > 0 ? NF : ms.f.nf;
+  const int np = ms.n_probe;
+  const bool exact = ms.exact;
+  const double th = exact ? 0.0 : ms.theta;
+  const int mD = ms.f.m;
+  Coef cf{1.0, 0.0, 0.0};
+  double y = 0.0;
+  double w[MAXF], pt[NP > 0 ? NP : 1];
+  for (int j = 0; j < MAXF; ++j) w[j] = 0.0;
+  for (int p = 0; p < (NP > 0 ? NP : 1); ++p) pt[p] = 0.0;
+  if (n < n0) {
+    cf = mode_coef(ms, ms.lam[n]);
+    for (int j = 0; j < nf; ++j) w[j] = ms.W[n + (int64_t)j * n0];
+    if (PROBE) {
+      for (int p = 0; p < np; ++p) pt[p] = ms.Pt[n + (int64_t)p * n0];
+      y = ystart[q * n0 + n];
+    }
+  }
+  const int64_t G = gridDim.x;
+  for (int64_t k = k0; k < k1; ++k) {
+    double e = 0.0;
+#pragma unroll
+    for (int j = 0; j < MAXF; ++j)
+      if (j < nf) e += w[j] * forcing_u(ms.f, j, k, th, ms.dt);
+    double b = cf.c * e;
+    if (exact) {
+      double e2 = 0.0;
+#pragma unroll
+      for (int j = 0; j < MAXF; ++j)
+        if (j < mD)
+          e2 += w[j] * (-ms.dt * (ms.f.i_D[(k + 1) * mD + j] - ms.f.i_D[k * mD + j]));
+      b += cf.g * e2;
+    }
+    const double dy = (cf.A - 1.0) * y + b;
+    y += dy;
+    if (PROBE) {
+      const int buf = (int)(k & 1);
+#pragma unroll
+      for (int p = 0; p < (NP > 0 ? NP : 1); ++p) {
+        if (p < np) {
+          const double v = wave_sum(pt[p] * dy);
+          if (lane == 0) red[buf][wave][p] = v;
+        }
+      }
+      __syncthreads();
+      if (t < np) {
+        const double s = (red[buf][0][t] + red[buf][1][t]) + (red[buf][2][t] + red[buf][3][t]);
+        ms.probe_partial[(k * G + blockIdx.x) * np + t] = s;
+      }
+    }
+  }
+  if (!PROBE && n < n0) Z[q * n0 + n] = y;
+}
+
+// start states of the chunks: ystart[q n0 + n], q < Q; the final state to ms.y
+__global__ void modal_chain_k(ModalStep ms, int64_t n_steps, int64_t L, int64_t Q,
+                              const double* Z, double* ystart) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n0 = ms.n0;
+  if (n >= n0) return;
+  const Coef cf = mode_coef(ms, ms.lam[n]);
+  const double AL = pow(cf.A, (double)L);
+  const double Alast = pow(cf.A, (double)(n_steps - (Q - 1) * L));
+  double y = ms.y[n];
+  for (int64_t q = 0; q < Q; ++q) {
+    ystart[q * n0 + n] = y;
+    y = (q < Q - 1 ? AL : Alast) * y + Z[q * n0 + n];
+  }
+  ms.y[n] = y;
+}
+
+template <int NF, int NP>
+void launch_scan(const ModalStep& m, int64_t n_steps, int64_t L, int64_t Q, double* Z,
+                 double* ystart, hipStream_t s) {
+  const dim3 grid((unsigned)modal_groups(m.n0), (unsigned)Q);
+  hipLaunchKernelGGL((modal_chunk_k<NF, NP, false>), grid, dim3(NT), 0, s, m, n_steps, L,
+                     (const double*)nullptr, Z);
+  hipLaunchKernelGGL(modal_chain_k, dim3((unsigned)ceil_div(m.n0, 256)), dim3(256), 0, s, m,
+                     n_steps, L, Q, (const double*)Z, ystart);
+  hipLaunchKernelGGL((modal_chunk_k<NF, NP, true>), grid, dim3(NT), 0, s, m, n_steps, L,
+                     (const double*)ystart, (double*)nullptr);
+}
+
+template <int NF>
+void launch_scan_np(const ModalStep& m, int64_t n_steps, int64_t L, int64_t Q, double* Z,
+                    double* ystart, hipStream_t s) {
+  if (m.n_probe <= 1) launch_scan<NF, 1>(m, n_steps, L, Q, Z, ystart, s);
+  else if (m.n_probe <= 2) launch_scan<NF, 2>(m, n_steps, L, Q, Z, ystart, s);
+  else if (m.n_probe <= 4) launch_scan<NF, 4>(m, n_steps, L, Q, Z, ystart, s);
+  else launch_scan<NF, 8>(m, n_steps, L, Q, Z, ystart, s);
+}
+
 template <int NF>
 void launch_np(const ModalStep& m, int64_t n_steps, hipStream_t s, dim3 grid) {
   if (m.n_probe <= 1) hipLaunchKernelGGL((modal_step_k<NF, 1>), grid, dim3(NT), 0, s, m, n_steps);
@@ -281,6 +427,29 @@ void batch_steps(const BatchStep& b, int tile, int64_t total_steps, double* sign
 }
 
 int modal_groups(int64_t n0) { return (int)std::max<int64_t>(1, ceil_div(n0, NT)); }
+
+int64_t scan_chunk(int64_t n0, int64_t n_steps) {
+  // about 2048 workgroups, chunks of at least 32 steps, at most 65535 chunks
+  const int64_t want = std::max<int64_t>(1, 2048 / modal_groups(n0));
+  int64_t L = std::max<int64_t>(32, ceil_div(n_steps, want));
+  L = std::max<int64_t>(L, ceil_div(n_steps, 65535));
+  return L;
+}
+
+void modal_steps_scan(const ModalStep& m, int64_t n_steps, int64_t L, double* ws,
+                      hipStream_t s) {
+  if (n_steps <= 0) return;
+  MM_REQUIRE(m.f.nf <= MAXF, kInvalid, "modal_steps: too many forcing columns");
+  MM_REQUIRE(m.n_probe >= 1 && m.n_probe <= MAXP, kInvalid,
+             "modal_steps: 1..8 probes per run");
+  const int64_t Q = ceil_div(n_steps, L);
+  MM_REQUIRE(L >= 1 && Q <= 65535, kInvalid, "modal_steps_scan: at most 65535 chunks");
+  double* Z = ws;
+  double* ystart = ws + Q * m.n0;
+  if (m.f.nf == 1) launch_scan_np<1>(m, n_steps, L, Q, Z, ystart, s);
+  else launch_scan_np<0>(m, n_steps, L, Q, Z, ystart, s);
+  MM_HIP_TRY(hipGetLastError());
+}
 
 void modal_steps(const ModalStep& m, int64_t k0, int64_t n_steps, hipStream_t s) {
   (void)k0;

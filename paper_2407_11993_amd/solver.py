@@ -124,6 +124,17 @@ class Solver:
         self._keep = (s, d)
         return sig
 
+    def step_modal_scan(self, theta, dt, n_steps, i_src, i_D=None, exact=False, out=None):
+        """step_modal (or step_modal_exact with exact=True), parallel in time."""
+        s, d = self._waves(n_steps, i_src, i_D)
+        sig = out if out is not None else torch.empty(
+            (n_steps, self.n_probe), dtype=torch.float64, device=self.device)
+        _lib.check(self.lib.mm_step_modal_scan(self.ctx, float(theta), int(bool(exact)),
+                                               float(dt), int(n_steps), _lib.ptr(s),
+                                               _lib.ptr(d), _lib.ptr(sig)), self.ctx)
+        self._keep = (s, d)
+        return sig
+
     def phasors(self, omegas, amp_src, amp_D=None):
         """Steady-state phasors (n_w x n_probe, complex) of the probe signals
         P dI/dt for sources Re{amp_src[w, c] exp(j omegas[w] t)} and electrode
