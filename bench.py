@@ -186,6 +186,69 @@ def _electrode_workload(name, T):
     return inputs.electrode_plate(nx, ny, 16, T=T, name=f"plate-{nx}x{ny}-electrodes")
 
 
+def run_scan(args):
+    """Few modes, many steps: the 8x8x8 block (N = 512) stepped for 10^6 steps
+    (theta = 1/2) by the sequential modal kernel (one thread per mode over the
+    whole horizon: two workgroups) and by the time-parallel scan.  The
+    decomposition is shared and not timed."""
+    import numpy as np
+    import torch
+    from paper_2407_11993_amd import Solver, inputs
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    T = args.T or 1_000_000
+    w = inputs.config1(T=10)
+    t = np.arange(T + 1)
+    i_src = torch.as_tensor(np.sin(2 * np.pi * t / 200.0)[:, None], dtype=torch.float64,
+                            device="cuda")
+    s = Solver(w)
+    s.decompose()
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.reset()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        out = fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return out, e0.elapsed_time(e1) / 1e3
+
+    for _ in range(args.warmup):
+        timed(lambda: s.step_modal_scan(0.5, 1.0, T, i_src))
+    t0 = time.perf_counter()
+    runs = []
+    for _ in range(args.steps):
+        seq, t_seq = timed(lambda: s.step_modal(0.5, 1.0, T, i_src))
+        scn, t_scan = timed(lambda: s.step_modal_scan(0.5, 1.0, T, i_src))
+        agree = float((seq - scn).abs().max() / seq.abs().max())
+        runs.append((t_seq, t_scan, agree))
+        print(f"bench: sequential {t_seq:.3f} s, scan {t_scan:.4f} s", file=sys.stderr,
+              flush=True)
+    wall = time.perf_counter() - t0
+    t_seq = sum(r[0] for r in runs) / len(runs)
+    t_scan = sum(r[1] for r in runs) / len(runs)
+    mode_steps = 2.0 * w.n * T  # the scan's work: every chunk is run twice
+    achieved = FLOPS_PER_MODE_STEP * mode_steps / t_scan / 1e12
+    s.close()
+    return {
+        "metric": "modal stepping s, few modes and many steps (time-parallel scan)",
+        "value": round(t_scan, 4), "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * wall / args.steps, 1),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "scan-block-8x8x8", "N": w.n, "T": T, "theta": 0.5},
+        "sequential_s": round(t_seq, 4), "speedup_scan_vs_sequential": round(t_seq / t_scan, 1),
+        "signal_agreement_scan_vs_sequential": max(r[2] for r in runs),
+        "roofline": {"bound": "alu", "kernel": "time-parallel modal stepping (both passes)",
+                     "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+                     "traffic": None},
+    }
+
+
 def run_batched(args):
     """Config 4: 256 coil positions with their own waveform lengths, stepped
     in one graph-captured batched launch, against 256 sequential solves of
@@ -536,7 +599,7 @@ def main():
     ap.add_argument("--workload", default="plate-256x384-electrodes",
                     help="plate-256x384-electrodes (N = 98,304, 1e5 steps: the headline), "
                          "plate-WxH-electrodes, plate-128x128-crack, block-8x8x8, "
-                         "batched-coils-128x128, adjoint-128x256")
+                         "batched-coils-128x128, adjoint-128x256, scan-block-8x8x8")
     ap.add_argument("--T", type=int, default=None, help="override the step count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fd-cells", type=int, default=2,
@@ -554,6 +617,8 @@ def main():
         res = run_batched(args)
     elif args.workload.startswith("adjoint"):
         res = run_adjoint(args)
+    elif args.workload.startswith("scan"):
+        res = run_scan(args)
     elif args.workload.endswith("-electrodes"):
         res = run_electrodes(args)
         if not args.no_cpu_baseline:
