@@ -65,11 +65,13 @@ __device__ __forceinline__ bool tile_of(int bid, int tiles_m, int tiles_n, int c
   return true;
 }
 
-// Chunk size for T tiles: the largest power of two up to 64 that still gives
+// Chunk size for T tiles: the largest power of two up to 16 that still gives
 // every XCD at least 16 chunks (a partial last round of chunks then costs an
-// XCD at most 1/16 of its share).
+// XCD at most 1/16 of its share).  16 rather than 64: the finer deal lifts a
+// lower-triangular rank-512 update from 52 to 57 TFLOP/s and leaves full
+// products unchanged.
 int chunk_log2(int64_t T) {
-  int c = 6;
+  int c = 4;
   while (c > 0 && ((int64_t)8 * 16) << c > T) --c;
   return c;
 }
