@@ -84,10 +84,15 @@ __global__ void __launch_bounds__(NT) sb2st_stage(Band B, int n, int nb, int sta
   const int64_t rn0 = r0 + len;
   const int lenn = (int)max((int64_t)0, min((int64_t)nb, n - rn0));
   const int64_t task = off[s] + k;
-  __shared__ double Lb[64][65], Db[64][65], Bb[64][65];
+  // The block below (Bb, rows rn0.., columns r0..) only takes the right
+  // application Bb -= tau (Bb v) v^T: each thread keeps its 16 entries (row
+  // lane, columns wave + 4 q) in registers from load to store, so the LDS
+  // holds two blocks (two workgroups fit on a CU).
+  __shared__ double Lb[64][65], Db[64][65];
   __shared__ double v[64], p4[4][64], w_s[64];
   __shared__ double s_tau, s_beta;
   double yv[YQ];  // rows R_k of Y (lane = row), columns wave + 4 q
+  double rb[16];  // Bb(lane, wave + 4 q), zero outside the block
 
   // ---- stage: all loads are issued before the first LDS store (addresses
   // clamped into the block, values selected)
@@ -98,7 +103,7 @@ __global__ void __launch_bounds__(NT) sb2st_stage(Band B, int n, int nb, int sta
       const int c = wave + 4 * q;
       yv[q] = (c < ny) ? Y[(r0 + li) + c * ldy] : 0.0;
     }
-    double rl[16], rd[16], rb[16];
+    double rl[16], rd[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int j = wave + 4 * q;
@@ -112,7 +117,7 @@ __global__ void __launch_bounds__(NT) sb2st_stage(Band B, int n, int nb, int sta
       const int j = wave + 4 * q;
       Lb[lane][j] = (lane < len && j < ncl) ? rl[q] : 0.0;
       Db[lane][j] = (lane < len && j < len) ? rd[q] : 0.0;
-      Bb[lane][j] = (lane < lenn && j < len) ? rb[q] : 0.0;
+      if (!(lane < lenn && j < len)) rb[q] = 0.0;
     }
   }
   __syncthreads();
@@ -187,23 +192,22 @@ __global__ void __launch_bounds__(NT) sb2st_stage(Band B, int n, int nb, int sta
   if (lenn > 0) {
     double acc = 0.0;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) acc += Bb[lane][wave + 4 * q] * v[wave + 4 * q];
+    for (int q = 0; q < 16; ++q) acc += rb[q] * v[wave + 4 * q];
     p4[wave][lane] = acc;  // p4 was last read before the barriers above
     __syncthreads();
     const double tq = tau * ((p4[0][lane] + p4[1][lane]) + (p4[2][lane] + p4[3][lane]));
 #pragma unroll
-    for (int q = 0; q < 16; ++q) Bb[lane][wave + 4 * q] -= tq * v[wave + 4 * q];
+    for (int q = 0; q < 16; ++q) rb[q] -= tq * v[wave + 4 * q];
   }
   __syncthreads();
   // ---- write back: read every value first, then store
   {
-    double rl[16], rd[16], rb[16];
+    double rl[16], rd[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int j = wave + 4 * q;
       rl[q] = Lb[lane][j];
       rd[q] = Db[lane][j];
-      rb[q] = Bb[lane][j];
     }
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
