@@ -84,14 +84,16 @@ __global__ void __launch_bounds__(NT) sb2st_stage(Band B, int n, int nb, int sta
   const int64_t rn0 = r0 + len;
   const int lenn = (int)max((int64_t)0, min((int64_t)nb, n - rn0));
   const int64_t task = off[s] + k;
-  // The block below (Bb, rows rn0.., columns r0..) only takes the right
-  // application Bb -= tau (Bb v) v^T: each thread keeps its 16 entries (row
-  // lane, columns wave + 4 q) in registers from load to store, so the LDS
-  // holds two blocks (two workgroups fit on a CU).
-  __shared__ double Lb[64][65], Db[64][65];
+  // The diagonal block (D) and the block below (Bb, rows rn0.., columns r0..)
+  // take only updates in which a thread reads and writes its own 16 entries
+  // (row lane, columns wave + 4 q) and exchanges one row sum per wave through
+  // p4: both stay in registers from load to store.  Only the left block,
+  // whose update needs column sums, is staged in LDS.
+  __shared__ double Lb[64][65];
   __shared__ double v[64], p4[4][64], w_s[64];
   __shared__ double s_tau, s_beta;
   double yv[YQ];  // rows R_k of Y (lane = row), columns wave + 4 q
+  double rd[16];  // D(lane, wave + 4 q), zero outside the block
   double rb[16];  // Bb(lane, wave + 4 q), zero outside the block
 
   // ---- stage: all loads are issued before the first LDS store (addresses
@@ -103,7 +105,7 @@ __global__ void __launch_bounds__(NT) sb2st_stage(Band B, int n, int nb, int sta
       const int c = wave + 4 * q;
       yv[q] = (c < ny) ? Y[(r0 + li) + c * ldy] : 0.0;
     }
-    double rl[16], rd[16];
+    double rl[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int j = wave + 4 * q;
@@ -116,7 +118,7 @@ __global__ void __launch_bounds__(NT) sb2st_stage(Band B, int n, int nb, int sta
     for (int q = 0; q < 16; ++q) {
       const int j = wave + 4 * q;
       Lb[lane][j] = (lane < len && j < ncl) ? rl[q] : 0.0;
-      Db[lane][j] = (lane < len && j < len) ? rd[q] : 0.0;
+      if (!(lane < len && j < len)) rd[q] = 0.0;
       if (!(lane < lenn && j < len)) rb[q] = 0.0;
     }
   }
@@ -173,7 +175,7 @@ __global__ void __launch_bounds__(NT) sb2st_stage(Band B, int n, int nb, int sta
   {
     double acc = 0.0;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) acc += Db[lane][wave + 4 * q] * v[wave + 4 * q];
+    for (int q = 0; q < 16; ++q) acc += rd[q] * v[wave + 4 * q];
     p4[wave][lane] = acc;
   }
   __syncthreads();
@@ -186,7 +188,7 @@ __global__ void __launch_bounds__(NT) sb2st_stage(Band B, int n, int nb, int sta
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const int j = wave + 4 * q;
-    Db[lane][j] -= vl * w_s[j] + wl * v[j];
+    rd[q] -= vl * w_s[j] + wl * v[j];
   }
   // ---- right application to the block below: Bb -= tau (Bb v) v^T
   if (lenn > 0) {
@@ -202,12 +204,11 @@ __global__ void __launch_bounds__(NT) sb2st_stage(Band B, int n, int nb, int sta
   __syncthreads();
   // ---- write back: read every value first, then store
   {
-    double rl[16], rd[16];
+    double rl[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int j = wave + 4 * q;
       rl[q] = Lb[lane][j];
-      rd[q] = Db[lane][j];
     }
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
