@@ -34,6 +34,31 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+  const int2 b = __builtin_bit_cast(int2, v);
+  int2 r;
+  r.x = __builtin_amdgcn_update_dpp(0, b.x, CTRL, 0xF, 0xF, false);
+  r.y = __builtin_amdgcn_update_dpp(0, b.y, CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, r);
+}
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const int2 b = __builtin_bit_cast(int2, v);
+  int2 r;
+  r.x = __builtin_amdgcn_readlane(b.x, l);
+  r.y = __builtin_amdgcn_readlane(b.y, l);
+  return __builtin_bit_cast(double, r);
+}
+// quads and rows of 16 by DPP (xor 1, xor 2, half-row and row mirrors), then
+// the four rows' sums by readlane, added in a fixed order
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v += dpp<0xB1>(v);
+  v += dpp<0x4E>(v);
+  v += dpp<0x141>(v);
+  v += dpp<0x140>(v);
+  return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
+}
+
 __device__ __forceinline__ double forcing_u(const Forcing& f, int j, int64_t k,
                                             double theta, double dt) {
   if (j < f.m) {
@@ -48,9 +73,11 @@ __device__ __forceinline__ double forcing_u(const Forcing& f, int j, int64_t k,
   return -(f.i_src[(k + 1) * f.n_src + c] - f.i_src[k * f.n_src + c]);
 }
 
+constexpr int SM = 8;  // steps whose probe sums are reduced together
+
 template <int NF, int NP>
 __global__ void __launch_bounds__(NT) modal_step_k(ModalStep ms, int64_t n_steps) {
-  __shared__ double red[2][NT / 64][NP > 0 ? NP : 1];
+  __shared__ double red[2][SM][NT / 64][NP > 0 ? NP : 1];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int64_t n = (int64_t)blockIdx.x * NT + t;
   const int64_t n0 = ms.n0;
@@ -95,35 +122,53 @@ __global__ void __launch_bounds__(NT) modal_step_k(ModalStep ms, int64_t n_steps
   }
   const int64_t G = gridDim.x;
   const int mD = ms.f.m;
-  for (int64_t k = 0; k < n_steps; ++k) {
-    double e = 0.0;
+  // Probe contributions of SM steps are kept per thread and reduced together:
+  // one DPP wave sum each, one barrier per SM steps (LDS double-buffered by
+  // batch parity), then threads t < SM np sum the four waves in order.
+  for (int64_t k0 = 0; k0 < n_steps; k0 += SM) {
+    double acc[SM][NP > 0 ? NP : 1];
 #pragma unroll
-    for (int j = 0; j < MAXF; ++j)
-      if (j < nf) e += w[j] * forcing_u(ms.f, j, k, th, ms.dt);
-    double dy;
-    if (exact) {
-      double e2 = 0.0;  // -dt (iD^{k+1} - iD^k) on the R_D columns
+    for (int i = 0; i < SM; ++i) {
+      const int64_t k = k0 + i;
+      double dy = 0.0;
+      if (k < n_steps) {
+        double e = 0.0;
 #pragma unroll
-      for (int j = 0; j < MAXF; ++j)
-        if (j < mD)
-          e2 += w[j] * (-ms.dt * (ms.f.i_D[(k + 1) * mD + j] - ms.f.i_D[k * mD + j]));
-      dy = c * e + g * e2 - a * y;
-    } else {
-      dy = c * (e - a * y);
-    }
-    y += dy;
-    const int buf = (int)(k & 1);
+        for (int j = 0; j < MAXF; ++j)
+          if (j < nf) e += w[j] * forcing_u(ms.f, j, k, th, ms.dt);
+        if (exact) {
+          double e2 = 0.0;  // -dt (iD^{k+1} - iD^k) on the R_D columns
 #pragma unroll
-    for (int p = 0; p < (NP > 0 ? NP : 1); ++p) {
-      if (p < np) {
-        const double v = wave_sum(pt[p] * dy);
-        if (lane == 0) red[buf][wave][p] = v;
+          for (int j = 0; j < MAXF; ++j)
+            if (j < mD)
+              e2 += w[j] * (-ms.dt * (ms.f.i_D[(k + 1) * mD + j] - ms.f.i_D[k * mD + j]));
+          dy = c * e + g * e2 - a * y;
+        } else {
+          dy = c * (e - a * y);
+        }
+        y += dy;
       }
+#pragma unroll
+      for (int p = 0; p < (NP > 0 ? NP : 1); ++p) acc[i][p] = pt[p] * dy;
     }
+    const int buf = (int)((k0 / SM) & 1);
+#pragma unroll
+    for (int i = 0; i < SM; ++i)
+#pragma unroll
+      for (int p = 0; p < (NP > 0 ? NP : 1); ++p)
+        if (p < np) {
+          const double v = wave_sum_dpp(acc[i][p]);
+          if (lane == 0) red[buf][i][wave][p] = v;
+        }
     __syncthreads();
-    if (t < np) {
-      const double s = (red[buf][0][t] + red[buf][1][t]) + (red[buf][2][t] + red[buf][3][t]);
-      ms.probe_partial[(k * G + blockIdx.x) * np + t] = s;
+    if (t < SM * np) {
+      const int i = t / np, p = t % np;
+      const int64_t k = k0 + i;
+      if (k < n_steps) {
+        const double s = (red[buf][i][0][p] + red[buf][i][1][p]) +
+                         (red[buf][i][2][p] + red[buf][i][3][p]);
+        ms.probe_partial[(k * G + blockIdx.x) * np + p] = s;
+      }
     }
   }
   if (n < n0) ms.y[n] = y;
@@ -290,31 +335,6 @@ void launch_np(const ModalStep& m, int64_t n_steps, hipStream_t s, dim3 grid) {
 // and reduced (wave by DPP moves, workgroup through LDS) once per S steps.
 // ---------------------------------------------------------------------------
 constexpr int S = 8;  // steps per reduction
-
-template <int CTRL>
-__device__ __forceinline__ double dpp(double v) {
-  const int2 b = __builtin_bit_cast(int2, v);
-  int2 r;
-  r.x = __builtin_amdgcn_update_dpp(0, b.x, CTRL, 0xF, 0xF, false);
-  r.y = __builtin_amdgcn_update_dpp(0, b.y, CTRL, 0xF, 0xF, false);
-  return __builtin_bit_cast(double, r);
-}
-__device__ __forceinline__ double lane_value(double v, int l) {
-  const int2 b = __builtin_bit_cast(int2, v);
-  int2 r;
-  r.x = __builtin_amdgcn_readlane(b.x, l);
-  r.y = __builtin_amdgcn_readlane(b.y, l);
-  return __builtin_bit_cast(double, r);
-}
-// quads and rows of 16 by DPP (xor 1, xor 2, half-row and row mirrors), then
-// the four rows' sums by readlane, added in a fixed order
-__device__ __forceinline__ double wave_sum_dpp(double v) {
-  v += dpp<0xB1>(v);
-  v += dpp<0x4E>(v);
-  v += dpp<0x141>(v);
-  v += dpp<0x140>(v);
-  return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
-}
 
 template <int NTB, int MPT>
 __global__ void __launch_bounds__(NTB) batch_step_k(BatchStep b) {
