@@ -78,6 +78,9 @@ constexpr int SM = 8;  // steps whose probe sums are reduced together
 template <int NF, int NP>
 __global__ void __launch_bounds__(NT) modal_step_k(ModalStep ms, int64_t n_steps) {
   __shared__ double red[2][SM][NT / 64][NP > 0 ? NP : 1];
+  // waveform samples of a batch, rows k0 .. k0 + SM of [i_src | i_D], staged
+  // one batch ahead (loaded while the current batch computes)
+  __shared__ double wv[2][SM + 1][MAXF];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int64_t n = (int64_t)blockIdx.x * NT + t;
   const int64_t n0 = ms.n0;
@@ -125,33 +128,50 @@ __global__ void __launch_bounds__(NT) modal_step_k(ModalStep ms, int64_t n_steps
   // Probe contributions of SM steps are kept per thread and reduced together:
   // one DPP wave sum each, one barrier per SM steps (LDS double-buffered by
   // batch parity), then threads t < SM np sum the four waves in order.
+  const int ns = ms.f.n_src, nwc = ns + mD;  // <= nf <= MAXF waveform columns
+  const bool stager = t < (SM + 1) * nwc;
+  const int sr = stager ? t / nwc : 0, sc = stager ? t % nwc : 0;
+  auto sample = [&](int64_t k0n) {  // row k0n + sr (clamped to the last sample)
+    const int64_t k = min(k0n + sr, n_steps);
+    return sc < ns ? ms.f.i_src[k * ns + sc] : ms.f.i_D[k * mD + (sc - ns)];
+  };
+  if (stager) wv[0][sr][sc] = sample(0);
+  __syncthreads();
   for (int64_t k0 = 0; k0 < n_steps; k0 += SM) {
+    const int buf = (int)((k0 / SM) & 1);
+    const double next = (stager && k0 + SM < n_steps) ? sample(k0 + SM) : 0.0;
     double acc[SM][NP > 0 ? NP : 1];
 #pragma unroll
     for (int i = 0; i < SM; ++i) {
       const int64_t k = k0 + i;
       double dy = 0.0;
       if (k < n_steps) {
-        double e = 0.0;
+        const double* S0 = wv[buf][i];      // samples k
+        const double* S1 = wv[buf][i + 1];  // samples k + 1
+        double e = 0.0, e2 = 0.0;
 #pragma unroll
-        for (int j = 0; j < MAXF; ++j)
-          if (j < nf) e += w[j] * forcing_u(ms.f, j, k, th, ms.dt);
-        if (exact) {
-          double e2 = 0.0;  // -dt (iD^{k+1} - iD^k) on the R_D columns
-#pragma unroll
-          for (int j = 0; j < MAXF; ++j)
-            if (j < mD)
-              e2 += w[j] * (-ms.dt * (ms.f.i_D[(k + 1) * mD + j] - ms.f.i_D[k * mD + j]));
-          dy = c * e + g * e2 - a * y;
-        } else {
-          dy = c * (e - a * y);
+        for (int j = 0; j < MAXF; ++j) {
+          if (j < nf) {
+            double u;
+            if (j < mD) {  // R_D: -dt (iD^k + theta d iD)
+              const double a0 = S0[ns + j], a1 = S1[ns + j];
+              u = -ms.dt * (a0 + th * (a1 - a0));
+              e2 += w[j] * (-ms.dt * (a1 - a0));
+            } else if (j < 2 * mD) {  // L_D: -d iD
+              u = -(S1[ns + j - mD] - S0[ns + j - mD]);
+            } else {  // sources: -d i0
+              u = -(S1[j - 2 * mD] - S0[j - 2 * mD]);
+            }
+            e += w[j] * u;
+          }
         }
+        dy = exact ? c * e + g * e2 - a * y : c * (e - a * y);
         y += dy;
       }
 #pragma unroll
       for (int p = 0; p < (NP > 0 ? NP : 1); ++p) acc[i][p] = pt[p] * dy;
     }
-    const int buf = (int)((k0 / SM) & 1);
+    if (stager && k0 + SM < n_steps) wv[buf ^ 1][sr][sc] = next;
 #pragma unroll
     for (int i = 0; i < SM; ++i)
 #pragma unroll
