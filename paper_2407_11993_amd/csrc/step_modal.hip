@@ -242,12 +242,13 @@ __device__ Coef mode_coef(const ModalStep& ms, double lam) {
 template <int NF, int NP, bool PROBE>
 __global__ void __launch_bounds__(NT) modal_chunk_k(ModalStep ms, int64_t n_steps, int64_t L,
                                                     const double* ystart, double* Z) {
-  __shared__ double red[2][NT / 64][NP > 0 ? NP : 1];
+  __shared__ double red[2][SM][NT / 64][NP > 0 ? NP : 1];
+  __shared__ double wv[2][SM + 1][MAXF];  // waveform samples, one batch ahead
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int64_t n = (int64_t)blockIdx.x * NT + t;
   const int64_t n0 = ms.n0;
   const int64_t q = blockIdx.y;
-  const int64_t k0 = q * L, k1 = min(k0 + L, n_steps);
+  const int64_t kc0 = q * L, kc1 = min(kc0 + L, n_steps);
   const int nf = NF > 0 ? NF : ms.f.nf;
   const int np = ms.n_probe;
   const bool exact = ms.exact;
@@ -267,35 +268,72 @@ __global__ void __launch_bounds__(NT) modal_chunk_k(ModalStep ms, int64_t n_step
     }
   }
   const int64_t G = gridDim.x;
-  for (int64_t k = k0; k < k1; ++k) {
-    double e = 0.0;
+  // batches of SM steps as in modal_step_k: samples staged one batch ahead,
+  // probe sums of the batch reduced together
+  const int ns = ms.f.n_src, nwc = ns + mD;
+  const bool stager = t < (SM + 1) * nwc;
+  const int sr = stager ? t / nwc : 0, sc = stager ? t % nwc : 0;
+  auto sample = [&](int64_t k0n) {
+    const int64_t k = min(k0n + sr, n_steps);
+    return sc < ns ? ms.f.i_src[k * ns + sc] : ms.f.i_D[k * mD + (sc - ns)];
+  };
+  if (stager) wv[0][sr][sc] = sample(kc0);
+  __syncthreads();
+  for (int64_t k0 = kc0; k0 < kc1; k0 += SM) {
+    const int buf = (int)(((k0 - kc0) / SM) & 1);
+    const double next = (stager && k0 + SM < kc1) ? sample(k0 + SM) : 0.0;
+    double acc[SM][NP > 0 ? NP : 1];
 #pragma unroll
-    for (int j = 0; j < MAXF; ++j)
-      if (j < nf) e += w[j] * forcing_u(ms.f, j, k, th, ms.dt);
-    double b = cf.c * e;
-    if (exact) {
-      double e2 = 0.0;
+    for (int i = 0; i < SM; ++i) {
+      const int64_t k = k0 + i;
+      double dy = 0.0;
+      if (k < kc1) {
+        const double* S0 = wv[buf][i];
+        const double* S1 = wv[buf][i + 1];
+        double e = 0.0, e2 = 0.0;
 #pragma unroll
-      for (int j = 0; j < MAXF; ++j)
-        if (j < mD)
-          e2 += w[j] * (-ms.dt * (ms.f.i_D[(k + 1) * mD + j] - ms.f.i_D[k * mD + j]));
-      b += cf.g * e2;
-    }
-    const double dy = (cf.A - 1.0) * y + b;
-    y += dy;
-    if (PROBE) {
-      const int buf = (int)(k & 1);
-#pragma unroll
-      for (int p = 0; p < (NP > 0 ? NP : 1); ++p) {
-        if (p < np) {
-          const double v = wave_sum(pt[p] * dy);
-          if (lane == 0) red[buf][wave][p] = v;
+        for (int j = 0; j < MAXF; ++j) {
+          if (j < nf) {
+            double u;
+            if (j < mD) {
+              const double a0 = S0[ns + j], a1 = S1[ns + j];
+              u = -ms.dt * (a0 + th * (a1 - a0));
+              e2 += w[j] * (-ms.dt * (a1 - a0));
+            } else if (j < 2 * mD) {
+              u = -(S1[ns + j - mD] - S0[ns + j - mD]);
+            } else {
+              u = -(S1[j - 2 * mD] - S0[j - 2 * mD]);
+            }
+            e += w[j] * u;
+          }
         }
+        double b = cf.c * e;
+        if (exact) b += cf.g * e2;
+        dy = (cf.A - 1.0) * y + b;
+        y += dy;
       }
-      __syncthreads();
-      if (t < np) {
-        const double s = (red[buf][0][t] + red[buf][1][t]) + (red[buf][2][t] + red[buf][3][t]);
-        ms.probe_partial[(k * G + blockIdx.x) * np + t] = s;
+#pragma unroll
+      for (int p = 0; p < (NP > 0 ? NP : 1); ++p) acc[i][p] = pt[p] * dy;
+    }
+    if (stager && k0 + SM < kc1) wv[buf ^ 1][sr][sc] = next;
+    if (PROBE) {
+#pragma unroll
+      for (int i = 0; i < SM; ++i)
+#pragma unroll
+        for (int p = 0; p < (NP > 0 ? NP : 1); ++p)
+          if (p < np) {
+            const double v = wave_sum_dpp(acc[i][p]);
+            if (lane == 0) red[buf][i][wave][p] = v;
+          }
+    }
+    __syncthreads();
+    if (PROBE && t < SM * np) {
+      const int i = t / np, p = t % np;
+      const int64_t k = k0 + i;
+      if (k < kc1) {
+        const double s = (red[buf][i][0][p] + red[buf][i][1][p]) +
+                         (red[buf][i][2][p] + red[buf][i][3][p]);
+        ms.probe_partial[(k * G + blockIdx.x) * np + p] = s;
       }
     }
   }
