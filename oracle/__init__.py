@@ -20,6 +20,10 @@ Decomposition in Numerical Computation of Eddy Current Transients"):
                            closed form over each step, waveforms linear between
                            samples (the analytical route of Sec. 3.3 left to later work).
 * ``exact_phi``         -- the two step integrals that closed form uses.
+* ``mode_weights``      -- the modal forcing and probe weights (Sec. 3.2).
+* ``select_modes``      -- the modes kept by the selective solution of Sec. 3.2
+                           (coupling score above a relative tolerance); the
+                           modal steppers take the kept set as ``keep``.
 * ``phasors_direct``    -- steady-state probe phasors under sinusoidal sources: one
                            complex solve of the unreduced system per frequency (the
                            frequency-domain method of Sec. 4.5).
@@ -39,6 +43,7 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 _dp = ctypes.POINTER(ctypes.c_double)
+_u8p = ctypes.POINTER(ctypes.c_uint8)
 _i64 = ctypes.c_int64
 
 
@@ -81,11 +86,13 @@ def _load():
         lib.orc_theta_direct.restype = ctypes.c_int
         lib.orc_theta_modal.argtypes = [
             ctypes.POINTER(_Problem), ctypes.c_double, ctypes.c_double, _i64,
-            _dp, _dp, _dp, _dp, _dp]
+            _dp, _dp, _dp, _dp, _dp, _u8p]
         lib.orc_theta_modal.restype = ctypes.c_int
         lib.orc_exact_modal.argtypes = [
-            ctypes.POINTER(_Problem), ctypes.c_double, _i64, _dp, _dp, _dp, _dp]
+            ctypes.POINTER(_Problem), ctypes.c_double, _i64, _dp, _dp, _dp, _dp, _u8p]
         lib.orc_exact_modal.restype = ctypes.c_int
+        lib.orc_mode_weights.argtypes = [ctypes.POINTER(_Problem), _dp, _dp, _dp]
+        lib.orc_mode_weights.restype = ctypes.c_int
         lib.orc_exact_phi.argtypes = [ctypes.c_double, ctypes.c_double, _dp, _dp]
         lib.orc_modal_eigen.argtypes = [
             ctypes.POINTER(_Problem), _dp, _dp, ctypes.POINTER(ctypes.c_int)]
@@ -257,17 +264,28 @@ def theta_direct(pb: Problem, theta: float, dt: float, T: int, i_src=None,
     return (sig, I_hist) if want_I else sig
 
 
+def _keep(pb: Problem, keep):
+    if keep is None:
+        return None
+    k = np.ascontiguousarray(np.asarray(keep, dtype=bool).astype(np.uint8))
+    assert k.shape == (pb.n - pb.m,)
+    return k
+
+
 def theta_modal(pb: Problem, theta: float, dt: float, T: int, i_src=None,
-                i_D=None, want_I: bool = False):
-    """Modal theta-method; returns (signal, lam) [+ I_hist]."""
+                i_D=None, want_I: bool = False, keep=None):
+    """Modal theta-method; returns (signal, lam) [+ I_hist].  keep (n0
+    booleans, modes in ascending eigenvalue order) steps only those modes."""
     i_src, i_D = pb._waves(T, i_src, i_D)
+    kp = _keep(pb, keep)
     sig = np.zeros((T, max(pb.n_probe, 1)))
     lam = np.zeros(pb.n - pb.m)
     I_hist = np.zeros((T + 1, pb.n)) if want_I else None
     st = pb._struct()
     rc = _load().orc_theta_modal(ctypes.byref(st), float(theta), float(dt),
                                  int(T), _ptr(i_src), _ptr(i_D), _ptr(sig),
-                                 _ptr(lam), _ptr(I_hist))
+                                 _ptr(lam), _ptr(I_hist),
+                                 None if kp is None else kp.ctypes.data_as(_u8p))
     if rc:
         raise RuntimeError(_ERR.get(rc, str(rc)))
     sig = sig[:, :pb.n_probe]
@@ -275,15 +293,18 @@ def theta_modal(pb: Problem, theta: float, dt: float, T: int, i_src=None,
 
 
 def exact_modal(pb: Problem, dt: float, T: int, i_src=None, i_D=None,
-                want_I: bool = False):
+                want_I: bool = False, keep=None):
     """Modal stepping with exact per-mode integration of waveforms that are
-    linear between samples; returns signal (T x n_probe) [, I_hist]."""
+    linear between samples; returns signal (T x n_probe) [, I_hist].  keep
+    as in theta_modal."""
     i_src, i_D = pb._waves(T, i_src, i_D)
+    kp = _keep(pb, keep)
     sig = np.zeros((T, max(pb.n_probe, 1)))
     I_hist = np.zeros((T + 1, pb.n)) if want_I else None
     st = pb._struct()
     rc = _load().orc_exact_modal(ctypes.byref(st), float(dt), int(T), _ptr(i_src),
-                                 _ptr(i_D), _ptr(sig), _ptr(I_hist))
+                                 _ptr(i_D), _ptr(sig), _ptr(I_hist),
+                                 None if kp is None else kp.ctypes.data_as(_u8p))
     if rc:
         raise RuntimeError(_ERR.get(rc, str(rc)))
     sig = sig[:, :pb.n_probe]
@@ -325,6 +346,40 @@ def phasors_direct(pb: Problem, omegas, amp_src, amp_D=None):
         I = np.linalg.solve(A, rhs)[:n]
         out[w] = 1j * om * (pb.P @ I)
     return out
+
+
+def mode_weights(pb: Problem):
+    """(lam, W, Pw): eigenvalues (ascending), the modal forcing weights
+    W = V^T [R_D | L_D | K^T M0] (n0 x (2m + n_src)) and the modal probe weights
+    Pw = (P K V)^T (n0 x n_probe), V the Li-normalised eigenvectors (Sec. 3.2)."""
+    n0 = pb.n - pb.m
+    nf = 2 * pb.m + pb.n_src
+    lam = np.zeros(n0)
+    W = np.zeros((n0, max(nf, 1)))
+    Pw = np.zeros((n0, max(pb.n_probe, 1)))
+    st = pb._struct()
+    rc = _load().orc_mode_weights(ctypes.byref(st), _ptr(lam), _ptr(W), _ptr(Pw))
+    if rc:
+        raise RuntimeError(_ERR.get(rc, str(rc)))
+    return lam, W[:, :nf], Pw[:, :pb.n_probe]
+
+
+def select_modes(pb: Problem, tol: float):
+    """Selective solution of the decoupled modal equations (Sec. 3.2, reading
+    13): mode n is kept when its coupling score
+        score_n = max_j |W(n, j)| * max_p |Pw(n, p)|
+    exceeds tol times the largest score (tol >= 0; every source and electrode
+    column counts with unit amplitude).  A mode with score 0 is never excited
+    or never seen, so tol = 0 drops only modes that cannot change a probe
+    signal.  Returns (keep, score), keep a boolean per mode in ascending
+    eigenvalue order."""
+    assert tol >= 0
+    _, W, Pw = mode_weights(pb)
+    a = np.abs(W).max(axis=1) if W.shape[1] else np.zeros(W.shape[0])
+    b = np.abs(Pw).max(axis=1) if Pw.shape[1] else np.zeros(Pw.shape[0])
+    score = a * b
+    top = score.max() if score.size else 0.0
+    return score > tol * top, score
 
 
 def modal_eigen(pb: Problem, want_V: bool = True):

@@ -658,6 +658,56 @@ int orc_modal_eigen(const orc_problem *pb, double *lam, double *V, int *sweeps)
     return rc;
 }
 
+/* Modal coupling weights (Sec. 3.2, eq. modal_decomposition_discrete): with */
+/* the Li-normalised eigenvectors V, the forcing of mode n by column j of    */
+/* [RD | LD | Mi] is W(n, j) = (V^T [RD | LD | Mi])(n, j), and its weight in  */
+/* probe p is Pw(n, p) = (P K V)(p, n).  A mode with a zero row in W is never */
+/* excited from I(0) = 0; one with a zero row in Pw is never seen by a probe. */
+/* W is n0 x (2m + n_src), Pw n0 x n_probe, both row-major; lam may be NULL. */
+int orc_mode_weights(const orc_problem *pb, double *lam_out, double *W, double *Pw)
+{
+    orc_reduced r;
+    const int64_t n0 = pb->n - pb->m, m = pb->m, ns = pb->n_src;
+    const int64_t nf = 2 * m + ns, np = pb->n_probe;
+    double *lam = (double *)malloc(sizeof(double) * (size_t)n0);
+    double *V = (double *)malloc(sizeof(double) * (size_t)(n0 * n0));
+    int rc = modal_parts(pb, &r, lam, V, NULL);
+    if (rc) {
+        free(lam);
+        free(V);
+        free_reduced(&r);
+        return rc;
+    }
+    for (int64_t nn = 0; nn < n0; ++nn) {
+        for (int64_t j = 0; j < nf; ++j) {
+            double s = 0.0;
+            for (int64_t i = 0; i < n0; ++i) {
+                double f;
+                if (j < m)
+                    f = r.RD[IDX(i, j, m)];
+                else if (j < 2 * m)
+                    f = r.LD[IDX(i, j - m, m)];
+                else
+                    f = r.Mi[IDX(i, j - 2 * m, ns)];
+                s += V[IDX(i, nn, n0)] * f;
+            }
+            W[IDX(nn, j, nf)] = s;
+        }
+        for (int64_t p = 0; p < np; ++p) {
+            double s = 0.0;
+            for (int64_t i = 0; i < n0; ++i)
+                s += r.PK[IDX(p, i, n0)] * V[IDX(i, nn, n0)];
+            Pw[IDX(nn, p, np)] = s;
+        }
+    }
+    if (lam_out)
+        memcpy(lam_out, lam, sizeof(double) * (size_t)n0);
+    free(lam);
+    free(V);
+    free_reduced(&r);
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* The modal theta-method (Sec. 3.3.2).  In the basis of Li-normalised       */
 /* generalized eigenvectors V the system decouples into                      */
@@ -666,11 +716,13 @@ int orc_modal_eigen(const orc_problem *pb, double *lam, double *V, int *sweeps)
 /*   (1 + theta dt lam_n) dy_n = -dt lam_n y_n + (V^T f^k)_n,                */
 /* where f^k is the same forcing as in the Cholesky method (reading r1).     */
 /* Ii = V y, so the probe signal is P (K V dy + AD d iD) / dt.               */
-/* lam_out (n0) and I_hist ((T+1) x n) may be NULL.                          */
+/* lam_out (n0) and I_hist ((T+1) x n) may be NULL.  keep (n0 flags, or      */
+/* NULL = every mode) solves only the flagged decoupled equations (the       */
+/* selective solution that Sec. 3.2 allows); the others stay at y_n = 0.     */
 /* ------------------------------------------------------------------------ */
 int orc_theta_modal(const orc_problem *pb, double theta, double dt, int64_t T,
                     const double *i_src, const double *i_D, double *signal,
-                    double *lam_out, double *I_hist)
+                    double *lam_out, double *I_hist, const unsigned char *keep)
 {
     orc_reduced r;
     const int64_t n0 = pb->n - pb->m;
@@ -698,7 +750,9 @@ int orc_theta_modal(const orc_problem *pb, double theta, double dt, int64_t T,
             double e = 0.0; /* modal forcing (V^T f)_n */
             for (int64_t i = 0; i < n0; ++i)
                 e += V[IDX(i, nn, n0)] * f[i];
-            dy[nn] = (-dt * lam[nn] * y[nn] + e) / (1.0 + theta * dt * lam[nn]);
+            dy[nn] = (keep && !keep[nn])
+                         ? 0.0
+                         : (-dt * lam[nn] * y[nn] + e) / (1.0 + theta * dt * lam[nn]);
         }
         for (int64_t nn = 0; nn < n0; ++nn)
             y[nn] += dy[nn];
@@ -768,11 +822,11 @@ void orc_exact_phi(double lam, double dt, double *phi1, double *phi2)
 /*   f(s) = f0 + f1 s,  f0 = -R_D iD^k - L_D d iD / dt - K^T M0 d i0 / dt,    */
 /*                      f1 = -R_D d iD / dt,                                 */
 /* its modal components e0 = V^T f0, e1 = V^T f1, and every mode advances as */
-/* in orc_exact_phi.  Probe signal and history as in orc_theta_modal.        */
+/* in orc_exact_phi.  Probe signal, history and keep as in orc_theta_modal. */
 /* ------------------------------------------------------------------------ */
 int orc_exact_modal(const orc_problem *pb, double dt, int64_t T,
                     const double *i_src, const double *i_D, double *signal,
-                    double *I_hist)
+                    double *I_hist, const unsigned char *keep)
 {
     orc_reduced r;
     const int64_t n0 = pb->n - pb->m, m = pb->m, ns = pb->n_src;
@@ -825,7 +879,7 @@ int orc_exact_modal(const orc_problem *pb, double dt, int64_t T,
                 e1 += V[IDX(i, nn, n0)] * f1[i];
             }
             const double ynew = decay[nn] * y[nn] + e0 * p1[nn] + e1 * p2[nn];
-            dy[nn] = ynew - y[nn];
+            dy[nn] = (keep && !keep[nn]) ? 0.0 : ynew - y[nn];
         }
         for (int64_t nn = 0; nn < n0; ++nn)
             y[nn] += dy[nn];

@@ -544,3 +544,74 @@ def test_phasor_conjugate_symmetry_and_linearity(orc):
     assert np.abs(s2 - np.conj(s1)).max() < 1e-12 * np.abs(s1).max()
     s3 = orc.phasors_direct(pb, om, 2.0 * a, 2.0 * d)
     assert np.abs(s3 - 2.0 * s1).max() < 1e-12 * np.abs(s1).max()
+
+
+# ---------------------------------------------------------------------------
+# selective solution of the decoupled modal equations (Sec. 3.2)
+# ---------------------------------------------------------------------------
+def _square_block(orc, nx, nz):
+    """Uniform nx x nx x nz block and a coil on its vertical axis: the eight
+    symmetries of the square (quarter turns and reflections) map the block,
+    L, R and the coil coupling onto themselves."""
+    dims = (nx, nx, nz)
+    xyz = inputs.grid(*dims)
+    n = xyz.shape[0]
+    R = inputs.resistance_csr(dims, np.ones(n)).to_dense()
+    L = orc.assemble_L(xyz, inputs.H_KERNEL)
+    c = (nx - 1) / 2.0
+    M = inputs.coil_coupling(xyz, (c, c, -2.0))[:, None]
+    return xyz, L, R, M
+
+
+def test_selected_modes_are_the_symmetric_ones(orc):
+    """The coil's coupling vector is invariant under the square's symmetries,
+    so it excites only modes of the invariant subspace, and (the probe being
+    the coil) only those are seen.  The selection at a tolerance above
+    rounding is therefore the eigenproblem restricted to that subspace: the
+    same eigenvalues, the same scores, and nothing else above rounding."""
+    nx, nz = 4, 3
+    xyz, L, R, M = _square_block(orc, nx, nz)
+    pb = orc.Problem(L, R, M, M.T)
+    keep, score = orc.select_modes(pb, 1e-10)
+    lam = orc.modal_eigen(pb, want_V=False)
+    # orthonormal basis of the invariant vectors: one normalised indicator per orbit
+    ix = xyz.astype(int)
+    a = np.minimum(ix[:, 0], nx - 1 - ix[:, 0])
+    b = np.minimum(ix[:, 1], nx - 1 - ix[:, 1])
+    key = (np.minimum(a, b) * nx + np.maximum(a, b)) * nz + ix[:, 2]
+    _, orbit = np.unique(key, return_inverse=True)
+    S = np.zeros((len(xyz), orbit.max() + 1))
+    S[np.arange(len(xyz)), orbit] = 1.0
+    S /= np.sqrt(S.sum(axis=0))
+    assert S.shape[1] == 3 * nz          # orbits of a 4 x 4 layer: {0,0}, {0,1}, {1,1}
+    lr, Vr = sla.eigh(S.T @ R @ S, S.T @ L @ S)   # Vr^T (S^T L S) Vr = I
+    sr = (Vr.T @ (S.T @ M[:, 0])) ** 2
+    assert (sr > 1e-10 * sr.max()).all()
+    assert keep.sum() == S.shape[1]
+    assert np.abs(lam[keep] - lr).max() < 1e-12 * lr.max()
+    assert np.abs(score[keep] - sr).max() < 1e-12 * sr.max()
+    assert score[~keep].max() < 1e-14 * score.max()
+
+
+@pytest.mark.parametrize("exact", [False, True])
+def test_selective_modes_superpose(orc, exact):
+    """The modes are independent: the signals of a kept set and of its
+    complement add up to the full signal once the direct electrode term,
+    present in both, is counted once; keeping every mode is the full stepper."""
+    w, L, R, E = _electrode_problem(orc)
+    pb = orc.Problem(L, R, w.M, w.P, E)
+    n0 = pb.n - pb.m
+    keep = np.random.default_rng(9).random(n0) < 0.4
+
+    def run(k):
+        if exact:
+            return orc.exact_modal(pb, w.dt, w.T, w.i_src, w.i_D, keep=k)
+        return orc.theta_modal(pb, 0.5, w.dt, w.T, w.i_src, w.i_D, keep=k)[0]
+
+    full = run(None)
+    assert np.array_equal(run(np.ones(n0, dtype=bool)), full)
+    none = run(np.zeros(n0, dtype=bool))
+    direct = w.P @ np.linalg.pinv(E) @ np.diff(w.i_D, axis=0).T / w.dt
+    assert np.abs(none - direct.T).max() < 1e-12 * np.abs(full).max()
+    s = run(keep) + run(~keep) - none
+    assert np.abs(s - full).max() < 1e-12 * np.abs(full).max()
