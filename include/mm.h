@@ -139,6 +139,36 @@ mm_status mm_step_modal_scan(mm_ctx* ctx, double theta, int32_t exact, double dt
                              int64_t n_steps, const double* i_src, const double* i_D,
                              double* signal);
 
+/* Selective solution of the decoupled modal equations (Sec. 3.2: each
+ * scalar equation can be solved on its own, so only a chosen subset need
+ * be).  Mode n is kept when its coupling score
+ *   score_n = max_j |W(n, j)| * max_p |P~(n, p)|
+ * (W the modal forcing weights of the columns [R_D | L_D | K^T M0], P~ the
+ * modal probe weights; every source counts with unit amplitude) exceeds
+ * tol times the largest score.  tol = 0 drops only modes with no forcing or
+ * no probe weight, which cannot change a probe signal; a larger tol drops
+ * weakly coupled modes, an approximation.  With degenerate eigenvalues the
+ * eigensolver's basis of each eigenspace decides which of its modes carry
+ * the coupling, so the kept count can differ between eigensolvers while the
+ * signals agree.
+ * *n_kept (host) receives the count; kept (device, n0 entries, or NULL)
+ * receives the kept mode indices in ascending eigenvalue order.  The kept set
+ * gets its own state, taken from the modal state at this call (zero after
+ * mm_reset_state); the full modal state, the reconstruction and the adjoint
+ * are not affected.  Synchronises the stream.  Requires mm_decompose or
+ * mm_decompose_projected (a new decomposition discards the selection);
+ * MM_E_INVALID for tol < 0, not finite, or n_kept NULL. */
+mm_status mm_select_modes(mm_ctx* ctx, double tol, int64_t* n_kept, int64_t* kept);
+
+/* mm_step_modal (exact = 0, theta in [0, 1]) or mm_step_modal_exact
+ * (exact != 0, theta ignored) on the modes kept by mm_select_modes only,
+ * from the kept set's own state: the cost per step scales with the kept
+ * count.  Arguments, signal and errors as those calls, and MM_E_STATE before
+ * mm_select_modes.  mm_reset_state zeroes this state too. */
+mm_status mm_step_modal_selective(mm_ctx* ctx, double theta, int32_t exact, double dt,
+                                  int64_t n_steps, const double* i_src, const double* i_D,
+                                  double* signal);
+
 /* Steady-state phasors of the probe signals under sinusoidal sources, from
  * the decomposition (Sec. 3.2, eq. modal_decomposition_discrete; the
  * frequency-domain comparison of Sec. 4.5): with i0_c(t) = Re{A_c e^{jwt}}

@@ -21,7 +21,7 @@ MM_MODAL = 0
 MM_CHOLESKY = 1
 
 # Every exported entry point of include/mm.h.
-SYMBOLS = ["mm_setup", "mm_decompose", "mm_decompose_projected", "mm_step_modal", "mm_step_modal_exact", "mm_step_modal_scan", "mm_modal_phasors", "mm_step_cholesky",
+SYMBOLS = ["mm_setup", "mm_decompose", "mm_decompose_projected", "mm_step_modal", "mm_step_modal_exact", "mm_step_modal_scan", "mm_modal_phasors", "mm_select_modes", "mm_step_modal_selective", "mm_step_cholesky",
            "mm_probe", "mm_reset_state", "mm_eigenvalues", "mm_info",
            "mm_destroy", "mm_last_error", "mm_batch_create", "mm_batch_run",
            "mm_batch_info", "mm_batch_destroy", "mm_adjoint_modal", "mmk_dgemm", "mmk_dgemm_tri", "mmk_dsymm_lower", "mmk_dpotrf",
@@ -60,6 +60,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "mm_step_modal_exact": [vp, dbl, i64, vp, vp, vp],
         "mm_modal_phasors": [vp, i64, vp, vp, vp, vp],
         "mm_step_modal_scan": [vp, dbl, i32, dbl, i64, vp, vp, vp],
+        "mm_select_modes": [vp, dbl, ctypes.POINTER(ctypes.c_int64), vp],
+        "mm_step_modal_selective": [vp, dbl, i32, dbl, i64, vp, vp, vp],
         "mm_step_cholesky": [vp, dbl, dbl, i64, vp, vp, vp],
         "mm_probe": [vp, i32, i32, vp, vp],
         "mm_reset_state": [vp],

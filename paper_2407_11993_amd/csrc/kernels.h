@@ -188,6 +188,17 @@ struct ModalPhasor {
   double* partial = nullptr;
   double* out = nullptr;            // n_w x n_probe pairs
 };
+// Selective modal stepping (select.hip): score[n] = max_j |W(n, j)| *
+// max_p |Pt(n, p)| (W n0 x nf, Pt n0 x np, ld n0); idx (n0 entries) receives
+// the modes with score > tol * max score in ascending order, count[0] their
+// number.  gather_modes copies the kept modes' lam, W and Pt rows and state
+// into compact arrays of leading dimension nk.
+void select_modes(const double* W, int nf, const double* Pt, int np, int64_t n0, double tol,
+                  double* score, int64_t* idx, int64_t* count, hipStream_t s);
+void gather_modes(const int64_t* idx, int64_t nk, int64_t n0, const double* lam, const double* W,
+                  int nf, const double* Pt, int np, const double* y, double* lam_s, double* W_s,
+                  double* Pt_s, double* y_s, hipStream_t s);
+
 int64_t phasor_groups(int64_t n0);
 void modal_phasors(const ModalPhasor& mp, hipStream_t s);
 void modal_steps(const ModalStep& m, int64_t k0, int64_t n_steps, hipStream_t s);

@@ -91,6 +91,11 @@ struct mm_ctx {
   bool decomposed = false;
   bool has_Q = false;  // the eigenvector matrix is formed (mm_decompose, not _projected)
   Dev G, Q, lam, Wm, Pm, y;
+  // selective modal stepping: the kept modes (ascending index), compact copies
+  // of their lam, forcing and probe weights (ld sel_n) and their own state
+  bool selected = false;
+  int64_t sel_n = 0;
+  Dev sel_score, sel_idx, sel_lam, sel_W, sel_P, sel_y;
   // Cholesky method
   bool factored = false;
   double f_theta = 0.0, f_dt = 0.0;
@@ -404,6 +409,7 @@ void decompose_impl(mm_ctx* c, bool project) {
                "(use mm_decompose)");
     c->decomposed = false;
     c->has_Q = false;
+    c->selected = false;
     // Buffers in the order they are needed, released as soon as they are not
     // (at N = 98,304 one n0^2 buffer is 77 GB: at most three live at once).
     // The small buffers of the eigensolver are allocated first: an
@@ -579,8 +585,10 @@ namespace {
 
 void step_modal_impl(mm_ctx* c, double theta, double dt, bool exact, int64_t n_steps,
                      const double* i_src, const double* i_D, double* signal,
-                     bool scan = false) {
+                     bool scan = false, bool selective = false) {
     MM_REQUIRE(c->decomposed, kState, "modal stepping before mm_decompose");
+    MM_REQUIRE(!selective || c->selected, kState,
+               "mm_step_modal_selective before mm_select_modes");
     check_steps(theta, dt, n_steps);
     check_run_columns(c);
     MM_REQUIRE(c->n_src == 0 || i_src, kInvalid, "i_src is required");
@@ -588,19 +596,20 @@ void step_modal_impl(mm_ctx* c, double theta, double dt, bool exact, int64_t n_s
     MM_REQUIRE(signal || n_steps == 0, kInvalid, "signal is required");
     if (n_steps == 0) return;
     hipStream_t s = c->stream;
-    const int G = modal_groups(c->n0);
+    const int64_t nm = selective ? c->sel_n : c->n0;
+    const int G = modal_groups(nm);
     c->pp.alloc(sizeof(double) * n_steps * G * c->n_probe);
     ModalStep ms;
-    ms.n0 = c->n0;
-    ms.lam = c->lam.d();
-    ms.W = c->Wm.d();
+    ms.n0 = nm;
+    ms.lam = selective ? c->sel_lam.d() : c->lam.d();
+    ms.W = selective ? c->sel_W.d() : c->Wm.d();
     ms.f.nf = c->nf; ms.f.m = (int)c->m; ms.f.n_src = c->n_src;
     ms.f.i_src = i_src; ms.f.i_D = i_D;
-    ms.Pt = c->Pm.d();
+    ms.Pt = selective ? c->sel_P.d() : c->Pm.d();
     ms.n_probe = c->n_probe;
     ms.theta = theta; ms.dt = dt;
     ms.exact = exact;
-    ms.y = c->y.d();
+    ms.y = selective ? c->sel_y.d() : c->y.d();
     ms.probe_partial = c->pp.d();
     if (scan) {
       const int64_t L = scan_chunk(c->n0, n_steps);
@@ -611,7 +620,8 @@ void step_modal_impl(mm_ctx* c, double theta, double dt, bool exact, int64_t n_s
     }
     probe_finish(c->pp.d(), n_steps, G, c->n_probe, c->m ? c->PD.d() : nullptr, (int)c->m,
                  i_D, 0, dt, signal, s);
-    if (c->m)
+    // the injected currents belong to the full modal state (current reconstruction)
+    if (c->m && !selective)
       MM_HIP_TRY(hipMemcpyAsync(c->iD_modal.p, i_D + n_steps * c->m, sizeof(double) * c->m,
                                 hipMemcpyDeviceToDevice, s));
 }
@@ -635,6 +645,49 @@ mm_status mm_step_modal_scan(mm_ctx* c, double theta, int32_t exact, double dt, 
   if (!c) return MM_E_INVALID;
   return guarded(c, [&] {
     step_modal_impl(c, exact ? 0.5 : theta, dt, exact != 0, n_steps, i_src, i_D, signal, true);
+  });
+}
+
+mm_status mm_select_modes(mm_ctx* c, double tol, int64_t* n_kept, int64_t* kept) {
+  if (!c) return MM_E_INVALID;
+  return guarded(c, [&] {
+    MM_REQUIRE(c->decomposed, kState, "mm_select_modes before mm_decompose");
+    MM_REQUIRE(std::isfinite(tol) && tol >= 0.0, kInvalid, "tol must be finite and >= 0");
+    MM_REQUIRE(n_kept, kInvalid, "n_kept is required");
+    hipStream_t s = c->stream;
+    const int64_t n0 = c->n0;
+    c->selected = false;
+    c->sel_score.alloc(sizeof(double) * n0);
+    c->sel_idx.alloc(sizeof(int64_t) * (n0 + 1));
+    int64_t* idx = c->sel_idx.as<int64_t>();
+    select_modes(c->Wm.d(), c->nf, c->Pm.d(), c->n_probe, n0, tol, c->sel_score.d(), idx,
+                 idx + n0, s);
+    int64_t nk = 0;
+    MM_HIP_TRY(hipMemcpyAsync(&nk, idx + n0, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    MM_HIP_TRY(hipStreamSynchronize(s));
+    MM_REQUIRE(nk >= 0 && nk <= n0, kDevice, "mm_select_modes: kept count out of range");
+    const int64_t cap = std::max<int64_t>(nk, 1);
+    c->sel_lam.alloc(sizeof(double) * cap);
+    c->sel_W.alloc(sizeof(double) * cap * std::max(1, c->nf));
+    c->sel_P.alloc(sizeof(double) * cap * std::max(1, c->n_probe));
+    c->sel_y.alloc(sizeof(double) * cap);
+    gather_modes(idx, nk, n0, c->lam.d(), c->Wm.d(), c->nf, c->Pm.d(), c->n_probe, c->y.d(),
+                 c->sel_lam.d(), c->sel_W.d(), c->sel_P.d(), c->sel_y.d(), s);
+    if (kept && nk > 0)
+      MM_HIP_TRY(hipMemcpyAsync(kept, idx, sizeof(int64_t) * nk, hipMemcpyDeviceToDevice, s));
+    c->sel_n = nk;
+    c->selected = true;
+    *n_kept = nk;
+  });
+}
+
+mm_status mm_step_modal_selective(mm_ctx* c, double theta, int32_t exact, double dt,
+                                  int64_t n_steps, const double* i_src, const double* i_D,
+                                  double* signal) {
+  if (!c) return MM_E_INVALID;
+  return guarded(c, [&] {
+    step_modal_impl(c, exact ? 0.5 : theta, dt, exact != 0, n_steps, i_src, i_D, signal, false,
+                    true);
   });
 }
 
@@ -809,6 +862,7 @@ mm_status mm_reset_state(mm_ctx* c) {
   if (!c) return MM_E_INVALID;
   return guarded(c, [&] {
     if (c->y.p) fill(c->y.d(), c->n0, 0.0, c->stream);
+    if (c->selected && c->sel_n > 0) fill(c->sel_y.d(), c->sel_n, 0.0, c->stream);
     if (c->I.p) fill(c->I.d(), c->n0, 0.0, c->stream);
     if (c->m) {
       fill(c->iD_modal.d(), c->m, 0.0, c->stream);

@@ -135,6 +135,27 @@ class Solver:
         self._keep = (s, d)
         return sig
 
+    def select_modes(self, tol):
+        """Keep the modes whose coupling score exceeds tol times the largest
+        (mm_select_modes); returns the kept mode indices (int64, on the device,
+        ascending).  step_modal_selective then steps only those."""
+        nk = ctypes.c_int64(0)
+        idx = torch.empty(max(self.n0, 1), dtype=torch.int64, device=self.device)
+        _lib.check(self.lib.mm_select_modes(self.ctx, float(tol), ctypes.byref(nk),
+                                            _lib.ptr(idx)), self.ctx)
+        return idx[:nk.value]
+
+    def step_modal_selective(self, theta, dt, n_steps, i_src, i_D=None, exact=False, out=None):
+        """step_modal (or step_modal_exact with exact=True) on the kept modes."""
+        s, d = self._waves(n_steps, i_src, i_D)
+        sig = out if out is not None else torch.empty(
+            (n_steps, self.n_probe), dtype=torch.float64, device=self.device)
+        _lib.check(self.lib.mm_step_modal_selective(self.ctx, float(theta), int(bool(exact)),
+                                                    float(dt), int(n_steps), _lib.ptr(s),
+                                                    _lib.ptr(d), _lib.ptr(sig)), self.ctx)
+        self._keep = (s, d)
+        return sig
+
     def phasors(self, omegas, amp_src, amp_D=None):
         """Steady-state phasors (n_w x n_probe, complex) of the probe signals
         P dI/dt for sources Re{amp_src[w, c] exp(j omegas[w] t)} and electrode

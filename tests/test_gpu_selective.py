@@ -1,0 +1,188 @@
+"""Selective modal stepping (mm_select_modes, mm_step_modal_selective)
+through the C ABI.
+
+* A plate with random resistivity and electrodes (simple spectrum): the kept
+  set equals the oracle's at a tolerance placed in a wide gap of the oracle's
+  scores, and the selective theta and exact signals equal the oracle's
+  steppers restricted to that set (within 1e-9 of max|s|); tol = 0 keeps
+  every mode and reproduces mm_step_modal bit for bit; a tolerance above 1
+  keeps none and leaves the direct electrode term.
+* The 8x8x8 block with a coil on its axis (degenerate spectrum): the kept
+  eigenvalues are exactly those of the pencil restricted to the subspace
+  invariant under the square's symmetries (80 of them, in clusters of up to
+  three modes), and the signal is the full oracle's within 1e-9.
+* State: continuation across calls, reset, a new decomposition discards the
+  selection, argument and state errors."""
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from paper_2407_11993_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+    oracle.build(force=False)
+    return oracle
+
+
+@pytest.fixture(scope="module")
+def plate(orc):
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2407_11993_amd import Solver
+    w = inputs.electrode_plate(10, 12, 2, T=300, seed=21, tau_D=60.0, coil_period=40.0)
+    pb = orc.Problem(orc.assemble_L(w.xyz, w.h), w.R.to_dense(), w.M, w.P, w.E.to_dense())
+    s = Solver(w)
+    s.decompose()
+    return w, pb, s
+
+
+def _gap_tol(score):
+    """A relative tolerance in the widest gap of the sorted scores between
+    the first and the last quarter of the modes."""
+    ss = np.sort(score)[::-1] / score.max()
+    lo, hi = len(ss) // 4, 3 * len(ss) // 4
+    k = lo + int(np.argmax(ss[lo:hi] / ss[lo + 1:hi + 1]))
+    assert ss[k] / ss[k + 1] > 1.1
+    return float(np.sqrt(ss[k] * ss[k + 1]))
+
+
+def test_selected_set_and_signals_match_oracle(orc, plate):
+    w, pb, s = plate
+    _, score = orc.select_modes(pb, 0.0)
+    tol = _gap_tol(score)
+    keep, _ = orc.select_modes(pb, tol)
+    assert 0 < keep.sum() < len(keep)
+    s.reset()
+    idx = _np(s.select_modes(tol))
+    assert np.array_equal(idx, np.nonzero(keep)[0])
+    got = _np(s.step_modal_selective(0.5, w.dt, w.T, w.i_src, w.i_D))
+    ref, _ = orc.theta_modal(pb, 0.5, w.dt, w.T, w.i_src, w.i_D, keep=keep)
+    assert _rel(got, ref) < 1e-9
+    s.reset()
+    got = _np(s.step_modal_selective(0.5, w.dt, w.T, w.i_src, w.i_D, exact=True))
+    ref = orc.exact_modal(pb, w.dt, w.T, w.i_src, w.i_D, keep=keep)
+    assert _rel(got, ref) < 1e-9
+    # the dropped modes matter here: the full signal is different
+    full, _ = orc.theta_modal(pb, 0.5, w.dt, w.T, w.i_src, w.i_D)
+    assert _rel(full, ref) > 1e-6
+
+
+def test_tol_zero_keeps_every_mode_bit_for_bit(plate):
+    w, pb, s = plate
+    s.reset()
+    idx = _np(s.select_modes(0.0))
+    assert np.array_equal(idx, np.arange(pb.n - pb.m))
+    for exact in (False, True):
+        s.reset()
+        sel = _np(s.step_modal_selective(0.5, w.dt, w.T, w.i_src, w.i_D, exact=exact))
+        s.reset()
+        full = _np(s.step_modal_exact(w.dt, w.T, w.i_src, w.i_D) if exact
+                   else s.step_modal(0.5, w.dt, w.T, w.i_src, w.i_D))
+        assert np.array_equal(sel, full)
+
+
+def test_nothing_kept_leaves_the_direct_term(orc, plate):
+    w, pb, s = plate
+    s.reset()
+    assert s.select_modes(2.0).numel() == 0
+    got = _np(s.step_modal_selective(0.5, w.dt, w.T, w.i_src, w.i_D))
+    ref, _ = orc.theta_modal(pb, 0.5, w.dt, w.T, w.i_src, w.i_D,
+                             keep=np.zeros(pb.n - pb.m, dtype=bool))
+    full, _ = orc.theta_modal(pb, 0.5, w.dt, w.T, w.i_src, w.i_D)
+    assert np.abs(got - ref).max() < 1e-12 * np.abs(full).max()
+
+
+def test_state_continues_and_resets(plate):
+    w, pb, s = plate
+    _ = s.select_modes(1e-3)
+    s.reset()
+    one = _np(s.step_modal_selective(0.5, w.dt, w.T, w.i_src, w.i_D))
+    s.reset()
+    k = 117
+    a = _np(s.step_modal_selective(0.5, w.dt, k, w.i_src[:k + 1], w.i_D[:k + 1]))
+    b = _np(s.step_modal_selective(0.5, w.dt, w.T - k, w.i_src[k:], w.i_D[k:]))
+    assert np.abs(np.concatenate([a, b]) - one).max() <= 1e-13 * np.abs(one).max()
+    s.reset()
+    again = _np(s.step_modal_selective(0.5, w.dt, w.T, w.i_src, w.i_D))
+    assert np.array_equal(again, one)
+
+
+def test_selection_errors():
+    import torch
+    from paper_2407_11993_amd import Solver, _lib
+    w = inputs.electrode_plate(6, 8, 2, T=20, seed=3, tau_D=10.0, coil_period=9.0)
+    s = Solver(w)
+    with pytest.raises(_lib.MMError) as e:
+        s.select_modes(0.0)
+    assert e.value.code == 5                       # before mm_decompose
+    s.decompose()
+    with pytest.raises(_lib.MMError) as e:
+        s.step_modal_selective(0.5, 1.0, w.T, w.i_src, w.i_D)
+    assert e.value.code == 5                       # before mm_select_modes
+    for bad in (-1.0, float("nan"), float("inf")):
+        with pytest.raises(_lib.MMError) as e:
+            s.select_modes(bad)
+        assert e.value.code == 1
+    assert s.select_modes(0.0).numel() == w.n - w.m
+    s.step_modal_selective(0.5, 1.0, w.T, w.i_src, w.i_D)
+    torch.cuda.synchronize()
+    s.decompose(projected=True)                    # a new decomposition drops the selection
+    with pytest.raises(_lib.MMError) as e:
+        s.step_modal_selective(0.5, 1.0, w.T, w.i_src, w.i_D)
+    assert e.value.code == 5
+    assert s.select_modes(0.0).numel() == w.n - w.m
+    s.close()
+
+
+def test_block8_keeps_the_symmetric_modes(orc):
+    """Coil on the axis of the 8x8x8 block: only the 80 eigenvalues of the
+    pencil restricted to the square-symmetric subspace carry coupling; the
+    cube's further symmetry puts some of them in clusters of up to three
+    equal eigenvalues, whose basis (and so the kept count, 80 to 180) is
+    the eigensolver's choice."""
+    import torch
+    from paper_2407_11993_amd import Solver
+    assert torch.cuda.is_available()
+    w = inputs.config1()
+    s = Solver(w)
+    s.decompose()
+    lam = _np(s.eigenvalues())
+    idx = _np(s.select_modes(1e-10))
+    assert 80 <= len(idx) <= 180
+    L = orc.assemble_L(w.xyz, w.h)
+    R = w.R.to_dense()
+    ix = w.xyz.astype(int)
+    a = np.minimum(ix[:, 0], 7 - ix[:, 0])
+    b = np.minimum(ix[:, 1], 7 - ix[:, 1])
+    key = (np.minimum(a, b) * 8 + np.maximum(a, b)) * 8 + ix[:, 2]
+    _, orbit = np.unique(key, return_inverse=True)
+    S = np.zeros((w.n, orbit.max() + 1))
+    S[np.arange(w.n), orbit] = 1.0
+    S /= np.sqrt(S.sum(axis=0))
+    lr = sla.eigh(S.T @ R @ S, S.T @ L @ S, eigvals_only=True)
+    assert len(lr) == 80
+    d = np.abs(lam[idx][:, None] - lr[None, :]) / lr.max()
+    assert d.min(axis=1).max() < 1e-9                # every kept mode is symmetric
+    assert d.min(axis=0).max() < 1e-9                # every symmetric eigenvalue is kept
+    ref = np.loadtxt(os.path.join(GOLDEN, "block8_signal_direct_cn.txt"))[:, None]
+    s.reset()
+    got = _np(s.step_modal_selective(0.5, w.dt, w.T, w.i_src))
+    assert _rel(got, ref) < 1e-9
+    s.close()

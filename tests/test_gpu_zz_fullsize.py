@@ -4,8 +4,10 @@ decomposition and the Cholesky factorisation at full size, 200 steps of each
 theta-method.  The oracle cannot run at this size; the property checked is
 that the two methods, which share no kernel beyond the problem setup, give
 the same probe signals (within 1e-8 of max|s|, the tolerance between them at
-every size), and that exact integration differs from theta = 1/2 by no more
-than the theta-method's time-step error seen on the smaller plates.
+every size), that exact integration differs from theta = 1/2 by no more
+than the theta-method's time-step error seen on the smaller plates, and that
+the selective stepping keeps every mode at tol = 0 and fewer than half of
+them, with the same signal to 1e-8, at tol = 1e-10.
 About a minute of GPU time (most of it the decomposition)."""
 import numpy as np
 import pytest
@@ -40,4 +42,19 @@ def test_modal_matches_cholesky_at_98304():
     assert torch.isfinite(sc).all()
     assert _rel(sm, sc) < 1e-8
     assert _rel(sx, sm) < 1e-2
+    # selective stepping: tol = 0 keeps every coupled mode (the same signal),
+    # 1e-10 drops the modes that the plate's two mirror symmetries decouple
+    # from the coil probe, within the modal-vs-Cholesky tolerance
+    n0 = w.n - w.m
+    s.reset()
+    k0 = s.select_modes(0.0).numel()
+    s0 = s.step_modal_selective(0.5, w.dt, T, i_src, i_D)
+    assert torch.equal(s0, sm) if k0 == n0 else _rel(s0, sm) < 1e-12
+    s.reset()
+    k1 = s.select_modes(1e-10).numel()
+    s1 = s.step_modal_selective(0.5, w.dt, T, i_src, i_D)
+    print(f"selective: {k0} and {k1} of {n0} modes kept, change {_rel(s1, sm):.2e}",
+          flush=True)
+    assert 0 < k1 < n0 // 2
+    assert _rel(s1, sm) < 1e-8
     s.close()
