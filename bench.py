@@ -77,7 +77,7 @@ def run_electrodes(args):
     amps_D = [[1.0] * w.m] * len(omegas) if w.m else None
 
     def one_step():
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(14)]
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(16)]
         torch.cuda.synchronize()
         ev[0].record(stream)
         s = Solver(w)
@@ -116,8 +116,14 @@ def run_electrodes(args):
         ev[12].record(stream)
         ss = s.step_modal_selective(theta, dt, T, i_src, i_D)
         ev[13].record(stream)
+        # the kept modes again, parallel in time
+        s.reset()
+        ev[14].record(stream)
+        sp = s.step_modal_selective(theta, dt, T, i_src, i_D, scan=True)
+        ev[15].record(stream)
         torch.cuda.synchronize()
-        sel = (int(kept.numel()), float((ss - sm).abs().max() / sm.abs().max()))
+        sel = (int(kept.numel()), float((ss - sm).abs().max() / sm.abs().max()),
+               float((sp - ss).abs().max() / ss.abs().max()))
         s.reset()
         ev[4].record(stream)
         s.step_cholesky(theta, dt, 0, i_src[:1], i_D[:1])  # the factorisation
@@ -135,7 +141,8 @@ def run_electrodes(args):
                 "modal_exact_steps": ev[7].elapsed_time(ev[8]) / 1e3,
                 "modal_phasors_30_tones": ev[9].elapsed_time(ev[10]) / 1e3,
                 "select_modes": ev[11].elapsed_time(ev[12]) / 1e3,
-                "modal_selective_steps": ev[12].elapsed_time(ev[13]) / 1e3}, \
+                "modal_selective_steps": ev[12].elapsed_time(ev[13]) / 1e3,
+                "modal_selective_steps_scan": ev[14].elapsed_time(ev[15]) / 1e3}, \
             (agree, exact_diff, sel)
 
     for _ in range(args.warmup):
@@ -148,6 +155,7 @@ def run_electrodes(args):
     exact_diff = max(r[1][1] for r in runs)
     n_kept = runs[-1][1][2][0]
     sel_diff = max(r[1][2][1] for r in runs)
+    sel_scan_diff = max(r[1][2][2] for r in runs)
     n0 = w.n - w.m
     per_step = avg["cholesky_steps_measured"] / K
     modal_s = avg["setup"] + avg["decompose"] + avg["modal_steps"]
@@ -182,7 +190,9 @@ def run_electrodes(args):
         "selective": {"tol": SELECT_TOL, "modes_kept": n_kept, "modes": n0,
                       "select_s": round(avg["select_modes"], 6),
                       "steps_s": round(avg["modal_selective_steps"], 6),
-                      "signal_difference_vs_all_modes": sel_diff},
+                      "steps_scan_s": round(avg["modal_selective_steps_scan"], 6),
+                      "signal_difference_vs_all_modes": sel_diff,
+                      "signal_difference_scan_vs_sequential": sel_scan_diff},
         "phases_s": {k: round(v, 3) for k, v in avg.items()},
         "decomposition_tflops": round(dec_flops / avg["decompose"] / 1e12, 3),
         "roofline": {"bound": "hbm", "kernel": "triangular solve pair (fwd+bwd per step)",

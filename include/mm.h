@@ -160,12 +160,17 @@ mm_status mm_step_modal_scan(mm_ctx* ctx, double theta, int32_t exact, double dt
  * MM_E_INVALID for tol < 0, not finite, or n_kept NULL. */
 mm_status mm_select_modes(mm_ctx* ctx, double tol, int64_t* n_kept, int64_t* kept);
 
-/* mm_step_modal (exact = 0, theta in [0, 1]) or mm_step_modal_exact
- * (exact != 0, theta ignored) on the modes kept by mm_select_modes only,
- * from the kept set's own state: the cost per step scales with the kept
- * count.  Arguments, signal and errors as those calls, and MM_E_STATE before
- * mm_select_modes.  mm_reset_state zeroes this state too. */
-mm_status mm_step_modal_selective(mm_ctx* ctx, double theta, int32_t exact, double dt,
+/* mm_step_modal (theta in [0, 1]), or mm_step_modal_exact with
+ * MM_STEP_EXACT in flags (theta ignored), on the modes kept by
+ * mm_select_modes only, from the kept set's own state; with MM_STEP_SCAN
+ * the steps run parallel in time as in mm_step_modal_scan (same signal to
+ * rounding), which pays off when few modes are kept for many steps.
+ * Arguments, signal and errors as those calls, MM_E_INVALID for unknown
+ * flags, and MM_E_STATE before mm_select_modes.  mm_reset_state zeroes this
+ * state too. */
+#define MM_STEP_EXACT 1u
+#define MM_STEP_SCAN 2u
+mm_status mm_step_modal_selective(mm_ctx* ctx, double theta, uint32_t flags, double dt,
                                   int64_t n_steps, const double* i_src, const double* i_D,
                                   double* signal);
 

@@ -19,6 +19,8 @@ STATUS = {0: "MM_OK", 1: "MM_E_INVALID", 2: "MM_E_NOMEM", 3: "MM_E_NOT_SPD",
           4: "MM_E_NO_CONVERGE", 5: "MM_E_STATE", 6: "MM_E_DEVICE"}
 MM_MODAL = 0
 MM_CHOLESKY = 1
+MM_STEP_EXACT = 1
+MM_STEP_SCAN = 2
 
 # Every exported entry point of include/mm.h.
 SYMBOLS = ["mm_setup", "mm_decompose", "mm_decompose_projected", "mm_step_modal", "mm_step_modal_exact", "mm_step_modal_scan", "mm_modal_phasors", "mm_select_modes", "mm_step_modal_selective", "mm_step_cholesky",
@@ -61,7 +63,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "mm_modal_phasors": [vp, i64, vp, vp, vp, vp],
         "mm_step_modal_scan": [vp, dbl, i32, dbl, i64, vp, vp, vp],
         "mm_select_modes": [vp, dbl, ctypes.POINTER(ctypes.c_int64), vp],
-        "mm_step_modal_selective": [vp, dbl, i32, dbl, i64, vp, vp, vp],
+        "mm_step_modal_selective": [vp, dbl, ctypes.c_uint32, dbl, i64, vp, vp, vp],
         "mm_step_cholesky": [vp, dbl, dbl, i64, vp, vp, vp],
         "mm_probe": [vp, i32, i32, vp, vp],
         "mm_reset_state": [vp],

@@ -611,9 +611,9 @@ void step_modal_impl(mm_ctx* c, double theta, double dt, bool exact, int64_t n_s
     ms.exact = exact;
     ms.y = selective ? c->sel_y.d() : c->y.d();
     ms.probe_partial = c->pp.d();
-    if (scan) {
-      const int64_t L = scan_chunk(c->n0, n_steps);
-      c->scanws.alloc(sizeof(double) * 2 * ceil_div(n_steps, L) * c->n0);
+    if (scan && nm > 0) {
+      const int64_t L = scan_chunk(nm, n_steps);
+      c->scanws.alloc(sizeof(double) * 2 * ceil_div(n_steps, L) * nm);
       modal_steps_scan(ms, n_steps, L, c->scanws.d(), s);
     } else {
       modal_steps(ms, 0, n_steps, s);
@@ -681,13 +681,15 @@ mm_status mm_select_modes(mm_ctx* c, double tol, int64_t* n_kept, int64_t* kept)
   });
 }
 
-mm_status mm_step_modal_selective(mm_ctx* c, double theta, int32_t exact, double dt,
+mm_status mm_step_modal_selective(mm_ctx* c, double theta, uint32_t flags, double dt,
                                   int64_t n_steps, const double* i_src, const double* i_D,
                                   double* signal) {
   if (!c) return MM_E_INVALID;
   return guarded(c, [&] {
-    step_modal_impl(c, exact ? 0.5 : theta, dt, exact != 0, n_steps, i_src, i_D, signal, false,
-                    true);
+    MM_REQUIRE((flags & ~(MM_STEP_EXACT | MM_STEP_SCAN)) == 0, kInvalid, "unknown flags");
+    const bool exact = (flags & MM_STEP_EXACT) != 0;
+    step_modal_impl(c, exact ? 0.5 : theta, dt, exact, n_steps, i_src, i_D, signal,
+                    (flags & MM_STEP_SCAN) != 0, true);
   });
 }
 

@@ -145,12 +145,15 @@ class Solver:
                                             _lib.ptr(idx)), self.ctx)
         return idx[:nk.value]
 
-    def step_modal_selective(self, theta, dt, n_steps, i_src, i_D=None, exact=False, out=None):
-        """step_modal (or step_modal_exact with exact=True) on the kept modes."""
+    def step_modal_selective(self, theta, dt, n_steps, i_src, i_D=None, exact=False,
+                             scan=False, out=None):
+        """step_modal (or step_modal_exact with exact=True) on the kept modes;
+        scan=True runs the steps parallel in time."""
         s, d = self._waves(n_steps, i_src, i_D)
         sig = out if out is not None else torch.empty(
             (n_steps, self.n_probe), dtype=torch.float64, device=self.device)
-        _lib.check(self.lib.mm_step_modal_selective(self.ctx, float(theta), int(bool(exact)),
+        flags = (_lib.MM_STEP_EXACT if exact else 0) | (_lib.MM_STEP_SCAN if scan else 0)
+        _lib.check(self.lib.mm_step_modal_selective(self.ctx, float(theta), flags,
                                                     float(dt), int(n_steps), _lib.ptr(s),
                                                     _lib.ptr(d), _lib.ptr(sig)), self.ctx)
         self._keep = (s, d)

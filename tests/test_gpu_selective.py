@@ -11,6 +11,8 @@ through the C ABI.
   eigenvalues are exactly those of the pencil restricted to the subspace
   invariant under the square's symmetries (80 of them, in clusters of up to
   three modes), and the signal is the full oracle's within 1e-9.
+* Parallel in time (MM_STEP_SCAN): the sequential selective signal and
+  state within 1e-11, for theta and exact integration.
 * State: continuation across calls, reset, a new decomposition discards the
   selection, argument and state errors."""
 import os
@@ -124,6 +126,31 @@ def test_state_continues_and_resets(plate):
     assert np.array_equal(again, one)
 
 
+@pytest.mark.parametrize("exact", [False, True])
+def test_selective_scan_matches_sequential(plate, exact):
+    """Parallel in time over several hundred chunks, then continued by the
+    sequential stepper from the state the scan left."""
+    w, pb, s = plate
+    T = 20000
+    t = np.arange(T + 1)
+    i_src = (np.sin(2 * np.pi * t / 97.0) * np.exp(-t / 1e4))[:, None]
+    i_D = (1.0 - np.exp(-t / 3000.0))[:, None]
+    assert 0 < s.select_modes(1e-3).numel() < pb.n - pb.m
+    s.reset()
+    seq = _np(s.step_modal_selective(0.5, w.dt, T, i_src, i_D, exact=exact))
+    seq2 = _np(s.step_modal_selective(0.5, w.dt, 50, i_src[:51], i_D[:51], exact=exact))
+    s.reset()
+    got = _np(s.step_modal_selective(0.5, w.dt, T, i_src, i_D, exact=exact, scan=True))
+    got2 = _np(s.step_modal_selective(0.5, w.dt, 50, i_src[:51], i_D[:51], exact=exact))
+    assert _rel(got, seq) < 1e-11
+    assert np.abs(got2 - seq2).max() < 1e-11 * np.abs(seq).max()
+    # nothing kept: the scan leaves the direct electrode term like the sequential run
+    assert s.select_modes(2.0).numel() == 0
+    a = _np(s.step_modal_selective(0.5, w.dt, T, i_src, i_D, exact=exact, scan=True))
+    b = _np(s.step_modal_selective(0.5, w.dt, T, i_src, i_D, exact=exact))
+    assert np.array_equal(a, b)
+
+
 def test_selection_errors():
     import torch
     from paper_2407_11993_amd import Solver, _lib
@@ -143,6 +170,12 @@ def test_selection_errors():
     assert s.select_modes(0.0).numel() == w.n - w.m
     s.step_modal_selective(0.5, 1.0, w.T, w.i_src, w.i_D)
     torch.cuda.synchronize()
+    src = torch.as_tensor(w.i_src, dtype=torch.float64, device="cuda")
+    iD = torch.as_tensor(w.i_D, dtype=torch.float64, device="cuda")
+    sig = torch.empty((w.T, w.n_probe), dtype=torch.float64, device="cuda")
+    rc = s.lib.mm_step_modal_selective(s.ctx, 0.5, 4, 1.0, w.T, _lib.ptr(src), _lib.ptr(iD),
+                                       _lib.ptr(sig))
+    assert rc == 1                                 # unknown flag
     s.decompose(projected=True)                    # a new decomposition drops the selection
     with pytest.raises(_lib.MMError) as e:
         s.step_modal_selective(0.5, 1.0, w.T, w.i_src, w.i_D)
