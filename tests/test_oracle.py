@@ -615,3 +615,29 @@ def test_selective_modes_superpose(orc, exact):
     assert np.abs(none - direct.T).max() < 1e-12 * np.abs(full).max()
     s = run(keep) + run(~keep) - none
     assert np.abs(s - full).max() < 1e-12 * np.abs(full).max()
+
+
+def test_tol_zero_keeps_exactly_the_driven_subsystem(orc):
+    """Two plates with no coupling (block-diagonal L and R), the source and
+    the probe on the first: the second plate's modes have no forcing and no
+    probe weight (Jacobi never rotates across the zero blocks), so tol = 0
+    keeps exactly the first plate's modes, and the signal is the first
+    plate's own, computed without the second."""
+    _, L1, R1, M1 = _small_problem(orc, dims=(3, 4, 1), seed=2, coil=(1.0, 1.5, 1.5))
+    _, L2, R2, _ = _small_problem(orc, dims=(4, 3, 1), seed=3)
+    n1, n2 = len(L1), len(L2)
+    L = sla.block_diag(L1, L2)
+    R = sla.block_diag(R1, R2)
+    M = np.concatenate([M1, np.zeros((n2, 1))])
+    pb = orc.Problem(L, R, M, M.T)
+    keep, score = orc.select_modes(pb, 0.0)
+    lam = orc.modal_eigen(pb, want_V=False)
+    lam1 = orc.modal_eigen(orc.Problem(L1, R1, M1, M1.T), want_V=False)
+    assert keep.sum() == n1
+    assert np.all(score[~keep] == 0.0)
+    assert np.abs(np.sort(lam[keep]) - lam1).max() < 1e-12 * lam1.max()
+    T = 60
+    i_src = np.sin(2 * np.pi * np.arange(T + 1) / 13.0)
+    s, _ = orc.theta_modal(pb, 0.5, 1.0, T, i_src, keep=keep)
+    s1, _ = orc.theta_modal(orc.Problem(L1, R1, M1, M1.T), 0.5, 1.0, T, i_src)
+    assert np.abs(s - s1).max() < 1e-12 * np.abs(s1).max()
