@@ -29,6 +29,9 @@
  *   - exact integration of the decoupled modal equations for inputs linear
  *     between samples (the analytical route Sec. 3.3 leaves to later work;
  *     reading r11)
+ *   - the modal forcing and probe weights, and both modal steppers on a chosen
+ *     subset of the decoupled equations (the selective solution of Sec. 3.2;
+ *     reading r13)
  *
  * Readings of the paper taken where it is silent or inconsistent:
  *   (r1) the modal right-hand side is the Cholesky right-hand side expressed in
@@ -41,7 +44,10 @@
  *   (r10) the probe signal after step k is P (I^{k+1} - I^k) / dt;
  *   (r11) "exact" integration takes every source waveform linear between its
  *        samples (first-order hold), so on a step the modal forcing is
- *        g(s) = e0 + e1 s and each mode is integrated in closed form.
+ *        g(s) = e0 + e1 s and each mode is integrated in closed form;
+ *   (r13) a mode left out of the selective solution keeps y_n = 0 (its
+ *        equation is not solved); which modes to keep is decided outside this
+ *        file, by the coupling score of the Python wrapper's select_modes.
  */
 #include <math.h>
 #include <stdint.h>
