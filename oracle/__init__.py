@@ -29,6 +29,10 @@ Decomposition in Numerical Computation of Eddy Current Transients"):
                            frequency-domain method of Sec. 4.5).
 * ``adjoint_direct``    -- gradient of a probe-signal misfit through the
                            theta-method (adjoint recursion, every state kept).
+* ``ldlt_inertia``      -- Sylvester inertia of a symmetric matrix (Bunch-Kaufman
+                           LDL^T).
+* ``inertia``           -- the number of eigenvalues of the pencil of Sec. 3.2
+                           below, at and above a shift sigma (inertia of Ri - sigma Li).
 """
 from __future__ import annotations
 
@@ -77,9 +81,6 @@ def _load():
         lib.orc_null_basis.argtypes = [_i64, _i64, _dp, _dp]
         lib.orc_null_basis.restype = ctypes.c_int
         lib.orc_standard_form.argtypes = [_i64, _dp, _dp, _dp]
-        lib.orc_csr_to_dense.argtypes = [
-            _i64, _i64, ctypes.POINTER(ctypes.c_int64),
-            ctypes.POINTER(ctypes.c_int32), _dp, _dp]
         lib.orc_theta_direct.argtypes = [
             ctypes.POINTER(_Problem), ctypes.c_double, ctypes.c_double, _i64,
             _dp, _dp, _dp, _dp]
@@ -101,6 +102,10 @@ def _load():
             _i64, _dp, _dp, _i64, _dp, _dp, ctypes.c_double, ctypes.c_double, _i64,
             _dp, _dp, _dp, _dp, _dp]
         lib.orc_adjoint_direct.restype = ctypes.c_int
+        lib.orc_ldlt_inertia.argtypes = [_i64, _dp, ctypes.POINTER(ctypes.c_int64)]
+        lib.orc_inertia.argtypes = [ctypes.POINTER(_Problem), ctypes.c_double,
+                                    ctypes.POINTER(ctypes.c_int64)]
+        lib.orc_inertia.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -129,18 +134,6 @@ def assemble_L(xyz, h: float) -> np.ndarray:
     n = xyz.shape[0]
     out = np.empty((n, n))
     _load().orc_assemble_L(n, _ptr(xyz), float(h), _ptr(out))
-    return out
-
-
-def csr_to_dense(shape, rowptr, col, val) -> np.ndarray:
-    rows, cols = shape
-    rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
-    col = np.ascontiguousarray(col, dtype=np.int32)
-    val = _f64(val)
-    out = np.empty((rows, cols))
-    _load().orc_csr_to_dense(
-        rows, cols, rowptr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-        col.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _ptr(val), _ptr(out))
     return out
 
 
@@ -418,3 +411,25 @@ def adjoint_direct(L, R, M, P, theta: float, dt: float, T: int, i_src, obs):
     if rc:
         raise RuntimeError(_ERR.get(rc, str(rc)))
     return float(J[0]), dJdR, dJdi
+
+
+def ldlt_inertia(A):
+    """(negative, zero, positive) eigenvalue counts of the symmetric matrix A
+    (only its lower triangle is read), from the block-diagonal D of its
+    Bunch-Kaufman factorisation P A P^T = L D L^T (Sylvester's law of inertia)."""
+    A = _f64(A).copy()
+    counts = (ctypes.c_int64 * 3)()
+    _load().orc_ldlt_inertia(A.shape[0], _ptr(A), counts)
+    return int(counts[0]), int(counts[1]), int(counts[2])
+
+
+def inertia(pb: Problem, sigma: float):
+    """(#{lam_n < sigma}, #{lam_n = sigma}, #{lam_n > sigma}) for the
+    eigenvalues lam = 1/tau of the reduced pencil Ri v = lam Li v (Sec. 3.2),
+    from the inertia of Ri - sigma Li, a congruence of C - sigma I.  Costs one
+    dense factorisation (n0^3 / 3); safe to call from several threads."""
+    counts = (ctypes.c_int64 * 3)()
+    st = pb._struct()
+    if _load().orc_inertia(ctypes.byref(st), float(sigma), counts):
+        raise RuntimeError(_ERR[1])
+    return int(counts[0]), int(counts[1]), int(counts[2])

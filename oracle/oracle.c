@@ -74,16 +74,6 @@ void orc_assemble_L(int64_t n, const double *xyz, double h, double *L)
     }
 }
 
-/* CSR (int64 row pointers, int32 columns) to a dense row-major matrix. */
-void orc_csr_to_dense(int64_t rows, int64_t cols, const int64_t *rowptr,
-                      const int32_t *col, const double *val, double *out)
-{
-    memset(out, 0, sizeof(double) * (size_t)(rows * cols));
-    for (int64_t i = 0; i < rows; ++i)
-        for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p)
-            out[IDX(i, col[p], cols)] += val[p];
-}
-
 /* ------------------------------------------------------------------------ */
 /* Dense Cholesky A = G G^T (lower), in place; the upper triangle is zeroed. */
 /* Returns -1 on success, else the index of the first non-positive pivot.    */
@@ -1026,5 +1016,161 @@ int orc_adjoint_direct(int64_t n, const double *L, const double *R, int64_t C,
     free(mu);
     free(b);
     free(dJdu);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sylvester inertia of a symmetric matrix by the symmetric-indefinite       */
+/* factorisation P A P^T = L D L^T with Bunch-Kaufman pivoting (Bunch &      */
+/* Kaufman, "Some stable methods for calculating inertia and solving         */
+/* symmetric linear systems", Math. Comp. 31, 1977; Golub & Van Loan 4.4).   */
+/* D is block diagonal with 1x1 and 2x2 blocks; A and D are congruent, so    */
+/* by Sylvester's law of inertia they have the same numbers of negative,     */
+/* zero and positive eigenvalues.  Only the lower triangle of the trailing   */
+/* matrix is read and updated (A[i*n + j], i >= j); A is destroyed.  L is    */
+/* not kept: only D's blocks are needed.                                     */
+/* counts[0] = #negative, counts[1] = #zero, counts[2] = #positive.          */
+/* ------------------------------------------------------------------------ */
+static double lo_get(const double *A, int64_t n, int64_t i, int64_t j)
+{
+    return i >= j ? A[IDX(i, j, n)] : A[IDX(j, i, n)];
+}
+
+/* Symmetric interchange of rows and columns p < q of the trailing matrix    */
+/* A[k:, k:] in lower-triangle storage.                                      */
+static void lo_swap(double *A, int64_t n, int64_t k, int64_t p, int64_t q)
+{
+    double t;
+    if (p == q)
+        return;
+    for (int64_t j = k; j < p; ++j) {          /* row entries left of p */
+        t = A[IDX(p, j, n)];
+        A[IDX(p, j, n)] = A[IDX(q, j, n)];
+        A[IDX(q, j, n)] = t;
+    }
+    t = A[IDX(p, p, n)];                        /* the two diagonal entries */
+    A[IDX(p, p, n)] = A[IDX(q, q, n)];
+    A[IDX(q, q, n)] = t;
+    for (int64_t i = p + 1; i < q; ++i) {       /* column p below p, row q left of q */
+        t = A[IDX(i, p, n)];
+        A[IDX(i, p, n)] = A[IDX(q, i, n)];
+        A[IDX(q, i, n)] = t;
+    }
+    for (int64_t i = q + 1; i < n; ++i) {       /* columns p and q below q */
+        t = A[IDX(i, p, n)];
+        A[IDX(i, p, n)] = A[IDX(i, q, n)];
+        A[IDX(i, q, n)] = t;
+    }
+}
+
+void orc_ldlt_inertia(int64_t n, double *A, int64_t *counts)
+{
+    const double alpha = (1.0 + sqrt(17.0)) / 8.0;
+    double *u = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *w = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    counts[0] = counts[1] = counts[2] = 0;
+    int64_t k = 0;
+    while (k < n) {
+        /* largest off-diagonal entry of column k of the trailing matrix */
+        double lam = 0.0;
+        int64_t r = k;
+        for (int64_t i = k + 1; i < n; ++i)
+            if (fabs(A[IDX(i, k, n)]) > lam) {
+                lam = fabs(A[IDX(i, k, n)]);
+                r = i;
+            }
+        const double akk = fabs(A[IDX(k, k, n)]);
+        if (akk == 0.0 && lam == 0.0) {         /* zero row and column */
+            counts[1] += 1;
+            k += 1;
+            continue;
+        }
+        int two = 0;
+        if (akk < alpha * lam) {
+            /* largest off-diagonal entry of row/column r of the trailing matrix */
+            double sig = 0.0;
+            for (int64_t j = k; j < n; ++j)
+                if (j != r && fabs(lo_get(A, n, r, j)) > sig)
+                    sig = fabs(lo_get(A, n, r, j));
+            if (akk * sig >= alpha * lam * lam) {
+                /* 1x1 pivot a_kk */
+            } else if (fabs(A[IDX(r, r, n)]) >= alpha * sig) {
+                lo_swap(A, n, k, k, r);         /* 1x1 pivot a_rr */
+            } else {
+                lo_swap(A, n, k, k + 1, r);     /* 2x2 pivot on rows k, r */
+                two = 1;
+            }
+        }
+        if (!two) {
+            const double d = A[IDX(k, k, n)];
+            counts[d > 0.0 ? 2 : (d < 0.0 ? 0 : 1)] += 1;
+            for (int64_t i = k + 1; i < n; ++i)
+                u[i] = A[IDX(i, k, n)];
+            /* A22 -= u u^T / d on the lower triangle */
+            for (int64_t i = k + 1; i < n; ++i) {
+                const double li = u[i] / d;
+                double *row = A + IDX(i, 0, n);
+                for (int64_t j = k + 1; j <= i; ++j)
+                    row[j] -= li * u[j];
+            }
+            k += 1;
+        } else {
+            const double a = A[IDX(k, k, n)], b = A[IDX(k + 1, k, n)];
+            const double c = A[IDX(k + 1, k + 1, n)];
+            const double det = a * c - b * b;
+            if (det < 0.0) {
+                counts[0] += 1;
+                counts[2] += 1;
+            } else if (det > 0.0) {
+                counts[a + c > 0.0 ? 2 : 0] += 2;
+            } else {
+                counts[1] += 1;
+                counts[a + c > 0.0 ? 2 : (a + c < 0.0 ? 0 : 1)] += 1;
+            }
+            for (int64_t i = k + 2; i < n; ++i) {
+                u[i] = A[IDX(i, k, n)];
+                w[i] = A[IDX(i, k + 1, n)];
+            }
+            /* A22 -= [u w] D^{-1} [u w]^T on the lower triangle */
+            for (int64_t i = k + 2; i < n; ++i) {
+                const double l1 = (c * u[i] - b * w[i]) / det;
+                const double l2 = (a * w[i] - b * u[i]) / det;
+                double *row = A + IDX(i, 0, n);
+                for (int64_t j = k + 2; j <= i; ++j)
+                    row[j] -= l1 * u[j] + l2 * w[j];
+            }
+            k += 2;
+        }
+    }
+    free(u);
+    free(w);
+}
+
+/* Inertia of Ri - sigma Li (Sec. 3.2, eq. generalized_eigenvalues_discrete, */
+/* lambda = 1/tau).  Ri - sigma Li = G (C - sigma I) G^T with Li = G G^T, a   */
+/* congruence, so counts[0] = #{lambda_n < sigma}, counts[1] = #{lambda_n =  */
+/* sigma} (exact zeros only) and counts[2] = #{lambda_n > sigma}.  Without   */
+/* electrodes the pencil is (R, L) itself and no reduction is formed.        */
+/* Returns 0, or 1 if the electrode matrix is rank deficient.                */
+int orc_inertia(const orc_problem *pb, double sigma, int64_t *counts)
+{
+    const int64_t n0 = pb->n - pb->m;
+    double *A = (double *)malloc(sizeof(double) * (size_t)(n0 * n0));
+    if (pb->m == 0) {
+        for (int64_t a = 0; a < n0 * n0; ++a)
+            A[a] = pb->R[a] - sigma * pb->L[a];
+    } else {
+        orc_reduced r;
+        if (reduce(pb, &r)) {
+            free_reduced(&r);
+            free(A);
+            return 1;
+        }
+        for (int64_t a = 0; a < n0 * n0; ++a)
+            A[a] = r.Ri[a] - sigma * r.Li[a];
+        free_reduced(&r);
+    }
+    orc_ldlt_inertia(n0, A, counts);
+    free(A);
     return 0;
 }

@@ -1,0 +1,67 @@
+"""Write stored eigenvalue counts of the 128x128 plate with a crack
+(N = 16,384: log-uniform resistivity in [0.5, 2], seed 0, a 10x3-cell crack
+of resistivity 1e3, the workload of the crack-signature runs).
+
+For each shift sigma on a fixed logarithmic grid the oracle computes the
+Sylvester inertia of R - sigma L (Sec. 3.2, eq. generalized_eigenvalues_
+discrete with lambda = 1/tau): the number of generalized eigenvalues below
+sigma equals the number of negative pivots of its Bunch-Kaufman LDL^T.  The
+grid does not depend on any computed eigenvalue.
+
+Run from the repository root:  python tests/golden/make_inertia_golden.py
+(one dense factorisation of order 16,384 per shift, 15-25 minutes each on
+one core; THREADS shifts at a time).  Every value comes from oracle/;
+nothing here comes from the GPU library.
+"""
+import concurrent.futures
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from paper_2407_11993_amd import inputs  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+OUT = os.path.join(HERE, "plate128_crack_inertia.txt")
+# half decades from 10^-4.5 to 10^5 (the spectrum of this plate lies inside)
+SIGMAS = [10.0 ** (e / 2.0) for e in range(-9, 11)]
+THREADS = int(os.environ.get("THREADS", "4"))
+
+
+def main():
+    oracle.build(force=False)
+    w = inputs.config2(T=1)
+    L = oracle.assemble_L(w.xyz, w.h)
+    R = w.R.to_dense()
+    pb = oracle.Problem(L, R, w.M, w.P)
+    done = {}
+    if os.path.exists(OUT):  # resume: keep the shifts already counted
+        for row in np.atleast_2d(np.loadtxt(OUT)):
+            done[float(row[0])] = (int(row[1]), int(row[2]), int(row[3]))
+    todo = [s for s in SIGMAS if not any(abs(s - d) <= 1e-12 * s for d in done)]
+
+    def count(sigma):
+        t0 = time.perf_counter()
+        c = oracle.inertia(pb, sigma)
+        print(f"sigma {sigma:.6e}: below {c[0]}, at {c[1]}, above {c[2]} "
+              f"({time.perf_counter() - t0:.0f} s)", flush=True)
+        return sigma, c
+
+    with concurrent.futures.ThreadPoolExecutor(max_workers=THREADS) as ex:
+        for sigma, c in ex.map(count, todo):
+            done[sigma] = c
+            rows = sorted((s, *v) for s, v in done.items())
+            np.savetxt(OUT, np.array(rows), fmt=["%.17e", "%d", "%d", "%d"],
+                       header=f"{w.name} (N = {w.n}): sigma, #lambda < sigma, "
+                              f"#lambda = sigma, #lambda > sigma for the pencil "
+                              f"R v = lambda L v; oracle.inertia "
+                              f"(Bunch-Kaufman LDL^T of R - sigma L)")
+
+
+if __name__ == "__main__":
+    main()

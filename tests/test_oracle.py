@@ -641,3 +641,125 @@ def test_tol_zero_keeps_exactly_the_driven_subsystem(orc):
     s, _ = orc.theta_modal(pb, 0.5, 1.0, T, i_src, keep=keep)
     s1, _ = orc.theta_modal(orc.Problem(L1, R1, M1, M1.T), 0.5, 1.0, T, i_src)
     assert np.abs(s - s1).max() < 1e-12 * np.abs(s1).max()
+
+
+# ---------------------------------------------------------------------------
+# Sylvester inertia (Bunch-Kaufman LDL^T): the large-size eigenvalue check
+# ---------------------------------------------------------------------------
+def _counts(eigs, sigma=0.0):
+    eigs = np.asarray(eigs)
+    return (int((eigs < sigma).sum()), int((eigs == sigma).sum()), int((eigs > sigma).sum()))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_ldlt_inertia_matches_library_eigenvalues(orc, seed):
+    rng = np.random.default_rng(seed)
+    n = 61
+    A = rng.standard_normal((n, n))
+    A = A + A.T
+    A -= rng.uniform(-2, 2) * np.eye(n)
+    assert orc.ldlt_inertia(A) == _counts(np.linalg.eigvalsh(A))
+
+
+def test_ldlt_inertia_needs_2x2_pivots(orc):
+    # zero diagonal: every first pivot is a 2x2 block (one negative, one positive)
+    assert orc.ldlt_inertia(np.array([[0.0, 1.0], [1.0, 0.0]])) == (1, 0, 1)
+    rng = np.random.default_rng(9)
+    B = rng.standard_normal((20, 20))
+    A = np.block([[np.zeros((20, 20)), B], [B.T, np.zeros((20, 20))]])  # +-singular values
+    assert orc.ldlt_inertia(A) == (20, 0, 20)
+    # a tiny diagonal next to large off-diagonal entries
+    A = np.array([[1e-8, 3.0, 0.5], [3.0, 1e-8, 2.0], [0.5, 2.0, -4.0]])
+    assert orc.ldlt_inertia(A) == _counts(np.linalg.eigvalsh(A))
+
+
+def test_ldlt_inertia_diagonal_and_zeros(orc):
+    d = np.array([3.0, -1.0, 0.0, 2.0, -5.0, 0.0, 7.0])
+    assert orc.ldlt_inertia(np.diag(d)) == (2, 2, 3)
+    # a zero row and column in the middle of an otherwise definite matrix
+    A = _spd(9, 11)
+    A[4, :] = 0.0
+    A[:, 4] = 0.0
+    assert orc.ldlt_inertia(A) == (0, 1, 8)
+    # a permuted positive definite matrix has no negative pivots
+    p = np.random.default_rng(12).permutation(30)
+    S = _spd(30, 13)[p][:, p]
+    assert orc.ldlt_inertia(S) == (0, 0, 30)
+
+
+def test_inertia_counts_pencil_eigenvalues(orc):
+    xyz, L, R, M = _small_problem(orc, dims=(4, 3, 2), seed=4)
+    pb = orc.Problem(L, R, M, M.T)
+    lam = np.sort(np.real(sla.eigvals(R, L)))
+    # shifts between consecutive eigenvalues (and beyond both ends)
+    cuts = np.concatenate([[lam[0] / 2], 0.5 * (lam[1:] + lam[:-1]), [2 * lam[-1]]])
+    for q, sigma in enumerate(cuts[::3]):
+        k = 3 * q
+        assert orc.inertia(pb, sigma) == (k, 0, lam.size - k)
+
+
+def test_inertia_2x2_pencil_quadratic_formula(orc):
+    # det(R - s L) = 0 for the pencil R = [[2, -1], [-1, 3]], L = [[1, .3], [.3, 1]]
+    R = np.array([[2.0, -1.0], [-1.0, 3.0]])
+    L = np.array([[1.0, 0.3], [0.3, 1.0]])
+    a = L[0, 0] * L[1, 1] - L[0, 1] ** 2
+    b = -(R[0, 0] * L[1, 1] + R[1, 1] * L[0, 0] - 2 * R[0, 1] * L[0, 1])
+    c = R[0, 0] * R[1, 1] - R[0, 1] ** 2
+    r1 = (-b - math.sqrt(b * b - 4 * a * c)) / (2 * a)
+    r2 = (-b + math.sqrt(b * b - 4 * a * c)) / (2 * a)
+    pb = orc.Problem(L, R, np.zeros((2, 1)), np.ones((1, 2)))
+    for sigma, k in ((r1 * (1 - 1e-9), 0), (r1 * (1 + 1e-9), 1), (r2 * (1 - 1e-9), 1),
+                     (r2 * (1 + 1e-9), 2)):
+        assert orc.inertia(pb, sigma)[0] == k
+
+
+def test_inertia_diagonal_pencil(orc):
+    # L, R diagonal: lam_i = R_ii / L_ii
+    Ld = np.array([1.0, 2.0, 0.5, 4.0, 1.5])
+    Rd = np.array([3.0, 1.0, 2.0, 8.0, 0.3])
+    pb = orc.Problem(np.diag(Ld), np.diag(Rd), np.zeros((5, 1)), np.ones((1, 5)))
+    lam = np.sort(Rd / Ld)   # 0.2, 0.5, 2, 3, 4
+    for sigma in (0.1, 0.3, 1.0, 2.5, 3.5, 5.0):
+        assert orc.inertia(pb, sigma)[0] == int((lam < sigma).sum())
+
+
+def test_inertia_with_electrodes_uses_the_reduced_pencil(orc):
+    w, L, R, E = _electrode_problem(orc)
+    pb = orc.Problem(L, R, w.M, w.P, E)
+    K2 = sla.null_space(E)
+    lam = np.sort(np.real(sla.eigvals(K2.T @ R @ K2, K2.T @ L @ K2)))
+    cuts = 0.5 * (lam[1:] + lam[:-1])
+    for k in (1, 5, 11, lam.size - 1):
+        assert orc.inertia(pb, cuts[k - 1]) == (k, 0, lam.size - k)
+
+
+# ---------------------------------------------------------------------------
+# modal weights: basis-free identities for every column, electrodes included
+# ---------------------------------------------------------------------------
+def test_mode_weights_basis_free_identities(orc):
+    """With L_i-normalised eigenvectors V (V^T L_i V = I, V^T R_i V = Lam),
+    V V^T = L_i^{-1} and V Lam^{-1} V^T = R_i^{-1}, so for the forcing columns
+    F = K^T [R A_D | L A_D | M0] and the probe weights Pw = (P K V)^T:
+        Pw^T W          = P K L_i^{-1} K^T [R A_D | L A_D | M0],
+        Pw^T Lam^{-1} W = P K R_i^{-1} K^T [R A_D | L A_D | M0],
+    both independent of the basis K of ker E (here scipy's SVD basis, not the
+    oracle's Householder one) and of the eigenvector basis.  A wrong sign,
+    scale or order of the R_D or L_D columns breaks them."""
+    w, L, R, E = _electrode_problem(orc)
+    P = np.vstack([w.P, np.random.default_rng(31).standard_normal((2, w.n))])
+    pb = orc.Problem(L, R, w.M, P, E)
+    lam, W, Pw = orc.mode_weights(pb)
+    K = sla.null_space(E)
+    AD = np.linalg.pinv(E)
+    Fu = np.hstack([R @ AD, L @ AD, w.M])
+    Li, Ri = K.T @ L @ K, K.T @ R @ K
+    ref1 = P @ K @ np.linalg.solve(Li, K.T @ Fu)
+    ref2 = P @ K @ np.linalg.solve(Ri, K.T @ Fu)
+    got1 = Pw.T @ W
+    got2 = Pw.T @ (W / lam[:, None])
+    assert W.shape == (w.n - 1, 3) and Pw.shape == (w.n - 1, 3)
+    assert np.abs(got1 - ref1).max() < 1e-11 * np.abs(ref1).max()
+    assert np.abs(got2 - ref2).max() < 1e-11 * np.abs(ref2).max()
+    # each column on its own, so that no column is checked only through others
+    for j in range(3):
+        assert np.abs(got1[:, j] - ref1[:, j]).max() < 1e-11 * np.abs(ref1[:, j]).max()
