@@ -24,6 +24,7 @@ import os
 import sys
 import time
 
+T_START = time.perf_counter()  # the wall-clock budget counts from here
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -55,7 +56,14 @@ def run_electrodes(args):
     decomposition, all steps), and the Cholesky method's factorisation plus a
     measured block of steps whose per-step time is extrapolated to all steps
     (reported as such).  The signals of the two methods are compared over the
-    measured steps."""
+    measured steps.
+
+    One end-to-end run of the paper-scale plate takes about a minute, so
+    --warmup and --steps are upper bounds: the warm-up runs use a 48 x 72
+    plate of the same kind (compiling and loading every kernel the timed run
+    uses), and timed runs are added while the wall-clock budget (--budget-s,
+    counted from the start of the process, with room kept for the CPU
+    baseline) leaves room for one more.  `steps` reports the runs timed."""
     import torch
     from paper_2407_11993_amd import Solver
 
@@ -67,33 +75,30 @@ def run_electrodes(args):
     theta, dt = w.thetas[0], w.dt
     K = min(args.chol_steps, T)
     stream = torch.cuda.current_stream()
-    i_src = torch.as_tensor(w.i_src, dtype=torch.float64, device="cuda")
-    i_D = torch.as_tensor(w.i_D, dtype=torch.float64, device="cuda")
     tones_hz = [1, 50, 100, 150, 250, 300, 400, 600, 700, 800, 900, 1000, 1500, 2000, 2500,
                 3000, 3500, 4000, 4500, 5000, 5500, 6000, 6500, 7000, 7500, 8000, 8500, 9000,
                 9500, 10000]
     omegas = [2 * math.pi * f / 30000.0 for f in tones_hz]
-    amps_src = [[1.0] * w.M.shape[1]] * len(omegas)
-    amps_D = [[1.0] * w.m] * len(omegas) if w.m else None
 
-    def one_step():
+    def one_step(w, K, tag):
+        T = w.T
+        # waveforms resident in HBM before the timed region of the run
+        i_src = torch.as_tensor(w.i_src, dtype=torch.float64, device="cuda")
+        i_D = torch.as_tensor(w.i_D, dtype=torch.float64, device="cuda")
+        amps_src = [[1.0] * w.M.shape[1]] * len(omegas)
+        amps_D = [[1.0] * w.m] * len(omegas) if w.m else None
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(16)]
         torch.cuda.synchronize()
         ev[0].record(stream)
         s = Solver(w)
         ev[1].record(stream)
-        torch.cuda.synchronize()
-        print("bench: setup done", file=sys.stderr, flush=True)
         s.decompose(projected=True)
         ev[2].record(stream)
         torch.cuda.synchronize()
-        print(f"bench: N={w.n}, projected decomposition "
+        print(f"bench: {tag} N={w.n}, projected decomposition "
               f"{ev[1].elapsed_time(ev[2]) / 1e3:.2f} s", file=sys.stderr, flush=True)
         sm = s.step_modal(theta, dt, T, i_src, i_D)
         ev[3].record(stream)
-        torch.cuda.synchronize()
-        print(f"bench: {T} modal steps {ev[2].elapsed_time(ev[3]) / 1e3:.2f} s",
-              file=sys.stderr, flush=True)
         # the same run with exact per-mode integration (waveforms linear
         # between samples): no time-step error, same cost
         s.reset()
@@ -102,10 +107,11 @@ def run_electrodes(args):
         ev[8].record(stream)
         torch.cuda.synchronize()
         exact_diff = float((sm - sx).abs().max() / sx.abs().max())
-        # steady-state phasors of the probe at the paper's 30 tones (Sec. 4.5,
-        # sampled at 30 kS/s, so w = 2 pi f / 30000 per step), unit amplitudes
+        # steady-state phasors of the probe at the paper's 30 tones (Sec. 4.3,
+        # sampled at 30 kS/s as in Sec. 4.6, so w = 2 pi f / 30000 per step),
+        # unit amplitudes
         ev[9].record(stream)
-        ph = s.phasors(omegas, amps_src, amps_D)
+        s.phasors(omegas, amps_src, amps_D)
         ev[10].record(stream)
         torch.cuda.synchronize()
         # selective solution (Sec. 3.2): only the modes with a coupling score
@@ -132,7 +138,7 @@ def run_electrodes(args):
         ev[6].record(stream)
         torch.cuda.synchronize()
         t = [ev[i].elapsed_time(ev[i + 1]) / 1e3 for i in range(6)]
-        print(f"bench: Cholesky factorisation {t[4]:.2f} s, {K} steps {t[5]:.2f} s",
+        print(f"bench: {tag} Cholesky factorisation {t[4]:.2f} s, {K} steps {t[5]:.2f} s",
               file=sys.stderr, flush=True)
         agree = float((sm[:K] - sc).abs().max() / sc.abs().max())
         s.close()
@@ -145,11 +151,23 @@ def run_electrodes(args):
                 "modal_selective_steps_scan": ev[14].elapsed_time(ev[15]) / 1e3}, \
             (agree, exact_diff, sel)
 
-    for _ in range(args.warmup):
-        one_step()
+    if args.warmup:
+        ww = _electrode_workload("plate-48x72-electrodes", min(T, 2000))
+        for i in range(args.warmup):
+            one_step(ww, min(K, ww.T), f"warm-up {i + 1}/{args.warmup}")
+    runs, walls = [], []
     t0 = time.perf_counter()
-    runs = [one_step() for _ in range(args.steps)]
+    while len(runs) < args.steps:
+        if walls:
+            left = args.budget_s - (time.perf_counter() - T_START) - args.cpu_reserve_s
+            if left < 1.1 * max(walls):
+                break
+        ts = time.perf_counter()
+        runs.append(one_step(w, K, f"timed run {len(runs) + 1}"))
+        walls.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    n_timed = len(runs)
     avg = {k: sum(r[0][k] for r in runs) / len(runs) for k in runs[0][0]}
     agree = max(r[1][0] for r in runs)
     exact_diff = max(r[1][1] for r in runs)
@@ -165,14 +183,17 @@ def run_electrodes(args):
     dec_flops = (1 / 3 + 1 / 3 + 1 / 3 + 4 / 3) * float(n0) ** 3  # potrf, trtri, C, band
     return {
         "metric": "end-to-end s, modal theta-method (Cholesky theta-method beside it)",
-        "value": round(modal_s, 3), "unit": "s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(1e3 * wall / args.steps, 1),
+        "value": round(modal_s, 3), "unit": "s", "n_gpus": 1, "steps": n_timed,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * wall / n_timed, 1),
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": w.name, "N": w.n, "N0": n0, "T": T, "theta": theta, "dt": dt,
                    "electrodes": w.m + 1, "probes": w.n_probe,
                    "decomposition": "eigenvalues and projected weights Q^T G^-1 [F, P] "
-                                    "(the eigenvector matrix is not formed)"},
+                                    "(the eigenvector matrix is not formed)",
+                   "step": "one end-to-end run of both methods (warm-up runs on a 48x72 "
+                           "plate with two electrodes, T = 2000)",
+                   "steps_requested": args.steps},
         "cholesky_s_extrapolated": round(chol_s, 1),
         "cholesky_steps_measured": K,
         "speedup_modal_vs_cholesky": round(chol_s / modal_s, 2),
@@ -577,57 +598,110 @@ def run_gpu(args):
     return res
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(args):
     """The oracle (plain C, one thread) on a bounded sample of the same kind
-    of workload, scaled to it: decomposition by (N/n)^3, stepping by
-    (N/n)^2 (T/t)."""
+    of workload: three small plates, each timed for the decomposition
+    (Cholesky, standard form, cyclic Jacobi, eigenvectors), the modal steps
+    and the direct Cholesky stepper.  Power laws t = a N^b fitted to the three
+    sizes (least squares in log-log) extrapolate the decomposition to the
+    workload's N and the steps to its N and T; the fitted exponents are
+    reported beside the value, which is an extrapolation."""
+    import numpy as np
     import oracle
     from paper_2407_11993_amd import inputs
     oracle.build(force=False)
-    t_sample = 4000
+    t_sample = 2000
     if args.workload.endswith("-electrodes"):
         full = _electrode_workload(args.workload, args.T)
-        w = inputs.electrode_plate(24, 36, 6, T=t_sample)
-        what = "a 24x36 plate with two 6-cell electrodes"
+        samples = [inputs.electrode_plate(nx, ny, ew, T=t_sample)
+                   for nx, ny, ew in ((12, 18, 4), (16, 24, 4), (20, 30, 6))]
+        what = "plates of 12x18, 16x24 and 20x30 cells with two electrodes"
     else:
         full = _workload(args.workload, args.T)
-        side = 20
-        w = inputs.plate(side, side, seed=0, crack=((8, 12), (9, 10), 1e3), T=t_sample,
-                         wave="gauss", coil=((side - 1) / 2, (side - 1) / 2, 2.0))
-        what = f"a {side}x{side} plate with a crack"
-    L = oracle.assemble_L(w.xyz, w.h)
-    pb = oracle.Problem(L, w.R.to_dense(), w.M, w.P,
-                        E=None if w.E is None else w.E.to_dense())
-    i_D = w.i_D if w.m else None
-    t0 = time.perf_counter()
-    oracle.modal_eigen(pb, want_V=True)
-    t_dec = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    oracle.theta_modal(pb, 0.5, 1.0, t_sample, w.i_src, i_D)
-    t_modal = time.perf_counter() - t0 - t_dec
-    t0 = time.perf_counter()
-    oracle.theta_direct(pb, 0.5, 1.0, t_sample, w.i_src, i_D)
-    t_direct = time.perf_counter() - t0
-    r = full.n / w.n
+        samples = []
+        for side in (14, 18, 24):
+            c0 = side // 2 - 2
+            samples.append(inputs.plate(side, side, seed=0, crack=((c0, c0 + 4), (c0, c0 + 1), 1e3),
+                                        T=t_sample, wave="gauss",
+                                        coil=((side - 1) / 2, (side - 1) / 2, 2.0)))
+        what = "square plates of 14, 18 and 24 cells a side with a crack"
+    ns, t_dec, t_mod, t_dir = [], [], [], []
+    for w, reps in zip(samples, (3, 2, 1)):  # best of a few at the small sizes
+        L = oracle.assemble_L(w.xyz, w.h)
+        pb = oracle.Problem(L, w.R.to_dense(), w.M, w.P,
+                            E=None if w.E is None else w.E.to_dense())
+        i_D = w.i_D if w.m else None
+        td = tm = tc = math.inf
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            oracle.modal_eigen(pb, want_V=True)
+            d = time.perf_counter() - t0
+            td = min(td, d)
+            t0 = time.perf_counter()
+            oracle.theta_modal(pb, 0.5, 1.0, t_sample, w.i_src, i_D)
+            tm = min(tm, max(time.perf_counter() - t0 - d, 1e-6))
+            t0 = time.perf_counter()
+            oracle.theta_direct(pb, 0.5, 1.0, t_sample, w.i_src, i_D)
+            tc = min(tc, time.perf_counter() - t0)
+        ns.append(w.n)
+        t_dec.append(td)
+        t_mod.append(tm / t_sample)
+        t_dir.append(tc / t_sample)
+        print(f"bench: cpu baseline N={w.n}: decomposition {td:.2f} s, modal steps "
+              f"{tm:.2f} s, direct {tc:.2f} s", file=sys.stderr, flush=True)
+
+    def fit(t):
+        b, a = np.polyfit(np.log(ns), np.log(t), 1)
+        return float(b), (lambda n: float(math.exp(a) * n ** b))
+
+    b_dec, f_dec = fit(t_dec)
+    b_dir, f_dir = fit(t_dir)
     nth = len(full.thetas)
-    modal_est = t_dec * r ** 3 + max(t_modal, 0.0) * r ** 2 * (full.T / t_sample) * nth
+    n_full = full.n - full.m
+    # the modal steps are N scalar recurrences per step: linear in N, the
+    # constant taken from the largest sample (a difference of two timings,
+    # too noisy at the small sizes for a fit of its own)
+    step_modal = t_mod[-1] * n_full / ns[-1]
+    modal_est = f_dec(n_full) + step_modal * full.T * nth
+    chol_est = f_dir(n_full) * full.T * nth
+    # the same from the largest sample by the textbook exponents (N^3 for the
+    # decomposition, N^2 per direct step)
+    r = n_full / ns[-1]
+    modal_text = t_dec[-1] * r ** 3 + step_modal * full.T * nth
+    chol_text = t_dir[-1] * r ** 2 * full.T * nth
     return {"value": round(modal_est, 1), "unit": "s", "cores": 1, "kind": "oracle",
+            "extrapolated": True,
+            "host": {"cpus": os.cpu_count(), "model": _cpu_model()},
             "sample": (f"oracle modal path (Jacobi decomposition + modal theta-steps) and "
-                       f"direct Cholesky stepper on {what} (N={w.n}, T={t_sample}, "
-                       f"theta=0.5): decomposition {t_dec:.2f} s, modal steps "
-                       f"{max(t_modal, 0):.2f} s, direct {t_direct:.2f} s; value "
-                       f"extrapolated to N={full.n}, T={full.T} x {nth} theta(s) by N^3 "
-                       f"(decomposition) and N^2 T (steps)"),
-            "cholesky_estimate_s": round(t_direct * r ** 2 * (full.T / t_sample) * nth, 1)}
+                       f"direct Cholesky stepper, one thread, on {what} (N = "
+                       f"{', '.join(str(n) for n in ns)}; T = {t_sample}, theta = 0.5): "
+                       f"decomposition {', '.join(f'{t:.2f}' for t in t_dec)} s; value "
+                       f"extrapolated to N = {n_full}, T = {full.T} x {nth} theta(s) by the "
+                       f"fitted power laws"),
+            "fitted_exponents": {"decomposition": round(b_dec, 2),
+                                 "direct_step": round(b_dir, 2)},
+            "cholesky_estimate_s": round(chol_est, 1),
+            "textbook_exponents_estimate_s": {"modal": round(modal_text, 1),
+                                              "cholesky": round(chol_text, 1)}}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=None,
-                    help="untimed runs first (default 1; 0 for the electrode plates, whose "
-                         "one run is minutes of GPU time at full size)")
+    ap.add_argument("--warmup", type=int, default=1,
+                    help="untimed runs first (the electrode plates warm up on a 48x72 plate)")
     ap.add_argument("--workload", default="plate-256x384-electrodes",
                     help="plate-256x384-electrodes (N = 98,304, 1e5 steps: the headline), "
                          "plate-WxH-electrodes, plate-128x128-crack, block-8x8x8, "
@@ -638,9 +712,12 @@ def main():
                     help="adjoint workload: cells checked by central differences")
     ap.add_argument("--chol-steps", type=int, default=300,
                     help="electrode plates: Cholesky steps measured (the rest extrapolated)")
+    ap.add_argument("--budget-s", type=float, default=420.0,
+                    help="electrode plates: wall-clock seconds from process start within "
+                         "which timed runs are added (at least one is always run)")
+    ap.add_argument("--cpu-reserve-s", type=float, default=60.0,
+                    help="electrode plates: seconds of the budget kept for the CPU baseline")
     args = ap.parse_args()
-    if args.warmup is None:
-        args.warmup = 0 if args.workload.endswith("-electrodes") else 1
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; --gpus above 1 is not supported "
               "(the design document describes how the method would shard)", file=sys.stderr)
