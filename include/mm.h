@@ -51,14 +51,16 @@ typedef enum {
 
 typedef struct mm_ctx mm_ctx;
 
-/* The problem statement (Sec. 3.1).  All pointers are device pointers. */
+/* The problem statement (Sec. 3.1).  All pointers are device pointers.
+ * Every floating-point input must be finite (MM_E_INVALID otherwise). */
 typedef struct {
   int64_t n;                /* unknowns N */
-  const double* xyz;        /* n x 3, row i = centre of cell i (row-major);
-                               L_ij = h / sqrt(|x_i - x_j|^2 + h^2) is
-                               assembled on the device (the SPD stand-in of
-                               the inductance matrix, Sec. 3.1 L_jk) */
-  double h;                 /* kernel width, > 0 */
+  const double* xyz;        /* when L is NULL: n x 3, row i = centre of cell i
+                               (row-major); L_ij = h / sqrt(|x_i - x_j|^2 + h^2)
+                               is then generated on the device (an SPD stand-in
+                               of the inductance matrix, Sec. 3.1 L_jk), and no
+                               dense copy of L is ever stored */
+  double h;                 /* kernel width, > 0 (used with xyz only) */
   int64_t r_nnz;            /* R: symmetric positive definite, CSR, n x n */
   const int64_t* r_rowptr;  /* n + 1 */
   const int32_t* r_col;     /* r_nnz, sorted per row */
@@ -73,6 +75,20 @@ typedef struct {
   int32_t n_probe;          /* probe rows, 1..4096 */
   const double* P;          /* n x n_probe, column-major: column p is probe
                                row p; signal_p = P(:,p)^T dI/dt */
+  const double* L;          /* NULL, or the inductance matrix itself (Sec. 3.1,
+                               the Galerkin L_jk of eq. discrete_version_1a):
+                               n x n, column-major with leading dimension ldl,
+                               symmetric positive definite.  Only its lower
+                               triangle is read.  BORROWED: the library reads it
+                               at setup (electrode reduction), at every
+                               decomposition and at every Cholesky
+                               factorisation, and never writes it, so it must
+                               stay valid and unchanged until mm_destroy.  xyz
+                               and h are then ignored.  It costs 8 n^2 bytes of
+                               device memory beside the library's own buffers
+                               (the projected decomposition peaks at three
+                               n0^2 buffers). */
+  int64_t ldl;              /* leading dimension of L, >= n */
 } mm_problem;
 
 /* Copy the problem to the device and prepare the context.  `stream` is a
@@ -86,10 +102,14 @@ typedef struct {
 mm_status mm_setup(const mm_problem* problem, void* stream, mm_ctx** out);
 
 /* The one-off modal decomposition (Sec. 3.2): Li = G G^T, C = G^{-1} Ri G^{-T},
- * C = Q Lam Q^T (two-stage tridiagonalisation + divide and conquer), and the
- * projections of the sources and probes onto the modes.  Independent of theta
- * and dt.  Synchronises the stream.  Errors: MM_E_NOT_SPD (Li not positive
- * definite), MM_E_NO_CONVERGE. */
+ * C = Q Lam Q^T (two-stage tridiagonalisation + divide and conquer), the
+ * pencil's eigenvectors V = G^{-T} Q (V^T Li V = I, V^T Ri V = Lam, the V_n of
+ * eq. modal_decomposition_discrete) and the projections V^T [F, P] of the
+ * sources and probes onto the modes.  Independent of theta and dt.  Device
+ * memory: at most three n0^2 buffers at any time (G^{-1} is formed twice,
+ * once for C and once for V, rather than held through the eigensolver); only
+ * V (n0^2) is kept afterwards.  Synchronises the stream.  Errors:
+ * MM_E_NOT_SPD (Li not positive definite), MM_E_NO_CONVERGE, MM_E_NOMEM. */
 mm_status mm_decompose(mm_ctx* ctx);
 
 /* The decomposition as the modal signals need it (Sec. 3.2 feeding Sec. 3.3.2):
@@ -110,7 +130,14 @@ mm_status mm_decompose_projected(mm_ctx* ctx);
  * eq. time_integration) written in the modal basis.  signal (n_steps x
  * n_probe, row-major by step) receives P^T (I^{k+1} - I^k) / dt for
  * k = 0..n_steps-1.  i_src: (n_steps+1) x n_src; i_D: (n_steps+1) x (Ne-1)
- * or NULL when Ne = 0.  Requires mm_decompose.  theta in [0, 1], dt > 0. */
+ * or NULL when Ne = 0.  Requires mm_decompose.  theta in [0, 1], dt > 0.
+ * Up to 8 probes the probe sums are reduced inside the stepping kernel; with
+ * more (Sec. 4.4 observes 301 points) the steps run in chunks whose
+ * amplitude increments dY (n0 x L, at most 2 GiB) are written out and
+ * projected as one matrix product P~^T dY; the signal is the same up to the
+ * order of the sums.  This holds for mm_step_modal_exact,
+ * mm_step_modal_selective (without MM_STEP_SCAN) and mm_step_cholesky
+ * (current increments, P^T dI) too. */
 mm_status mm_step_modal(mm_ctx* ctx, double theta, double dt, int64_t n_steps,
                         const double* i_src, const double* i_D, double* signal);
 
@@ -134,7 +161,8 @@ mm_status mm_step_modal_exact(mm_ctx* ctx, double dt, int64_t n_steps,
  * in parallel, are chained by A^L per mode, and run again from their start
  * states (twice the mode-steps, (N/256) x (T/L) workgroups instead of N/256).
  * Same arguments, state, signal (to rounding) and errors as those calls; at
- * most 65535 x 2^16 steps.  Allocates 2 T/L N doubles of workspace. */
+ * most 65535 x 2^16 steps and 8 probes.  Allocates 2 T/L N doubles of
+ * workspace. */
 mm_status mm_step_modal_scan(mm_ctx* ctx, double theta, int32_t exact, double dt,
                              int64_t n_steps, const double* i_src, const double* i_D,
                              double* signal);
@@ -176,7 +204,7 @@ mm_status mm_step_modal_selective(mm_ctx* ctx, double theta, uint32_t flags, dou
 
 /* Steady-state phasors of the probe signals under sinusoidal sources, from
  * the decomposition (Sec. 3.2, eq. modal_decomposition_discrete; the
- * frequency-domain comparison of Sec. 4.5): with i0_c(t) = Re{A_c e^{jwt}}
+ * frequency-domain comparison of Sec. 4.6): with i0_c(t) = Re{A_c e^{jwt}}
  * and iD_a(t) = Re{D_a e^{jwt}} every mode has the phasor
  *   y_n = (W u(w))_n / (lam_n + j w),
  * u: -D on the R_D columns, -j w D on the L_D columns, -j w A on the source
@@ -206,7 +234,7 @@ mm_status mm_step_cholesky(mm_ctx* ctx, double theta, double dt, int64_t n_steps
 #define MM_CHOLESKY 1
 
 /* Reconstruction of the current (Sec. 3.1, eq. current_electrodes):
- * I = K Ii + E^T (E E^T)^{-1} iD, with Ii = G^{-T} Q y for the modal state.
+ * I = K Ii + E^T (E E^T)^{-1} iD, with Ii = V y for the modal state.
  * rows == NULL: out (n) receives I.  Otherwise rows is n x n_rows
  * (column-major) and out (n_rows) receives rows^T I. */
 mm_status mm_probe(mm_ctx* ctx, int32_t which, int32_t n_rows,
@@ -214,6 +242,20 @@ mm_status mm_probe(mm_ctx* ctx, int32_t which, int32_t n_rows,
 
 /* Set both states back to I = 0. */
 mm_status mm_reset_state(mm_ctx* ctx);
+
+/* Checkpoint and restart of one method's time stepping (Sec. 3.3: every step
+ * continues from the state the previous one left).  The state is n doubles
+ * (device): the method's reduced unknowns, n0 of them (which = MM_MODAL: the
+ * modal amplitudes y; MM_CHOLESKY: the reduced currents Ii), followed by the
+ * Ne - 1 injected currents of its last step.  The reduced unknowns depend on
+ * the basis of ker E and, for MM_MODAL, on the decomposition, so a state is
+ * meaningful only for a context of the same problem (and, for MM_MODAL, the
+ * same decomposition).  The selective stepper's own state is not included.
+ * mm_get_state: MM_E_STATE for MM_MODAL before a decomposition and for
+ * MM_CHOLESKY before its first step; mm_set_state: MM_E_STATE for MM_MODAL
+ * before a decomposition.  Stream-ordered copies. */
+mm_status mm_get_state(mm_ctx* ctx, int32_t which, double* out);
+mm_status mm_set_state(mm_ctx* ctx, int32_t which, const double* in);
 
 /* Eigenvalues lam_n = 1/tau_n of the reduced pencil, ascending (n0 doubles,
  * device).  Requires mm_decompose. */

@@ -26,7 +26,7 @@ Decomposition in Numerical Computation of Eddy Current Transients"):
                            modal steppers take the kept set as ``keep``.
 * ``phasors_direct``    -- steady-state probe phasors under sinusoidal sources: one
                            complex solve of the unreduced system per frequency (the
-                           frequency-domain method of Sec. 4.5).
+                           frequency-domain method of Sec. 4.6).
 * ``adjoint_direct``    -- gradient of a probe-signal misfit through the
                            theta-method (adjoint recursion, every state kept).
 * ``ldlt_inertia``      -- Sylvester inertia of a symmetric matrix (Bunch-Kaufman
@@ -98,6 +98,8 @@ def _load():
         lib.orc_modal_eigen.argtypes = [
             ctypes.POINTER(_Problem), _dp, _dp, ctypes.POINTER(ctypes.c_int)]
         lib.orc_modal_eigen.restype = ctypes.c_int
+        lib.orc_time_constants.argtypes = [ctypes.POINTER(_Problem), _dp]
+        lib.orc_time_constants.restype = ctypes.c_int
         lib.orc_adjoint_direct.argtypes = [
             _i64, _dp, _dp, _i64, _dp, _dp, ctypes.c_double, ctypes.c_double, _i64,
             _dp, _dp, _dp, _dp, _dp]
@@ -387,6 +389,20 @@ def modal_eigen(pb: Problem, want_V: bool = True):
     if rc:
         raise RuntimeError(_ERR.get(rc, str(rc)))
     return (lam, V) if want_V else lam
+
+
+def time_constants(pb: Problem):
+    """The pencil's eigenvalues as the paper writes them (Sec. 3.2, eq.
+    generalized_eigenvalues_discrete: Li v = tau Ri v), in its order
+    tau_1 >= tau_2 >= ... (Sec. 2.3), from the standard form on Ri's side:
+    Ri = H H^T, Jacobi on H^{-1} Li H^{-T}."""
+    n0 = pb.n - pb.m
+    tau = np.zeros(n0)
+    st = pb._struct()
+    rc = _load().orc_time_constants(ctypes.byref(st), _ptr(tau))
+    if rc:
+        raise RuntimeError(_ERR.get(rc, str(rc)))
+    return np.sort(tau)[::-1].copy()
 
 
 def adjoint_direct(L, R, M, P, theta: float, dt: float, T: int, i_src, obs):

@@ -11,7 +11,7 @@
  *
  * Storage: every dense matrix here is ROW-MAJOR, A[i*n + j].
  * Precision: IEEE double throughout (the paper fixes none; FP64 is the
- * paper's own setting, ScaLAPACK double routines, Sec. 4.5).
+ * paper's own setting, ScaLAPACK double routines, Sec. 4.6).
  *
  * What is computed (citations are to the paper's sections and equations):
  *   - the Galerkin circuit system  R I + L dI/dt + E^T phi = V0 + VD,
@@ -650,6 +650,41 @@ int orc_modal_eigen(const orc_problem *pb, double *lam, double *V, int *sweeps)
     int rc = modal_parts(pb, &r, lam, Vtmp, sweeps);
     if (!V)
         free(Vtmp);
+    free_reduced(&r);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The time constants of the pencil as the paper writes its eigenproblem    */
+/* (Sec. 3.2, eq. generalized_eigenvalues_discrete):  Li v = tau Ri v.  With  */
+/* Ri = H H^T, C' = H^{-1} Li H^{-T} has the eigenvalues tau (the standard   */
+/* form taken from the other side of the pencil than orc_modal_eigen).       */
+/* tau is returned ascending (n0 values).  Returns 0, 1 (bad electrodes),    */
+/* 2 (Ri not SPD), 3 (Jacobi did not converge).                              */
+/* ------------------------------------------------------------------------ */
+int orc_time_constants(const orc_problem *pb, double *tau)
+{
+    orc_reduced r;
+    if (reduce(pb, &r)) {
+        free_reduced(&r);
+        return 1;
+    }
+    const int64_t n0 = r.n0;
+    double *H = (double *)malloc(sizeof(double) * (size_t)(n0 * n0));
+    memcpy(H, r.Ri, sizeof(double) * (size_t)(n0 * n0));
+    int rc = 0;
+    if (orc_cholesky(n0, H) >= 0) {
+        rc = 2;
+    } else {
+        double *C = (double *)malloc(sizeof(double) * (size_t)(n0 * n0));
+        double *Q = (double *)malloc(sizeof(double) * (size_t)(n0 * n0));
+        orc_standard_form(n0, H, r.Li, C);
+        if (orc_jacobi(n0, C, Q, tau, 100) < 0)
+            rc = 3;
+        free(C);
+        free(Q);
+    }
+    free(H);
     free_reduced(&r);
     return rc;
 }

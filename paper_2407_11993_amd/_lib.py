@@ -24,7 +24,7 @@ MM_STEP_SCAN = 2
 
 # Every exported entry point of include/mm.h.
 SYMBOLS = ["mm_setup", "mm_decompose", "mm_decompose_projected", "mm_step_modal", "mm_step_modal_exact", "mm_step_modal_scan", "mm_modal_phasors", "mm_select_modes", "mm_step_modal_selective", "mm_step_cholesky",
-           "mm_probe", "mm_reset_state", "mm_eigenvalues", "mm_info",
+           "mm_probe", "mm_reset_state", "mm_get_state", "mm_set_state", "mm_eigenvalues", "mm_info",
            "mm_destroy", "mm_last_error", "mm_batch_create", "mm_batch_run",
            "mm_batch_info", "mm_batch_destroy", "mm_adjoint_modal", "mmk_dgemm", "mmk_dgemm_tri", "mmk_dsymm_lower", "mmk_dpotrf",
            "mmk_dtrtri", "mmk_dsy2sb", "mmk_dsb2st", "mmk_dstedc", "mmk_dsyevd"]
@@ -44,7 +44,7 @@ class Problem(ctypes.Structure):
                 ("e_rowptr", ctypes.c_void_p), ("e_col", ctypes.c_void_p),
                 ("e_val", ctypes.c_void_p), ("n_src", ctypes.c_int32),
                 ("M0", ctypes.c_void_p), ("n_probe", ctypes.c_int32),
-                ("P", ctypes.c_void_p)]
+                ("P", ctypes.c_void_p), ("L", ctypes.c_void_p), ("ldl", ctypes.c_int64)]
 
 
 def load(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -67,6 +67,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "mm_step_cholesky": [vp, dbl, dbl, i64, vp, vp, vp],
         "mm_probe": [vp, i32, i32, vp, vp],
         "mm_reset_state": [vp],
+        "mm_get_state": [vp, i32, vp],
+        "mm_set_state": [vp, i32, vp],
         "mm_eigenvalues": [vp, vp],
         "mm_info": [vp, ctypes.POINTER(ctypes.c_int64)],
         "mm_destroy": [vp],

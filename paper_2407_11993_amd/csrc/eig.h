@@ -4,6 +4,7 @@
 #pragma once
 #include "kernels.h"
 
+#include <functional>
 #include <vector>
 
 namespace mm {
@@ -52,11 +53,16 @@ void apply_q2(const Sb2stPlan& plan, const int64_t* d_offset, const double* V2,
 
 // ---- tridiagonal divide and conquer ---------------------------------------
 int64_t stedc_ws_elems(int64_t n);
-// Eigenvalues (ascending) and eigenvectors (n x n, ld ldz) of the symmetric
-// tridiagonal (d, e).  d and e are not modified.  *d_status receives a
-// non-zero code if a secular equation did not converge.
-void stedc(const double* d, const double* e, int64_t n, double* lam, double* Z,
-           int64_t ldz, double* ws, int64_t ws_elems, int64_t* d_status, hipStream_t s);
+// Eigenvalues (ascending) and eigenvectors of the symmetric tridiagonal
+// (d, e): X (n x n, ldx = n) receives Z, or (pre P) P(Z_leaves) Z_merges when
+// `pre` transforms the leaves' block-diagonal eigenvectors in place before
+// the merges are applied (the eigensolver's back-transform: X = Q1 Q2 Z).
+// U is n^2 doubles of scratch (it may not overlap X or ws; `pre` may still
+// read it, the merges write it only afterwards).  d and e are not modified.
+// *d_status receives a non-zero code if a secular equation did not converge.
+void stedc(const double* d, const double* e, int64_t n, double* lam, double* X,
+           int64_t ldx, double* U, double* ws, int64_t ws_elems, int64_t* d_status,
+           hipStream_t s, const std::function<void(double*)>& pre = {});
 // Eigenvalues and ZY = Z^T Y (n x ny) without forming Z: every node of the
 // tree keeps its eigenvectors' projections and boundary entries only.  U is
 // n^2 doubles of scratch for the merges' eigenvector blocks (it may not
@@ -79,9 +85,14 @@ struct EigWork {
   double* e = nullptr;
   double* ws = nullptr;
   int64_t ws_elems = 0;
+  // optional phase marks (the caller's progress trace): called with the name
+  // of each finished phase
+  std::function<void(const char*)> mark;
 };
 // C (symmetric, only its lower triangle read; destroyed: it keeps the stage-1
-// reflectors) -> lam, Q.
+// reflectors, then serves as the divide and conquer's scratch) -> lam, Q.
+// w.ws must hold syevd_ws_elems(n, nb) doubles.
+int64_t syevd_ws_elems(int64_t n, int nb);
 void syevd(double* C, int64_t ldc, int64_t n, double* lam, double* Q, int64_t ldq,
            const EigWork& w, const Sb2stPlan& plan, int64_t* d_status, hipStream_t s);
 // Eigenvalues and Q^T Y for a few columns Y (n x ny, ny <= sb2st_max_cols()),

@@ -8,6 +8,10 @@
 namespace mm {
 namespace {
 
+// the back-transform's block reflectors are built in batches of at most this
+// many doubles (2 GiB)
+constexpr int64_t kQ2WsCap = (int64_t)1 << 28;
+
 __global__ void extract_v_k(const double* P, int64_t ldp, int64_t m, int nb, double* V) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= m * nb) return;
@@ -115,26 +119,51 @@ void syevd_project(double* C, int64_t ldc, int64_t n, double* lam, double* Y, in
   MM_REQUIRE(ny >= 1 && ny <= sb2st_max_cols(), kInvalid,
              "syevd_project: 1..32 projected columns");
   const int nb = w.nb;
+  auto mark = [&](const char* what) { if (w.mark) w.mark(what); };
   sy2sb(C, ldc, n, nb, w.tau1, w.T1, w.ws, w.ws_elems, s);
   apply_q1t(C, ldc, n, nb, w.T1, Y, ldy, ny, w.ws, w.ws_elems, s);
+  mark("band reduction");
   const int64_t ldab = 2 * nb + 1;
   extract_band(C, ldc, n, nb, w.AB, ldab, s);
   sb2st(w.AB, ldab, plan, w.d_offset, w.V2, w.tau2, w.d, w.e, s, Y, ldy, ny);
+  mark("bulge chase");
   // C is dead from here on (its reflectors were applied to Y, its band copied)
   stedc_project(w.d, w.e, n, lam, Y, ldy, ny, ZY, ldzy, C, w.ws, w.ws_elems, d_status, s);
+  mark("divide and conquer");
+}
+
+int64_t syevd_ws_elems(int64_t n, int nb) {
+  const int64_t bt = std::max(apply_q1_ws_elems(n, nb, n),
+                              std::min(apply_q2_ws_elems(n, nb), kQ2WsCap));
+  return std::max(sy2sb_ws_elems(n, nb), stedc_ws_elems(n) + bt);
 }
 
 void syevd(double* C, int64_t ldc, int64_t n, double* lam, double* Q, int64_t ldq,
            const EigWork& w, const Sb2stPlan& plan, int64_t* d_status, hipStream_t s) {
   MM_REQUIRE(ldq == n, kInvalid, "syevd: ldq must equal n");
+  MM_REQUIRE(w.ws_elems >= syevd_ws_elems(n, w.nb), kInvalid, "syevd: workspace too small");
   const int nb = w.nb;
+  auto mark = [&](const char* what) { if (w.mark) w.mark(what); };
   sy2sb(C, ldc, n, nb, w.tau1, w.T1, w.ws, w.ws_elems, s);
+  mark("band reduction");
   const int64_t ldab = 2 * nb + 1;
   extract_band(C, ldc, n, nb, w.AB, ldab, s);
   sb2st(w.AB, ldab, plan, w.d_offset, w.V2, w.tau2, w.d, w.e, s);
-  stedc(w.d, w.e, n, lam, Q, ldq, w.ws, w.ws_elems, d_status, s);
-  apply_q2(plan, w.d_offset, w.V2, w.tau2, Q, ldq, n, w.ws, w.ws_elems, s);
-  apply_q1(C, ldc, n, nb, w.T1, Q, ldq, n, w.ws, w.ws_elems, s);
+  mark("bulge chase");
+  // the divide and conquer keeps its arrays at the start of ws; the
+  // back-transform of its leaves (Q1 Q2 Z_leaves, before any merge) works
+  // behind them.  C's reflectors are read there; afterwards its storage
+  // (ldc n >= n^2 doubles) is the merges' scratch U.
+  const int64_t n_dc = stedc_ws_elems(n);
+  double* ws_bt = w.ws + n_dc;
+  const int64_t n_bt = w.ws_elems - n_dc;
+  stedc(w.d, w.e, n, lam, Q, ldq, C, w.ws, n_dc, d_status, s, [&](double* X) {
+    apply_q2(plan, w.d_offset, w.V2, w.tau2, X, ldq, n, ws_bt, n_bt, s);
+    mark("back-transform Q2");
+    apply_q1(C, ldc, n, nb, w.T1, X, ldq, n, ws_bt, n_bt, s);
+    mark("back-transform Q1");
+  });
+  mark("divide and conquer merges");
 }
 
 }  // namespace mm

@@ -134,21 +134,29 @@ __global__ void __launch_bounds__(QT) hh_finish_k(const double* V, int64_t n, in
     }
 }
 
-__global__ void l_times_rows_k(const double* __restrict__ xyz, double h, int64_t n,
-                               const int32_t* __restrict__ idx, int ns,
+__global__ void l_times_rows_k(LSrc src, int64_t n, const int32_t* __restrict__ idx, int ns,
                                const double* __restrict__ U, int64_t ldu, int k,
                                double* __restrict__ out, int64_t ldo) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const double xi = xyz[3 * i], yi = xyz[3 * i + 1], zi = xyz[3 * i + 2];
-  const double h2 = h * h;
+  double xi = 0.0, yi = 0.0, zi = 0.0;
+  if (!src.L) {
+    xi = src.xyz[3 * i]; yi = src.xyz[3 * i + 1]; zi = src.xyz[3 * i + 2];
+  }
+  const double h2 = src.h * src.h;
   double acc[MAXM];
 #pragma unroll
   for (int c = 0; c < MAXM; ++c) acc[c] = 0.0;
   for (int q = 0; q < ns; ++q) {
     const int64_t s = idx[q];
-    const double dx = xi - xyz[3 * s], dy = yi - xyz[3 * s + 1], dz = zi - xyz[3 * s + 2];
-    const double l = h / sqrt(dx * dx + dy * dy + dz * dz + h2);
+    double l;
+    if (src.L) {  // lower triangle of the borrowed matrix (off = 0 here)
+      l = i >= s ? src.L[i + s * src.ld] : src.L[s + i * src.ld];
+    } else {
+      const double dx = xi - src.xyz[3 * s], dy = yi - src.xyz[3 * s + 1],
+                   dz = zi - src.xyz[3 * s + 2];
+      l = src.h / sqrt(dx * dx + dy * dy + dz * dz + h2);
+    }
 #pragma unroll
     for (int c = 0; c < MAXM; ++c)
       if (c < k) acc[c] += l * U[s + c * ldu];
@@ -289,11 +297,12 @@ void two_sided_y(const double* V, const double* T, int64_t n, int m, const doubl
   gemm(g4, s);
 }
 
-void l_times_rows(const double* xyz, double h, int64_t n, const int32_t* idx, int ns,
+void l_times_rows(const LSrc& src, int64_t n, const int32_t* idx, int ns,
                   const double* U, int64_t ldu, int k, double* out, int64_t ldo,
                   hipStream_t s) {
   MM_REQUIRE(k >= 1 && k <= MAXM, kInvalid, "l_times_rows: 1 <= k <= 8");
-  hipLaunchKernelGGL(l_times_rows_k, dim3(blocks(n)), dim3(256), 0, s, xyz, h, n, idx, ns, U,
+  MM_REQUIRE(src.off == 0, kInvalid, "l_times_rows: the full matrix only");
+  hipLaunchKernelGGL(l_times_rows_k, dim3(blocks(n)), dim3(256), 0, s, src, n, idx, ns, U,
                      ldu, k, out, ldo);
   MM_HIP_TRY(hipGetLastError());
 }

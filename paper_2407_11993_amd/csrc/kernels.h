@@ -44,10 +44,28 @@ struct LowRank {
   int64_t ld = 0;
   int m = 0;
 };
-// L_ij = h / sqrt(|x_i - x_j|^2 + h^2) - (U Yc^T + Yc U^T)_ij for i >= j
-// (lower triangle + diagonal), or the full matrix if `full`.
-void assemble_L(const double* xyz, double h, int64_t n, double* L, int64_t ld,
-                bool full, hipStream_t s, const LowRank& lr = LowRank{});
+// Where the inductance matrix comes from: a borrowed dense matrix (its lower
+// triangle, column-major with leading dimension ld) or, when L is null, the
+// smooth kernel h / sqrt(|x_i - x_j|^2 + h^2) of the cell centres xyz (n x 3,
+// row-major).  Logical entry (i, j) is entry (i + off, j + off): off = m
+// selects the trailing block the electrode reduction keeps.
+struct LSrc {
+  const double* xyz = nullptr;
+  double h = 0.0;
+  const double* L = nullptr;
+  int64_t ld = 0;
+  int64_t off = 0;
+};
+// out(i, j) = L(i, j) - (U Yc^T + Yc U^T)_ij for i >= j (lower triangle +
+// diagonal), or the full matrix if `full`.
+void assemble_L(const LSrc& src, int64_t n, double* out, int64_t ld, bool full,
+                hipStream_t s, const LowRank& lr = LowRank{});
+// *d_flag = 1 if one of count doubles at p (or, for the _lower form, an entry
+// of the lower triangle of the n x n matrix A) is NaN or infinite; the flag
+// is left unchanged otherwise.
+void flag_nonfinite(const double* p, int64_t count, int64_t* d_flag, hipStream_t s);
+void flag_nonfinite_lower(const double* A, int64_t lda, int64_t n, int64_t* d_flag,
+                          hipStream_t s);
 // Z(i,j) += alpha R(i,j) for the lower-triangle entries of R.
 void add_csr_lower(double* Z, int64_t ld, double alpha, const Csr& R, hipStream_t s);
 // max_j (j - min{c : R(c,j) != 0}) over the stored rows of symmetric R (an
@@ -75,8 +93,8 @@ void apply_h(const double* V, const double* T, int64_t n, int m, double* X, int6
 // Y = X T - 1/2 V (T^T V^T X T) for X = A V: then H^T A H = A - V Y^T - Y V^T.
 void two_sided_y(const double* V, const double* T, int64_t n, int m, const double* X,
                  double* Y, double* ws, int64_t ws_elems, hipStream_t s);
-// out (n x k) = L U for the inductance stand-in, U non-zero only on rows idx.
-void l_times_rows(const double* xyz, double h, int64_t n, const int32_t* idx, int ns,
+// out (n x k) = L U for the inductance matrix of src, U non-zero only on rows idx.
+void l_times_rows(const LSrc& src, int64_t n, const int32_t* idx, int ns,
                   const double* U, int64_t ldu, int k, double* out, int64_t ldo,
                   hipStream_t s);
 // out (R.rows x k) = R U (logical R, offset honoured), k <= 8.
@@ -138,6 +156,9 @@ struct CholStep {
   const double* Pt = nullptr;  // probe weights (n0 x n_probe, column-major)
   int n_probe = 0;
   double* probe_partial = nullptr;  // n_steps x trsv_parts(n0) x n_probe
+  // many probes: with n_probe = 0 and dI_out set, step k writes its
+  // increment dI to column k of dI_out (n0 x n_steps)
+  double* dI_out = nullptr;
 };
 void chol_steps(const CholStep& c, int64_t k0, int64_t n_steps, hipStream_t s);
 // Once per factorisation: with C the factor (lower, leading dimension n) and
@@ -167,6 +188,10 @@ struct ModalStep {
   bool exact = false;            // exact per-mode integration instead of theta
   double* y = nullptr;           // modal amplitudes (state)
   double* probe_partial = nullptr;  // n_steps x n_groups x n_probe
+  // many probes: with n_probe = 0 and dy_out set, the steps write the
+  // amplitude increments instead (n0 x n_steps, column k = step k), whose
+  // projection P~^T dY is then one matrix product
+  double* dy_out = nullptr;
 };
 int modal_groups(int64_t n0);
 

@@ -4,7 +4,9 @@
 #include "mm.h"
 
 #include <algorithm>
+#include <chrono>
 #include <climits>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -52,18 +54,15 @@ constexpr int kBand = 64;         // bandwidth of the first tridiagonalisation s
 constexpr int kMaxColumns = 4096;  // sources, probes
 constexpr int kMaxRunColumns = 8;  // forcing columns and probes of one stepping call
 
-// workspace of the eigensolver; the projected one never needs the full
-// divide-and-conquer buffers (4 n^2) or Q1 applied to n columns, and its
-// divide and conquer keeps its n^2 eigenvector scratch in C's storage
+// workspace of the eigensolver (both divide and conquer modes keep their n^2
+// scratch in C's storage)
 int64_t eig_ws_elems(int64_t n, int nb, bool project = false) {
   int64_t w = sy2sb_ws_elems(n, nb);
   if (project) {
     w = std::max(w, stedc_project_ws_elems(n, sb2st_max_cols()));
     w = std::max(w, apply_q1_ws_elems(n, nb, sb2st_max_cols()));
   } else {
-    w = std::max(w, stedc_ws_elems(n));
-    w = std::max(w, apply_q1_ws_elems(n, nb, n));
-    w = std::max(w, apply_q2_ws_elems(n, nb));
+    w = std::max(w, syevd_ws_elems(n, nb));
   }
   return w;
 }
@@ -75,10 +74,12 @@ struct mm_ctx {
   int64_t n = 0, m = 0, n0 = 0;
   int n_src = 0, n_probe = 0, nf = 0;
   double h = 0.0;
+  const double* Lb = nullptr;  // borrowed inductance matrix (or null: generated from xyz)
+  int64_t ldl = 0;
   int64_t r_nnz = 0, band = 0;
   Dev xyz, r_rowptr, r_col, r_val, M0, P;
   Dev status;  // [0] potrf pivot (INT64_MAX = fine), [1] eigensolver status,
-               // [2] band of R, [3] electrode rank test
+               // [2] band of R, [3] electrode rank test, [4] non-finite input
   // reduced problem: forcing columns F = [R_D | L_D | K^T M0] (n0 x nf), probe
   // weights Pt = K^T P (n0 x n_probe), direct probe term PD = P A_D (n_probe x m)
   Dev F, Pt, PD;
@@ -89,8 +90,11 @@ struct mm_ctx {
   Dev iD_modal, iD_chol;  // injected currents at each method's current step
   // modal method
   bool decomposed = false;
-  bool has_Q = false;  // the eigenvector matrix is formed (mm_decompose, not _projected)
-  Dev G, Q, lam, Wm, Pm, y;
+  bool has_V = false;  // the eigenvectors are formed (mm_decompose, not _projected)
+  // G: L_i's Cholesky factor, then its inverse (during the decomposition);
+  // Q: the eigenvectors of C; V = G^{-T} Q the pencil's eigenvectors
+  // (L_i-orthonormal), the only n0^2 buffer kept after mm_decompose
+  Dev G, Q, V, lam, Wm, Pm, y;
   // selective modal stepping: the kept modes (ascending index), compact copies
   // of their lam, forcing and probe weights (ld sel_n) and their own state
   bool selected = false;
@@ -101,6 +105,10 @@ struct mm_ctx {
   double f_theta = 0.0, f_dt = 0.0;
   Dev Z, Dinv, DinvT, panels, I, b, yv, kstep;
   bool use_graph = true;  // MM_NO_GRAPH=1 in the environment turns graphs off
+  // MM_TRACE=1: the decomposition synchronises at the end of each phase and
+  // prints the phase and its seconds to stderr (a progress trace; off by default)
+  bool trace = false;
+  std::chrono::steady_clock::time_point t_mark;
   // probe partial sums of one step call
   Dev pp;
   Dev scanws;  // chunk end values and start states of the time-parallel stepping
@@ -137,6 +145,16 @@ struct mm_ctx {
     r.idx = lr_idx.as<int32_t>(); r.Vs = lr_V.d(); r.Ys = lr_Y.d();
     return r;
   }
+  // the inductance matrix, from row and column `off` on
+  LSrc lsrc(int64_t off) const {
+    LSrc l;
+    l.xyz = Lb ? nullptr : xyz.d();
+    l.h = h;
+    l.L = Lb;
+    l.ld = ldl;
+    l.off = off;
+    return l;
+  }
   const double* T() const { return small.d(); }
   const double* RinvT() const { return small.d() + m * m; }
 };
@@ -170,14 +188,23 @@ void copy_in(Dev& dst, const void* src, size_t bytes, hipStream_t s) {
 
 void check_steps(double theta, double dt, int64_t n_steps) {
   MM_REQUIRE(theta >= 0.0 && theta <= 1.0, kInvalid, "theta must lie in [0, 1]");
-  MM_REQUIRE(dt > 0.0, kInvalid, "dt must be positive");
+  MM_REQUIRE(std::isfinite(dt) && dt > 0.0, kInvalid, "dt must be finite and positive");
   MM_REQUIRE(n_steps >= 0, kInvalid, "n_steps must be >= 0");
 }
 
-void check_run_columns(const mm_ctx* c) {
-  MM_REQUIRE(c->nf <= kMaxRunColumns && c->n_probe <= kMaxRunColumns, kInvalid,
-             "a stepping call drives at most 8 forcing columns (2(Ne-1) + n_src) and 8 probes; "
-             "use mm_batch for many sources or probes");
+void check_run_columns(const mm_ctx* c, bool many_probes = false) {
+  MM_REQUIRE(c->nf <= kMaxRunColumns, kInvalid,
+             "a stepping call drives at most 8 forcing columns (2(Ne-1) + n_src); "
+             "use mm_batch for many sources");
+  MM_REQUIRE(many_probes || c->n_probe <= kMaxRunColumns, kInvalid,
+             "this call observes at most 8 probes (mm_step_modal, mm_step_modal_exact and "
+             "mm_step_modal_selective take more)");
+}
+
+// Steps per chunk of the many-probe modal stepping: the increments of a
+// chunk (n0 x steps) take at most 2^28 doubles (2 GiB).
+int64_t dy_chunk_steps(int64_t n0) {
+  return std::max<int64_t>(8, ((int64_t)1 << 28) / std::max<int64_t>(n0, 1));
 }
 
 // Factor `A` (n x n) in place and report the first bad pivot.
@@ -264,7 +291,7 @@ void reduce_problem(mm_ctx* c, const mm_problem* pb) {
   // two-sided factors: H^T L H = L - V YL^T - YL V^T (likewise R)
   c->YL.alloc(sizeof(double) * n * m);
   c->YR.alloc(sizeof(double) * n * m);
-  l_times_rows(c->xyz.d(), c->h, n, c->idxV.as<int32_t>(), c->nsV, V, n, m, X.d(), n, s);
+  l_times_rows(c->lsrc(0), n, c->idxV.as<int32_t>(), c->nsV, V, n, m, X.d(), n, s);
   two_sided_y(V, T, n, m, X.d(), c->YL.d(), ws.d(), wse, s);
   csr_times_dense(c->Rfull(), V, n, m, X.d(), n, s);
   two_sided_y(V, T, n, m, X.d(), c->YR.d(), ws.d(), wse, s);
@@ -283,7 +310,7 @@ void reduce_problem(mm_ctx* c, const mm_problem* pb) {
   };
   csr_times_dense(c->Rfull(), U.d(), n, m, X.d(), n, s);
   project(X.d(), 0);
-  l_times_rows(c->xyz.d(), c->h, n, c->idxV.as<int32_t>(), c->nsV, U.d(), n, m, X.d(), n, s);
+  l_times_rows(c->lsrc(0), n, c->idxV.as<int32_t>(), c->nsV, U.d(), n, m, X.d(), n, s);
   project(X.d(), m);
   if (c->n_src > 0) {  // K^T M0
     MM_HIP_TRY(hipMemcpyAsync(X.p, c->M0.p, sizeof(double) * n * c->n_src,
@@ -349,9 +376,14 @@ mm_status mm_setup(const mm_problem* pb, void* stream, mm_ctx** out) {
   mm_status st = guarded(c, [&] {
     MM_REQUIRE(pb != nullptr, kInvalid, "problem is NULL");
     MM_REQUIRE(pb->n >= 1 && pb->n < ((int64_t)1 << 31), kInvalid, "n out of range");
-    MM_REQUIRE(pb->h > 0.0, kInvalid, "h must be positive");
-    MM_REQUIRE(pb->xyz && pb->r_rowptr && pb->r_col && pb->r_val, kInvalid,
-               "xyz and R are required");
+    if (pb->L) {
+      MM_REQUIRE(pb->ldl >= pb->n, kInvalid, "L: ldl must be >= n");
+    } else {
+      MM_REQUIRE(pb->xyz, kInvalid, "L or xyz is required");
+      MM_REQUIRE(std::isfinite(pb->h) && pb->h > 0.0, kInvalid, "h must be finite and positive");
+    }
+    MM_REQUIRE(pb->r_rowptr && pb->r_col && pb->r_val && pb->r_nnz >= 1, kInvalid,
+               "R is required");
     MM_REQUIRE(pb->n_probe >= 1 && pb->n_probe <= kMaxColumns && pb->P, kInvalid,
                "1..4096 probe rows are required");
     MM_REQUIRE(pb->n_src >= 0 && pb->n_src <= kMaxColumns && (pb->n_src == 0 || pb->M0),
@@ -362,6 +394,8 @@ mm_status mm_setup(const mm_problem* pb, void* stream, mm_ctx** out) {
     hipStream_t s = c->stream;
     const char* ng = std::getenv("MM_NO_GRAPH");
     c->use_graph = !(ng && ng[0] == '1');
+    const char* tr = std::getenv("MM_TRACE");
+    c->trace = tr && tr[0] == '1';
     c->n = pb->n;
     c->m = pb->n_e > 0 ? pb->n_e - 1 : 0;
     c->n0 = c->n - c->m;
@@ -370,14 +404,30 @@ mm_status mm_setup(const mm_problem* pb, void* stream, mm_ctx** out) {
     c->nf = 2 * (int)c->m + c->n_src;
     MM_REQUIRE(2 * c->m <= 8, kInvalid, "at most 5 electrodes");
     c->h = pb->h;
+    c->Lb = pb->L;
+    c->ldl = pb->ldl;
     c->r_nnz = pb->r_nnz;
-    copy_in(c->xyz, pb->xyz, sizeof(double) * 3 * c->n, s);
+    if (!c->Lb) copy_in(c->xyz, pb->xyz, sizeof(double) * 3 * c->n, s);
     copy_in(c->r_rowptr, pb->r_rowptr, sizeof(int64_t) * (c->n + 1), s);
     copy_in(c->r_col, pb->r_col, sizeof(int32_t) * std::max<int64_t>(1, c->r_nnz), s);
     copy_in(c->r_val, pb->r_val, sizeof(double) * std::max<int64_t>(1, c->r_nnz), s);
     copy_in(c->M0, pb->M0, sizeof(double) * c->n * c->n_src, s);
     copy_in(c->P, pb->P, sizeof(double) * c->n * c->n_probe, s);
-    c->status.alloc(4 * sizeof(int64_t));
+    c->status.alloc(5 * sizeof(int64_t));
+    {  // every floating-point input must be finite
+      int64_t* flag = c->status.as<int64_t>() + 4;
+      fill_i64(flag, 1, 0, s);
+      if (c->Lb) flag_nonfinite_lower(c->Lb, c->ldl, c->n, flag, s);
+      else flag_nonfinite(c->xyz.d(), 3 * c->n, flag, s);
+      flag_nonfinite(c->r_val.d(), c->r_nnz, flag, s);
+      flag_nonfinite(c->M0.d(), c->n * c->n_src, flag, s);
+      flag_nonfinite(c->P.d(), c->n * c->n_probe, flag, s);
+      if (c->m > 0 && pb->e_val && pb->e_nnz > 0) flag_nonfinite(pb->e_val, pb->e_nnz, flag, s);
+      int64_t bad = 0;
+      MM_HIP_TRY(hipMemcpyAsync(&bad, flag, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+      MM_HIP_TRY(hipStreamSynchronize(s));
+      MM_REQUIRE(bad == 0, kInvalid, "an input (L or xyz, R, E, M0 or P) holds NaN or Inf");
+    }
     csr_lower_band(c->Rfull(), c->status.as<int64_t>() + 2, s);
     MM_HIP_TRY(hipMemcpyAsync(&c->band, c->status.as<int64_t>() + 2, sizeof(int64_t),
                               hipMemcpyDeviceToHost, s));
@@ -395,6 +445,18 @@ mm_status mm_setup(const mm_problem* pb, void* stream, mm_ctx** out) {
 
 namespace {
 
+// The progress trace: with MM_TRACE=1, wait for the stream and print the
+// phase just finished with its seconds.
+void mark(mm_ctx* c, const char* what) {
+  if (!c->trace) return;
+  MM_HIP_TRY(hipStreamSynchronize(c->stream));
+  const auto now = std::chrono::steady_clock::now();
+  const double sec = std::chrono::duration<double>(now - c->t_mark).count();
+  c->t_mark = now;
+  std::fprintf(stderr, "libmm: n0 = %lld, %s done (%.2f s)\n", (long long)c->n0, what, sec);
+  std::fflush(stderr);
+}
+
 // a0-a8.  project: eigenvalues and the projected forcing and probe weights
 // only, the eigenvector matrix Q = Q1 Q2 Z never formed (Q^T Y = Z^T Q2^T Q1^T Y
 // applied to the few columns Y = G^{-1} [F, P] on the way through the band
@@ -408,14 +470,16 @@ void decompose_impl(mm_ctx* c, bool project) {
                "mm_decompose_projected: at most 32 forcing and probe columns in all "
                "(use mm_decompose)");
     c->decomposed = false;
-    c->has_Q = false;
+    c->has_V = false;
     c->selected = false;
+    c->t_mark = std::chrono::steady_clock::now();
     // Buffers in the order they are needed, released as soon as they are not
     // (at N = 98,304 one n0^2 buffer is 77 GB: at most three live at once).
     // The small buffers of the eigensolver are allocated first: an
     // allocation that has to reuse memory just freed by another one of this
     // size can take seconds.
     c->Q.release();
+    c->V.release();
     const int64_t wse = eig_ws_elems(n0, nb, project);
     Dev Cb, ws, GFP;
     ws.alloc(sizeof(double) * std::max(wse, potrf_ws_elems(n0)));
@@ -428,8 +492,10 @@ void decompose_impl(mm_ctx* c, bool project) {
     off.alloc(sizeof(int64_t) * (n0 + 1));
     dv.alloc(sizeof(double) * n0);
     ev.alloc(sizeof(double) * std::max<int64_t>(1, n0));
-    if (project) ZY.alloc(sizeof(double) * n0 * ny);
-    GFP.alloc(sizeof(double) * n0 * ny);
+    if (project) {
+      ZY.alloc(sizeof(double) * n0 * ny);
+      GFP.alloc(sizeof(double) * n0 * ny);
+    }
     c->G.alloc(sizeof(double) * n0 * n0);
     c->lam.alloc(sizeof(double) * n0);
     c->Wm.alloc(sizeof(double) * n0 * std::max(1, c->nf));
@@ -439,8 +505,9 @@ void decompose_impl(mm_ctx* c, bool project) {
     int64_t* st = c->status.as<int64_t>();
     // a0, a1: L_i (lower triangle);  a2: L_i = G G^T  (Ne = 0: L_i = L)
     const int m = (int)c->m;
-    assemble_L(c->xyz.d() + 3 * m, c->h, n0, G, n0, false, s, c->lr(0.0));
+    assemble_L(c->lsrc(m), n0, G, n0, false, s, c->lr(0.0));
     factor_checked(G, n0, st, ws, s, "L");
+    mark(c, "Cholesky factorisation of L_i");
     // a3: C = G^{-1} R G^{-T}:  G <- G^{-1};  W = G^{-1} R (in Q);  C = G^{-1} W^T
     {
       Dev tws;
@@ -491,10 +558,11 @@ void decompose_impl(mm_ctx* c, bool project) {
       gemm(g, s);
       MM_HIP_TRY(hipStreamSynchronize(s));  // ABA is released here
     }
+    mark(c, "standard form C");
     // G^{-1} applied to the forcing columns and the probe weights, side by side
-    double* GF = GFP.d();
-    double* GP = GFP.d() + (int64_t)c->nf * n0;
-    if (c->nf > 0) {
+    double* GF = project ? GFP.d() : nullptr;
+    double* GP = project ? GFP.d() + (int64_t)c->nf * n0 : nullptr;
+    if (project && c->nf > 0) {
       Gemm g;
       g.m = n0; g.n = c->nf; g.k = n0;
       g.A = G; g.lda = n0; g.a_lower = true;
@@ -502,20 +570,24 @@ void decompose_impl(mm_ctx* c, bool project) {
       g.C = GF; g.ldc = n0;
       gemm(g, s);
     }
-    {
+    if (project) {
       Gemm g;
       g.m = n0; g.n = c->n_probe; g.k = n0;
       g.A = G; g.lda = n0; g.a_lower = true;
       g.B = c->Pt.d(); g.ldb = n0;
       g.C = GP; g.ldc = n0;
       gemm(g, s);
-    }
-    if (project) {
       // neither G^{-1} nor W is needed again without the eigenvector matrix
       MM_HIP_TRY(hipStreamSynchronize(s));
       c->Q.release();
       c->G.release();
       Q = nullptr;
+    } else {
+      // W is dead (Q's storage receives the eigenvectors); G^{-1} is formed
+      // again after the eigensolver rather than held through it, so that at
+      // most three n0^2 buffers are live at any time
+      MM_HIP_TRY(hipStreamSynchronize(s));
+      c->G.release();
     }
     // a4-a7: C = Q Lam Q^T
     if (!project) {  // the bulge-chase reflectors, kept for the back-transform
@@ -531,6 +603,7 @@ void decompose_impl(mm_ctx* c, bool project) {
     w.tau2 = project ? nullptr : tau2.d();
     w.d_offset = off.as<int64_t>(); w.d = dv.d(); w.e = ev.d();
     w.ws = ws.d(); w.ws_elems = wse;
+    w.mark = [c](const char* what) { mark(c, what); };
     fill_i64(st + 1, 1, 0, s);
     if (project) {
       // a4-a8 without Q: [W, Pt] = Z^T Q2^T Q1^T G^{-1} [F, P]
@@ -539,21 +612,51 @@ void decompose_impl(mm_ctx* c, bool project) {
       copy_matrix(ZY.d() + (int64_t)c->nf * n0, n0, c->Pm.d(), n0, n0, c->n_probe, s);
       MM_HIP_TRY(hipStreamSynchronize(s));  // ZY is released here
     } else {
+      // a4-a7: Q = Q1 Q2 Z in Q's storage (C's storage is the merges' scratch)
       syevd(C, ldC, n0, c->lam.d(), Q, n0, w, plan, st + 1, s);
-      // a8: modal weights  W = Q^T G^{-1} F,  Pt = Q^T G^{-1} P
+      MM_HIP_TRY(hipStreamSynchronize(s));
+      V2.release();
+      tau2.release();
+      // G^{-1} again, in C's storage (L_i's Cholesky factor and its inverse)
+      double* Gi = C;
+      assemble_L(c->lsrc(m), n0, Gi, n0, false, s, c->lr(0.0));
+      factor_checked(Gi, n0, st, ws, s, "L");
+      {
+        Dev tws;
+        tws.alloc(sizeof(double) * trtri_ws_elems(n0));
+        trtri_lower(Gi, n0, n0, tws.d(), trtri_ws_elems(n0), s);
+        MM_HIP_TRY(hipStreamSynchronize(s));
+      }
+      mark(c, "inverse factor G^{-1} again");
+      // V = G^{-T} Q: the pencil's eigenvectors, V^T L_i V = I, V^T R_i V = Lam
+      c->V.alloc(sizeof(double) * n0 * n0);
+      {
+        Gemm g;
+        g.m = n0; g.n = n0; g.k = n0;
+        g.A = Gi; g.lda = n0; g.ta = true; g.a_upper = true;
+        g.B = Q; g.ldb = n0;
+        g.C = c->V.d(); g.ldc = n0;
+        gemm(g, s);
+      }
+      mark(c, "eigenvectors V = G^{-T} Q");
+      MM_HIP_TRY(hipStreamSynchronize(s));
+      Cb.release();
+      c->Q.release();
+      Q = nullptr;
+      // a8: modal weights  W = V^T F,  Pt = V^T P
       if (c->nf > 0) {
         Gemm g;
         g.m = n0; g.n = c->nf; g.k = n0;
-        g.A = Q; g.lda = n0; g.ta = true;
-        g.B = GF; g.ldb = n0;
+        g.A = c->V.d(); g.lda = n0; g.ta = true;
+        g.B = c->F.d(); g.ldb = n0;
         g.C = c->Wm.d(); g.ldc = n0;
         gemm(g, s);
       }
       {
         Gemm g;
         g.m = n0; g.n = c->n_probe; g.k = n0;
-        g.A = Q; g.lda = n0; g.ta = true;
-        g.B = GP; g.ldb = n0;
+        g.A = c->V.d(); g.lda = n0; g.ta = true;
+        g.B = c->Pt.d(); g.ldb = n0;
         g.C = c->Pm.d(); g.ldc = n0;
         gemm(g, s);
       }
@@ -564,9 +667,8 @@ void decompose_impl(mm_ctx* c, bool project) {
     MM_HIP_TRY(hipStreamSynchronize(s));
     MM_HIP_TRY(hipGetLastError());
     if (est != 0) throw Error{kNoConverge, "a secular equation did not converge"};
-    if (project) c->Q.release();  // it held the tridiagonal eigenvectors only
     c->decomposed = true;
-    c->has_Q = !project;
+    c->has_V = !project;
 }
 
 }  // namespace
@@ -590,15 +692,62 @@ void step_modal_impl(mm_ctx* c, double theta, double dt, bool exact, int64_t n_s
     MM_REQUIRE(!selective || c->selected, kState,
                "mm_step_modal_selective before mm_select_modes");
     check_steps(theta, dt, n_steps);
-    check_run_columns(c);
+    const bool many = c->n_probe > kMaxRunColumns;
+    MM_REQUIRE(!(many && scan), kInvalid,
+               "the time-parallel stepping observes at most 8 probes");
+    check_run_columns(c, true);
     MM_REQUIRE(c->n_src == 0 || i_src, kInvalid, "i_src is required");
     MM_REQUIRE(c->m == 0 || i_D, kInvalid, "i_D is required");
     MM_REQUIRE(signal || n_steps == 0, kInvalid, "signal is required");
     if (n_steps == 0) return;
     hipStream_t s = c->stream;
     const int64_t nm = selective ? c->sel_n : c->n0;
+    if (many) {
+      // a10 for many probes: the steps of a chunk write their amplitude
+      // increments dY (nm x L), and the chunk's signals are one product
+      // P~^T dY (n_probe x L, i.e. L rows of the row-major signal)
+      const int64_t L = std::min(n_steps, dy_chunk_steps(nm));
+      c->pp.alloc(sizeof(double) * L * c->n_probe);
+      c->tmp.alloc(sizeof(double) * std::max<int64_t>(1, nm) * L);
+      const double* Pm = selective ? c->sel_P.d() : c->Pm.d();
+      for (int64_t k0 = 0; k0 < n_steps; k0 += L) {
+        const int64_t kl = std::min(L, n_steps - k0);
+        ModalStep ms;
+        ms.n0 = nm;
+        ms.lam = selective ? c->sel_lam.d() : c->lam.d();
+        ms.W = selective ? c->sel_W.d() : c->Wm.d();
+        ms.f.nf = c->nf; ms.f.m = (int)c->m; ms.f.n_src = c->n_src;
+        ms.f.i_src = i_src ? i_src + k0 * c->n_src : nullptr;
+        ms.f.i_D = i_D ? i_D + k0 * c->m : nullptr;
+        ms.n_probe = 0;
+        ms.theta = theta; ms.dt = dt;
+        ms.exact = exact;
+        ms.y = selective ? c->sel_y.d() : c->y.d();
+        ms.dy_out = c->tmp.d();
+        if (nm > 0) {
+          modal_steps(ms, 0, kl, s);
+          Gemm g;
+          g.m = c->n_probe; g.n = kl; g.k = nm;
+          g.A = Pm; g.lda = nm; g.ta = true;
+          g.B = c->tmp.d(); g.ldb = nm;
+          g.C = c->pp.d(); g.ldc = c->n_probe;
+          gemm(g, s);
+        } else {
+          fill(c->pp.d(), kl * c->n_probe, 0.0, s);
+        }
+        probe_finish(c->pp.d(), kl, 1, c->n_probe, c->m ? c->PD.d() : nullptr, (int)c->m,
+                     i_D ? i_D + k0 * c->m : nullptr, 0, dt, signal + k0 * c->n_probe, s);
+      }
+      MM_HIP_TRY(hipStreamSynchronize(s));  // the chunk buffers are released here
+      c->tmp.release();
+      if (c->m && !selective)
+        MM_HIP_TRY(hipMemcpyAsync(c->iD_modal.p, i_D + n_steps * c->m, sizeof(double) * c->m,
+                                  hipMemcpyDeviceToDevice, s));
+      return;
+    }
     const int G = modal_groups(nm);
     c->pp.alloc(sizeof(double) * n_steps * G * c->n_probe);
+    double* partial = c->pp.d();
     ModalStep ms;
     ms.n0 = nm;
     ms.lam = selective ? c->sel_lam.d() : c->lam.d();
@@ -610,7 +759,7 @@ void step_modal_impl(mm_ctx* c, double theta, double dt, bool exact, int64_t n_s
     ms.theta = theta; ms.dt = dt;
     ms.exact = exact;
     ms.y = selective ? c->sel_y.d() : c->y.d();
-    ms.probe_partial = c->pp.d();
+    ms.probe_partial = partial;
     if (scan && nm > 0) {
       const int64_t L = scan_chunk(nm, n_steps);
       c->scanws.alloc(sizeof(double) * 2 * ceil_div(n_steps, L) * nm);
@@ -618,7 +767,7 @@ void step_modal_impl(mm_ctx* c, double theta, double dt, bool exact, int64_t n_s
     } else {
       modal_steps(ms, 0, n_steps, s);
     }
-    probe_finish(c->pp.d(), n_steps, G, c->n_probe, c->m ? c->PD.d() : nullptr, (int)c->m,
+    probe_finish(partial, n_steps, G, c->n_probe, c->m ? c->PD.d() : nullptr, (int)c->m,
                  i_D, 0, dt, signal, s);
     // the injected currents belong to the full modal state (current reconstruction)
     if (c->m && !selective)
@@ -726,7 +875,7 @@ mm_status mm_step_cholesky(mm_ctx* c, double theta, double dt, int64_t n_steps,
   if (!c) return MM_E_INVALID;
   return guarded(c, [&] {
     check_steps(theta, dt, n_steps);
-    check_run_columns(c);
+    check_run_columns(c, true);
     MM_REQUIRE(c->n_src == 0 || i_src, kInvalid, "i_src is required");
     MM_REQUIRE(c->m == 0 || i_D, kInvalid, "i_D is required");
     MM_REQUIRE(signal || n_steps == 0, kInvalid, "signal is required");
@@ -749,7 +898,7 @@ mm_status mm_step_cholesky(mm_ctx* c, double theta, double dt, int64_t n_steps,
       // b0: Z = Li + theta dt Ri = C C^T   (Ne = 0: Li = L, Ri = R)
       double* Z = c->Z.d();
       const int m = (int)c->m;
-      assemble_L(c->xyz.d() + 3 * m, c->h, n0, Z, n0, false, s, c->lr(theta * dt));
+      assemble_L(c->lsrc(m), n0, Z, n0, false, s, c->lr(theta * dt));
       add_csr_lower(Z, n0, theta * dt, c->R(), s);
       factor_checked(Z, n0, c->status.as<int64_t>(), c->tmp, s, "Li + theta dt Ri");
       c->tmp.alloc(sizeof(double) * trtri_ws_elems(B));
@@ -768,7 +917,7 @@ mm_status mm_step_cholesky(mm_ctx* c, double theta, double dt, int64_t n_steps,
     }
     if (n_steps == 0) return;
     const int64_t parts = trsv_parts(n0);
-    c->pp.alloc(sizeof(double) * n_steps * parts * c->n_probe);
+    if (c->n_probe <= kMaxRunColumns) c->pp.alloc(sizeof(double) * n_steps * parts * c->n_probe);
     CholStep cs;
     cs.n0 = n0;
     {
@@ -789,9 +938,36 @@ mm_status mm_step_cholesky(mm_ctx* c, double theta, double dt, int64_t n_steps,
     cs.I = c->I.d(); cs.b = c->b.d(); cs.y = c->yv.d();
     cs.Pt = c->Pt.d(); cs.n_probe = c->n_probe;
     cs.probe_partial = c->pp.d();
-    chol_steps(cs, 0, n_steps, s);
-    probe_finish(c->pp.d(), n_steps, parts, c->n_probe, c->m ? c->PD.d() : nullptr, (int)c->m,
-                 i_D, 0, dt, signal, s);
+    if (c->n_probe > kMaxRunColumns) {
+      // many probes (b4): the steps of a chunk write their increments dI
+      // (n0 x L), and the chunk's signals are one product P^T dI
+      const int64_t L = std::min(n_steps, dy_chunk_steps(n0));
+      c->pp.alloc(sizeof(double) * L * c->n_probe);
+      c->tmp.alloc(sizeof(double) * n0 * L);
+      cs.n_probe = 0;
+      cs.probe_partial = nullptr;
+      cs.dI_out = c->tmp.d();
+      for (int64_t k0 = 0; k0 < n_steps; k0 += L) {
+        const int64_t kl = std::min(L, n_steps - k0);
+        cs.f.i_src = i_src ? i_src + k0 * c->n_src : nullptr;
+        cs.f.i_D = i_D ? i_D + k0 * c->m : nullptr;
+        chol_steps(cs, 0, kl, s);
+        Gemm g;
+        g.m = c->n_probe; g.n = kl; g.k = n0;
+        g.A = c->Pt.d(); g.lda = n0; g.ta = true;
+        g.B = c->tmp.d(); g.ldb = n0;
+        g.C = c->pp.d(); g.ldc = c->n_probe;
+        gemm(g, s);
+        probe_finish(c->pp.d(), kl, 1, c->n_probe, c->m ? c->PD.d() : nullptr, (int)c->m,
+                     i_D ? i_D + k0 * c->m : nullptr, 0, dt, signal + k0 * c->n_probe, s);
+      }
+      MM_HIP_TRY(hipStreamSynchronize(s));  // the chunk buffer is released here
+      c->tmp.release();
+    } else {
+      chol_steps(cs, 0, n_steps, s);
+      probe_finish(c->pp.d(), n_steps, parts, c->n_probe, c->m ? c->PD.d() : nullptr,
+                   (int)c->m, i_D, 0, dt, signal, s);
+    }
     if (c->m)
       MM_HIP_TRY(hipMemcpyAsync(c->iD_chol.p, i_D + n_steps * c->m, sizeof(double) * c->m,
                                 hipMemcpyDeviceToDevice, s));
@@ -808,28 +984,21 @@ mm_status mm_probe(mm_ctx* c, int32_t which, int32_t n_rows, const double* rows,
     const int64_t n = c->n, n0 = c->n0;
     const int m = (int)c->m;
     Dev buf;
-    buf.alloc(sizeof(double) * (2 * n0 + n));
+    buf.alloc(sizeof(double) * (n0 + n));
     double* Ii = buf.d();           // reduced current (n0)
     double* Ifull = buf.d() + n0;   // full current (n)
     if (which == MM_MODAL) {
       MM_REQUIRE(c->decomposed, kState, "mm_probe(MM_MODAL) before mm_decompose");
-      MM_REQUIRE(c->has_Q, kState,
+      MM_REQUIRE(c->has_V, kState,
                  "mm_probe(MM_MODAL) needs the eigenvectors: use mm_decompose, not "
                  "mm_decompose_projected");
-      double* t = buf.d() + n0 + n;
-      // a11: Ii = G^{-T} (Q y)
-      Gemm g1;
-      g1.m = n0; g1.n = 1; g1.k = n0;
-      g1.A = c->Q.d(); g1.lda = n0;
-      g1.B = c->y.d(); g1.ldb = n0;
-      g1.C = t; g1.ldc = n0;
-      gemm(g1, s);
-      Gemm g2;
-      g2.m = n0; g2.n = 1; g2.k = n0;
-      g2.A = c->G.d(); g2.lda = n0; g2.ta = true; g2.a_upper = true;
-      g2.B = t; g2.ldb = n0;
-      g2.C = Ii; g2.ldc = n0;
-      gemm(g2, s);
+      // a11: Ii = V y  (V = G^{-T} Q)
+      Gemm g;
+      g.m = n0; g.n = 1; g.k = n0;
+      g.A = c->V.d(); g.lda = n0;
+      g.B = c->y.d(); g.ldb = n0;
+      g.C = Ii; g.ldc = n0;
+      gemm(g, s);
     } else {
       MM_REQUIRE(c->I.p != nullptr, kState, "mm_probe(MM_CHOLESKY) before any Cholesky step");
       MM_HIP_TRY(hipMemcpyAsync(Ii, c->I.p, sizeof(double) * n0, hipMemcpyDeviceToDevice, s));
@@ -870,6 +1039,52 @@ mm_status mm_reset_state(mm_ctx* c) {
       fill(c->iD_modal.d(), c->m, 0.0, c->stream);
       fill(c->iD_chol.d(), c->m, 0.0, c->stream);
     }
+  });
+}
+
+namespace {
+
+// The state vector of one method: its reduced unknowns (n0) and the injected
+// currents of its last step (m).
+double* state_of(mm_ctx* c, int32_t which, bool create) {
+  MM_REQUIRE(which == MM_MODAL || which == MM_CHOLESKY, kInvalid, "which");
+  if (which == MM_MODAL) {
+    MM_REQUIRE(c->decomposed, kState, "the modal state exists after mm_decompose");
+    return c->y.d();
+  }
+  if (!c->I.p) {
+    MM_REQUIRE(create, kState, "no Cholesky step has run");
+    c->I.alloc(sizeof(double) * c->n0);
+    fill(c->I.d(), c->n0, 0.0, c->stream);
+  }
+  return c->I.d();
+}
+
+}  // namespace
+
+mm_status mm_get_state(mm_ctx* c, int32_t which, double* out) {
+  if (!c) return MM_E_INVALID;
+  return guarded(c, [&] {
+    MM_REQUIRE(out != nullptr, kInvalid, "out is NULL");
+    const double* st = state_of(c, which, false);
+    hipStream_t s = c->stream;
+    MM_HIP_TRY(hipMemcpyAsync(out, st, sizeof(double) * c->n0, hipMemcpyDeviceToDevice, s));
+    if (c->m)
+      MM_HIP_TRY(hipMemcpyAsync(out + c->n0, (which == MM_MODAL ? c->iD_modal : c->iD_chol).p,
+                                sizeof(double) * c->m, hipMemcpyDeviceToDevice, s));
+  });
+}
+
+mm_status mm_set_state(mm_ctx* c, int32_t which, const double* in) {
+  if (!c) return MM_E_INVALID;
+  return guarded(c, [&] {
+    MM_REQUIRE(in != nullptr, kInvalid, "in is NULL");
+    double* st = state_of(c, which, true);
+    hipStream_t s = c->stream;
+    MM_HIP_TRY(hipMemcpyAsync(st, in, sizeof(double) * c->n0, hipMemcpyDeviceToDevice, s));
+    if (c->m)
+      MM_HIP_TRY(hipMemcpyAsync((which == MM_MODAL ? c->iD_modal : c->iD_chol).p, in + c->n0,
+                                sizeof(double) * c->m, hipMemcpyDeviceToDevice, s));
   });
 }
 
@@ -1073,7 +1288,7 @@ mm_status mm_adjoint_modal(mm_ctx* c, double theta, double dt, int64_t n_steps,
   if (!c) return MM_E_INVALID;
   return guarded(c, [&] {
     MM_REQUIRE(c->decomposed, kState, "mm_adjoint_modal before mm_decompose");
-    MM_REQUIRE(c->has_Q, kState,
+    MM_REQUIRE(c->has_V, kState,
                "mm_adjoint_modal needs the eigenvectors: use mm_decompose, not "
                "mm_decompose_projected");
     check_steps(theta, dt, n_steps);
@@ -1137,22 +1352,15 @@ mm_status mm_adjoint_modal(mm_ctx* c, double theta, double dt, int64_t n_steps,
     MM_HIP_TRY(hipStreamSynchronize(s));  // Zb, Lb released below
     Zb.release();
     Lb.release();
-    // dJ/dR = -V S V^T at the stored entries, V = G^{-T} Q
-    Dev V, T1;
-    V.alloc(sizeof(double) * n0 * n0);
+    // dJ/dR = -V S V^T at the stored entries (V = G^{-T} Q, the pencil's
+    // eigenvectors)
+    Dev T1;
     T1.alloc(sizeof(double) * n0 * n0);
+    const double* V = c->V.d();
     {
       Gemm g;
       g.m = n0; g.n = n0; g.k = n0;
-      g.A = c->G.d(); g.lda = n0; g.ta = true; g.a_upper = true;
-      g.B = c->Q.d(); g.ldb = n0;
-      g.C = V.d(); g.ldc = n0;
-      gemm(g, s);
-    }
-    {
-      Gemm g;
-      g.m = n0; g.n = n0; g.k = n0;
-      g.A = V.d(); g.lda = n0;
+      g.A = V; g.lda = n0;
       g.B = S.d(); g.ldb = n0;
       g.C = T1.d(); g.ldc = n0;
       gemm(g, s);
@@ -1161,7 +1369,7 @@ mm_status mm_adjoint_modal(mm_ctx* c, double theta, double dt, int64_t n_steps,
       Gemm g;  // Phi = T1 V^T, into S's storage
       g.m = n0; g.n = n0; g.k = n0;
       g.A = T1.d(); g.lda = n0;
-      g.B = V.d(); g.ldb = n0; g.tb = true;
+      g.B = V; g.ldb = n0; g.tb = true;
       g.C = S.d(); g.ldc = n0;
       gemm(g, s);
     }
@@ -1316,11 +1524,12 @@ mm_status mmk_dstedc(int64_t n, const double* d, const double* e, double* w, dou
   return guarded(nullptr, [&] {
     MM_REQUIRE(n >= 1, kInvalid, "n");
     hipStream_t s = (hipStream_t)stream;
-    Dev ws, st;
+    Dev ws, U, st;
     ws.alloc(sizeof(double) * stedc_ws_elems(n));
+    U.alloc(sizeof(double) * n * n);
     st.alloc(sizeof(int64_t));
     fill_i64(st.as<int64_t>(), 1, 0, s);
-    stedc(d, e, n, w, Z, n, ws.d(), stedc_ws_elems(n), st.as<int64_t>(), s);
+    stedc(d, e, n, w, Z, n, U.d(), ws.d(), stedc_ws_elems(n), st.as<int64_t>(), s);
     int64_t est = 0;
     MM_HIP_TRY(hipMemcpyAsync(&est, st.p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     MM_HIP_TRY(hipStreamSynchronize(s));

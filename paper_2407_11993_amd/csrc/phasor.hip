@@ -1,5 +1,5 @@
 // Steady-state probe phasors by the modal decomposition (Sec. 3.2, eq.
-// modal_decomposition_discrete; the frequency-domain comparison of Sec. 4.5).
+// modal_decomposition_discrete; the frequency-domain comparison of Sec. 4.6).
 // With sources i(t) = Re{A exp(j w t)} every decoupled mode obeys
 //   (lam_n + j w) y_n = sum_j W(n, j) u_j(w),
 // where the forcing columns keep the time-domain encoding with d/dt -> j w:

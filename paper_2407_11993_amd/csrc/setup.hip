@@ -6,14 +6,28 @@ namespace mm {
 namespace {
 
 // One thread per element of a column segment; consecutive threads walk
-// consecutive rows, so the column-major stores are contiguous.  The optional
-// symmetric low-rank term (the electrode reduction's two-sided Householder
-// update) is subtracted on the fly.
-__global__ void assemble_L_k(const double* __restrict__ xyz, double h, int64_t n,
-                             double* __restrict__ L, int64_t ld, int full, LowRank lr) {
+// consecutive rows, so the column-major stores (and, from a borrowed matrix,
+// the loads) are contiguous.  The optional symmetric low-rank term (the
+// electrode reduction's two-sided Householder update) is subtracted on the fly.
+__device__ __forceinline__ double l_entry(const LSrc& src, int64_t i, int64_t j, double xj,
+                                          double yj, double zj) {
+  if (src.L) {  // lower triangle of the borrowed matrix
+    const int64_t r = i >= j ? i : j, c = i >= j ? j : i;
+    return src.L[(r + src.off) + (c + src.off) * src.ld];
+  }
+  const double* x = src.xyz + 3 * (i + src.off);
+  const double dx = x[0] - xj, dy = x[1] - yj, dz = x[2] - zj;
+  return src.h / sqrt(dx * dx + dy * dy + dz * dz + src.h * src.h);
+}
+
+__global__ void assemble_L_k(LSrc src, int64_t n, double* __restrict__ L, int64_t ld, int full,
+                             LowRank lr) {
   const int64_t j = blockIdx.x;
-  const double xj = xyz[3 * j], yj = xyz[3 * j + 1], zj = xyz[3 * j + 2];
-  const double h2 = h * h;
+  double xj = 0.0, yj = 0.0, zj = 0.0;
+  if (!src.L) {
+    const double* x = src.xyz + 3 * (j + src.off);
+    xj = x[0]; yj = x[1]; zj = x[2];
+  }
   double uj[8], yj_[8];
   for (int a = 0; a < lr.m; ++a) {
     uj[a] = lr.U[j + a * lr.ld];
@@ -21,8 +35,7 @@ __global__ void assemble_L_k(const double* __restrict__ xyz, double h, int64_t n
   }
   const int64_t i_begin = full ? 0 : j;
   for (int64_t i = i_begin + threadIdx.x; i < n; i += blockDim.x) {
-    const double dx = xyz[3 * i] - xj, dy = xyz[3 * i + 1] - yj, dz = xyz[3 * i + 2] - zj;
-    double v = h / sqrt(dx * dx + dy * dy + dz * dz + h2);
+    double v = l_entry(src, i, j, xj, yj, zj);
     for (int a = 0; a < lr.m; ++a) {
       const double ui = lr.U[i + a * lr.ld];
       const double yi = lr.Y1[i + a * lr.ld] + (lr.Y2 ? lr.w2 * lr.Y2[i + a * lr.ld] : 0.0);
@@ -30,6 +43,26 @@ __global__ void assemble_L_k(const double* __restrict__ xyz, double h, int64_t n
     }
     L[i + j * ld] = v;
   }
+}
+
+// Grid-stride scan; any non-finite value sets the flag (a plain store of 1:
+// every writer writes the same value).
+__global__ void flag_nonfinite_k(const double* __restrict__ p, int64_t count,
+                                 int64_t* __restrict__ flag) {
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    bad |= !isfinite(p[i]);
+  if (bad) *flag = 1;
+}
+
+// One workgroup per column j, rows j..n-1.
+__global__ void flag_nonfinite_lower_k(const double* __restrict__ A, int64_t lda, int64_t n,
+                                       int64_t* __restrict__ flag) {
+  bool bad = false;
+  for (int64_t j = blockIdx.x; j < n; j += gridDim.x)
+    for (int64_t i = j + threadIdx.x; i < n; i += blockDim.x) bad |= !isfinite(A[i + j * lda]);
+  if (bad) *flag = 1;
 }
 
 __global__ void add_csr_lower_k(double* Z, int64_t ld, double alpha, Csr R) {
@@ -104,14 +137,29 @@ unsigned grid1(int64_t count, int per = 256) {
 
 }  // namespace
 
-void assemble_L(const double* xyz, double h, int64_t n, double* L, int64_t ld,
-                bool full, hipStream_t s, const LowRank& lr) {
+void assemble_L(const LSrc& src, int64_t n, double* L, int64_t ld, bool full, hipStream_t s,
+                const LowRank& lr) {
   if (n <= 0) return;
   MM_REQUIRE(n < (int64_t)1 << 31, kInvalid, "assemble_L: n too large");
+  MM_REQUIRE(src.L || (src.xyz && src.h > 0.0), kInvalid, "assemble_L: no inductance source");
   MM_REQUIRE(lr.m >= 0 && lr.m <= 8 && (lr.m == 0 || (lr.U && lr.Y1)), kInvalid,
              "assemble_L: bad low-rank term");
-  hipLaunchKernelGGL(assemble_L_k, dim3((unsigned)n), dim3(256), 0, s, xyz, h, n, L, ld,
-                     (int)full, lr);
+  hipLaunchKernelGGL(assemble_L_k, dim3((unsigned)n), dim3(256), 0, s, src, n, L, ld, (int)full,
+                     lr);
+  MM_HIP_TRY(hipGetLastError());
+}
+
+void flag_nonfinite(const double* p, int64_t count, int64_t* d_flag, hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(flag_nonfinite_k, dim3(grid1(count)), dim3(256), 0, s, p, count, d_flag);
+  MM_HIP_TRY(hipGetLastError());
+}
+
+void flag_nonfinite_lower(const double* A, int64_t lda, int64_t n, int64_t* d_flag,
+                          hipStream_t s) {
+  if (n <= 0) return;
+  const unsigned g = (unsigned)std::min<int64_t>(n, 65536);
+  hipLaunchKernelGGL(flag_nonfinite_lower_k, dim3(g), dim3(256), 0, s, A, lda, n, d_flag);
   MM_HIP_TRY(hipGetLastError());
 }
 

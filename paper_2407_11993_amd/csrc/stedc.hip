@@ -17,14 +17,25 @@
 //   U(i,j) = zhat_i / (d_i - lam_j) normalised;  Z_new = Z_kept U (matrix
 //   cores);  and the merged spectrum is sorted into place.
 //
-// Projected mode (stedc_project): only Z^T Y for a few columns Y is wanted.
-// Every node keeps, row q for its q-th eigenvector, the projections
-// Z_node^T Y_node and two boundary columns Z_node^T e_first, Z_node^T e_last
-// (its eigenvectors' first and last entries, which the parent's z needs).
-// A merge applies its rotations to rows, U^T to the kept rows, copies the
-// deflated ones and sorts rows into place; nothing of size n^2 but U is kept.
+// Every node keeps, row q for its q-th eigenvector, two boundary columns
+// Z_node^T e_first, Z_node^T e_last (its eigenvectors' first and last
+// entries, which the parent's z needs) and, in projected mode
+// (stedc_project), the projections Z_node^T Y_node for a few columns Y.  A
+// merge applies its rotations to rows, U^T to the kept rows, copies the
+// deflated ones and sorts rows into place.
+//
+// Eigenvector mode (stedc) never stores the tree's eigenvectors Z.  Z is the
+// product Z_leaves M_{D-1} ... M_0 of the leaves' block-diagonal eigenvectors
+// and one block-diagonal factor per level (a merge's rotations, its U on the
+// kept columns and the sort), so X <- X Z is taken from the left: X receives
+// Z_leaves, a caller hook may transform it (the eigensolver applies Q1 Q2
+// there, so that X ends as Q1 Q2 Z), and every level's merges are applied to
+// X's columns in chunks of rows (gather the node's columns in merge order,
+// one grouped product with U, scatter them to their sorted places).  Besides
+// X this needs U (n^2, the caller's scratch) and two row chunks.
 #include "eig.h"
 
+#include <functional>
 #include <vector>
 
 namespace mm {
@@ -151,8 +162,8 @@ __global__ void __launch_bounds__(64) leaf_jacobi(const double* dw, const double
       }
       PY[(lo + rank[j]) + (int64_t)c * ldpy] = acc;
     }
-    return;
   }
+  if (!Z) return;
   for (int q = t; q < m * m; q += 64) {
     const int i = q % m, j = q / m;
     Z[(lo + i) + (lo + rank[j]) * ldz] = V[i][j];
@@ -177,6 +188,8 @@ struct MergeBufs {
   double* vals; int64_t* src;  // final values and their source (>=0 kept index, <0 -(col+1))
   int64_t* dfl;    // sorted positions of the deflated entries, in deflation order
   double* dk; double* zk;  // kept d and z, compact
+  int64_t* colmap; // merge-order entry p = lo + q: the child column it comes from
+  int64_t* dst;    // merge-order entry p: its sorted place (global index)
 };
 
 __global__ void __launch_bounds__(NT) merge_prepare(const Merge* merges, const double* e,
@@ -279,22 +292,6 @@ __global__ void __launch_bounds__(NT) merge_prepare(const Merge* merges, const d
   b.meta[2 * blockIdx.x] = k;
   b.meta[2 * blockIdx.x + 1] = nrot;
   b.rho[blockIdx.x] = rho;
-}
-
-// merge step 2: Givens rotations on the columns of Z (rows of the merge)
-__global__ void merge_rotate(const Merge* merges, MergeBufs b, double* Z, int64_t ldz) {
-  const Merge mg = merges[blockIdx.y];
-  const int64_t nrot = b.meta[2 * blockIdx.y + 1];
-  if (nrot == 0) return;
-  const int64_t r = mg.lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= mg.hi) return;
-  for (int64_t q = 0; q < nrot; ++q) {
-    const int64_t ca = b.rot_a[mg.lo + q], cb = b.rot_b[mg.lo + q];
-    const double c = b.rot_c[mg.lo + q], s = b.rot_s[mg.lo + q];
-    const double za = Z[r + ca * ldz], zb = Z[r + cb * ldz];
-    Z[r + ca * ldz] = c * za - s * zb;
-    Z[r + cb * ldz] = s * za + c * zb;
-  }
 }
 
 // merge step 3: one secular root per thread.  Kept entries j of merge g are
@@ -447,36 +444,6 @@ __global__ void __launch_bounds__(NT) merge_form_u(const Merge* merges, MergeBuf
   for (int64_t i = t; i < k; i += NT) Uj[i] *= inv;
 }
 
-// merge step 6: gather the kept columns (rows lo..hi) into G (nm x k, ld nm)
-__global__ void merge_gather(const Merge* merges, MergeBufs b, const double* Z, int64_t ldz,
-                             double* Gbuf, int64_t n) {
-  const Merge mg = merges[blockIdx.y];
-  const int64_t lo = mg.lo, nm = mg.hi - mg.lo;
-  const int64_t k = b.meta[2 * blockIdx.y];
-  const int64_t j = blockIdx.x;
-  if (j >= k) return;
-  const int64_t col = b.cols[lo + b.kept[lo + j]];
-  double* G = Gbuf + lo * n + j * nm;
-  for (int64_t r = threadIdx.x; r < nm; r += blockDim.x) G[r] = Z[(lo + r) + col * ldz];
-}
-
-// grouped GEMM descriptors for the merges of a level
-__global__ void merge_gemm_desc(const Merge* merges, const MergeBufs b, double* Gbuf,
-                                double* U, double* Zt, int64_t n, GemmGroup* desc,
-                                int64_t nmerge) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= nmerge) return;
-  const Merge mg = merges[g];
-  const int64_t lo = mg.lo, nm = mg.hi - mg.lo;
-  const int64_t k = b.meta[2 * g];
-  GemmGroup d;
-  d.A = Gbuf + lo * n; d.lda = nm;
-  d.B = U + lo * n; d.ldb = k > 0 ? k : 1;
-  d.C = Zt + lo * n; d.ldc = nm;
-  d.m = nm; d.n = k; d.k = k;
-  desc[g] = d;
-}
-
 // Rank-sort the merged spectrum.  Entry q < k is root q; entry q >= k is the
 // (q-k)-th deflated sorted position.  Writes lam and the output columns.
 __global__ void merge_collect(const Merge* merges, MergeBufs b) {
@@ -489,22 +456,23 @@ __global__ void merge_collect(const Merge* merges, MergeBufs b) {
   if (q < k) {
     b.vals[lo + q] = b.lamk[lo + q];
     b.src[lo + q] = q;
+    b.colmap[lo + q] = b.cols[lo + b.kept[lo + q]];
   } else {
     const int64_t pos = b.dfl[lo + (q - k)];
     b.vals[lo + q] = b.ds[lo + pos];
     b.src[lo + q] = -(b.cols[lo + pos] + 1);
+    b.colmap[lo + q] = b.cols[lo + pos];
   }
 }
 
-__global__ void merge_place(const Merge* merges, MergeBufs b, const double* Zold, const double* Zt,
-                            double* Znew, int64_t ldz, double* lam, int64_t n) {
+// The sorted place of every merge-order entry: its rank among the merged
+// values, ties broken by merge order.  One workgroup per entry.
+__global__ void merge_rank(const Merge* merges, MergeBufs b, double* lam) {
   const Merge mg = merges[blockIdx.y];
   const int64_t lo = mg.lo, nm = mg.hi - mg.lo;
   const int64_t q = blockIdx.x;
   if (q >= nm) return;
   const double v = b.vals[lo + q];
-  const int64_t sq = b.src[lo + q];
-  // rank among the merged entries (ties broken by list index)
   __shared__ int64_t s_rank;
   if (threadIdx.x == 0) s_rank = 0;
   __syncthreads();
@@ -515,16 +483,62 @@ __global__ void merge_place(const Merge* merges, MergeBufs b, const double* Zold
   }
   atomicAdd((unsigned long long*)&s_rank, (unsigned long long)r);
   __syncthreads();
-  const int64_t dst = lo + s_rank;
-  if (threadIdx.x == 0) lam[dst] = v;
-  if (sq >= 0) {
-    const double* src = Zt + lo * n + sq * nm;
-    for (int64_t i = threadIdx.x; i < nm; i += blockDim.x) Znew[(lo + i) + dst * ldz] = src[i];
-  } else {
-    const int64_t col = -sq - 1;
-    for (int64_t i = threadIdx.x; i < nm; i += blockDim.x)
-      Znew[(lo + i) + dst * ldz] = Zold[(lo + i) + col * ldz];
+  if (threadIdx.x == 0) {
+    b.dst[lo + q] = lo + s_rank;
+    lam[lo + s_rank] = v;
   }
+}
+
+// ---- eigenvector mode: the merges of a level applied to X's columns.
+// Rotations: every row r of X (nr rows) rotates its columns (ca, cb).
+__global__ void merge_rotate_cols(const Merge* merges, MergeBufs b, double* X, int64_t ldx,
+                                  int64_t nr) {
+  const int64_t nrot = b.meta[2 * blockIdx.y + 1];
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (nrot == 0 || r >= nr) return;
+  const Merge mg = merges[blockIdx.y];
+  for (int64_t q = 0; q < nrot; ++q) {
+    const int64_t ca = b.rot_a[mg.lo + q], cb = b.rot_b[mg.lo + q];
+    const double c = b.rot_c[mg.lo + q], s = b.rot_s[mg.lo + q];
+    const double xa = X[r + ca * ldx], xb = X[r + cb * ldx];
+    X[r + ca * ldx] = c * xa - s * xb;
+    X[r + cb * ldx] = s * xa + c * xb;
+  }
+}
+
+// Rows r0 .. r0+rows-1 of X in merge order: Tc(i, p) = X(r0 + i, colmap[p])
+// for every entry p of the level (column p of Tc at Tc + p rr).
+__global__ void merge_gather_cols(MergeBufs b, const double* X, int64_t ldx, int64_t r0,
+                                  int64_t rows, double* Tc, int64_t rr) {
+  const int64_t p = blockIdx.x;
+  const double* src = X + r0 + b.colmap[p] * ldx;
+  double* dst = Tc + p * rr;
+  for (int64_t i = threadIdx.x; i < rows; i += blockDim.x) dst[i] = src[i];
+}
+
+// grouped products of a level: Oc(:, lo .. lo+k) = Tc(:, lo .. lo+k) U_merge
+__global__ void merge_gemm_desc_cols(const Merge* merges, const MergeBufs b, const double* Tc,
+                                     const double* U, double* Oc, int64_t n, int64_t rows,
+                                     int64_t rr, GemmGroup* desc, int64_t nmerge) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nmerge) return;
+  const int64_t lo = merges[g].lo;
+  const int64_t k = b.meta[2 * g];
+  GemmGroup d;
+  d.A = Tc + lo * rr; d.lda = rr;
+  d.B = U + lo * n; d.ldb = k > 0 ? k : 1;
+  d.C = Oc + lo * rr; d.ldc = rr;
+  d.m = rows; d.n = k; d.k = k;
+  desc[g] = d;
+}
+
+// X(r0 + i, dst[p]) = (root ? Oc : Tc)(i, p)
+__global__ void merge_place_cols(MergeBufs b, const double* Tc, const double* Oc, int64_t rr,
+                                 double* X, int64_t ldx, int64_t r0, int64_t rows) {
+  const int64_t p = blockIdx.x;
+  const double* src = (b.src[p] >= 0 ? Oc : Tc) + p * rr;
+  double* dst = X + r0 + b.dst[p] * ldx;
+  for (int64_t i = threadIdx.x; i < rows; i += blockDim.x) dst[i] = src[i];
 }
 
 // ---- projected mode: the merge steps on the rows of PY (n x W, W = ny + 2).
@@ -572,29 +586,16 @@ __global__ void merge_gemm_desc_rows(const Merge* merges, const MergeBufs b, dou
   desc[g] = d;
 }
 
-// sort rows into place: destination rank as in merge_place
+// sort rows into place (destinations from merge_rank)
 __global__ void merge_place_rows(const Merge* merges, MergeBufs b, const double* PYold,
-                                 const double* Ptb, double* PYnew, int64_t ldpy, int W,
-                                 double* lam) {
+                                 const double* Ptb, double* PYnew, int64_t ldpy, int W) {
   const Merge mg = merges[blockIdx.y];
   const int64_t lo = mg.lo, nm = mg.hi - mg.lo;
   const int64_t q = blockIdx.x;
   if (q >= nm) return;
   const int64_t k = b.meta[2 * blockIdx.y];
-  const double v = b.vals[lo + q];
   const int64_t sq = b.src[lo + q];
-  __shared__ int64_t s_rank;
-  if (threadIdx.x == 0) s_rank = 0;
-  __syncthreads();
-  int64_t r = 0;
-  for (int64_t p = threadIdx.x; p < nm; p += blockDim.x) {
-    const double w = b.vals[lo + p];
-    if (w < v || (w == v && p < q)) ++r;
-  }
-  atomicAdd((unsigned long long*)&s_rank, (unsigned long long)r);
-  __syncthreads();
-  const int64_t dst = lo + s_rank;
-  if (threadIdx.x == 0) lam[dst] = v;
+  const int64_t dst = b.dst[lo + q];
   for (int c = threadIdx.x; c < W; c += blockDim.x)
     PYnew[dst + (int64_t)c * ldpy] =
         sq >= 0 ? Ptb[lo * W + sq + (int64_t)c * k] : PYold[(-sq - 1) + (int64_t)c * ldpy];
@@ -605,56 +606,17 @@ __global__ void copy_vec(const double* s, double* d, int64_t n) {
   if (i < n) d[i] = s[i];
 }
 
-struct Layout {
-  int64_t n;
-  double *dw, *lamA, *lamB, *Zb, *U, *G, *Zt;
-  int64_t *cuts, *leaf_lo, *leaf_hi;
-  Merge* merges;
-  GemmGroup* desc;
-  MergeBufs mb;
-  double* end;
-};
-
-// carve the workspace (doubles) into the arrays above
-Layout carve(double* ws, int64_t n, int64_t max_merges) {
-  Layout L;
-  L.n = n;
-  double* p = ws;
-  auto take = [&](int64_t count) { double* r = p; p += count; return r; };
-  L.dw = take(n);
-  L.lamA = take(n);
-  L.lamB = take(n);
-  L.Zb = take(n * n);
-  L.U = take(n * n);
-  L.G = take(n * n);
-  L.Zt = take(n * n);
-  L.cuts = (int64_t*)take(n + 1);
-  L.leaf_lo = (int64_t*)take(n + 1);
-  L.leaf_hi = (int64_t*)take(n + 1);
-  L.merges = (Merge*)take(3 * (max_merges + 1));
-  L.desc = (GemmGroup*)take((int64_t)(sizeof(GemmGroup) / 8 + 1) * (max_merges + 1));
-  MergeBufs& b = L.mb;
-  b.ds = take(n); b.zs = take(n); b.cols = (int64_t*)take(n); b.kind = (int*)take(n);
-  b.kept = (int64_t*)take(n);
-  b.rot_a = (int64_t*)take(n); b.rot_b = (int64_t*)take(n); b.rot_c = take(n); b.rot_s = take(n);
-  b.meta = (int64_t*)take(2 * (max_merges + 1)); b.rho = take(max_merges + 1);
-  b.origin = (int64_t*)take(n); b.tau = take(n); b.lamk = take(n); b.zhat = take(n);
-  b.vals = take(n); b.src = (int64_t*)take(n);
-  b.dfl = (int64_t*)take(n); b.dk = take(n); b.zk = take(n);
-  L.end = p;
-  return L;
-}
-
 int depth_for(int64_t n) {
   int D = 0;
   while (ceil_div(n, (int64_t)1 << D) > LEAF) ++D;
   return D;
 }
 
-// projected mode: U (n^2), and n x W blocks for the rows (current, next),
-// the gathered kept rows and their product with U^T
+// U (n^2, the caller's) and n x W blocks for the rows (current, next), the
+// gathered kept rows and their product with U^T; in eigenvector mode two
+// row chunks of X (rr x n each) in merge order and their products with U.
 struct LayoutP {
-  double *dw, *lamA, *lamB, *U, *G, *Pt, *PYa, *PYb;
+  double *dw, *lamA, *lamB, *U, *G, *Pt, *PYa, *PYb, *Tc, *Oc;
   int64_t *cuts, *leaf_lo, *leaf_hi;
   Merge* merges;
   GemmGroup* desc;
@@ -662,7 +624,7 @@ struct LayoutP {
   double* end;
 };
 
-LayoutP carve_proj(double* ws, int64_t n, int64_t max_merges, int W, double* U) {
+LayoutP carve_proj(double* ws, int64_t n, int64_t max_merges, int W, int64_t rr, double* U) {
   LayoutP L;
   double* p = ws;
   auto take = [&](int64_t count) { double* r = p; p += count; return r; };
@@ -674,6 +636,8 @@ LayoutP carve_proj(double* ws, int64_t n, int64_t max_merges, int W, double* U) 
   L.Pt = take(n * W);
   L.PYa = take(n * W);
   L.PYb = take(n * W);
+  L.Tc = rr ? take(rr * n) : nullptr;
+  L.Oc = rr ? take(rr * n) : nullptr;
   L.cuts = (int64_t*)take(n + 1);
   L.leaf_lo = (int64_t*)take(n + 1);
   L.leaf_hi = (int64_t*)take(n + 1);
@@ -687,8 +651,15 @@ LayoutP carve_proj(double* ws, int64_t n, int64_t max_merges, int W, double* U) 
   b.origin = (int64_t*)take(n); b.tau = take(n); b.lamk = take(n); b.zhat = take(n);
   b.vals = take(n); b.src = (int64_t*)take(n);
   b.dfl = (int64_t*)take(n); b.dk = take(n); b.zk = take(n);
+  b.colmap = (int64_t*)take(n); b.dst = (int64_t*)take(n);
   L.end = p;
   return L;
+}
+
+// rows of X per chunk in eigenvector mode: two chunks of at most 2^27
+// doubles (1 GiB) each
+int64_t chunk_rows(int64_t n) {
+  return std::max<int64_t>(1, std::min<int64_t>(n, ((int64_t)1 << 27) / std::max<int64_t>(n, 1)));
 }
 
 // The balanced tree over [0, n): levels[d] are the nodes at depth d (every
@@ -723,112 +694,23 @@ Tree build_tree(int64_t n) {
 
 }  // namespace
 
-int64_t stedc_ws_elems(int64_t n) {
-  const int64_t mm = (int64_t)1 << depth_for(n);
-  double* base = reinterpret_cast<double*>(64);
-  Layout L = carve(base, n, mm);
-  return (int64_t)(L.end - base);
-}
 
-void stedc(const double* d, const double* e, int64_t n, double* lam, double* Z, int64_t ldz,
-           double* ws, int64_t ws_elems, int64_t* d_status, hipStream_t s) {
-  MM_REQUIRE(ldz == n, kInvalid, "stedc: ldz must equal n");
-  MM_REQUIRE(ws_elems >= stedc_ws_elems(n), kInvalid, "stedc: workspace too small");
-  if (n <= 0) return;
-  const int D = depth_for(n);
-  const int64_t max_merges = (int64_t)1 << D;
-  Layout L = carve(ws, n, max_merges);
-  // tree: levels[d] = nodes at depth d; every node above the leaves is cut at
-  // its midpoint
-  std::vector<std::vector<Merge>> levels(D + 1);
-  levels[0].push_back({0, 0, n});
-  for (int dd = 0; dd < D; ++dd) {
-    for (size_t q = 0; q < levels[dd].size(); ++q) {
-      const int64_t lo = levels[dd][q].lo, hi = levels[dd][q].hi;
-      const int64_t mid = lo + (hi - lo) / 2;
-      levels[dd][q].mid = mid;
-      levels[dd + 1].push_back({lo, lo, mid});
-      levels[dd + 1].push_back({mid, mid, hi});
-    }
-  }
-  // levels[D] are the leaves; merges happen at depths D-1 .. 0
-  std::vector<int64_t> cuts, llo, lhi;
-  for (int dd = 0; dd < D; ++dd)
-    for (const Merge& nd : levels[dd]) cuts.push_back(nd.mid);
-  for (const Merge& nd : levels[D]) { llo.push_back(nd.lo); lhi.push_back(nd.hi); }
-  if (D == 0) { llo.assign(1, 0); lhi.assign(1, n); }
-  const int64_t ncuts = (int64_t)cuts.size();
-  if (ncuts) MM_HIP_TRY(hipMemcpyAsync(L.cuts, cuts.data(), ncuts * 8, hipMemcpyHostToDevice, s));
-  MM_HIP_TRY(hipMemcpyAsync(L.leaf_lo, llo.data(), llo.size() * 8, hipMemcpyHostToDevice, s));
-  MM_HIP_TRY(hipMemcpyAsync(L.leaf_hi, lhi.data(), lhi.size() * 8, hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(tear_k, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, d, e, n, L.cuts,
-                     ncuts, L.dw);
-  fill(Z, n * n, 0.0, s);
-  fill(L.Zb, n * n, 0.0, s);
-  hipLaunchKernelGGL(leaf_jacobi, dim3((unsigned)llo.size()), dim3(64), 0, s, L.dw, e, L.leaf_lo,
-                     L.leaf_hi, L.lamA, Z, ldz, nullptr, 0, 0, nullptr, 0);
-  MM_HIP_TRY(hipGetLastError());
-  double* Zc = Z;      // current eigenvectors
-  double* Zn = L.Zb;   // next
-  double* lc = L.lamA;
-  double* ln = L.lamB;
-  for (int dd = D - 1; dd >= 0; --dd) {
-    const std::vector<Merge>& lv = levels[dd];
-    const int64_t nmg = (int64_t)lv.size();
-    int64_t maxm = 0;
-    for (const Merge& mg : lv) maxm = std::max(maxm, mg.hi - mg.lo);
-    MM_HIP_TRY(hipMemcpyAsync(L.merges, lv.data(), nmg * sizeof(Merge), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(merge_prepare, dim3((unsigned)nmg), dim3(NT), 0, s, L.merges, e, lc, Zc,
-                       ldz, L.mb, nullptr, 0, 0);
-    hipLaunchKernelGGL(merge_rotate, dim3((unsigned)ceil_div(maxm, 256), (unsigned)nmg), dim3(256),
-                       0, s, L.merges, L.mb, Zc, ldz);
-    hipLaunchKernelGGL(merge_compact, dim3((unsigned)ceil_div(maxm, 256), (unsigned)nmg), dim3(256),
-                       0, s, L.merges, L.mb);
-    hipLaunchKernelGGL(merge_secular, dim3((unsigned)ceil_div(maxm, 64), (unsigned)nmg), dim3(64),
-                       0, s, L.merges, L.mb, d_status);
-    hipLaunchKernelGGL(merge_lowner, dim3((unsigned)ceil_div(maxm, 64), (unsigned)nmg), dim3(64),
-                       0, s, L.merges, L.mb);
-    hipLaunchKernelGGL(merge_form_u, dim3((unsigned)maxm, (unsigned)nmg), dim3(NT), 0, s, L.merges,
-                       L.mb, L.U, n);
-    hipLaunchKernelGGL(merge_gather, dim3((unsigned)maxm, (unsigned)nmg), dim3(256), 0, s,
-                       L.merges, L.mb, Zc, ldz, L.G, n);
-    hipLaunchKernelGGL(merge_gemm_desc, dim3((unsigned)ceil_div(nmg, 64)), dim3(64), 0, s,
-                       L.merges, L.mb, L.G, L.U, L.Zt, n, L.desc, nmg);
-    MM_HIP_TRY(hipGetLastError());
-    gemm_grouped(L.desc, nmg, maxm, maxm, false, false, 1.0, 0.0, s);
-    hipLaunchKernelGGL(merge_collect, dim3((unsigned)ceil_div(maxm, 256), (unsigned)nmg),
-                       dim3(256), 0, s, L.merges, L.mb);
-    hipLaunchKernelGGL(merge_place, dim3((unsigned)maxm, (unsigned)nmg), dim3(256), 0, s,
-                       L.merges, L.mb, Zc, L.Zt, Zn, ldz, ln, n);
-    MM_HIP_TRY(hipGetLastError());
-    std::swap(Zc, Zn);
-    std::swap(lc, ln);
-  }
-  hipLaunchKernelGGL(copy_vec, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, lc, lam, n);
-  if (Zc != Z) copy_matrix(Zc, n, Z, ldz, n, n, s);
-  MM_HIP_TRY(hipGetLastError());
-}
+namespace {
 
-int64_t stedc_project_ws_elems(int64_t n, int ny) {
-  const int64_t mm = (int64_t)1 << depth_for(n);
-  double* base = reinterpret_cast<double*>(64);
-  LayoutP L = carve_proj(base, n, mm, ny + 2, nullptr);
-  return (int64_t)(L.end - base);
-}
-
-void stedc_project(const double* d, const double* e, int64_t n, double* lam, const double* Y,
-                   int64_t ldy, int ny, double* ZY, int64_t ldzy, double* U, double* ws,
-                   int64_t ws_elems, int64_t* d_status, hipStream_t s) {
-  MM_REQUIRE(ny >= 1, kInvalid, "stedc_project: at least one column");
-  MM_REQUIRE(U != nullptr || n <= 0, kInvalid, "stedc_project: no eigenvector scratch");
-  MM_REQUIRE(ws_elems >= stedc_project_ws_elems(n, ny), kInvalid,
-             "stedc_project: workspace too small");
-  if (n <= 0) return;
+// The divide and conquer of both modes.  Projected (X null): ZY = Z^T Y
+// (n x ny).  Eigenvector mode (X non-null, ny = 0): X <- X_pre Z, where
+// X_pre is the leaves' block-diagonal eigenvectors after `pre`.
+void dc_core(const double* d, const double* e, int64_t n, double* lam, const double* Y,
+             int64_t ldy, int ny, double* ZY, int64_t ldzy, double* X, int64_t ldx,
+             const std::function<void(double*)>& pre, double* U, double* ws, int64_t ws_elems,
+             int64_t* d_status, hipStream_t s) {
   const int W = ny + 2;
   const Tree tr = build_tree(n);
   const int D = tr.D;
   const int64_t max_merges = (int64_t)1 << D;
-  LayoutP L = carve_proj(ws, n, max_merges, W, U);
+  const int64_t rr = X ? chunk_rows(n) : 0;
+  LayoutP L = carve_proj(ws, n, max_merges, W, rr, U);
+  MM_REQUIRE(L.end - ws <= ws_elems, kInvalid, "stedc: workspace too small");
   const int64_t ncuts = (int64_t)tr.cuts.size();
   if (ncuts)
     MM_HIP_TRY(hipMemcpyAsync(L.cuts, tr.cuts.data(), ncuts * 8, hipMemcpyHostToDevice, s));
@@ -836,9 +718,11 @@ void stedc_project(const double* d, const double* e, int64_t n, double* lam, con
   MM_HIP_TRY(hipMemcpyAsync(L.leaf_hi, tr.lhi.data(), tr.lhi.size() * 8, hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(tear_k, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, d, e, n, L.cuts,
                      ncuts, L.dw);
+  if (X) fill(X, n * n, 0.0, s);  // the leaves write their diagonal blocks
   hipLaunchKernelGGL(leaf_jacobi, dim3((unsigned)tr.llo.size()), dim3(64), 0, s, L.dw, e,
-                     L.leaf_lo, L.leaf_hi, L.lamA, nullptr, 0, Y, ldy, ny, L.PYa, n);
+                     L.leaf_lo, L.leaf_hi, L.lamA, X, ldx, Y, ldy, ny, L.PYa, n);
   MM_HIP_TRY(hipGetLastError());
+  if (X && pre) pre(X);
   double* PYc = L.PYa;
   double* PYn = L.PYb;
   double* lc = L.lamA;
@@ -853,6 +737,9 @@ void stedc_project(const double* d, const double* e, int64_t n, double* lam, con
                        nullptr, 0, L.mb, PYc, n, ny);
     hipLaunchKernelGGL(merge_rotate_rows, dim3((unsigned)ceil_div(W, 64), (unsigned)nmg), dim3(64),
                        0, s, L.merges, L.mb, PYc, n, W);
+    if (X)
+      hipLaunchKernelGGL(merge_rotate_cols, dim3((unsigned)ceil_div(n, 256), (unsigned)nmg),
+                         dim3(256), 0, s, L.merges, L.mb, X, ldx, n);
     hipLaunchKernelGGL(merge_compact, dim3((unsigned)ceil_div(maxm, 256), (unsigned)nmg), dim3(256),
                        0, s, L.merges, L.mb);
     hipLaunchKernelGGL(merge_secular, dim3((unsigned)ceil_div(maxm, 64), (unsigned)nmg), dim3(64),
@@ -869,15 +756,62 @@ void stedc_project(const double* d, const double* e, int64_t n, double* lam, con
     gemm_grouped(L.desc, nmg, maxm, W, true, false, 1.0, 0.0, s);
     hipLaunchKernelGGL(merge_collect, dim3((unsigned)ceil_div(maxm, 256), (unsigned)nmg),
                        dim3(256), 0, s, L.merges, L.mb);
+    hipLaunchKernelGGL(merge_rank, dim3((unsigned)maxm, (unsigned)nmg), dim3(256), 0, s,
+                       L.merges, L.mb, ln);
     hipLaunchKernelGGL(merge_place_rows, dim3((unsigned)maxm, (unsigned)nmg), dim3(64), 0, s,
-                       L.merges, L.mb, PYc, L.Pt, PYn, n, W, ln);
+                       L.merges, L.mb, PYc, L.Pt, PYn, n, W);
     MM_HIP_TRY(hipGetLastError());
+    if (X) {
+      for (int64_t r0 = 0; r0 < n; r0 += rr) {
+        const int64_t rows = std::min(rr, n - r0);
+        hipLaunchKernelGGL(merge_gather_cols, dim3((unsigned)n), dim3(256), 0, s, L.mb, X, ldx,
+                           r0, rows, L.Tc, rr);
+        hipLaunchKernelGGL(merge_gemm_desc_cols, dim3((unsigned)ceil_div(nmg, 64)), dim3(64), 0,
+                           s, L.merges, L.mb, L.Tc, L.U, L.Oc, n, rows, rr, L.desc, nmg);
+        MM_HIP_TRY(hipGetLastError());
+        gemm_grouped(L.desc, nmg, rows, maxm, false, false, 1.0, 0.0, s);
+        hipLaunchKernelGGL(merge_place_cols, dim3((unsigned)n), dim3(256), 0, s, L.mb, L.Tc,
+                           L.Oc, rr, X, ldx, r0, rows);
+        MM_HIP_TRY(hipGetLastError());
+      }
+    }
     std::swap(PYc, PYn);
     std::swap(lc, ln);
   }
   hipLaunchKernelGGL(copy_vec, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, lc, lam, n);
-  copy_matrix(PYc, n, ZY, ldzy, n, ny, s);
+  if (ZY) copy_matrix(PYc, n, ZY, ldzy, n, ny, s);
   MM_HIP_TRY(hipGetLastError());
+}
+
+int64_t ws_size(int64_t n, int ny, bool eigvec) {
+  const int64_t mm = (int64_t)1 << depth_for(n);
+  double* base = reinterpret_cast<double*>(64);
+  LayoutP L = carve_proj(base, n, mm, ny + 2, eigvec ? chunk_rows(n) : 0, nullptr);
+  return (int64_t)(L.end - base);
+}
+
+}  // namespace
+
+int64_t stedc_ws_elems(int64_t n) { return ws_size(n, 0, true); }
+
+void stedc(const double* d, const double* e, int64_t n, double* lam, double* X, int64_t ldx,
+           double* U, double* ws, int64_t ws_elems, int64_t* d_status, hipStream_t s,
+           const std::function<void(double*)>& pre) {
+  MM_REQUIRE(ldx == n, kInvalid, "stedc: ldx must equal n");
+  MM_REQUIRE(X != nullptr && U != nullptr, kInvalid, "stedc: X and U are required");
+  if (n <= 0) return;
+  dc_core(d, e, n, lam, nullptr, 0, 0, nullptr, 0, X, ldx, pre, U, ws, ws_elems, d_status, s);
+}
+
+int64_t stedc_project_ws_elems(int64_t n, int ny) { return ws_size(n, ny, false); }
+
+void stedc_project(const double* d, const double* e, int64_t n, double* lam, const double* Y,
+                   int64_t ldy, int ny, double* ZY, int64_t ldzy, double* U, double* ws,
+                   int64_t ws_elems, int64_t* d_status, hipStream_t s) {
+  MM_REQUIRE(ny >= 1, kInvalid, "stedc_project: at least one column");
+  MM_REQUIRE(U != nullptr || n <= 0, kInvalid, "stedc_project: no eigenvector scratch");
+  if (n <= 0) return;
+  dc_core(d, e, n, lam, Y, ldy, ny, ZY, ldzy, nullptr, 0, {}, U, ws, ws_elems, d_status, s);
 }
 
 }  // namespace mm

@@ -229,16 +229,18 @@ __global__ void __launch_bounds__(NT) finish_k(int64_t n, const double* __restri
                                                double* __restrict__ state,
                                                const double* __restrict__ Pt, int n_probe,
                                                double* __restrict__ pp_base,
-                                               int64_t* kstep, int64_t parts) {
+                                               int64_t* kstep, int64_t parts,
+                                               double* __restrict__ dI_out) {
   __shared__ double red[8][NT / 64];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int64_t i = (int64_t)blockIdx.x * NT + t;
+  const int64_t k = kstep[1];
   double d = 0.0;
   if (i < n) {
     d = x[i];
     state[i] += d;
+    if (dI_out) dI_out[i + k * n] = d;
   }
-  const int64_t k = kstep[1];
   if (i == 0) kstep[0] = k + 1;
   for (int p = 0; p < n_probe; ++p) {
     const double v = wave_sum_dpp(i < n ? Pt[i + (int64_t)p * n] * d : 0.0);
@@ -329,7 +331,7 @@ void enqueue_step_b(const CholStep& c, hipStream_t s) {
     launch_rowupd<NL>(0, K * B, K * B, (int)std::min<int64_t>(B, n - K * B),
                       c.pb + bwd_panel_offset(B, K), c.b, s);
   hipLaunchKernelGGL(finish_k, dim3((unsigned)parts), dim3(NT), 0, s, n, c.b, c.I, c.Pt,
-                     c.n_probe, c.probe_partial, c.kstep, parts);
+                     c.n_probe, c.probe_partial, c.kstep, parts, c.dI_out);
 }
 
 void enqueue_step(const CholStep& c, hipStream_t s) {
@@ -357,7 +359,8 @@ int64_t trsv_parts(int64_t n) { return ceil_div(n, NT); }
 void chol_steps(const CholStep& c, int64_t k0, int64_t n_steps, hipStream_t s) {
   MM_REQUIRE(c.B == 256 || c.B == 512 || c.B == 1024 || c.B == 2048, kInvalid,
              "chol_steps: block size must be a power of two in [256, 2048]");
-  MM_REQUIRE(c.n_probe <= 8, kInvalid, "chol_steps: at most 8 probes");
+  MM_REQUIRE(c.dI_out ? c.n_probe == 0 : c.n_probe <= 8, kInvalid,
+             "chol_steps: at most 8 probes, or none with the increments written out");
   MM_REQUIRE(c.Rlr.ns == 0 || (c.Rlr.m >= 1 && c.Rlr.m <= 8), kInvalid,
              "chol_steps: low-rank resistance term of rank 1..8");
   if (n_steps <= 0) return;

@@ -167,6 +167,7 @@ __global__ void __launch_bounds__(NT) modal_step_k(ModalStep ms, int64_t n_steps
         }
         dy = exact ? c * e + g * e2 - a * y : c * (e - a * y);
         y += dy;
+        if (ms.dy_out && n < n0) ms.dy_out[n + k * n0] = dy;
       }
 #pragma unroll
       for (int p = 0; p < (NP > 0 ? NP : 1); ++p) acc[i][p] = pt[p] * dy;
@@ -533,8 +534,8 @@ void modal_steps(const ModalStep& m, int64_t k0, int64_t n_steps, hipStream_t s)
   (void)k0;
   if (n_steps <= 0) return;
   MM_REQUIRE(m.f.nf <= MAXF, kInvalid, "modal_steps: too many forcing columns");
-  MM_REQUIRE(m.n_probe >= 1 && m.n_probe <= MAXP, kInvalid,
-             "modal_steps: 1..8 probes per run");
+  MM_REQUIRE(m.dy_out ? m.n_probe == 0 : (m.n_probe >= 1 && m.n_probe <= MAXP), kInvalid,
+             "modal_steps: 1..8 probes per run, or none with the increments written out");
   dim3 grid((unsigned)modal_groups(m.n0));
   if (m.f.nf == 1) launch_np<1>(m, n_steps, s, grid);
   else launch_np<0>(m, n_steps, s, grid);

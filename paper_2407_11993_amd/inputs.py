@@ -8,7 +8,7 @@ arithmetic: the inductance matrix L, every factorisation, the modal
 decomposition and the time stepping are computed separately by each side.
 
 The paper's own workload (an Inconel tube meshed with 100,676 edge-element
-unknowns, Sec. 4.1 and 4.5) is not available; these plates stand in for it.
+unknowns, Sec. 4.1 and 4.6) is not available; these plates stand in for it.
 
 Conventions
 -----------

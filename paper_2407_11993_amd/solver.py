@@ -29,19 +29,27 @@ class Solver:
     """One problem (Sec. 3.1) on one GPU: the modal and the Cholesky method.
 
     ``workload`` is a :class:`paper_2407_11993_amd.inputs.Workload` (or any
-    object with the same fields: xyz, h, R (CSR), M, P, E).
+    object with the same fields: xyz, h, R (CSR), M, P, E).  An attribute
+    ``L`` (an n x n symmetric positive definite matrix, numpy or torch) is
+    handed to the library as the inductance matrix itself instead of the
+    generator xyz, h; the device copy is kept by the solver, which the
+    library borrows.
     """
 
     def __init__(self, workload, device: str = "cuda"):
         self.lib = _lib.lib()
         w = workload
         self.device = device
-        self.n = int(w.xyz.shape[0])
+        L = getattr(w, "L", None)
+        self.n = int(w.xyz.shape[0]) if L is None else int(L.shape[0])
         self.m = 0 if w.E is None else int(w.E.shape[0])
         self.n_src = int(w.M.shape[1])
         self.n_probe = int(w.P.shape[0])
         # device copies of the problem statement (kept alive by self)
-        self._xyz = _dev(w.xyz.reshape(-1))
+        # column-major device copy (the library reads its lower triangle)
+        self._L = None if L is None else _dev(
+            L.T if isinstance(L, torch.Tensor) else np.asarray(L).T)
+        self._xyz = None if L is not None else _dev(w.xyz.reshape(-1))
         self._rp = _dev(w.R.rowptr, torch.int64)
         self._rc = _dev(w.R.col, torch.int32)
         # the resistance values may be given as a device tensor (R_val), e.g.
@@ -57,7 +65,10 @@ class Solver:
         pb = _lib.Problem()
         pb.n = self.n
         pb.xyz = _lib.ptr(self._xyz)
-        pb.h = float(w.h)
+        pb.h = float(w.h) if L is None else 0.0
+        if L is not None:
+            pb.L = _lib.ptr(self._L)
+            pb.ldl = self.n
         pb.r_nnz = int(w.R.val.size)
         pb.r_rowptr, pb.r_col, pb.r_val = (_lib.ptr(self._rp), _lib.ptr(self._rc),
                                            _lib.ptr(self._rv))
@@ -230,6 +241,19 @@ class Solver:
 
     def reset(self):
         _lib.check(self.lib.mm_reset_state(self.ctx), self.ctx)
+
+    def get_state(self, which=_lib.MM_CHOLESKY):
+        """The method's stepping state (n doubles: reduced unknowns, then the
+        injected currents of its last step), for a later set_state."""
+        out = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        _lib.check(self.lib.mm_get_state(self.ctx, which, _lib.ptr(out)), self.ctx)
+        return out
+
+    def set_state(self, state, which=_lib.MM_CHOLESKY):
+        st = _dev(state)
+        assert st.numel() == self.n, "the state holds n values"
+        _lib.check(self.lib.mm_set_state(self.ctx, which, _lib.ptr(st)), self.ctx)
+        torch.cuda.current_stream().synchronize()  # st may be released on return
 
     def eigenvalues(self):
         out = torch.empty(self.n0, dtype=torch.float64, device=self.device)

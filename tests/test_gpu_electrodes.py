@@ -130,3 +130,37 @@ def test_dependent_electrode_rows_are_rejected():
     with pytest.raises(_lib.MMError) as ei:
         Solver(w)
     assert "linearly dependent" in str(ei.value)
+
+
+def test_state_checkpoint_restart(orc):
+    """Steps 0..k in one context, the state handed to a fresh context of the
+    same problem (mm_get_state / mm_set_state), steps k..T there: the
+    oracle's signal over the whole run, for both methods."""
+    from paper_2407_11993_amd import Solver, _lib
+    w = inputs.electrode_plate(10, 14, 4, T=300, tau_D=60.0, coil_period=120.0)
+    pb = _oracle(orc, w)
+    ref = orc.theta_direct(pb, 0.5, w.dt, w.T, w.i_src, w.i_D)
+    k = 137
+    a = Solver(w)
+    a.decompose()
+    m1 = _np(a.step_modal(0.5, w.dt, k, w.i_src[:k + 1], w.i_D[:k + 1]))
+    c1 = _np(a.step_cholesky(0.5, w.dt, k, w.i_src[:k + 1], w.i_D[:k + 1]))
+    st_m = a.get_state(_lib.MM_MODAL).clone()
+    st_c = a.get_state(_lib.MM_CHOLESKY).clone()
+    a.close()
+    b = Solver(w)
+    with pytest.raises(_lib.MMError) as ei:
+        b.get_state(_lib.MM_CHOLESKY)
+    assert ei.value.code == 5
+    b.decompose()
+    b.set_state(st_m, _lib.MM_MODAL)
+    b.set_state(st_c, _lib.MM_CHOLESKY)
+    assert np.array_equal(_np(b.get_state(_lib.MM_CHOLESKY)), _np(st_c))
+    m2 = _np(b.step_modal(0.5, w.dt, w.T - k, w.i_src[k:], w.i_D[k:]))
+    c2 = _np(b.step_cholesky(0.5, w.dt, w.T - k, w.i_src[k:], w.i_D[k:]))
+    assert _rel(np.vstack([m1, m2]), ref) < 1e-9
+    assert _rel(np.vstack([c1, c2]), ref) < 1e-9
+    # the full current after the restart: K Ii + A_D iD with iD from the state
+    I_last = orc.theta_direct(pb, 0.5, w.dt, w.T, w.i_src, w.i_D, want_I=True)[1][-1]
+    assert _rel(_np(b.current(_lib.MM_CHOLESKY)), I_last) < 1e-9
+    b.close()

@@ -238,3 +238,58 @@ def test_syevd_clustered(K):
     A = (A + A.T) / 2
     w, Z = K.syevd(A)
     _check_eig(A, _np(w), _np(Z), tol=5e-13)
+
+
+def _check_eig_gpu(apply_A, w, Z, scale, tol):
+    """Residual and orthogonality on the GPU (torch products) for sizes where
+    a dense numpy check would take minutes; w sorted."""
+    import torch
+    n = Z.shape[0]
+    assert bool(torch.all(w[1:] >= w[:-1]))
+    eye = torch.eye(n, dtype=torch.float64, device=Z.device)
+    orth = float((Z.T @ Z - eye).abs().max())
+    res = float((apply_A(Z) - Z * w).abs().max())
+    assert orth < tol * np.sqrt(n), orth
+    assert res < tol * scale * np.sqrt(n), res
+
+
+def test_stedc_two_row_chunks(K):
+    """n = 12,000: the merges are applied to the eigenvector matrix in two
+    chunks of rows (11,184 and a ragged 816)."""
+    import torch
+    n = 12000
+    rng = np.random.default_rng(12)
+    d = rng.standard_normal(n)
+    e = rng.standard_normal(n - 1)
+    e[::997] = 0.0  # a few exact splits deflate whole subproblems
+    w, Z = K.stedc(d, e)
+    ref = sla.eigvalsh_tridiagonal(d, e)
+    scale = np.abs(ref).max()
+    assert np.abs(_np(w) - ref).max() < 1e-13 * scale * np.sqrt(n)
+    dt = torch.as_tensor(d, device="cuda")
+    et = torch.as_tensor(e, device="cuda")
+
+    def T_times(X):
+        Y = dt[:, None] * X
+        Y[:-1] += et[:, None] * X[1:]
+        Y[1:] += et[:, None] * X[:-1]
+        return Y
+    _check_eig_gpu(T_times, w, Z, scale, 1e-13)
+
+
+def test_syevd_two_row_chunks(K):
+    """n = 11,700, a dense symmetric matrix with a known spectrum (clusters
+    included): the back-transform of the leaves, then the merges in two
+    chunks of rows."""
+    import torch
+    n = 11700
+    g = torch.Generator(device="cuda").manual_seed(5)
+    Qr, _ = torch.linalg.qr(torch.randn(n, n, dtype=torch.float64, device="cuda", generator=g))
+    lam = torch.cat([torch.full((300,), 1.0), torch.full((200,), -2.0),
+                     torch.linspace(-5.0, 7.0, n - 500)]).to(torch.float64).cuda()
+    A = (Qr * lam) @ Qr.T
+    A = (A + A.T) / 2
+    w, Z = K.syevd(A)
+    ref = torch.sort(lam).values
+    assert float((w - ref).abs().max()) < 1e-13 * 7.0 * np.sqrt(n)
+    _check_eig_gpu(lambda X: A @ X, w, Z, 7.0, 1e-13)

@@ -763,3 +763,67 @@ def test_mode_weights_basis_free_identities(orc):
     # each column on its own, so that no column is checked only through others
     for j in range(3):
         assert np.abs(got1[:, j] - ref1[:, j]).max() < 1e-11 * np.abs(ref1[:, j]).max()
+
+
+# ---------------------------------------------------------------------------
+# time constants from the other side of the pencil (Li v = tau Ri v)
+# ---------------------------------------------------------------------------
+def test_time_constants_diagonal_pencil(orc):
+    Ld = np.array([1.0, 2.0, 0.5, 4.0])
+    Rd = np.array([3.0, 1.0, 2.0, 2.0])
+    pb = orc.Problem(np.diag(Ld), np.diag(Rd), np.zeros((4, 1)), np.zeros((1, 4)))
+    tau = orc.time_constants(pb)
+    assert np.allclose(tau, np.sort(Ld / Rd)[::-1], rtol=1e-15, atol=0)
+
+
+def test_time_constants_2x2_quadratic_formula(orc):
+    L = np.array([[2.0, 0.6], [0.6, 1.0]])
+    R = np.array([[1.0, -0.3], [-0.3, 3.0]])
+    pb = orc.Problem(L, R, np.zeros((2, 1)), np.zeros((1, 2)))
+    tau = orc.time_constants(pb)
+    # det(L - tau R) = a tau^2 + b tau + c
+    a = R[0, 0] * R[1, 1] - R[0, 1] ** 2
+    b = -(L[0, 0] * R[1, 1] + L[1, 1] * R[0, 0] - 2 * L[0, 1] * R[0, 1])
+    c = L[0, 0] * L[1, 1] - L[0, 1] ** 2
+    disc = math.sqrt(b * b - 4 * a * c)
+    ref = sorted([(-b - disc) / (2 * a), (-b + disc) / (2 * a)], reverse=True)
+    assert np.allclose(tau, ref, rtol=1e-14, atol=0)
+
+
+def test_time_constants_match_library_and_invariants(orc):
+    _, L, R, M = _small_problem(orc)
+    pb = orc.Problem(L, R, M, M.T)
+    tau = orc.time_constants(pb)
+    assert np.all(tau > 0) and np.all(np.diff(tau) <= 0)     # Sec. 2.3 ordering
+    ref = np.sort(np.real(sla.eigvals(L, R)))[::-1]
+    assert np.abs(tau - ref).max() < 1e-12 * tau.max()
+    # trace invariant: sum tau = tr(R^{-1} L)
+    assert abs(tau.sum() - np.trace(np.linalg.solve(R, L))) < 1e-12 * tau.sum()
+    # R -> kR  =>  tau -> tau / k  (Sec. 3.2)
+    tau3 = orc.time_constants(orc.Problem(L, 3.0 * R, M, M.T))
+    assert np.allclose(tau3, tau / 3.0, rtol=1e-12)
+
+
+def test_time_constants_with_electrodes_use_the_reduced_pencil(orc):
+    w, L, R, E = _electrode_problem(orc)
+    pb = orc.Problem(L, R, w.M, w.P, E)
+    K2 = sla.null_space(E)
+    ref = np.sort(np.real(sla.eigvals(K2.T @ L @ K2, K2.T @ R @ K2)))[::-1]
+    tau = orc.time_constants(pb)
+    assert tau.shape == ref.shape
+    assert np.abs(tau - ref).max() < 1e-11 * tau.max()
+
+
+def test_time_constants_accurate_at_the_slow_end_under_high_contrast(orc):
+    """A cracked plate (resistivity 1e3 in the crack, kappa ~ 1e7): the
+    slowest time constants from Ri's side agree with the inertia counts of
+    Ri - sigma Li to 1e-10 relative, where the standard form from Li's side
+    fixes the small eigenvalues lam = 1/tau only to eps kappa."""
+    w = inputs.plate(10, 9, seed=2, crack=((3, 7), (4, 5), 1e3), T=1)
+    L = orc.assemble_L(w.xyz, w.h)
+    pb = orc.Problem(L, w.R.to_dense(), w.M, w.P)
+    tau = orc.time_constants(pb)
+    for k in range(3):  # lam_k = 1/tau_k, the k-th smallest eigenvalue
+        lam = 1.0 / tau[k]
+        assert orc.inertia(pb, lam * (1 - 1e-10))[0] == k
+        assert orc.inertia(pb, lam * (1 + 1e-10))[0] == k + 1
