@@ -141,6 +141,19 @@ mm_status mm_decompose_projected(mm_ctx* ctx);
 mm_status mm_step_modal(mm_ctx* ctx, double theta, double dt, int64_t n_steps,
                         const double* i_src, const double* i_D, double* signal);
 
+/* mm_step_modal without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, state, signal and errors as
+ * mm_step_modal, and the same kernels; the probe partial sums live in a
+ * file-scope device array of 2^23 doubles (64 MiB) that every GPU the
+ * library runs on holds until the process ends.  Limits: at most 8 probes,
+ * and n_steps * ceil(n0 / 256) * n_probe <= 2^23 per call (MM_E_INVALID
+ * otherwise; longer runs are several calls, the state continues).  All calls
+ * on one GPU share its array: calls that overlap in time on one GPU (two
+ * streams, two host threads) race. */
+mm_status mm_step_modal_noalloc(mm_ctx* ctx, double theta, double dt, int64_t n_steps,
+                                const double* i_src, const double* i_D, double* signal);
+
 /* Exact integration of the decoupled modal equations (Sec. 3.2, eq.
  * modal_decomposition_discrete), the analytical route Sec. 3.3 leaves to
  * later work: every source waveform is taken linear between its samples

@@ -23,7 +23,7 @@ MM_STEP_EXACT = 1
 MM_STEP_SCAN = 2
 
 # Every exported entry point of include/mm.h.
-SYMBOLS = ["mm_setup", "mm_decompose", "mm_decompose_projected", "mm_step_modal", "mm_step_modal_exact", "mm_step_modal_scan", "mm_modal_phasors", "mm_select_modes", "mm_step_modal_selective", "mm_step_cholesky",
+SYMBOLS = ["mm_setup", "mm_decompose", "mm_decompose_projected", "mm_step_modal", "mm_step_modal_noalloc", "mm_step_modal_exact", "mm_step_modal_scan", "mm_modal_phasors", "mm_select_modes", "mm_step_modal_selective", "mm_step_cholesky",
            "mm_probe", "mm_reset_state", "mm_get_state", "mm_set_state", "mm_eigenvalues", "mm_info",
            "mm_destroy", "mm_last_error", "mm_batch_create", "mm_batch_run",
            "mm_batch_info", "mm_batch_destroy", "mm_adjoint_modal", "mmk_dgemm", "mmk_dgemm_tri", "mmk_dsymm_lower", "mmk_dpotrf",
@@ -59,6 +59,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "mm_decompose": [vp],
         "mm_decompose_projected": [vp],
         "mm_step_modal": [vp, dbl, dbl, i64, vp, vp, vp],
+        "mm_step_modal_noalloc": [vp, dbl, dbl, i64, vp, vp, vp],
         "mm_step_modal_exact": [vp, dbl, i64, vp, vp, vp],
         "mm_modal_phasors": [vp, i64, vp, vp, vp, vp],
         "mm_step_modal_scan": [vp, dbl, i32, dbl, i64, vp, vp, vp],

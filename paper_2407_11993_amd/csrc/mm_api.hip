@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -67,6 +68,32 @@ int64_t eig_ws_elems(int64_t n, int nb, bool project = false) {
   return w;
 }
 
+// Probe partial sums of mm_step_modal_noalloc: a file-scope device array
+// (one copy per GPU, held until the process ends).  Host code reaches it
+// only through the address hipGetSymbolAddress returns on each device.
+constexpr int64_t kScratchDoubles = (int64_t)1 << 23;  // 64 MiB
+__device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[kMaxDevices] = {};
+
+// The scratch array's address on the current device, looked up once per
+// device (with that device current).
+double* scratch_on_current_device() {
+  int dev = 0;
+  MM_HIP_TRY(hipGetDevice(&dev));
+  MM_REQUIRE(dev >= 0 && dev < kMaxDevices, kDevice, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    MM_HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    MM_REQUIRE(ptr != nullptr, kDevice, "no address for the scratch array");
+    g_scratch[dev] = static_cast<double*>(ptr);
+  }
+  return g_scratch[dev];
+}
+
 }  // namespace
 
 struct mm_ctx {
@@ -111,6 +138,7 @@ struct mm_ctx {
   std::chrono::steady_clock::time_point t_mark;
   // probe partial sums of one step call
   Dev pp;
+  double* scratch = nullptr;  // this device's scratch array (mm_step_modal_noalloc)
   Dev scanws;  // chunk end values and start states of the time-parallel stepping
   Dev tmp;
   std::string err;
@@ -392,6 +420,7 @@ mm_status mm_setup(const mm_problem* pb, void* stream, mm_ctx** out) {
                "Ne must be 0 or 2..n");
     c->stream = (hipStream_t)stream;
     hipStream_t s = c->stream;
+    c->scratch = scratch_on_current_device();
     const char* ng = std::getenv("MM_NO_GRAPH");
     c->use_graph = !(ng && ng[0] == '1');
     const char* tr = std::getenv("MM_TRACE");
@@ -687,7 +716,7 @@ namespace {
 
 void step_modal_impl(mm_ctx* c, double theta, double dt, bool exact, int64_t n_steps,
                      const double* i_src, const double* i_D, double* signal,
-                     bool scan = false, bool selective = false) {
+                     bool scan = false, bool selective = false, bool no_alloc = false) {
     MM_REQUIRE(c->decomposed, kState, "modal stepping before mm_decompose");
     MM_REQUIRE(!selective || c->selected, kState,
                "mm_step_modal_selective before mm_select_modes");
@@ -746,8 +775,16 @@ void step_modal_impl(mm_ctx* c, double theta, double dt, bool exact, int64_t n_s
       return;
     }
     const int G = modal_groups(nm);
-    c->pp.alloc(sizeof(double) * n_steps * G * c->n_probe);
-    double* partial = c->pp.d();
+    double* partial = nullptr;
+    if (no_alloc) {
+      MM_REQUIRE(n_steps * G * c->n_probe <= kScratchDoubles, kInvalid,
+                 "mm_step_modal_noalloc: n_steps x ceil(n0 / 256) x n_probe must not exceed "
+                 "2^23 (call it on fewer steps at a time)");
+      partial = c->scratch;
+    } else {
+      c->pp.alloc(sizeof(double) * n_steps * G * c->n_probe);
+      partial = c->pp.d();
+    }
     ModalStep ms;
     ms.n0 = nm;
     ms.lam = selective ? c->sel_lam.d() : c->lam.d();
@@ -781,6 +818,17 @@ mm_status mm_step_modal(mm_ctx* c, double theta, double dt, int64_t n_steps,
                         const double* i_src, const double* i_D, double* signal) {
   if (!c) return MM_E_INVALID;
   return guarded(c, [&] { step_modal_impl(c, theta, dt, false, n_steps, i_src, i_D, signal); });
+}
+
+mm_status mm_step_modal_noalloc(mm_ctx* c, double theta, double dt, int64_t n_steps,
+                                const double* i_src, const double* i_D, double* signal) {
+  if (!c) return MM_E_INVALID;
+  return guarded(c, [&] {
+    MM_REQUIRE(c->n_probe <= kMaxRunColumns, kInvalid,
+               "mm_step_modal_noalloc: at most 8 probes");
+    MM_REQUIRE(c->scratch != nullptr, kState, "mm_step_modal_noalloc: no scratch array");
+    step_modal_impl(c, theta, dt, false, n_steps, i_src, i_D, signal, false, false, true);
+  });
 }
 
 mm_status mm_step_modal_exact(mm_ctx* c, double dt, int64_t n_steps, const double* i_src,
