@@ -180,7 +180,7 @@ def run_electrodes(args):
     chol_s = avg["setup"] + avg["cholesky_factor"] + per_step * T
     trsv_bytes = 2 * 8.0 * n0 * (n0 + 1) / 2
     achieved = trsv_bytes / per_step / 1e9
-    dec_flops = (1 / 3 + 1 / 3 + 1 / 3 + 4 / 3) * float(n0) ** 3  # potrf, trtri, C, band
+    dec_flops = _decomp_flops(n0, _band_block(w.R), full=False)
     return {
         "metric": "end-to-end s, modal theta-method (Cholesky theta-method beside it)",
         "value": round(modal_s, 3), "unit": "s", "n_gpus": 1, "steps": n_timed,
@@ -189,7 +189,7 @@ def run_electrodes(args):
         "data": "synthetic",
         "config": {"workload": w.name, "N": w.n, "N0": n0, "T": T, "theta": theta, "dt": dt,
                    "electrodes": w.m + 1, "probes": w.n_probe,
-                   "decomposition": "eigenvalues and projected weights Q^T G^-1 [F, P] "
+                   "decomposition": "eigenvalues and projected weights V^T [F, P] "
                                     "(the eigenvector matrix is not formed)",
                    "step": "one end-to-end run of both methods (warm-up runs on a 48x72 "
                            "plate with two electrodes, T = 2000)",
@@ -219,8 +219,8 @@ def run_electrodes(args):
         "roofline": {"bound": "hbm", "kernel": "triangular solve pair (fwd+bwd per step)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
-        # the modal value's dominant phase: GEMM-bound (Cholesky, triangular
-        # inverse, standard form, band reduction), timed on the stream it runs on
+        # the modal value's dominant phase: GEMM-bound (the banded standard
+        # form and the band reduction), timed on the stream it runs on
         "roofline_decomposition": {
             "bound": "mfma", "kernel": "projected decomposition (all its kernels)",
             "achieved": round(dec_flops / avg["decompose"] / 1e12, 2),
@@ -480,12 +480,28 @@ def run_adjoint(args):
     return res
 
 
-def _decomp_flops(n: int) -> float:
-    # algorithmic FP64 flops of the full modal decomposition:
-    # potrf n^3/3, trtri n^3/3, C = G^{-1} W^T (lower) n^3/3,
-    # band reduction 4n^3/3, back-transform Q2 2n^3 + Q1 2n^3,
-    # D&C merges <= 4n^3/3 (not counted: deflation dependent)
-    return (1 / 3 + 1 / 3 + 1 / 3 + 4 / 3 + 2 + 2) * float(n) ** 3
+def _band_block(R) -> int:
+    """Block size of R's banded factor: R's lower bandwidth rounded up to a
+    multiple of 64 (at least 64), as the library chooses it."""
+    import numpy as np
+    rows = np.repeat(np.arange(R.shape[0]), np.diff(R.rowptr))
+    band = int((rows - R.col).max()) if R.col.size else 0
+    return max(64, -(-max(band, 1) // 64) * 64)
+
+
+def _decomp_flops(n: int, Bb: int, full: bool) -> float:
+    """Algorithmic FP64 flops of the modal decomposition: the standard form
+    from R's side, two block-bidiagonal solves with n right-hand sides
+    (3 Bb n^2 each: the off-diagonal product 2 Bb^2 n and the triangular
+    diagonal-block product Bb^2 n per block row), the band reduction 4n^3/3;
+    with the eigenvectors also the back-transforms Q2 and Q1 (2n^3 each) and
+    V = H^{-T} Q' (3 Bb n^2).  The divide and conquer's merges (at most
+    4n^3/3, deflation dependent) and the bulge chase (O(n^2 b)) are not
+    counted."""
+    f = 6.0 * Bb * float(n) ** 2 + 4.0 / 3.0 * float(n) ** 3
+    if full:
+        f += 4.0 * float(n) ** 3 + 3.0 * Bb * float(n) ** 2
+    return f
 
 
 def run_gpu(args):
@@ -582,7 +598,7 @@ def run_gpu(args):
         "data": "synthetic",
         "config": {"workload": w.name, "N": n, "T": w.T, "thetas": list(w.thetas),
                    "dt": w.dt, "probes": w.n_probe,
-                   "decomposition": "eigenvalues and projected weights Q^T G^-1 [F, P] "
+                   "decomposition": "eigenvalues and projected weights V^T [F, P] "
                                     "(the eigenvector matrix is not formed)"},
         "cholesky_s": round(chol_s, 4),
         "speedup_modal_vs_cholesky": round(chol_s / modal_s, 3),
@@ -590,7 +606,8 @@ def run_gpu(args):
         "phases_s": {k: round(v, 4) for k, v in avg.items()},
         "modal_with_eigenvectors_s": round(avg["setup"] + avg["decompose_full"]
                                            + avg["modal_steps"], 4),
-        "decomposition_tflops": round(_decomp_flops(n) / avg["decompose_full"] / 1e12, 3),
+        "decomposition_tflops": round(_decomp_flops(n, _band_block(w.R), full=True)
+                                      / avg["decompose_full"] / 1e12, 3),
         "roofline": {"bound": "hbm", "kernel": "triangular solve pair (fwd+bwd per step)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},

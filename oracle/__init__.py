@@ -16,6 +16,8 @@ Decomposition in Numerical Computation of Eddy Current Transients"):
 * ``theta_direct``      -- the Cholesky theta-method (Sec. 3.3.1, eq. time_integration).
 * ``theta_modal``       -- the modal theta-method (Sec. 3.3.2).
 * ``modal_eigen``       -- eigenvalues and Li-normalised eigenvectors (Sec. 3.2).
+* ``time_constants``    -- the eigenvalues tau of Li v = tau Ri v as the paper writes
+                           them (Sec. 3.2), from the standard form on Ri's side.
 * ``exact_modal``       -- the decoupled modal equations of Sec. 3.2 integrated in
                            closed form over each step, waveforms linear between
                            samples (the analytical route of Sec. 3.3 left to later work).

@@ -26,6 +26,11 @@
  *                                               (Sec. 3.3.1, eq. time_integration)
  *   - the modal theta-method on the generalized eigenpairs of (Li, Ri)
  *                                               (Sec. 3.2 and Sec. 3.3.2)
+ *   - the time constants tau of Li v = tau Ri v, from the standard form on
+ *     Ri's side                                 (Sec. 3.2, eq. generalized_
+ *                                                eigenvalues_discrete)
+ *   - the Sylvester inertia of Ri - sigma Li (the number of eigenvalues
+ *     below a shift, for checks at sizes Jacobi cannot reach)
  *   - exact integration of the decoupled modal equations for inputs linear
  *     between samples (the analytical route Sec. 3.3 leaves to later work;
  *     reading r11)

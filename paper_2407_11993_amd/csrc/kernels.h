@@ -79,6 +79,38 @@ void symmetrize_from_lower(double* A, int64_t lda, int64_t n, hipStream_t s);
 void fill(double* p, int64_t count, double v, hipStream_t s);
 void fill_i64(int64_t* p, int64_t count, int64_t v, hipStream_t s);
 
+// ---- the resistance side of the pencil (band.hip) -------------------------
+// Block size (a multiple of 64, >= 64) for R's bandwidth `band`.
+int64_t band_block(int64_t band);
+// R (logical, n x n, lower band <= Bb) = H H^T with H block lower bidiagonal
+// in blocks of Bb: Hinv receives the inverses of the diagonal blocks, Hs the
+// sub-diagonal blocks (nblk = ceil(n / Bb) blocks of Bb x Bb each).  The
+// first failing pivot (local to its block) is min-ed into *d_status (left
+// INT64_MAX if none); MM_E_INVALID if an entry lies outside the band.
+int64_t band_factor_ws_elems(int Bb);
+void band_factor(const Csr& R, int64_t n, int Bb, double* Hinv, double* Hs, double* ws,
+                 int64_t ws_elems, int64_t* d_status, hipStream_t s);
+// X <- H^{-1} X and X <- H^{-T} X (X n x ncols; tmp Bb x ncols doubles),
+// X <- X H^{-T} (X nrows x n; tmp nrows x Bb doubles).
+void band_solve_left(const double* Hinv, const double* Hs, int64_t n, int Bb, double* X,
+                     int64_t ldx, int64_t ncols, double* tmp, hipStream_t s);
+void band_solve_left_t(const double* Hinv, const double* Hs, int64_t n, int Bb, double* X,
+                       int64_t ldx, int64_t ncols, double* tmp, hipStream_t s);
+void band_solve_right_t(const double* Hinv, const double* Hs, int64_t n, int Bb, double* X,
+                        int64_t ldx, int64_t nrows, double* tmp, hipStream_t s);
+// Gamma (2m x 2m) with (I + Z S Z^T)^{-1/2} = I + Z Gamma Z^T from Gz = Z^T Z,
+// S = -[[0, I_m], [I_m, 0]]; *d_bad = 1 if I + Z S Z^T is not definite.
+void lowrank_gamma(const double* Gz, int m, double* Gamma, int64_t* d_bad, hipStream_t s);
+// K = Gamma Qm Gamma / 2 (k x k, k <= 8)
+void lowrank_gqg(const double* Gamma, const double* Qm, int k, double* K, hipStream_t s);
+// From the time constants tau (ascending) and ZY (n0 x (nf + np)):
+// lam_n = 1 / tau_r, W(n, :) = tau_r^{-1/2} ZY(r, :nf), P(n, :) likewise, r = n0-1-n.
+void modes_from_tau(const double* tau, const double* ZY, int64_t n0, int nf, int np,
+                    double* lam, double* W, double* P, hipStream_t s);
+// In place: X(:, n) <- tau_r^{-1/2} X(:, r), r = n0-1-n; lam_n = 1 / tau_r.
+void reverse_scale_cols(double* X, int64_t ld, int64_t n0, const double* tau, double* lam,
+                        hipStream_t s);
+
 // ---- electrode reduction (electrode.hip) ----------------------------------
 // Householder QR of E^T for the m x n electrode matrix E (CSR, m <= 8):
 // E^T = H [Re; 0] with H = H_0 ... H_{m-1} = I - V T V^T.  Writes V (n x m,

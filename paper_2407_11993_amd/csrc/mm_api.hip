@@ -52,6 +52,7 @@ struct Dev {
 };
 
 constexpr int kBand = 64;         // bandwidth of the first tridiagonalisation stage
+constexpr int kMaxBandBlock = 8192;  // largest block of R's banded factor
 constexpr int kMaxColumns = 4096;  // sources, probes
 constexpr int kMaxRunColumns = 8;  // forcing columns and probes of one stepping call
 
@@ -486,34 +487,48 @@ void mark(mm_ctx* c, const char* what) {
   std::fflush(stderr);
 }
 
-// a0-a8.  project: eigenvalues and the projected forcing and probe weights
-// only, the eigenvector matrix Q = Q1 Q2 Z never formed (Q^T Y = Z^T Q2^T Q1^T Y
-// applied to the few columns Y = G^{-1} [F, P] on the way through the band
-// reduction and the bulge chase).
+// a0-a8 with the standard form taken on the resistance side, as the paper
+// writes the eigenproblem (Sec. 3.2, eq. generalized_eigenvalues_discrete:
+// Li v = tau Ri v).  Ri = R'' - V Y^T - Y V^T (R'' = R[m:, m:], sparse and
+// banded; the electrode term of rank 2m) factors as F F^T with
+// F = H A^{1/2}, R'' = H H^T (block bidiagonal, band.hip) and
+// A = I + Z S Z^T, Z = H^{-1} [V, Y]; A^{-1/2} = I + Z Gamma Z^T.  Then
+// C' = F^{-1} Li F^{-T} = A^{-1/2} (H^{-1} Li H^{-T}) A^{-1/2} has the time
+// constants tau as eigenvalues, and with C' = Q' T Q'^T the pencil's
+// Li-normalised eigenvectors are V = F^{-T} Q' T^{-1/2} (V^T Li V = I,
+// V^T Ri V = T^{-1}), ordered by ascending lam = 1 / tau.  No dense
+// factorisation of L is needed: the standard form costs 4 n0^2 Bb flops.
+// project: eigenvalues and the projected weights V^T [F, P] only (Q' applied
+// to the few columns F^{-1} [F, P] on the way through the eigensolver).
 void decompose_impl(mm_ctx* c, bool project) {
     hipStream_t s = c->stream;
     const int64_t n0 = c->n0;
+    const int m = (int)c->m;
     const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(kBand, n0 - 1));
     const int ny = c->nf + c->n_probe;
     MM_REQUIRE(!project || ny <= sb2st_max_cols(), kInvalid,
                "mm_decompose_projected: at most 32 forcing and probe columns in all "
                "(use mm_decompose)");
+    const int Bb = (int)band_block(c->band);
+    MM_REQUIRE(Bb <= kMaxBandBlock, kInvalid,
+               "R's bandwidth exceeds 8192: number the unknowns so that R is banded "
+               "(a grid's natural order, or a bandwidth-reducing order)");
+    const int64_t nblk = ceil_div(n0, (int64_t)Bb);
     c->decomposed = false;
     c->has_V = false;
     c->selected = false;
     c->t_mark = std::chrono::steady_clock::now();
-    // Buffers in the order they are needed, released as soon as they are not
-    // (at N = 98,304 one n0^2 buffer is 77 GB: at most three live at once).
-    // The small buffers of the eigensolver are allocated first: an
-    // allocation that has to reuse memory just freed by another one of this
-    // size can take seconds.
     c->Q.release();
     c->V.release();
+    c->G.release();
+    // The small buffers first (an allocation that has to reuse memory just
+    // freed by a large one of the same size can take seconds); at N = 98,304
+    // one n0^2 buffer is 77 GB, and at most two and a half are live.
     const int64_t wse = eig_ws_elems(n0, nb, project);
-    Dev Cb, ws, GFP;
-    ws.alloc(sizeof(double) * std::max(wse, potrf_ws_elems(n0)));
+    Dev Cb, ws, Hinv, Hs, tmp, Zh, small, Yc, ZY, tau;
+    ws.alloc(sizeof(double) * std::max(wse, band_factor_ws_elems(Bb)));
     Sb2stPlan plan = sb2st_plan(n0, nb);
-    Dev tau1, T1, AB, V2, tau2, off, dv, ev, ZY;
+    Dev tau1, T1, AB, V2, tau2, off, dv, ev;
     const int64_t np = std::max<int64_t>(1, sy2sb_npanels(n0, nb));
     tau1.alloc(sizeof(double) * np * nb);
     T1.alloc(sizeof(double) * np * nb * nb);
@@ -521,104 +536,149 @@ void decompose_impl(mm_ctx* c, bool project) {
     off.alloc(sizeof(int64_t) * (n0 + 1));
     dv.alloc(sizeof(double) * n0);
     ev.alloc(sizeof(double) * std::max<int64_t>(1, n0));
+    tau.alloc(sizeof(double) * n0);
+    Hinv.alloc(sizeof(double) * nblk * Bb * Bb);
+    Hs.alloc(sizeof(double) * nblk * Bb * Bb);
+    tmp.alloc(sizeof(double) * (int64_t)Bb * std::max<int64_t>(n0, ny));
     if (project) {
+      Yc.alloc(sizeof(double) * n0 * ny);
       ZY.alloc(sizeof(double) * n0 * ny);
-      GFP.alloc(sizeof(double) * n0 * ny);
     }
-    c->G.alloc(sizeof(double) * n0 * n0);
+    const int k2 = 2 * m;
+    if (m > 0) {
+      Zh.alloc(sizeof(double) * n0 * 5 * k2);   // [Z | U2 | Z] and P = X Z
+      small.alloc(sizeof(double) * 4 * 64 + 8);  // Gz, Gamma, Qm, K, bad flag
+    }
     c->lam.alloc(sizeof(double) * n0);
     c->Wm.alloc(sizeof(double) * n0 * std::max(1, c->nf));
     c->Pm.alloc(sizeof(double) * n0 * c->n_probe);
     c->y.alloc(sizeof(double) * n0);
-    double* G = c->G.d();
     int64_t* st = c->status.as<int64_t>();
-    // a0, a1: L_i (lower triangle);  a2: L_i = G G^T  (Ne = 0: L_i = L)
-    const int m = (int)c->m;
-    assemble_L(c->lsrc(m), n0, G, n0, false, s, c->lr(0.0));
-    factor_checked(G, n0, st, ws, s, "L");
-    mark(c, "Cholesky factorisation of L_i");
-    // a3: C = G^{-1} R G^{-T}:  G <- G^{-1};  W = G^{-1} R (in Q);  C = G^{-1} W^T
+    // a2': R'' = H H^T
+    band_factor(c->R(), n0, Bb, Hinv.d(), Hs.d(), ws.d(),
+                std::max(wse, band_factor_ws_elems(Bb)), st, s);
     {
-      Dev tws;
-      tws.alloc(sizeof(double) * trtri_ws_elems(n0));
-      trtri_lower(G, n0, n0, tws.d(), trtri_ws_elems(n0), s);
+      int64_t piv = INT64_MAX;
+      MM_HIP_TRY(hipMemcpyAsync(&piv, st, sizeof(int64_t), hipMemcpyDeviceToHost, s));
       MM_HIP_TRY(hipStreamSynchronize(s));
+      if (piv != INT64_MAX)
+        throw Error{kNotSpd, "R (its block of the unknowns without the excluded electrode "
+                             "rows) is not positive definite"};
     }
-    c->Q.alloc(sizeof(double) * n0 * n0);  // W = G^{-1} R here, later the eigenvectors
-    double* Q = c->Q.d();
-    dense_times_csr(G, n0, c->R(), Q, n0, s);
-    // C's columns start on 128-byte boundaries (n0 is odd at the electrode
-    // plates): the band reduction reads C's lower triangle also row-wise, in
-    // 128-byte pieces of many columns, which would otherwise straddle lines
+    mark(c, "banded Cholesky factorisation of R''");
+    // a0, a1: Li, both triangles, in C's storage.  C's columns start on
+    // 128-byte boundaries (n0 is odd at the electrode plates): the band
+    // reduction reads C's lower triangle also row-wise, in 128-byte pieces
+    // of many columns, which would otherwise straddle lines
     const int64_t ldC = ceil_div(n0, 16) * 16;
     Cb.alloc(sizeof(double) * ldC * n0);
     double* C = Cb.d();
-    {
-      Gemm g;
-      g.m = n0; g.n = n0; g.k = n0;
-      g.A = G; g.lda = n0; g.a_lower = true;
-      g.B = Q; g.ldb = n0; g.tb = true; g.b_band = c->band;
-      g.C = C; g.ldc = ldC;
-      g.lower = true;
-      gemm(g, s);
-    }
+    assemble_L(c->lsrc(m), n0, C, ldC, true, s, c->lr(0.0));
+    // a3': X = H^{-1} Li H^{-T}
+    band_solve_left(Hinv.d(), Hs.d(), n0, Bb, C, ldC, n0, tmp.d(), s);
+    band_solve_right_t(Hinv.d(), Hs.d(), n0, Bb, C, ldC, n0, tmp.d(), s);
+    double* Z = nullptr;
+    double* Gamma = nullptr;
     if (m > 0) {
-      // low-rank part of R_i = R[m:, m:] - V Y^T - Y V^T:
-      // C -= A B^T + B A^T with A = G^{-1} V, B = G^{-1} Y, as one rank-2m product
-      Dev ABA;
-      ABA.alloc(sizeof(double) * n0 * 3 * m);
-      const double* src[2] = {c->Vh.d() + m, c->YR.d() + m};
-      for (int q = 0; q < 2; ++q) {
-        Gemm g;
-        g.m = n0; g.n = m; g.k = n0;
-        g.A = G; g.lda = n0; g.a_lower = true;
-        g.B = src[q]; g.ldb = c->n;
-        g.C = ABA.d() + (int64_t)q * m * n0; g.ldc = n0;
+      // Z = H^{-1} [V, Y] (rows m.. of the Householder vectors and of YR)
+      Z = Zh.d();
+      double* U2 = Z + n0 * k2;
+      double* P = Z + 3 * n0 * k2;
+      double* Gz = small.d();
+      Gamma = Gz + 64;
+      double* Qm = Gz + 128;
+      double* K = Gz + 192;
+      int64_t* bad = reinterpret_cast<int64_t*>(Gz + 256);
+      copy_matrix(c->Vh.d() + m, c->n, Z, n0, n0, m, s);
+      copy_matrix(c->YR.d() + m, c->n, Z + n0 * m, n0, n0, m, s);
+      band_solve_left(Hinv.d(), Hs.d(), n0, Bb, Z, n0, k2, tmp.d(), s);
+      {
+        Gemm g;  // Gz = Z^T Z
+        g.m = k2; g.n = k2; g.k = n0;
+        g.A = Z; g.lda = n0; g.ta = true;
+        g.B = Z; g.ldb = n0;
+        g.C = Gz; g.ldc = k2;
         gemm(g, s);
       }
-      copy_matrix(ABA.d(), n0, ABA.d() + (int64_t)2 * m * n0, n0, n0, m, s);
+      fill_i64(bad, 1, 0, s);
+      lowrank_gamma(Gz, m, Gamma, bad, s);
+      {
+        Gemm g;  // P = X Z (X symmetric, both triangles present)
+        g.m = n0; g.n = k2; g.k = n0;
+        g.A = C; g.lda = ldC;
+        g.B = Z; g.ldb = n0;
+        g.C = P; g.ldc = n0;
+        gemm(g, s);
+      }
+      {
+        Gemm g;  // Qm = Z^T P
+        g.m = k2; g.n = k2; g.k = n0;
+        g.A = Z; g.lda = n0; g.ta = true;
+        g.B = P; g.ldb = n0;
+        g.C = Qm; g.ldc = k2;
+        gemm(g, s);
+      }
+      lowrank_gqg(Gamma, Qm, k2, K, s);
+      {
+        Gemm g;  // U2 = P Gamma
+        g.m = n0; g.n = k2; g.k = k2;
+        g.A = P; g.lda = n0;
+        g.B = Gamma; g.ldb = k2;
+        g.C = U2; g.ldc = n0;
+        gemm(g, s);
+      }
+      {
+        Gemm g;  // U2 += Z K
+        g.m = n0; g.n = k2; g.k = k2;
+        g.beta = 1.0;
+        g.A = Z; g.lda = n0;
+        g.B = K; g.ldb = k2;
+        g.C = U2; g.ldc = n0;
+        gemm(g, s);
+      }
+      // C' = X + Z U2^T + U2 Z^T (lower triangle): [Z | U2] [U2 | Z]^T
+      copy_matrix(Z, n0, U2 + n0 * k2, n0, n0, k2, s);
       Gemm g;
-      g.m = n0; g.n = n0; g.k = 2 * m;
-      g.alpha = -1.0; g.beta = 1.0;
-      g.A = ABA.d(); g.lda = n0;
-      g.B = ABA.d() + (int64_t)m * n0; g.ldb = n0; g.tb = true;
+      g.m = n0; g.n = n0; g.k = 2 * k2;
+      g.beta = 1.0;
+      g.A = Z; g.lda = n0;
+      g.B = U2; g.ldb = n0; g.tb = true;
       g.C = C; g.ldc = ldC;
       g.lower = true;
       gemm(g, s);
-      MM_HIP_TRY(hipStreamSynchronize(s));  // ABA is released here
-    }
-    mark(c, "standard form C");
-    // G^{-1} applied to the forcing columns and the probe weights, side by side
-    double* GF = project ? GFP.d() : nullptr;
-    double* GP = project ? GFP.d() + (int64_t)c->nf * n0 : nullptr;
-    if (project && c->nf > 0) {
-      Gemm g;
-      g.m = n0; g.n = c->nf; g.k = n0;
-      g.A = G; g.lda = n0; g.a_lower = true;
-      g.B = c->F.d(); g.ldb = n0;
-      g.C = GF; g.ldc = n0;
-      gemm(g, s);
-    }
-    if (project) {
-      Gemm g;
-      g.m = n0; g.n = c->n_probe; g.k = n0;
-      g.A = G; g.lda = n0; g.a_lower = true;
-      g.B = c->Pt.d(); g.ldb = n0;
-      g.C = GP; g.ldc = n0;
-      gemm(g, s);
-      // neither G^{-1} nor W is needed again without the eigenvector matrix
+      int64_t nbad = 0;
+      MM_HIP_TRY(hipMemcpyAsync(&nbad, bad, sizeof(int64_t), hipMemcpyDeviceToHost, s));
       MM_HIP_TRY(hipStreamSynchronize(s));
-      c->Q.release();
-      c->G.release();
-      Q = nullptr;
-    } else {
-      // W is dead (Q's storage receives the eigenvectors); G^{-1} is formed
-      // again after the eigensolver rather than held through it, so that at
-      // most three n0^2 buffers are live at any time
-      MM_HIP_TRY(hipStreamSynchronize(s));
-      c->G.release();
+      MM_REQUIRE(nbad == 0, kNotSpd, "the reduced resistance R_i is not positive definite");
     }
-    // a4-a7: C = Q Lam Q^T
+    mark(c, "standard form C' = F^{-1} L_i F^{-T}");
+    // F^{-1} Y = A^{-1/2} H^{-1} Y for a few columns Y: H^{-1}, then
+    // Y += Z (Gamma (Z^T Y)); the product buffer is the low-rank area's P
+    auto apply_finv = [&](double* Y, int64_t ldy, int64_t cols) {
+      band_solve_left(Hinv.d(), Hs.d(), n0, Bb, Y, ldy, cols, tmp.d(), s);
+      if (m == 0 || cols == 0) return;
+      double* t1 = tmp.d();             // k2 x cols
+      double* t2 = tmp.d() + k2 * cols;  // k2 x cols
+      Gemm g1;
+      g1.m = k2; g1.n = cols; g1.k = n0;
+      g1.A = Z; g1.lda = n0; g1.ta = true;
+      g1.B = Y; g1.ldb = ldy;
+      g1.C = t1; g1.ldc = k2;
+      gemm(g1, s);
+      Gemm g2;
+      g2.m = k2; g2.n = cols; g2.k = k2;
+      g2.A = Gamma; g2.lda = k2;
+      g2.B = t1; g2.ldb = k2;
+      g2.C = t2; g2.ldc = k2;
+      gemm(g2, s);
+      Gemm g3;
+      g3.m = n0; g3.n = cols; g3.k = k2;
+      g3.beta = 1.0;
+      g3.A = Z; g3.lda = n0;
+      g3.B = t2; g3.ldb = k2;
+      g3.C = Y; g3.ldc = ldy;
+      gemm(g3, s);
+    };
     if (!project) {  // the bulge-chase reflectors, kept for the back-transform
       V2.alloc(sizeof(double) * std::max<int64_t>(1, plan.tasks) * nb);
       tau2.alloc(sizeof(double) * std::max<int64_t>(1, plan.tasks));
@@ -635,43 +695,52 @@ void decompose_impl(mm_ctx* c, bool project) {
     w.mark = [c](const char* what) { mark(c, what); };
     fill_i64(st + 1, 1, 0, s);
     if (project) {
-      // a4-a8 without Q: [W, Pt] = Z^T Q2^T Q1^T G^{-1} [F, P]
-      syevd_project(C, ldC, n0, c->lam.d(), GFP.d(), n0, ny, ZY.d(), n0, w, plan, st + 1, s);
-      if (c->nf > 0) copy_matrix(ZY.d(), n0, c->Wm.d(), n0, n0, c->nf, s);
-      copy_matrix(ZY.d() + (int64_t)c->nf * n0, n0, c->Pm.d(), n0, n0, c->n_probe, s);
-      MM_HIP_TRY(hipStreamSynchronize(s));  // ZY is released here
+      // a8 without Q': F^{-1} [F, P], then Q'^T on the way through
+      if (c->nf > 0) copy_matrix(c->F.d(), n0, Yc.d(), n0, n0, c->nf, s);
+      copy_matrix(c->Pt.d(), n0, Yc.d() + (int64_t)c->nf * n0, n0, n0, c->n_probe, s);
+      apply_finv(Yc.d(), n0, ny);
+      syevd_project(C, ldC, n0, tau.d(), Yc.d(), n0, ny, ZY.d(), n0, w, plan, st + 1, s);
+      modes_from_tau(tau.d(), ZY.d(), n0, c->nf, c->n_probe, c->lam.d(), c->Wm.d(),
+                     c->Pm.d(), s);
     } else {
-      // a4-a7: Q = Q1 Q2 Z in Q's storage (C's storage is the merges' scratch)
-      syevd(C, ldC, n0, c->lam.d(), Q, n0, w, plan, st + 1, s);
+      // a4-a7: Q' in Q's storage (C's storage is the merges' scratch)
+      c->Q.alloc(sizeof(double) * n0 * n0);
+      double* Q = c->Q.d();
+      syevd(C, ldC, n0, tau.d(), Q, n0, w, plan, st + 1, s);
       MM_HIP_TRY(hipStreamSynchronize(s));
       V2.release();
       tau2.release();
-      // G^{-1} again, in C's storage (L_i's Cholesky factor and its inverse)
-      double* Gi = C;
-      assemble_L(c->lsrc(m), n0, Gi, n0, false, s, c->lr(0.0));
-      factor_checked(Gi, n0, st, ws, s, "L");
-      {
-        Dev tws;
-        tws.alloc(sizeof(double) * trtri_ws_elems(n0));
-        trtri_lower(Gi, n0, n0, tws.d(), trtri_ws_elems(n0), s);
-        MM_HIP_TRY(hipStreamSynchronize(s));
-      }
-      mark(c, "inverse factor G^{-1} again");
-      // V = G^{-T} Q: the pencil's eigenvectors, V^T L_i V = I, V^T R_i V = Lam
-      c->V.alloc(sizeof(double) * n0 * n0);
-      {
-        Gemm g;
-        g.m = n0; g.n = n0; g.k = n0;
-        g.A = Gi; g.lda = n0; g.ta = true; g.a_upper = true;
-        g.B = Q; g.ldb = n0;
-        g.C = c->V.d(); g.ldc = n0;
-        gemm(g, s);
-      }
-      mark(c, "eigenvectors V = G^{-T} Q");
-      MM_HIP_TRY(hipStreamSynchronize(s));
       Cb.release();
-      c->Q.release();
-      Q = nullptr;
+      // V = F^{-T} Q' T^{-1/2} = H^{-T} (Q' + Z Gamma (Z^T Q')) T^{-1/2}, columns
+      // in ascending lam
+      if (m > 0) {
+        double* t1 = tmp.d();
+        double* t2 = tmp.d() + k2 * n0;
+        Gemm g1;
+        g1.m = k2; g1.n = n0; g1.k = n0;
+        g1.A = Z; g1.lda = n0; g1.ta = true;
+        g1.B = Q; g1.ldb = n0;
+        g1.C = t1; g1.ldc = k2;
+        gemm(g1, s);
+        Gemm g2;
+        g2.m = k2; g2.n = n0; g2.k = k2;
+        g2.A = Gamma; g2.lda = k2;
+        g2.B = t1; g2.ldb = k2;
+        g2.C = t2; g2.ldc = k2;
+        gemm(g2, s);
+        Gemm g3;
+        g3.m = n0; g3.n = n0; g3.k = k2;
+        g3.beta = 1.0;
+        g3.A = Z; g3.lda = n0;
+        g3.B = t2; g3.ldb = k2;
+        g3.C = Q; g3.ldc = n0;
+        gemm(g3, s);
+      }
+      band_solve_left_t(Hinv.d(), Hs.d(), n0, Bb, Q, n0, n0, tmp.d(), s);
+      reverse_scale_cols(Q, n0, n0, tau.d(), c->lam.d(), s);
+      std::swap(c->V.p, c->Q.p);
+      std::swap(c->V.bytes, c->Q.bytes);
+      mark(c, "eigenvectors V = F^{-T} Q' T^{-1/2}");
       // a8: modal weights  W = V^T F,  Pt = V^T P
       if (c->nf > 0) {
         Gemm g;

@@ -90,7 +90,13 @@ def test_plate_vs_oracle(orc, nx, ny, crack):
     if crack is None:
         assert np.max(np.abs(lam - ref_lam) / ref_lam) < 1e-10
     else:
-        assert np.abs(lam - ref_lam).max() < 1e-10 * ref_lam.max()
+        # high contrast (kappa ~ 2.5e7): backward-stable solvers fix the
+        # eigenvalues norm-wise in the variable of their standard form; the
+        # library's is the paper's tau (Li v = tau Ri v, from Ri's side), so
+        # it is compared with the oracle's time constants, norm-wise in tau
+        tau = 1.0 / lam  # descending, as the oracle returns them
+        tau_ref = orc.time_constants(pb)
+        assert np.abs(tau - tau_ref).max() < 1e-10 * tau_ref.max()
     for theta in (0.5, 1.0):
         s.reset()
         ref = orc.theta_direct(pb, theta, 1.0, w.T, w.i_src)
