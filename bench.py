@@ -159,7 +159,8 @@ def run_electrodes(args):
     t0 = time.perf_counter()
     while len(runs) < args.steps:
         if walls:
-            left = args.budget_s - (time.perf_counter() - T_START) - args.cpu_reserve_s
+            reserve = 0.0 if args.no_cpu_baseline else args.cpu_reserve_s
+            left = args.budget_s - (time.perf_counter() - T_START) - reserve
             if left < 1.1 * max(walls):
                 break
         ts = time.perf_counter()
