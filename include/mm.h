@@ -86,8 +86,8 @@ typedef struct {
                                stay valid and unchanged until mm_destroy.  xyz
                                and h are then ignored.  It costs 8 n^2 bytes of
                                device memory beside the library's own buffers
-                               (the projected decomposition peaks at three
-                               n0^2 buffers). */
+                               (the projected decomposition holds one n0^2
+                               buffer). */
   int64_t ldl;              /* leading dimension of L, >= n */
 } mm_problem;
 
@@ -101,25 +101,31 @@ typedef struct {
  * 2 (Ne - 1) + n_src > 8. */
 mm_status mm_setup(const mm_problem* problem, void* stream, mm_ctx** out);
 
-/* The one-off modal decomposition (Sec. 3.2): Li = G G^T, C = G^{-1} Ri G^{-T},
- * C = Q Lam Q^T (two-stage tridiagonalisation + divide and conquer), the
- * pencil's eigenvectors V = G^{-T} Q (V^T Li V = I, V^T Ri V = Lam, the V_n of
- * eq. modal_decomposition_discrete) and the projections V^T [F, P] of the
- * sources and probes onto the modes.  Independent of theta and dt.  Device
- * memory: at most three n0^2 buffers at any time (G^{-1} is formed twice,
- * once for C and once for V, rather than held through the eigensolver); only
- * V (n0^2) is kept afterwards.  Synchronises the stream.  Errors:
- * MM_E_NOT_SPD (Li not positive definite), MM_E_NO_CONVERGE, MM_E_NOMEM. */
+/* The one-off modal decomposition (Sec. 3.2, eq. generalized_eigenvalues_
+ * discrete: Li v = tau Ri v, lam = 1 / tau), taken from the resistance side:
+ * Ri = F F^T with F = H A^{1/2}, H the banded (block-bidiagonal) Cholesky
+ * factor of R's block of the kept unknowns and A = I + Z S Z^T the electrodes'
+ * low-rank correction; C' = F^{-1} Li F^{-T} = Q' T Q'^T (two-stage
+ * tridiagonalisation + divide and conquer); the pencil's Li-normalised
+ * eigenvectors V = F^{-T} Q' T^{-1/2} (V^T Li V = I, V^T Ri V = Lam, the V_n of
+ * eq. modal_decomposition_discrete), columns by ascending lam, and the
+ * projections V^T [F, P] of the sources and probes onto the modes.  No dense
+ * factorisation of L.  Independent of theta and dt.  Device memory: at most
+ * two and a half n0^2 buffers at any time (C', then Q' beside it while the
+ * merges use C's storage); only V (n0^2) is kept afterwards.  Synchronises the
+ * stream.  Errors: MM_E_INVALID when R's bandwidth in the given numbering
+ * exceeds 8192; MM_E_NOT_SPD when R's block or Ri is not positive definite,
+ * or Li is not (a time constant <= 0); MM_E_NO_CONVERGE; MM_E_NOMEM. */
 mm_status mm_decompose(mm_ctx* ctx);
 
 /* The decomposition as the modal signals need it (Sec. 3.2 feeding Sec. 3.3.2):
- * the eigenvalues and the projected source and probe weights Q^T G^{-1} [F, P],
- * without forming the eigenvector matrix Q.  Q = Q1 Q2 Z is applied to the
- * few columns only: Q1^T panel by panel after the band reduction, Q2^T by
- * every bulge-chase task as it generates its reflector, Z^T by one product
- * after divide and conquer.  Afterwards mm_step_modal, mm_eigenvalues and
- * mm_batch_* work as after mm_decompose; mm_probe(MM_MODAL) and
- * mm_adjoint_modal return MM_E_STATE (they need Q).  Synchronises the
+ * the eigenvalues and the projected source and probe weights
+ * T^{-1/2} Q'^T F^{-1} [F, P], without forming the eigenvector matrix Q'.
+ * Q' = Q1 Q2 Z is applied to the few columns only: Q1^T panel by panel after
+ * the band reduction, Q2^T by every bulge-chase task as it generates its
+ * reflector, Z^T by one product after divide and conquer.  Afterwards
+ * mm_step_modal, mm_eigenvalues and mm_batch_* work as after mm_decompose;
+ * mm_probe(MM_MODAL) and mm_adjoint_modal return MM_E_STATE (they need V).  Synchronises the
  * stream.  Errors: those of mm_decompose; MM_E_INVALID when the forcing
  * columns (2 (Ne-1) + n_src) and the probes exceed 32 in all. */
 mm_status mm_decompose_projected(mm_ctx* ctx);

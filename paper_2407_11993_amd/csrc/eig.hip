@@ -12,7 +12,10 @@ namespace {
 // many doubles (2 GiB)
 constexpr int64_t kQ2WsCap = (int64_t)1 << 28;
 
-__global__ void extract_v_k(const double* P, int64_t ldp, int64_t m, int nb, double* V) {
+// V(:, c) (m rows, leading dimension ldv) = column c of the panel's
+// reflectors: unit diagonal, zero above it.
+__global__ void extract_v_k(const double* P, int64_t ldp, int64_t m, int nb, double* V,
+                            int64_t ldv) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= m * nb) return;
   const int64_t i = e % m;
@@ -20,13 +23,22 @@ __global__ void extract_v_k(const double* P, int64_t ldp, int64_t m, int nb, dou
   double v = 0.0;
   if (i == c) v = 1.0;
   else if (i > c) v = P[i + (int64_t)c * ldp];
-  V[e] = v;
+  V[i + c * ldv] = v;
 }
 
 }  // namespace
 
+// Q1 is applied in groups of up to Q1G panels: H_p H_{p+1} ... H_{p+g-1} =
+// I - Vg Tg Vg^T with Vg = [V_p ... V_{p+g-1}] on the group's common rows
+// (V_{p+j} zero above its own first row) and Tg upper triangular, built one
+// panel at a time (Schreiber & Van Loan's compact WY aggregation):
+//   Tg <- [[Tg, -Tg (Vg^T V_j) T_j], [0, T_j]],
+// so the products with Z have depth g nb instead of nb.
+constexpr int Q1G = 4;
+
 int64_t apply_q1_ws_elems(int64_t n, int nb, int64_t ncols) {
-  return n * nb + 2 * nb * ncols + 8 * nb * ncols;
+  const int64_t kg = (int64_t)Q1G * nb;
+  return n * kg + 2 * kg * ncols + 8 * kg * ncols + 3 * kg * kg;
 }
 
 void apply_q1(const double* A, int64_t lda, int64_t n, int nb, const double* T_all, double* Z,
@@ -34,38 +46,78 @@ void apply_q1(const double* A, int64_t lda, int64_t n, int nb, const double* T_a
   MM_REQUIRE(ws_elems >= apply_q1_ws_elems(n, nb, ncols), kInvalid,
              "apply_q1: workspace too small");
   const int64_t np = sy2sb_npanels(n, nb);
-  double* V = ws;                       // m x nb
-  double* W = V + n * nb;               // nb x ncols
-  double* W2 = W + nb * ncols;          // nb x ncols
-  double* split = W2 + nb * ncols;
-  const int64_t split_elems = 8 * nb * ncols;
-  for (int64_t p = np - 1; p >= 0; --p) {
-    const int64_t j = p * nb, r0 = j + nb, m = n - r0;
-    const double* P = A + r0 + j * lda;
-    hipLaunchKernelGGL(extract_v_k, dim3((unsigned)ceil_div(m * nb, 256)), dim3(256), 0, s, P,
-                       lda, m, nb, V);
+  const int64_t kg = (int64_t)Q1G * nb;
+  double* V = ws;                       // m x kg (the group's reflectors)
+  double* W = V + n * kg;               // kg x ncols
+  double* W2 = W + kg * ncols;          // kg x ncols
+  double* split = W2 + kg * ncols;
+  const int64_t split_elems = 8 * kg * ncols;
+  double* S = split + split_elems;      // kg x kg:  Vg^T Vg
+  double* Tg = S + kg * kg;             // kg x kg
+  double* Tw = Tg + kg * kg;            // kg x nb scratch
+  // groups from the last panel down: group [p0, p0 + g)
+  for (int64_t p1 = np; p1 > 0;) {
+    const int64_t g = std::min<int64_t>(Q1G, p1);
+    const int64_t p0 = p1 - g;
+    p1 = p0;
+    const int64_t r0 = (p0 + 1) * nb, m = n - r0;  // the group's common rows
+    const int64_t kk = g * nb;
+    fill(V, m * kk, 0.0, s);
+    for (int64_t q = 0; q < g; ++q) {
+      const int64_t p = p0 + q, j = p * nb, rq = (p + 1) * nb, mq = n - rq;
+      const double* P = A + rq + j * lda;
+      hipLaunchKernelGGL(extract_v_k, dim3((unsigned)ceil_div(mq * nb, 256)), dim3(256), 0, s, P,
+                         lda, mq, nb, V + (rq - r0) + q * nb * m, m);
+    }
     MM_HIP_TRY(hipGetLastError());
-    const double* T = T_all + p * (int64_t)nb * nb;
-    // W = V^T Z(r0:, :)
+    // Tg: the diagonal blocks are the panels' T, the others from S = Vg^T Vg
+    fill(Tg, kk * kk, 0.0, s);
+    for (int64_t q = 0; q < g; ++q)
+      copy_matrix(T_all + (p0 + q) * (int64_t)nb * nb, nb, Tg + q * nb * (kk + 1), kk, nb, nb, s);
+    if (g > 1) {
+      Gemm gs;  // S = Vg^T Vg (only its strictly upper blocks are read)
+      gs.m = kk; gs.n = kk; gs.k = m;
+      gs.A = V; gs.lda = m; gs.ta = true;
+      gs.B = V; gs.ldb = m;
+      gs.C = S; gs.ldc = kk;
+      gemm(gs, s, split, split_elems);
+      for (int64_t q = 1; q < g; ++q) {
+        const int64_t c0 = q * nb;
+        Gemm ga;  // Tw = Tg[0:c0, 0:c0] S[0:c0, c0:c0+nb]   (Tg upper)
+        ga.m = c0; ga.n = nb; ga.k = c0;
+        ga.A = Tg; ga.lda = kk; ga.a_upper = true;
+        ga.B = S + c0 * kk; ga.ldb = kk;
+        ga.C = Tw; ga.ldc = kk;
+        gemm(ga, s);
+        Gemm gb;  // Tg[0:c0, c0:c0+nb] = -Tw T_q   (T_q upper: op(B)(k, j) = 0 for k > j)
+        gb.m = c0; gb.n = nb; gb.k = nb;
+        gb.alpha = -1.0;
+        gb.A = Tw; gb.lda = kk;
+        gb.B = Tg + c0 * (kk + 1); gb.ldb = kk; gb.b_band = 0;
+        gb.C = Tg + c0 * kk; gb.ldc = kk;
+        gemm(gb, s);
+      }
+    }
+    // W = Vg^T Z(r0:, :)
     Gemm g1;
-    g1.m = nb; g1.n = ncols; g1.k = m;
+    g1.m = kk; g1.n = ncols; g1.k = m;
     g1.A = V; g1.lda = m; g1.ta = true;
     g1.B = Z + r0; g1.ldb = ldz;
-    g1.C = W; g1.ldc = nb;
+    g1.C = W; g1.ldc = kk;
     gemm(g1, s, split, split_elems);
-    // W2 = T W   (T upper: op(A)(i,k) = 0 for k < i)
+    // W2 = Tg W   (Tg upper: op(A)(i,k) = 0 for k < i)
     Gemm g2;
-    g2.m = nb; g2.n = ncols; g2.k = nb;
-    g2.A = T; g2.lda = nb; g2.a_upper = true;
-    g2.B = W; g2.ldb = nb;
-    g2.C = W2; g2.ldc = nb;
+    g2.m = kk; g2.n = ncols; g2.k = kk;
+    g2.A = Tg; g2.lda = kk; g2.a_upper = true;
+    g2.B = W; g2.ldb = kk;
+    g2.C = W2; g2.ldc = kk;
     gemm(g2, s);
-    // Z(r0:, :) -= V W2
+    // Z(r0:, :) -= Vg W2
     Gemm g3;
-    g3.m = m; g3.n = ncols; g3.k = nb;
+    g3.m = m; g3.n = ncols; g3.k = kk;
     g3.alpha = -1.0; g3.beta = 1.0;
     g3.A = V; g3.lda = m;
-    g3.B = W2; g3.ldb = nb;
+    g3.B = W2; g3.ldb = kk;
     g3.C = Z + r0; g3.ldc = ldz;
     gemm(g3, s);
   }
@@ -85,7 +137,7 @@ void apply_q1t(const double* A, int64_t lda, int64_t n, int nb, const double* T_
     const int64_t j = p * nb, r0 = j + nb, m = n - r0;
     const double* P = A + r0 + j * lda;
     hipLaunchKernelGGL(extract_v_k, dim3((unsigned)ceil_div(m * nb, 256)), dim3(256), 0, s, P,
-                       lda, m, nb, V);
+                       lda, m, nb, V, m);
     MM_HIP_TRY(hipGetLastError());
     const double* T = T_all + p * (int64_t)nb * nb;
     // W = V^T Y(r0:, :)

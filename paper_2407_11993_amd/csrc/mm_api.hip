@@ -761,10 +761,17 @@ void decompose_impl(mm_ctx* c, bool project) {
     }
     fill(c->y.d(), n0, 0.0, s);
     int64_t est = 0;
+    double tau_min = 0.0;  // the eigenvalues of C' ascend
     MM_HIP_TRY(hipMemcpyAsync(&est, st + 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    MM_HIP_TRY(hipMemcpyAsync(&tau_min, tau.d(), sizeof(double), hipMemcpyDeviceToHost, s));
     MM_HIP_TRY(hipStreamSynchronize(s));
     MM_HIP_TRY(hipGetLastError());
     if (est != 0) throw Error{kNoConverge, "a secular equation did not converge"};
+    // C' is congruent to Li, so a time constant <= 0 means Li is not
+    // positive definite (a dense L handed over by the caller can be anything)
+    if (!(tau_min > 0.0))
+      throw Error{kNotSpd, "the reduced inductance L_i is not positive definite (smallest "
+                           "time constant " + std::to_string(tau_min) + ")"};
     c->decomposed = true;
     c->has_V = !project;
 }

@@ -154,3 +154,22 @@ def test_non_finite_dt_is_rejected():
                                                        device="cuda"))
     assert ei.value.code == 1
     s.close()
+
+
+def test_indefinite_L_is_rejected(orc):
+    """A borrowed L with a negative direction: the time constants of
+    Li v = tau Ri v are then not all positive, and the decomposition reports
+    MM_E_NOT_SPD rather than returning negative or infinite eigenvalues."""
+    from paper_2407_11993_amd import Solver, _lib
+    w = inputs.plate(8, 9, seed=4, T=10)
+    L = orc.assemble_L(w.xyz, w.h)
+    u = np.random.default_rng(5).standard_normal(w.n)
+    u /= np.linalg.norm(u)
+    w.L = L - (np.linalg.eigvalsh(L)[-1] + 1.0) * np.outer(u, u)
+    s = Solver(w)
+    for projected in (False, True):
+        with pytest.raises(_lib.MMError) as ei:
+            s.decompose(projected=projected)
+        assert ei.value.code == 3, projected
+        assert "L_i" in str(ei.value)
+    s.close()
