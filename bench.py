@@ -18,6 +18,7 @@ reported beside it.
 from __future__ import annotations
 
 import argparse
+import copy
 import math
 import json
 import os
@@ -64,8 +65,9 @@ def run_electrodes(args):
     uses), and timed runs are added while the wall-clock budget (--budget-s,
     counted from the start of the process, with room kept for the CPU
     baseline) leaves room for one more.  `steps` reports the runs timed."""
+    import numpy as np
     import torch
-    from paper_2407_11993_amd import Solver
+    from paper_2407_11993_amd import Solver, inputs
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
@@ -79,6 +81,8 @@ def run_electrodes(args):
                 3000, 3500, 4000, 4500, 5000, 5500, 6000, 6500, 7000, 7500, 8000, 8500, 9000,
                 9500, 10000]
     omegas = [2 * math.pi * f / 30000.0 for f in tones_hz]
+
+    last_signal = [None]  # the coil signal of the latest run
 
     def one_step(w, K, tag):
         T = w.T
@@ -141,6 +145,7 @@ def run_electrodes(args):
         print(f"bench: {tag} Cholesky factorisation {t[4]:.2f} s, {K} steps {t[5]:.2f} s",
               file=sys.stderr, flush=True)
         agree = float((sm[:K] - sc).abs().max() / sc.abs().max())
+        last_signal[0] = sm[:, 0].clone()
         s.close()
         return {"setup": t[0], "decompose": t[1], "modal_steps": t[2], "cholesky_factor": t[4],
                 "cholesky_steps_measured": t[5],
@@ -151,23 +156,73 @@ def run_electrodes(args):
                 "modal_selective_steps_scan": ev[14].elapsed_time(ev[15]) / 1e3}, \
             (agree, exact_diff, sel)
 
+    def many_probe_run(w):
+        """Sec. 4.4 observes the field at 301 points: the same run with the
+        coil and 300 point probes on a line 2 cells above the plate's long
+        axis, one projected decomposition of all forcing and probe columns
+        (more than the bulge chase carries along: its reflectors are kept
+        and Q2^T is applied afterwards) and the modal steps."""
+        nx, ny = w.dims[0], w.dims[1]
+        ys = [0.5 + (ny - 2.0) * i / 299.0 for i in range(300)]
+        wp = copy.copy(w)
+        wp.P = np.vstack([w.P[:1]] + [inputs.coil_coupling(w.xyz, (nx / 2.0 - 0.5, y, 2.0))[None]
+                                      for y in ys])
+        i_src = torch.as_tensor(w.i_src, dtype=torch.float64, device="cuda")
+        i_D = torch.as_tensor(w.i_D, dtype=torch.float64, device="cuda")
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        s = Solver(wp)
+        ev[1].record(stream)
+        s.decompose(projected=True)
+        ev[2].record(stream)
+        sp = s.step_modal(theta, dt, wp.T, i_src, i_D)
+        ev[3].record(stream)
+        torch.cuda.synchronize()
+        t = [ev[i].elapsed_time(ev[i + 1]) / 1e3 for i in range(3)]
+        ref = last_signal[0]
+        diff = float((sp[:, 0] - ref).abs().max() / ref.abs().max())
+        s.close()
+        print(f"bench: 301 probes, projected decomposition {t[1]:.2f} s, "
+              f"{wp.T} steps {t[2]:.3f} s", file=sys.stderr, flush=True)
+        return {"probes": wp.n_probe, "columns": int(wp.M.shape[1] + 2 * wp.m + wp.n_probe),
+                "setup_s": round(t[0], 3), "decompose_s": round(t[1], 3),
+                "modal_steps_s": round(t[2], 4),
+                "end_to_end_s": round(sum(t), 3),
+                "coil_signal_difference_vs_one_probe_run": diff}
+
     if args.warmup:
         ww = _electrode_workload("plate-48x72-electrodes", min(T, 2000))
         for i in range(args.warmup):
             one_step(ww, min(K, ww.T), f"warm-up {i + 1}/{args.warmup}")
     runs, walls = [], []
     t0 = time.perf_counter()
+    reserve = 0.0 if args.no_cpu_baseline else args.cpu_reserve_s
+
+    def many_estimate():  # seconds the 301-probe leg needs, from the last run
+        if args.no_many_probes:
+            return 0.0
+        r = runs[-1][0]
+        return 1.2 * (r["setup"] + r["decompose"]) + 15.0
+
     while len(runs) < args.steps:
         if walls:
-            reserve = 0.0 if args.no_cpu_baseline else args.cpu_reserve_s
             left = args.budget_s - (time.perf_counter() - T_START) - reserve
-            if left < 1.1 * max(walls):
+            if left < 1.1 * max(walls) + many_estimate():
                 break
         ts = time.perf_counter()
         runs.append(one_step(w, K, f"timed run {len(runs) + 1}"))
         walls.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    many = None
+    if not args.no_many_probes:
+        left = args.budget_s - (time.perf_counter() - T_START) - reserve
+        if left >= many_estimate():
+            many = many_probe_run(w)
+        else:
+            many = {"skipped": f"{left:.0f} s of the budget left, "
+                               f"{many_estimate():.0f} s needed"}
     n_timed = len(runs)
     avg = {k: sum(r[0][k] for r in runs) / len(runs) for k in runs[0][0]}
     agree = max(r[1][0] for r in runs)
@@ -215,6 +270,9 @@ def run_electrodes(args):
                       "steps_scan_s": round(avg["modal_selective_steps_scan"], 6),
                       "signal_difference_vs_all_modes": sel_diff,
                       "signal_difference_scan_vs_sequential": sel_scan_diff},
+        # the same plate observed at 301 points (Sec. 4.4), run once after the
+        # timed runs: its own projected decomposition and all modal steps
+        "many_probes": many,
         "phases_s": {k: round(v, 3) for k, v in avg.items()},
         "decomposition_tflops": round(dec_flops / avg["decompose"] / 1e12, 3),
         # the same time against the 7/3 N0^3 flops of the standard form taken from
@@ -739,6 +797,8 @@ def main():
     ap.add_argument("--budget-s", type=float, default=420.0,
                     help="electrode plates: wall-clock seconds from process start within "
                          "which timed runs are added (at least one is always run)")
+    ap.add_argument("--no-many-probes", action="store_true",
+                    help="electrode plates: skip the run observed at 301 points")
     ap.add_argument("--cpu-reserve-s", type=float, default=60.0,
                     help="electrode plates: seconds of the budget kept for the CPU baseline")
     args = ap.parse_args()

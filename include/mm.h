@@ -125,9 +125,12 @@ mm_status mm_decompose(mm_ctx* ctx);
  * the band reduction, Q2^T by every bulge-chase task as it generates its
  * reflector, Z^T by one product after divide and conquer.  Afterwards
  * mm_step_modal, mm_eigenvalues and mm_batch_* work as after mm_decompose;
- * mm_probe(MM_MODAL) and mm_adjoint_modal return MM_E_STATE (they need V).  Synchronises the
- * stream.  Errors: those of mm_decompose; MM_E_INVALID when the forcing
- * columns (2 (Ne-1) + n_src) and the probes exceed 32 in all. */
+ * mm_probe(MM_MODAL) and mm_adjoint_modal return MM_E_STATE (they need V).
+ * Up to 32 forcing columns (2 (Ne-1) + n_src) and probes in all ride along
+ * the bulge chase; with more (Sec. 4.4 observes 301 points) the chase keeps
+ * its reflectors (half an n0^2 buffer beside C') and Q2^T is applied to the
+ * columns afterwards.  Synchronises the stream.  Errors: those of
+ * mm_decompose. */
 mm_status mm_decompose_projected(mm_ctx* ctx);
 
 /* The modal theta-method (Sec. 3.3.2) for n_steps steps:

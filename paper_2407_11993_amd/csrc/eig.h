@@ -50,6 +50,13 @@ int64_t apply_q2_ws_elems(int64_t n, int nb);
 void apply_q2(const Sb2stPlan& plan, const int64_t* d_offset, const double* V2,
               const double* tau2, double* Z, int64_t ldz, int64_t ncols, double* ws,
               int64_t ws_elems, hipStream_t s);
+// Y <- Q2^T Y for a few columns (the reflectors kept by sb2st), in a
+// wavefront of launches over the same blocks; ws holds the block list,
+// apply_q2t_ws_elems(n, nb) doubles.
+int64_t apply_q2t_ws_elems(int64_t n, int nb);
+void apply_q2t(const Sb2stPlan& plan, const int64_t* d_offset, const double* V2,
+               const double* tau2, double* Y, int64_t ldy, int64_t ncols, double* ws,
+               int64_t ws_elems, hipStream_t s);
 
 // ---- tridiagonal divide and conquer ---------------------------------------
 int64_t stedc_ws_elems(int64_t n);
@@ -95,12 +102,15 @@ struct EigWork {
 int64_t syevd_ws_elems(int64_t n, int nb);
 void syevd(double* C, int64_t ldc, int64_t n, double* lam, double* Q, int64_t ldq,
            const EigWork& w, const Sb2stPlan& plan, int64_t* d_status, hipStream_t s);
-// Eigenvalues and Q^T Y for a few columns Y (n x ny, ny <= sb2st_max_cols()),
-// without forming Q: Y <- Q2^T Q1^T Y on the way through the band reduction
-// and the bulge chase, then ZY = Z^T Y from the projected divide and conquer
-// (w.ws must hold stedc_project_ws_elems and sy2sb's and apply_q1t's needs).
-// C is destroyed: once its band is extracted, its storage (ldc n >= n^2
-// doubles) is the divide and conquer's eigenvector scratch.
+// Eigenvalues and Q^T Y for a few columns Y (n x ny), without forming Q:
+// Y <- Q2^T Q1^T Y on the way through the band reduction and the bulge chase
+// (up to sb2st_max_cols() columns the chase takes Y along; with more, w.V2
+// and w.tau2 keep its reflectors and apply_q2t follows it), then ZY = Z^T Y
+// from the projected divide and conquer.  w.ws must hold
+// syevd_project_ws_elems(n, nb, ny) doubles.  C is destroyed: once its band
+// is extracted, its storage (ldc n >= n^2 doubles) is the divide and
+// conquer's eigenvector scratch.
+int64_t syevd_project_ws_elems(int64_t n, int nb, int ny);
 void syevd_project(double* C, int64_t ldc, int64_t n, double* lam, double* Y, int64_t ldy,
                    int ny, double* ZY, int64_t ldzy, const EigWork& w, const Sb2stPlan& plan,
                    int64_t* d_status, hipStream_t s);

@@ -168,20 +168,36 @@ void apply_q1t(const double* A, int64_t lda, int64_t n, int nb, const double* T_
 void syevd_project(double* C, int64_t ldc, int64_t n, double* lam, double* Y, int64_t ldy,
                    int ny, double* ZY, int64_t ldzy, const EigWork& w, const Sb2stPlan& plan,
                    int64_t* d_status, hipStream_t s) {
-  MM_REQUIRE(ny >= 1 && ny <= sb2st_max_cols(), kInvalid,
-             "syevd_project: 1..32 projected columns");
+  MM_REQUIRE(ny >= 1, kInvalid, "syevd_project: at least one projected column");
   const int nb = w.nb;
+  MM_REQUIRE(w.ws_elems >= syevd_project_ws_elems(n, nb, ny), kInvalid,
+             "syevd_project: workspace too small");
+  const bool along = ny <= sb2st_max_cols();  // Y rides along the bulge chase
+  MM_REQUIRE(along || (w.V2 && w.tau2), kInvalid,
+             "syevd_project: more columns than the bulge chase carries need V2 and tau2");
   auto mark = [&](const char* what) { if (w.mark) w.mark(what); };
   sy2sb(C, ldc, n, nb, w.tau1, w.T1, w.ws, w.ws_elems, s);
   apply_q1t(C, ldc, n, nb, w.T1, Y, ldy, ny, w.ws, w.ws_elems, s);
   mark("band reduction");
   const int64_t ldab = 2 * nb + 1;
   extract_band(C, ldc, n, nb, w.AB, ldab, s);
-  sb2st(w.AB, ldab, plan, w.d_offset, w.V2, w.tau2, w.d, w.e, s, Y, ldy, ny);
+  if (along) {
+    sb2st(w.AB, ldab, plan, w.d_offset, nullptr, nullptr, w.d, w.e, s, Y, ldy, ny);
+  } else {
+    sb2st(w.AB, ldab, plan, w.d_offset, w.V2, w.tau2, w.d, w.e, s);
+    apply_q2t(plan, w.d_offset, w.V2, w.tau2, Y, ldy, ny, w.ws, w.ws_elems, s);
+  }
   mark("bulge chase");
   // C is dead from here on (its reflectors were applied to Y, its band copied)
   stedc_project(w.d, w.e, n, lam, Y, ldy, ny, ZY, ldzy, C, w.ws, w.ws_elems, d_status, s);
   mark("divide and conquer");
+}
+
+int64_t syevd_project_ws_elems(int64_t n, int nb, int ny) {
+  int64_t w = std::max(sy2sb_ws_elems(n, nb), stedc_project_ws_elems(n, ny));
+  w = std::max(w, apply_q1_ws_elems(n, nb, ny));
+  if (ny > sb2st_max_cols()) w = std::max(w, apply_q2t_ws_elems(n, nb));
+  return w;
 }
 
 int64_t syevd_ws_elems(int64_t n, int nb) {

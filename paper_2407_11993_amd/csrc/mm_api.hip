@@ -57,16 +57,9 @@ constexpr int kMaxColumns = 4096;  // sources, probes
 constexpr int kMaxRunColumns = 8;  // forcing columns and probes of one stepping call
 
 // workspace of the eigensolver (both divide and conquer modes keep their n^2
-// scratch in C's storage)
-int64_t eig_ws_elems(int64_t n, int nb, bool project = false) {
-  int64_t w = sy2sb_ws_elems(n, nb);
-  if (project) {
-    w = std::max(w, stedc_project_ws_elems(n, sb2st_max_cols()));
-    w = std::max(w, apply_q1_ws_elems(n, nb, sb2st_max_cols()));
-  } else {
-    w = std::max(w, syevd_ws_elems(n, nb));
-  }
-  return w;
+// scratch in C's storage); ny: the projected columns (0: the full solver)
+int64_t eig_ws_elems(int64_t n, int nb, int ny = 0) {
+  return ny > 0 ? syevd_project_ws_elems(n, nb, ny) : syevd_ws_elems(n, nb);
 }
 
 // Probe partial sums of mm_step_modal_noalloc: a file-scope device array
@@ -506,9 +499,6 @@ void decompose_impl(mm_ctx* c, bool project) {
     const int m = (int)c->m;
     const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(kBand, n0 - 1));
     const int ny = c->nf + c->n_probe;
-    MM_REQUIRE(!project || ny <= sb2st_max_cols(), kInvalid,
-               "mm_decompose_projected: at most 32 forcing and probe columns in all "
-               "(use mm_decompose)");
     const int Bb = (int)band_block(c->band);
     MM_REQUIRE(Bb <= kMaxBandBlock, kInvalid,
                "R's bandwidth exceeds 8192: number the unknowns so that R is banded "
@@ -524,7 +514,7 @@ void decompose_impl(mm_ctx* c, bool project) {
     // The small buffers first (an allocation that has to reuse memory just
     // freed by a large one of the same size can take seconds); at N = 98,304
     // one n0^2 buffer is 77 GB, and at most two and a half are live.
-    const int64_t wse = eig_ws_elems(n0, nb, project);
+    const int64_t wse = eig_ws_elems(n0, nb, project ? ny : 0);
     Dev Cb, ws, Hinv, Hs, tmp, Zh, small, Yc, ZY, tau;
     ws.alloc(sizeof(double) * std::max(wse, band_factor_ws_elems(Bb)));
     Sb2stPlan plan = sb2st_plan(n0, nb);
@@ -679,7 +669,10 @@ void decompose_impl(mm_ctx* c, bool project) {
       g3.C = Y; g3.ldc = ldy;
       gemm(g3, s);
     };
-    if (!project) {  // the bulge-chase reflectors, kept for the back-transform
+    // the bulge-chase reflectors, kept for the back-transform, or for Q2^T of
+    // more projected columns than the chase carries along
+    const bool keep_q2 = !project || ny > sb2st_max_cols();
+    if (keep_q2) {
       V2.alloc(sizeof(double) * std::max<int64_t>(1, plan.tasks) * nb);
       tau2.alloc(sizeof(double) * std::max<int64_t>(1, plan.tasks));
     }
@@ -688,8 +681,8 @@ void decompose_impl(mm_ctx* c, bool project) {
     EigWork w;
     w.nb = nb;
     w.tau1 = tau1.d(); w.T1 = T1.d(); w.AB = AB.d();
-    w.V2 = project ? nullptr : V2.d();
-    w.tau2 = project ? nullptr : tau2.d();
+    w.V2 = keep_q2 ? V2.d() : nullptr;
+    w.tau2 = keep_q2 ? tau2.d() : nullptr;
     w.d_offset = off.as<int64_t>(); w.d = dv.d(); w.e = ev.d();
     w.ws = ws.d(); w.ws_elems = wse;
     w.mark = [c](const char* what) { mark(c, what); };

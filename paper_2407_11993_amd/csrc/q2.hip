@@ -255,6 +255,70 @@ __global__ void __launch_bounds__(NT) q2_apply_k(const Pair* pairs, int64_t p0, 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Y <- Q2^T Y for a few columns (one launch per stage of a wavefront)
+// ---------------------------------------------------------------------------
+// Q2^T = (B_0 ... B_last)^T with the blocks B in the order of q2_pairs, so
+// Q2^T Y applies the blocks in the reverse order (g ascending, k descending),
+// each as its reflectors in generation order (sweep ascending; the block's
+// transpose I - V T^T V^T).  The blocks of one launch share no row.  Each
+// workgroup applies one block to 64 columns: the 128-row window staged in
+// LDS, the block's reflectors one after the other (wave w sums and updates
+// reflector rows [16 w, 16 w + 16), lane = column).
+__global__ void __launch_bounds__(NT) q2t_apply_k(const Pair* pairs, int64_t p0, int64_t n,
+                                                  int nb, const int64_t* off, const double* V2,
+                                                  const double* tau2, double* Y, int64_t ldy,
+                                                  int64_t ncols) {
+  __shared__ double Yw[WR][ZC + LP];
+  __shared__ double Vs[GS][GS + LP];  // Vs[gs][i]: element i of sweep sa + gs's reflector
+  __shared__ double ts[GS];
+  __shared__ double red[4][ZC];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const Pair pr = pairs[p0 + blockIdx.x];
+  const int64_t col0 = (int64_t)blockIdx.y * ZC;
+  const int ncl = (int)min((int64_t)ZC, ncols - col0);
+  for (int e = t; e < WR * ZC; e += NT) {
+    const int i = e % WR, j = e / WR;
+    const int64_t row = pr.wlo + i;
+    Yw[i][j] = (row < n && j < ncl) ? Y[row + (col0 + j) * ldy] : 0.0;
+  }
+  for (int e = t; e < GS * GS; e += NT) {
+    const int i = e % GS, gs = e / GS;
+    const int64_t s = pr.sa + gs;
+    const bool ok = s < pr.sl && pr.k < ceil_div(n - 1 - s, nb) && i < nb;
+    Vs[gs][i] = ok ? V2[(off[s] + pr.k) * nb + i] : 0.0;
+  }
+  for (int gs = t; gs < GS; gs += NT) {
+    const int64_t s = pr.sa + gs;
+    ts[gs] = (s < pr.sl && pr.k < ceil_div(n - 1 - s, nb)) ? tau2[off[s] + pr.k] : 0.0;
+  }
+  __syncthreads();
+  // the reflector of sweep sa + gs starts at window row gs
+  for (int gs = 0; gs < GS; ++gs) {
+    const double tau = ts[gs];
+    if (tau == 0.0) continue;  // uniform: H = I
+    const int i0 = 16 * wave;
+    double yr[16];
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      yr[q] = Yw[gs + i0 + q][lane];
+      acc += Vs[gs][i0 + q] * yr[q];
+    }
+    red[wave][lane] = acc;
+    __syncthreads();
+    const double d = tau * ((red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]));
+#pragma unroll
+    for (int q = 0; q < 16; ++q) Yw[gs + i0 + q][lane] = yr[q] - Vs[gs][i0 + q] * d;
+    __syncthreads();
+  }
+  for (int e = t; e < WR * ZC; e += NT) {
+    const int i = e % WR, j = e / WR;
+    const int64_t row = pr.wlo + i;
+    if (row < n && j < ncl) Y[row + (col0 + j) * ldy] = Yw[i][j];
+  }
+}
+
 // the (g, k) blocks in application order: g descending, k ascending
 std::vector<Pair> q2_pairs(int64_t n, int nb) {
   std::vector<Pair> pairs;
@@ -313,6 +377,62 @@ void apply_q2(const Sb2stPlan& plan, const int64_t* d_offset, const double* V2,
                        n, ncols);
     MM_HIP_TRY(hipGetLastError());
   }
+  // the host vector must outlive the copy
+  MM_HIP_TRY(hipStreamSynchronize(s));
+}
+
+int64_t apply_q2t_ws_elems(int64_t n, int nb) {
+  return pair_list_words((int64_t)q2_pairs(n, nb).size()) + 1;
+}
+
+void apply_q2t(const Sb2stPlan& plan, const int64_t* d_offset, const double* V2,
+               const double* tau2, double* Y, int64_t ldy, int64_t ncols, double* ws,
+               int64_t ws_elems, hipStream_t s) {
+  const int64_t n = plan.n;
+  const int nb = plan.nb;
+  MM_REQUIRE(nb + GS - 1 <= WR, kInvalid, "apply_q2t: band too wide");
+  if (n < 3 || ncols <= 0) return;
+  const std::vector<Pair> fwd = q2_pairs(n, nb);
+  const int64_t npairs = (int64_t)fwd.size();
+  MM_REQUIRE(ws_elems >= pair_list_words(npairs), kInvalid, "apply_q2t: workspace too small");
+  // Stages.  With nb = GS the window of block (g, k) starts at row
+  // GS (g + k) + 1, so the blocks before it (in the order g ascending,
+  // k descending) that share rows with it have windows g' + k' within one of
+  // g + k and g' - k' < g - k; blocks with equal g - k are 2 GS rows apart.
+  // Stage g - k (shifted to start at 0) is therefore a valid wavefront.
+  // Otherwise (nb < GS: at most GS + 1 unknowns, a handful of blocks) every
+  // block is a stage of its own.
+  std::vector<Pair> order;
+  std::vector<int64_t> start;
+  if (nb == GS) {
+    int64_t kmax = 0, gmax = 0;
+    for (const Pair& p : fwd) {
+      kmax = std::max(kmax, p.k);
+      gmax = std::max(gmax, p.sa / GS);
+    }
+    const int64_t nst = gmax + kmax + 1;
+    std::vector<int64_t> cnt(nst + 1, 0);
+    for (const Pair& p : fwd) ++cnt[p.sa / GS - p.k + kmax + 1];
+    for (int64_t i = 0; i < nst; ++i) cnt[i + 1] += cnt[i];
+    start = cnt;
+    order.resize(npairs);
+    for (const Pair& p : fwd) order[cnt[p.sa / GS - p.k + kmax]++] = p;
+  } else {
+    order.assign(fwd.rbegin(), fwd.rend());
+    start.resize(npairs + 1);
+    for (int64_t i = 0; i <= npairs; ++i) start[i] = i;
+  }
+  Pair* d_pairs = reinterpret_cast<Pair*>(ws);
+  MM_HIP_TRY(hipMemcpyAsync(d_pairs, order.data(), sizeof(Pair) * npairs,
+                            hipMemcpyHostToDevice, s));
+  const unsigned cgrid = (unsigned)ceil_div(ncols, ZC);
+  for (size_t st = 0; st + 1 < start.size(); ++st) {
+    const int64_t p0 = start[st], p1 = start[st + 1];
+    if (p1 == p0) continue;
+    hipLaunchKernelGGL(q2t_apply_k, dim3((unsigned)(p1 - p0), cgrid), dim3(NT), 0, s, d_pairs,
+                       p0, n, nb, d_offset, V2, tau2, Y, ldy, ncols);
+  }
+  MM_HIP_TRY(hipGetLastError());
   // the host vector must outlive the copy
   MM_HIP_TRY(hipStreamSynchronize(s));
 }

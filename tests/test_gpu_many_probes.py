@@ -101,3 +101,60 @@ def test_many_probes_across_chunks_at_16384():
     sc = _np(s.step_cholesky(0.5, w.dt, T, i_src))
     assert _rel_cols(sc, few) < 1e-8
     s.close()
+
+
+@pytest.mark.parametrize("case", sorted(CASES) + ["tiny"])
+def test_projected_many_columns_match_oracle(orc, case):
+    """More forcing and probe columns than the bulge chase carries along (32):
+    the projected decomposition keeps the chase's reflectors and applies Q2^T
+    to the columns afterwards (a wavefront of launches over the blocks of 64
+    sweeps; "tiny" has fewer than 66 unknowns, a band narrower than 64 and one
+    block per launch).  Against the oracle and the full decomposition."""
+    from paper_2407_11993_amd import Solver
+    if case == "tiny":
+        w = inputs.plate(7, 8, seed=6, T=200, wave="sin", thetas=(0.5,))
+    else:
+        w = CASES[case]()
+    w = _with_probes(w, 6)  # 37 probes
+    assert w.M.shape[1] + 2 * w.m + w.n_probe > 32
+    i_D = w.i_D if w.m else None
+    E = None if w.E is None else w.E.to_dense()
+    pb = orc.Problem(orc.assemble_L(w.xyz, w.h), w.R.to_dense(), w.M, w.P, E=E)
+    ref = orc.theta_direct(pb, 0.5, w.dt, w.T, w.i_src, i_D)
+    s = Solver(w)
+    s.decompose(projected=True)
+    sp = _np(s.step_modal(0.5, w.dt, w.T, w.i_src, i_D))
+    s.close()
+    f = Solver(w)
+    f.decompose()
+    sf = _np(f.step_modal(0.5, w.dt, w.T, w.i_src, i_D))
+    f.close()
+    assert sp.shape == ref.shape == (w.T, 37)
+    assert _rel_cols(sp, ref) < 1e-9
+    assert _rel_cols(sp, sf) < 1e-11
+
+
+def test_301_probes_projected_at_16384():
+    """N = 16,384 (the crack plate) observed at 301 points (the number of
+    Sec. 4.4) on a line 2 cells above the plate, over the crack: the
+    projected decomposition with 302 columns against the full one, and the
+    Cholesky method against both (1e-8)."""
+    from paper_2407_11993_amd import Solver
+    T = 3000
+    w = inputs.config2(T=T)
+    xs = np.linspace(0.5, w.dims[0] - 1.5, 301)
+    w.P = np.vstack([inputs.coil_coupling(w.xyz, (x, w.dims[1] / 2.0 - 0.5, 2.0))
+                     for x in xs])
+    s = Solver(w)
+    s.decompose(projected=True)
+    sp = _np(s.step_modal(0.5, w.dt, T, w.i_src))
+    s.close()
+    f = Solver(w)
+    f.decompose()
+    sf = _np(f.step_modal(0.5, w.dt, T, w.i_src))
+    f.reset()
+    sc = _np(f.step_cholesky(0.5, w.dt, T, w.i_src))
+    f.close()
+    assert sp.shape == sf.shape == (T, 301)
+    assert _rel_cols(sp, sf) < 1e-10
+    assert _rel_cols(sc, sf) < 1e-8
