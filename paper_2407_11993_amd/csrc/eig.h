@@ -23,7 +23,9 @@ void apply_q1(const double* A, int64_t lda, int64_t n, int nb, const double* T_a
               double* Z, int64_t ldz, int64_t ncols, double* ws, int64_t ws_elems,
               hipStream_t s);
 int64_t apply_q1_ws_elems(int64_t n, int nb, int64_t ncols);
-// Y <- Q1^T Y (the panels' block reflectors transposed, first panel first).
+// Y <- Q1^T Y (the panels' block reflectors transposed, first panel first);
+// ws holds apply_q1t_ws_elems(n, nb, ncols) doubles.
+int64_t apply_q1t_ws_elems(int64_t n, int nb, int64_t ncols);
 void apply_q1t(const double* A, int64_t lda, int64_t n, int nb, const double* T_all,
                double* Y, int64_t ldy, int64_t ncols, double* ws, int64_t ws_elems,
                hipStream_t s);

@@ -123,16 +123,24 @@ void apply_q1(const double* A, int64_t lda, int64_t n, int nb, const double* T_a
   }
 }
 
+// Split-K shares of the few-column products V^T Y: one per 128 rows (a
+// product of nb x ncols outputs over m rows runs on m / 128 workgroups).
+static int64_t q1t_splits(int64_t n) { return std::max<int64_t>(8, std::min<int64_t>(1024, n / 128)); }
+
+int64_t apply_q1t_ws_elems(int64_t n, int nb, int64_t ncols) {
+  return n * nb + 2 * (int64_t)nb * ncols + q1t_splits(n) * nb * ncols;
+}
+
 void apply_q1t(const double* A, int64_t lda, int64_t n, int nb, const double* T_all, double* Y,
                int64_t ldy, int64_t ncols, double* ws, int64_t ws_elems, hipStream_t s) {
-  MM_REQUIRE(ws_elems >= apply_q1_ws_elems(n, nb, ncols), kInvalid,
+  MM_REQUIRE(ws_elems >= apply_q1t_ws_elems(n, nb, ncols), kInvalid,
              "apply_q1t: workspace too small");
   const int64_t np = sy2sb_npanels(n, nb);
   double* V = ws;                       // m x nb
   double* W = V + n * nb;               // nb x ncols
   double* W2 = W + nb * ncols;          // nb x ncols
   double* split = W2 + nb * ncols;
-  const int64_t split_elems = 8 * nb * ncols;
+  const int64_t split_elems = q1t_splits(n) * nb * ncols;
   for (int64_t p = 0; p < np; ++p) {
     const int64_t j = p * nb, r0 = j + nb, m = n - r0;
     const double* P = A + r0 + j * lda;
@@ -195,7 +203,7 @@ void syevd_project(double* C, int64_t ldc, int64_t n, double* lam, double* Y, in
 
 int64_t syevd_project_ws_elems(int64_t n, int nb, int ny) {
   int64_t w = std::max(sy2sb_ws_elems(n, nb), stedc_project_ws_elems(n, ny));
-  w = std::max(w, apply_q1_ws_elems(n, nb, ny));
+  w = std::max(w, apply_q1t_ws_elems(n, nb, ny));
   if (ny > sb2st_max_cols()) w = std::max(w, apply_q2t_ws_elems(n, nb));
   return w;
 }

@@ -611,17 +611,35 @@ void launch_big(const KArgs& ka, bool ta, bool tb, bool sym, dim3 grid, hipStrea
   else hipLaunchKernelGGL((gemm_big_kernel<BN, true, true, false>), grid, block, 0, s, ka);
 }
 
-// C = beta C + sum_z W_z, in a fixed order (deterministic split-K).
-__global__ void splitk_reduce(int64_t M, int64_t N, int splits, const double* W,
-                              double beta, double* C, int64_t ldc, int lower) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= M * N) return;
+// C = beta C + sum_z W_z in a fixed order (deterministic split-K): 64
+// consecutive outputs per workgroup (lane = output, coalesced reads), wave w
+// sums the partials z = w, w + 4, ... in ascending z, and the four wave sums
+// are added in wave order.
+__global__ void __launch_bounds__(256) splitk_reduce(int64_t M, int64_t N, int splits,
+                                                     const double* W, double beta, double* C,
+                                                     int64_t ldc, int lower) {
+  __shared__ double part[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t idx = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t MN = M * N;
+  double s = 0.0;
+  if (idx < MN) {
+    int z = wave;
+    for (; z + 12 < splits; z += 16) {  // four loads in flight
+      const double a = W[(int64_t)z * MN + idx], b = W[(int64_t)(z + 4) * MN + idx];
+      const double c = W[(int64_t)(z + 8) * MN + idx], d = W[(int64_t)(z + 12) * MN + idx];
+      s = (((s + a) + b) + c) + d;
+    }
+    for (; z < splits; z += 4) s += W[(int64_t)z * MN + idx];
+  }
+  part[wave][lane] = s;
+  __syncthreads();
+  if (wave != 0 || idx >= MN) return;
   const int64_t i = idx % M, j = idx / M;
   if (lower && i < j) return;
-  double s = 0.0;
-  for (int z = 0; z < splits; ++z) s += W[(int64_t)z * M * N + idx];
-  if (beta != 0.0) s += beta * C[i + j * ldc];
-  C[i + j * ldc] = s;
+  double r = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+  if (beta != 0.0) r += beta * C[i + j * ldc];
+  C[i + j * ldc] = r;
 }
 
 template <int BM, int BN, int WGM, int WGN, bool GROUPED>
@@ -672,10 +690,12 @@ void gemm(const Gemm& g, hipStream_t stream, double* ws, int64_t ws_elems) {
   ka.ch_log2 = chunk_log2(tiles);
   const int64_t wgs = padded_tiles(tiles, ka.ch_log2);
   MM_REQUIRE(wgs < (int64_t)1 << 31, kInvalid, "gemm: too many tiles");
-  // split-K for few output tiles over a long k (never together with batching)
+  // split-K for few output tiles over a long k (never together with batching):
+  // at least 128 of k per workgroup (eight slices: each workgroup's slices
+  // are latency-bound, so many short shares beat few long ones)
   int splits = 1;
   if (ws && g.batch == 1 && tiles * 4 < 1024 && g.k >= 2048) {
-    splits = (int)std::min<int64_t>(ceil_div(1024, tiles), g.k / 512);
+    splits = (int)std::min<int64_t>(ceil_div(1024, tiles), g.k / 128);
     const int64_t cap = ws_elems / (g.m * g.n);
     splits = (int)std::min<int64_t>(splits, cap);
     if (splits < 2) splits = 1;
@@ -713,7 +733,7 @@ void gemm(const Gemm& g, hipStream_t stream, double* ws, int64_t ws_elems) {
     MM_HIP_TRY(hipGetLastError());
     if (sp > 1) {
       const int64_t total = g.m * g.n;
-      hipLaunchKernelGGL(splitk_reduce, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, stream,
+      hipLaunchKernelGGL(splitk_reduce, dim3((unsigned)ceil_div(total, 64)), dim3(256), 0, stream,
                          g.m, g.n, sp, ws, g.beta, g.C, g.ldc, (int)g.lower);
       MM_HIP_TRY(hipGetLastError());
     }
@@ -725,7 +745,7 @@ void gemm(const Gemm& g, hipStream_t stream, double* ws, int64_t ws_elems) {
   MM_HIP_TRY(hipGetLastError());
   if (splits > 1) {
     const int64_t total = g.m * g.n;
-    hipLaunchKernelGGL(splitk_reduce, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, stream,
+    hipLaunchKernelGGL(splitk_reduce, dim3((unsigned)ceil_div(total, 64)), dim3(256), 0, stream,
                        g.m, g.n, splits, ws, g.beta, g.C, g.ldc, (int)g.lower);
     MM_HIP_TRY(hipGetLastError());
   }

@@ -40,6 +40,9 @@ constexpr int QROWS = 256;  // panel rows per workgroup
 // of that row it works on in registers: every global load of a launch is
 // issued at its start, so a launch costs about one memory latency.
 constexpr int MAXNB = 64;
+// partials read per thread at once when the previous column's sums are
+// formed (a quarter of the workgroups' partials: 96 at 98,304 rows)
+constexpr int PB = 48;
 
 __global__ void __launch_bounds__(QT) panel_qr_step(double* P, int64_t ldp, int64_t m,
                                                     int nb, int c, double* scratch,
@@ -71,13 +74,13 @@ __global__ void __launch_bounds__(QT) panel_qr_step(double* P, int64_t ldp, int6
     // four threads per column, each summing a contiguous quarter of slices
     const int j = t & 63, h = t >> 6, G4 = (G + 3) / 4;
     double ps = 0.0;
-    for (int u0 = 0; u0 < G4; u0 += 16) {
-      double xs[16];  // clamped addresses: all sixteen loads in flight at once
+    for (int u0 = 0; u0 < G4; u0 += PB) {
+      double xs[PB];  // clamped addresses: all PB loads in flight at once
 #pragma unroll
-      for (int u = 0; u < 16; ++u)
+      for (int u = 0; u < PB; ++u)
         xs[u] = part[(int64_t)min(h * G4 + u0 + u, G - 1) * stride + min(j, ncol - 1)];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
+      for (int u = 0; u < PB; ++u) {
         const int q = h * G4 + u0 + u;
         ps += (u0 + u < G4 && q < G && j < ncol) ? xs[u] : 0.0;
       }
@@ -169,24 +172,33 @@ __global__ void extract_v(const double* P, int64_t ldp, int64_t m, int nb, doubl
 
 // T (nb x nb, upper) from tau and the Gram matrix S = V^T V:
 //   T(c,c) = tau_c,  T(0:c, c) = -tau_c T(0:c, 0:c) S(0:c, c).
-// Columns with tau_c = 0 give zero columns.
-__global__ void form_t(const double* S, const double* tau, int nb, double* T) {
-  __shared__ double col[128];
+// Columns with tau_c = 0 give zero columns.  S and T live in LDS (the
+// recurrence reads T's finished columns nb times).
+__global__ void __launch_bounds__(64) form_t(const double* S, const double* tau, int nb,
+                                             double* T) {
+  __shared__ double Ss[64][65];
+  __shared__ double Ts[64][65];
+  __shared__ double tv[64];
   const int t = threadIdx.x;
-  for (int e = t; e < nb * nb; e += blockDim.x) T[e] = 0.0;
+  for (int e = t; e < 64 * 64; e += 64) {
+    const int r = e % 64, c = e / 64;
+    Ss[r][c] = (r < nb && c < nb) ? S[r + c * nb] : 0.0;
+    Ts[r][c] = 0.0;
+  }
+  if (t < nb) tv[t] = tau[t];
   __syncthreads();
   for (int c = 0; c < nb; ++c) {
-    const double tc = tau[c];
-    if (t < c) {
-      double s = 0.0;
-      for (int q = t; q < c; ++q) s += T[t + q * nb] * S[q + c * nb];
-      col[t] = -tc * s;
-    }
-    __syncthreads();
-    if (t < c) T[t + c * nb] = col[t];
-    if (t == 0) T[c + c * nb] = tc;
+    // row t of T is zero outside columns [t, c) so far: a fixed-length,
+    // unrolled sum (its LDS reads pipeline, unlike a loop of t-dependent length)
+    double v = 0.0;
+#pragma unroll 16
+    for (int q = 0; q < 64; ++q) v += Ts[t][q] * Ss[q][c];
+    v = (t < c) ? -tv[c] * v : (t == c ? tv[c] : 0.0);
+    __syncthreads();  // every read of column c's inputs is done
+    if (t <= c) Ts[t][c] = v;
     __syncthreads();
   }
+  for (int e = t; e < nb * nb; e += 64) T[e] = Ts[e % nb][e / nb];
 }
 
 }  // namespace
@@ -195,7 +207,10 @@ __global__ void form_t(const double* S, const double* tau, int nb, double* T) {
 // boundaries (the products read them row-wise in 128-byte pieces).
 static inline int64_t ld16(int64_t m) { return ceil_div(m, 16) * 16; }
 
-constexpr int GP = 4;  // panels per group
+#ifndef MM_SY2SB_GP
+#define MM_SY2SB_GP 6
+#endif
+constexpr int GP = MM_SY2SB_GP;  // panels per group
 
 int64_t sy2sb_ws_elems(int64_t n, int nb) {
   const int64_t G = ceil_div(n, QROWS);
@@ -244,7 +259,7 @@ void qr_panel(double* P, int64_t lda, int64_t m, int nb, double* tau, double* T,
   gs.B = V1; gs.ldb = ldv;
   gs.C = w.Sm; gs.ldc = nb;
   gemm(gs, s, w.split, w.split_elems);
-  hipLaunchKernelGGL(form_t, dim3(1), dim3(128), 0, s, w.Sm, tau, nb, T);
+  hipLaunchKernelGGL(form_t, dim3(1), dim3(64), 0, s, w.Sm, tau, nb, T);
   MM_HIP_TRY(hipGetLastError());
 }
 
