@@ -197,7 +197,10 @@ mm_status mm_step_modal_scan(mm_ctx* ctx, double theta, int32_t exact, double dt
  * modal probe weights; every source counts with unit amplitude) exceeds
  * tol times the largest score.  tol = 0 drops only modes with no forcing or
  * no probe weight, which cannot change a probe signal; a larger tol drops
- * weakly coupled modes, an approximation.  With degenerate eigenvalues the
+ * weakly coupled modes, an approximation.  The score weights the columns
+ * neither by the run's waveforms (R_D is driven by dt i_D, the others by
+ * increments) nor by 1/lambda_n, so for tol > 0 it is a heuristic whose
+ * reach depends on the units of the sources and electrodes and on dt.  With degenerate eigenvalues the
  * eigensolver's basis of each eigenspace decides which of its modes carry
  * the coupling, so the kept count can differ between eigensolvers while the
  * signals agree.
