@@ -41,8 +41,11 @@ constexpr int QROWS = 256;  // panel rows per workgroup
 // issued at its start, so a launch costs about one memory latency.
 constexpr int MAXNB = 64;
 // partials read per thread at once when the previous column's sums are
-// formed (a quarter of the workgroups' partials: 96 at 98,304 rows)
-constexpr int PB = 48;
+// formed (each thread sums a quarter of the workgroups' partials)
+#ifndef MM_SY2SB_PB
+#define MM_SY2SB_PB 32
+#endif
+constexpr int PB = MM_SY2SB_PB;
 
 __global__ void __launch_bounds__(QT) panel_qr_step(double* P, int64_t ldp, int64_t m,
                                                     int nb, int c, double* scratch,
