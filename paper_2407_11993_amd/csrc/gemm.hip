@@ -601,6 +601,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BN == 
       }
 }
 
+// split-K of the 128-row-tile products: enough shares for this many rounds
+// of resident workgroups, at most MM_GEMM_SPLIT_MAX, each at least
+// MM_GEMM_SPLIT_MINK of k
+#ifndef MM_GEMM_SPLIT_ROUNDS
+#define MM_GEMM_SPLIT_ROUNDS 12
+#endif
+#ifndef MM_GEMM_SPLIT_MAX
+#define MM_GEMM_SPLIT_MAX 32
+#endif
+#ifndef MM_GEMM_SPLIT_MINK
+#define MM_GEMM_SPLIT_MINK 2048
+#endif
+
 template <int BN>
 void launch_big(const KArgs& ka, bool ta, bool tb, bool sym, dim3 grid, hipStream_t s) {
   const dim3 block(256);
@@ -714,14 +727,17 @@ void gemm(const Gemm& g, hipStream_t stream, double* ws, int64_t ws_elems) {
     ka.tiles_m = (int)ceil_div(g.m, 128);
     ka.tiles_n = (int)ceil_div(g.n, bnb);
     const int64_t tb = (int64_t)ka.tiles_m * ka.tiles_n;
-    // split-K when a long-k product has fewer tiles than two rounds of
+    // split-K when a long-k product has fewer tiles than twelve rounds of
     // resident workgroups (three 128 x 64 or two 128 x 128 per CU): tall,
-    // narrow products with k = m, such as the band reduction's A22 V
-    const int64_t slots = bnb == 64 ? 768 : 512;
+    // narrow products with k = m, such as the band reduction's A22 V.  Many
+    // shares of at least 2048 of k each run faster than few long ones (the
+    // paper-scale band reduction: 28.1 s with two rounds, 26.7 s with twelve),
+    // their workgroups reading A at many distant places at once.
+    const int64_t slots = MM_GEMM_SPLIT_ROUNDS * (bnb == 64 ? 768 : 512);
     int sp = 1;
-    if (ws && g.batch == 1 && g.k >= 4096 && tb < 2 * slots) {
-      sp = (int)std::min<int64_t>(std::min<int64_t>(ceil_div(2 * slots, tb), g.k / 2048),
-                                  std::min<int64_t>(ws_elems / (g.m * g.n), 8));
+    if (ws && g.batch == 1 && g.k >= 4096 && tb < slots) {
+      sp = (int)std::min<int64_t>(std::min<int64_t>(ceil_div(slots, tb), g.k / MM_GEMM_SPLIT_MINK),
+                                  std::min<int64_t>(ws_elems / (g.m * g.n), MM_GEMM_SPLIT_MAX));
       if (sp < 2) sp = 1;
     }
     ka.splits = sp;

@@ -214,15 +214,21 @@ static inline int64_t ld16(int64_t m) { return ceil_div(m, 16) * 16; }
 #define MM_SY2SB_GP 6
 #endif
 constexpr int GP = MM_SY2SB_GP;  // panels per group
+// split-K partials of the n x nb products, in units of n nb doubles (the
+// symmetric products split up to this many ways at full height)
+#ifndef MM_SY2SB_SPLIT_WS
+#define MM_SY2SB_SPLIT_WS 32
+#endif
+constexpr int64_t SPLIT_WS = MM_SY2SB_SPLIT_WS;
 
 int64_t sy2sb_ws_elems(int64_t n, int nb) {
   const int64_t G = ceil_div(n, QROWS);
   const int64_t stride = nb + 1;
   const int64_t np = ld16(n);
   // scratch (2 (G stride + nb)) + X (np x nb) + small (3 nb^2 + 2 GP nb^2)
-  // + U1, U2 (np x 2 GP nb each) + split-K partials (8 n nb)
+  // + U1, U2 (np x 2 GP nb each) + split-K partials (SPLIT_WS n nb)
   return 2 * (G * stride + nb) + np * nb + (3 + 2 * GP) * (int64_t)nb * nb +
-         2 * np * 2 * GP * nb + 8 * n * nb;
+         2 * np * 2 * GP * nb + SPLIT_WS * n * nb;
 }
 
 int64_t sy2sb_npanels(int64_t n, int nb) {
@@ -352,7 +358,7 @@ void sy2sb(double* A, int64_t lda, int64_t n, int nb, double* tau_all, double* T
   double* U1 = w.S2 + 2 * GP * (int64_t)nb * nb;     // np x 2 GP nb
   double* U2 = U1 + np * 2 * GP * nb;                // np x 2 GP nb
   w.split = U2 + np * 2 * GP * nb;
-  w.split_elems = 8 * n * nb;
+  w.split_elems = SPLIT_WS * n * nb;
   int64_t p = 0;
   for (int64_t j = 0; j + nb < n - 1;) {
     const int64_t m = n - (j + nb);  // rows of the group's first panel
