@@ -41,6 +41,15 @@ struct Error {
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// A store written through to the device's point of coherence (relaxed, agent
+// scope: a plain vector store with the device-scope cache policy).  For data
+// that the next launch of a long chain of small kernels reads, possibly on
+// another XCD: the write-back of dirty L2 lines that ends each launch then
+// has little left to do.
+__device__ __forceinline__ void store_dev(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // ---------------------------------------------------------------------------
 // GEMM: C = alpha op(A) op(B) + beta C, column-major, FP64 MFMA.
 // Options that restrict the work to the non-zero structure:

@@ -141,8 +141,8 @@ __global__ void __launch_bounds__(NT) sb2st_stage(Band B, int n, int nb, int sta
       s_beta = beta;
     }
     if (V2) {  // kept for the back-transform (not when only Q2^T Y is wanted)
-      if (lane < nb) V2[task * nb + lane] = vv;
-      if (lane == 0) tau2[task] = tv;
+      if (lane < nb) store_dev(&V2[task * nb + lane], vv);
+      if (lane == 0) store_dev(&tau2[task], tv);
     }
   }
   __syncthreads();
@@ -202,7 +202,8 @@ __global__ void __launch_bounds__(NT) sb2st_stage(Band B, int n, int nb, int sta
     for (int q = 0; q < 16; ++q) rb[q] -= tq * v[wave + 4 * q];
   }
   __syncthreads();
-  // ---- write back: read every value first, then store
+  // ---- write back: read every value first, then store (written through:
+  //      the next stage reads these blocks, on whichever XCD its tasks run)
   {
     double rl[16];
 #pragma unroll
@@ -213,14 +214,14 @@ __global__ void __launch_bounds__(NT) sb2st_stage(Band B, int n, int nb, int sta
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int j = wave + 4 * q;
-      if (lane < len && j < ncl) B.at(r0 + lane, c0 + j) = rl[q];
-      if (lane < len && j <= lane) B.at(r0 + lane, r0 + j) = rd[q];
-      if (lane < lenn && j < len) B.at(rn0 + lane, r0 + j) = rb[q];
+      if (lane < len && j < ncl) store_dev(&B.at(r0 + lane, c0 + j), rl[q]);
+      if (lane < len && j <= lane) store_dev(&B.at(r0 + lane, r0 + j), rd[q]);
+      if (lane < lenn && j < len) store_dev(&B.at(rn0 + lane, r0 + j), rb[q]);
     }
 #pragma unroll
     for (int q = 0; q < YQ; ++q) {
       const int c = wave + 4 * q;
-      if (c < ny && lane < len) Y[(r0 + lane) + c * ldy] = yv[q];
+      if (c < ny && lane < len) store_dev(&Y[(r0 + lane) + c * ldy], yv[q]);
     }
   }
 }

@@ -38,7 +38,9 @@ constexpr int QROWS = 256;  // panel rows per workgroup
 //                          slices still need the value of the previous one)
 // Each thread owns exactly one panel row (QROWS == QT) and holds the columns
 // of that row it works on in registers: every global load of a launch is
-// issued at its start, so a launch costs about one memory latency.
+// issued at its start, so a launch costs about one memory latency.  The row
+// and the partial sums are stored written through (the next launch reads them
+// on other XCDs).
 constexpr int MAXNB = 64;
 // partials read per thread at once when the previous column's sums are
 // formed (each thread sums a quarter of the workgroups' partials)
@@ -119,7 +121,7 @@ __global__ void __launch_bounds__(QT) panel_qr_step(double* P, int64_t ldp, int6
       double* wrow = P + i + (int64_t)b0 * ldp;
 #pragma unroll
       for (int u = 0; u < MAXNB; ++u)
-        if (u < nx) wrow[(int64_t)u * ldp] = x[u];
+        if (u < nx) store_dev(&wrow[(int64_t)u * ldp], x[u]);
     }
   } else if (c >= 1 && g == 0 && t == 0) {
     tau[cp] = 0.0;
@@ -143,7 +145,7 @@ __global__ void __launch_bounds__(QT) panel_qr_step(double* P, int64_t ldp, int6
 #pragma unroll
     for (int u = 0; u < MAXNB; ++u) {
       const int jj = u - uc;
-      if (jj >= 0 && jj < ncol) rowv[jj] = x[u];
+      if (jj >= 0 && jj < ncol) store_dev(&rowv[jj], x[u]);
     }
   }
   __syncthreads();
@@ -157,7 +159,7 @@ __global__ void __launch_bounds__(QT) panel_qr_step(double* P, int64_t ldp, int6
     red[h][j] = s2;
   }
   __syncthreads();
-  if (t < ncol) po[t] = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
+  if (t < ncol) store_dev(&po[t], (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]));
 }
 
 // Explicit V (m x nb, column-major, ld ldv) from the stored reflectors.
