@@ -49,15 +49,22 @@ constexpr int MAXNB = 64;
 #endif
 constexpr int PB = MM_SY2SB_PB;
 
-__global__ void __launch_bounds__(QT) panel_qr_step(double* P, int64_t ldp, int64_t m,
-                                                    int nb, int c, double* scratch,
-                                                    int G, double* tau) {
+// CW: columns summed per pass of the partial sums through LDS.  CW = 64
+// (one pass, 132 KB of LDS: one workgroup per CU) for panels of up to 256 row
+// blocks; CW = 32 (two passes, 66 KB: two workgroups per CU) for taller ones,
+// which then run in one round instead of two.
+template <int CW>
+__global__ void __launch_bounds__(QT) __attribute__((amdgpu_waves_per_eu(CW == 32 ? 2 : 1)))
+    panel_qr_step(double* P, int64_t ldp, int64_t m, int nb, int c, double* scratch, int G,
+                  double* tau) {
   const int t = threadIdx.x;
   const int g = blockIdx.x;
   const int64_t i = (int64_t)g * QROWS + t;  // this thread's panel row
   const int stride = nb + 1;
   const int64_t per_buf = (int64_t)G * stride + nb;
-  __shared__ double red2[MAXNB][QT + 1];  // products, column-major by row
+  constexpr int TPC = QT / CW;  // threads per column in the sums
+  __shared__ double red2[CW][QT + 1];  // products of CW columns, by row
+  __shared__ double redc[TPC][CW + 1];
   __shared__ double red[4][MAXNB + 1];
   __shared__ double tot[MAXNB + 1];
   __shared__ double wv[MAXNB + 1];
@@ -134,11 +141,6 @@ __global__ void __launch_bounds__(QT) panel_qr_step(double* P, int64_t ldp, int6
   const int ncol = nb - c;
   const bool mine = row_ok && i > c;
   const double a = mine ? (uc ? x[1] : x[0]) : 0.0;
-#pragma unroll
-  for (int u = 0; u < MAXNB; ++u) {
-    const int jj = u - uc;
-    if (jj >= 0 && jj < ncol) red2[jj][t] = a * x[u];
-  }
   // snapshot of row c (owned by slice 0, thread c)
   if (g == 0 && t == c) {
     double* rowv = part + (int64_t)G * stride;
@@ -148,18 +150,33 @@ __global__ void __launch_bounds__(QT) panel_qr_step(double* P, int64_t ldp, int6
       if (jj >= 0 && jj < ncol) store_dev(&rowv[jj], x[u]);
     }
   }
-  __syncthreads();
-  {
-    const int j = t & 63, h = t >> 6;
-    double s2 = 0.0;
-    if (j < ncol) {
-#pragma unroll 16
-      for (int r = 0; r < 64; ++r) s2 += red2[j][64 * h + r];
+  // the products a x_u summed over the workgroup's rows, CW columns at a time
+  // through an LDS transpose
+  for (int j0 = 0; j0 < ncol; j0 += CW) {
+#pragma unroll
+    for (int u = 0; u < MAXNB; ++u) {
+      const int jj = u - uc - j0;
+      if (jj >= 0 && jj < CW && j0 + jj < ncol) red2[jj][t] = a * x[u];
     }
-    red[h][j] = s2;
+    __syncthreads();
+    {
+      const int j = t % CW, h = t / CW;  // TPC threads per column, CW rows each
+      double s2 = 0.0;
+      if (j0 + j < ncol) {
+#pragma unroll 16
+        for (int r = 0; r < CW; ++r) s2 += red2[j][CW * h + r];
+      }
+      redc[h][j] = s2;
+    }
+    __syncthreads();
+    if (t < CW && j0 + t < ncol) {
+      double s2 = 0.0;
+#pragma unroll
+      for (int h = 0; h < TPC; ++h) s2 += redc[h][t];
+      store_dev(&po[j0 + t], s2);
+    }
+    __syncthreads();  // red2 and redc are reused by the next CW columns
   }
-  __syncthreads();
-  if (t < ncol) store_dev(&po[t], (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]));
 }
 
 // Explicit V (m x nb, column-major, ld ldv) from the stored reflectors.
@@ -257,8 +274,14 @@ struct Sy2sbWs {
 void qr_panel(double* P, int64_t lda, int64_t m, int nb, double* tau, double* T, double* V1,
               double* V2, int64_t ldv, const Sy2sbWs& w, hipStream_t s) {
   const int G = (int)ceil_div(m, QROWS);
-  for (int c = 0; c <= nb; ++c)
-    hipLaunchKernelGGL(panel_qr_step, dim3(G), dim3(QT), 0, s, P, lda, m, nb, c, w.part, G, tau);
+  for (int c = 0; c <= nb; ++c) {
+    if (G > 256)
+      hipLaunchKernelGGL(panel_qr_step<32>, dim3(G), dim3(QT), 0, s, P, lda, m, nb, c, w.part, G,
+                         tau);
+    else
+      hipLaunchKernelGGL(panel_qr_step<64>, dim3(G), dim3(QT), 0, s, P, lda, m, nb, c, w.part, G,
+                         tau);
+  }
   MM_HIP_TRY(hipGetLastError());
   const dim3 gv((unsigned)ceil_div(m * nb, 256));
   hipLaunchKernelGGL(extract_v, gv, dim3(256), 0, s, P, lda, m, nb, V1, ldv);
