@@ -37,9 +37,9 @@ FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 matrix (= vector), published
 def _workload(name: str, T: int | None):
     from paper_2407_11993_amd import inputs
     if name == "plate-128x128-crack":
-        return inputs.config2(T=T or 10000)
+        return inputs.plate_128x128_crack(T=T or 10000)
     if name == "block-8x8x8":
-        return inputs.config1(T=T or 2000)
+        return inputs.block_8x8x8(T=T or 2000)
     if name == "batched-coils-128x128":
         return inputs.batched_coils()
     raise SystemExit(f"unknown workload {name}")
@@ -300,7 +300,7 @@ def _electrode_workload(name, T):
     nx, ny = (int(v) for v in name.split("-")[1].split("x"))
     T = T or 100000
     if (nx, ny) == (256, 384):
-        return inputs.config3(T=T)
+        return inputs.plate_256x384_electrodes(T=T)
     return inputs.electrode_plate(nx, ny, 16, T=T, name=f"plate-{nx}x{ny}-electrodes")
 
 
@@ -316,7 +316,7 @@ def run_scan(args):
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
     T = args.T or 1_000_000
-    w = inputs.config1(T=10)
+    w = inputs.block_8x8x8(T=10)
     t = np.arange(T + 1)
     i_src = torch.as_tensor(np.sin(2 * np.pi * t / 200.0)[:, None], dtype=torch.float64,
                             device="cuda")
@@ -368,9 +368,10 @@ def run_scan(args):
 
 
 def run_batched(args):
-    """Config 4: 256 coil positions with their own waveform lengths, stepped
-    in one graph-captured batched launch, against 256 sequential solves of
-    one run each (same tile).  The decomposition is shared and not timed."""
+    """Batched coils on the 128x128 crack plate: 256 coil positions with
+    their own waveform lengths, stepped in one graph-captured batched launch,
+    against 256 sequential solves of one run each (same tile).  The
+    decomposition is shared and not timed."""
     import numpy as np
     import torch
     from paper_2407_11993_amd import Solver
@@ -439,10 +440,11 @@ def run_batched(args):
 
 
 def run_adjoint(args):
-    """Config 5: gradient of the 64-coil probe-signal misfit with respect to
-    every cell's resistivity and the shared waveform (modal adjoint with
-    checkpoints every 500 steps), evaluated at the background field, with
-    observations from the reference field (two defects).  Timed: problem
+    """Adjoint on the 128x256 plate: gradient of the 64-coil probe-signal
+    misfit with respect to every cell's resistivity and the shared waveform
+    (modal adjoint with checkpoints every 500 steps), evaluated at the
+    background field, with observations from the reference field (two
+    defects).  Timed: problem
     setup, decomposition and the adjoint (forward, backward, S GEMMs,
     V S V^T).  A few cells are checked by central differences."""
     import numpy as np
@@ -452,7 +454,7 @@ def run_adjoint(args):
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
-    cfg = inputs.config5(T=args.T or 10000)
+    cfg = inputs.adjoint_plate_128x256(T=args.T or 10000)
     T, M, dims = cfg["T"], cfg["M"], cfg["dims"]
     C = M.shape[1]
     dev = "cuda"

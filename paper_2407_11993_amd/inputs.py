@@ -230,7 +230,7 @@ def tk(T: int, dt: float) -> np.ndarray:
 # ---------------------------------------------------------------------------
 # the five configurations (and small variants used by the tests)
 # ---------------------------------------------------------------------------
-def config1(T: int = 2000) -> Workload:
+def block_8x8x8(T: int = 2000) -> Workload:
     """8x8x8 block, rho = 1, one coil below it, sinusoidal drive."""
     dims = (8, 8, 8)
     xyz = grid(*dims)
@@ -268,7 +268,7 @@ def plate(nx: int, ny: int, *, seed: Optional[int] = 0, crack=None,
                     np.zeros((T + 1, 0)))
 
 
-def config2(T: int = 10000) -> Workload:
+def plate_128x128_crack(T: int = 10000) -> Workload:
     """128x128 plate, log-uniform rho in [0.5, 2] (seed 0), 10x3 crack of
     rho = 1e3, coil two cells above the centre, Gaussian pulse."""
     return plate(128, 128, seed=0, crack=((59, 69), (63, 66), 1e3),
@@ -299,7 +299,7 @@ def electrode_plate(nx: int, ny: int, ew: int, *, T: int, tau_D: float = 2000.0,
                     rho, R, M, M.T.copy(), E, (0.5,), 1.0, T, i_src, i_D)
 
 
-def config5(nx: int = 128, ny: int = 256, n_i: int = 8, n_j: int = 8, T: int = 10000,
+def adjoint_plate_128x256(nx: int = 128, ny: int = 256, n_i: int = 8, n_j: int = 8, T: int = 10000,
             seed: int = 5):
     """Adjoint workload: background resistivity log-uniform (seed 5), the
     reference field adds defect A (x in [40,52), y in [60,63), rho = 1e3) and
@@ -321,7 +321,7 @@ def config5(nx: int = 128, ny: int = 256, n_i: int = 8, n_j: int = 8, T: int = 1
                 rho_bg=rho_bg, rho_ref=rho_ref, M=M, i_src=i_src, T=T)
 
 
-def config5_mini(T: int = 2000, seed: int = 5):
+def adjoint_plate_32x64(T: int = 2000, seed: int = 5):
     """The adjoint workload at a quarter of the size in x and y: 32x64 plate
     (N = 2048), background log-uniform (seed 5), defect A at x in [10,13),
     y in [15,16) (rho = 1e3) and defect B at x in [20,22), y in [45,47)
@@ -343,7 +343,7 @@ def config5_mini(T: int = 2000, seed: int = 5):
                 rho_bg=rho_bg, rho_ref=rho_ref, M=M, i_src=i_src, T=T)
 
 
-def config3(T: int = 100000) -> Workload:
+def plate_256x384_electrodes(T: int = 100000) -> Workload:
     """256x384 plate, rho = 1, electrodes of 16 cells on the two short edges,
     iD = 1 - exp(-t/2000), coil at the centre with period 500."""
     return electrode_plate(256, 384, 16, T=T, name="plate-256x384-electrodes")
@@ -380,10 +380,3 @@ def batched_coils(nx: int = 128, ny: int = 128, n_side: int = 16,
                     base.xyz, H_KERNEL, base.rho, base.R, M, M.T.copy(), None,
                     (0.5,), 1.0, T, waves, np.zeros((T + 1, 0)),
                     lengths=lengths)
-
-
-CONFIGS = {
-    1: config1,
-    2: config2,
-    3: config3,
-}

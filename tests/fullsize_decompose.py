@@ -30,7 +30,7 @@ def main():
     from paper_2407_11993_amd import Solver, _lib, inputs
     torch.cuda.set_device(0)
     T = 500
-    w = inputs.config3(T=T)
+    w = inputs.plate_256x384_electrodes(T=T)
     print(f"full decomposition: N = {w.n}, T = {T}", flush=True)
     i_src = torch.as_tensor(w.i_src, dtype=torch.float64, device="cuda")
     i_D = torch.as_tensor(w.i_D, dtype=torch.float64, device="cuda")

@@ -57,7 +57,7 @@ def part(which, out, state_path, half):
     import torch
     from paper_2407_11993_amd import Solver, _lib, inputs
     torch.cuda.set_device(0)
-    w = inputs.config3()
+    w = inputs.plate_256x384_electrodes()
     T = w.T
     H = half or T // 2
     i_src = torch.as_tensor(w.i_src, dtype=torch.float64, device="cuda")

@@ -25,7 +25,7 @@ N_SAMPLED = 512  # stored dJ/dR entries: the largest 64 and 448 at random (seed 
 
 def main():
     oracle.build(force=False)
-    cfg = inputs.config5_mini()
+    cfg = inputs.adjoint_plate_32x64()
     T, M, dims, xyz = cfg["T"], cfg["M"], cfg["dims"], cfg["xyz"]
     C = M.shape[1]
     L = oracle.assemble_L(xyz, inputs.H_KERNEL)

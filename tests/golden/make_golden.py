@@ -20,7 +20,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 def main():
     oracle.build(force=False)
-    w = inputs.config1()
+    w = inputs.block_8x8x8()
     L = oracle.assemble_L(w.xyz, w.h)
     pb = oracle.Problem(L, w.R.to_dense(), w.M, w.P)
     for theta in (0.5, 1.0):

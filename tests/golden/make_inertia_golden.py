@@ -35,7 +35,7 @@ THREADS = int(os.environ.get("THREADS", "4"))
 
 def main():
     oracle.build(force=False)
-    w = inputs.config2(T=1)
+    w = inputs.plate_128x128_crack(T=1)
     L = oracle.assemble_L(w.xyz, w.h)
     R = w.R.to_dense()
     pb = oracle.Problem(L, R, w.M, w.P)

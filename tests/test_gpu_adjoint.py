@@ -64,7 +64,7 @@ def test_quarter_size_workload_matches_stored_oracle_adjoint():
     import os
     import re
     here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
-    cfg = inputs.config5_mini()
+    cfg = inputs.adjoint_plate_32x64()
     T, M = cfg["T"], cfg["M"]
     C = M.shape[1]
     obs = np.loadtxt(os.path.join(here, "adjoint_mini_obs.txt")).reshape(C, T)

@@ -25,7 +25,7 @@ def _rel(a, b):
 
 
 CASES = {
-    "block8": lambda: inputs.config1(T=600),
+    "block8": lambda: inputs.block_8x8x8(T=600),
     "plate-crack": lambda: inputs.plate(23, 19, seed=23, crack=((5, 12), (8, 10), 1e3), T=300,
                                         wave="gauss"),
     "electrodes": lambda: inputs.electrode_plate(12, 9, 3, T=250, tau_D=40.0, coil_period=70.0,
@@ -85,7 +85,7 @@ def test_exact_differs_from_theta_by_the_time_step_error(case):
 def test_exact_is_step_size_invariant_at_16384():
     import torch
     from paper_2407_11993_amd import Solver
-    w = inputs.config2(T=300)
+    w = inputs.plate_128x128_crack(T=300)
     s = Solver(w)
     s.decompose(projected=True)
     coarse = _np(s.step_modal_exact(w.dt, w.T, w.i_src))
@@ -103,7 +103,7 @@ def test_exact_is_step_size_invariant_at_16384():
 
 def test_exact_rejects_bad_arguments():
     from paper_2407_11993_amd import Solver, _lib
-    w = inputs.config1(T=10)
+    w = inputs.block_8x8x8(T=10)
     s = Solver(w)
     with pytest.raises(_lib.MMError) as e:  # before the decomposition
         s.step_modal_exact(1.0, 10, w.i_src)

@@ -28,7 +28,7 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
 def test_eigenvalue_counts_match_inertia():
     from paper_2407_11993_amd import Solver
     rows = np.atleast_2d(np.loadtxt(GOLDEN))
-    w = inputs.config2(T=1)
+    w = inputs.plate_128x128_crack(T=1)
     s = Solver(w)
     s.decompose(projected=True)
     lam = s.eigenvalues().cpu().numpy()

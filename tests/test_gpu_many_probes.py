@@ -78,7 +78,7 @@ def test_many_probes_across_chunks_at_16384():
     import torch
     from paper_2407_11993_amd import Solver
     T = 20000
-    w = _with_probes(inputs.config2(T=T), 3, lift=2.0)  # 10 probes
+    w = _with_probes(inputs.plate_128x128_crack(T=T), 3, lift=2.0)  # 10 probes
     w.P = np.vstack([w.P, inputs.coil_coupling(w.xyz, (30.5, 90.5, 1.0))[None],
                      inputs.coil_coupling(w.xyz, (100.5, 20.5, 3.0))[None]])
     i_src = torch.as_tensor(w.i_src, dtype=torch.float64, device="cuda")
@@ -88,7 +88,7 @@ def test_many_probes_across_chunks_at_16384():
     s.close()
     parts = []
     for sl in (slice(0, 6), slice(6, 12)):
-        w6 = inputs.config2(T=1)
+        w6 = inputs.plate_128x128_crack(T=1)
         w6.P = w.P[sl]
         s6 = Solver(w6)
         s6.decompose(projected=True)
@@ -141,7 +141,7 @@ def test_301_probes_projected_at_16384():
     Cholesky method against both (1e-8)."""
     from paper_2407_11993_amd import Solver
     T = 3000
-    w = inputs.config2(T=T)
+    w = inputs.plate_128x128_crack(T=T)
     xs = np.linspace(0.5, w.dims[0] - 1.5, 301)
     w.P = np.vstack([inputs.coil_coupling(w.xyz, (x, w.dims[1] / 2.0 - 0.5, 2.0))
                      for x in xs])

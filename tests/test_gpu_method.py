@@ -30,7 +30,7 @@ def block8():
     import torch
     assert torch.cuda.is_available()
     from paper_2407_11993_amd import Solver
-    w = inputs.config1()
+    w = inputs.block_8x8x8()
     s = Solver(w)
     s.decompose()
     return w, s

@@ -31,7 +31,7 @@ def _check(got, ref, tol):
 
 
 CASES = {
-    "block8": lambda: inputs.config1(T=10),
+    "block8": lambda: inputs.block_8x8x8(T=10),
     "plate-crack": lambda: inputs.plate(23, 19, seed=23, crack=((5, 12), (8, 10), 1e3), T=10),
     "electrodes": lambda: inputs.electrode_plate(12, 9, 3, T=10, seed=3),
 }
@@ -91,7 +91,7 @@ def test_crack_signature(orc):
 def test_phasors_reject_bad_arguments():
     import torch
     from paper_2407_11993_amd import Solver, _lib
-    w = inputs.config1(T=10)
+    w = inputs.block_8x8x8(T=10)
     s = Solver(w)
     with pytest.raises(_lib.MMError) as e:
         s.phasors([1.0], [[1.0]])

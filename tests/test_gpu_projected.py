@@ -34,7 +34,7 @@ def _pair(w):
 @pytest.mark.parametrize("case", ["block8", "plate-crack", "plate-576"])
 def test_projected_matches_oracle_and_full(orc, case):
     if case == "block8":
-        w = inputs.config1()
+        w = inputs.block_8x8x8()
         w.T = 600
         w.i_src = w.i_src[:w.T + 1]
     elif case == "plate-crack":
@@ -90,7 +90,7 @@ def test_projected_batched_runs_match_full():
 
 def test_projected_error_paths():
     from paper_2407_11993_amd import Solver, _lib
-    w = inputs.config1()
+    w = inputs.block_8x8x8()
     s = Solver(w)
     s.decompose(projected=True)
     with pytest.raises(_lib.MMError) as e:

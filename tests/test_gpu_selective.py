@@ -193,7 +193,7 @@ def test_block8_keeps_the_symmetric_modes(orc):
     import torch
     from paper_2407_11993_amd import Solver
     assert torch.cuda.is_available()
-    w = inputs.config1()
+    w = inputs.block_8x8x8()
     s = Solver(w)
     s.decompose()
     lam = _np(s.eigenvalues())

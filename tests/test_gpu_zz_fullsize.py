@@ -31,7 +31,7 @@ def test_modal_matches_cholesky_at_98304():
     from paper_2407_11993_amd import Solver
     assert torch.cuda.is_available()
     T = 3000
-    w = inputs.config3(T=T)
+    w = inputs.plate_256x384_electrodes(T=T)
     print(f"full-size parity: N = {w.n}, T = {T}", flush=True)
     i_src = torch.as_tensor(w.i_src, dtype=torch.float64, device="cuda")
     i_D = torch.as_tensor(w.i_D, dtype=torch.float64, device="cuda")

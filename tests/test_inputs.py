@@ -19,8 +19,8 @@ def test_resistance_model_reproduces_the_assembly():
 def test_adjoint_workloads_have_the_stated_shapes():
     """The full and quarter-size adjoint workloads: plate sizes, coil counts,
     the two defects only in the reference field, the shared pulse."""
-    for cfg, n, C, T, (a, b) in ((inputs.config5(T=50), 128 * 256, 64, 50, (1e3, 5.0)),
-                                 (inputs.config5_mini(T=40), 32 * 64, 8, 40, (1e3, 5.0))):
+    for cfg, n, C, T, (a, b) in ((inputs.adjoint_plate_128x256(T=50), 128 * 256, 64, 50, (1e3, 5.0)),
+                                 (inputs.adjoint_plate_32x64(T=40), 32 * 64, 8, 40, (1e3, 5.0))):
         assert cfg["xyz"].shape == (n, 3)
         assert cfg["M"].shape == (n, C)
         assert cfg["i_src"].shape == (T + 1,)
