@@ -7,9 +7,9 @@ are checked by tests/fullsize_decompose.py, run on its own.)  The oracle
 cannot run at this size; the property checked is that the two methods give
 the same probe signals (within 1e-8 of the largest, the tolerance between
 them at every size).  They share the problem setup, the
-Cholesky kernel (of L_i for the modal method, of L_i + theta dt R_i for the
-other) and the GEMM; the eigensolver, the modal stepping and the triangular
-solves are their own.  Exact integration must differ from theta = 1/2 by no
+blocked Cholesky kernel (on the diagonal blocks of R's banded factor for the
+modal method, on L_i + theta dt R_i for the other) and the GEMM; the
+eigensolver, the modal stepping and the triangular solves are their own.  Exact integration must differ from theta = 1/2 by no
 more than the theta-method's time-step error seen on the smaller plates, and
 the selective stepping keeps every mode at tol = 0 and fewer than half of
 them, with the same signal to 1e-8, at tol = 1e-10.
