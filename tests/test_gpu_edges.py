@@ -1,0 +1,64 @@
+"""Edge cases of the boundary against the CPU oracle.
+
+* Problems smaller than every tile, block and band of the path (N = 1, 2, 3
+  and 7 cells: one cell, a band of width 0 or 1 for the band reduction, no
+  bulge to chase, a single leaf for the divide and conquer, one partial
+  block for the Cholesky method's solves), with the full and the projected
+  decomposition: eigenvalues to 1e-10 relative, signals of both
+  theta-methods to 1e-9 of max|s| (Sec. 3.2, Sec. 3.3).
+* Zero-step calls: an empty signal, and the state left as it was, so that a
+  run cut as 15 + 0 + 25 steps gives the 40-step run's signal (both
+  methods)."""
+import numpy as np
+import pytest
+
+from paper_2407_11993_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+@pytest.mark.parametrize("projected", [False, True])
+@pytest.mark.parametrize("nx,ny", [(1, 1), (1, 2), (1, 3), (7, 1)])
+def test_tiny_problems_match_oracle(orc, nx, ny, projected):
+    from paper_2407_11993_amd import Solver
+    w = inputs.plate(nx, ny, seed=1, T=30, wave="sin", thetas=(0.5,))
+    pb = orc.Problem(orc.assemble_L(w.xyz, w.h), w.R.to_dense(), w.M, w.P)
+    lam_ref = orc.modal_eigen(pb, want_V=False)
+    ref = orc.theta_direct(pb, 0.5, w.dt, w.T, w.i_src)
+    s = Solver(w)
+    s.decompose(projected=projected)
+    lam = _np(s.eigenvalues())
+    assert lam.shape == lam_ref.shape == (w.n,)
+    assert np.max(np.abs(lam - lam_ref) / lam_ref) < 1e-10
+    sm = _np(s.step_modal(0.5, w.dt, w.T, w.i_src))
+    s.reset()
+    sc = _np(s.step_cholesky(0.5, w.dt, w.T, w.i_src))
+    assert sm.shape == sc.shape == ref.shape == (w.T, 1)
+    assert _rel(sm, ref) < 1e-9
+    assert _rel(sc, ref) < 1e-9
+    s.close()
+
+
+@pytest.mark.parametrize("method", ["modal", "cholesky"])
+def test_zero_steps_leave_the_state(method):
+    from paper_2407_11993_amd import Solver
+    w = inputs.plate(6, 7, seed=2, T=40, wave="sin", thetas=(0.5,))
+    s = Solver(w)
+    s.decompose()
+    step = s.step_modal if method == "modal" else s.step_cholesky
+    whole = _np(step(0.5, 1.0, 40, w.i_src))
+    s.reset()
+    first = _np(step(0.5, 1.0, 15, w.i_src[:16]))
+    empty = step(0.5, 1.0, 0, w.i_src[15:16])
+    assert tuple(empty.shape) == (0, w.n_probe)
+    rest = _np(step(0.5, 1.0, 25, w.i_src[15:]))
+    assert _rel(np.vstack([first, rest]), whole) < 1e-14
+    s.close()
