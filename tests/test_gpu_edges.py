@@ -6,6 +6,9 @@
   block for the Cholesky method's solves), with the full and the projected
   decomposition: eigenvalues to 1e-10 relative, signals of both
   theta-methods to 1e-9 of max|s| (Sec. 3.2, Sec. 3.3).
+* The same with two electrodes on plates of 2, 4 and 12 cells (N0 = 1, 3 and
+  11 after the reduction: the electrode term's rank 2 then exceeds or nears
+  N0, and its low-rank factor is singular).
 * Zero-step calls: an empty signal, and the state left as it was, so that a
   run cut as 15 + 0 + 25 steps gives the 40-step run's signal (both
   methods)."""
@@ -42,6 +45,28 @@ def test_tiny_problems_match_oracle(orc, nx, ny, projected):
     s.reset()
     sc = _np(s.step_cholesky(0.5, w.dt, w.T, w.i_src))
     assert sm.shape == sc.shape == ref.shape == (w.T, 1)
+    assert _rel(sm, ref) < 1e-9
+    assert _rel(sc, ref) < 1e-9
+    s.close()
+
+
+@pytest.mark.parametrize("projected", [False, True])
+@pytest.mark.parametrize("nx,ny,ew", [(1, 2, 1), (2, 2, 1), (3, 4, 2)])
+def test_tiny_electrode_problems_match_oracle(orc, nx, ny, ew, projected):
+    from paper_2407_11993_amd import Solver
+    w = inputs.electrode_plate(nx, ny, ew, T=30, tau_D=20.0, coil_period=40.0)
+    pb = orc.Problem(orc.assemble_L(w.xyz, w.h), w.R.to_dense(), w.M, w.P,
+                     E=w.E.to_dense())
+    lam_ref = orc.modal_eigen(pb, want_V=False)
+    ref = orc.theta_direct(pb, 0.5, w.dt, w.T, w.i_src, w.i_D)
+    s = Solver(w)
+    s.decompose(projected=projected)
+    lam = _np(s.eigenvalues())
+    assert lam.shape == lam_ref.shape == (w.n - w.m,)
+    assert np.max(np.abs(lam - lam_ref) / lam_ref) < 1e-10
+    sm = _np(s.step_modal(0.5, w.dt, w.T, w.i_src, w.i_D))
+    s.reset()
+    sc = _np(s.step_cholesky(0.5, w.dt, w.T, w.i_src, w.i_D))
     assert _rel(sm, ref) < 1e-9
     assert _rel(sc, ref) < 1e-9
     s.close()
