@@ -87,3 +87,30 @@ def test_zero_steps_leave_the_state(method):
     rest = _np(step(0.5, 1.0, 25, w.i_src[15:]))
     assert _rel(np.vstack([first, rest]), whole) < 1e-14
     s.close()
+
+
+def test_unbanded_numbering_is_rejected():
+    """R's factor is taken banded (block bidiagonal with blocks of the
+    bandwidth, at most 8192): a 100 x 100 plate numbered in random order has
+    a bandwidth near N and is refused with MM_E_INVALID by both
+    decompositions, before any large allocation; the Cholesky method, which
+    needs no band, still runs."""
+    import scipy.sparse as sp
+    from paper_2407_11993_amd import Solver, _lib
+    w = inputs.plate(100, 100, seed=3, T=5, wave="sin", thetas=(0.5,))
+    perm = np.random.default_rng(7).permutation(w.n)
+    R = sp.csr_matrix((w.R.val, w.R.col, w.R.rowptr), shape=w.R.shape)[perm][:, perm].tocsr()
+    R.sort_indices()
+    w.R = inputs.CSR(R.shape, R.indptr.astype(np.int64), R.indices.astype(np.int32),
+                     R.data.astype(np.float64))
+    w.xyz = w.xyz[perm]
+    w.M = w.M[perm]
+    w.P = w.P[:, perm]
+    s = Solver(w)
+    for projected in (False, True):
+        with pytest.raises(_lib.MMError) as ei:
+            s.decompose(projected=projected)
+        assert ei.value.code == 1 and "bandwidth" in str(ei.value)
+    sc = _np(s.step_cholesky(0.5, w.dt, w.T, w.i_src))
+    assert sc.shape == (w.T, 1) and np.all(np.isfinite(sc))
+    s.close()
